@@ -1,0 +1,344 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is checked against things other than itself: hand-derived closed
+forms (tests/golden), the textbook voxel walk through tensor lattices
+(oracle/dda.py), an exact rational sweep over all pairwise bisector crossings
+(oracle/exact.py), invariants evaluated by plain numpy brute force,
+metamorphic relations, scipy's kd-tree and Delaunay triangulation, and the
+published mean neighbour count of a uniform Poisson-Voronoi tessellation.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.dda import lattice_path
+from oracle.exact import exact_path, exact_tau
+from paper_1310_1854_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _np_nearest(sites, x):
+    d = ((sites[None, :, :] - x[:, None, :]) ** 2).sum(axis=2)
+    return d
+
+
+def _np_chord(box, r0, k):
+    k = np.asarray(k, float) / np.linalg.norm(k)
+    with np.errstate(divide="ignore"):
+        hi = np.where(k > 0, (box[3:] - r0) / np.where(k == 0, 1, k), np.inf)
+        lo = np.where(k < 0, (box[:3] - r0) / np.where(k == 0, 1, k), np.inf)
+    return float(min(hi.min(), lo.min()))
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+def test_golden_hand_paths(oracle_lib):
+    g = json.load(open(os.path.join(HERE, "golden", "hand_paths.json")))
+    for c in g["cases"]:
+        o = oracle.trace(c["sites"], c["box"], c["density"], [c["origin"]], [c["dir"]], cap=8)
+        cells, lens = oracle.segments_of(o, 0)
+        L = c["chord"]
+        tol = c["rel_tol"] * max(L, 1.0)
+        assert list(cells) == c["cells"], c["name"]
+        assert np.allclose(lens, c["lengths"], rtol=0, atol=tol), c["name"]
+        assert abs(o["tau"][0] - c["tau"]) <= tol * max(1.0, c["tau"]), c["name"]
+        assert abs(o["chord"][0] - L) <= tol, c["name"]
+        assert o["status"][0] == 0
+
+
+def test_single_site_one_segment(oracle_lib):
+    w = W.uniform_cube(M=1, N=300, seed=11)
+    o = oracle.trace(w.sites, w.box, [2.5], w.origins, w.dirs, cap=4)
+    assert np.all(o["nseg"] == 1)
+    assert np.all(o["seg_cell"][:, 0] == 0)
+    for r in range(w.N):
+        L = _np_chord(w.box, w.origins[r], w.dirs[r])
+        assert abs(o["seg_len"][r, 0] - L) <= 1e-15 * L
+        assert abs(o["tau"][r] - 2.5 * L) <= 1e-15 * 2.5 * L
+
+
+def test_two_sites_midplane(oracle_lib):
+    rng = np.random.default_rng(3)
+    box = np.array([-1, -1, -1, 1, 1, 1.0])
+    for _ in range(200):
+        a, b = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+        r0 = rng.uniform(-1, 1, 3)
+        k = W.isotropic_dirs(rng, 1)[0]
+        o = oracle.trace(np.stack([a, b]), box, [1.0, 3.0], [r0], [k], cap=4)
+        L = _np_chord(box, r0, k)
+        # closed form: |x-a|^2 - |x-b|^2 is linear along the ray; it changes sign once
+        f0 = np.sum((r0 - a) ** 2) - np.sum((r0 - b) ** 2)
+        df = 2 * np.dot(k, b - a)          # d/ds of f
+        start = 0 if (f0 < 0 or (f0 == 0 and df > 0)) else 1
+        s = -f0 / df if df != 0 else np.inf
+        cells, lens = oracle.segments_of(o, 0)
+        if 0 < s < L and ((start == 0 and df > 0) or (start == 1 and df < 0)):
+            assert list(cells) == [start, 1 - start]
+            assert abs(lens[0] - s) <= 1e-12 * L
+            assert abs(lens.sum() - L) <= 1e-14 * L
+        else:
+            assert list(cells) == [start]
+            assert abs(lens[0] - L) <= 1e-14 * L
+
+
+def test_cubic_lattice_matches_voxel_walk_bit_exact(oracle_lib):
+    w = W.cubic_lattice(6, N=1500)
+    o = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    xs, ys, zs = w.meta["xs"], w.meta["ys"], w.meta["zs"]
+    for r in range(w.N):
+        c, l, L = lattice_path(xs, ys, zs, w.box, w.origins[r], w.dirs[r])
+        c2, l2 = oracle.segments_of(o, r)
+        assert list(c2) == c
+        # on the dyadic lattice both routes evaluate the same rounded quotients
+        assert np.array_equal(l2, np.array(l))
+        assert o["chord"][r] == L
+
+
+def test_random_tensor_lattice_matches_voxel_walk(oracle_lib):
+    w = W.random_tensor_lattice((5, 7, 4), N=1500)
+    o = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    xs, ys, zs = w.meta["xs"], w.meta["ys"], w.meta["zs"]
+    for r in range(w.N):
+        c, l, L = lattice_path(xs, ys, zs, w.box, w.origins[r], w.dirs[r])
+        c2, l2 = oracle.segments_of(o, r)
+        assert list(c2) == c
+        assert np.max(np.abs(l2 - np.array(l))) <= 1e-14 * L
+
+
+@pytest.mark.parametrize("seed,M", [(1, 8), (2, 16), (3, 24), (4, 32), (5, 40)])
+def test_exact_rational_sweep(oracle_lib, seed, M):
+    w = W.uniform_cube(M=M, N=12, seed=1000 + seed)
+    o = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    for r in range(w.N):
+        path, T = exact_path(w.sites, w.box, w.origins[r], w.dirs[r])
+        kn = math.sqrt(float(sum(x * x for x in w.dirs[r])))
+        L = float(T) * kn
+        c2, l2 = oracle.segments_of(o, r)
+        assert list(c2) == [m for m, _ in path]
+        assert np.max(np.abs(l2 - np.array([float(dt) * kn for _, dt in path]))) <= 1e-14 * L
+        tau = float(exact_tau(path, w.density)) * kn
+        assert abs(o["tau"][r] - tau) <= 1e-14 * max(tau, 1e-300)
+        assert abs(o["chord"][r] - L) <= 1e-15 * L
+
+
+def test_exact_sweep_lattice_vertex_ties(oracle_lib):
+    """Rays through lattice edges and vertices (exact ties)."""
+    w = W.cubic_lattice(3, N=1)
+    cases = [((0.25, 0.25, 0.25), (1, 1, 1)), ((0.5, 0.25, 0.5), (0, 1, 1)),
+             ((0.1, 0.1, 0.5), (1, 1, 0)), ((2.75, 0.25, 1.5), (-1, 1, 0))]
+    for r0, k in cases:
+        path, T = exact_path(w.sites, w.box, r0, k)
+        kn = math.sqrt(sum(x * x for x in k))
+        o = oracle.trace(w.sites, w.box, w.density, [r0], [k], cap=32)
+        c2, l2 = oracle.segments_of(o, 0)
+        assert list(c2) == [m for m, _ in path]
+        assert np.max(np.abs(l2 - np.array([float(dt) * kn for _, dt in path]))) <= 1e-14 * float(T) * kn
+
+
+# --------------------------------------------------------------------------
+# invariants by numpy brute force
+# --------------------------------------------------------------------------
+
+def test_invariants_uniform_cube(oracle_lib):
+    w = W.uniform_cube(M=1000, N=1500, seed=77)
+    o = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    scale = 2.0
+    n_checked = 0
+    for r in range(w.N):
+        assert o["status"][r] == 0
+        cells, lens = oracle.segments_of(o, r)
+        L = _np_chord(w.box, w.origins[r], w.dirs[r])
+        k = w.dirs[r] / np.linalg.norm(w.dirs[r])
+        assert abs(o["chord"][r] - L) <= 1e-15 * L
+        assert np.all(lens > 0)
+        assert abs(lens.sum() - L) <= 1e-13 * L
+        assert np.all(cells[1:] != cells[:-1])
+        d0 = _np_nearest(w.sites, w.origins[r][None])[0]
+        assert d0[cells[0]] == d0.min()
+        if o["n_near"][r]:
+            continue
+        n_checked += 1
+        b = np.concatenate([[0.0], np.cumsum(lens)])
+        mids = w.origins[r] + 0.5 * (b[:-1] + b[1:])[:, None] * k
+        dm = _np_nearest(w.sites, mids)
+        assert np.array_equal(np.argmin(dm, axis=1), cells)
+        ends = w.origins[r] + b[1:-1, None] * k
+        de = _np_nearest(w.sites, ends)
+        for i in range(len(cells) - 1):
+            a, c = de[i, cells[i]], de[i, cells[i + 1]]
+            assert abs(a - c) <= 1e-12 * scale
+            assert min(a, c) <= de[i].min() + 1e-12 * scale
+        tau = np.sum(w.density[cells] * lens)
+        assert abs(o["tau"][r] - tau) <= 1e-13 * tau
+    assert n_checked > 0.99 * w.N
+
+
+def test_reversed_ray_reverses_path(oracle_lib):
+    w = W.uniform_cube(M=500, N=400, seed=5)
+    o = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    k = w.dirs / np.linalg.norm(w.dirs, axis=1, keepdims=True)
+    ends = w.origins + o["chord"][:, None] * k
+    ends = np.clip(ends, w.box[:3], w.box[3:])
+    o2 = oracle.trace(w.sites, w.box, w.density, ends, -k, cap=64)
+    for r in range(w.N):
+        if o["n_near"][r] or o2["n_near"][r]:
+            continue
+        c1, l1 = oracle.segments_of(o, r)
+        c2, l2 = oracle.segments_of(o2, r)
+        # the reversed ray passes r0 and goes on to the opposite wall: its
+        # first n1 cells are the original ones in reverse order, and all but
+        # the last of those segments have the original lengths
+        n1 = len(c1)
+        assert list(c1[::-1]) == list(c2[:n1])
+        if n1 > 1:
+            assert np.max(np.abs(l1[::-1][:n1 - 1] - l2[:n1 - 1])) <= 1e-12 * o["chord"][r]
+        assert l2[n1 - 1] >= l1[0] - 1e-12 * o["chord"][r]
+
+
+def test_power_of_two_scaling_is_exact(oracle_lib):
+    w = W.uniform_cube(M=400, N=300, seed=9)
+    o = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    o4 = oracle.trace(4.0 * w.sites, 4.0 * w.box, w.density, 4.0 * w.origins, w.dirs, cap=64)
+    assert np.array_equal(o["nseg"], o4["nseg"])
+    for r in range(w.N):
+        c1, l1 = oracle.segments_of(o, r)
+        c2, l2 = oracle.segments_of(o4, r)
+        assert np.array_equal(c1, c2)
+        assert np.array_equal(4.0 * l1, l2)
+    assert np.array_equal(4.0 * o["tau"], o4["tau"])
+
+
+def test_site_permutation_permutes_ids(oracle_lib):
+    w = W.uniform_cube(M=300, N=300, seed=21)
+    perm = np.random.default_rng(0).permutation(w.M)      # new[i] = old[perm[i]]
+    inv = np.argsort(perm)
+    o = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    o2 = oracle.trace(w.sites[perm], w.box, w.density[perm], w.origins, w.dirs, cap=64)
+    for r in range(w.N):
+        c1, l1 = oracle.segments_of(o, r)
+        c2, l2 = oracle.segments_of(o2, r)
+        assert np.array_equal(inv[c1], c2)
+        assert np.array_equal(l1, l2)
+
+
+def test_constant_density_gives_kappa_rho_L(oracle_lib):
+    w = W.exp_disc(M=2000, N=200, seed=4)
+    o = oracle.trace(w.sites, w.box, np.full(w.M, 0.75), w.origins, w.dirs, kappa=2.0, cap=256)
+    assert np.all(np.abs(o["tau"] - 1.5 * o["chord"]) <= 1e-13 * 1.5 * o["chord"])
+
+
+def test_status_codes(oracle_lib):
+    box = [-1, -1, -1, 1, 1, 1]
+    sites = [[0.1, 0.2, 0.3], [-0.4, 0.1, 0.0]]
+    o = oracle.trace(sites, box, [1, 1], [[2, 0, 0], [0, 0, 0], [1, 0, 0], [0, 0, 0]],
+                     [[1, 0, 0], [0, 0, 0], [1, 0, 0], [np.nan, 0, 1]], cap=4)
+    assert list(o["status"]) == [oracle.ST_OUTSIDE, oracle.ST_BADDIR, oracle.ST_OK, oracle.ST_BADDIR]
+    assert o["nseg"][2] == 0 and o["chord"][2] == 0.0 and o["tau"][2] == 0.0
+    o = oracle.trace(sites, box, [1, 1], [[0, 0, 0]], [[-1, 0, 0]], cap=1)
+    assert o["status"][0] == oracle.ST_OVERFLOW and o["nseg"][0] == 2
+
+
+# --------------------------------------------------------------------------
+# locate
+# --------------------------------------------------------------------------
+
+def test_locate_matches_kdtree(oracle_lib):
+    from scipy.spatial import cKDTree
+    w = W.exp_disc(M=5000, N=1, seed=8)
+    pts = W.uniform_in_box(np.random.default_rng(1), 5000, w.box)
+    cell, gap = oracle.locate(w.sites, w.box, pts)
+    _, idx = cKDTree(w.sites).query(pts)
+    ok = gap > 1e-12
+    assert ok.mean() > 0.999
+    assert np.array_equal(cell[ok], idx[ok])
+    out = np.array([[11.0, 0, 0], [0, 0, -3.5]])
+    assert list(oracle.locate(w.sites, w.box, out)[0]) == [-1, -1]
+
+
+def test_locate_ties_take_lowest_index(oracle_lib):
+    sites = np.array([[0.5, 0.0, 0.0], [-0.5, 0.0, 0.0], [0.0, 0.5, 0.0]])
+    cell, gap = oracle.locate(sites, [-1, -1, -1, 1, 1, 1], [[0.0, 0.0, 0.0], [0.0, -0.2, 0.0]])
+    assert list(cell) == [0, 0]
+    assert gap[0] == 0.0 and gap[1] == 0.0
+
+
+# --------------------------------------------------------------------------
+# cell faces (neighbour lists) and volumes
+# --------------------------------------------------------------------------
+
+AREA_TOL = 1e-12
+
+
+def _face_sets(res, scale2):
+    return [set(int(j) for j, a in zip(n, ar) if a > AREA_TOL * scale2) for n, ar in res]
+
+
+def test_faces_volumes_sum_to_box_and_are_symmetric(oracle_lib):
+    w = W.uniform_cube(M=600, N=1, seed=31)
+    res, vol = oracle.faces(w.sites, w.box, np.arange(w.M))
+    assert abs(vol.sum() - 8.0) <= 1e-11
+    assert np.all(vol > 0)
+    sets = _face_sets(res, 1.0)
+    areas = [dict(zip(map(int, n), ar)) for n, ar in res]
+    for i, s in enumerate(sets):
+        for j in s:
+            if j >= 0:
+                assert i in sets[j]
+                assert abs(areas[i][j] - areas[j][i]) <= 1e-10 * max(areas[i][j], 1e-3)
+
+
+def test_faces_subset_of_delaunay_and_equal_inside(oracle_lib):
+    from scipy.spatial import Delaunay
+    w = W.uniform_cube(M=800, N=1, seed=32)
+    res, _ = oracle.faces(w.sites, w.box, np.arange(w.M))
+    sets = _face_sets(res, 1.0)
+    tri = Delaunay(w.sites)
+    ptr, ind = tri.vertex_neighbor_vertices
+    n_inside = 0
+    for i in range(w.M):
+        dl = set(int(j) for j in ind[ptr[i]:ptr[i + 1]])
+        own = set(j for j in sets[i] if j >= 0)
+        assert own <= dl
+        if not any(j < 0 for j in sets[i]):
+            # the clipped cell touches no wall: it is the unclipped cell, whose
+            # faces are exactly the Delaunay edges unless an edge's dual face
+            # lies outside the box (then a wall face would show)
+            assert own == dl
+            n_inside += 1
+    assert n_inside > 100
+
+
+def test_faces_cubic_lattice_closed_form(oracle_lib):
+    n = 4
+    w = W.cubic_lattice(n, N=1)
+    res, vol = oracle.faces(w.sites, w.box, np.arange(w.M))
+    assert np.allclose(vol, 1.0, rtol=0, atol=1e-13)
+    for idx, (nb, ar) in enumerate(res):
+        i, j, k = idx // (n * n), (idx // n) % n, idx % n
+        want = set()
+        for a, (c, lo_wall) in enumerate(((i, -1), (j, -3), (k, -5))):
+            step = (n * n, n, 1)[a]
+            want.add(idx - step if c > 0 else lo_wall)
+            want.add(idx + step if c < n - 1 else lo_wall - 1)
+        got = set(int(x) for x, a in zip(nb, ar) if a > 1e-9)
+        assert got == want
+        assert np.allclose([a for a in ar if a > 1e-9], 1.0, atol=1e-12)
+
+
+def test_mean_neighbour_count_uniform(oracle_lib):
+    """Poisson-Voronoi cells have 15.54 face neighbours on average (Sect. 2.1,
+    literature value). Averaged over cells far from the walls of a
+    4000-site uniform cube; the statistical spread of the mean is ~0.1."""
+    w = W.uniform_cube(M=4000, N=1, seed=33)
+    far = np.all(np.abs(w.sites) < 0.55, axis=1)
+    cells = np.nonzero(far)[0]
+    res, _ = oracle.faces(w.sites, w.box, cells)
+    counts = np.array([len(s) for s in _face_sets(res, (2.0 / 4000 ** (1 / 3)) ** 2)])
+    assert abs(counts.mean() - 15.54) < 0.5, counts.mean()
