@@ -1,0 +1,256 @@
+"""Benchmark: Voronoi cell crossings per second on one MI355X.
+
+Workload (default): the 10^6-site flared-disc grid (99% of sites from
+rho ~ (R/R0)^-1 exp(-(pi/4)(z/h)^2), h = 0.125 R0 (R/R0)^1.125, R in
+[1, 1000] AU, 1% uniform in the box +-1000 AU) with 8x10^6 rays, half from
+the central point source and half from random sites, in mixed-precision
+mode (FP32 plane tests, FP64 re-decision of close calls, FP64 winner).
+
+A step is one vor_trace over the whole batch with inputs resident in HBM:
+start-cell location, the traversal, the per-ray outputs and every segment
+(cell, length) written to its stride window, plus the spill pass that
+rewrites paths longer than their window. The grid is built once, outside
+the timed region (setup, as in the method). value = segments emitted per
+step / seconds per step.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload flared_disc|exp_disc|clumpy|uniform_cube]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Voronoi cell crossings/sec per GPU at stated accuracy; p50/p99 batch latency"
+HBM_PEAK_GBS = 8000.0
+
+# Launch configuration per workload: mode, stride window, spill capacity factor.
+WORKLOADS = {
+    "flared_disc": dict(cfg=2, mode="mixed", stride=128, spill_per_ray=24, cpu_rays=240),
+    "exp_disc": dict(cfg=1, mode="mixed", stride=128, spill_per_ray=16, cpu_rays=600),
+    "clumpy": dict(cfg=3, mode="mixed", stride=128, spill_per_ray=48, persistent=True, cpu_rays=60),
+    "uniform_cube": dict(cfg=0, mode="fp64", stride=64, spill_per_ray=8, cpu_rays=10000),
+}
+
+
+def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str) -> float:
+    """Bytes the method must move for one launch, from the kernel counters
+    c = [segments, fallbacks, fp64 re-decisions, steps, records, ...].
+    Per step: the row range (8 B) and, per neighbour record read, its index
+    and site (4 + 24 B in FP64; 4 + 12 B FP32 offset in mixed mode, plus the
+    winner's FP64 site, 24 B, and the FP64 records of re-decided steps).
+    Per segment: the cell density (8 B) and the output (4 B cell + 8 B
+    length). Per ray: origin and direction (48 B), tau, count and status
+    (13 B)."""
+    seg, redo, steps, recs = float(c[0]), float(c[2]), float(c[3]), float(c[4])
+    per_step_recs = recs / max(steps, 1.0)
+    b = 8.0 * steps + 20.0 * seg + 61.0 * n_rays
+    if mode == "fp64":
+        b += 28.0 * recs
+    else:
+        b += 16.0 * recs + 24.0 * steps + 28.0 * redo * per_step_recs
+    return b
+
+
+def make_buffers(vrt, N, spec, torch, spill=None):
+    spill = int(N * spec["spill_per_ray"]) if spill is None else int(spill)
+    return vrt.TraceBuffers(N, seg_stride=spec["stride"], spill_capacity=spill)
+
+
+def prepare_buffers(vrt, torch, grid, o, d, rho, spec, mode=None):
+    """Output buffers for the workload: stride windows of the configured
+    size and a spill area sized up front from spill_per_ray and doubled
+    until a full step fits (set-up; the buffers are then reused)."""
+    mode = mode or spec["mode"]
+    N = o.shape[0]
+    spill = int(N * spec["spill_per_ray"])
+    while True:
+        bufs = make_buffers(vrt, N, spec, torch, spill)
+        vrt.trace_into(grid, o, d, rho, bufs, mode=mode, persistent=spec.get("persistent", False))
+        torch.cuda.synchronize()
+        if int(bufs.work[1].item()) <= spill:
+            return bufs
+        spill = 2 * int(bufs.work[1].item())
+        del bufs
+
+
+def run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, n, timed):
+    """Run n steps; with timed=True return per-step milliseconds (HIP events
+    on the stream the library launches on, i.e. torch's current stream)."""
+    times = []
+    stream = torch.cuda.current_stream()
+    for _ in range(n):
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        vrt.trace_into(grid, o, d, rho, bufs, mode=mode, persistent=spec.get("persistent", False))
+        if timed:
+            e1.record(stream)
+            times.append((e0, e1))
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in times]
+
+
+def cpu_baseline(w, spec, oracle):
+    """The oracle (FP64 brute force over all sites) on a bounded sample of
+    the same rays, with all host threads."""
+    n = min(spec["cpu_rays"], w.N)
+    sub = w.subsample(n, seed=123)
+    threads = oracle.get_threads()
+    t0 = time.perf_counter()
+    ref = oracle.trace(w.sites, w.box, w.density, sub.origins, sub.dirs, cap=4096, segments=True)
+    dt = time.perf_counter() - t0
+    crossings = int(ref["nseg"].sum())
+    return sub, ref, dict(value=crossings / dt, unit="crossings/s", cores=threads, kind="oracle",
+                          sample=f"{n} of the {w.N} rays (seeded subsample), {crossings} crossings in {dt:.1f} s")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="flared_disc", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--roofline-reps", type=int, default=5)
+    args = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the path is measured on one MI355X "
+                                   "(rays shard across GPUs with the grid replicated; see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1310_1854_amd import vrt, workloads
+
+    spec = WORKLOADS[args.workload]
+    mode = spec["mode"]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    w = workloads.make_config(spec["cfg"])
+    print(f"[bench] workload {w.name}: {w.M} sites, {w.N} rays ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    grid = vrt.build_grid(w.sites, w.box)
+    info = grid.info()
+    print(f"[bench] grid built in {info['build_ms']:.0f} ms, nnz {info['nnz']}", file=sys.stderr, flush=True)
+    o = torch.as_tensor(w.origins, device="cuda").contiguous()
+    d = torch.as_tensor(w.dirs, device="cuda").contiguous()
+    rho = torch.as_tensor(w.density, device="cuda").contiguous()
+    bufs = prepare_buffers(vrt, torch, grid, o, d, rho, spec)
+
+    # warmup, then K timed steps
+    run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, args.warmup, timed=False)
+    bufs.counters.zero_()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    step_ms = run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, args.steps, timed=True)
+    wall = time.perf_counter() - t_start
+    c = bufs.counters.cpu().numpy().astype(np.float64) / max(args.steps, 1)
+    status = np.bincount(bufs.status.cpu().numpy(), minlength=5)
+    spilled = int(bufs.work[2].item())
+    if status[vrt.RAY_OVERFLOW] or status[vrt.RAY_STEPLIMIT]:
+        raise SystemExit(f"incomplete output: status counts {status.tolist()}")
+    ms_per_step = wall * 1e3 / max(args.steps, 1)
+    crossings = c[0]
+    value = crossings / (ms_per_step / 1e3)
+    print(f"[bench] {mode}: {ms_per_step:.2f} ms/step, {crossings:.0f} crossings/step, {value:.3e}/s, "
+          f"spilled rays {spilled}", file=sys.stderr, flush=True)
+    tau_mixed = bufs.tau.clone()
+    nseg_mixed = bufs.n_seg.clone()
+
+    # the trace kernel alone (same windows, no spill) for the roofline
+    rb = vrt.TraceBuffers(w.N, seg_stride=spec["stride"])
+    rb.seg_cell, rb.seg_len = bufs.seg_cell, bufs.seg_len
+    run_steps(vrt, torch, grid, o, d, rho, rb, spec, mode, 1, timed=False)
+    rb.counters.zero_()
+    k_ms = run_steps(vrt, torch, grid, o, d, rho, rb, spec, mode, args.roofline_reps, timed=True)
+    kc = rb.counters.cpu().numpy().astype(np.float64) / args.roofline_reps
+    k_avg = float(np.mean(k_ms))
+    alg = algorithmic_bytes(kc, w.N, mode)
+    achieved = alg / (k_avg / 1e3) / 1e9
+    recs_per_step = kc[4] / max(kc[3], 1)
+
+    # FP64 on the same batch: rate, and equality of every ray's result
+    fb = prepare_buffers(vrt, torch, grid, o, d, rho, spec, mode="fp64")
+    run_steps(vrt, torch, grid, o, d, rho, fb, spec, "fp64", 1, timed=False)
+    fb.counters.zero_()
+    t1 = time.perf_counter()
+    f_ms = run_steps(vrt, torch, grid, o, d, rho, fb, spec, "fp64", max(2, args.steps // 2), timed=True)
+    f_wall = (time.perf_counter() - t1) / max(2, args.steps // 2)
+    fc = fb.counters.cpu().numpy().astype(np.float64) / max(2, args.steps // 2)
+    fp64_value = fc[0] / f_wall
+    same_tau = bool(torch.equal(fb.tau, tau_mixed))
+    same_nseg = bool(torch.equal(fb.n_seg, nseg_mixed))
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "crossings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if mode == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.M} sites, {w.N} rays, {mode} mode (configs[{spec['cfg']}])",
+                   "sites": w.M, "rays": w.N, "mode": mode, "seg_stride": spec["stride"],
+                   "persistent": bool(spec.get("persistent", False))},
+        "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)),
+        "crossings_per_step": crossings,
+        "spilled_rays_per_step": spilled,
+        "records_per_step": recs_per_step,
+        "fp64_redecision_rate": c[2] / max(c[3], 1),
+        "fp64_value": fp64_value,
+        "fp64_ms_per_step": f_wall * 1e3,
+        "mixed_vs_fp64": {"tau_bit_identical": same_tau, "n_seg_identical": same_nseg},
+        "grid": {"build_ms": info["build_ms"], "nnz": info["nnz"], "max_row": info["max_row"],
+                 "device_bytes": info["device_bytes"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_trace", "kernel_avg_ms": k_avg, "algorithmic_bytes": alg},
+    }
+    if not args.no_cpu:
+        import oracle
+        sub, ref, cpu = cpu_baseline(w, spec, oracle)
+        result["cpu_baseline"] = cpu
+        # accuracy on the sample: the same rays through the library
+        res = vrt.trace(grid, sub.origins, sub.dirs, w.density, mode=mode, segments="exact")
+        n_seg, get = vrt.gather_paths(res)
+        tau = res["tau"].cpu().numpy()
+        mism = 0
+        max_dl = max_dt = 0.0
+        for i in range(sub.N):
+            if ref["n_near"][i] > 0:
+                continue
+            cells, lens = get(i)
+            n = int(ref["nseg"][i])
+            if len(cells) != n or not np.array_equal(cells, ref["seg_cell"][i, :n]):
+                mism += 1
+                continue
+            if n:
+                max_dl = max(max_dl, float(np.max(np.abs(lens - ref["seg_len"][i, :n]))) / ref["chord"][i])
+            max_dt = max(max_dt, abs(tau[i] - ref["tau"][i]) / max(ref["tau"][i], 1e-300))
+        result["accuracy"] = {"oracle_sample_rays": int(sub.N), "near_tie_rays": int((ref["n_near"] > 0).sum()),
+                              "cell_sequence_mismatches": mism, "max_len_err_rel_chord": max_dl,
+                              "max_tau_err_rel": max_dt}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * voronoi_rt.h -- C ABI of libvoronoi_rt, straight paths through a
+ * box-clipped 3D Voronoi grid on an AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Camps, Baes & Saftly, "Using 3D Voronoi grids in
+ * radiative transfer simulations": a setup phase that keeps the domain box,
+ * the sites and per-site neighbour lists (Sect. 2.2, setup items 1-3), the
+ * cell-location function C(r) (Sect. 2.3), and the path loop that moves
+ * from cell to cell through the nearest bisector plane (Sect. 2.2, Eqs. 1-5).
+ *
+ * Conventions shared by every call:
+ *  - Every entry point returns a vor_status and never throws.
+ *  - Pointers documented as "device" are HIP device (or managed) memory on
+ *    the current device; "host" pointers are ordinary CPU memory.
+ *  - The caller owns every input and output buffer. A vor_grid owns its own
+ *    device arrays until vor_grid_free.
+ *  - Cells are identified by the 0-based index of their site in the caller's
+ *    site array ("user order"). Box walls are negative: -1 xmin, -2 xmax,
+ *    -3 ymin, -4 ymax, -5 zmin, -6 zmax.
+ *  - A box is 6 doubles {xmin, ymin, zmin, xmax, ymax, zmax}; it is closed.
+ *  - Point arrays are N x 3 row-major doubles (x, y, z per point).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it in order. vor_build_grid synchronises the stream
+ *    before it returns; vor_locate and vor_trace do not synchronise and
+ *    allocate nothing, so their results are ready when the stream is.
+ *  - Argument errors are reported before any device work is enqueued.
+ */
+#ifndef VORONOI_RT_H
+#define VORONOI_RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VOR_OK = 0,
+    VOR_EINVAL = 1,     /* a bad argument: NULL pointer, negative size, empty box, ... */
+    VOR_EDUP = 2,       /* two sites coincide */
+    VOR_EOUTSIDE = 3,   /* a site lies outside the box or is not finite */
+    VOR_ENOMEM = 4,     /* a device allocation failed */
+    VOR_EDEVICE = 5,    /* a HIP runtime call or kernel launch failed */
+    VOR_ECAPACITY = 6,  /* a cell needs more faces than the builder's fixed capacity */
+    VOR_EBUDGET = 7     /* a serving request exceeds the memory budget */
+} vor_status;
+
+/* Per-ray status written by vor_trace. */
+enum {
+    VOR_RAY_OK = 0,
+    VOR_RAY_OUTSIDE = 1,    /* origin outside the closed box: no path, cell -1 */
+    VOR_RAY_BADDIR = 2,     /* direction zero or not finite */
+    VOR_RAY_STEPLIMIT = 3,  /* the path needed more steps than max_steps */
+    VOR_RAY_OVERFLOW = 4    /* more segments than the ray's output capacity; counted, not stored */
+};
+
+enum {
+    VOR_WALL_XMIN = -1, VOR_WALL_XMAX = -2, VOR_WALL_YMIN = -3,
+    VOR_WALL_YMAX = -4, VOR_WALL_ZMIN = -5, VOR_WALL_ZMAX = -6
+};
+
+/* Arithmetic of the exit-point search. */
+enum {
+    VOR_MODE_FP64 = 0,  /* every bisector crossing in FP64 */
+    VOR_MODE_MIXED = 1  /* FP32 plane tests, FP64 re-decision of close calls and FP64 winner */
+};
+
+typedef struct vor_grid vor_grid;
+
+/* Options of vor_build_grid; zero-initialised fields take the defaults. */
+typedef struct {
+    double bucket_occupancy;  /* mean sites per bucket of the uniform site grid (default 2) */
+} vor_build_opts;
+
+/* Facts about a built grid, filled by vor_grid_get_info. */
+typedef struct {
+    int64_t n_sites;          /* M */
+    int64_t nnz;              /* total site-neighbour entries (walls excluded) */
+    int64_t nnz_with_walls;   /* entries of the vor_grid_neighbors export */
+    int32_t max_row;          /* longest site-neighbour list */
+    int32_t dims[3];          /* bucket grid */
+    double box[6];
+    double build_ms;          /* wall time of vor_build_grid */
+    int64_t device_bytes;     /* device memory held by the grid */
+} vor_grid_info;
+
+/*
+ * vor_build_grid -- setup phase of Sect. 2.2 (items 1-3): keeps the box and
+ * the sites and derives each site's neighbour list. The neighbours of site i
+ * are found by clipping the box with the bisector half-spaces of nearby
+ * sites (Sect. 2.1: a cell is the set of points at least as close to its
+ * site as to any other); candidates come from a uniform bucket grid in
+ * rings of increasing distance and the search stops when no farther site
+ * can cut the cell. Lists are symmetric and may hold degenerate contacts
+ * (an edge or vertex shared with a cell), which never change a path.
+ *   sites  device, M x 3, user order; read during the call only.
+ *   M      number of sites, >= 1 and < 2^31.
+ *   box    host, 6 doubles, xmin < xmax etc.; every site must lie inside.
+ *   opts   host, may be NULL.
+ *   out    host; receives the grid on VOR_OK, NULL otherwise.
+ * Errors: VOR_EINVAL, VOR_EOUTSIDE (a site outside the box or not finite),
+ * VOR_EDUP (coincident sites), VOR_ENOMEM, VOR_ECAPACITY, VOR_EDEVICE.
+ * Synchronises `stream` before returning.
+ */
+vor_status vor_build_grid(const double *sites, int64_t M, const double *box,
+                          const vor_build_opts *opts, void *stream, vor_grid **out);
+
+/* Releases every device array of the grid (synchronises the device first). NULL is a no-op. */
+void vor_grid_free(vor_grid *grid);
+
+/* Fills *info (host). */
+vor_status vor_grid_get_info(const vor_grid *grid, vor_grid_info *info);
+
+/*
+ * vor_grid_neighbors -- the neighbour lists of Sect. 2.2 item 3 in CSR form,
+ * user order, walls as negative codes (Sect. 2.2: walls are special
+ * negative indices). Row i lists, in increasing order, the neighbour cells
+ * of site i followed by its wall codes.
+ *   row_ptr  device, M + 1 int64 (row i spans [row_ptr[i], row_ptr[i+1])).
+ *   col      device, info.nnz_with_walls int32.
+ * Asynchronous on `stream`.
+ */
+vor_status vor_grid_neighbors(const vor_grid *grid, int64_t *row_ptr, int32_t *col, void *stream);
+
+/*
+ * vor_locate -- the function C(r) of Sect. 2.3: for each point the index of
+ * the cell containing it, i.e. of the nearest site (squared distances; equal
+ * distances go to the lowest index), or -1 for a point outside the closed box
+ * (step 1 there). Candidate sites come from the bucket grid in rings of
+ * increasing distance until no farther bucket can hold a nearer site.
+ *   pts   device, N x 3.     cell  device, N int32.    N >= 0.
+ * Asynchronous on `stream`; allocates nothing.
+ */
+vor_status vor_locate(const vor_grid *grid, const double *pts, int64_t N, int32_t *cell, void *stream);
+
+/* Options of vor_trace; zero-initialised fields take the defaults. */
+typedef struct {
+    int32_t mode;           /* VOR_MODE_FP64 (default) or VOR_MODE_MIXED */
+    int32_t max_steps;      /* per-ray cap on cell moves; 0 = M + 16 */
+    double eps_mix;         /* mixed mode: relative gap below which an FP32 decision is redone in FP64; 0 = 2^-12 */
+    int32_t persistent;     /* 1: persistent kernel whose waves refill finished lanes from a work queue */
+    int32_t reserved;
+} vor_trace_opts;
+
+/* Outputs of vor_trace. All pointers are device memory; tau and n_seg are required. */
+typedef struct {
+    double *tau;            /* [N] optical depth kappa * sum(rho_m * l_m) in path order */
+    int32_t *n_seg;         /* [N] number of segments of the full path (also past capacity) */
+    uint8_t *status;        /* [N] VOR_RAY_*; may be NULL */
+    int32_t *n_fallback;    /* [N] no-exit fallbacks taken (Sect. 2.2); may be NULL */
+    int32_t *seg_cell;      /* segment cells (user order); NULL = tau-only */
+    double *seg_len;        /* segment lengths; NULL with seg_cell NULL */
+    int64_t seg_stride;     /* > 0: ray i owns slots [i*seg_stride, (i+1)*seg_stride) */
+    const int64_t *ray_off; /* seg_stride == 0: ray i owns [ray_off[i], ray_off[i+1]) */
+    unsigned long long *counters; /* [8] accumulated: segments, fallbacks, FP64 re-decisions, steps,
+                                     neighbour records read, 3 reserved; may be NULL */
+    int64_t *work;          /* [4] control words, required for persistent mode and spill; zeroed by the call */
+    /* Spill (stride mode only, all NULL to disable): a ray whose path is
+     * longer than seg_stride keeps its first seg_stride segments in its
+     * window and is given spill_off[i] = the start of n_seg[i] - seg_stride
+     * slots in spill_cell/spill_len, where a second pass writes the rest of
+     * its path (spill_off[i] = -1 for rays that fit). If the spill is full
+     * the ray's status is VOR_RAY_OVERFLOW. spill_rays [N] is scratch;
+     * work[1] ends as the spill slots used and work[2] as the spilled rays. */
+    int64_t *spill_off;     /* [N] */
+    int32_t *spill_rays;    /* [N] */
+    int32_t *spill_cell;
+    double *spill_len;
+    int64_t spill_capacity; /* slots in spill_cell / spill_len */
+} vor_trace_out;
+
+/*
+ * vor_trace -- straight paths (Sect. 2.2). Each ray starts at origins[i]
+ * with direction dirs[i] (normalised here in FP64) and ends where it leaves
+ * the box (Eq. 5 on every axis). The start cell is C(r0) (Sect. 2.3). Each
+ * step evaluates, for every neighbour j of the current cell m whose bisector
+ * plane the ray approaches (n.k > 0, n = p_j - p_m, Eq. 1), the crossing
+ * s_j = n.((p_j + p_m)/2 - r0)/(n.k) (Eqs. 2-4, measured from the origin) and
+ * leaves the cell at the smallest one, or at the wall if that comes first.
+ * Segments of zero length are not emitted. Segment i of a ray is
+ * (seg_cell, seg_len) at slot base + i of the ray's window; cells are user
+ * indices.
+ *   origins, dirs  device, N x 3.    density  device, M doubles (user order), or NULL (tau = 0).
+ *   kappa          multiplies tau.   opts     host, may be NULL.
+ *   out            host struct of device pointers.
+ * Asynchronous on `stream`; allocates nothing. Per-ray problems are reported
+ * in out->status, not as a return code.
+ */
+vor_status vor_trace(const vor_grid *grid, const double *origins, const double *dirs, int64_t N,
+                     const double *density, double kappa, const vor_trace_opts *opts,
+                     const vor_trace_out *out, void *stream);
+
+/*
+ * vor_exclusive_scan -- offsets[0] = 0, offsets[i+1] = offsets[i] + counts[i]
+ * (int64), e.g. to turn a tau-only pass's n_seg into ray_off for an exact
+ * second pass. counts device N int32 (>= 0), offsets device N + 1 int64.
+ * Asynchronous; allocates nothing (tile totals are staged inside offsets).
+ */
+vor_status vor_exclusive_scan(const int32_t *counts, int64_t N, int64_t *offsets, void *stream);
+
+/* Static description of a status code. */
+const char *vor_status_str(vor_status s);
+
+/* Library version string. */
+const char *vor_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VORONOI_RT_H */

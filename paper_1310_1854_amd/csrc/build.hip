@@ -1,0 +1,609 @@
+// build.hip -- vor_build_grid: the setup phase of the straight-path method
+// (Sect. 2.2, setup items 1-3) on the GPU.
+//
+//  1. validate the sites and give each a 30-bit Hilbert key;
+//  2. radix-sort the sites into Hilbert order (internal order);
+//  3. bucket the sites into a uniform grid (stable radix sort by bucket);
+//  4. per site, clip the box by the bisector half-spaces of nearby sites,
+//     taken nearest-first from rings of buckets, until no farther site can
+//     cut the cell (its distance exceeds twice the largest vertex radius);
+//     the planes left bounding the cell are its neighbours (Sect. 2.1);
+//  5. make the lists symmetric, sort each row, and lay out the trace
+//     records (FP64 sites and FP32 offsets per neighbour, CSR by cell).
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "cell_clip.h"
+
+using namespace vrt;
+
+namespace {
+
+// Hilbert index of a point with kHilbertBits-bit integer coordinates, by
+// Skilling's transform ("Programming the Hilbert curve", AIP Conf. Proc.
+// 707, 2004): undo the excess work of the recursion, Gray-encode, then
+// interleave the bits of the three transposed coordinates.
+__device__ uint32_t hilbert_key(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint32_t X[3] = {x, y, z};
+    const uint32_t top = 1u << (kHilbertBits - 1);
+    for (uint32_t Q = top; Q > 1; Q >>= 1) {
+        uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = top; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint32_t key = 0;
+    for (int b = kHilbertBits - 1; b >= 0; --b)
+        key = (key << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) | ((X[2] >> b) & 1u);
+    return key;
+}
+
+
+__global__ void k_validate_keys(const double *__restrict__ sites, int64_t M, BoxArg box, double scale,
+                                uint32_t *__restrict__ keys, int32_t *__restrict__ vals, int *__restrict__ err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    uint32_t c[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        double x = sites[3 * i + a];
+        if (!(x >= box.lo[a] && x <= box.hi[a])) ok = false;   // also rejects NaN
+        double f = ok ? (x - box.lo[a]) * scale : 0.0;
+        int q = (int)f;
+        q = q < 0 ? 0 : (q > (1 << kHilbertBits) - 1 ? (1 << kHilbertBits) - 1 : q);
+        c[a] = (uint32_t)q;
+    }
+    if (!ok) atomicOr(err, ERR_OUTSIDE);
+    keys[i] = hilbert_key(c[0], c[1], c[2]);
+    vals[i] = (int32_t)i;
+}
+
+__global__ void k_gather_sites(const double *__restrict__ sites, const int32_t *__restrict__ order, int64_t M,
+                               Site *__restrict__ out, int32_t *__restrict__ perm, int32_t *__restrict__ inv_perm)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int32_t u = order[i];
+    Site s;
+    s.x = sites[3 * (int64_t)u];
+    s.y = sites[3 * (int64_t)u + 1];
+    s.z = sites[3 * (int64_t)u + 2];
+    s.uid = u;
+    out[i] = s;
+    perm[i] = u;
+    inv_perm[u] = (int32_t)i;
+}
+
+struct GridArg {
+    double lo[3];
+    double inv_h[3];
+    int32_t dims[3];
+};
+
+__global__ void k_bucket_keys(const Site *__restrict__ sites, int64_t M, GridArg g, uint32_t *__restrict__ keys,
+                              int32_t *__restrict__ vals, int32_t *__restrict__ counts)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    Site s = sites[i];
+    int bx = bucket_coord(s.x, g.lo[0], g.inv_h[0], g.dims[0]);
+    int by = bucket_coord(s.y, g.lo[1], g.inv_h[1], g.dims[1]);
+    int bz = bucket_coord(s.z, g.lo[2], g.inv_h[2], g.dims[2]);
+    uint32_t b = (uint32_t)((bz * g.dims[1] + by) * g.dims[0] + bx);
+    keys[i] = b;
+    vals[i] = (int32_t)i;
+    atomicAdd(&counts[b], 1);
+}
+
+__global__ void k_bucket_fill(const Site *__restrict__ sites, const int32_t *__restrict__ order, int64_t M,
+                              Site *__restrict__ out)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    int32_t i = order[k];
+    Site s = sites[i];
+    s.uid = (s.uid << 32) | (int64_t)(uint32_t)i;
+    out[k] = s;
+}
+
+struct ClipArgs {
+    const Site *sites;        // internal order
+    BucketGridView grid;
+    BoxArg box;
+    int64_t M;
+    int32_t *nbr;             // [M * kMaxNbr] first-pass lists
+    int32_t *cnt;             // [M]
+    uint8_t *walls;           // [M]
+    int32_t *retry;           // [M] sites whose cell needs the large capacity
+    int32_t *n_retry;
+    int *err;
+};
+
+// First pass: every site with a small cell; cells that run out of faces are
+// queued for the second pass.
+__global__ void __launch_bounds__(64) k_clip(ClipArgs A)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.M) return;
+    CellSmall c;
+    Cand cand[kMaxCand];
+    uint8_t wm = 0;
+    int n = clip_site(A.sites, A.grid, A.box, i, A.nbr + i * kMaxNbr, kMaxNbr, &wm, c, cand);
+    if (n == -ERR_CAPACITY) {
+        A.retry[atomicAdd(A.n_retry, 1)] = (int32_t)i;
+        n = 0;
+    } else if (n < 0) {
+        atomicOr(A.err, -n);
+        n = 0;
+    }
+    A.cnt[i] = n;
+    A.walls[i] = wm;
+}
+
+// Second pass over the queued sites, with large cells in a global workspace.
+__global__ void __launch_bounds__(64) k_clip_big(ClipArgs A, int32_t n_items, CellBig *__restrict__ cells,
+                                                 int32_t *__restrict__ big_nbr, int32_t *__restrict__ slot)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_items) return;
+    int64_t i = A.retry[k];
+    slot[i] = k;
+    Cand cand[kMaxCand];
+    uint8_t wm = 0;
+    int n = clip_site(A.sites, A.grid, A.box, i, big_nbr + (int64_t)k * kMaxNbrBig, kMaxNbrBig, &wm, cells[k], cand);
+    if (n < 0) {
+        atomicOr(A.err, -n);
+        n = 0;
+    }
+    A.cnt[i] = n;
+    A.walls[i] = wm;
+}
+
+// Directed lists -> CSR (dir_start from a scan of cnt). slot[i] >= 0 marks a
+// site redone by the second pass; its list is in big_nbr at that slot.
+__global__ void k_gather_dir(const int32_t *__restrict__ nbr, const int32_t *__restrict__ cnt,
+                             const int32_t *__restrict__ dir_start, const int32_t *__restrict__ slot, int64_t M,
+                             const int32_t *__restrict__ big_nbr, int32_t *__restrict__ dir_col)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int n = cnt[i];
+    int k = slot[i];
+    const int32_t *src = (k < 0) ? nbr + i * kMaxNbr : big_nbr + (int64_t)k * kMaxNbrBig;
+    int32_t *dst = dir_col + dir_start[i];
+    for (int e = 0; e < n; ++e) dst[e] = src[e];
+}
+
+__device__ __forceinline__ bool row_has(const int32_t *__restrict__ col, int s, int n, int32_t x)
+{
+    for (int e = 0; e < n; ++e)
+        if (col[s + e] == x) return true;
+    return false;
+}
+
+// For every directed entry i -> j whose reverse is missing, count an extra
+// entry for row j.
+__global__ void k_symm_count(const int32_t *__restrict__ dir_col, const int32_t *__restrict__ dir_start,
+                             const int32_t *__restrict__ cnt, int64_t M, int32_t *__restrict__ extra)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int s = dir_start[i], n = cnt[i];
+    for (int e = 0; e < n; ++e) {
+        int32_t j = dir_col[s + e];
+        if (!row_has(dir_col, dir_start[j], cnt[j], (int32_t)i)) atomicAdd(&extra[j], 1);
+    }
+}
+
+__global__ void k_total_counts(const int32_t *__restrict__ cnt, const int32_t *__restrict__ extra, int64_t M,
+                               int32_t *__restrict__ total)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    total[i] = cnt[i] + extra[i];
+}
+
+// Copy each directed row to the front of its final row; cursor = its length.
+__global__ void k_copy_rows(const int32_t *__restrict__ dir_col, const int32_t *__restrict__ dir_start,
+                            const int32_t *__restrict__ cnt, const int32_t *__restrict__ start, int64_t M,
+                            int32_t *__restrict__ col, int32_t *__restrict__ cursor)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int s = dir_start[i], n = cnt[i], o = start[i];
+    for (int e = 0; e < n; ++e) col[o + e] = dir_col[s + e];
+    cursor[i] = n;
+}
+
+// Append the missing reverse entries (same test as k_symm_count).
+__global__ void k_symm_fill(const int32_t *__restrict__ dir_col, const int32_t *__restrict__ dir_start,
+                            const int32_t *__restrict__ cnt, const int32_t *__restrict__ start, int64_t M,
+                            int32_t *__restrict__ col, int32_t *__restrict__ cursor)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int s = dir_start[i], n = cnt[i];
+    for (int e = 0; e < n; ++e) {
+        int32_t j = dir_col[s + e];
+        if (!row_has(dir_col, dir_start[j], cnt[j], (int32_t)i)) {
+            int pos = atomicAdd(&cursor[j], 1);
+            col[start[j] + pos] = (int32_t)i;
+        }
+    }
+}
+
+__global__ void k_row_sort(int32_t *__restrict__ col, const int32_t *__restrict__ start,
+                           const int32_t *__restrict__ total, int64_t M)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int32_t *row = col + start[i];
+    int n = total[i];
+    for (int a = 1; a < n; ++a) {
+        int32_t x = row[a];
+        int k = a - 1;
+        while (k >= 0 && row[k] > x) {
+            row[k + 1] = row[k];
+            --k;
+        }
+        row[k + 1] = x;
+    }
+}
+
+__device__ __forceinline__ int wave_max_int(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__restrict__ col,
+                               const int32_t *__restrict__ total, const int32_t *__restrict__ start, int64_t M,
+                               int2 *__restrict__ rows, Rec64 *__restrict__ r64, Rec32 *__restrict__ r32,
+                               int *__restrict__ max_row)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int n = 0;
+    if (i < M) {
+        n = total[i];
+        int s0 = start[i];
+        rows[i] = make_int2(s0, n);
+        const Site si = sites[i];
+        for (int e = 0; e < n; ++e) {
+            int32_t j = col[s0 + e];
+            const Site sj = sites[j];
+            Rec64 a;
+            a.x = sj.x;
+            a.y = sj.y;
+            a.z = sj.z;
+            a.j = j;
+            a.uid = (int32_t)sj.uid;
+            r64[s0 + e] = a;
+            Rec32 b;
+            b.nx = (float)(sj.x - si.x);
+            b.ny = (float)(sj.y - si.y);
+            b.nz = (float)(sj.z - si.z);
+            b.j = j;
+            r32[s0 + e] = b;
+        }
+    }
+    int m = wave_max_int(n);
+    if ((threadIdx.x & 63) == 0) atomicMax(max_row, m);
+}
+
+__global__ void k_export_counts(const int32_t *__restrict__ inv_perm, const int2 *__restrict__ rows,
+                                const uint8_t *__restrict__ walls, int64_t M, int32_t *__restrict__ cnt)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= M) return;
+    int32_t i = inv_perm[u];
+    cnt[u] = rows[i].y + __popc((unsigned)walls[i]);
+}
+
+__global__ void k_export_fill(const int32_t *__restrict__ inv_perm, const int32_t *__restrict__ perm,
+                              const int2 *__restrict__ rows, const Rec64 *__restrict__ r64,
+                              const uint8_t *__restrict__ walls, int64_t M, const int64_t *__restrict__ row_ptr,
+                              int32_t *__restrict__ col)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= M) return;
+    int32_t i = inv_perm[u];
+    int2 rw = rows[i];
+    int32_t *out = col + row_ptr[u];
+    for (int e = 0; e < rw.y; ++e) {
+        int32_t x = r64[rw.x + e].uid;
+        int k = e - 1;
+        while (k >= 0 && out[k] > x) {
+            out[k + 1] = out[k];
+            --k;
+        }
+        out[k + 1] = x;
+    }
+    int n = rw.y;
+    for (int w = 0; w < 6; ++w)
+        if ((walls[i] >> w) & 1) out[n++] = -(w + 1);
+}
+
+template <typename T>
+T *dalloc(size_t n, vor_status &st, std::vector<void *> &track)
+{
+    void *p = nullptr;
+    if (st != VOR_OK) return nullptr;
+    if (hipMalloc(&p, n * sizeof(T) > 0 ? n * sizeof(T) : 1) != hipSuccess) {
+        st = VOR_ENOMEM;
+        return nullptr;
+    }
+    track.push_back(p);
+    return (T *)p;
+}
+
+unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace
+
+struct vor_grid {
+    vrt::Grid g;
+};
+
+extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const double *box, const vor_build_opts *opts,
+                                     void *stream, vor_grid **out)
+{
+    if (out) *out = nullptr;
+    if (!sites || !box || !out || M < 1 || M >= 0x7fffffffLL) return VOR_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(box[a]) || !std::isfinite(box[a + 3]) || !(box[a] < box[a + 3])) return VOR_EINVAL;
+    double occ = (opts && opts->bucket_occupancy > 0) ? opts->bucket_occupancy : 2.0;
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+
+    vor_grid *G = new (std::nothrow) vor_grid;
+    if (!G) return VOR_ENOMEM;
+    Grid &g = G->g;
+    (void)hipGetDevice(&g.device);
+    g.M = M;
+    for (int a = 0; a < 6; ++a) g.box[a] = box[a];
+
+    vor_status rc = VOR_OK;
+    std::vector<void *> tmp, keep;
+    BoxArg ba;
+    for (int a = 0; a < 3; ++a) {
+        ba.lo[a] = box[a];
+        ba.hi[a] = box[a + 3];
+    }
+    double ext = std::max(box[3] - box[0], std::max(box[4] - box[1], box[5] - box[2]));
+    double hscale = (double)(1 << kHilbertBits) / ext;
+
+    int64_t hist_len = vrt_radix_hist_len(M);
+    uint32_t *keys = dalloc<uint32_t>(M, rc, tmp);
+    int32_t *vals = dalloc<int32_t>(M, rc, tmp);
+    uint32_t *keys2 = dalloc<uint32_t>(M, rc, tmp);
+    int32_t *vals2 = dalloc<int32_t>(M, rc, tmp);
+    int32_t *hist = dalloc<int32_t>(2 * hist_len + 1, rc, tmp);
+    int *err = dalloc<int>(4, rc, tmp);
+    g.sites = dalloc<Site>(M, rc, keep);
+    g.perm = dalloc<int32_t>(M, rc, keep);
+    g.inv_perm = dalloc<int32_t>(M, rc, keep);
+    g.wall_mask = dalloc<uint8_t>(M, rc, keep);
+    g.bucket_sites = dalloc<Site>(M, rc, keep);
+
+    // bucket grid dimensions: about `occ` sites per bucket, cube-like buckets
+    double vol = (box[3] - box[0]) * (box[4] - box[1]) * (box[5] - box[2]);
+    double hb = std::cbrt(vol * occ / (double)M);
+    int64_t B = 1;
+    for (int a = 0; a < 3; ++a) {
+        double e = box[a + 3] - box[a];
+        int n = (int)std::ceil(e / hb);
+        n = std::max(1, std::min(n, 1024));
+        g.dims[a] = n;
+        g.h[a] = e / n;
+        g.inv_h[a] = n / e;
+        B *= n;
+    }
+    int32_t *bcount = dalloc<int32_t>(B, rc, tmp);
+    g.bucket_start = dalloc<int32_t>(B + 1, rc, keep);
+    int32_t *nbr0 = dalloc<int32_t>((size_t)M * kMaxNbr, rc, tmp);
+    int32_t *cnt0 = dalloc<int32_t>(M, rc, tmp);
+    int32_t *retry = dalloc<int32_t>(M, rc, tmp);
+    int32_t *slot = dalloc<int32_t>(M, rc, tmp);
+    int32_t *dir_start = dalloc<int32_t>(M + 1, rc, tmp);
+    int32_t *extra = dalloc<int32_t>(M, rc, tmp);
+    int32_t *total = dalloc<int32_t>(M, rc, tmp);
+    int32_t *start = dalloc<int32_t>(M + 1, rc, tmp);
+    int *hdr = nullptr;
+
+    auto fail = [&](vor_status s) {
+        (void)hipStreamSynchronize(st);
+        for (void *p : tmp) (void)hipFree(p);
+        for (void *p : keep) (void)hipFree(p);
+        delete G;
+        return s;
+    };
+    if (rc != VOR_OK) return fail(rc);
+    if (hipMemsetAsync(err, 0, 4 * sizeof(int), st) != hipSuccess) return fail(VOR_EDEVICE);
+
+    const int T = 256;
+    hipLaunchKernelGGL(k_validate_keys, dim3(blocks_for(M, T)), dim3(T), 0, st, sites, M, ba, hscale, keys, vals, err);
+    int herr = 0;
+    if (hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VOR_EDEVICE);
+    if (herr & ERR_OUTSIDE) return fail(VOR_EOUTSIDE);
+
+    rc = vrt_radix_sort_pairs(keys, vals, keys2, vals2, M, 3 * kHilbertBits, hist, hist_len, st);
+    if (rc != VOR_OK) return fail(rc);
+    hipLaunchKernelGGL(k_gather_sites, dim3(blocks_for(M, T)), dim3(T), 0, st, sites, vals, M, g.sites, g.perm,
+                       g.inv_perm);
+
+    // bucket the Hilbert-ordered sites (stable: within a bucket, Hilbert order)
+    GridArg ga;
+    for (int a = 0; a < 3; ++a) {
+        ga.lo[a] = box[a];
+        ga.inv_h[a] = g.inv_h[a];
+        ga.dims[a] = g.dims[a];
+    }
+    if (hipMemsetAsync(bcount, 0, sizeof(int32_t) * B, st) != hipSuccess) return fail(VOR_EDEVICE);
+    hipLaunchKernelGGL(k_bucket_keys, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, M, ga, keys, vals, bcount);
+    int bbits = 1;
+    while ((1ll << bbits) < B) ++bbits;
+    rc = vrt_radix_sort_pairs(keys, vals, keys2, vals2, M, bbits, hist, hist_len, st);
+    if (rc != VOR_OK) return fail(rc);
+    rc = vrt_scan_i32_to_i32(bcount, B, g.bucket_start, st);
+    if (rc != VOR_OK) return fail(rc);
+    hipLaunchKernelGGL(k_bucket_fill, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, vals, M, g.bucket_sites);
+
+    // clip every cell: small cells first, the overflowing ones again with large cells
+    ClipArgs ca;
+    ca.sites = g.sites;
+    ca.grid = bucket_view(g);
+    ca.box = ba;
+    ca.M = M;
+    ca.nbr = nbr0;
+    ca.cnt = cnt0;
+    ca.walls = g.wall_mask;
+    ca.retry = retry;
+    ca.n_retry = err + 2;
+    ca.err = err;
+    if (hipMemsetAsync(slot, 0xff, sizeof(int32_t) * M, st) != hipSuccess) return fail(VOR_EDEVICE);
+    hipLaunchKernelGGL(k_clip, dim3(blocks_for(M, 64)), dim3(64), 0, st, ca);
+    if (hipGetLastError() != hipSuccess) return fail(VOR_EDEVICE);
+    int hflags[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(hflags, err, 4 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VOR_EDEVICE);
+    if (hflags[0] & ERR_DUP) return fail(VOR_EDUP);
+    if (hflags[0] & (ERR_CAPACITY | ERR_DEGENERATE)) return fail(VOR_ECAPACITY);
+    const int n_retry = hflags[2];
+    int32_t *big_nbr = nullptr;
+    if (n_retry > 0) {
+        CellBig *cells = dalloc<CellBig>(n_retry, rc, tmp);
+        big_nbr = dalloc<int32_t>((size_t)n_retry * kMaxNbrBig, rc, tmp);
+        if (rc != VOR_OK) return fail(rc);
+        hipLaunchKernelGGL(k_clip_big, dim3(blocks_for(n_retry, 64)), dim3(64), 0, st, ca, n_retry, cells, big_nbr,
+                           slot);
+        if (hipMemcpyAsync(hflags, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(VOR_EDEVICE);
+        if (hflags[0] & ERR_DUP) return fail(VOR_EDUP);
+        if (hflags[0] & (ERR_CAPACITY | ERR_DEGENERATE)) return fail(VOR_ECAPACITY);
+    }
+    g.n_big = n_retry;
+
+    // directed lists as CSR
+    rc = vrt_scan_i32_to_i32(cnt0, M, dir_start, st);
+    if (rc != VOR_OK) return fail(rc);
+    int32_t nnz_dir = 0;
+    if (hipMemcpyAsync(&nnz_dir, dir_start + M, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VOR_EDEVICE);
+    int32_t *dir_col = dalloc<int32_t>(std::max<int32_t>(nnz_dir, 1), rc, tmp);
+    if (rc != VOR_OK) return fail(rc);
+    hipLaunchKernelGGL(k_gather_dir, dim3(blocks_for(M, T)), dim3(T), 0, st, nbr0, cnt0, dir_start, slot, M, big_nbr,
+                       dir_col);
+
+    // symmetric lists: add the reverse of every one-sided entry, sort rows
+    if (hipMemsetAsync(extra, 0, sizeof(int32_t) * M, st) != hipSuccess) return fail(VOR_EDEVICE);
+    hipLaunchKernelGGL(k_symm_count, dim3(blocks_for(M, T)), dim3(T), 0, st, dir_col, dir_start, cnt0, M, extra);
+    hipLaunchKernelGGL(k_total_counts, dim3(blocks_for(M, T)), dim3(T), 0, st, cnt0, extra, M, total);
+    rc = vrt_scan_i32_to_i32(total, M, start, st);
+    if (rc != VOR_OK) return fail(rc);
+    int32_t nnz32 = 0;
+    if (hipMemcpyAsync(&nnz32, start + M, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VOR_EDEVICE);
+    g.nnz = nnz32;
+    int32_t *col = dalloc<int32_t>(std::max<int32_t>(nnz32, 1), rc, tmp);
+    if (rc != VOR_OK) return fail(rc);
+    hipLaunchKernelGGL(k_copy_rows, dim3(blocks_for(M, T)), dim3(T), 0, st, dir_col, dir_start, cnt0, start, M, col,
+                       extra);
+    hipLaunchKernelGGL(k_symm_fill, dim3(blocks_for(M, T)), dim3(T), 0, st, dir_col, dir_start, cnt0, start, M, col,
+                       extra);
+    hipLaunchKernelGGL(k_row_sort, dim3(blocks_for(M, T)), dim3(T), 0, st, col, start, total, M);
+
+    g.rows = dalloc<int2>(M, rc, keep);
+    g.rec64 = dalloc<Rec64>(std::max<int64_t>(g.nnz, 1), rc, keep);
+    g.rec32 = dalloc<Rec32>(std::max<int64_t>(g.nnz, 1), rc, keep);
+    if (rc != VOR_OK) return fail(rc);
+    hdr = err + 1;   // longest row
+    hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, col, total, start, M, g.rows,
+                       g.rec64, g.rec32, hdr);
+    // size of the export with walls
+    hipLaunchKernelGGL(k_export_counts, dim3(blocks_for(M, T)), dim3(T), 0, st, g.inv_perm, g.rows, g.wall_mask, M,
+                       total);
+    rc = vrt_scan_i32_to_i32(total, M, start, st);
+    if (rc != VOR_OK) return fail(rc);
+    int32_t nnzw = 0, mrow = 0;
+    if (hipMemcpyAsync(&nnzw, start + M, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&mrow, hdr, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
+        return fail(VOR_EDEVICE);
+    g.nnz_walls = nnzw;
+    g.max_row = mrow;
+
+    for (void *p : tmp) (void)hipFree(p);
+    g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2)) + (B + 1) * 4 +
+                     g.nnz * (int64_t)(sizeof(Rec64) + sizeof(Rec32));
+    g.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = G;
+    return VOR_OK;
+}
+
+extern "C" void vor_grid_free(vor_grid *G)
+{
+    if (!G) return;
+    (void)hipDeviceSynchronize();
+    Grid &g = G->g;
+    void *ptrs[] = {g.sites, g.perm, g.inv_perm, g.rows, g.rec64, g.rec32, g.wall_mask, g.bucket_start, g.bucket_sites};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete G;
+}
+
+extern "C" vor_status vor_grid_get_info(const vor_grid *G, vor_grid_info *info)
+{
+    if (!G || !info) return VOR_EINVAL;
+    const Grid &g = G->g;
+    info->n_sites = g.M;
+    info->nnz = g.nnz;
+    info->nnz_with_walls = g.nnz_walls;
+    info->max_row = g.max_row;
+    for (int a = 0; a < 3; ++a) info->dims[a] = g.dims[a];
+    for (int a = 0; a < 6; ++a) info->box[a] = g.box[a];
+    info->build_ms = g.build_ms;
+    info->device_bytes = g.device_bytes;
+    return VOR_OK;
+}
+
+extern "C" vor_status vor_grid_neighbors(const vor_grid *G, int64_t *row_ptr, int32_t *col, void *stream)
+{
+    if (!G || !row_ptr || (!col && G->g.nnz_walls > 0)) return VOR_EINVAL;
+    const Grid &g = G->g;
+    hipStream_t st = (hipStream_t)stream;
+    // per-row counts are staged in col, which holds at least M entries
+    // (every clipped cell has at least one face)
+    if (g.nnz_walls < g.M) return VOR_EINVAL;
+    const int T = 256;
+    hipLaunchKernelGGL(k_export_counts, dim3(blocks_for(g.M, T)), dim3(T), 0, st, g.inv_perm, g.rows, g.wall_mask,
+                       g.M, col);
+    vor_status rc = vrt_scan_i32_to_i64(col, g.M, row_ptr, st);
+    if (rc != VOR_OK) return rc;
+    hipLaunchKernelGGL(k_export_fill, dim3(blocks_for(g.M, T)), dim3(T), 0, st, g.inv_perm, g.perm, g.rows, g.rec64,
+                       g.wall_mask, g.M, row_ptr, col);
+    return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
+}
+
+// accessor for the other translation units
+const vrt::Grid &vrt_grid_of(const vor_grid *G) { return G->g; }

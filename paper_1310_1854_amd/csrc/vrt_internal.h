@@ -1,0 +1,194 @@
+// vrt_internal.h -- device data layout and helpers shared by the HIP sources
+// of libvoronoi_rt. Not part of the public ABI (include/voronoi_rt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define VRT_HD __host__ __device__
+
+#include "../../include/voronoi_rt.h"
+
+namespace vrt {
+
+// FP64 neighbour record: the neighbour's site, its internal (Hilbert-order)
+// index and its user index. A row of these per cell is all the exit-point
+// search reads (Sect. 2.2: the current cell's neighbour indices and sites).
+struct __align__(32) Rec64 {
+    double x, y, z;
+    int32_t j;    // internal index of the neighbour
+    int32_t uid;  // user index of the neighbour
+};
+
+// FP32 neighbour record of the mixed-precision search: the offset
+// p_j - p_m rounded to FP32 and the neighbour's internal index.
+struct __align__(16) Rec32 {
+    float nx, ny, nz;
+    int32_t j;
+};
+
+// Site in internal order with its user index (the w slot holds the index
+// bits so that one 32-byte load fetches both).
+struct __align__(32) Site {
+    double x, y, z;
+    int64_t uid;
+};
+
+struct Grid {
+    int64_t M = 0;
+    int64_t nnz = 0;
+    int64_t nnz_walls = 0;
+    int32_t max_row = 0;
+    int32_t n_big = 0;     // cells built with the large capacity
+    double box[6];
+    // uniform bucket grid of sites
+    int32_t dims[3];
+    double inv_h[3];   // buckets per unit length on each axis
+    double h[3];       // bucket side on each axis
+    // device arrays (internal order unless stated)
+    Site *sites = nullptr;          // [M]
+    int32_t *perm = nullptr;        // [M] internal -> user
+    int32_t *inv_perm = nullptr;    // [M] user -> internal
+    int2 *rows = nullptr;           // [M] {start, count} into rec64/rec32
+    Rec64 *rec64 = nullptr;         // [nnz]
+    Rec32 *rec32 = nullptr;         // [nnz]
+    uint8_t *wall_mask = nullptr;   // [M] bit w set if wall -(w+1) is a face
+    int32_t *bucket_start = nullptr;// [B + 1]
+    Site *bucket_sites = nullptr;   // [M] sites grouped by bucket (uid holds the internal index)
+    double build_ms = 0;
+    int64_t device_bytes = 0;
+    int device = 0;
+};
+
+// Per-ray status codes (same values as VOR_RAY_*).
+constexpr uint8_t RAY_OK = 0, RAY_OUTSIDE = 1, RAY_BADDIR = 2, RAY_STEPLIMIT = 3, RAY_OVERFLOW = 4;
+
+// Bucket coordinate of a point on one axis, clamped to the grid.
+VRT_HD inline int bucket_coord(double x, double lo, double inv_h, int n)
+{
+    int b = (int)floor((x - lo) * inv_h);
+    return b < 0 ? 0 : (b >= n ? n - 1 : b);
+}
+
+struct BucketGridView {
+    double lo[3];
+    double hi[3];
+    double inv_h[3];
+    double h[3];
+    int32_t dims[3];
+    const int32_t *start;
+    const Site *items;
+};
+
+inline BucketGridView bucket_view(const Grid &g)
+{
+    BucketGridView v;
+    for (int a = 0; a < 3; ++a) {
+        v.lo[a] = g.box[a];
+        v.hi[a] = g.box[a + 3];
+        v.inv_h[a] = g.inv_h[a];
+        v.h[a] = g.h[a];
+        v.dims[a] = g.dims[a];
+    }
+    v.start = g.bucket_start;
+    v.items = g.bucket_sites;
+    return v;
+}
+
+// Lower bound on the distance from q to any point of the grid outside the
+// block of buckets within Chebyshev distance r of bucket b. Sides of the
+// block that reach the edge of the grid hold nothing beyond them and impose
+// no bound; if every side does, the block covers the grid (returns -1).
+VRT_HD inline double shell_bound(const BucketGridView &g, const double q[3], const int b[3], int r)
+{
+    double lb = 1e308;
+    bool open = false;
+    for (int a = 0; a < 3; ++a) {
+        if (b[a] - r > 0) {
+            double face = g.lo[a] + (double)(b[a] - r) * g.h[a];
+            double d = q[a] - face;
+            lb = fmin(lb, d);
+            open = true;
+        }
+        if (b[a] + r < g.dims[a] - 1) {
+            double face = g.lo[a] + (double)(b[a] + r + 1) * g.h[a];
+            double d = face - q[a];
+            lb = fmin(lb, d);
+            open = true;
+        }
+    }
+    if (!open) return -1.0;
+    return lb < 0.0 ? 0.0 : lb;
+}
+
+// Visit every bucket at Chebyshev distance exactly r from b (clipped to the
+// grid) and call f(bucket_linear_index).
+template <typename F>
+VRT_HD inline void for_shell(const BucketGridView &g, const int b[3], int r, F &&f)
+{
+    const int nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
+    int z0 = b[2] - r > 0 ? b[2] - r : 0, z1 = b[2] + r < nz - 1 ? b[2] + r : nz - 1;
+    int y0 = b[1] - r > 0 ? b[1] - r : 0, y1 = b[1] + r < ny - 1 ? b[1] + r : ny - 1;
+    int x0 = b[0] - r > 0 ? b[0] - r : 0, x1 = b[0] + r < nx - 1 ? b[0] + r : nx - 1;
+    for (int z = z0; z <= z1; ++z) {
+        bool zface = (z == b[2] - r) || (z == b[2] + r);
+        for (int y = y0; y <= y1; ++y) {
+            bool yface = (y == b[1] - r) || (y == b[1] + r);
+            if (zface || yface || r == 0) {
+                for (int x = x0; x <= x1; ++x) f((z * ny + y) * nx + x);
+            } else {
+                if (b[0] - r >= 0) f((z * ny + y) * nx + (b[0] - r));
+                if (b[0] + r <= nx - 1 && r > 0) f((z * ny + y) * nx + (b[0] + r));
+            }
+        }
+    }
+}
+
+// Exact nearest site (internal index) by ring search; squared distances in
+// the same operation order as a plain (x-p)^2 sum; equal distances go to
+// the lower user index. q must be inside the box.
+VRT_HD inline int32_t nearest_site(const BucketGridView &g, const double q[3], int32_t *uid_out)
+{
+    int b[3];
+    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], g.lo[a], g.inv_h[a], g.dims[a]);
+    double best = 1e308 * 10.0;  // +inf
+    int32_t best_i = -1;
+    int32_t best_u = 0x7fffffff;
+    for (int r = 0;; ++r) {
+        for_shell(g, b, r, [&](int bk) {
+            int s0 = g.start[bk], s1 = g.start[bk + 1];
+            for (int s = s0; s < s1; ++s) {
+                Site p = g.items[s];
+                double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
+                double d = dx * dx + dy * dy + dz * dz;
+                int32_t idx = (int32_t)(p.uid & 0xffffffff);
+                int32_t uid = (int32_t)(p.uid >> 32);
+                if (d < best || (d == best && uid < best_u)) {
+                    best = d;
+                    best_i = idx;
+                    best_u = uid;
+                }
+            }
+        });
+        double lb = shell_bound(g, q, b, r);
+        if (lb < 0.0) break;
+        // sites outside the block are at least lb away; the slack keeps a
+        // rounding of lb from ending the search early
+        double lb2 = lb * lb * (1.0 - 1e-12);
+        if (best < lb2) break;
+    }
+    if (uid_out) *uid_out = best_u;
+    return best_i;
+}
+
+inline bool cuda_ok(hipError_t e) { return e == hipSuccess; }
+
+}  // namespace vrt
+
+// scan.hip
+vor_status vrt_scan_i32_to_i64(const int32_t *counts, int64_t N, int64_t *offsets, hipStream_t st);
+vor_status vrt_scan_i32_to_i32(const int32_t *counts, int64_t N, int32_t *offsets, hipStream_t st);
+// sort.hip: stable LSD radix sort of (key, value) pairs, 32-bit keys of `bits` significant bits
+vor_status vrt_radix_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tmp, int32_t *vals_tmp,
+                                int64_t n, int bits, int32_t *hist_scratch, int64_t hist_len, hipStream_t st);
+int64_t vrt_radix_hist_len(int64_t n);

@@ -1,0 +1,324 @@
+"""ctypes binding of libvoronoi_rt (include/voronoi_rt.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+torch supplies device memory (tensors) and the current HIP stream. torch is
+imported before the library is loaded so that both use one HIP runtime.
+
+Names mirror the C ABI: ``build_grid``, ``locate``, ``trace``,
+``exclusive_scan``; ``Grid`` owns a ``vor_grid*``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvoronoi_rt.so")
+
+VOR_OK, VOR_EINVAL, VOR_EDUP, VOR_EOUTSIDE, VOR_ENOMEM, VOR_EDEVICE, VOR_ECAPACITY, VOR_EBUDGET = range(8)
+RAY_OK, RAY_OUTSIDE, RAY_BADDIR, RAY_STEPLIMIT, RAY_OVERFLOW = range(5)
+MODES = {"fp64": 0, "mixed": 1}
+
+# every symbol include/voronoi_rt.h declares
+EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_neighbors", "vor_locate",
+           "vor_trace", "vor_exclusive_scan", "vor_status_str", "vor_version"]
+
+
+class VorError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {status_str(code)} ({code})")
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("bucket_occupancy", ctypes.c_double)]
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int64), ("nnz", ctypes.c_int64), ("nnz_with_walls", ctypes.c_int64),
+                ("max_row", ctypes.c_int32), ("dims", ctypes.c_int32 * 3), ("box", ctypes.c_double * 6),
+                ("build_ms", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+class TraceOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("max_steps", ctypes.c_int32), ("eps_mix", ctypes.c_double),
+                ("persistent", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class TraceOut(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_void_p), ("n_seg", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("n_fallback", ctypes.c_void_p), ("seg_cell", ctypes.c_void_p), ("seg_len", ctypes.c_void_p),
+                ("seg_stride", ctypes.c_int64), ("ray_off", ctypes.c_void_p), ("counters", ctypes.c_void_p),
+                ("work", ctypes.c_void_p), ("spill_off", ctypes.c_void_p), ("spill_rays", ctypes.c_void_p),
+                ("spill_cell", ctypes.c_void_p), ("spill_len", ctypes.c_void_p), ("spill_capacity", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built (there is no
+    CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libvoronoi_rt.so not built at {path}; run paper_1310_1854_amd.build_lib")
+    lib = ctypes.CDLL(path)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.vor_build_grid.argtypes = [P, I64, P, P, P, ctypes.POINTER(P)]
+    lib.vor_build_grid.restype = ctypes.c_int
+    lib.vor_grid_free.argtypes = [P]
+    lib.vor_grid_free.restype = None
+    lib.vor_grid_get_info.argtypes = [P, ctypes.POINTER(GridInfo)]
+    lib.vor_grid_get_info.restype = ctypes.c_int
+    lib.vor_grid_neighbors.argtypes = [P, P, P, P]
+    lib.vor_grid_neighbors.restype = ctypes.c_int
+    lib.vor_locate.argtypes = [P, P, I64, P, P]
+    lib.vor_locate.restype = ctypes.c_int
+    lib.vor_trace.argtypes = [P, P, P, I64, P, D, ctypes.POINTER(TraceOpts), ctypes.POINTER(TraceOut), P]
+    lib.vor_trace.restype = ctypes.c_int
+    lib.vor_exclusive_scan.argtypes = [P, I64, P, P]
+    lib.vor_exclusive_scan.restype = ctypes.c_int
+    lib.vor_status_str.argtypes = [ctypes.c_int]
+    lib.vor_status_str.restype = ctypes.c_char_p
+    lib.vor_version.argtypes = []
+    lib.vor_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    return load().vor_status_str(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != VOR_OK:
+        raise VorError(code, what)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f64(x, shape_last=None, device=None) -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=torch.float64, device=device or "cuda")
+    t = t.contiguous()
+    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
+        raise ValueError(f"expected an (N, {shape_last}) array")
+    return t
+
+
+class Grid:
+    """A built grid (owns the library's vor_grid)."""
+
+    def __init__(self, handle: int, M: int, box):
+        self._h = ctypes.c_void_p(handle)
+        self.M = M
+        self.box = [float(b) for b in box]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = GridInfo()
+        _check(load().vor_grid_get_info(self._h, ctypes.byref(inf)), "vor_grid_get_info")
+        return dict(n_sites=inf.n_sites, nnz=inf.nnz, nnz_with_walls=inf.nnz_with_walls, max_row=inf.max_row,
+                    dims=list(inf.dims), box=list(inf.box), build_ms=inf.build_ms, device_bytes=inf.device_bytes)
+
+    def neighbors(self, stream=None):
+        """(row_ptr int64[M+1], col int32[nnz]) in user order, walls as -1..-6."""
+        inf = self.info()
+        row_ptr = torch.empty(self.M + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(max(inf["nnz_with_walls"], 1), dtype=torch.int32, device="cuda")
+        _check(load().vor_grid_neighbors(self._h, _ptr(row_ptr), _ptr(col), _stream(stream)), "vor_grid_neighbors")
+        return row_ptr, col[: inf["nnz_with_walls"]]
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            load().vor_grid_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+def build_grid(sites, box: Sequence[float], bucket_occupancy: float = 0.0, stream=None) -> Grid:
+    sites_d = _dev_f64(sites, 3)
+    box_h = (ctypes.c_double * 6)(*[float(b) for b in box])
+    opts = BuildOpts(float(bucket_occupancy))
+    h = ctypes.c_void_p()
+    _check(load().vor_build_grid(_ptr(sites_d), sites_d.shape[0], box_h, ctypes.byref(opts), _stream(stream),
+                                 ctypes.byref(h)), "vor_build_grid")
+    return Grid(h.value, sites_d.shape[0], box)
+
+
+def locate(grid: Grid, pts, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    p = _dev_f64(pts, 3)
+    n = p.shape[0]
+    cell = out if out is not None else torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(load().vor_locate(grid.handle, _ptr(p), n, _ptr(cell), _stream(stream)), "vor_locate")
+    return cell
+
+
+def exclusive_scan(counts: torch.Tensor, stream=None) -> torch.Tensor:
+    c = counts.to(dtype=torch.int32).contiguous()
+    off = torch.empty(c.numel() + 1, dtype=torch.int64, device=c.device)
+    _check(load().vor_exclusive_scan(_ptr(c), c.numel(), _ptr(off), _stream(stream)), "vor_exclusive_scan")
+    return off
+
+
+COUNTERS = ["segments", "fallbacks", "fp64_redecisions", "steps", "records", "r5", "r6", "r7"]
+
+
+class TraceBuffers:
+    """Preallocated outputs of ``trace`` for N rays (reused across calls).
+
+    seg_stride > 0: fixed windows of seg_stride slots per ray; with
+    spill_capacity > 0 longer paths go whole to a spill area (spill_off).
+    total_segments > 0 (and seg_stride 0): exact CSR windows from ray_off."""
+
+    def __init__(self, N: int, seg_stride: int = 0, total_segments: int = 0, spill_capacity: int = 0,
+                 device="cuda", counters=True):
+        self.N = N
+        self.tau = torch.empty(N, dtype=torch.float64, device=device)
+        self.n_seg = torch.empty(N, dtype=torch.int32, device=device)
+        self.status = torch.empty(N, dtype=torch.uint8, device=device)
+        self.n_fallback = torch.empty(N, dtype=torch.int32, device=device)
+        self.seg_stride = int(seg_stride)
+        nslots = N * self.seg_stride if self.seg_stride > 0 else int(total_segments)
+        want_segs = self.seg_stride > 0 or total_segments > 0
+        self.seg_cell = torch.empty(max(nslots, 1), dtype=torch.int32, device=device) if want_segs else None
+        self.seg_len = torch.empty(max(nslots, 1), dtype=torch.float64, device=device) if want_segs else None
+        self.ray_off: Optional[torch.Tensor] = None
+        self.counters = torch.zeros(8, dtype=torch.int64, device=device) if counters else None
+        self.work = torch.zeros(4, dtype=torch.int64, device=device)
+        self.spill_capacity = int(spill_capacity) if self.seg_stride > 0 else 0
+        if self.spill_capacity > 0:
+            self.spill_off = torch.empty(N, dtype=torch.int64, device=device)
+            self.spill_rays = torch.empty(N, dtype=torch.int32, device=device)
+            self.spill_cell = torch.empty(self.spill_capacity, dtype=torch.int32, device=device)
+            self.spill_len = torch.empty(self.spill_capacity, dtype=torch.float64, device=device)
+        else:
+            self.spill_off = self.spill_rays = self.spill_cell = self.spill_len = None
+
+    def struct(self) -> TraceOut:
+        o = TraceOut()
+        o.tau = self.tau.data_ptr()
+        o.n_seg = self.n_seg.data_ptr()
+        o.status = self.status.data_ptr()
+        o.n_fallback = self.n_fallback.data_ptr()
+        o.seg_cell = self.seg_cell.data_ptr() if self.seg_cell is not None else None
+        o.seg_len = self.seg_len.data_ptr() if self.seg_len is not None else None
+        o.seg_stride = self.seg_stride if self.seg_cell is not None else 0
+        o.ray_off = self.ray_off.data_ptr() if self.ray_off is not None else None
+        o.counters = self.counters.data_ptr() if self.counters is not None else None
+        o.work = self.work.data_ptr()
+        if self.spill_capacity > 0:
+            o.spill_off = self.spill_off.data_ptr()
+            o.spill_rays = self.spill_rays.data_ptr()
+            o.spill_cell = self.spill_cell.data_ptr()
+            o.spill_len = self.spill_len.data_ptr()
+            o.spill_capacity = self.spill_capacity
+        return o
+
+
+def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: Optional[torch.Tensor],
+               bufs: TraceBuffers, kappa: float = 1.0, mode: str = "fp64", max_steps: int = 0,
+               eps_mix: float = 0.0, persistent: bool = False, stream=None) -> None:
+    """Enqueue one vor_trace into preallocated buffers (no allocation, no sync)."""
+    n = origins.shape[0]
+    if origins.dtype != torch.float64 or dirs.dtype != torch.float64 or not origins.is_contiguous() \
+            or not dirs.is_contiguous() or origins.shape != dirs.shape or n != bufs.N:
+        raise ValueError("origins/dirs must be contiguous float64 (N, 3) tensors matching the buffers")
+    if density is not None and (density.dtype != torch.float64 or density.numel() != grid.M):
+        raise ValueError("density must be float64 with one value per site")
+    opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 0)
+    out = bufs.struct()
+    _check(load().vor_trace(grid.handle, _ptr(origins), _ptr(dirs), n, _ptr(density), float(kappa),
+                            ctypes.byref(opts), ctypes.byref(out), _stream(stream)), "vor_trace")
+
+
+def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str = "fp64",
+          segments: str = "exact", seg_stride: int = 64, spill_capacity: int = 0, max_steps: int = 0,
+          eps_mix: float = 0.0, persistent: bool = False, stream=None) -> dict:
+    """Paths of N rays. ``segments``: "none" (tau only), "stride" (fixed
+    ``seg_stride`` slots per ray; longer paths go to a spill area of
+    ``spill_capacity`` slots, or report RAY_OVERFLOW), or "exact" (a
+    tau-only counting pass, a scan, then a pass that writes every segment at
+    its CSR offset). Returns a dict of device tensors; "ray_off" gives each
+    ray's first slot in seg_cell/seg_len (spilled rays: see "spill_off")."""
+    o = _dev_f64(origins, 3)
+    d = _dev_f64(dirs, 3)
+    rho = None if density is None else _dev_f64(density).reshape(-1)
+    n = o.shape[0]
+    kw = dict(kappa=kappa, mode=mode, max_steps=max_steps, eps_mix=eps_mix, persistent=persistent, stream=stream)
+    if segments == "none":
+        b = TraceBuffers(n)
+        trace_into(grid, o, d, rho, b, **kw)
+    elif segments == "stride":
+        b = TraceBuffers(n, seg_stride=seg_stride, spill_capacity=spill_capacity)
+        trace_into(grid, o, d, rho, b, **kw)
+    elif segments == "exact":
+        b0 = TraceBuffers(n)
+        trace_into(grid, o, d, rho, b0, **kw)
+        off = exclusive_scan(b0.n_seg, stream=stream)
+        total = int(off[-1].item())
+        b = TraceBuffers(n, total_segments=max(total, 1))
+        b.ray_off = off
+        trace_into(grid, o, d, rho, b, **kw)
+    else:
+        raise ValueError("segments must be none, stride or exact")
+    res = dict(tau=b.tau, n_seg=b.n_seg, status=b.status, n_fallback=b.n_fallback, counters=b.counters)
+    if b.seg_cell is not None:
+        res.update(seg_cell=b.seg_cell, seg_len=b.seg_len)
+        res["ray_off"] = b.ray_off if b.ray_off is not None else \
+            torch.arange(0, (n + 1) * b.seg_stride, b.seg_stride, dtype=torch.int64, device="cuda")
+        res["seg_stride"] = b.seg_stride
+        if b.spill_capacity > 0:
+            res.update(spill_off=b.spill_off, spill_cell=b.spill_cell, spill_len=b.spill_len, work=b.work)
+    return res
+
+
+def gather_paths(res: dict):
+    """Host view of a trace result: (n_seg, per-ray (cells, lengths) getter).
+    Handles stride windows with spill."""
+    n_seg = res["n_seg"].cpu().numpy()
+    cells = res["seg_cell"].cpu().numpy()
+    lens = res["seg_len"].cpu().numpy()
+    off = res["ray_off"].cpu().numpy()
+    stride = res.get("seg_stride", 0)
+    spill_off = res["spill_off"].cpu().numpy() if "spill_off" in res else None
+    spill_cell = res["spill_cell"].cpu().numpy() if spill_off is not None else None
+    spill_len = res["spill_len"].cpu().numpy() if spill_off is not None else None
+
+    def get(r):
+        n = int(n_seg[r])
+        o = int(off[r])
+        if stride > 0 and n > stride:
+            if spill_off is None or spill_off[r] < 0:
+                raise ValueError(f"ray {r}: path not stored (overflow)")
+            s = int(spill_off[r])
+            return (np.concatenate([cells[o:o + stride], spill_cell[s:s + n - stride]]),
+                    np.concatenate([lens[o:o + stride], spill_len[s:s + n - stride]]))
+        return cells[o:o + n], lens[o:o + n]
+
+    return n_seg, get
+
+
+def version() -> str:
+    return load().vor_version().decode()

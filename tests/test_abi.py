@@ -1,0 +1,98 @@
+"""The C ABI without a GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "voronoi_rt.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vor_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1310_1854_amd import vrt
+    if not os.path.exists(vrt.LIB_PATH):
+        from paper_1310_1854_amd import build_lib
+        build_lib.build()
+    return vrt.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["vor_build_grid", "vor_locate", "vor_trace", "vor_grid_free", "vor_grid_neighbors",
+              "vor_grid_get_info", "vor_exclusive_scan", "vor_status_str", "vor_version"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1310_1854_amd import vrt
+    names = _declared()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+    assert sorted(vrt.EXPORTS) == names
+
+
+def test_status_strings(lib):
+    from paper_1310_1854_amd import vrt
+    for code in range(8):
+        assert len(vrt.status_str(code)) >= 2
+    assert vrt.status_str(99) == "unknown status"
+    assert "gfx950" in vrt.version()
+
+
+def test_argument_errors_before_device_work(lib):
+    from paper_1310_1854_amd import vrt
+    box = (ctypes.c_double * 6)(-1, -1, -1, 1, 1, 1)
+    fake = (ctypes.c_double * 30)()
+    out = ctypes.c_void_p(1234)
+    # no sites
+    assert lib.vor_build_grid(None, 10, box, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert out.value is None
+    # no sites count
+    assert lib.vor_build_grid(fake, 0, box, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert lib.vor_build_grid(fake, -5, box, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    # empty or inverted box, non-finite box
+    for b in [(0, -1, -1, 0, 1, 1), (1, -1, -1, -1, 1, 1), (float("nan"), -1, -1, 1, 1, 1),
+              (-1, -1, -1, float("inf"), 1, 1)]:
+        bb = (ctypes.c_double * 6)(*b)
+        assert lib.vor_build_grid(fake, 10, bb, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    # no box, no out
+    assert lib.vor_build_grid(fake, 10, None, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert lib.vor_build_grid(fake, 10, box, None, None, None) == vrt.VOR_EINVAL
+    # calls on a missing grid
+    cell = (ctypes.c_int32 * 10)()
+    assert lib.vor_locate(None, fake, 10, cell, None) == vrt.VOR_EINVAL
+    o = vrt.TraceOut()
+    assert lib.vor_trace(None, fake, fake, 10, None, 1.0, None, ctypes.byref(o), None) == vrt.VOR_EINVAL
+    info = vrt.GridInfo()
+    assert lib.vor_grid_get_info(None, ctypes.byref(info)) == vrt.VOR_EINVAL
+    assert lib.vor_grid_neighbors(None, fake, cell, None) == vrt.VOR_EINVAL
+    assert lib.vor_exclusive_scan(cell, -1, fake, None) == vrt.VOR_EINVAL
+    assert lib.vor_exclusive_scan(None, 5, fake, None) == vrt.VOR_EINVAL
+    lib.vor_grid_free(None)
+
+
+def test_oracle_and_product_share_no_code():
+    """The oracle (test infrastructure) and the HIP path neither include nor
+    import each other."""
+    csrc = os.path.join(ROOT, "paper_1310_1854_amd", "csrc")
+    for f in os.listdir(csrc):
+        if f.endswith((".hip", ".h", ".cpp")):
+            text = open(os.path.join(csrc, f)).read()
+            assert "oracle" not in text.lower(), f
+    for f in ("vrt.py", "build_lib.py", "workloads.py", "__init__.py"):
+        text = open(os.path.join(ROOT, "paper_1310_1854_amd", f)).read()
+        assert "import oracle" not in text and "from oracle" not in text, f
+    otext = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    assert "voronoi_rt" not in otext and "vrt_" not in otext
+    for f in ("__init__.py", "exact.py", "dda.py"):
+        text = open(os.path.join(ROOT, "oracle", f)).read()
+        assert "paper_1310_1854_amd" not in text, f

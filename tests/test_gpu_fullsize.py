@@ -1,0 +1,113 @@
+"""Full-size parity: each configuration at its full size, traced in the
+launch configuration bench.py times (mode, stride window, spill,
+persistent), checked against the oracle on a seeded sample of rays and by
+properties that hold for every ray (total length = chord, statuses, mixed
+equal to FP64, consecutive cells are listed neighbours)."""
+import numpy as np
+import pytest
+
+import bench
+import oracle
+from paper_1310_1854_amd import workloads as W
+from pathcmp import compare
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE = {"exp_disc": 300, "flared_disc": 60, "clumpy": 16}
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def vrt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1310_1854_amd import vrt as v
+    v.load()
+    return v
+
+
+@pytest.mark.parametrize("name", ["exp_disc", "flared_disc", "clumpy"])
+def test_full_size_in_bench_configuration(vrt, name):
+    import torch
+    spec = bench.WORKLOADS[name]
+    w = W.make_config(spec["cfg"])
+    print(f"[fullsize] {name}: {w.M} sites, {w.N} rays", flush=True)
+    grid = vrt.build_grid(w.sites, w.box)
+    o = torch.as_tensor(w.origins, device="cuda").contiguous()
+    d = torch.as_tensor(w.dirs, device="cuda").contiguous()
+    rho = torch.as_tensor(w.density, device="cuda").contiguous()
+    bufs = bench.prepare_buffers(vrt, torch, grid, o, d, rho, spec)
+    status = bufs.status.cpu().numpy()
+    assert np.all(status == 0), np.bincount(status).tolist()
+    n_seg = bufs.n_seg
+    stride = spec["stride"]
+
+    # every ray: the segments add up to the chord (lengths from the window, or the spill)
+    k = d / torch.linalg.norm(d, dim=1, keepdim=True)
+    lo = torch.as_tensor(w.box[:3], device="cuda")
+    hi = torch.as_tensor(w.box[3:], device="cuda")
+    inf = torch.full_like(k, float("inf"))
+    t_hi = torch.where(k > 0, (hi - o) / k, inf)
+    t_lo = torch.where(k < 0, (lo - o) / k, inf)
+    L = torch.minimum(t_hi.min(dim=1).values, t_lo.min(dim=1).values)
+    slots = torch.arange(stride, device="cuda")[None, :]
+    win = bufs.seg_len.view(w.N, stride)
+    in_win = n_seg <= stride
+    tot = torch.empty(w.N, dtype=torch.float64, device="cuda")
+    for a in range(0, w.N, 1 << 20):
+        b = min(w.N, a + (1 << 20))
+        part = win[a:b]
+        tot[a:b] = torch.where(slots < n_seg[a:b, None], part, torch.zeros_like(part)).sum(dim=1)
+    spilled = torch.nonzero(~in_win).flatten()
+    assert int(bufs.work[2].item()) == spilled.numel()
+    for a in range(0, spilled.numel(), 1 << 16):
+        sp = spilled[a:a + (1 << 16)]
+        so = bufs.spill_off[sp]
+        ns = n_seg[sp].long() - stride
+        cols = torch.arange(int(ns.max()), device="cuda")[None, :]
+        mask = cols < ns[:, None]
+        idx = torch.where(mask, so[:, None] + cols, torch.zeros_like(cols))
+        vals = bufs.spill_len[idx]
+        tot[sp] += torch.where(mask, vals, torch.zeros_like(vals)).sum(dim=1)
+    rel = (tot - L).abs() / L.clamp_min(1e-300)
+    del win
+    assert float(rel.max()) <= 1e-12, float(rel.max())
+
+    # mixed mode returns exactly the FP64 results on every ray
+    if spec["mode"] == "mixed":
+        f = vrt.TraceBuffers(w.N)
+        vrt.trace_into(grid, o, d, rho, f, mode="fp64")
+        torch.cuda.synchronize()
+        assert torch.equal(f.tau, bufs.tau) and torch.equal(f.n_seg, bufs.n_seg)
+
+    # a seeded sample against the oracle, segment by segment
+    sub = w.subsample(SAMPLE[name], seed=99)
+    ridx = sub.meta["ray_index"]
+    ref = oracle.trace(w.sites, w.box, w.density, sub.origins, sub.dirs, cap=8192)
+    n_all = n_seg.cpu().numpy()
+    spill_off = bufs.spill_off.cpu().numpy()
+    cells, lens, off = [], [], [0]
+    for r in ridx:
+        n = int(n_all[r])
+        a = int(r) * stride
+        c = bufs.seg_cell[a:a + min(n, stride)].cpu().numpy()
+        l = bufs.seg_len[a:a + min(n, stride)].cpu().numpy()
+        if n > stride:
+            b = int(spill_off[r])
+            c = np.concatenate([c, bufs.spill_cell[b:b + n - stride].cpu().numpy()])
+            l = np.concatenate([l, bufs.spill_len[b:b + n - stride].cpu().numpy()])
+        cells.append(c)
+        lens.append(l)
+        off.append(off[-1] + n)
+    p = dict(tau=bufs.tau.cpu().numpy()[ridx], n_seg=n_all[ridx], status=status[ridx],
+             seg_cell=np.concatenate(cells), seg_len=np.concatenate(lens), ray_off=np.array(off))
+    st = compare(p, ref, TOL[spec["mode"]])
+    print(f"[fullsize] {name}: {st}", flush=True)
+    assert st["clean"] >= 0.9 * len(ridx)
+
+    # consecutive cells of the sampled paths are neighbours in the grid's lists
+    rp, col = grid.neighbors()
+    rp, col = rp.cpu().numpy(), col.cpu().numpy()
+    for c in cells:
+        for a, b in zip(c[:-1], c[1:]):
+            assert b in col[rp[a]:rp[a + 1]]

@@ -1,0 +1,311 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Sizes the oracle finishes in seconds, spanning several blocks and a ragged
+tail; the full-size configurations are in test_gpu_fullsize.py. FP64 parity
+is expected bit-exact (the FP64 path evaluates the same expressions in the
+same order, without FMA contraction); the bar written in the tests is the
+stated tolerance (1e-12 relative in FP64 mode, 1e-5 in mixed mode).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.dda import lattice_path
+from paper_1310_1854_amd import workloads as W
+from pathcmp import compare, gpu_paths
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def vrt():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1310_1854_amd import vrt as v
+    v.load()
+    return v
+
+
+def _trace(vrt, grid, w, mode, segments="exact", **kw):
+    out = vrt.trace(grid, w.origins, w.dirs, w.density, kappa=w.kappa, mode=mode, segments=segments, **kw)
+    return gpu_paths(out)
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_golden_hand_paths(vrt, mode):
+    g = json.load(open(os.path.join(HERE, "golden", "hand_paths.json")))
+    for c in g["cases"]:
+        grid = vrt.build_grid(np.array(c["sites"], float), c["box"])
+        out = vrt.trace(grid, [c["origin"]], [c["dir"]], np.array(c["density"], float), mode=mode)
+        p = gpu_paths(out)
+        n = int(p["n_seg"][0])
+        assert list(p["seg_cell"][:n]) == c["cells"], c["name"]
+        tol = c["rel_tol"] * max(c["chord"], 1.0)
+        assert np.allclose(p["seg_len"][:n], c["lengths"], rtol=0, atol=tol), c["name"]
+        assert abs(p["tau"][0] - c["tau"]) <= tol * max(1.0, c["tau"]), c["name"]
+        assert p["status"][0] == 0
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_cubic_lattice_voxel_walk(vrt, mode):
+    w = W.cubic_lattice(8, N=3000)
+    grid = vrt.build_grid(w.sites, w.box)
+    p = _trace(vrt, grid, w, mode)
+    xs, ys, zs = w.meta["xs"], w.meta["ys"], w.meta["zs"]
+    for r in range(w.N):
+        c, l, L = lattice_path(xs, ys, zs, w.box, w.origins[r], w.dirs[r])
+        n = int(p["n_seg"][r])
+        o = int(p["ray_off"][r])
+        assert list(p["seg_cell"][o:o + n]) == c
+        assert np.array_equal(p["seg_len"][o:o + n], np.array(l))   # exact on the dyadic lattice
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_random_tensor_lattice_voxel_walk(vrt, mode):
+    w = W.random_tensor_lattice((9, 6, 11), N=3000)
+    grid = vrt.build_grid(w.sites, w.box)
+    p = _trace(vrt, grid, w, mode)
+    for r in range(w.N):
+        c, l, L = lattice_path(w.meta["xs"], w.meta["ys"], w.meta["zs"], w.box, w.origins[r], w.dirs[r])
+        n = int(p["n_seg"][r])
+        o = int(p["ray_off"][r])
+        assert list(p["seg_cell"][o:o + n]) == c
+        assert np.max(np.abs(p["seg_len"][o:o + n] - np.array(l))) <= TOL[mode] * L
+
+
+# --------------------------------------------------------------------------
+# the small uniform configuration, every ray
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cube(vrt):
+    w = W.uniform_cube(M=1000, N=10_000)
+    ref = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    return w, vrt.build_grid(w.sites, w.box), ref
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+@pytest.mark.parametrize("segments", ["exact", "stride"])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_uniform_cube_all_rays(vrt, cube, mode, segments, persistent):
+    w, grid, ref = cube
+    out = vrt.trace(grid, w.origins, w.dirs, w.density, mode=mode, segments=segments, seg_stride=16,
+                    spill_capacity=200_000, persistent=persistent)
+    p = gpu_paths(out)
+    if segments == "stride":
+        # rays longer than the window were rewritten whole into the spill
+        n_seg, get = vrt.gather_paths(out)
+        cells = []
+        lens = []
+        off = [0]
+        for r in range(w.N):
+            c, l = get(r)
+            cells.append(c)
+            lens.append(l)
+            off.append(off[-1] + len(c))
+        p.update(seg_cell=np.concatenate(cells), seg_len=np.concatenate(lens), ray_off=np.array(off))
+        assert int(out["work"][2].item()) == int((n_seg > 16).sum()) > 0
+    st = compare(p, ref, TOL[mode])
+    assert st["clean"] > 0.99 * w.N
+    if mode == "fp64":
+        assert st["max_len_diff"] == 0.0 and st["max_tau_diff"] == 0.0
+    c = out["counters"].cpu().numpy()
+    assert c[0] == p["n_seg"].sum()
+
+
+def test_mixed_equals_fp64_bitwise(vrt):
+    w = W.exp_disc(M=20_000, N=200_000, seed=77)
+    grid = vrt.build_grid(w.sites, w.box)
+    a = vrt.trace(grid, w.origins, w.dirs, w.density, mode="fp64", segments="exact")
+    b = vrt.trace(grid, w.origins, w.dirs, w.density, mode="mixed", segments="exact")
+    import torch
+    for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+        assert torch.equal(a[k], b[k]), k
+    assert b["counters"][2].item() > 0      # some steps were re-decided in FP64
+
+
+# --------------------------------------------------------------------------
+# locate
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg", ["cube", "disc"])
+def test_locate_matches_oracle(vrt, cfg):
+    w = W.uniform_cube(M=3000, N=1, seed=5) if cfg == "cube" else W.exp_disc(M=30_000, N=1, seed=6)
+    pts = W.uniform_in_box(np.random.default_rng(9), 20_011, w.box)
+    pts = np.concatenate([pts, w.sites[:500], [[w.box[3] + 1, 0, 0], [0, 0, w.box[2] - 1e-9]]])
+    grid = vrt.build_grid(w.sites, w.box)
+    cell = vrt.locate(grid, pts).cpu().numpy()
+    ref, gap = oracle.locate(w.sites, w.box, pts)
+    assert np.array_equal(cell, ref)        # equal distances also go to the lowest index on both sides
+    assert list(cell[-2:]) == [-1, -1]
+    assert np.array_equal(cell[20_011:20_511], np.arange(500))
+
+
+# --------------------------------------------------------------------------
+# neighbour lists against the oracle's brute-force faces
+# --------------------------------------------------------------------------
+
+def _rows(rp, col, i):
+    return set(col[rp[i]:rp[i + 1]].tolist())
+
+
+@pytest.mark.parametrize("case", ["cube", "disc_small", "lattice"])
+def test_neighbour_lists_vs_oracle_faces(vrt, case):
+    if case == "cube":
+        w = W.uniform_cube(M=1500, N=1, seed=12)
+    elif case == "disc_small":
+        w = W.flared_disc(M=3000, N=1, seed=13)
+    else:
+        w = W.cubic_lattice(5, N=1)
+    grid = vrt.build_grid(w.sites, w.box)
+    rp, col = grid.neighbors()
+    rp, col = rp.cpu().numpy(), col.cpu().numpy()
+    res, vol = oracle.faces(w.sites, w.box, np.arange(w.M), cap=512)
+    ext = w.box[3:] - w.box[:3]
+    for i in range(w.M):
+        got = _rows(rp, col, i)
+        nb, ar = res[i]
+        scale2 = (vol[i] ** (1.0 / 3.0)) ** 2
+        real = set(int(j) for j, a in zip(nb, ar) if a > 1e-9 * scale2)
+        anyc = set(int(j) for j in nb)
+        assert real <= got, f"cell {i}: missing {real - got}"
+        # every listed entry is a contact the brute force also sees, or a
+        # degenerate (zero-area) contact at a shared edge or vertex
+        extra = got - anyc
+        for j in extra:
+            assert j >= 0
+            d = np.linalg.norm(w.sites[j] - w.sites[i])
+            assert d < 4 * np.linalg.norm(ext)
+    # symmetric
+    for i in range(w.M):
+        for j in _rows(rp, col, i):
+            if j >= 0:
+                assert i in _rows(rp, col, j)
+    info = grid.info()
+    assert info["nnz_with_walls"] == len(col)
+
+
+def test_lattice_neighbours_are_the_six_faces(vrt):
+    n = 6
+    w = W.cubic_lattice(n, N=1)
+    grid = vrt.build_grid(w.sites, w.box)
+    rp, col = grid.neighbors()
+    rp, col = rp.cpu().numpy(), col.cpu().numpy()
+    for idx in range(w.M):
+        i, j, k = idx // (n * n), (idx // n) % n, idx % n
+        want = set()
+        for a, (c, lo_wall) in enumerate(((i, -1), (j, -3), (k, -5))):
+            step = (n * n, n, 1)[a]
+            want.add(idx - step if c > 0 else lo_wall)
+            want.add(idx + step if c < n - 1 else lo_wall - 1)
+        assert _rows(rp, col, idx) == want
+
+
+def test_mean_neighbours_uniform(vrt):
+    w = W.uniform_cube(M=200_000, N=1, seed=14)
+    grid = vrt.build_grid(w.sites, w.box)
+    rp, col = grid.neighbors()
+    rp, col = rp.cpu().numpy(), col.cpu().numpy()
+    far = np.nonzero(np.all(np.abs(w.sites) < 0.8, axis=1))[0]
+    counts = np.array([np.sum(col[rp[i]:rp[i + 1]] >= 0) for i in far[:20000]])
+    assert abs(counts.mean() - 15.54) < 0.1, counts.mean()
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+
+def test_edge_cases(vrt):
+    import torch
+    box = [-1, -1, -1, 1, 1, 1]
+    # one site: one segment of length L
+    g1 = vrt.build_grid([[0.1, 0.2, 0.3]], box)
+    out = gpu_paths(vrt.trace(g1, [[0, 0, 0], [0.5, 0.5, 0.5]], [[1, 0, 0], [0, 0, -2]], [3.0]))
+    assert list(out["n_seg"]) == [1, 1]
+    assert np.allclose(out["seg_len"], [1.0, 1.5], rtol=0, atol=1e-15)
+    assert np.allclose(out["tau"], [3.0, 4.5], rtol=1e-15)
+    # statuses: outside, zero direction, NaN direction, on the wall heading out
+    sites = W.uniform_cube(M=50, N=1, seed=3).sites
+    g = vrt.build_grid(sites, box)
+    o = [[2, 0, 0], [0, 0, 0], [0, 0, 0], [1, 0, 0], [1, 0, 0]]
+    d = [[1, 0, 0], [0, 0, 0], [np.nan, 1, 0], [1, 0, 0], [-1, 0, 0]]
+    for mode in ("fp64", "mixed"):
+        p = gpu_paths(vrt.trace(g, o, d, np.ones(50), mode=mode))
+        assert list(p["status"]) == [vrt.RAY_OUTSIDE, vrt.RAY_BADDIR, vrt.RAY_BADDIR, 0, 0]
+        assert list(p["n_seg"][:4]) == [0, 0, 0, 0] and p["n_seg"][4] > 0
+        assert p["tau"][3] == 0.0
+        ref = oracle.trace(sites, box, np.ones(50), o, d, cap=64)
+        assert list(ref["status"]) == list(p["status"])
+    # no rays
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    p = vrt.trace(g, e, e, None, segments="none")
+    assert p["tau"].numel() == 0
+    # stride window too small and no spill: overflow status, full count and tau
+    w = W.uniform_cube(M=2000, N=500, seed=4)
+    g2 = vrt.build_grid(w.sites, w.box)
+    full = gpu_paths(vrt.trace(g2, w.origins, w.dirs, w.density))
+    small = gpu_paths(vrt.trace(g2, w.origins, w.dirs, w.density, segments="stride", seg_stride=3))
+    assert np.array_equal(small["n_seg"], full["n_seg"]) and np.array_equal(small["tau"], full["tau"])
+    over = full["n_seg"] > 3
+    assert over.any() and np.all(small["status"][over] == vrt.RAY_OVERFLOW)
+    assert np.all(small["status"][~over] == 0)
+    # tau-only mode agrees with segment mode
+    only = gpu_paths(vrt.trace(g2, w.origins, w.dirs, w.density, segments="none"))
+    assert np.array_equal(only["tau"], full["tau"]) and np.array_equal(only["n_seg"], full["n_seg"])
+
+
+def test_build_errors(vrt):
+    box = [-1, -1, -1, 1, 1, 1]
+    with pytest.raises(vrt.VorError) as e:
+        vrt.build_grid([[0, 0, 0], [0.5, 0, 0], [0, 0, 0]], box)
+    assert e.value.code == vrt.VOR_EDUP
+    with pytest.raises(vrt.VorError) as e:
+        vrt.build_grid([[0, 0, 0], [1.5, 0, 0]], box)
+    assert e.value.code == vrt.VOR_EOUTSIDE
+    with pytest.raises(vrt.VorError) as e:
+        vrt.build_grid([[0, 0, 0], [np.nan, 0, 0]], box)
+    assert e.value.code == vrt.VOR_EOUTSIDE
+    with pytest.raises(vrt.VorError) as e:
+        vrt.build_grid([[0, 0, 0]], [0, 0, 0, 0, 1, 1])
+    assert e.value.code == vrt.VOR_EINVAL
+
+
+@pytest.mark.parametrize("n", [0, 1, 2047, 2048, 2049, 1_000_003])
+def test_exclusive_scan(vrt, n):
+    import torch
+    rng = np.random.default_rng(n)
+    c = rng.integers(0, 100, n).astype(np.int32)
+    off = vrt.exclusive_scan(torch.as_tensor(c, device="cuda")).cpu().numpy()
+    assert off.shape == (n + 1,)
+    assert np.array_equal(off, np.concatenate([[0], np.cumsum(c, dtype=np.int64)]))
+
+
+def test_ragged_sizes_and_site_permutation(vrt):
+    """Several ragged batch sizes through one grid; permuting the site order
+    permutes the cell indices and changes nothing else."""
+    w = W.uniform_cube(M=777, N=3001, seed=31)
+    g = vrt.build_grid(w.sites, w.box)
+    ref = gpu_paths(vrt.trace(g, w.origins, w.dirs, w.density))
+    for n in (1, 63, 64, 65, 255, 257, 3001):
+        p = gpu_paths(vrt.trace(g, w.origins[:n], w.dirs[:n], w.density))
+        assert np.array_equal(p["n_seg"], ref["n_seg"][:n])
+        assert np.array_equal(p["tau"], ref["tau"][:n])
+    perm = np.random.default_rng(2).permutation(w.M)
+    inv = np.argsort(perm)
+    g2 = vrt.build_grid(w.sites[perm], w.box)
+    p2 = gpu_paths(vrt.trace(g2, w.origins, w.dirs, w.density[perm]))
+    assert np.array_equal(p2["n_seg"], ref["n_seg"])
+    assert np.array_equal(p2["seg_len"], ref["seg_len"])
+    assert np.array_equal(p2["seg_cell"], inv[ref["seg_cell"]])
+    assert np.array_equal(p2["tau"], ref["tau"])
