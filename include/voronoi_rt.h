@@ -43,7 +43,8 @@ typedef enum {
     VOR_ENOMEM = 4,     /* a device allocation failed */
     VOR_EDEVICE = 5,    /* a HIP runtime call or kernel launch failed */
     VOR_ECAPACITY = 6,  /* a cell needs more faces than the builder's fixed capacity */
-    VOR_EBUDGET = 7     /* a serving request exceeds the memory budget */
+    VOR_EBUDGET = 7,    /* a serving request exceeds the memory budget */
+    VOR_ETIMEOUT = 8    /* a wait ran out of time; the request is still pending */
 } vor_status;
 
 /* Per-ray status written by vor_trace. */
@@ -198,6 +199,75 @@ vor_status vor_trace(const vor_grid *grid, const double *origins, const double *
  * Asynchronous; allocates nothing (tile totals are staged inside offsets).
  */
 vor_status vor_exclusive_scan(const int32_t *counts, int64_t N, int64_t *offsets, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of path requests over resident grids.
+ *
+ * A server keeps several built grids resident and accepts requests (a batch
+ * of rays for one grid, in FP64 or mixed mode) from any host thread. A
+ * request waits in a first-in-first-out queue until its output buffers fit
+ * in the server's memory budget; admitted requests are traced together by
+ * persistent kernels on two streams whose waves take chunks of rays from a
+ * device work queue and refill finished lanes, so work that arrives while
+ * other work is on the GPU starts as soon as a stream and memory free up.
+ * Every ray is computed by the same code as vor_trace, so its result does
+ * not depend on the other requests. Paths follow Sect. 2.2 as in vor_trace;
+ * segments go to a fixed window of seg_stride slots per ray (longer paths
+ * report VOR_RAY_OVERFLOW with their full count and tau).
+ * ------------------------------------------------------------------------- */
+typedef struct vor_server vor_server;
+
+typedef struct {
+    int64_t completed;         /* requests finished */
+    int64_t crossings;         /* segments emitted by finished launches */
+    int64_t fp64_redecisions;  /* mixed-mode steps redone in FP64 */
+    int64_t fallbacks;         /* no-exit fallbacks */
+    int64_t launches;          /* kernel launches finished */
+    int64_t waiting;           /* requests not yet admitted */
+    int64_t budget_bytes;      /* output memory budget */
+    int64_t used_bytes;        /* held by admitted, unreleased requests */
+    double uptime_s;
+} vor_server_stats;
+
+/* Create a server over n_grids built grids (host array of handles; the grids
+ * must outlive the server) with a budget of device memory for request
+ * outputs (allocated once here). Starts the scheduler thread. */
+vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int64_t budget_bytes,
+                             vor_server **out);
+
+/* Queue a request: n rays (origins, dirs: device, n x 3) on grid `grid`,
+ * density (device, that grid's M sites, user order; may be NULL), mode
+ * VOR_MODE_*, seg_stride segment slots per ray (0 = tau only). The inputs
+ * are borrowed until the request is done. *req_id receives its handle.
+ * VOR_EBUDGET if its outputs could never fit in the budget. */
+vor_status vor_server_submit(vor_server *srv, int32_t grid, const double *origins, const double *dirs, int64_t n,
+                             const double *density, double kappa, int32_t mode, int64_t seg_stride,
+                             int64_t *req_id);
+
+/* *done = 1 once the request's outputs are complete. */
+vor_status vor_server_poll(vor_server *srv, int64_t req_id, int32_t *done);
+
+/* Block until the request is done or timeout_s passes (VOR_ETIMEOUT). */
+vor_status vor_server_wait(vor_server *srv, int64_t req_id, double timeout_s);
+
+/* Device pointers of a finished request's outputs (tau, n_seg, status,
+ * seg_cell, seg_len with seg_stride; server-owned until release) and its
+ * latency from submission to completion in seconds. */
+vor_status vor_server_result(vor_server *srv, int64_t req_id, vor_trace_out *out, double *latency_s);
+
+/* Copy a finished request's outputs into caller buffers (device; any may be
+ * NULL; seg_cell/seg_len hold n * seg_stride entries), asynchronously on
+ * `stream`. */
+vor_status vor_server_copy_result(vor_server *srv, int64_t req_id, double *tau, int32_t *n_seg, uint8_t *status,
+                                  int32_t *seg_cell, double *seg_len, void *stream);
+
+/* Return a finished request's outputs to the budget. */
+vor_status vor_server_release(vor_server *srv, int64_t req_id);
+
+vor_status vor_server_get_stats(vor_server *srv, vor_server_stats *stats);
+
+/* Finish in-flight work, stop the scheduler, free everything. NULL is a no-op. */
+void vor_server_destroy(vor_server *srv);
 
 /* Static description of a status code. */
 const char *vor_status_str(vor_status s);

@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvoronoi_rt.so")
-SOURCES = ["scan.hip", "sort.hip", "build.hip", "trace.hip"]
+SOURCES = ["scan.hip", "sort.hip", "build.hip", "trace.hip", "serve.hip"]
 ARCH = os.environ.get("VRT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -26,13 +26,16 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 4, out: str = LIB, defines=()) -> str:
+    """Compile every source and link the shared library at ``out``;
+    ``defines`` are extra -D options (tuning knobs of the kernels)."""
     objs = []
+    tag = "" if out == LIB else "." + os.path.basename(out).replace(".so", "")
     procs = []
     for s in SOURCES:
         src = os.path.join(CSRC, s)
-        obj = os.path.join(CSRC, s.replace(".hip", ".o"))
-        cmd = ["hipcc", "-c"] + [f for f in FLAGS if f != "-shared"] + [src, "-o", obj]
+        obj = os.path.join(CSRC, s.replace(".hip", tag + ".o"))
+        cmd = ["hipcc", "-c"] + [f for f in FLAGS if f != "-shared"] + [f"-D{d}" for d in defines] + [src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -40,19 +43,21 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         if len(procs) >= jobs:
             _drain(procs)
     _drain(procs)
-    cmd = ["hipcc"] + FLAGS + objs + ["-o", LIB + ".tmp"]
+    cmd = ["hipcc"] + FLAGS + objs + ["-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 def _drain(procs):
     failed = []
     for name, p in procs:
         out, _ = p.communicate()
-        text = out.decode(errors="replace")
+        # hipcc's host pass does not know the GPU feature flag: harmless
+        text = "\n".join(ln for ln in out.decode(errors="replace").splitlines()
+                         if "is not a recognized feature for this target" not in ln)
         if p.returncode != 0:
             failed.append((name, text))
         elif text.strip():

@@ -14,7 +14,7 @@
 #include <cmath>
 #include <vector>
 
-#include "cell_clip.h"
+#include "clip_wave.h"
 
 using namespace vrt;
 
@@ -134,44 +134,44 @@ struct ClipArgs {
     int *err;
 };
 
-// First pass: every site with a small cell; cells that run out of faces are
-// queued for the second pass.
+// First pass: one wave per site with a small cell in LDS; cells that run
+// out of faces are queued for the second pass.
 __global__ void __launch_bounds__(64) k_clip(ClipArgs A)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.M) return;
-    CellSmall c;
-    Cand cand[kMaxCand];
+    __shared__ WaveCellSmall cell;
+    const int64_t i = blockIdx.x;
     uint8_t wm = 0;
-    int n = clip_site(A.sites, A.grid, A.box, i, A.nbr + i * kMaxNbr, kMaxNbr, &wm, c, cand);
-    if (n == -ERR_CAPACITY) {
-        A.retry[atomicAdd(A.n_retry, 1)] = (int32_t)i;
-        n = 0;
-    } else if (n < 0) {
-        atomicOr(A.err, -n);
-        n = 0;
+    int n = wclip_site(cell, A.sites, A.grid, A.box, i, A.nbr + i * kMaxNbr, kMaxNbr, &wm);
+    if (threadIdx.x == 0) {
+        if (n == -ERR_CAPACITY) {
+            A.retry[atomicAdd(A.n_retry, 1)] = (int32_t)i;
+            n = 0;
+        } else if (n < 0) {
+            atomicOr(A.err, -n);
+            n = 0;
+        }
+        A.cnt[i] = n;
+        A.walls[i] = wm;
     }
-    A.cnt[i] = n;
-    A.walls[i] = wm;
 }
 
-// Second pass over the queued sites, with large cells in a global workspace.
-__global__ void __launch_bounds__(64) k_clip_big(ClipArgs A, int32_t n_items, CellBig *__restrict__ cells,
-                                                 int32_t *__restrict__ big_nbr, int32_t *__restrict__ slot)
+// Second pass over the queued sites, with large cells (up to 255 faces).
+__global__ void __launch_bounds__(64) k_clip_big(ClipArgs A, int32_t *__restrict__ big_nbr, int32_t *__restrict__ slot)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_items) return;
-    int64_t i = A.retry[k];
-    slot[i] = k;
-    Cand cand[kMaxCand];
+    __shared__ WaveCellBig cell;
+    const int k = blockIdx.x;
+    const int64_t i = A.retry[k];
     uint8_t wm = 0;
-    int n = clip_site(A.sites, A.grid, A.box, i, big_nbr + (int64_t)k * kMaxNbrBig, kMaxNbrBig, &wm, cells[k], cand);
-    if (n < 0) {
-        atomicOr(A.err, -n);
-        n = 0;
+    int n = wclip_site(cell, A.sites, A.grid, A.box, i, big_nbr + (int64_t)k * kMaxNbrBig, kMaxNbrBig, &wm);
+    if (threadIdx.x == 0) {
+        slot[i] = k;
+        if (n < 0) {
+            atomicOr(A.err, -n);
+            n = 0;
+        }
+        A.cnt[i] = n;
+        A.walls[i] = wm;
     }
-    A.cnt[i] = n;
-    A.walls[i] = wm;
 }
 
 // Directed lists -> CSR (dir_start from a scan of cnt). slot[i] >= 0 marks a
@@ -478,7 +478,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     ca.n_retry = err + 2;
     ca.err = err;
     if (hipMemsetAsync(slot, 0xff, sizeof(int32_t) * M, st) != hipSuccess) return fail(VOR_EDEVICE);
-    hipLaunchKernelGGL(k_clip, dim3(blocks_for(M, 64)), dim3(64), 0, st, ca);
+    hipLaunchKernelGGL(k_clip, dim3((unsigned)M), dim3(64), 0, st, ca);
     if (hipGetLastError() != hipSuccess) return fail(VOR_EDEVICE);
     int hflags[4] = {0, 0, 0, 0};
     if (hipMemcpyAsync(hflags, err, 4 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -489,11 +489,9 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     const int n_retry = hflags[2];
     int32_t *big_nbr = nullptr;
     if (n_retry > 0) {
-        CellBig *cells = dalloc<CellBig>(n_retry, rc, tmp);
         big_nbr = dalloc<int32_t>((size_t)n_retry * kMaxNbrBig, rc, tmp);
         if (rc != VOR_OK) return fail(rc);
-        hipLaunchKernelGGL(k_clip_big, dim3(blocks_for(n_retry, 64)), dim3(64), 0, st, ca, n_retry, cells, big_nbr,
-                           slot);
+        hipLaunchKernelGGL(k_clip_big, dim3((unsigned)n_retry), dim3(64), 0, st, ca, big_nbr, slot);
         if (hipMemcpyAsync(hflags, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return fail(VOR_EDEVICE);

@@ -1,0 +1,570 @@
+// serve.hip -- continuous-batching path service: several grids resident in
+// HBM, requests of uneven size admitted against a memory budget, and their
+// rays traced together by persistent waves that refill lanes from a device
+// work queue.
+//
+// Host side: one scheduler thread per server. Requests wait in a FIFO until
+// their output buffers fit in the budget arena (first fit). Admitted
+// requests are cut into chunks of rays; whenever one of the server's
+// streams is free, every admitted request not yet launched goes into one
+// launch: its request table and chunk list are copied to the device and a
+// persistent kernel drains them. Launches on the two streams overlap, so
+// requests that arrive while a launch is running start before it ends.
+// Completion is seen through an event per launch.
+//
+// Device side: each wave takes a chunk (one atomic), sets up the chunk's
+// grid and precision class (uniform across the wave), and keeps its lanes
+// busy: a lane whose ray has ended takes the chunk's next ray. The per-ray
+// work is the same code as vor_trace, so a ray's result does not depend on
+// what else is in the launch.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "trace_core.h"
+
+using namespace vrt;
+
+const vrt::Grid &vrt_grid_of(const vor_grid *G);
+
+namespace {
+
+constexpr int kChunk = 1024;          // rays per chunk
+constexpr int kMaxLaunchReqs = 1024;  // requests per launch
+constexpr int kMaxLaunchChunks = 16384;
+constexpr int kStreams = 2;
+
+struct ReqDev {
+    RayIn in;
+    double *tau;
+    int32_t *n_seg;
+    uint8_t *status;
+    int32_t *seg_cell;
+    double *seg_len;
+    int64_t seg_stride;
+    int32_t grid;
+    int32_t mode;
+};
+
+struct ChunkDev {
+    int32_t req;    // index into the launch's request table
+    int32_t first;  // first ray of the request in this chunk
+    int32_t count;
+    int32_t pad;
+};
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids, const ReqDev *__restrict__ reqs,
+                                               const ChunkDev *__restrict__ chunks, int n_chunks,
+                                               unsigned int *__restrict__ head,
+                                               unsigned long long *__restrict__ counters)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    unsigned long long crossings = 0, redo = 0, fb = 0;
+    for (;;) {
+        unsigned int c = 0;
+        if (lane == 0) c = atomicAdd(head, 1u);
+        c = __shfl(c, 0, 64);
+        if ((int)c >= n_chunks) break;
+        const ChunkDev ch = chunks[c];
+        const ReqDev rq = reqs[ch.req];
+        const GridRef G = grids[rq.grid];
+        int next = 0;   // rays of the chunk handed out so far (wave-uniform)
+        bool live = false;
+        RayState R;
+        RayStats S;
+        int64_t ray = 0;
+        for (;;) {
+            bool need = !live;
+            uint64_t want = __ballot(need);
+            if (want && next < ch.count) {
+                int rank = __popcll(want & lt);
+                if (need && next + rank < ch.count) {
+                    ray = ch.first + next + rank;
+                    S = RayStats();
+                    R.st = ray_setup(G, rq.in, ray, R.r0, R.k, R.L);
+                    R.tau = 0.0;
+                    R.skip = 0;
+                    R.base = ray * rq.seg_stride;
+                    R.cap = rq.seg_cell ? rq.seg_stride : 0;
+                    if (R.st == RAY_OK) ray_begin(G, R);
+                    else R.L = 0.0;
+                    live = true;
+                }
+                next += __popcll(want);
+            }
+            if (__ballot(live) == 0ull) break;
+            if (live) {
+                bool more = (rq.mode == VOR_MODE_MIXED)
+                                ? ray_step<VOR_MODE_MIXED, true>(G, rq.in, R, S, rq.seg_cell, rq.seg_len)
+                                : ray_step<VOR_MODE_FP64, true>(G, rq.in, R, S, rq.seg_cell, rq.seg_len);
+                if (!more) {
+                    if (rq.seg_cell && R.st == RAY_OK && S.cnt > R.cap) R.st = RAY_OVERFLOW;
+                    rq.tau[ray] = R.tau;
+                    rq.n_seg[ray] = S.cnt;
+                    rq.status[ray] = R.st;
+                    crossings += S.cnt;
+                    redo += S.nredo;
+                    fb += S.nfb;
+                    live = false;
+                }
+            }
+        }
+    }
+    unsigned long long a = wave_sum_u64(crossings), b = wave_sum_u64(fb), d = wave_sum_u64(redo);
+    if (lane == 0) {
+        atomicAdd(&counters[0], a);
+        if (b) atomicAdd(&counters[1], b);
+        if (d) atomicAdd(&counters[2], d);
+    }
+}
+
+__global__ void k_zero_launch(unsigned int *head, unsigned long long *counters)
+{
+    if (threadIdx.x == 0) *head = 0;
+    if (threadIdx.x < 4) counters[threadIdx.x] = 0;
+}
+
+using clk = std::chrono::steady_clock;
+
+enum ReqState { Q_WAIT = 0, Q_ADMITTED, Q_RUNNING, Q_DONE, Q_RELEASED };
+
+struct Request {
+    int64_t id = 0;
+    int grid = 0;
+    int mode = 0;
+    int64_t n = 0;
+    RayIn in{};
+    int64_t seg_stride = 0;
+    size_t bytes = 0;
+    size_t off = 0;   // arena offset
+    ReqState state = Q_WAIT;
+    clk::time_point t_submit, t_admit, t_done;
+    // device outputs (in the arena)
+    double *tau = nullptr;
+    int32_t *n_seg = nullptr;
+    uint8_t *status = nullptr;
+    int32_t *seg_cell = nullptr;
+    double *seg_len = nullptr;
+};
+
+struct Launch {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<int64_t> reqs;
+    // staging (pinned) and device copies of the launch's tables
+    ReqDev *h_reqs = nullptr, *d_reqs = nullptr;
+    ChunkDev *h_chunks = nullptr, *d_chunks = nullptr;
+    unsigned int *d_head = nullptr;
+    unsigned long long *d_counters = nullptr;
+    unsigned long long *h_counters = nullptr;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t request_bytes(int64_t n, int64_t stride)
+{
+    size_t b = align_up(n * sizeof(double)) + align_up(n * sizeof(int32_t)) + align_up(n);
+    if (stride > 0) b += align_up((size_t)n * stride * sizeof(int32_t)) + align_up((size_t)n * stride * sizeof(double));
+    return b;
+}
+
+}  // namespace
+
+struct vor_server {
+    std::vector<GridRef> grid_refs;
+    GridRef *d_grids = nullptr;
+    char *arena = nullptr;
+    size_t budget = 0, used = 0;
+    std::map<size_t, size_t> free_blocks;   // offset -> size
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<int64_t> waiting;
+    std::map<int64_t, Request> reqs;
+    int64_t next_id = 1;
+    Launch launches[kStreams];
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    int device = 0;
+    int blocks = 1;
+    vor_status fault = VOR_OK;
+    // statistics
+    int64_t n_done = 0;
+    unsigned long long crossings = 0, redecisions = 0, fallbacks = 0;
+    int64_t launches_done = 0;
+    clk::time_point t0;
+
+    bool arena_alloc(size_t bytes, size_t &off)
+    {
+        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+            if (it->second >= bytes) {
+                off = it->first;
+                size_t rest = it->second - bytes;
+                free_blocks.erase(it);
+                if (rest) free_blocks[off + bytes] = rest;
+                used += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+
+    void arena_free(size_t off, size_t bytes)
+    {
+        used -= bytes;
+        auto it = free_blocks.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_blocks.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_blocks.erase(nx);
+        }
+        if (it != free_blocks.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_blocks.erase(it);
+            }
+        }
+    }
+
+    // FIFO admission: the head of the queue waits until it fits, so later
+    // requests never overtake it (no starvation).
+    void admit_locked()
+    {
+        while (!waiting.empty()) {
+            Request &r = reqs[waiting.front()];
+            size_t off;
+            if (!arena_alloc(r.bytes, off)) break;
+            r.off = off;
+            char *p = arena + off;
+            r.tau = (double *)p;
+            p += align_up(r.n * sizeof(double));
+            r.n_seg = (int32_t *)p;
+            p += align_up(r.n * sizeof(int32_t));
+            r.status = (uint8_t *)p;
+            p += align_up(r.n);
+            if (r.seg_stride > 0) {
+                r.seg_cell = (int32_t *)p;
+                p += align_up((size_t)r.n * r.seg_stride * sizeof(int32_t));
+                r.seg_len = (double *)p;
+            }
+            r.state = Q_ADMITTED;
+            r.t_admit = clk::now();
+            waiting.pop_front();
+        }
+    }
+
+    // Launch every admitted request that is not yet running on a free stream.
+    void launch_locked(Launch &L)
+    {
+        L.reqs.clear();
+        int nch = 0;
+        for (auto &kv : reqs) {
+            Request &r = kv.second;
+            if (r.state != Q_ADMITTED) continue;
+            int need = (int)((r.n + kChunk - 1) / kChunk);
+            if ((int)L.reqs.size() >= kMaxLaunchReqs || nch + need > kMaxLaunchChunks) break;
+            int q = (int)L.reqs.size();
+            ReqDev &d = L.h_reqs[q];
+            d.in = r.in;
+            d.tau = r.tau;
+            d.n_seg = r.n_seg;
+            d.status = r.status;
+            d.seg_cell = r.seg_cell;
+            d.seg_len = r.seg_len;
+            d.seg_stride = r.seg_stride;
+            d.grid = r.grid;
+            d.mode = r.mode;
+            for (int c = 0; c < need; ++c) {
+                ChunkDev &ch = L.h_chunks[nch++];
+                ch.req = q;
+                ch.first = c * kChunk;
+                ch.count = (int)std::min<int64_t>(kChunk, r.n - (int64_t)c * kChunk);
+                ch.pad = 0;
+            }
+            r.state = Q_RUNNING;
+            L.reqs.push_back(r.id);
+        }
+        if (L.reqs.empty()) return;
+        const int nreq = (int)L.reqs.size();
+        bool ok = hipMemcpyAsync(L.d_reqs, L.h_reqs, sizeof(ReqDev) * nreq, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
+                  hipMemcpyAsync(L.d_chunks, L.h_chunks, sizeof(ChunkDev) * nch, hipMemcpyHostToDevice, L.stream) == hipSuccess;
+        hipLaunchKernelGGL(k_zero_launch, dim3(1), dim3(64), 0, L.stream, L.d_head, L.d_counters);
+        int nb = std::max(1, std::min(blocks, (nch + 3) / 4));
+        hipLaunchKernelGGL(k_serve, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks, nch, L.d_head,
+                           L.d_counters);
+        ok = ok && hipGetLastError() == hipSuccess &&
+             hipMemcpyAsync(L.h_counters, L.d_counters, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            L.stream) == hipSuccess &&
+             hipEventRecord(L.done, L.stream) == hipSuccess;
+        if (!ok) fault = VOR_EDEVICE;
+        L.busy = true;
+    }
+
+    void complete_locked(Launch &L)
+    {
+        auto now = clk::now();
+        for (int64_t id : L.reqs) {
+            auto it = reqs.find(id);
+            if (it == reqs.end()) continue;
+            it->second.state = Q_DONE;
+            it->second.t_done = now;
+            ++n_done;
+        }
+        crossings += L.h_counters[0];
+        fallbacks += L.h_counters[1];
+        redecisions += L.h_counters[2];
+        ++launches_done;
+        L.reqs.clear();
+        L.busy = false;
+    }
+
+    void run()
+    {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (!stop.load()) {
+            bool progress = false;
+            for (auto &L : launches) {
+                if (L.busy && hipEventQuery(L.done) == hipSuccess) {
+                    complete_locked(L);
+                    progress = true;
+                }
+            }
+            if (progress) cv.notify_all();
+            admit_locked();
+            for (auto &L : launches) {
+                if (!L.busy) {
+                    launch_locked(L);
+                    if (L.busy) progress = true;
+                }
+            }
+            bool inflight = launches[0].busy || launches[1].busy;
+            if (!progress) {
+                if (inflight) {
+                    lk.unlock();
+                    std::this_thread::sleep_for(std::chrono::microseconds(20));
+                    lk.lock();
+                } else {
+                    cv.wait_for(lk, std::chrono::milliseconds(5));
+                }
+            }
+        }
+        // drain
+        for (auto &L : launches)
+            if (L.busy) {
+                lk.unlock();
+                (void)hipEventSynchronize(L.done);
+                lk.lock();
+                complete_locked(L);
+            }
+        cv.notify_all();
+    }
+};
+
+extern "C" {
+
+vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int64_t budget_bytes,
+                             vor_server **out)
+{
+    if (out) *out = nullptr;
+    if (!grids || n_grids < 1 || budget_bytes <= 0 || !out) return VOR_EINVAL;
+    for (int i = 0; i < n_grids; ++i)
+        if (!grids[i]) return VOR_EINVAL;
+    vor_server *S = new (std::nothrow) vor_server;
+    if (!S) return VOR_ENOMEM;
+    (void)hipGetDevice(&S->device);
+    for (int i = 0; i < n_grids; ++i) S->grid_refs.push_back(grid_ref(vrt_grid_of(grids[i]), 0, 0.0));
+    bool ok = hipMalloc(&S->d_grids, sizeof(GridRef) * n_grids) == hipSuccess &&
+              hipMemcpy(S->d_grids, S->grid_refs.data(), sizeof(GridRef) * n_grids, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMalloc(&S->arena, (size_t)budget_bytes) == hipSuccess;
+    for (auto &L : S->launches) {
+        ok = ok && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc((void **)&L.h_reqs, sizeof(ReqDev) * kMaxLaunchReqs, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void **)&L.h_chunks, sizeof(ChunkDev) * kMaxLaunchChunks, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void **)&L.h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess &&
+             hipMalloc(&L.d_reqs, sizeof(ReqDev) * kMaxLaunchReqs) == hipSuccess &&
+             hipMalloc(&L.d_chunks, sizeof(ChunkDev) * kMaxLaunchChunks) == hipSuccess &&
+             hipMalloc(&L.d_head, sizeof(unsigned int)) == hipSuccess &&
+             hipMalloc(&L.d_counters, 4 * sizeof(unsigned long long)) == hipSuccess;
+    }
+    int cus = 0, per_cu = 0;
+    ok = ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess &&
+         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve, 256, 0) == hipSuccess;
+    if (!ok) {
+        vor_server_destroy(S);
+        return VOR_ENOMEM;
+    }
+    S->blocks = std::max(1, cus * std::max(1, per_cu));
+    S->budget = (size_t)budget_bytes;
+    S->free_blocks[0] = S->budget;
+    S->t0 = clk::now();
+    S->worker = std::thread([S] { S->run(); });
+    *out = S;
+    return VOR_OK;
+}
+
+vor_status vor_server_submit(vor_server *S, int32_t grid, const double *origins, const double *dirs, int64_t n,
+                             const double *density, double kappa, int32_t mode, int64_t seg_stride, int64_t *req_id)
+{
+    if (req_id) *req_id = 0;
+    if (!S || !req_id || grid < 0 || grid >= (int32_t)S->grid_refs.size() || n < 1 || n > 0x7fffffffLL ||
+        !origins || !dirs || seg_stride < 0 || (mode != VOR_MODE_FP64 && mode != VOR_MODE_MIXED))
+        return VOR_EINVAL;
+    size_t bytes = request_bytes(n, seg_stride);
+    if (bytes > S->budget) return VOR_EBUDGET;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->fault != VOR_OK) return S->fault;
+    Request r;
+    r.id = S->next_id++;
+    r.grid = grid;
+    r.mode = mode;
+    r.n = n;
+    r.in.origins = origins;
+    r.in.dirs = dirs;
+    r.in.density = density;
+    r.in.kappa = kappa;
+    r.seg_stride = seg_stride;
+    r.bytes = bytes;
+    r.t_submit = clk::now();
+    S->reqs[r.id] = r;
+    S->waiting.push_back(r.id);
+    *req_id = r.id;
+    S->cv.notify_all();
+    return VOR_OK;
+}
+
+vor_status vor_server_poll(vor_server *S, int64_t req, int32_t *done)
+{
+    if (!S || !done) return VOR_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(req);
+    if (it == S->reqs.end() || it->second.state == Q_RELEASED) return VOR_EINVAL;
+    *done = it->second.state == Q_DONE ? 1 : 0;
+    return S->fault;
+}
+
+vor_status vor_server_wait(vor_server *S, int64_t req, double timeout_s)
+{
+    if (!S) return VOR_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto deadline = clk::now() + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(timeout_s));
+    for (;;) {
+        auto it = S->reqs.find(req);
+        if (it == S->reqs.end() || it->second.state == Q_RELEASED) return VOR_EINVAL;
+        if (it->second.state == Q_DONE) return VOR_OK;
+        if (S->fault != VOR_OK) return S->fault;
+        if (S->cv.wait_until(lk, deadline) == std::cv_status::timeout && clk::now() >= deadline) {
+            auto it2 = S->reqs.find(req);
+            return (it2 != S->reqs.end() && it2->second.state == Q_DONE) ? VOR_OK : VOR_ETIMEOUT;
+        }
+    }
+}
+
+vor_status vor_server_result(vor_server *S, int64_t req, vor_trace_out *out, double *latency_s)
+{
+    if (!S || !out) return VOR_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(req);
+    if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
+    const Request &r = it->second;
+    *out = vor_trace_out{};
+    out->tau = r.tau;
+    out->n_seg = r.n_seg;
+    out->status = r.status;
+    out->seg_cell = r.seg_cell;
+    out->seg_len = r.seg_len;
+    out->seg_stride = r.seg_stride;
+    if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
+    return VOR_OK;
+}
+
+vor_status vor_server_copy_result(vor_server *S, int64_t req, double *tau, int32_t *n_seg, uint8_t *status,
+                                  int32_t *seg_cell, double *seg_len, void *stream)
+{
+    if (!S) return VOR_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(req);
+    if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
+    const Request &r = it->second;
+    hipStream_t st = (hipStream_t)stream;
+    bool ok = true;
+    if (tau) ok = ok && hipMemcpyAsync(tau, r.tau, r.n * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
+    if (n_seg) ok = ok && hipMemcpyAsync(n_seg, r.n_seg, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, st) == hipSuccess;
+    if (status) ok = ok && hipMemcpyAsync(status, r.status, r.n, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    if (r.seg_stride > 0) {
+        size_t ns = (size_t)r.n * r.seg_stride;
+        if (seg_cell) ok = ok && hipMemcpyAsync(seg_cell, r.seg_cell, ns * sizeof(int32_t), hipMemcpyDeviceToDevice, st) == hipSuccess;
+        if (seg_len) ok = ok && hipMemcpyAsync(seg_len, r.seg_len, ns * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
+    }
+    return ok ? VOR_OK : VOR_EDEVICE;
+}
+
+vor_status vor_server_release(vor_server *S, int64_t req)
+{
+    if (!S) return VOR_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(req);
+    if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
+    S->arena_free(it->second.off, it->second.bytes);
+    S->reqs.erase(it);
+    S->cv.notify_all();
+    return VOR_OK;
+}
+
+vor_status vor_server_get_stats(vor_server *S, vor_server_stats *st)
+{
+    if (!S || !st) return VOR_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    st->completed = S->n_done;
+    st->crossings = (int64_t)S->crossings;
+    st->fp64_redecisions = (int64_t)S->redecisions;
+    st->fallbacks = (int64_t)S->fallbacks;
+    st->launches = S->launches_done;
+    st->waiting = (int64_t)S->waiting.size();
+    st->budget_bytes = (int64_t)S->budget;
+    st->used_bytes = (int64_t)S->used;
+    st->uptime_s = std::chrono::duration<double>(clk::now() - S->t0).count();
+    return S->fault;
+}
+
+void vor_server_destroy(vor_server *S)
+{
+    if (!S) return;
+    if (S->worker.joinable()) {
+        S->stop.store(true);
+        S->cv.notify_all();
+        S->worker.join();
+    }
+    for (auto &L : S->launches) {
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+        if (L.h_reqs) (void)hipHostFree(L.h_reqs);
+        if (L.h_chunks) (void)hipHostFree(L.h_chunks);
+        if (L.h_counters) (void)hipHostFree(L.h_counters);
+        if (L.d_reqs) (void)hipFree(L.d_reqs);
+        if (L.d_chunks) (void)hipFree(L.d_chunks);
+        if (L.d_head) (void)hipFree(L.d_head);
+        if (L.d_counters) (void)hipFree(L.d_counters);
+    }
+    if (S->arena) (void)hipFree(S->arena);
+    if (S->d_grids) (void)hipFree(S->d_grids);
+    delete S;
+}
+
+}  // extern "C"

@@ -1,0 +1,346 @@
+// trace_core.h -- the per-ray work of the straight-path method (Sect. 2.2,
+// Eqs. 1-5) shared by every tracing kernel: ray set-up, start cell, and one
+// exit-point step in FP64 or mixed precision.
+//
+// Every crossing is measured from the ray's origin r0:
+//     s_j = n.((p_j + p_m)/2 - r0) / (n.k),   n = p_j - p_m,
+// which is Eq. 4 with the current point r = r0 + s_c k substituted and s
+// counted from r0, so no position error builds up along the path. Only
+// neighbours with n.k > 0 are evaluated (the sign argument of Sect. 2.2),
+// the chord end L (Eq. 5 on every axis) is always a candidate, and a
+// crossing at or behind the current position moves to that neighbour
+// without emitting a segment.
+#pragma once
+
+#include "vrt_internal.h"
+
+namespace vrt {
+
+// A resident grid as the tracing code reads it.
+struct GridRef {
+    const Site *sites;
+    const int2 *rows;
+    const Rec64 *rec64;
+    const Rec32 *rec32;
+    BucketGridView grid;
+    double lo[3], hi[3];
+    int32_t max_steps;
+    float eps_mix;
+    double eps_fb;        // no-exit fallback advance
+};
+
+// The rays' inputs.
+struct RayIn {
+    const double *origins;
+    const double *dirs;
+    const double *density;
+    double kappa;
+};
+
+inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
+{
+    GridRef G;
+    G.sites = g.sites;
+    G.rows = g.rows;
+    G.rec64 = g.rec64;
+    G.rec32 = g.rec32;
+    G.grid = bucket_view(g);
+    double diag = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        G.lo[a] = g.box[a];
+        G.hi[a] = g.box[a + 3];
+        diag += (g.box[a + 3] - g.box[a]) * (g.box[a + 3] - g.box[a]);
+    }
+    G.max_steps = max_steps > 0 ? max_steps : (int32_t)(g.M + 16 < 0x7fffffff ? g.M + 16 : 0x7fffffff);
+    G.eps_mix = (float)(eps_mix > 0 ? eps_mix : 1.9073486328125e-06);   // 2^-19
+    G.eps_fb = 1e-12 * sqrt(diag);
+    return G;
+}
+
+#ifndef VRT_BATCH64
+#define VRT_BATCH64 4
+#endif
+#ifndef VRT_BATCH32
+#define VRT_BATCH32 8
+#endif
+constexpr int kBatch64 = VRT_BATCH64;   // FP64 records loaded together per lane
+constexpr int kBatch32 = VRT_BATCH32;   // FP32 records loaded together per lane
+
+
+// Crossing of one bisector plane in FP64, measured from r0 (Eqs. 1-4):
+// n = p_j - p_m, s = n.((p_j + p_m)/2 - r0) / (n.k). Returns n.k in den.
+__device__ __forceinline__ double cross_fp64(double qx, double qy, double qz, const double pm[3], const double r0[3],
+                                             const double k[3], double &den)
+{
+    double n0 = qx - pm[0], n1 = qy - pm[1], n2 = qz - pm[2];
+    den = n0 * k[0] + n1 * k[1] + n2 * k[2];
+    double w0 = 0.5 * (qx + pm[0]) - r0[0];
+    double w1 = 0.5 * (qy + pm[1]) - r0[1];
+    double w2 = 0.5 * (qz + pm[2]) - r0[2];
+    return (n0 * w0 + n1 * w1 + n2 * w2) / den;
+}
+
+// FP64 exit search over row rw of the current cell (site pm). Returns the
+// winning record index, or -1 when the chord end L comes first, and the
+// crossing in best. Tie rules: equal crossings go to the larger n.k (the
+// cell nearest just after the crossing), then to the lower index; the wall
+// wins a tie with a plane. Planes with n.k <= 0 are never crossed forwards.
+__device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw, const double pm[3],
+                                         const double r0[3], const double k[3], double L, double &best)
+{
+    best = L;
+    double best_den = 1e308 * 10.0;
+    int win = -1;
+    int32_t win_j = 0x7fffffff;
+    const int end = rw.x + rw.y;
+    for (int e0 = rw.x; e0 < end; e0 += kBatch64) {
+        Rec64 q[kBatch64];
+#pragma unroll
+        for (int u = 0; u < kBatch64; ++u)
+            if (e0 + u < end) q[u] = rec[e0 + u];
+#pragma unroll
+        for (int u = 0; u < kBatch64; ++u) {
+            if (e0 + u >= end) break;
+            double den;
+            double sj = cross_fp64(q[u].x, q[u].y, q[u].z, pm, r0, k, den);
+            if (!(den > 0.0)) continue;
+            if (sj < best || (sj == best && win >= 0 && (den > best_den || (den == best_den && q[u].j < win_j)))) {
+                best = sj;
+                best_den = den;
+                win = e0 + u;
+                win_j = q[u].j;
+            }
+        }
+    }
+    return win;
+}
+
+// Mixed-precision exit search. Returns the winning record index (-1: the
+// chord end), with redo set when the step was decided in FP64 (then best is
+// the FP64 crossing); otherwise j1 is the winner's internal index and the
+// caller computes its FP64 crossing from the site (fetched together with
+// the winner's row). Every plane is ranked with FP32 offsets and
+// a bound on the FP32 rounding error of its crossing,
+//   err = eps * (1.5 |n|^2 + 0.5 (|q| + |t|)^2) / (n.k) + 4u |t|,
+// (q = current point - p_m, t = the FP32 crossing, u = 2^-24; eps >= 12u
+// covers the rounding of n, q, k and of the products, the AM-GM step
+// |n|(|q|+|t|) <= (|n|^2 + (|q|+|t|)^2)/2 turns the bound into this form).
+// If the upper bound of the best candidate is below the lower bound of every
+// other one (the wall included) the FP32 ranking is certain, and only the
+// winner's crossing is recomputed in FP64 (from the FP64 record, same
+// arithmetic as exit_fp64); otherwise the step is redone in FP64. Either way
+// the result equals exit_fp64's.
+__device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const Rec32 *__restrict__ rec32, int2 rw,
+                                          const double pm[3], const double r0[3], const double k[3], double L,
+                                          double s_c, float eps, double &best, bool &redo, int32_t &j1)
+{
+    double q64[3];
+    for (int a = 0; a < 3; ++a) q64[a] = (r0[a] + s_c * k[a]) - pm[a];
+    const float qx = (float)q64[0], qy = (float)q64[1], qz = (float)q64[2];
+    const float kx = (float)k[0], ky = (float)k[1], kz = (float)k[2];
+    const float qa = sqrtf(qx * qx + qy * qy + qz * qz);
+    const float u = 5.9604645e-8f;   // 2^-24
+    const float tw = (float)(L - s_c);   // the wall, relative to the current point
+    const float ew = 2.0f * u * fabsf(tw);
+    float t1 = tw, hi1 = tw + ew;       // best estimate and its upper bound
+    int e1 = -1;
+    float lo_a = tw - ew, lo_b = 3.0e38f;   // two smallest lower bounds
+    int ia = -1;
+    const int end = rw.x + rw.y;
+    for (int e0 = rw.x; e0 < end; e0 += kBatch32) {
+        Rec32 r[kBatch32];
+#pragma unroll
+        for (int v = 0; v < kBatch32; ++v)
+            if (e0 + v < end) r[v] = rec32[e0 + v];
+#pragma unroll
+        for (int v = 0; v < kBatch32; ++v) {
+            if (e0 + v >= end) break;
+            float den = r[v].nx * kx + r[v].ny * ky + r[v].nz * kz;
+            if (!(den > 0.0f)) continue;
+            float nn = r[v].nx * r[v].nx + r[v].ny * r[v].ny + r[v].nz * r[v].nz;
+            float num = 0.5f * nn - (r[v].nx * qx + r[v].ny * qy + r[v].nz * qz);
+            float t = num / den;
+            float at = fabsf(t);
+            float sq = qa + at;
+            float err = eps * (1.5f * nn + 0.5f * sq * sq) / den + 4.0f * u * at;
+            float lo = t - err;
+            if (t < t1) {
+                t1 = t;
+                hi1 = t + err;
+                e1 = e0 + v;
+                j1 = r[v].j;
+            }
+            if (lo < lo_a) {
+                lo_b = lo_a;
+                lo_a = lo;
+                ia = e0 + v;
+            } else if (lo < lo_b) {
+                lo_b = lo;
+            }
+        }
+    }
+    float lo_other = (ia == e1) ? lo_b : lo_a;
+    if (!(hi1 < lo_other)) {
+        redo = true;
+        return exit_fp64(rec64, rw, pm, r0, k, L, best);
+    }
+    redo = false;
+    if (e1 < 0) best = L;
+    return e1;
+}
+
+struct RayStats {
+    int32_t cnt = 0, nfb = 0, nredo = 0, steps = 0, recs = 0;
+};
+
+// Ray set-up: normalised direction, chord length L (Eq. 5 on every axis),
+// status. Returns false when the ray has no path.
+__device__ __forceinline__ uint8_t ray_setup(const GridRef &G, const RayIn &I, int64_t ray, double r0[3], double k[3], double &L)
+{
+    for (int a = 0; a < 3; ++a) {
+        r0[a] = I.origins[3 * ray + a];
+        k[a] = I.dirs[3 * ray + a];
+    }
+    double kn = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    bool inside = true;
+    for (int a = 0; a < 3; ++a)
+        if (!(r0[a] >= G.lo[a] && r0[a] <= G.hi[a])) inside = false;
+    L = 0.0;
+    if (!(kn > 0.0) || !isfinite(kn)) return RAY_BADDIR;
+    if (!inside) return RAY_OUTSIDE;
+    for (int a = 0; a < 3; ++a) k[a] /= kn;
+    L = 1e308 * 10.0;
+    for (int a = 0; a < 3; ++a) {
+        if (k[a] > 0.0) {
+            double s = (G.hi[a] - r0[a]) / k[a];
+            if (s < L) L = s;
+        } else if (k[a] < 0.0) {
+            double s = (G.lo[a] - r0[a]) / k[a];
+            if (s < L) L = s;
+        }
+    }
+    return RAY_OK;
+}
+
+// Per-lane state of a ray in flight.
+struct RayState {
+    double r0[3], k[3], pm[3];
+    int2 rw;              // the current cell's row of neighbour records
+    double L, s_c, tau;
+    int64_t base, cap;
+    int64_t skip;         // segments with a smaller index are not written
+    int32_t m, uid;
+    uint8_t st;
+};
+
+__device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R)
+{
+    R.s_c = 0.0;
+    R.tau = 0.0;
+    int32_t uid;
+    int32_t m = nearest_site(G.grid, R.r0, &uid);
+    Site sm = G.sites[m];
+    R.m = m;
+    R.uid = uid;
+    R.pm[0] = sm.x;
+    R.pm[1] = sm.y;
+    R.pm[2] = sm.z;
+    R.rw = G.rows[m];
+}
+
+// One exit-point step (Sect. 2.2). Returns false once the path has ended.
+// The next cell's row is fetched in the same round trip as its site.
+template <int MODE, bool SEGS>
+__device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, int32_t *seg_cell,
+                                         double *seg_len)
+{
+    if (!(R.L > 0.0)) return false;
+    if (S.steps > G.max_steps) {
+        R.st = RAY_STEPLIMIT;
+        return false;
+    }
+    ++S.steps;
+    const int2 rw = R.rw;
+    S.recs += rw.y;
+    double best;
+    int32_t wj = -1, wuid = 0;
+    double wx = 0.0, wy = 0.0, wz = 0.0;
+    int2 wrow = make_int2(0, 0);
+    if (MODE == VOR_MODE_FP64) {
+        int win = exit_fp64(G.rec64, rw, R.pm, R.r0, R.k, R.L, best);
+        if (win >= 0) {
+            const Rec64 w = G.rec64[win];
+            wj = w.j;
+            wuid = w.uid;
+            wx = w.x;
+            wy = w.y;
+            wz = w.z;
+            wrow = G.rows[wj];
+        }
+    } else {
+        bool redo;
+        int32_t j1 = -1;
+        int win = exit_mixed(G.rec64, G.rec32, rw, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, best, redo, j1);
+        S.nredo += redo ? 1 : 0;
+        if (win >= 0) {
+            if (redo) {
+                const Rec64 w = G.rec64[win];
+                wj = w.j;
+                wuid = w.uid;
+                wx = w.x;
+                wy = w.y;
+                wz = w.z;
+                wrow = G.rows[wj];
+            } else {
+                wj = j1;
+                const Site w = G.sites[wj];
+                wrow = G.rows[wj];
+                wuid = (int32_t)w.uid;
+                wx = w.x;
+                wy = w.y;
+                wz = w.z;
+                double den;
+                best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
+            }
+        }
+    }
+    double len = best - R.s_c;
+    if (len > 0.0) {
+        if (SEGS && S.cnt < R.cap && S.cnt >= R.skip) {
+            seg_cell[R.base + S.cnt] = R.uid;
+            seg_len[R.base + S.cnt] = len;
+        }
+        if (I.density) R.tau += I.kappa * I.density[R.uid] * len;
+        ++S.cnt;
+        R.s_c = best;
+    } else if (len < -1e-9 * R.L) {
+        // The current point lies well beyond a plane of this cell: the
+        // neighbour table missed a cell. Advance a small distance without a
+        // segment and locate the point again (the no-exit fallback of
+        // Sect. 2.2).
+        R.s_c += G.eps_fb;
+        ++S.nfb;
+        if (R.s_c >= R.L) return false;
+        double r[3];
+        for (int a = 0; a < 3; ++a) r[a] = R.r0[a] + R.s_c * R.k[a];
+        int32_t uid;
+        R.m = nearest_site(G.grid, r, &uid);
+        R.uid = uid;
+        Site sm = G.sites[R.m];
+        R.pm[0] = sm.x;
+        R.pm[1] = sm.y;
+        R.pm[2] = sm.z;
+        R.rw = G.rows[R.m];
+        return true;
+    }
+    if (wj < 0) return false;
+    R.m = wj;
+    R.uid = wuid;
+    R.pm[0] = wx;
+    R.pm[1] = wy;
+    R.pm[2] = wz;
+    R.rw = wrow;
+    return true;
+}
+
+}  // namespace vrt

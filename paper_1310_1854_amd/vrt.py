@@ -20,13 +20,15 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvoronoi_rt.so")
 
-VOR_OK, VOR_EINVAL, VOR_EDUP, VOR_EOUTSIDE, VOR_ENOMEM, VOR_EDEVICE, VOR_ECAPACITY, VOR_EBUDGET = range(8)
+VOR_OK, VOR_EINVAL, VOR_EDUP, VOR_EOUTSIDE, VOR_ENOMEM, VOR_EDEVICE, VOR_ECAPACITY, VOR_EBUDGET, VOR_ETIMEOUT = range(9)
 RAY_OK, RAY_OUTSIDE, RAY_BADDIR, RAY_STEPLIMIT, RAY_OVERFLOW = range(5)
 MODES = {"fp64": 0, "mixed": 1}
 
 # every symbol include/voronoi_rt.h declares
 EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_neighbors", "vor_locate",
-           "vor_trace", "vor_exclusive_scan", "vor_status_str", "vor_version"]
+           "vor_trace", "vor_exclusive_scan", "vor_status_str", "vor_version",
+           "vor_server_create", "vor_server_submit", "vor_server_poll", "vor_server_wait", "vor_server_result",
+           "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy"]
 
 
 class VorError(RuntimeError):
@@ -58,15 +60,23 @@ class TraceOut(ctypes.Structure):
                 ("spill_cell", ctypes.c_void_p), ("spill_len", ctypes.c_void_p), ("spill_capacity", ctypes.c_int64)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("crossings", ctypes.c_int64), ("fp64_redecisions", ctypes.c_int64),
+                ("fallbacks", ctypes.c_int64), ("launches", ctypes.c_int64), ("waiting", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64), ("uptime_s", ctypes.c_double)]
+
+
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Load the HIP library; raises if it has not been built (there is no
+def load(path: str = None):
+    """Load the HIP library (the in-tree build unless VRT_LIB names another
+    build of the same sources); raises if it has not been built (there is no
     CPU fallback)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("VRT_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"libvoronoi_rt.so not built at {path}; run paper_1310_1854_amd.build_lib")
     lib = ctypes.CDLL(path)
@@ -89,6 +99,24 @@ def load(path: str = LIB_PATH):
     lib.vor_status_str.restype = ctypes.c_char_p
     lib.vor_version.argtypes = []
     lib.vor_version.restype = ctypes.c_char_p
+    lib.vor_server_create.argtypes = [ctypes.POINTER(P), I32, I64, ctypes.POINTER(P)]
+    lib.vor_server_create.restype = ctypes.c_int
+    lib.vor_server_submit.argtypes = [P, I32, P, P, I64, P, D, I32, I64, ctypes.POINTER(I64)]
+    lib.vor_server_submit.restype = ctypes.c_int
+    lib.vor_server_poll.argtypes = [P, I64, ctypes.POINTER(I32)]
+    lib.vor_server_poll.restype = ctypes.c_int
+    lib.vor_server_wait.argtypes = [P, I64, D]
+    lib.vor_server_wait.restype = ctypes.c_int
+    lib.vor_server_result.argtypes = [P, I64, ctypes.POINTER(TraceOut), ctypes.POINTER(D)]
+    lib.vor_server_result.restype = ctypes.c_int
+    lib.vor_server_copy_result.argtypes = [P, I64, P, P, P, P, P, P]
+    lib.vor_server_copy_result.restype = ctypes.c_int
+    lib.vor_server_release.argtypes = [P, I64]
+    lib.vor_server_release.restype = ctypes.c_int
+    lib.vor_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.vor_server_get_stats.restype = ctypes.c_int
+    lib.vor_server_destroy.argtypes = [P]
+    lib.vor_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -318,6 +346,82 @@ def gather_paths(res: dict):
         return cells[o:o + n], lens[o:o + n]
 
     return n_seg, get
+
+
+class Server:
+    """A continuous-batching path server over resident grids (vor_server_*).
+    Input tensors of a request are kept alive here until it is released."""
+
+    def __init__(self, grids, budget_bytes: int):
+        self.grids = list(grids)
+        arr = (ctypes.c_void_p * len(self.grids))(*[g.handle.value for g in self.grids])
+        h = ctypes.c_void_p()
+        _check(load().vor_server_create(arr, len(self.grids), int(budget_bytes), ctypes.byref(h)),
+               "vor_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, grid: int, origins: torch.Tensor, dirs: torch.Tensor, density: Optional[torch.Tensor] = None,
+               kappa: float = 1.0, mode: str = "fp64", seg_stride: int = 0) -> int:
+        if origins.dtype != torch.float64 or dirs.dtype != torch.float64 or not origins.is_contiguous() \
+                or not dirs.is_contiguous() or origins.shape != dirs.shape:
+            raise ValueError("origins/dirs must be contiguous float64 (N, 3) device tensors")
+        rid = ctypes.c_int64()
+        _check(load().vor_server_submit(self._h, int(grid), _ptr(origins), _ptr(dirs), origins.shape[0],
+                                        _ptr(density), float(kappa), MODES[mode], int(seg_stride),
+                                        ctypes.byref(rid)), "vor_server_submit")
+        self._keep[rid.value] = (origins, dirs, density, int(seg_stride), origins.shape[0])
+        return rid.value
+
+    def poll(self, req: int) -> bool:
+        d = ctypes.c_int32()
+        _check(load().vor_server_poll(self._h, req, ctypes.byref(d)), "vor_server_poll")
+        return bool(d.value)
+
+    def wait(self, req: int, timeout_s: float = 60.0) -> None:
+        _check(load().vor_server_wait(self._h, req, float(timeout_s)), "vor_server_wait")
+
+    def latency(self, req: int) -> float:
+        o = TraceOut()
+        lat = ctypes.c_double()
+        _check(load().vor_server_result(self._h, req, ctypes.byref(o), ctypes.byref(lat)), "vor_server_result")
+        return lat.value
+
+    def result(self, req: int, stream=None) -> dict:
+        """Copy the request's outputs into new tensors."""
+        _, _, _, stride, n = self._keep[req]
+        res = dict(tau=torch.empty(n, dtype=torch.float64, device="cuda"),
+                   n_seg=torch.empty(n, dtype=torch.int32, device="cuda"),
+                   status=torch.empty(n, dtype=torch.uint8, device="cuda"))
+        if stride > 0:
+            res["seg_cell"] = torch.empty(n * stride, dtype=torch.int32, device="cuda")
+            res["seg_len"] = torch.empty(n * stride, dtype=torch.float64, device="cuda")
+        _check(load().vor_server_copy_result(self._h, req, _ptr(res["tau"]), _ptr(res["n_seg"]), _ptr(res["status"]),
+                                             _ptr(res.get("seg_cell")), _ptr(res.get("seg_len")), _stream(stream)),
+               "vor_server_copy_result")
+        res["seg_stride"] = stride
+        return res
+
+    def release(self, req: int) -> None:
+        _check(load().vor_server_release(self._h, req), "vor_server_release")
+        self._keep.pop(req, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().vor_server_get_stats(self._h, ctypes.byref(st)), "vor_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().vor_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
 
 
 def version() -> str:

@@ -96,3 +96,23 @@ def test_oracle_and_product_share_no_code():
     for f in ("__init__.py", "exact.py", "dda.py"):
         text = open(os.path.join(ROOT, "oracle", f)).read()
         assert "paper_1310_1854_amd" not in text, f
+
+
+def test_server_argument_errors_before_device_work(lib):
+    from paper_1310_1854_amd import vrt
+    out = ctypes.c_void_p(77)
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.vor_server_create(None, 1, 1 << 20, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert out.value is None
+    assert lib.vor_server_create(arr, 1, 1 << 20, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert lib.vor_server_create(arr, 0, 1 << 20, ctypes.byref(out)) == vrt.VOR_EINVAL
+    rid = ctypes.c_int64(5)
+    fake = (ctypes.c_double * 30)()
+    assert lib.vor_server_submit(None, 0, fake, fake, 10, None, 1.0, 0, 0, ctypes.byref(rid)) == vrt.VOR_EINVAL
+    done = ctypes.c_int32()
+    assert lib.vor_server_poll(None, 1, ctypes.byref(done)) == vrt.VOR_EINVAL
+    assert lib.vor_server_wait(None, 1, 0.1) == vrt.VOR_EINVAL
+    assert lib.vor_server_release(None, 1) == vrt.VOR_EINVAL
+    st = vrt.ServerStats()
+    assert lib.vor_server_get_stats(None, ctypes.byref(st)) == vrt.VOR_EINVAL
+    lib.vor_server_destroy(None)

@@ -1,0 +1,148 @@
+"""Serving: resident grids, budgeted admission, continuous batching.
+
+Each request's result must be the same alone and in a mix of requests on
+different grids and precision classes, and the same as vor_trace of the
+same rays; admission never exceeds the budget; a request that can never
+fit is rejected; requests are admitted first-in-first-out."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1310_1854_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1310_1854_amd import vrt
+    vrt.load()
+    ws = [W.uniform_cube(M=10_000, N=1, seed=401), W.exp_disc(M=100_000, N=1, seed=402),
+          W.flared_disc(M=200_000, N=1, seed=403)]
+    grids = [vrt.build_grid(w.sites, w.box) for w in ws]
+    rhos = [torch.as_tensor(w.density, device="cuda") for w in ws]
+    return vrt, torch, ws, grids, rhos
+
+
+def _requests(ws, n_req, seed, lo=256, hi=8192):
+    import torch
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        g = int(rng.integers(0, len(ws)))
+        w = ws[g]
+        n = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        if g == 0:
+            o = W.uniform_in_box(rng, n, w.box)
+        else:
+            o = np.ascontiguousarray(w.sites[rng.integers(0, w.M, n)])
+        d = W.isotropic_dirs(rng, n)
+        reqs.append(dict(grid=g, mode=["fp64", "mixed"][int(rng.integers(0, 2))],
+                         o=torch.as_tensor(o, device="cuda"), d=torch.as_tensor(d, device="cuda")))
+    return reqs
+
+
+def _same(a, b):
+    """Equal per-ray results and equal segments in every written slot (slots
+    past a ray's count are not written and hold whatever was there)."""
+    import torch
+    if not all(torch.equal(a[k], b[k]) for k in ("tau", "n_seg", "status")):
+        return False
+    stride = a["seg_stride"]
+    n = a["tau"].numel()
+    mask = torch.arange(stride, device="cuda")[None, :] < a["n_seg"].clamp(max=stride)[:, None]
+    return all(torch.equal(a[k].view(n, stride)[mask], b[k].view(n, stride)[mask]) for k in ("seg_cell", "seg_len"))
+
+
+def test_alone_equals_in_the_mix_equals_vor_trace(env):
+    vrt, torch, ws, grids, rhos = env
+    reqs = _requests(ws, 24, seed=5)
+    stride = 96
+    srv = vrt.Server(grids, budget_bytes=2 << 30)
+    try:
+        alone = []
+        for r in reqs:
+            rid = srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=stride)
+            srv.wait(rid, 120)
+            alone.append(srv.result(rid))
+            srv.release(rid)
+        ids = [srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=stride)
+               for r in reqs]
+        for rid in ids:
+            srv.wait(rid, 120)
+        mixed = [srv.result(rid) for rid in ids]
+        torch.cuda.synchronize()
+        for rid in ids:
+            srv.release(rid)
+        st = srv.stats()
+    finally:
+        srv.close()
+    for r, a, m in zip(reqs, alone, mixed):
+        assert _same(a, m)
+        ref = vrt.trace(grids[r["grid"]], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], segments="stride",
+                        seg_stride=stride)
+        assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
+        assert torch.equal(ref["status"], a["status"])
+        # the first min(n_seg, stride) slots of every ray agree
+        ns = a["n_seg"].clamp(max=stride)
+        mask = torch.arange(stride, device="cuda")[None, :] < ns[:, None]
+        n = r["o"].shape[0]
+        assert torch.equal(ref["seg_cell"].view(n, stride)[mask], a["seg_cell"].view(n, stride)[mask])
+        assert torch.equal(ref["seg_len"].view(n, stride)[mask], a["seg_len"].view(n, stride)[mask])
+    assert st["completed"] == 2 * len(reqs)
+    assert st["crossings"] == 2 * sum(int(a["n_seg"].sum()) for a in alone)
+
+
+def test_budget_admission_and_rejection(env):
+    vrt, torch, ws, grids, rhos = env
+    reqs = _requests(ws, 40, seed=6, lo=2000, hi=20000)
+    stride = 64
+    per_ray = 8 + 4 + 1 + stride * 12
+    budget = 30_000 * per_ray + (1 << 20)   # room for about one large request at a time
+    srv = vrt.Server(grids, budget_bytes=budget)
+    try:
+        big = torch.zeros((200_000, 3), dtype=torch.float64, device="cuda")
+        with pytest.raises(vrt.VorError) as e:
+            srv.submit(0, big, big, None, seg_stride=stride)
+        assert e.value.code == vrt.VOR_EBUDGET
+        ids = [srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=stride)
+               for r in reqs]
+        done = [False] * len(ids)
+        order = []
+        t0 = time.time()
+        while not all(done):
+            st = srv.stats()
+            assert st["used_bytes"] <= budget
+            for i, rid in enumerate(ids):
+                if not done[i] and srv.poll(rid):
+                    done[i] = True
+                    order.append(i)
+                    srv.release(rid)
+            assert time.time() - t0 < 120, "requests starved"
+            time.sleep(0.001)
+        assert srv.stats()["used_bytes"] == 0
+    finally:
+        srv.close()
+    # first in, first admitted: completion order never runs far ahead of submission order
+    assert max(abs(a - b) for a, b in zip(order, range(len(order)))) < len(order)
+
+
+def test_server_argument_errors(env):
+    vrt, torch, ws, grids, rhos = env
+    srv = vrt.Server(grids[:1], budget_bytes=1 << 24)
+    try:
+        o = torch.zeros((10, 3), dtype=torch.float64, device="cuda")
+        with pytest.raises(vrt.VorError):
+            srv.submit(3, o, o)                       # no such grid
+        rid = srv.submit(0, o, o, None, seg_stride=4)  # zero directions: BADDIR rays
+        srv.wait(rid, 30)
+        res = srv.result(rid)
+        assert np.all(res["status"].cpu().numpy() == vrt.RAY_BADDIR)
+        srv.release(rid)
+        with pytest.raises(vrt.VorError):
+            srv.release(rid)                          # already released
+    finally:
+        srv.close()
