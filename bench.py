@@ -33,12 +33,16 @@ if ROOT not in sys.path:
 METRIC = "Voronoi cell crossings/sec per GPU at stated accuracy; p50/p99 batch latency"
 HBM_PEAK_GBS = 8000.0
 
-# Launch configuration per workload: mode, stride window, spill capacity factor.
+# Launch configuration per workload: mode, segment window per ray, spill
+# chunks (of 64 segments) per ray, coherent ray order, persistent kernel.
 WORKLOADS = {
-    "flared_disc": dict(cfg=2, mode="mixed", stride=128, spill_per_ray=24, cpu_rays=240),
-    "exp_disc": dict(cfg=1, mode="mixed", stride=128, spill_per_ray=16, cpu_rays=600),
-    "clumpy": dict(cfg=3, mode="mixed", stride=128, spill_per_ray=48, persistent=True, cpu_rays=60),
-    "uniform_cube": dict(cfg=0, mode="fp64", stride=64, spill_per_ray=8, cpu_rays=10000),
+    "flared_disc": dict(cfg=2, mode="mixed", stride=128, spill_chunks_per_ray=0.5, ordered=True, persistent=True,
+                        cpu_rays=240),
+    "exp_disc": dict(cfg=1, mode="mixed", stride=128, spill_chunks_per_ray=0.25, ordered=True, persistent=True,
+                     cpu_rays=600),
+    "clumpy": dict(cfg=3, mode="mixed", stride=128, spill_chunks_per_ray=1.0, ordered=True, persistent=True,
+                   cpu_rays=60),
+    "uniform_cube": dict(cfg=0, mode="fp64", stride=64, spill_chunks_per_ray=0.25, ordered=True, cpu_rays=10000),
 }
 
 
@@ -61,29 +65,44 @@ def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str) -> float:
     return b
 
 
-def make_buffers(vrt, N, spec, torch, spill=None):
-    spill = int(N * spec["spill_per_ray"]) if spill is None else int(spill)
-    return vrt.TraceBuffers(N, seg_stride=spec["stride"], spill_capacity=spill)
+def make_buffers(vrt, N, spec, torch, chunks=None):
+    chunks = int(N * spec["spill_chunks_per_ray"]) + 1 if chunks is None else int(chunks)
+    return vrt.TraceBuffers(N, seg_stride=spec["stride"], spill_chunks=chunks, ordered=spec.get("ordered", False))
 
 
 def prepare_buffers(vrt, torch, grid, o, d, rho, spec, mode=None):
-    """Output buffers for the workload: stride windows of the configured
-    size and a spill area sized up front from spill_per_ray and doubled
-    until a full step fits (set-up; the buffers are then reused)."""
+    """Output buffers for the workload: windows of the configured size and a
+    spill sized up front from spill_chunks_per_ray, doubled until a full step
+    fits (set-up; the buffers are then reused)."""
     mode = mode or spec["mode"]
     N = o.shape[0]
-    spill = int(N * spec["spill_per_ray"])
+    chunks = int(N * spec["spill_chunks_per_ray"]) + 1
     while True:
-        bufs = make_buffers(vrt, N, spec, torch, spill)
-        vrt.trace_into(grid, o, d, rho, bufs, mode=mode, persistent=spec.get("persistent", False))
+        bufs = make_buffers(vrt, N, spec, torch, chunks)
+        step(vrt, grid, o, d, rho, bufs, spec, mode)
         torch.cuda.synchronize()
-        if int(bufs.work[1].item()) <= spill:
+        asked = int(bufs.work[1].item())
+        if asked <= chunks:
             return bufs
-        spill = 2 * int(bufs.work[1].item())
+        chunks = 2 * asked
         del bufs
 
 
-def run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, n, timed):
+def step(vrt, grid, o, d, rho, bufs, spec, mode, reuse_order=False):
+    """One step of the path: the coherent ray order (unless reused), then the
+    trace with segment windows and spill."""
+    ordered = spec.get("ordered", False)
+    if ordered and not reuse_order:
+        vrt.order_rays(grid, o, d, bufs.order, bufs.order_ws)
+    opts = vrt.TraceOpts(vrt.MODES[mode], 0, 0.0, 1 if spec.get("persistent", False) else 0, 0)
+    out = bufs.struct(use_order=ordered)
+    rc = vrt.load().vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(d), o.shape[0], vrt._ptr(rho), 1.0,
+                              vrt.ctypes.byref(opts), vrt.ctypes.byref(out), vrt._stream())
+    if rc != vrt.VOR_OK:
+        raise vrt.VorError(rc, "vor_trace")
+
+
+def run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, n, timed, reuse_order=False):
     """Run n steps; with timed=True return per-step milliseconds (HIP events
     on the stream the library launches on, i.e. torch's current stream)."""
     times = []
@@ -93,7 +112,7 @@ def run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, n, timed):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-        vrt.trace_into(grid, o, d, rho, bufs, mode=mode, persistent=spec.get("persistent", False))
+        step(vrt, grid, o, d, rho, bufs, spec, mode, reuse_order=reuse_order)
         if timed:
             e1.record(stream)
             times.append((e0, e1))
@@ -257,13 +276,13 @@ def main(argv=None):
     tau_mixed = bufs.tau.clone()
     nseg_mixed = bufs.n_seg.clone()
 
-    # the trace kernel alone (same windows, no spill) for the roofline
-    rb = vrt.TraceBuffers(w.N, seg_stride=spec["stride"])
-    rb.seg_cell, rb.seg_len = bufs.seg_cell, bufs.seg_len
-    run_steps(vrt, torch, grid, o, d, rho, rb, spec, mode, 1, timed=False)
-    rb.counters.zero_()
-    k_ms = run_steps(vrt, torch, grid, o, d, rho, rb, spec, mode, args.roofline_reps, timed=True)
-    kc = rb.counters.cpu().numpy().astype(np.float64) / args.roofline_reps
+    # the trace kernel alone for the roofline: the same launch with the order
+    # already computed (events around vor_trace only)
+    k_ms = run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, 1, timed=False)
+    bufs.counters.zero_()
+    k_ms = run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, args.roofline_reps, timed=True,
+                     reuse_order=True)
+    kc = bufs.counters.cpu().numpy().astype(np.float64) / args.roofline_reps
     k_avg = float(np.mean(k_ms))
     alg = algorithmic_bytes(kc, w.N, mode)
     achieved = alg / (k_avg / 1e3) / 1e9
@@ -296,11 +315,12 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.M} sites, {w.N} rays, {mode} mode (configs[{spec['cfg']}])",
                    "sites": w.M, "rays": w.N, "mode": mode, "seg_stride": spec["stride"],
+                   "ordered": bool(spec.get("ordered", False)),
                    "persistent": bool(spec.get("persistent", False))},
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),
         "crossings_per_step": crossings,
-        "spilled_rays_per_step": spilled,
+        "rays_past_window_per_step": spilled,
         "records_per_step": recs_per_step,
         "fp64_redecision_rate": c[2] / max(c[3], 1),
         "fp64_value": fp64_value,
@@ -310,7 +330,8 @@ def main(argv=None):
                  "device_bytes": info["device_bytes"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_trace", "kernel_avg_ms": k_avg, "algorithmic_bytes": alg},
+                     "kernel": "k_trace_persistent" if spec.get("persistent") else "k_trace",
+                     "kernel_avg_ms": k_avg, "algorithmic_bytes": alg},
     }
     if not args.no_cpu:
         import oracle
@@ -318,14 +339,13 @@ def main(argv=None):
         result["cpu_baseline"] = cpu
         # accuracy on the sample: the same rays through the library
         res = vrt.trace(grid, sub.origins, sub.dirs, w.density, mode=mode, segments="exact")
-        n_seg, get = vrt.gather_paths(res)
         tau = res["tau"].cpu().numpy()
         mism = 0
         max_dl = max_dt = 0.0
         for i in range(sub.N):
             if ref["n_near"][i] > 0:
                 continue
-            cells, lens = get(i)
+            cells, lens = vrt.ray_path(res, i)
             n = int(ref["nseg"][i])
             if len(cells) != n or not np.array_equal(cells, ref["seg_cell"][i, :n]):
                 mism += 1

@@ -69,6 +69,9 @@ enum {
 
 typedef struct vor_grid vor_grid;
 
+/* Segments per spill chunk (see vor_trace_out). */
+#define VOR_SPILL_CHUNK 64
+
 /* Options of vor_build_grid; zero-initialised fields take the defaults. */
 typedef struct {
     double bucket_occupancy;  /* mean sites per bucket of the uniform site grid (default 2) */
@@ -159,16 +162,19 @@ typedef struct {
     int64_t *work;          /* [4] control words, required for persistent mode and spill; zeroed by the call */
     /* Spill (stride mode only, all NULL to disable): a ray whose path is
      * longer than seg_stride keeps its first seg_stride segments in its
-     * window and is given spill_off[i] = the start of n_seg[i] - seg_stride
-     * slots in spill_cell/spill_len, where a second pass writes the rest of
-     * its path (spill_off[i] = -1 for rays that fit). If the spill is full
-     * the ray's status is VOR_RAY_OVERFLOW. spill_rays [N] is scratch;
-     * work[1] ends as the spill slots used and work[2] as the spilled rays. */
-    int64_t *spill_off;     /* [N] */
-    int32_t *spill_rays;    /* [N] */
-    int32_t *spill_cell;
-    double *spill_len;
-    int64_t spill_capacity; /* slots in spill_cell / spill_len */
+     * window and continues in a chain of chunks of VOR_SPILL_CHUNK slots in
+     * spill_cell/spill_len: spill_first[i] is the ray's first chunk (-1 if
+     * none), spill_next[c] the chunk after chunk c (-1 at the end). Chunks
+     * are handed out as paths grow, in one pass. If the chunks run out the
+     * ray's status is VOR_RAY_OVERFLOW (count and tau stay complete).
+     * work[1] ends as the number of chunks asked for. */
+    int64_t *spill_first;   /* [N] */
+    int32_t *spill_next;    /* [spill_chunks] */
+    int32_t *spill_cell;    /* [spill_chunks * VOR_SPILL_CHUNK] */
+    double *spill_len;      /* [spill_chunks * VOR_SPILL_CHUNK] */
+    int64_t spill_chunks;
+    const int32_t *ray_order; /* optional [N]: lane i traces ray ray_order[i] (a permutation, e.g. from
+                                 vor_order_rays); outputs stay indexed by ray */
 } vor_trace_out;
 
 /*
@@ -191,6 +197,20 @@ typedef struct {
 vor_status vor_trace(const vor_grid *grid, const double *origins, const double *dirs, int64_t N,
                      const double *density, double kappa, const vor_trace_opts *opts,
                      const vor_trace_out *out, void *stream);
+
+/*
+ * vor_order_rays -- a processing order for a batch of rays that keeps
+ * neighbouring lanes on neighbouring paths: rays sorted by the Hilbert
+ * index of their origin (10 bits per axis over the grid's box) and, among
+ * equal origins, of their direction. Pass it as vor_trace_out.ray_order;
+ * results do not depend on the order, only the speed does.
+ *   origins, dirs  device, N x 3.   order  device, N int32 (a permutation).
+ *   workspace      device, at least vor_order_workspace_bytes(N) bytes.
+ * Asynchronous; allocates nothing.
+ */
+vor_status vor_order_rays(const vor_grid *grid, const double *origins, const double *dirs, int64_t N,
+                          int32_t *order, void *workspace, int64_t workspace_bytes, void *stream);
+int64_t vor_order_workspace_bytes(int64_t N);
 
 /*
  * vor_exclusive_scan -- offsets[0] = 0, offsets[i+1] = offsets[i] + counts[i]

@@ -20,39 +20,6 @@ using namespace vrt;
 
 namespace {
 
-// Hilbert index of a point with kHilbertBits-bit integer coordinates, by
-// Skilling's transform ("Programming the Hilbert curve", AIP Conf. Proc.
-// 707, 2004): undo the excess work of the recursion, Gray-encode, then
-// interleave the bits of the three transposed coordinates.
-__device__ uint32_t hilbert_key(uint32_t x, uint32_t y, uint32_t z)
-{
-    uint32_t X[3] = {x, y, z};
-    const uint32_t top = 1u << (kHilbertBits - 1);
-    for (uint32_t Q = top; Q > 1; Q >>= 1) {
-        uint32_t P = Q - 1;
-        for (int i = 0; i < 3; ++i) {
-            if (X[i] & Q) {
-                X[0] ^= P;
-            } else {
-                uint32_t t = (X[0] ^ X[i]) & P;
-                X[0] ^= t;
-                X[i] ^= t;
-            }
-        }
-    }
-    X[1] ^= X[0];
-    X[2] ^= X[1];
-    uint32_t t = 0;
-    for (uint32_t Q = top; Q > 1; Q >>= 1)
-        if (X[2] & Q) t ^= Q - 1;
-    for (int i = 0; i < 3; ++i) X[i] ^= t;
-    uint32_t key = 0;
-    for (int b = kHilbertBits - 1; b >= 0; --b)
-        key = (key << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) | ((X[2] >> b) & 1u);
-    return key;
-}
-
-
 __global__ void k_validate_keys(const double *__restrict__ sites, int64_t M, BoxArg box, double scale,
                                 uint32_t *__restrict__ keys, int32_t *__restrict__ vals, int *__restrict__ err)
 {

@@ -81,6 +81,10 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
         const ChunkDev ch = chunks[c];
         const ReqDev rq = reqs[ch.req];
         const GridRef G = grids[rq.grid];
+        SegOut O{};
+        O.cell = rq.seg_cell;
+        O.len = rq.seg_len;
+        O.vec4 = (rq.seg_cell && rq.seg_stride % 4 == 0) ? 1 : 0;
         int next = 0;   // rays of the chunk handed out so far (wave-uniform)
         bool live = false;
         RayState R;
@@ -96,7 +100,8 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     S = RayStats();
                     R.st = ray_setup(G, rq.in, ray, R.r0, R.k, R.L);
                     R.tau = 0.0;
-                    R.skip = 0;
+                    R.chunk = -1;
+                    R.ray = (int32_t)ray;
                     R.base = ray * rq.seg_stride;
                     R.cap = rq.seg_cell ? rq.seg_stride : 0;
                     if (R.st == RAY_OK) ray_begin(G, R);
@@ -108,9 +113,10 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
             if (__ballot(live) == 0ull) break;
             if (live) {
                 bool more = (rq.mode == VOR_MODE_MIXED)
-                                ? ray_step<VOR_MODE_MIXED, true>(G, rq.in, R, S, rq.seg_cell, rq.seg_len)
-                                : ray_step<VOR_MODE_FP64, true>(G, rq.in, R, S, rq.seg_cell, rq.seg_len);
+                                ? ray_step<VOR_MODE_MIXED, true>(G, rq.in, R, S, O)
+                                : ray_step<VOR_MODE_FP64, true>(G, rq.in, R, S, O);
                 if (!more) {
+                    finish_segments(O, R, S.cnt);
                     if (rq.seg_cell && R.st == RAY_OK && S.cnt > R.cap) R.st = RAY_OVERFLOW;
                     rq.tau[ray] = R.tau;
                     rq.n_seg[ray] = S.cnt;

@@ -74,7 +74,21 @@ __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__re
     }
 }
 
+__global__ void k_gather_u32(const uint32_t *__restrict__ src, const int32_t *__restrict__ idx, int64_t n,
+                             uint32_t *__restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
 }  // namespace
+
+vor_status vrt_gather_u32(const uint32_t *src, const int32_t *idx, int64_t n, uint32_t *dst, hipStream_t st)
+{
+    if (n <= 0) return VOR_OK;
+    hipLaunchKernelGGL(k_gather_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, idx, n, dst);
+    return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
+}
 
 int64_t vrt_radix_hist_len(int64_t n)
 {

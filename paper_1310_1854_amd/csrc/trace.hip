@@ -18,24 +18,31 @@ namespace {
 struct TraceArgs {
     GridRef G;
     RayIn I;
+    SegOut O;
     int64_t N;
     double *tau;
     int32_t *n_seg;
     uint8_t *status;
     int32_t *n_fb;
-    int32_t *seg_cell;
-    double *seg_len;
     int64_t seg_stride;
     const int64_t *ray_off;
+    const int32_t *order;
     unsigned long long *counters;
-    // spill of paths longer than their window (stride mode)
-    int64_t *work;        // [0] persistent queue head, [1] spill slots used, [2] spilled rays
-    int32_t *spill_rays;
-    int64_t *spill_off;
-    int32_t *spill_cell;
-    double *spill_len;
-    int64_t spill_capacity;
+    int64_t *work;        // [0] persistent queue head, [1] spill chunks asked for, [2] rays past their window
 };
+
+#ifndef VRT_REFILL_MIN
+#define VRT_REFILL_MIN 48
+#endif
+#ifndef VRT_WAVES_PER_EU
+#define VRT_WAVES_PER_EU 0
+#endif
+#if VRT_WAVES_PER_EU
+#define VRT_OCC __attribute__((amdgpu_waves_per_eu(VRT_WAVES_PER_EU)))
+#else
+#define VRT_OCC
+#endif
+constexpr int kRefillMin = VRT_REFILL_MIN;   // idle lanes that trigger a refill in the persistent kernel
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
 {
@@ -43,13 +50,14 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
     return v;
 }
 
-// Output window of ray `ray` in the main pass.
+// Output window of ray `ray`.
 template <bool SEGS>
 __device__ __forceinline__ void ray_window(const TraceArgs &A, int64_t ray, RayState &R)
 {
     R.base = 0;
     R.cap = 0;
-    R.skip = 0;
+    R.chunk = -1;
+    R.ray = (int32_t)ray;
     if (SEGS) {
         if (A.seg_stride > 0) {
             R.base = ray * A.seg_stride;
@@ -61,25 +69,14 @@ __device__ __forceinline__ void ray_window(const TraceArgs &A, int64_t ray, RayS
     }
 }
 
-// Results of a finished ray; a path longer than its stride window gets a
-// slot range in the spill (when one is given) for the part past the
-// window, which the spill pass writes.
+// Results of a finished ray.
 template <bool SEGS>
 __device__ __forceinline__ void ray_finish(const TraceArgs &A, int64_t ray, RayState &R, const RayStats &S)
 {
-    if (SEGS && R.st == RAY_OK && S.cnt > R.cap) {
-        bool spilled = false;
-        if (A.spill_cell && A.seg_stride > 0) {
-            const int64_t tail = S.cnt - R.cap;
-            unsigned long long off = atomicAdd((unsigned long long *)&A.work[1], (unsigned long long)tail);
-            if ((int64_t)off + tail <= A.spill_capacity) {
-                A.spill_off[ray] = (int64_t)off;
-                unsigned long long idx = atomicAdd((unsigned long long *)&A.work[2], 1ull);
-                A.spill_rays[idx] = (int32_t)ray;
-                spilled = true;
-            }
-        }
-        if (!spilled) R.st = RAY_OVERFLOW;
+    if (SEGS) finish_segments(A.O, R, S.cnt);
+    if (SEGS && S.cnt > R.cap) {
+        if (A.work) atomicAdd((unsigned long long *)&A.work[2], 1ull);
+        if (R.st == RAY_OK && (!A.O.spill_cell || R.chunk == -2)) R.st = RAY_OVERFLOW;
     }
     A.tau[ray] = R.tau;
     A.n_seg[ray] = S.cnt;
@@ -104,32 +101,39 @@ __device__ __forceinline__ void flush_counters(const TraceArgs &A, const RayStat
     }
 }
 
+__device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RayState &R)
+{
+    R.st = ray_setup(A.G, A.I, ray, R.r0, R.k, R.L);
+    R.tau = 0.0;
+    if (R.st == RAY_OK) ray_begin(A.G, R);
+    else R.L = 0.0;
+}
+
 // One ray per lane.
 template <int MODE, bool SEGS>
-__global__ void __launch_bounds__(256) k_trace(TraceArgs A)
+__global__ void __launch_bounds__(256) VRT_OCC k_trace(TraceArgs A)
 {
-    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t lane_ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     RayStats S;
-    if (ray < A.N) {
+    if (lane_ray < A.N) {
+        const int64_t ray = A.order ? (int64_t)A.order[lane_ray] : lane_ray;
         RayState R;
-        R.st = ray_setup(A.G, A.I, ray, R.r0, R.k, R.L);
         ray_window<SEGS>(A, ray, R);
-        R.tau = 0.0;
-        if (R.st == RAY_OK) {
-            ray_begin(A.G, R);
-            while (ray_step<MODE, SEGS>(A.G, A.I, R, S, A.seg_cell, A.seg_len)) {
-            }
+        ray_start(A, ray, R);
+        while (ray_step<MODE, SEGS>(A.G, A.I, R, S, A.O)) {
         }
         ray_finish<SEGS>(A, ray, R, S);
     }
     flush_counters(A, S);
 }
 
-// Persistent waves: every lane keeps a ray in flight; when rays end, the
-// wave's idle lanes take the next rays from the work queue together (one
-// atomic per wave, ranks from the ballot).
+// Persistent waves: every lane keeps a ray in flight. Lanes whose ray has
+// ended wait until at least kRefillMin of the wave's lanes are idle (or
+// none is busy); then they take the next rays from the work queue together
+// (one atomic per wave, ranks from the ballot) and start them side by side,
+// so the start-cell searches of the refilled lanes overlap.
 template <int MODE, bool SEGS>
-__global__ void __launch_bounds__(256) k_trace_persistent(TraceArgs A)
+__global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -140,32 +144,35 @@ __global__ void __launch_bounds__(256) k_trace_persistent(TraceArgs A)
     unsigned long long *head = (unsigned long long *)&A.work[0];
     bool drained = false;   // wave-uniform: the queue has run out
     for (;;) {
-        bool need = !live;
-        uint64_t want = __ballot(need);
-        if (want && !drained) {
+        const bool need = !live;
+        const uint64_t want = __ballot(need);
+        const uint64_t busy = ~want & __ballot(true);
+        if (want && !drained && (__popcll(want) >= kRefillMin || busy == 0ull)) {
             int n = __popcll(want);
+            int leader = __ffsll((long long)want) - 1;
             unsigned long long base0 = 0;
-            if (lane == __ffsll((long long)want) - 1) base0 = atomicAdd(head, (unsigned long long)n);
-            base0 = __shfl(base0, __ffsll((long long)want) - 1, 64);
+            if (lane == leader) base0 = atomicAdd(head, (unsigned long long)n);
+            base0 = __shfl(base0, leader, 64);
             if (need) {
-                ray = (int64_t)(base0 + __popcll(want & lt));
-                if (ray < A.N) {
+                int64_t q = (int64_t)(base0 + __popcll(want & lt));
+                if (q < A.N) {
+                    ray = A.order ? (int64_t)A.order[q] : q;
                     S = RayStats();
-                    R.st = ray_setup(A.G, A.I, ray, R.r0, R.k, R.L);
                     ray_window<SEGS>(A, ray, R);
-                    R.tau = 0.0;
+                    ray_start(A, ray, R);
                     live = true;
-                    if (R.st == RAY_OK) ray_begin(A.G, R);
-                    else R.L = 0.0;
                 } else {
                     ray = -1;
                 }
             }
             drained = __ballot(need && ray < 0) != 0ull;
         }
-        if (__ballot(live) == 0ull) break;   // the queue is drained and every ray has ended
+        if (__ballot(live) == 0ull) {
+            if (drained) break;   // the queue is drained and every ray has ended
+            continue;
+        }
         if (live) {
-            if (!ray_step<MODE, SEGS>(A.G, A.I, R, S, A.seg_cell, A.seg_len)) {
+            if (!ray_step<MODE, SEGS>(A.G, A.I, R, S, A.O)) {
                 ray_finish<SEGS>(A, ray, R, S);
                 T.cnt += S.cnt;
                 T.nfb += S.nfb;
@@ -179,27 +186,28 @@ __global__ void __launch_bounds__(256) k_trace_persistent(TraceArgs A)
     flush_counters(A, T);
 }
 
-// Spill pass: rays whose path outgrew their stride window are traced again
-// and write the segments past the window at their spill offset. Grid-stride
-// over the spilled rays counted by the main pass.
-template <int MODE>
-__global__ void __launch_bounds__(256) k_trace_spill(TraceArgs A)
+// Sort keys of a ray: Hilbert index of its origin (10 bits per axis over the
+// box) and of its direction ((k/|k| + 1)/2 over the unit cube).
+__global__ void k_ray_keys(const double *__restrict__ origins, const double *__restrict__ dirs, int64_t N,
+                           double lo0, double lo1, double lo2, double s0, double s1, double s2,
+                           uint32_t *__restrict__ okey, uint32_t *__restrict__ dkey, int32_t *__restrict__ idx)
 {
-    const int64_t n = A.work[2];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t ray = A.spill_rays[i];
-        RayState R;
-        RayStats S;
-        R.st = ray_setup(A.G, A.I, ray, R.r0, R.k, R.L);
-        R.skip = A.seg_stride;
-        R.base = A.spill_off[ray] - A.seg_stride;
-        R.cap = 1ll << 62;
-        if (R.st == RAY_OK) {
-            ray_begin(A.G, R);
-            while (ray_step<MODE, true>(A.G, A.I, R, S, A.spill_cell, A.spill_len)) {
-            }
-        }
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double lo[3] = {lo0, lo1, lo2}, sc[3] = {s0, s1, s2};
+    uint32_t qo[3], qd[3];
+    double k[3] = {dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
+    double kn = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    if (!(kn > 0.0) || !isfinite(kn)) kn = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        double f = (origins[3 * i + a] - lo[a]) * sc[a];
+        double g = (k[a] / kn + 1.0) * 512.0;
+        qo[a] = (uint32_t)(f > 0.0 ? (f < 1023.0 ? f : 1023.0) : 0.0);
+        qd[a] = (uint32_t)(g > 0.0 ? (g < 1023.0 ? g : 1023.0) : 0.0);
     }
+    okey[i] = hilbert_key(qo[0], qo[1], qo[2]);
+    dkey[i] = hilbert_key(qd[0], qd[1], qd[2]);
+    idx[i] = (int32_t)i;
 }
 
 __global__ void k_zero_i64(int64_t *p, int n)
@@ -257,8 +265,8 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     if (!segs && out->seg_len) return VOR_EINVAL;
     if (out->seg_stride < 0) return VOR_EINVAL;
     const bool spill = out->spill_cell != nullptr;
-    if (spill && (!segs || out->seg_stride <= 0 || !out->spill_len || !out->spill_off || !out->spill_rays ||
-                  !out->work || out->spill_capacity < 0))
+    if (spill && (!segs || out->seg_stride <= 0 || !out->spill_len || !out->spill_first || !out->spill_next ||
+                  !out->work || out->spill_chunks < 0 || out->spill_chunks > 0x7fffffffLL))
         return VOR_EINVAL;
     int mode = opts ? opts->mode : VOR_MODE_FP64;
     if (mode != VOR_MODE_FP64 && mode != VOR_MODE_MIXED) return VOR_EINVAL;
@@ -277,23 +285,26 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     A.n_seg = out->n_seg;
     A.status = out->status;
     A.n_fb = out->n_fallback;
-    A.seg_cell = out->seg_cell;
-    A.seg_len = out->seg_len;
     A.seg_stride = out->seg_stride;
     A.ray_off = out->ray_off;
+    A.order = out->ray_order;
     A.counters = out->counters;
     A.work = out->work;
-    A.spill_rays = out->spill_rays;
-    A.spill_off = out->spill_off;
-    A.spill_cell = out->spill_cell;
-    A.spill_len = out->spill_len;
-    A.spill_capacity = out->spill_capacity;
+    A.O.cell = out->seg_cell;
+    A.O.len = out->seg_len;
+    A.O.vec4 = (out->seg_stride > 0 && out->seg_stride % 4 == 0) ? 1 : 0;
+    A.O.spill_cell = spill ? out->spill_cell : nullptr;
+    A.O.spill_len = out->spill_len;
+    A.O.spill_next = out->spill_next;
+    A.O.spill_first = out->spill_first;
+    A.O.spill_chunks = out->spill_chunks;
+    A.O.chunk_head = out->work ? (unsigned long long *)&out->work[1] : nullptr;
     hipStream_t st = (hipStream_t)stream;
     const int T = 256;
     if (A.work) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, A.work, 4);
     if (spill) {
         int64_t nb = std::min<int64_t>((N + T - 1) / T, 65535);
-        hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)nb), dim3(T), 0, st, A.spill_off, N, (int64_t)-1);
+        hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)nb), dim3(T), 0, st, A.O.spill_first, N, (int64_t)-1);
     }
     dim3 block(T);
     if (persistent) {
@@ -328,11 +339,45 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
             else hipLaunchKernelGGL((k_trace<VOR_MODE_MIXED, false>), grid, block, 0, st, A);
         }
     }
-    if (spill) {
-        dim3 grid(1024);
-        if (mode == VOR_MODE_FP64) hipLaunchKernelGGL((k_trace_spill<VOR_MODE_FP64>), grid, block, 0, st, A);
-        else hipLaunchKernelGGL((k_trace_spill<VOR_MODE_MIXED>), grid, block, 0, st, A);
-    }
+    return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
+}
+
+extern "C" int64_t vor_order_workspace_bytes(int64_t N)
+{
+    if (N < 0) return -1;
+    int64_t hl = vrt_radix_hist_len(N);
+    return 4 * N * (int64_t)sizeof(uint32_t) + (2 * hl + 1) * (int64_t)sizeof(int32_t) + 1024;
+}
+
+extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, const double *dirs, int64_t N,
+                                     int32_t *order, void *workspace, int64_t workspace_bytes, void *stream)
+{
+    if (!G || N < 0 || (N > 0 && (!origins || !dirs || !order || !workspace))) return VOR_EINVAL;
+    if (N == 0) return VOR_OK;
+    if (N > 0x7fffffffLL || workspace_bytes < vor_order_workspace_bytes(N)) return VOR_EINVAL;
+    const Grid &g = vrt_grid_of(G);
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    uint32_t *okey = (uint32_t *)w;
+    uint32_t *dkey = okey + N;
+    uint32_t *ktmp = dkey + N;
+    int32_t *vtmp = (int32_t *)(ktmp + N);
+    int64_t hl = vrt_radix_hist_len(N);
+    int32_t *hist = vtmp + N;
+    (void)hl;
+    double sc[3];
+    for (int a = 0; a < 3; ++a) sc[a] = 1024.0 / (g.box[a + 3] - g.box[a]);
+    const int T = 256;
+    hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((N + T - 1) / T)), dim3(T), 0, st, origins, dirs, N, g.box[0],
+                       g.box[1], g.box[2], sc[0], sc[1], sc[2], okey, dkey, order);
+    // by direction, then stably by origin: rays from one place in similar directions end up together
+    vor_status rc = vrt_radix_sort_pairs(dkey, order, ktmp, vtmp, N, 30, hist, vrt_radix_hist_len(N), st);
+    if (rc != VOR_OK) return rc;
+    // the origin keys must follow the same permutation before the second sort
+    rc = vrt_gather_u32(okey, order, N, ktmp, st);
+    if (rc != VOR_OK) return rc;
+    rc = vrt_radix_sort_pairs(ktmp, order, okey, vtmp, N, 30, hist, vrt_radix_hist_len(N), st);
+    if (rc != VOR_OK) return rc;
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 

@@ -37,6 +37,26 @@ struct RayIn {
     double kappa;
 };
 
+// Where segments go: a window per ray, then (optionally) a chain of spill
+// chunks of kSpillChunk segments for the part of a path past its window.
+constexpr int kSpillChunk = VOR_SPILL_CHUNK;
+
+#ifndef VRT_VEC_STORE
+#define VRT_VEC_STORE 1
+#endif
+
+struct SegOut {
+    int32_t *cell;                  // window slots
+    double *len;
+    int vec4;                       // windows start on multiples of 4 slots: store 4 segments at a time
+    int32_t *spill_cell;            // chunk c holds slots [c * kSpillChunk, (c + 1) * kSpillChunk)
+    double *spill_len;
+    int32_t *spill_next;            // next chunk of the same path, -1 at the end
+    int64_t *spill_first;           // first chunk of each ray, -1 if none
+    int64_t spill_chunks;           // capacity in chunks
+    unsigned long long *chunk_head; // chunks handed out
+};
+
 inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
 {
     GridRef G;
@@ -227,8 +247,13 @@ struct RayState {
     double r0[3], k[3], pm[3];
     int2 rw;              // the current cell's row of neighbour records
     double L, s_c, tau;
-    int64_t base, cap;
-    int64_t skip;         // segments with a smaller index are not written
+    int64_t base, cap;    // window of this ray's first segments
+    int32_t chunk;        // current spill chunk, -1 none yet, -2 spill exhausted
+    int32_t ray;
+#if VRT_VEC_STORE
+    int32_t c0, c1, c2, c3;   // the last four segments, oldest first, written 4 at a time
+    double l0, l1, l2, l3;
+#endif
     int32_t m, uid;
     uint8_t st;
 };
@@ -250,9 +275,109 @@ __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R)
 
 // One exit-point step (Sect. 2.2). Returns false once the path has ended.
 // The next cell's row is fetched in the same round trip as its site.
+// Slot of segment idx of the ray: its window, else its current spill chunk;
+// null when the spill is exhausted or absent.
+__device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState &R, int64_t idx, bool &spill)
+{
+    if (idx < R.cap) {
+        spill = false;
+        return R.base + idx;
+    }
+    spill = true;
+    if (!O.spill_cell || R.chunk < 0) return -1;
+    return (int64_t)R.chunk * kSpillChunk + (idx - R.cap) % kSpillChunk;
+}
+
+// Store segment number idx of the ray: in its window, else in its spill
+// chain. A new chunk is taken when a path reaches the first slot of one;
+// lanes that do so in the same step share one atomic.
+__device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int64_t idx, int32_t cell, double len)
+{
+    if (idx >= R.cap && O.spill_cell) {
+        const int64_t k = idx - R.cap;
+        const bool need = (k % kSpillChunk) == 0 && R.chunk != -2;
+        const uint64_t bal = __ballot(need);
+        if (bal) {
+            const int lane = threadIdx.x & 63;
+            const int leader = __ffsll((long long)bal) - 1;
+            unsigned long long b = 0;
+            if (lane == leader) b = atomicAdd(O.chunk_head, (unsigned long long)__popcll(bal));
+            b = __shfl(b, leader, 64);
+            if (need) {
+                const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+                const int64_t c = (int64_t)b + __popcll(bal & lt);
+                if (c < O.spill_chunks) {
+                    O.spill_next[c] = -1;
+                    if (R.chunk < 0) O.spill_first[R.ray] = c;
+                    else O.spill_next[R.chunk] = (int32_t)c;
+                    R.chunk = (int32_t)c;
+                } else {
+                    R.chunk = -2;
+                }
+            }
+        }
+    }
+#if VRT_VEC_STORE
+    if (O.vec4) {
+        R.c0 = R.c1;
+        R.c1 = R.c2;
+        R.c2 = R.c3;
+        R.c3 = cell;
+        R.l0 = R.l1;
+        R.l1 = R.l2;
+        R.l2 = R.l3;
+        R.l3 = len;
+        if ((idx & 3) == 3) {
+            bool spill;
+            const int64_t p = segment_slot(O, R, idx - 3, spill);
+            if (p >= 0) {
+                int32_t *cp = spill ? O.spill_cell : O.cell;
+                double *lp = spill ? O.spill_len : O.len;
+                *reinterpret_cast<int4 *>(cp + p) = make_int4(R.c0, R.c1, R.c2, R.c3);
+                *reinterpret_cast<double2 *>(lp + p) = make_double2(R.l0, R.l1);
+                *reinterpret_cast<double2 *>(lp + p + 2) = make_double2(R.l2, R.l3);
+            }
+        }
+        return;
+    }
+#endif
+    bool spill;
+    const int64_t p = segment_slot(O, R, idx, spill);
+    if (p >= 0) {
+        (spill ? O.spill_cell : O.cell)[p] = cell;
+        (spill ? O.spill_len : O.len)[p] = len;
+    }
+}
+
+// Write the segments still held back when a path of n segments ends.
+__device__ __forceinline__ void finish_segments(const SegOut &O, const RayState &R, int64_t n)
+{
+#if VRT_VEC_STORE
+    if (!O.vec4) return;
+    const int rest = (int)(n & 3);
+    if (rest == 0) return;
+    const int32_t cs[4] = {R.c0, R.c1, R.c2, R.c3};
+    const double ls[4] = {R.l0, R.l1, R.l2, R.l3};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (j < rest) {
+            bool spill;
+            const int64_t p = segment_slot(O, R, n - rest + j, spill);
+            if (p >= 0) {
+                (spill ? O.spill_cell : O.cell)[p] = cs[4 - rest + j];
+                (spill ? O.spill_len : O.len)[p] = ls[4 - rest + j];
+            }
+        }
+    }
+#else
+    (void)O;
+    (void)R;
+    (void)n;
+#endif
+}
+
 template <int MODE, bool SEGS>
-__device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, int32_t *seg_cell,
-                                         double *seg_len)
+__device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, const SegOut &O)
 {
     if (!(R.L > 0.0)) return false;
     if (S.steps > G.max_steps) {
@@ -306,10 +431,7 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
     }
     double len = best - R.s_c;
     if (len > 0.0) {
-        if (SEGS && S.cnt < R.cap && S.cnt >= R.skip) {
-            seg_cell[R.base + S.cnt] = R.uid;
-            seg_len[R.base + S.cnt] = len;
-        }
+        if (SEGS) store_segment(O, R, S.cnt, R.uid, len);
         if (I.density) R.tau += I.kappa * I.density[R.uid] * len;
         ++S.cnt;
         R.s_c = best;

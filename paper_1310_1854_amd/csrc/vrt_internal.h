@@ -181,6 +181,41 @@ VRT_HD inline int32_t nearest_site(const BucketGridView &g, const double q[3], i
     return best_i;
 }
 
+constexpr int kHilbertBits10 = 10;   // bits per axis of the Hilbert keys
+
+// Hilbert index of a point with kHilbertBits10-bit integer coordinates, by
+// Skilling's transform ("Programming the Hilbert curve", AIP Conf. Proc.
+// 707, 2004): undo the excess work of the recursion, Gray-encode, then
+// interleave the bits of the three transposed coordinates.
+__device__ __forceinline__ uint32_t hilbert_key(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint32_t X[3] = {x, y, z};
+    const uint32_t top = 1u << (kHilbertBits10 - 1);
+    for (uint32_t Q = top; Q > 1; Q >>= 1) {
+        uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = top; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint32_t key = 0;
+    for (int b = kHilbertBits10 - 1; b >= 0; --b)
+        key = (key << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) | ((X[2] >> b) & 1u);
+    return key;
+}
+
+
 inline bool cuda_ok(hipError_t e) { return e == hipSuccess; }
 
 }  // namespace vrt
@@ -192,3 +227,5 @@ vor_status vrt_scan_i32_to_i32(const int32_t *counts, int64_t N, int32_t *offset
 vor_status vrt_radix_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tmp, int32_t *vals_tmp,
                                 int64_t n, int bits, int32_t *hist_scratch, int64_t hist_len, hipStream_t st);
 int64_t vrt_radix_hist_len(int64_t n);
+// dst[i] = src[idx[i]]
+vor_status vrt_gather_u32(const uint32_t *src, const int32_t *idx, int64_t n, uint32_t *dst, hipStream_t st);

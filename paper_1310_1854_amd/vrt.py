@@ -26,7 +26,7 @@ MODES = {"fp64": 0, "mixed": 1}
 
 # every symbol include/voronoi_rt.h declares
 EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_neighbors", "vor_locate",
-           "vor_trace", "vor_exclusive_scan", "vor_status_str", "vor_version",
+           "vor_trace", "vor_order_rays", "vor_order_workspace_bytes", "vor_exclusive_scan", "vor_status_str", "vor_version",
            "vor_server_create", "vor_server_submit", "vor_server_poll", "vor_server_wait", "vor_server_result",
            "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy"]
 
@@ -56,8 +56,12 @@ class TraceOut(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_void_p), ("n_seg", ctypes.c_void_p), ("status", ctypes.c_void_p),
                 ("n_fallback", ctypes.c_void_p), ("seg_cell", ctypes.c_void_p), ("seg_len", ctypes.c_void_p),
                 ("seg_stride", ctypes.c_int64), ("ray_off", ctypes.c_void_p), ("counters", ctypes.c_void_p),
-                ("work", ctypes.c_void_p), ("spill_off", ctypes.c_void_p), ("spill_rays", ctypes.c_void_p),
-                ("spill_cell", ctypes.c_void_p), ("spill_len", ctypes.c_void_p), ("spill_capacity", ctypes.c_int64)]
+                ("work", ctypes.c_void_p), ("spill_first", ctypes.c_void_p), ("spill_next", ctypes.c_void_p),
+                ("spill_cell", ctypes.c_void_p), ("spill_len", ctypes.c_void_p), ("spill_chunks", ctypes.c_int64),
+                ("ray_order", ctypes.c_void_p)]
+
+
+SPILL_CHUNK = 64
 
 
 class ServerStats(ctypes.Structure):
@@ -93,6 +97,10 @@ def load(path: str = None):
     lib.vor_locate.restype = ctypes.c_int
     lib.vor_trace.argtypes = [P, P, P, I64, P, D, ctypes.POINTER(TraceOpts), ctypes.POINTER(TraceOut), P]
     lib.vor_trace.restype = ctypes.c_int
+    lib.vor_order_rays.argtypes = [P, P, P, I64, P, P, I64, P]
+    lib.vor_order_rays.restype = ctypes.c_int
+    lib.vor_order_workspace_bytes.argtypes = [I64]
+    lib.vor_order_workspace_bytes.restype = ctypes.c_int64
     lib.vor_exclusive_scan.argtypes = [P, I64, P, P]
     lib.vor_exclusive_scan.restype = ctypes.c_int
     lib.vor_status_str.argtypes = [ctypes.c_int]
@@ -216,12 +224,13 @@ COUNTERS = ["segments", "fallbacks", "fp64_redecisions", "steps", "records", "r5
 class TraceBuffers:
     """Preallocated outputs of ``trace`` for N rays (reused across calls).
 
-    seg_stride > 0: fixed windows of seg_stride slots per ray; with
-    spill_capacity > 0 longer paths go whole to a spill area (spill_off).
-    total_segments > 0 (and seg_stride 0): exact CSR windows from ray_off."""
+    seg_stride > 0: a window of seg_stride slots per ray; with spill_chunks
+    > 0 longer paths continue in chained spill chunks of SPILL_CHUNK slots.
+    total_segments > 0 (and seg_stride 0): exact CSR windows from ray_off.
+    ordered: also hold a processing order (vor_order_rays) and its workspace."""
 
-    def __init__(self, N: int, seg_stride: int = 0, total_segments: int = 0, spill_capacity: int = 0,
-                 device="cuda", counters=True):
+    def __init__(self, N: int, seg_stride: int = 0, total_segments: int = 0, spill_chunks: int = 0,
+                 device="cuda", counters=True, ordered=False):
         self.N = N
         self.tau = torch.empty(N, dtype=torch.float64, device=device)
         self.n_seg = torch.empty(N, dtype=torch.int32, device=device)
@@ -235,16 +244,21 @@ class TraceBuffers:
         self.ray_off: Optional[torch.Tensor] = None
         self.counters = torch.zeros(8, dtype=torch.int64, device=device) if counters else None
         self.work = torch.zeros(4, dtype=torch.int64, device=device)
-        self.spill_capacity = int(spill_capacity) if self.seg_stride > 0 else 0
-        if self.spill_capacity > 0:
-            self.spill_off = torch.empty(N, dtype=torch.int64, device=device)
-            self.spill_rays = torch.empty(N, dtype=torch.int32, device=device)
-            self.spill_cell = torch.empty(self.spill_capacity, dtype=torch.int32, device=device)
-            self.spill_len = torch.empty(self.spill_capacity, dtype=torch.float64, device=device)
+        self.spill_chunks = int(spill_chunks) if self.seg_stride > 0 else 0
+        if self.spill_chunks > 0:
+            self.spill_first = torch.empty(N, dtype=torch.int64, device=device)
+            self.spill_next = torch.empty(self.spill_chunks, dtype=torch.int32, device=device)
+            self.spill_cell = torch.empty(self.spill_chunks * SPILL_CHUNK, dtype=torch.int32, device=device)
+            self.spill_len = torch.empty(self.spill_chunks * SPILL_CHUNK, dtype=torch.float64, device=device)
         else:
-            self.spill_off = self.spill_rays = self.spill_cell = self.spill_len = None
+            self.spill_first = self.spill_next = self.spill_cell = self.spill_len = None
+        self.order = None
+        self.order_ws = None
+        if ordered:
+            self.order = torch.empty(max(N, 1), dtype=torch.int32, device=device)
+            self.order_ws = torch.empty(int(load().vor_order_workspace_bytes(N)), dtype=torch.uint8, device=device)
 
-    def struct(self) -> TraceOut:
+    def struct(self, use_order: bool = False) -> TraceOut:
         o = TraceOut()
         o.tau = self.tau.data_ptr()
         o.n_seg = self.n_seg.data_ptr()
@@ -256,96 +270,117 @@ class TraceBuffers:
         o.ray_off = self.ray_off.data_ptr() if self.ray_off is not None else None
         o.counters = self.counters.data_ptr() if self.counters is not None else None
         o.work = self.work.data_ptr()
-        if self.spill_capacity > 0:
-            o.spill_off = self.spill_off.data_ptr()
-            o.spill_rays = self.spill_rays.data_ptr()
+        if self.spill_chunks > 0:
+            o.spill_first = self.spill_first.data_ptr()
+            o.spill_next = self.spill_next.data_ptr()
             o.spill_cell = self.spill_cell.data_ptr()
             o.spill_len = self.spill_len.data_ptr()
-            o.spill_capacity = self.spill_capacity
+            o.spill_chunks = self.spill_chunks
+        if use_order and self.order is not None:
+            o.ray_order = self.order.data_ptr()
         return o
+
+
+def order_rays(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, order: torch.Tensor,
+               workspace: torch.Tensor, stream=None) -> None:
+    """Enqueue vor_order_rays into ``order`` (int32, N)."""
+    n = origins.shape[0]
+    _check(load().vor_order_rays(grid.handle, _ptr(origins), _ptr(dirs), n, _ptr(order), _ptr(workspace),
+                                 workspace.numel(), _stream(stream)), "vor_order_rays")
 
 
 def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: Optional[torch.Tensor],
                bufs: TraceBuffers, kappa: float = 1.0, mode: str = "fp64", max_steps: int = 0,
-               eps_mix: float = 0.0, persistent: bool = False, stream=None) -> None:
-    """Enqueue one vor_trace into preallocated buffers (no allocation, no sync)."""
+               eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, stream=None) -> None:
+    """Enqueue one vor_trace into preallocated buffers (no allocation, no
+    sync); with ``ordered`` the rays are first put in coherent order by
+    vor_order_rays (buffers made with ordered=True)."""
     n = origins.shape[0]
     if origins.dtype != torch.float64 or dirs.dtype != torch.float64 or not origins.is_contiguous() \
             or not dirs.is_contiguous() or origins.shape != dirs.shape or n != bufs.N:
         raise ValueError("origins/dirs must be contiguous float64 (N, 3) tensors matching the buffers")
     if density is not None and (density.dtype != torch.float64 or density.numel() != grid.M):
         raise ValueError("density must be float64 with one value per site")
+    if ordered:
+        if bufs.order is None:
+            raise ValueError("buffers were made without ordered=True")
+        order_rays(grid, origins, dirs, bufs.order, bufs.order_ws, stream=stream)
     opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 0)
-    out = bufs.struct()
+    out = bufs.struct(use_order=ordered)
     _check(load().vor_trace(grid.handle, _ptr(origins), _ptr(dirs), n, _ptr(density), float(kappa),
                             ctypes.byref(opts), ctypes.byref(out), _stream(stream)), "vor_trace")
 
 
 def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str = "fp64",
-          segments: str = "exact", seg_stride: int = 64, spill_capacity: int = 0, max_steps: int = 0,
-          eps_mix: float = 0.0, persistent: bool = False, stream=None) -> dict:
-    """Paths of N rays. ``segments``: "none" (tau only), "stride" (fixed
-    ``seg_stride`` slots per ray; longer paths go to a spill area of
-    ``spill_capacity`` slots, or report RAY_OVERFLOW), or "exact" (a
-    tau-only counting pass, a scan, then a pass that writes every segment at
-    its CSR offset). Returns a dict of device tensors; "ray_off" gives each
-    ray's first slot in seg_cell/seg_len (spilled rays: see "spill_off")."""
+          segments: str = "exact", seg_stride: int = 64, spill_chunks: int = 0, max_steps: int = 0,
+          eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, stream=None) -> dict:
+    """Paths of N rays. ``segments``: "none" (tau only), "stride" (a window
+    of ``seg_stride`` slots per ray; longer paths continue in up to
+    ``spill_chunks`` chained spill chunks, or report RAY_OVERFLOW), or
+    "exact" (a tau-only counting pass, a scan, then a pass that writes every
+    segment at its CSR offset). Returns a dict of device tensors."""
     o = _dev_f64(origins, 3)
     d = _dev_f64(dirs, 3)
     rho = None if density is None else _dev_f64(density).reshape(-1)
     n = o.shape[0]
-    kw = dict(kappa=kappa, mode=mode, max_steps=max_steps, eps_mix=eps_mix, persistent=persistent, stream=stream)
+    kw = dict(kappa=kappa, mode=mode, max_steps=max_steps, eps_mix=eps_mix, persistent=persistent, ordered=ordered,
+              stream=stream)
     if segments == "none":
-        b = TraceBuffers(n)
+        b = TraceBuffers(n, ordered=ordered)
         trace_into(grid, o, d, rho, b, **kw)
     elif segments == "stride":
-        b = TraceBuffers(n, seg_stride=seg_stride, spill_capacity=spill_capacity)
+        b = TraceBuffers(n, seg_stride=seg_stride, spill_chunks=spill_chunks, ordered=ordered)
         trace_into(grid, o, d, rho, b, **kw)
     elif segments == "exact":
-        b0 = TraceBuffers(n)
+        b0 = TraceBuffers(n, ordered=ordered)
         trace_into(grid, o, d, rho, b0, **kw)
         off = exclusive_scan(b0.n_seg, stream=stream)
         total = int(off[-1].item())
-        b = TraceBuffers(n, total_segments=max(total, 1))
+        b = TraceBuffers(n, total_segments=max(total, 1), ordered=ordered)
         b.ray_off = off
         trace_into(grid, o, d, rho, b, **kw)
     else:
         raise ValueError("segments must be none, stride or exact")
-    res = dict(tau=b.tau, n_seg=b.n_seg, status=b.status, n_fallback=b.n_fallback, counters=b.counters)
+    res = dict(tau=b.tau, n_seg=b.n_seg, status=b.status, n_fallback=b.n_fallback, counters=b.counters, work=b.work)
     if b.seg_cell is not None:
         res.update(seg_cell=b.seg_cell, seg_len=b.seg_len)
         res["ray_off"] = b.ray_off if b.ray_off is not None else \
             torch.arange(0, (n + 1) * b.seg_stride, b.seg_stride, dtype=torch.int64, device="cuda")
         res["seg_stride"] = b.seg_stride
-        if b.spill_capacity > 0:
-            res.update(spill_off=b.spill_off, spill_cell=b.spill_cell, spill_len=b.spill_len, work=b.work)
+        if b.spill_chunks > 0:
+            res.update(spill_first=b.spill_first, spill_next=b.spill_next, spill_cell=b.spill_cell,
+                       spill_len=b.spill_len)
     return res
 
 
-def gather_paths(res: dict):
-    """Host view of a trace result: (n_seg, per-ray (cells, lengths) getter).
-    Handles stride windows with spill."""
-    n_seg = res["n_seg"].cpu().numpy()
-    cells = res["seg_cell"].cpu().numpy()
-    lens = res["seg_len"].cpu().numpy()
-    off = res["ray_off"].cpu().numpy()
+def ray_path(res: dict, r: int, host: Optional[dict] = None):
+    """(cells, lengths) of ray r of a trace result, from its window and its
+    spill chain. ``host`` caches numpy copies of the spill arrays."""
+    n = int(res["n_seg"][r])
     stride = res.get("seg_stride", 0)
-    spill_off = res["spill_off"].cpu().numpy() if "spill_off" in res else None
-    spill_cell = res["spill_cell"].cpu().numpy() if spill_off is not None else None
-    spill_len = res["spill_len"].cpu().numpy() if spill_off is not None else None
-
-    def get(r):
-        n = int(n_seg[r])
-        o = int(off[r])
-        if stride > 0 and n > stride:
-            if spill_off is None or spill_off[r] < 0:
-                raise ValueError(f"ray {r}: path not stored (overflow)")
-            s = int(spill_off[r])
-            return (np.concatenate([cells[o:o + stride], spill_cell[s:s + n - stride]]),
-                    np.concatenate([lens[o:o + stride], spill_len[s:s + n - stride]]))
-        return cells[o:o + n], lens[o:o + n]
-
-    return n_seg, get
+    o = int(res["ray_off"][r])
+    if stride <= 0 or n <= stride:
+        return res["seg_cell"][o:o + n].cpu().numpy(), res["seg_len"][o:o + n].cpu().numpy()
+    if "spill_first" not in res:
+        raise ValueError(f"ray {r}: path past its window was not stored")
+    if host is None:
+        host = {}
+    if "next" not in host:
+        host["first"] = res["spill_first"].cpu().numpy()
+        host["next"] = res["spill_next"].cpu().numpy()
+    cells = [res["seg_cell"][o:o + stride].cpu().numpy()]
+    lens = [res["seg_len"][o:o + stride].cpu().numpy()]
+    c = int(host["first"][r])
+    left = n - stride
+    while left > 0:
+        if c < 0:
+            raise ValueError(f"ray {r}: spill chain ends early")
+        k = min(left, SPILL_CHUNK)
+        cells.append(res["spill_cell"][c * SPILL_CHUNK:c * SPILL_CHUNK + k].cpu().numpy())
+        lens.append(res["spill_len"][c * SPILL_CHUNK:c * SPILL_CHUNK + k].cpu().numpy())
+        left -= k
+        c = int(host["next"][c])
+    return np.concatenate(cells), np.concatenate(lens)
 
 
 class Server:

@@ -42,7 +42,11 @@ def test_full_size_in_bench_configuration(vrt, name):
     n_seg = bufs.n_seg
     stride = spec["stride"]
 
-    # every ray: the segments add up to the chord (lengths from the window, or the spill)
+    # every ray: the segments add up to the chord (window, then spill chain).
+    # The spill is re-run with zeroed chunks so that unwritten slots add 0.
+    bufs.spill_len.zero_()
+    bench.step(vrt, grid, o, d, rho, bufs, spec, spec["mode"])
+    torch.cuda.synchronize()
     k = d / torch.linalg.norm(d, dim=1, keepdim=True)
     lo = torch.as_tensor(w.box[:3], device="cuda")
     hi = torch.as_tensor(w.box[3:], device="cuda")
@@ -52,25 +56,25 @@ def test_full_size_in_bench_configuration(vrt, name):
     L = torch.minimum(t_hi.min(dim=1).values, t_lo.min(dim=1).values)
     slots = torch.arange(stride, device="cuda")[None, :]
     win = bufs.seg_len.view(w.N, stride)
-    in_win = n_seg <= stride
     tot = torch.empty(w.N, dtype=torch.float64, device="cuda")
     for a in range(0, w.N, 1 << 20):
         b = min(w.N, a + (1 << 20))
         part = win[a:b]
         tot[a:b] = torch.where(slots < n_seg[a:b, None], part, torch.zeros_like(part)).sum(dim=1)
-    spilled = torch.nonzero(~in_win).flatten()
-    assert int(bufs.work[2].item()) == spilled.numel()
-    for a in range(0, spilled.numel(), 1 << 16):
-        sp = spilled[a:a + (1 << 16)]
-        so = bufs.spill_off[sp]
-        ns = n_seg[sp].long() - stride
-        cols = torch.arange(int(ns.max()), device="cuda")[None, :]
-        mask = cols < ns[:, None]
-        idx = torch.where(mask, so[:, None] + cols, torch.zeros_like(cols))
-        vals = bufs.spill_len[idx]
-        tot[sp] += torch.where(mask, vals, torch.zeros_like(vals)).sum(dim=1)
-    rel = (tot - L).abs() / L.clamp_min(1e-300)
     del win
+    past = torch.nonzero(n_seg > stride).flatten()
+    assert int(bufs.work[2].item()) == past.numel()
+    chunk_sum = bufs.spill_len.view(-1, 64).sum(dim=1)
+    cur = bufs.spill_first[past]
+    assert bool((cur >= 0).all())
+    extra = torch.zeros(past.numel(), dtype=torch.float64, device="cuda")
+    nxt = bufs.spill_next.long()
+    while bool((cur >= 0).any()):
+        ok = cur >= 0
+        extra[ok] += chunk_sum[cur[ok]]
+        cur = torch.where(ok, nxt[cur.clamp(min=0)], cur)
+    tot[past] += extra
+    rel = (tot - L).abs() / L.clamp_min(1e-300)
     assert float(rel.max()) <= 1e-12, float(rel.max())
 
     # mixed mode returns exactly the FP64 results on every ray
@@ -85,20 +89,16 @@ def test_full_size_in_bench_configuration(vrt, name):
     ridx = sub.meta["ray_index"]
     ref = oracle.trace(w.sites, w.box, w.density, sub.origins, sub.dirs, cap=8192)
     n_all = n_seg.cpu().numpy()
-    spill_off = bufs.spill_off.cpu().numpy()
+    res = dict(n_seg=bufs.n_seg, seg_cell=bufs.seg_cell, seg_len=bufs.seg_len, seg_stride=stride,
+               ray_off=torch.arange(0, (w.N + 1) * stride, stride, device="cuda"), spill_first=bufs.spill_first,
+               spill_next=bufs.spill_next, spill_cell=bufs.spill_cell, spill_len=bufs.spill_len)
+    host = {}
     cells, lens, off = [], [], [0]
     for r in ridx:
-        n = int(n_all[r])
-        a = int(r) * stride
-        c = bufs.seg_cell[a:a + min(n, stride)].cpu().numpy()
-        l = bufs.seg_len[a:a + min(n, stride)].cpu().numpy()
-        if n > stride:
-            b = int(spill_off[r])
-            c = np.concatenate([c, bufs.spill_cell[b:b + n - stride].cpu().numpy()])
-            l = np.concatenate([l, bufs.spill_len[b:b + n - stride].cpu().numpy()])
+        c, l = vrt.ray_path(res, int(r), host)
         cells.append(c)
         lens.append(l)
-        off.append(off[-1] + n)
+        off.append(off[-1] + len(c))
     p = dict(tau=bufs.tau.cpu().numpy()[ridx], n_seg=n_all[ridx], status=status[ridx],
              seg_cell=np.concatenate(cells), seg_len=np.concatenate(lens), ray_off=np.array(off))
     st = compare(p, ref, TOL[spec["mode"]])

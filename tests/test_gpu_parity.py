@@ -98,30 +98,56 @@ def cube(vrt):
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 @pytest.mark.parametrize("segments", ["exact", "stride"])
 @pytest.mark.parametrize("persistent", [False, True])
-def test_uniform_cube_all_rays(vrt, cube, mode, segments, persistent):
+@pytest.mark.parametrize("ordered", [False, True])
+def test_uniform_cube_all_rays(vrt, cube, mode, segments, persistent, ordered):
     w, grid, ref = cube
-    out = vrt.trace(grid, w.origins, w.dirs, w.density, mode=mode, segments=segments, seg_stride=16,
-                    spill_capacity=200_000, persistent=persistent)
+    out = vrt.trace(grid, w.origins, w.dirs, w.density, mode=mode, segments=segments, seg_stride=8,
+                    spill_chunks=20000, persistent=persistent, ordered=ordered)
     p = gpu_paths(out)
     if segments == "stride":
-        # rays longer than the window were rewritten whole into the spill
-        n_seg, get = vrt.gather_paths(out)
-        cells = []
-        lens = []
-        off = [0]
+        # paths longer than the window continue in their spill chain
+        host = {}
+        cells, lens, off = [], [], [0]
         for r in range(w.N):
-            c, l = get(r)
+            c, l = vrt.ray_path(out, r, host)
             cells.append(c)
             lens.append(l)
             off.append(off[-1] + len(c))
         p.update(seg_cell=np.concatenate(cells), seg_len=np.concatenate(lens), ray_off=np.array(off))
-        assert int(out["work"][2].item()) == int((n_seg > 16).sum()) > 0
+        assert int(out["work"][2].item()) == int((p["n_seg"] > 8).sum()) > 0
     st = compare(p, ref, TOL[mode])
     assert st["clean"] > 0.99 * w.N
     if mode == "fp64":
         assert st["max_len_diff"] == 0.0 and st["max_tau_diff"] == 0.0
     c = out["counters"].cpu().numpy()
     assert c[0] == p["n_seg"].sum()
+
+
+def test_ray_order_is_a_permutation_and_changes_nothing(vrt):
+    import torch
+    w = W.flared_disc(M=50_000, N=300_001, seed=21)
+    grid = vrt.build_grid(w.sites, w.box)
+    o = torch.as_tensor(w.origins, device="cuda")
+    d = torch.as_tensor(w.dirs, device="cuda")
+    order = torch.empty(w.N, dtype=torch.int32, device="cuda")
+    ws = torch.empty(int(vrt.load().vor_order_workspace_bytes(w.N)), dtype=torch.uint8, device="cuda")
+    vrt.order_rays(grid, o, d, order, ws)
+    ordr = order.cpu().numpy()
+    assert np.array_equal(np.sort(ordr), np.arange(w.N))
+    a = vrt.trace(grid, o, d, w.density, mode="mixed", segments="stride", seg_stride=32, spill_chunks=200_000)
+    b = vrt.trace(grid, o, d, w.density, mode="mixed", segments="stride", seg_stride=32, spill_chunks=200_000,
+                  ordered=True)
+    for k in ("tau", "n_seg", "status"):
+        assert torch.equal(a[k], b[k]), k
+    n = w.N
+    mask = torch.arange(32, device="cuda")[None, :] < a["n_seg"].clamp(max=32)[:, None]
+    assert torch.equal(a["seg_cell"].view(n, 32)[mask], b["seg_cell"].view(n, 32)[mask])
+    assert torch.equal(a["seg_len"].view(n, 32)[mask], b["seg_len"].view(n, 32)[mask])
+    ha, hb = {}, {}
+    for r in np.nonzero(a["n_seg"].cpu().numpy() > 32)[0][:200]:
+        ca, la = vrt.ray_path(a, int(r), ha)
+        cb, lb = vrt.ray_path(b, int(r), hb)
+        assert np.array_equal(ca, cb) and np.array_equal(la, lb)
 
 
 def test_mixed_equals_fp64_bitwise(vrt):
@@ -256,6 +282,10 @@ def test_edge_cases(vrt):
     g2 = vrt.build_grid(w.sites, w.box)
     full = gpu_paths(vrt.trace(g2, w.origins, w.dirs, w.density))
     small = gpu_paths(vrt.trace(g2, w.origins, w.dirs, w.density, segments="stride", seg_stride=3))
+    # and with a spill too small for the longest paths
+    tiny = gpu_paths(vrt.trace(g2, w.origins, w.dirs, w.density, segments="stride", seg_stride=3, spill_chunks=1))
+    assert np.array_equal(tiny["n_seg"], full["n_seg"]) and np.array_equal(tiny["tau"], full["tau"])
+    assert (tiny["status"] == vrt.RAY_OVERFLOW).sum() >= 1
     assert np.array_equal(small["n_seg"], full["n_seg"]) and np.array_equal(small["tau"], full["tau"])
     over = full["n_seg"] > 3
     assert over.any() and np.all(small["status"][over] == vrt.RAY_OVERFLOW)
