@@ -6,18 +6,23 @@ rho ~ (R/R0)^-1 exp(-(pi/4)(z/h)^2), h = 0.125 R0 (R/R0)^1.125, R in
 the central point source and half from random sites, in mixed-precision
 mode (FP32 plane tests, FP64 re-decision of close calls, FP64 winner).
 
-A step is one vor_trace over the whole batch with inputs resident in HBM:
-start-cell location, the traversal, the per-ray outputs and every segment
-(cell, length) written to its stride window, plus the spill pass that
-rewrites paths longer than their window. The grid is built once, outside
-the timed region (setup, as in the method). value = segments emitted per
-step / seconds per step.
+A step is one pass of the whole path over the batch with inputs resident in
+HBM: the coherent ray order (vor_order_rays), then vor_trace: start-cell
+location, the traversal, the per-ray outputs and every segment (cell,
+length) written to its stride window or, past it, to the ray's chain of
+spill chunks. The grid is built once, outside the timed region (set-up, as
+in the method). value = segments emitted per step / seconds per step.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload flared_disc|exp_disc|clumpy|uniform_cube]
+roofline.traffic is the trace kernel's HBM traffic per launch from the
+committed hardware-counter summary (profiles/), reported only while the
+kernel sources still hash to the value recorded there (else null).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload flared_disc|exp_disc|clumpy|uniform_cube|serving]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -32,6 +37,44 @@ if ROOT not in sys.path:
 
 METRIC = "Voronoi cell crossings/sec per GPU at stated accuracy; p50/p99 batch latency"
 HBM_PEAK_GBS = 8000.0
+
+# The sources the trace kernel is compiled from: a traffic figure measured
+# on another version of them is not reported.
+KERNEL_SOURCES = ("paper_1310_1854_amd/csrc/trace.hip", "paper_1310_1854_amd/csrc/trace_core.h",
+                  "paper_1310_1854_amd/csrc/vrt_internal.h", "include/voronoi_rt.h",
+                  "paper_1310_1854_amd/build_lib.py")
+TRAFFIC_SUMMARY = "profiles/k_trace_flared_disc_1e6_mixed_traffic.md"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """(bytes per launch, summary path) of the trace kernel's HBM traffic from
+    the counter summary, or (None, reason) when there is none for this
+    workload or the kernel sources have changed since it was taken."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("workload") != workload:
+        return None, "counter summary is for another workload"
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    try:
+        return float(fields["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY
+    except (KeyError, ValueError):
+        return None, "counter summary lacks traffic_bytes_per_launch"
 
 # Launch configuration per workload: mode, segment window per ray, spill
 # chunks (of 64 segments) per ray, coherent ray order, persistent kernel.
@@ -162,18 +205,19 @@ def serving(args, torch, vrt, workloads):
         done = threading.Event()
         lock = threading.Lock()
 
+        index = {}
+
         def reaper():
-            pending = set()
             nfin = 0
             while nfin < len(reqs):
-                with lock:
-                    cur = [i for i in range(len(reqs)) if ids[i] is not None and lat[i] is None]
-                for i in cur:
-                    if srv.poll(ids[i]):
-                        lat[i] = srv.latency(ids[i])
-                        srv.release(ids[i])
-                        nfin += 1
-                time.sleep(0.0002)
+                rid = srv.next_done(1.0)
+                if rid is None:
+                    continue
+                with lock:   # the submitter records the id under the same lock
+                    i = index[rid]
+                lat[i] = srv.latency(rid)
+                srv.release(rid)
+                nfin += 1
             done.set()
 
         th = threading.Thread(target=reaper, daemon=True)
@@ -183,12 +227,17 @@ def serving(args, torch, vrt, workloads):
             wait = t0 + offsets[i] - time.perf_counter()
             if wait > 0:
                 time.sleep(wait)
-            rid = srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=stride)
             with lock:
+                rid = srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=stride)
                 ids[i] = rid
-        done.wait(600)
+                index[rid] = i
+        if not done.wait(600):
+            raise RuntimeError("serving run did not finish within 600 s")
         t1 = time.perf_counter()
         st = srv.stats()
+        while st["running"]:   # crossings are counted when a launch ends
+            time.sleep(0.001)
+            st = srv.stats()
         srv.close()
         lat = np.array(lat, dtype=np.float64)
         return dict(seconds=t1 - t0, crossings=st["crossings"], rate=st["crossings"] / (t1 - t0),
@@ -226,12 +275,15 @@ def main(argv=None):
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, three elementwise copies of 512 MiB (float64 negation) whose "
+                         "hardware counters calibrate the trace kernel's")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the path is measured on one MI355X "
-                                   "(rays shard across GPUs with the grid replicated; see DESIGN.md)",
+        print(json.dumps({"error": "bench.py runs on one GPU only: the path is measured on one MI355X "
+                                   "(rays would shard across GPUs with the grid replicated on each)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -300,6 +352,8 @@ def main(argv=None):
     same_tau = bool(torch.equal(fb.tau, tau_mixed))
     same_nseg = bool(torch.equal(fb.n_seg, nseg_mixed))
 
+    traffic, traffic_src = measured_traffic(args.workload)
+
     result = {
         "metric": METRIC,
         "value": value,
@@ -313,7 +367,7 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32+f64" if mode == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.M} sites, {w.N} rays, {mode} mode (configs[{spec['cfg']}])",
+        "config": {"workload": f"{w.name}: {w.M} sites, {w.N} rays, {mode} mode",
                    "sites": w.M, "rays": w.N, "mode": mode, "seg_stride": spec["stride"],
                    "ordered": bool(spec.get("ordered", False)),
                    "persistent": bool(spec.get("persistent", False))},
@@ -329,9 +383,10 @@ def main(argv=None):
         "grid": {"build_ms": info["build_ms"], "nnz": info["nnz"], "max_row": info["max_row"],
                  "device_bytes": info["device_bytes"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_trace_persistent" if spec.get("persistent") else "k_trace",
-                     "kernel_avg_ms": k_avg, "algorithmic_bytes": alg},
+                     "kernel_avg_ms": k_avg, "algorithmic_bytes": alg, "traffic_source": traffic_src,
+                     "kernel_source_sha256_16": kernel_source_hash()},
     }
     if not args.no_cpu:
         import oracle
@@ -357,6 +412,19 @@ def main(argv=None):
                               "cell_sequence_mismatches": mism, "max_len_err_rel_chord": max_dl,
                               "max_tau_err_rel": max_dt}
     print(json.dumps(result), flush=True)
+    if args.copy_calibration:
+        copy_calibration(torch)
+
+
+def copy_calibration(torch, mib: int = 512, reps: int = 3):
+    """A plain streaming kernel of known size: read mib MiB, write mib MiB."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: {reps} x negation of {mib} MiB float64", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -226,23 +226,26 @@ vor_status vor_exclusive_scan(const int32_t *counts, int64_t N, int64_t *offsets
  * A server keeps several built grids resident and accepts requests (a batch
  * of rays for one grid, in FP64 or mixed mode) from any host thread. A
  * request waits in a first-in-first-out queue until its output buffers fit
- * in the server's memory budget; admitted requests are traced together by
- * persistent kernels on two streams whose waves take chunks of rays from a
- * device work queue and refill finished lanes, so work that arrives while
- * other work is on the GPU starts as soon as a stream and memory free up.
- * Every ray is computed by the same code as vor_trace, so its result does
- * not depend on the other requests. Paths follow Sect. 2.2 as in vor_trace;
- * segments go to a fixed window of seg_stride slots per ray (longer paths
- * report VOR_RAY_OVERFLOW with their full count and tau).
+ * in the server's memory budget. Admitted requests are traced together by
+ * persistent kernels on several streams: their rays are cut into chunks
+ * that the waves take from a device work queue, refilling finished lanes,
+ * and a later launch starts on the GPU as the blocks of an earlier one
+ * retire. A request is complete as soon as its own rays are (the kernel
+ * raises a flag in host memory), not when its launch ends. Every ray is
+ * computed by the same code as vor_trace, so its result does not depend on
+ * the other requests. Paths follow Sect. 2.2 as in vor_trace; segments go to
+ * a fixed window of seg_stride slots per ray (longer paths report
+ * VOR_RAY_OVERFLOW with their full count and tau).
  * ------------------------------------------------------------------------- */
 typedef struct vor_server vor_server;
 
 typedef struct {
     int64_t completed;         /* requests finished */
-    int64_t crossings;         /* segments emitted by finished launches */
+    int64_t crossings;         /* segments emitted by finished launches (counted when a launch ends) */
     int64_t fp64_redecisions;  /* mixed-mode steps redone in FP64 */
     int64_t fallbacks;         /* no-exit fallbacks */
     int64_t launches;          /* kernel launches finished */
+    int64_t running;           /* kernel launches in flight */
     int64_t waiting;           /* requests not yet admitted */
     int64_t budget_bytes;      /* output memory budget */
     int64_t used_bytes;        /* held by admitted, unreleased requests */
@@ -264,11 +267,18 @@ vor_status vor_server_submit(vor_server *srv, int32_t grid, const double *origin
                              const double *density, double kappa, int32_t mode, int64_t seg_stride,
                              int64_t *req_id);
 
-/* *done = 1 once the request's outputs are complete. */
+/* *done = 1 once the request's outputs are complete; they are then visible
+ * to work on any stream and to copies to the host, even while the launch
+ * that computed them is still running. */
 vor_status vor_server_poll(vor_server *srv, int64_t req_id, int32_t *done);
 
 /* Block until the request is done or timeout_s passes (VOR_ETIMEOUT). */
 vor_status vor_server_wait(vor_server *srv, int64_t req_id, double timeout_s);
+
+/* Completion queue: *req_id receives the next request that has completed
+ * (in completion order; each once, released ones skipped), waiting up to
+ * timeout_s (VOR_ETIMEOUT, *req_id = 0, if none completes). */
+vor_status vor_server_next_done(vor_server *srv, double timeout_s, int64_t *req_id);
 
 /* Device pointers of a finished request's outputs (tau, n_seg, status,
  * seg_cell, seg_len with seg_stride; server-owned until release) and its

@@ -4,19 +4,24 @@
 // work queue.
 //
 // Host side: one scheduler thread per server. Requests wait in a FIFO until
-// their output buffers fit in the budget arena (first fit). Admitted
-// requests are cut into chunks of rays; whenever one of the server's
-// streams is free, every admitted request not yet launched goes into one
-// launch: its request table and chunk list are copied to the device and a
-// persistent kernel drains them. Launches on the two streams overlap, so
-// requests that arrive while a launch is running start before it ends.
-// Completion is seen through an event per launch.
+// their output buffers fit in the budget arena (first fit). Whenever one of
+// the server's streams is free, every admitted request not yet launched goes
+// into one launch: its rays are cut into chunks (sized so that the launch has
+// a few chunks per wave), the request table and chunk list are copied to the
+// device and a persistent kernel drains them. Launches on different streams
+// overlap: the blocks of a later launch start as those of an earlier one
+// retire. A request is complete as soon as its last chunk is: the kernel
+// publishes that to a flag in host memory, which the scheduler polls, so a
+// small request does not wait for the large ones launched with it, and its
+// memory returns to the budget at once.
 //
-// Device side: each wave takes a chunk (one atomic), sets up the chunk's
-// grid and precision class (uniform across the wave), and keeps its lanes
-// busy: a lane whose ray has ended takes the chunk's next ray. The per-ray
-// work is the same code as vor_trace, so a ray's result does not depend on
-// what else is in the launch.
+// Device side: each wave works in one context (grid and precision class,
+// uniform across the wave) and keeps its lanes busy with rays of the chunks
+// it takes from the queue; lanes of one wave may hold rays of different
+// requests of the same context. A wave that takes a chunk of another context
+// lets its running rays finish before starting it. The per-ray work is the
+// same code as vor_trace, so a ray's result does not depend on what else is
+// in the launch.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -35,10 +40,14 @@ const vrt::Grid &vrt_grid_of(const vor_grid *G);
 
 namespace {
 
-constexpr int kChunk = 1024;          // rays per chunk
-constexpr int kMaxLaunchReqs = 1024;  // requests per launch
+constexpr int kMaxLaunchReqs = 1024;   // requests per launch
 constexpr int kMaxLaunchChunks = 16384;
-constexpr int kStreams = 2;
+constexpr int kChunkMin = 64;          // rays per chunk, at least ...
+constexpr int kChunkMax = 4096;        // ... and at most
+constexpr int kChunksPerWave = 4;      // target chunks per wave of a launch
+constexpr int kStreams = 3;
+constexpr int kSlots = 4;              // chunks a wave may have open at once
+constexpr int kServeRefillMin = 48;    // idle lanes that trigger a refill
 
 struct ReqDev {
     RayIn in;
@@ -48,21 +57,36 @@ struct ReqDev {
     int32_t *seg_cell;
     double *seg_len;
     int64_t seg_stride;
-    int32_t grid;
-    int32_t mode;
+    int32_t *remaining;   // chunks of the request not yet complete (device memory)
+    int32_t *done;        // completion flag (host memory, device address)
 };
 
 struct ChunkDev {
     int32_t req;    // index into the launch's request table
     int32_t first;  // first ray of the request in this chunk
-    int32_t count;
-    int32_t pad;
+    int32_t count;  // rays in the chunk (>= 1)
+    int32_t ctx;    // 2 * grid + (mode == mixed)
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Every ray of chunk slot's request chunk has been written by this wave:
+// make the writes visible device-wide, count the chunk off its request, and
+// the wave that completes the request's last chunk raises its flag in host
+// memory (release at system scope, so the flag is seen after the data).
+__device__ __forceinline__ void chunk_complete(const ReqDev *__restrict__ reqs, int q)
+{
+    __threadfence();
+    if ((threadIdx.x & 63) == 0) {
+        const int prev = __hip_atomic_fetch_add(reqs[q].remaining, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == 1) __hip_atomic_store(reqs[q].done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids, const ReqDev *__restrict__ reqs,
@@ -72,31 +96,90 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
 {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    unsigned long long crossings = 0, redo = 0, fb = 0;
+    // Wave-uniform state.
+    int ctx = -1;                     // context of the rays in flight
+    GridRef G{};
+    int cur_req = -1, cur_first = 0, cur_left = 0, cur_slot = 0;   // chunk being handed out
+    int p_req = -1, p_first = 0, p_count = 0, p_ctx = -1;         // chunk taken, not yet started
+    bool have_p = false, drained = false;
+    int slot_req[kSlots], slot_left[kSlots];   // open chunks: request, rays not yet finished
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        slot_req[s] = -1;
+        slot_left[s] = 0;
+    }
+    // Per-lane state.
+    bool live = false;
+    int slot = -1, q = -1;
+    int64_t ray = 0;
+    const double *dens = nullptr;
+    double kappa = 0.0;
+    int32_t *cellp = nullptr;
+    double *lenp = nullptr;
+    int vec4 = 0;
+    RayState R;
+    RayStats S, T;
     for (;;) {
-        unsigned int c = 0;
-        if (lane == 0) c = atomicAdd(head, 1u);
-        c = __shfl(c, 0, 64);
-        if ((int)c >= n_chunks) break;
-        const ChunkDev ch = chunks[c];
-        const ReqDev rq = reqs[ch.req];
-        const GridRef G = grids[rq.grid];
-        SegOut O{};
-        O.cell = rq.seg_cell;
-        O.len = rq.seg_len;
-        O.vec4 = (rq.seg_cell && rq.seg_stride % 4 == 0) ? 1 : 0;
-        int next = 0;   // rays of the chunk handed out so far (wave-uniform)
-        bool live = false;
-        RayState R;
-        RayStats S;
-        int64_t ray = 0;
-        for (;;) {
-            bool need = !live;
-            uint64_t want = __ballot(need);
-            if (want && next < ch.count) {
-                int rank = __popcll(want & lt);
-                if (need && next + rank < ch.count) {
-                    ray = ch.first + next + rank;
+        const bool need = !live;
+        const uint64_t want = __ballot(need);
+        uint64_t busy = ~want & __ballot(true);
+        if (want && (__popcll(want) >= kServeRefillMin || busy == 0ull)) {
+            uint64_t pend = want;
+            // Each pass starts a chunk or hands out rays; eight passes serve
+            // every idle lane but in the rarest cases (the rest wait).
+            for (int pass = 0; pass < 8 && pend; ++pass) {
+                if (cur_left == 0) {
+                    if (!have_p) {
+                        if (drained) break;
+                        unsigned int c = 0;
+                        if (lane == 0) c = atomicAdd(head, 1u);
+                        const int cu = uniform((int)c);
+                        if (cu >= n_chunks) {
+                            drained = true;
+                            break;
+                        }
+                        const ChunkDev ch = chunks[cu];
+                        p_req = uniform(ch.req);
+                        p_first = uniform(ch.first);
+                        p_count = uniform(ch.count);
+                        p_ctx = uniform(ch.ctx);
+                        have_p = true;
+                    }
+                    if (p_ctx != ctx && busy != 0ull) break;   // let the other context's rays finish first
+                    int fs = -1;
+#pragma unroll
+                    for (int s = kSlots - 1; s >= 0; --s)
+                        if (slot_left[s] == 0) fs = s;
+                    if (fs < 0) break;                          // every slot open: wait for one to close
+#pragma unroll
+                    for (int s = 0; s < kSlots; ++s)
+                        if (s == fs) {
+                            slot_req[s] = p_req;
+                            slot_left[s] = p_count;
+                        }
+                    cur_req = p_req;
+                    cur_first = p_first;
+                    cur_left = p_count;
+                    cur_slot = fs;
+                    if (p_ctx != ctx) {
+                        ctx = p_ctx;
+                        G = grids[ctx >> 1];
+                    }
+                    have_p = false;
+                }
+                const int take = min(__popcll(pend), cur_left);
+                const int rank = __popcll(pend & lt);
+                const bool mine = ((pend >> lane) & 1ull) && rank < take;
+                if (mine) {
+                    const ReqDev &rq = reqs[cur_req];
+                    q = cur_req;
+                    slot = cur_slot;
+                    ray = cur_first + rank;
+                    dens = rq.in.density;
+                    kappa = rq.in.kappa;
+                    cellp = rq.seg_cell;
+                    lenp = rq.seg_len;
+                    vec4 = (rq.seg_cell && rq.seg_stride % 4 == 0) ? 1 : 0;
                     S = RayStats();
                     R.st = ray_setup(G, rq.in, ray, R.r0, R.k, R.L);
                     R.tau = 0.0;
@@ -108,28 +191,54 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     else R.L = 0.0;
                     live = true;
                 }
-                next += __popcll(want);
+                const uint64_t taken = __ballot(mine);
+                pend &= ~taken;
+                busy |= taken;
+                cur_first += take;
+                cur_left -= take;
             }
-            if (__ballot(live) == 0ull) break;
-            if (live) {
-                bool more = (rq.mode == VOR_MODE_MIXED)
-                                ? ray_step<VOR_MODE_MIXED, true>(G, rq.in, R, S, O)
-                                : ray_step<VOR_MODE_FP64, true>(G, rq.in, R, S, O);
-                if (!more) {
-                    finish_segments(O, R, S.cnt);
-                    if (rq.seg_cell && R.st == RAY_OK && S.cnt > R.cap) R.st = RAY_OVERFLOW;
-                    rq.tau[ray] = R.tau;
-                    rq.n_seg[ray] = S.cnt;
-                    rq.status[ray] = R.st;
-                    crossings += S.cnt;
-                    redo += S.nredo;
-                    fb += S.nfb;
-                    live = false;
+        }
+        if (__ballot(live) == 0ull) {
+            if (drained && !have_p && cur_left == 0) break;   // queue drained, every ray ended
+            continue;
+        }
+        bool fin = false;
+        if (live) {
+            const RayIn I{nullptr, nullptr, dens, kappa};
+            SegOut O{};
+            O.cell = cellp;
+            O.len = lenp;
+            O.vec4 = vec4;
+            const bool more = (ctx & 1) ? ray_step<VOR_MODE_MIXED, true>(G, I, R, S, O)
+                                        : ray_step<VOR_MODE_FP64, true>(G, I, R, S, O);
+            if (!more) {
+                finish_segments(O, R, S.cnt);
+                if (R.cap > 0 && R.st == RAY_OK && S.cnt > R.cap) R.st = RAY_OVERFLOW;
+                const ReqDev &rq = reqs[q];
+                rq.tau[ray] = R.tau;
+                rq.n_seg[ray] = S.cnt;
+                rq.status[ray] = R.st;
+                T.cnt += S.cnt;
+                T.nfb += S.nfb;
+                T.nredo += S.nredo;
+                live = false;
+                fin = true;
+            }
+        }
+        if (__ballot(fin)) {
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                const int n = __popcll(__ballot(fin && slot == s));
+                if (n) {
+                    slot_left[s] -= n;
+                    if (slot_left[s] == 0) chunk_complete(reqs, slot_req[s]);
                 }
             }
         }
     }
-    unsigned long long a = wave_sum_u64(crossings), b = wave_sum_u64(fb), d = wave_sum_u64(redo);
+    const unsigned long long a = wave_sum_u64((unsigned long long)T.cnt);
+    const unsigned long long b = wave_sum_u64((unsigned long long)T.nfb);
+    const unsigned long long d = wave_sum_u64((unsigned long long)T.nredo);
     if (lane == 0) {
         atomicAdd(&counters[0], a);
         if (b) atomicAdd(&counters[1], b);
@@ -170,10 +279,14 @@ struct Launch {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
-    std::vector<int64_t> reqs;
+    std::vector<int64_t> reqs;      // request ids, in table order
+    std::vector<uint8_t> seen;      // completion already taken from the flag
+    int open = 0;                   // requests of the launch not yet seen complete
     // staging (pinned) and device copies of the launch's tables
     ReqDev *h_reqs = nullptr, *d_reqs = nullptr;
     ChunkDev *h_chunks = nullptr, *d_chunks = nullptr;
+    int32_t *h_remaining = nullptr, *d_remaining = nullptr;
+    int32_t *h_flags = nullptr, *d_flags = nullptr;   // host memory, mapped for the device
     unsigned int *d_head = nullptr;
     unsigned long long *d_counters = nullptr;
     unsigned long long *h_counters = nullptr;
@@ -211,6 +324,8 @@ struct vor_server {
     int64_t n_done = 0;
     unsigned long long crossings = 0, redecisions = 0, fallbacks = 0;
     int64_t launches_done = 0;
+    int launches_running = 0;
+    std::deque<int64_t> done_queue;   // completed requests not yet taken by vor_server_next_done
     clk::time_point t0;
 
     bool arena_alloc(size_t bytes, size_t &off)
@@ -274,16 +389,46 @@ struct vor_server {
     }
 
     // Launch every admitted request that is not yet running on a free stream.
+    // Requests are grouped by context (grid, precision class) so that a wave
+    // rarely has to switch; chunks are sized for a few per wave.
     void launch_locked(Launch &L)
     {
         L.reqs.clear();
-        int nch = 0;
+        int64_t rays = 0;
         for (auto &kv : reqs) {
-            Request &r = kv.second;
+            const Request &r = kv.second;
             if (r.state != Q_ADMITTED) continue;
-            int need = (int)((r.n + kChunk - 1) / kChunk);
-            if ((int)L.reqs.size() >= kMaxLaunchReqs || nch + need > kMaxLaunchChunks) break;
-            int q = (int)L.reqs.size();
+            if ((int)L.reqs.size() >= kMaxLaunchReqs) break;
+            L.reqs.push_back(r.id);
+            rays += r.n;
+        }
+        if (L.reqs.empty()) return;
+        const int64_t waves = (int64_t)blocks * 4;
+        int64_t chunk = (rays + waves * kChunksPerWave - 1) / (waves * kChunksPerWave);
+        chunk = std::min<int64_t>(std::max<int64_t>(chunk, kChunkMin), kChunkMax);
+        // at most half the table for the rays, the rest covers one partial chunk per request
+        chunk = std::max<int64_t>(chunk, (rays + kMaxLaunchChunks / 2 - 1) / (kMaxLaunchChunks / 2));
+        chunk = (chunk + 63) / 64 * 64;
+        // cap the launch so its chunks fit the table
+        int64_t nch_total = 0;
+        size_t keep = 0;
+        for (; keep < L.reqs.size(); ++keep) {
+            const Request &r = reqs[L.reqs[keep]];
+            const int64_t need = (r.n + chunk - 1) / chunk;
+            if (nch_total + need > kMaxLaunchChunks) break;
+            nch_total += need;
+        }
+        L.reqs.resize(keep);
+        if (L.reqs.empty()) return;   // cannot happen: the requests need at most kMaxLaunchChunks / 2 + kMaxLaunchReqs chunks
+        std::stable_sort(L.reqs.begin(), L.reqs.end(), [this](int64_t x, int64_t y) {
+            const Request &a = reqs[x], &b = reqs[y];
+            return (2 * a.grid + a.mode) < (2 * b.grid + b.mode);
+        });
+        int nch = 0;
+        for (size_t qi = 0; qi < L.reqs.size(); ++qi) {
+            Request &r = reqs[L.reqs[qi]];
+            const int q = (int)qi;
+            const int need = (int)((r.n + chunk - 1) / chunk);
             ReqDev &d = L.h_reqs[q];
             d.in = r.in;
             d.tau = r.tau;
@@ -292,22 +437,27 @@ struct vor_server {
             d.seg_cell = r.seg_cell;
             d.seg_len = r.seg_len;
             d.seg_stride = r.seg_stride;
-            d.grid = r.grid;
-            d.mode = r.mode;
+            d.remaining = L.d_remaining + q;
+            d.done = L.d_flags + q;
+            L.h_remaining[q] = need;
+            L.h_flags[q] = 0;
+            const int32_t ctx = 2 * r.grid + (r.mode == VOR_MODE_MIXED ? 1 : 0);
             for (int c = 0; c < need; ++c) {
                 ChunkDev &ch = L.h_chunks[nch++];
                 ch.req = q;
-                ch.first = c * kChunk;
-                ch.count = (int)std::min<int64_t>(kChunk, r.n - (int64_t)c * kChunk);
-                ch.pad = 0;
+                ch.first = (int32_t)(c * chunk);
+                ch.count = (int32_t)std::min<int64_t>(chunk, r.n - (int64_t)c * chunk);
+                ch.ctx = ctx;
             }
             r.state = Q_RUNNING;
-            L.reqs.push_back(r.id);
         }
-        if (L.reqs.empty()) return;
         const int nreq = (int)L.reqs.size();
+        L.seen.assign(nreq, 0);
+        L.open = nreq;
         bool ok = hipMemcpyAsync(L.d_reqs, L.h_reqs, sizeof(ReqDev) * nreq, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
-                  hipMemcpyAsync(L.d_chunks, L.h_chunks, sizeof(ChunkDev) * nch, hipMemcpyHostToDevice, L.stream) == hipSuccess;
+                  hipMemcpyAsync(L.d_chunks, L.h_chunks, sizeof(ChunkDev) * nch, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
+                  hipMemcpyAsync(L.d_remaining, L.h_remaining, sizeof(int32_t) * nreq, hipMemcpyHostToDevice,
+                                 L.stream) == hipSuccess;
         hipLaunchKernelGGL(k_zero_launch, dim3(1), dim3(64), 0, L.stream, L.d_head, L.d_counters);
         int nb = std::max(1, std::min(blocks, (nch + 3) / 4));
         hipLaunchKernelGGL(k_serve, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks, nch, L.d_head,
@@ -318,23 +468,52 @@ struct vor_server {
              hipEventRecord(L.done, L.stream) == hipSuccess;
         if (!ok) fault = VOR_EDEVICE;
         L.busy = true;
+        ++launches_running;
     }
 
+    void mark_done_locked(int64_t id, clk::time_point now)
+    {
+        auto it = reqs.find(id);
+        if (it == reqs.end() || it->second.state != Q_RUNNING) return;
+        it->second.state = Q_DONE;
+        it->second.t_done = now;
+        ++n_done;
+        done_queue.push_back(id);
+    }
+
+    // Requests whose flag the kernel has raised. Returns true if any.
+    bool poll_flags_locked(Launch &L)
+    {
+        if (L.open == 0) return false;
+        bool any = false;
+        const auto now = clk::now();
+        for (size_t q = 0; q < L.reqs.size(); ++q) {
+            if (L.seen[q]) continue;
+            if (__atomic_load_n(&L.h_flags[q], __ATOMIC_ACQUIRE) != 0) {
+                L.seen[q] = 1;
+                --L.open;
+                mark_done_locked(L.reqs[q], now);
+                any = true;
+            }
+        }
+        return any;
+    }
+
+    // The launch's kernel has ended: every request in it is complete.
     void complete_locked(Launch &L)
     {
-        auto now = clk::now();
-        for (int64_t id : L.reqs) {
-            auto it = reqs.find(id);
-            if (it == reqs.end()) continue;
-            it->second.state = Q_DONE;
-            it->second.t_done = now;
-            ++n_done;
-        }
+        poll_flags_locked(L);
+        const auto now = clk::now();
+        for (size_t q = 0; q < L.reqs.size(); ++q)
+            if (!L.seen[q]) mark_done_locked(L.reqs[q], now);
         crossings += L.h_counters[0];
         fallbacks += L.h_counters[1];
         redecisions += L.h_counters[2];
         ++launches_done;
+        --launches_running;
         L.reqs.clear();
+        L.seen.clear();
+        L.open = 0;
         L.busy = false;
     }
 
@@ -345,7 +524,9 @@ struct vor_server {
         while (!stop.load()) {
             bool progress = false;
             for (auto &L : launches) {
-                if (L.busy && hipEventQuery(L.done) == hipSuccess) {
+                if (!L.busy) continue;
+                if (poll_flags_locked(L)) progress = true;
+                if (hipEventQuery(L.done) == hipSuccess) {
                     complete_locked(L);
                     progress = true;
                 }
@@ -358,9 +539,8 @@ struct vor_server {
                     if (L.busy) progress = true;
                 }
             }
-            bool inflight = launches[0].busy || launches[1].busy;
             if (!progress) {
-                if (inflight) {
+                if (launches_running > 0) {
                     lk.unlock();
                     std::this_thread::sleep_for(std::chrono::microseconds(20));
                     lk.lock();
@@ -403,6 +583,11 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
              hipHostMalloc((void **)&L.h_reqs, sizeof(ReqDev) * kMaxLaunchReqs, hipHostMallocDefault) == hipSuccess &&
              hipHostMalloc((void **)&L.h_chunks, sizeof(ChunkDev) * kMaxLaunchChunks, hipHostMallocDefault) == hipSuccess &&
              hipHostMalloc((void **)&L.h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void **)&L.h_remaining, sizeof(int32_t) * kMaxLaunchReqs, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void **)&L.h_flags, sizeof(int32_t) * kMaxLaunchReqs,
+                           hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+             hipHostGetDevicePointer((void **)&L.d_flags, L.h_flags, 0) == hipSuccess &&
+             hipMalloc(&L.d_remaining, sizeof(int32_t) * kMaxLaunchReqs) == hipSuccess &&
              hipMalloc(&L.d_reqs, sizeof(ReqDev) * kMaxLaunchReqs) == hipSuccess &&
              hipMalloc(&L.d_chunks, sizeof(ChunkDev) * kMaxLaunchChunks) == hipSuccess &&
              hipMalloc(&L.d_head, sizeof(unsigned int)) == hipSuccess &&
@@ -481,6 +666,28 @@ vor_status vor_server_wait(vor_server *S, int64_t req, double timeout_s)
     }
 }
 
+vor_status vor_server_next_done(vor_server *S, double timeout_s, int64_t *req_id)
+{
+    if (req_id) *req_id = 0;
+    if (!S || !req_id) return VOR_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto deadline = clk::now() + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(timeout_s));
+    for (;;) {
+        while (!S->done_queue.empty()) {
+            const int64_t id = S->done_queue.front();
+            S->done_queue.pop_front();
+            auto it = S->reqs.find(id);
+            if (it != S->reqs.end() && it->second.state == Q_DONE) {
+                *req_id = id;
+                return VOR_OK;
+            }
+        }
+        if (S->fault != VOR_OK) return S->fault;
+        if (S->cv.wait_until(lk, deadline) == std::cv_status::timeout && clk::now() >= deadline && S->done_queue.empty())
+            return VOR_ETIMEOUT;
+    }
+}
+
 vor_status vor_server_result(vor_server *S, int64_t req, vor_trace_out *out, double *latency_s)
 {
     if (!S || !out) return VOR_EINVAL;
@@ -528,6 +735,14 @@ vor_status vor_server_release(vor_server *S, int64_t req)
     if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
     S->arena_free(it->second.off, it->second.bytes);
     S->reqs.erase(it);
+    // ids of released requests are skipped by vor_server_next_done; drop
+    // them once they make up most of its queue (callers that only wait/poll)
+    if (S->done_queue.size() > 2 * S->reqs.size() + 64) {
+        std::deque<int64_t> keep;
+        for (int64_t id : S->done_queue)
+            if (S->reqs.count(id)) keep.push_back(id);
+        S->done_queue.swap(keep);
+    }
     S->cv.notify_all();
     return VOR_OK;
 }
@@ -541,6 +756,7 @@ vor_status vor_server_get_stats(vor_server *S, vor_server_stats *st)
     st->fp64_redecisions = (int64_t)S->redecisions;
     st->fallbacks = (int64_t)S->fallbacks;
     st->launches = S->launches_done;
+    st->running = S->launches_running;
     st->waiting = (int64_t)S->waiting.size();
     st->budget_bytes = (int64_t)S->budget;
     st->used_bytes = (int64_t)S->used;
@@ -563,6 +779,9 @@ void vor_server_destroy(vor_server *S)
         if (L.h_reqs) (void)hipHostFree(L.h_reqs);
         if (L.h_chunks) (void)hipHostFree(L.h_chunks);
         if (L.h_counters) (void)hipHostFree(L.h_counters);
+        if (L.h_remaining) (void)hipHostFree(L.h_remaining);
+        if (L.h_flags) (void)hipHostFree(L.h_flags);
+        if (L.d_remaining) (void)hipFree(L.d_remaining);
         if (L.d_reqs) (void)hipFree(L.d_reqs);
         if (L.d_chunks) (void)hipFree(L.d_chunks);
         if (L.d_head) (void)hipFree(L.d_head);

@@ -28,7 +28,8 @@ MODES = {"fp64": 0, "mixed": 1}
 EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_neighbors", "vor_locate",
            "vor_trace", "vor_order_rays", "vor_order_workspace_bytes", "vor_exclusive_scan", "vor_status_str", "vor_version",
            "vor_server_create", "vor_server_submit", "vor_server_poll", "vor_server_wait", "vor_server_result",
-           "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy"]
+           "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy",
+           "vor_server_next_done"]
 
 
 class VorError(RuntimeError):
@@ -66,7 +67,8 @@ SPILL_CHUNK = 64
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("crossings", ctypes.c_int64), ("fp64_redecisions", ctypes.c_int64),
-                ("fallbacks", ctypes.c_int64), ("launches", ctypes.c_int64), ("waiting", ctypes.c_int64),
+                ("fallbacks", ctypes.c_int64), ("launches", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("waiting", ctypes.c_int64),
                 ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64), ("uptime_s", ctypes.c_double)]
 
 
@@ -115,6 +117,8 @@ def load(path: str = None):
     lib.vor_server_poll.restype = ctypes.c_int
     lib.vor_server_wait.argtypes = [P, I64, D]
     lib.vor_server_wait.restype = ctypes.c_int
+    lib.vor_server_next_done.argtypes = [P, D, ctypes.POINTER(I64)]
+    lib.vor_server_next_done.restype = ctypes.c_int
     lib.vor_server_result.argtypes = [P, I64, ctypes.POINTER(TraceOut), ctypes.POINTER(D)]
     lib.vor_server_result.restype = ctypes.c_int
     lib.vor_server_copy_result.argtypes = [P, I64, P, P, P, P, P, P]
@@ -415,6 +419,16 @@ class Server:
 
     def wait(self, req: int, timeout_s: float = 60.0) -> None:
         _check(load().vor_server_wait(self._h, req, float(timeout_s)), "vor_server_wait")
+
+    def next_done(self, timeout_s: float = 60.0) -> Optional[int]:
+        """The next request to complete (completion order), or None when none
+        completes within timeout_s."""
+        rid = ctypes.c_int64()
+        code = load().vor_server_next_done(self._h, float(timeout_s), ctypes.byref(rid))
+        if code == VOR_ETIMEOUT:
+            return None
+        _check(code, "vor_server_next_done")
+        return rid.value
 
     def latency(self, req: int) -> float:
         o = TraceOut()

@@ -57,6 +57,17 @@ def _same(a, b):
     return all(torch.equal(a[k].view(n, stride)[mask], b[k].view(n, stride)[mask]) for k in ("seg_cell", "seg_len"))
 
 
+def _idle_stats(srv, timeout=60.0):
+    """Server statistics once no launch is in flight (crossings are counted
+    when a launch ends, which can be after its requests completed)."""
+    t0 = time.time()
+    while True:
+        st = srv.stats()
+        if st["running"] == 0 or time.time() - t0 > timeout:
+            return st
+        time.sleep(0.001)
+
+
 def test_alone_equals_in_the_mix_equals_vor_trace(env):
     vrt, torch, ws, grids, rhos = env
     reqs = _requests(ws, 24, seed=5)
@@ -77,7 +88,7 @@ def test_alone_equals_in_the_mix_equals_vor_trace(env):
         torch.cuda.synchronize()
         for rid in ids:
             srv.release(rid)
-        st = srv.stats()
+        st = _idle_stats(srv)
     finally:
         srv.close()
     for r, a, m in zip(reqs, alone, mixed):
@@ -146,3 +157,52 @@ def test_server_argument_errors(env):
             srv.release(rid)                          # already released
     finally:
         srv.close()
+
+
+def test_completion_queue_and_early_completion(env):
+    """next_done hands out every request once, in completion order; a small
+    request launched with large ones completes before they do; a result read
+    as soon as its request is done equals vor_trace."""
+    vrt, torch, ws, grids, rhos = env
+    stride = 32
+    rng = np.random.default_rng(11)
+    w = ws[2]
+    sizes = [200_000, 200_000, 300, 200_000, 500]
+    reqs = []
+    for n in sizes:
+        o = torch.as_tensor(np.ascontiguousarray(w.sites[rng.integers(0, w.M, n)]), device="cuda")
+        d = torch.as_tensor(W.isotropic_dirs(rng, n), device="cuda")
+        reqs.append((o, d))
+    srv = vrt.Server(grids, budget_bytes=2 << 30)
+    try:
+        ids = [srv.submit(2, o, d, rhos[2], mode="mixed", seg_stride=stride) for o, d in reqs]
+        seen = []
+        got = {}
+        while len(seen) < len(ids):
+            rid = srv.next_done(60)
+            assert rid is not None, "no request completed within 60 s"
+            assert rid not in seen
+            seen.append(rid)
+            got[rid] = srv.result(rid)      # read while other requests may still run
+        assert sorted(seen) == sorted(ids)
+        assert srv.next_done(0.01) is None
+        lat = {rid: srv.latency(rid) for rid in ids}
+        for rid in ids:
+            srv.release(rid)
+        st = _idle_stats(srv)
+    finally:
+        srv.close()
+    # requests of one launch complete in any order; the small ones need not wait for the large ones
+    small = [ids[2], ids[4]]
+    large = [ids[0], ids[1], ids[3]]
+    assert min(lat[r] for r in small) <= max(lat[r] for r in large)
+    for (o, d), rid in zip(reqs, ids):
+        ref = vrt.trace(grids[2], o, d, rhos[2], mode="mixed", segments="stride", seg_stride=stride)
+        a = got[rid]
+        assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
+        assert torch.equal(ref["status"], a["status"])
+        n = o.shape[0]
+        mask = torch.arange(stride, device="cuda")[None, :] < a["n_seg"].clamp(max=stride)[:, None]
+        assert torch.equal(ref["seg_cell"].view(n, stride)[mask], a["seg_cell"].view(n, stride)[mask])
+        assert torch.equal(ref["seg_len"].view(n, stride)[mask], a["seg_len"].view(n, stride)[mask])
+    assert st["completed"] == len(ids) and st["running"] == 0
