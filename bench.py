@@ -132,12 +132,15 @@ def prepare_buffers(vrt, torch, grid, o, d, rho, spec, mode=None):
 
 
 def step(vrt, grid, o, d, rho, bufs, spec, mode, reuse_order=False):
-    """One step of the path: the coherent ray order (unless reused), then the
-    trace with segment windows and spill."""
+    """One step of the path: the coherent ray order, then vor_trace (start
+    cells, traversal, segment windows and spill). reuse_order: the order and
+    the start cells of the previous step on the same rays are reused, so
+    only the traversal kernel runs (the roofline launches)."""
     ordered = spec.get("ordered", False)
     if ordered and not reuse_order:
         vrt.order_rays(grid, o, d, bufs.order, bufs.order_ws)
-    opts = vrt.TraceOpts(vrt.MODES[mode], 0, 0.0, 1 if spec.get("persistent", False) else 0, 0)
+    opts = vrt.TraceOpts(vrt.MODES[mode], 0, 0.0, 1 if spec.get("persistent", False) else 0,
+                         1 if reuse_order else 0)
     out = bufs.struct(use_order=ordered)
     rc = vrt.load().vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(d), o.shape[0], vrt._ptr(rho), 1.0,
                               vrt.ctypes.byref(opts), vrt.ctypes.byref(out), vrt._stream())
@@ -329,7 +332,7 @@ def main(argv=None):
     nseg_mixed = bufs.n_seg.clone()
 
     # the trace kernel alone for the roofline: the same launch with the order
-    # already computed (events around vor_trace only)
+    # and the start cells already computed (events around vor_trace only)
     k_ms = run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, 1, timed=False)
     bufs.counters.zero_()
     k_ms = run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, args.roofline_reps, timed=True,

@@ -142,9 +142,12 @@ vor_status vor_locate(const vor_grid *grid, const double *pts, int64_t N, int32_
 typedef struct {
     int32_t mode;           /* VOR_MODE_FP64 (default) or VOR_MODE_MIXED */
     int32_t max_steps;      /* per-ray cap on cell moves; 0 = M + 16 */
-    double eps_mix;         /* mixed mode: relative gap below which an FP32 decision is redone in FP64; 0 = 2^-12 */
+    double eps_mix;         /* mixed mode: relative rounding allowance of the FP32 crossing bound; 0 = 2^-19,
+                               else in [2^-19, 0.25] (larger values only redo more steps in FP64) */
     int32_t persistent;     /* 1: persistent kernel whose waves refill finished lanes from a work queue */
-    int32_t reserved;
+    int32_t start_given;    /* 1: out->start_cell already holds the start cells of these rays, left there by
+                               an earlier call on the same grid with the same origins (another density,
+                               kappa or mode); the start-cell pass is skipped */
 } vor_trace_opts;
 
 /* Outputs of vor_trace. All pointers are device memory; tau and n_seg are required. */
@@ -158,7 +161,9 @@ typedef struct {
     int64_t seg_stride;     /* > 0: ray i owns slots [i*seg_stride, (i+1)*seg_stride) */
     const int64_t *ray_off; /* seg_stride == 0: ray i owns [ray_off[i], ray_off[i+1]) */
     unsigned long long *counters; /* [8] accumulated: segments, fallbacks, FP64 re-decisions, steps,
-                                     neighbour records read, 3 reserved; may be NULL */
+                                     neighbour records read, wave iterations and refills of the persistent
+                                     kernel (steps / (64 x iterations) is its lane utilisation), 1 reserved;
+                                     may be NULL */
     int64_t *work;          /* [4] control words, required for persistent mode and spill; zeroed by the call */
     /* Spill (stride mode only, all NULL to disable): a ray whose path is
      * longer than seg_stride keeps its first seg_stride segments in its
@@ -175,6 +180,10 @@ typedef struct {
     int64_t spill_chunks;
     const int32_t *ray_order; /* optional [N]: lane i traces ray ray_order[i] (a permutation, e.g. from
                                  vor_order_rays); outputs stay indexed by ray */
+    int32_t *start_cell;    /* optional [N] scratch: when set, the start cells C(r0) of all rays are located
+                               in a pass of their own before the traversal (faster, mostly with the
+                               persistent kernel) and left here (internal cell indices, -1 for rays
+                               without a path) for reuse through opts.start_given */
 } vor_trace_out;
 
 /*
@@ -191,8 +200,13 @@ typedef struct {
  *   origins, dirs  device, N x 3.    density  device, M doubles (user order), or NULL (tau = 0).
  *   kappa          multiplies tau.   opts     host, may be NULL.
  *   out            host struct of device pointers.
+ * VOR_MODE_MIXED ranks the planes in FP32 with a certified bound on each
+ * crossing's rounding error and decides in FP64 whenever the bounds do not
+ * separate the winner, so its results equal VOR_MODE_FP64's bit for bit.
  * Asynchronous on `stream`; allocates nothing. Per-ray problems are reported
- * in out->status, not as a return code.
+ * in out->status, not as a return code; VOR_EINVAL for inconsistent
+ * pointers, an option out of range, or mixed mode on a box with a
+ * coordinate of magnitude 1e30 or more.
  */
 vor_status vor_trace(const vor_grid *grid, const double *origins, const double *dirs, int64_t N,
                      const double *density, double kappa, const vor_trace_opts *opts,

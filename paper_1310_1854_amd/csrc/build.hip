@@ -499,9 +499,12 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     hipLaunchKernelGGL(k_row_sort, dim3(blocks_for(M, T)), dim3(T), 0, st, col, start, total, M);
 
     g.rows = dalloc<int2>(M, rc, keep);
-    g.rec64 = dalloc<Rec64>(std::max<int64_t>(g.nnz, 1), rc, keep);
-    g.rec32 = dalloc<Rec32>(std::max<int64_t>(g.nnz, 1), rc, keep);
+    g.rec64 = dalloc<Rec64>(g.nnz + kRecPad, rc, keep);
+    g.rec32 = dalloc<Rec32>(g.nnz + kRecPad, rc, keep);
     if (rc != VOR_OK) return fail(rc);
+    if (hipMemsetAsync(g.rec64 + g.nnz, 0, sizeof(Rec64) * kRecPad, st) != hipSuccess ||
+        hipMemsetAsync(g.rec32 + g.nnz, 0, sizeof(Rec32) * kRecPad, st) != hipSuccess)
+        return fail(VOR_EDEVICE);
     hdr = err + 1;   // longest row
     hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, col, total, start, M, g.rows,
                        g.rec64, g.rec32, hdr);
@@ -520,7 +523,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
 
     for (void *p : tmp) (void)hipFree(p);
     g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2)) + (B + 1) * 4 +
-                     g.nnz * (int64_t)(sizeof(Rec64) + sizeof(Rec32));
+                     (g.nnz + kRecPad) * (int64_t)(sizeof(Rec64) + sizeof(Rec32));
     g.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = G;
     return VOR_OK;

@@ -29,10 +29,14 @@ struct TraceArgs {
     const int32_t *order;
     unsigned long long *counters;
     int64_t *work;        // [0] persistent queue head, [1] spill chunks asked for, [2] rays past their window
+    int32_t *start;       // start cell (internal) of every ray from k_start_cells, or null: located at ray start
 };
 
 #ifndef VRT_REFILL_MIN
 #define VRT_REFILL_MIN 48
+#endif
+#ifndef VRT_DEFER_FINISH
+#define VRT_DEFER_FINISH 1
 #endif
 #ifndef VRT_WAVES_PER_EU
 #define VRT_WAVES_PER_EU 0
@@ -105,8 +109,79 @@ __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RaySt
 {
     R.st = ray_setup(A.G, A.I, ray, R.r0, R.k, R.L);
     R.tau = 0.0;
-    if (R.st == RAY_OK) ray_begin(A.G, R);
-    else R.L = 0.0;
+    if (R.st == RAY_OK) {
+        if (A.start) ray_begin_at(A.G, R, A.start[ray]);
+        else ray_begin(A.G, R);
+    } else {
+        R.L = 0.0;
+    }
+}
+
+// nearest_site for a point shared by the whole wave: the sites of each
+// bucket are split over the 64 lanes, and after each shell the lanes agree
+// on the lexicographic minimum of (squared distance, user index). The
+// shells visited, the distances and the minimum are those of nearest_site.
+__device__ int32_t nearest_site_wave(const BucketGridView &g, const double q[3], int32_t *uid_out)
+{
+    const int lane = threadIdx.x & 63;
+    int b[3];
+    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], g.lo[a], g.inv_h[a], g.dims[a]);
+    double best = 1e308 * 10.0;
+    int32_t best_i = -1;
+    int32_t best_u = 0x7fffffff;
+    for (int r = 0;; ++r) {
+        for_shell(g, b, r, [&](int bk) {
+            const int s0 = g.start[bk], s1 = g.start[bk + 1];
+            for (int s = s0 + lane; s < s1; s += 64) {
+                const Site p = g.items[s];
+                const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
+                const double d = dx * dx + dy * dy + dz * dz;
+                const int32_t idx = (int32_t)(p.uid & 0xffffffff);
+                const int32_t uid = (int32_t)(p.uid >> 32);
+                if (d < best || (d == best && uid < best_u)) {
+                    best = d;
+                    best_i = idx;
+                    best_u = uid;
+                }
+            }
+        });
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int32_t ou = __shfl_xor(best_u, off, 64);
+            const int32_t oi = __shfl_xor(best_i, off, 64);
+            if (ob < best || (ob == best && ou < best_u)) {
+                best = ob;
+                best_u = ou;
+                best_i = oi;
+            }
+        }
+        const double lb = shell_bound(g, q, b, r);
+        if (lb < 0.0) break;
+        const double lb2 = lb * lb * (1.0 - 1e-12);
+        if (best < lb2) break;
+    }
+    if (uid_out) *uid_out = best_u;
+    return best_i;
+}
+
+// The start cell C(r0) of every ray (Sect. 2.3), in processing order, ahead
+// of the traversal: the ring searches of neighbouring lanes run side by side
+// here instead of interrupting the persistent waves at every refill. A wave
+// whose 64 rays share one origin (a point source, rays in coherent order)
+// searches once, cooperatively.
+__global__ void __launch_bounds__(256) k_start_cells(TraceArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < A.N;
+    const int64_t ray = valid ? (A.order ? (int64_t)A.order[i] : i) : 0;
+    double r0[3] = {0.0, 0.0, 0.0}, k[3], L;
+    const uint8_t st = valid ? ray_setup(A.G, A.I, ray, r0, k, L) : (uint8_t)RAY_BADDIR;
+    const double q0 = __shfl(r0[0], 0, 64), q1 = __shfl(r0[1], 0, 64), q2 = __shfl(r0[2], 0, 64);
+    const bool same = valid && st == RAY_OK && r0[0] == q0 && r0[1] == q1 && r0[2] == q2;
+    int32_t m = -1;
+    if (__ballot(true) == ~0ull && __ballot(same) == ~0ull) m = nearest_site_wave(A.G.grid, r0, nullptr);
+    else if (valid && st == RAY_OK) m = nearest_site(A.G.grid, r0, nullptr);
+    if (valid) A.start[ray] = (st == RAY_OK) ? m : -1;
 }
 
 // One ray per lane.
@@ -143,11 +218,20 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
     bool live = false;
     unsigned long long *head = (unsigned long long *)&A.work[0];
     bool drained = false;   // wave-uniform: the queue has run out
+    bool pending = false;   // this lane's ray has ended and its results are not yet written
+    unsigned int wit = 0, wref = 0;   // wave-uniform: iterations with a live lane, refills
     for (;;) {
         const bool need = !live;
         const uint64_t want = __ballot(need);
         const uint64_t busy = ~want & __ballot(true);
         if (want && !drained && (__popcll(want) >= kRefillMin || busy == 0ull)) {
+            ++wref;
+#if VRT_DEFER_FINISH
+            if (pending) {   // the ended rays of the wave write their results together
+                ray_finish<SEGS>(A, ray, R, S);
+                pending = false;
+            }
+#endif
             int n = __popcll(want);
             int leader = __ffsll((long long)want) - 1;
             unsigned long long base0 = 0;
@@ -171,9 +255,14 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
             if (drained) break;   // the queue is drained and every ray has ended
             continue;
         }
+        ++wit;
         if (live) {
             if (!ray_step<MODE, SEGS>(A.G, A.I, R, S, A.O)) {
+#if VRT_DEFER_FINISH
+                pending = true;
+#else
                 ray_finish<SEGS>(A, ray, R, S);
+#endif
                 T.cnt += S.cnt;
                 T.nfb += S.nfb;
                 T.nredo += S.nredo;
@@ -183,7 +272,14 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
             }
         }
     }
+#if VRT_DEFER_FINISH
+    if (pending) ray_finish<SEGS>(A, ray, R, S);
+#endif
     flush_counters(A, T);
+    if (A.counters && (threadIdx.x & 63) == 0) {
+        atomicAdd(&A.counters[5], (unsigned long long)wit);
+        atomicAdd(&A.counters[6], (unsigned long long)wref);
+    }
 }
 
 // Sort keys of a ray: Hilbert index of its origin (10 bits per axis over the
@@ -270,10 +366,13 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
         return VOR_EINVAL;
     int mode = opts ? opts->mode : VOR_MODE_FP64;
     if (mode != VOR_MODE_FP64 && mode != VOR_MODE_MIXED) return VOR_EINVAL;
-    if (opts && (opts->max_steps < 0 || opts->eps_mix < 0 || !(opts->eps_mix < 1.0))) return VOR_EINVAL;
+    if (opts && (opts->max_steps < 0 || !(opts->eps_mix == 0.0 || (opts->eps_mix >= kEpsMixMin && opts->eps_mix <= 0.25))))
+        return VOR_EINVAL;
     const bool persistent = opts && opts->persistent;
     if (persistent && !out->work) return VOR_EINVAL;
+    if (opts && opts->start_given && !out->start_cell) return VOR_EINVAL;
     const Grid &g = vrt_grid_of(G);
+    if (mode == VOR_MODE_MIXED && !mixed_mode_fits(g)) return VOR_EINVAL;
     TraceArgs A;
     A.G = grid_ref(g, opts ? opts->max_steps : 0, opts ? opts->eps_mix : 0.0);
     A.I.origins = origins;
@@ -299,9 +398,12 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     A.O.spill_first = out->spill_first;
     A.O.spill_chunks = out->spill_chunks;
     A.O.chunk_head = out->work ? (unsigned long long *)&out->work[1] : nullptr;
+    A.start = out->start_cell;
     hipStream_t st = (hipStream_t)stream;
     const int T = 256;
     if (A.work) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, A.work, 4);
+    if (A.start && !(opts && opts->start_given))
+        hipLaunchKernelGGL(k_start_cells, dim3((unsigned)((N + T - 1) / T)), dim3(T), 0, st, A);
     if (spill) {
         int64_t nb = std::min<int64_t>((N + T - 1) / T, 65535);
         hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)nb), dim3(T), 0, st, A.O.spill_first, N, (int64_t)-1);
@@ -398,3 +500,16 @@ extern "C" const char *vor_status_str(vor_status s)
 }
 
 extern "C" const char *vor_version(void) { return "voronoi_rt 0.1 (gfx950)"; }
+
+#if VRT_DIAG
+// Diagnostic build only: read and clear the batch counters.
+extern "C" int vor_diag_take(unsigned long long *out)
+{
+    unsigned long long z[4] = {0, 0, 0, 0};
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpyFromSymbol(out, HIP_SYMBOL(vrt_diag), sizeof(z)) != hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(vrt_diag), z, sizeof(z)) != hipSuccess)
+        return 1;
+    return 0;
+}
+#endif

@@ -26,6 +26,7 @@ struct GridRef {
     double lo[3], hi[3];
     int32_t max_steps;
     float eps_mix;
+    float eps_abs;        // FP64 rounding allowance of the mixed-mode bound (2^-48 x coordinate scale)
     double eps_fb;        // no-exit fallback advance
 };
 
@@ -57,6 +58,19 @@ struct SegOut {
     unsigned long long *chunk_head; // chunks handed out
 };
 
+// Smallest accepted eps of the mixed-mode bound (2^-19): 2.6 times what the
+// first-order rounding analysis needs.
+constexpr double kEpsMixMin = 1.9073486328125e-06;
+
+// Mixed mode keeps offsets, points and bounds in FP32: the box must lie
+// well inside the FP32 range.
+inline bool mixed_mode_fits(const Grid &g)
+{
+    for (int a = 0; a < 6; ++a)
+        if (!(fabs(g.box[a]) < 1e30)) return false;
+    return true;
+}
+
 inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
 {
     GridRef G;
@@ -65,14 +79,16 @@ inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
     G.rec64 = g.rec64;
     G.rec32 = g.rec32;
     G.grid = bucket_view(g);
-    double diag = 0.0;
+    double diag = 0.0, cmax = 0.0;
     for (int a = 0; a < 3; ++a) {
         G.lo[a] = g.box[a];
         G.hi[a] = g.box[a + 3];
         diag += (g.box[a + 3] - g.box[a]) * (g.box[a + 3] - g.box[a]);
+        cmax = fmax(cmax, fmax(fabs(g.box[a]), fabs(g.box[a + 3])));
     }
     G.max_steps = max_steps > 0 ? max_steps : (int32_t)(g.M + 16 < 0x7fffffff ? g.M + 16 : 0x7fffffff);
-    G.eps_mix = (float)(eps_mix > 0 ? eps_mix : 1.9073486328125e-06);   // 2^-19
+    G.eps_mix = (float)(eps_mix > 0 ? eps_mix : kEpsMixMin);
+    G.eps_abs = (float)(3.552713678800501e-15 * (2.0 * cmax + sqrt(diag)));   // 2^-48
     G.eps_fb = 1e-12 * sqrt(diag);
     return G;
 }
@@ -80,11 +96,28 @@ inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
 #ifndef VRT_BATCH64
 #define VRT_BATCH64 4
 #endif
+#ifndef VRT_DIAG
+#define VRT_DIAG 0
+#endif
+#if VRT_DIAG
+// Diagnostic build only: batches executed by each wave, counted by the
+// wave's first active lane.
+__device__ unsigned long long vrt_diag[4];
+__device__ __forceinline__ void diag_count(int i)
+{
+    const uint64_t act = __ballot(true);
+    if ((int)(threadIdx.x & 63) == __ffsll((long long)act) - 1) atomicAdd(&vrt_diag[i], 1ull);
+}
+#define VRT_DIAG_COUNT(i) diag_count(i)
+#else
+#define VRT_DIAG_COUNT(i)
+#endif
 #ifndef VRT_BATCH32
 #define VRT_BATCH32 8
 #endif
 constexpr int kBatch64 = VRT_BATCH64;   // FP64 records loaded together per lane
 constexpr int kBatch32 = VRT_BATCH32;   // FP32 records loaded together per lane
+static_assert(kBatch64 - 1 <= kRecPad && kBatch32 - 1 <= kRecPad, "a batch may read past a row end");
 
 
 // Crossing of one bisector plane in FP64, measured from r0 (Eqs. 1-4):
@@ -114,22 +147,21 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
     int32_t win_j = 0x7fffffff;
     const int end = rw.x + rw.y;
     for (int e0 = rw.x; e0 < end; e0 += kBatch64) {
+        VRT_DIAG_COUNT(1);
         Rec64 q[kBatch64];
 #pragma unroll
-        for (int u = 0; u < kBatch64; ++u)
-            if (e0 + u < end) q[u] = rec[e0 + u];
+        for (int u = 0; u < kBatch64; ++u) q[u] = rec[e0 + u];   // past the row end: padding or the next row, unused
 #pragma unroll
         for (int u = 0; u < kBatch64; ++u) {
-            if (e0 + u >= end) break;
             double den;
-            double sj = cross_fp64(q[u].x, q[u].y, q[u].z, pm, r0, k, den);
-            if (!(den > 0.0)) continue;
-            if (sj < best || (sj == best && win >= 0 && (den > best_den || (den == best_den && q[u].j < win_j)))) {
-                best = sj;
-                best_den = den;
-                win = e0 + u;
-                win_j = q[u].j;
-            }
+            const double sj = cross_fp64(q[u].x, q[u].y, q[u].z, pm, r0, k, den);
+            const bool take = e0 + u < end && den > 0.0 &&
+                              (sj < best || (sj == best && win >= 0 &&
+                                             (den > best_den || (den == best_den && q[u].j < win_j))));
+            best = take ? sj : best;
+            best_den = take ? den : best_den;
+            win = take ? e0 + u : win;
+            win_j = take ? q[u].j : win_j;
         }
     }
     return win;
@@ -138,21 +170,35 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
 // Mixed-precision exit search. Returns the winning record index (-1: the
 // chord end), with redo set when the step was decided in FP64 (then best is
 // the FP64 crossing); otherwise j1 is the winner's internal index and the
-// caller computes its FP64 crossing from the site (fetched together with
-// the winner's row). Every plane is ranked with FP32 offsets and
-// a bound on the FP32 rounding error of its crossing,
-//   err = eps * (1.5 |n|^2 + 0.5 (|q| + |t|)^2) / (n.k) + 4u |t|,
-// (q = current point - p_m, t = the FP32 crossing, u = 2^-24; eps >= 12u
-// covers the rounding of n, q, k and of the products, the AM-GM step
-// |n|(|q|+|t|) <= (|n|^2 + (|q|+|t|)^2)/2 turns the bound into this form).
-// If the upper bound of the best candidate is below the lower bound of every
-// other one (the wall included) the FP32 ranking is certain, and only the
-// winner's crossing is recomputed in FP64 (from the FP64 record, same
-// arithmetic as exit_fp64); otherwise the step is redone in FP64. Either way
-// the result equals exit_fp64's.
+// caller computes its FP64 crossing from the site (fetched together with the
+// winner's row). Either way the result equals exit_fp64's.
+//
+// Each plane is ranked in FP32 from its stored offset n = p_j - p_m
+// (rounded once to FP32), the current point q = r - p_m and k (both
+// rounded to FP32), with one hardware reciprocal (error <= 1 ulp) for
+// 1/(n.k) and a bound on how far the FP32 crossing t can be from the one
+// exit_fp64 computes:
+//   err = [eps (1.5 |n|^2 + 0.5 (|q| + |t|)^2) + e_abs |n|_1] / (n.k) + 6u |t|
+// (u = 2^-24). eps >= 12u covers the rounding of n, q, k and of the
+// products and sums (fused or not) to first order (|n|(|q|+|t|) <= (|n|^2 + (|q|+|t|)^2)/2 turns
+// the cross terms into this form); 6u |t| covers the reciprocal, the
+// product and the roundings of t - err and t + err; e_abs |n|_1 / (n.k)
+// covers the FP64 roundings of exit_fp64 itself (2^-48 times twice the
+// largest box coordinate plus the box diagonal). The error of the FP32 n.k
+// is at most d = 8u |n|_1; planes with n.k > 2d have an FP64 n.k > 0 and a
+// first-order bound that holds (the relative error of n.k is below 1/2 and
+// eps is 2.6 times the first-order need); planes with n.k <= -d have an
+// FP64 n.k <= 0 and are skipped as exit_fp64 skips them; a plane in between
+// (nearly parallel to the ray) gets lower bound -inf and forces the FP64
+// decision. If the upper bound of the best candidate is below the lower
+// bound of every other one (the wall included), the FP32 ranking is certain
+// and only the winner's crossing is recomputed in FP64 (from its site, same
+// arithmetic as exit_fp64); otherwise the step is redone in FP64.
+// Records are loaded a whole batch at a time, unconditionally (the record
+// arrays are padded for the last row); entries past the row end are masked.
 __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const Rec32 *__restrict__ rec32, int2 rw,
                                           const double pm[3], const double r0[3], const double k[3], double L,
-                                          double s_c, float eps, double &best, bool &redo, int32_t &j1)
+                                          double s_c, float eps, float e_abs, double &best, bool &redo, int32_t &j1)
 {
     double q64[3];
     for (int a = 0; a < 3; ++a) q64[a] = (r0[a] + s_c * k[a]) - pm[a];
@@ -160,46 +206,52 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const
     const float kx = (float)k[0], ky = (float)k[1], kz = (float)k[2];
     const float qa = sqrtf(qx * qx + qy * qy + qz * qz);
     const float u = 5.9604645e-8f;   // 2^-24
+    const float c1 = 1.5f * eps, c2 = 0.5f * eps, cd = 8.0f * u, ct = 6.0f * u;
+    const float inf = __builtin_huge_valf();
     const float tw = (float)(L - s_c);   // the wall, relative to the current point
-    const float ew = 2.0f * u * fabsf(tw);
+    const float ew = 2.0f * u * fabsf(tw) + e_abs;
     float t1 = tw, hi1 = tw + ew;       // best estimate and its upper bound
     int e1 = -1;
-    float lo_a = tw - ew, lo_b = 3.0e38f;   // two smallest lower bounds
+    float lo_a = tw - ew, lo_b = inf;   // two smallest lower bounds
     int ia = -1;
     const int end = rw.x + rw.y;
     for (int e0 = rw.x; e0 < end; e0 += kBatch32) {
+        VRT_DIAG_COUNT(0);
         Rec32 r[kBatch32];
 #pragma unroll
-        for (int v = 0; v < kBatch32; ++v)
-            if (e0 + v < end) r[v] = rec32[e0 + v];
+        for (int v = 0; v < kBatch32; ++v) r[v] = rec32[e0 + v];   // past the row end: padding or the next row, masked
 #pragma unroll
         for (int v = 0; v < kBatch32; ++v) {
-            if (e0 + v >= end) break;
-            float den = r[v].nx * kx + r[v].ny * ky + r[v].nz * kz;
-            if (!(den > 0.0f)) continue;
-            float nn = r[v].nx * r[v].nx + r[v].ny * r[v].ny + r[v].nz * r[v].nz;
-            float num = 0.5f * nn - (r[v].nx * qx + r[v].ny * qy + r[v].nz * qz);
-            float t = num / den;
-            float at = fabsf(t);
-            float sq = qa + at;
-            float err = eps * (1.5f * nn + 0.5f * sq * sq) / den + 4.0f * u * at;
-            float lo = t - err;
-            if (t < t1) {
-                t1 = t;
-                hi1 = t + err;
-                e1 = e0 + v;
-                j1 = r[v].j;
-            }
-            if (lo < lo_a) {
-                lo_b = lo_a;
-                lo_a = lo;
-                ia = e0 + v;
-            } else if (lo < lo_b) {
-                lo_b = lo;
-            }
+            const bool in = e0 + v < end;
+            const float nx = r[v].nx, ny = r[v].ny, nz = r[v].nz;
+            const float den = fmaf(nx, kx, fmaf(ny, ky, nz * kz));
+            const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+            const float nq = fmaf(nx, qx, fmaf(ny, qy, nz * qz));
+            const float num = fmaf(0.5f, nn, -nq);
+            const float n1 = fabsf(nx) + fabsf(ny) + fabsf(nz);
+            const float d = cd * n1;
+            const bool pos = in && den > fmaxf(2.0f * d, 1.17549435e-38f);
+            const bool maybe = in && den > -d;
+            const float rc = __builtin_amdgcn_rcpf(den);
+            const float t = num * rc;
+            const float at = fabsf(t);
+            const float sq = qa + at;
+            const float E = fmaf(c2 * sq, sq, fmaf(c1, nn, e_abs * n1));
+            const float err = fmaf(E, rc, ct * at);
+            const float lo = pos ? t - err : (maybe ? -inf : inf);
+            // branch-free updates of the winner and of the two smallest lower bounds
+            const bool w = pos && t < t1;
+            t1 = w ? t : t1;
+            hi1 = w ? t + err : hi1;
+            e1 = w ? e0 + v : e1;
+            j1 = w ? r[v].j : j1;
+            const bool b1 = lo < lo_a, b2 = lo < lo_b;
+            lo_b = b1 ? lo_a : (b2 ? lo : lo_b);
+            lo_a = b1 ? lo : lo_a;
+            ia = b1 ? e0 + v : ia;
         }
     }
-    float lo_other = (ia == e1) ? lo_b : lo_a;
+    const float lo_other = (ia == e1) ? lo_b : lo_a;
     if (!(hi1 < lo_other)) {
         redo = true;
         return exit_fp64(rec64, rw, pm, r0, k, L, best);
@@ -267,6 +319,20 @@ __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R)
     Site sm = G.sites[m];
     R.m = m;
     R.uid = uid;
+    R.pm[0] = sm.x;
+    R.pm[1] = sm.y;
+    R.pm[2] = sm.z;
+    R.rw = G.rows[m];
+}
+
+// Start in cell m (internal index), found beforehand by nearest_site.
+__device__ __forceinline__ void ray_begin_at(const GridRef &G, RayState &R, int32_t m)
+{
+    R.s_c = 0.0;
+    R.tau = 0.0;
+    const Site sm = G.sites[m];
+    R.m = m;
+    R.uid = (int32_t)sm.uid;
     R.pm[0] = sm.x;
     R.pm[1] = sm.y;
     R.pm[2] = sm.z;
@@ -405,7 +471,7 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
     } else {
         bool redo;
         int32_t j1 = -1;
-        int win = exit_mixed(G.rec64, G.rec32, rw, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, best, redo, j1);
+        int win = exit_mixed(G.rec64, G.rec32, rw, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs, best, redo, j1);
         S.nredo += redo ? 1 : 0;
         if (win >= 0) {
             if (redo) {

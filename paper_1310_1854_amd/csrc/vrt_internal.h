@@ -34,6 +34,10 @@ struct __align__(32) Site {
     int64_t uid;
 };
 
+// Records readable past the end of the last row (zeroed): the exit search
+// loads whole batches and masks the entries past a row's end.
+constexpr int kRecPad = 16;
+
 struct Grid {
     int64_t M = 0;
     int64_t nnz = 0;
@@ -50,8 +54,8 @@ struct Grid {
     int32_t *perm = nullptr;        // [M] internal -> user
     int32_t *inv_perm = nullptr;    // [M] user -> internal
     int2 *rows = nullptr;           // [M] {start, count} into rec64/rec32
-    Rec64 *rec64 = nullptr;         // [nnz]
-    Rec32 *rec32 = nullptr;         // [nnz]
+    Rec64 *rec64 = nullptr;         // [nnz + kRecPad]
+    Rec32 *rec32 = nullptr;         // [nnz + kRecPad]
     uint8_t *wall_mask = nullptr;   // [M] bit w set if wall -(w+1) is a face
     int32_t *bucket_start = nullptr;// [B + 1]
     Site *bucket_sites = nullptr;   // [M] sites grouped by bucket (uid holds the internal index)

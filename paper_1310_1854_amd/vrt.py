@@ -50,7 +50,7 @@ class GridInfo(ctypes.Structure):
 
 class TraceOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_steps", ctypes.c_int32), ("eps_mix", ctypes.c_double),
-                ("persistent", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("start_given", ctypes.c_int32)]
 
 
 class TraceOut(ctypes.Structure):
@@ -59,7 +59,7 @@ class TraceOut(ctypes.Structure):
                 ("seg_stride", ctypes.c_int64), ("ray_off", ctypes.c_void_p), ("counters", ctypes.c_void_p),
                 ("work", ctypes.c_void_p), ("spill_first", ctypes.c_void_p), ("spill_next", ctypes.c_void_p),
                 ("spill_cell", ctypes.c_void_p), ("spill_len", ctypes.c_void_p), ("spill_chunks", ctypes.c_int64),
-                ("ray_order", ctypes.c_void_p)]
+                ("ray_order", ctypes.c_void_p), ("start_cell", ctypes.c_void_p)]
 
 
 SPILL_CHUNK = 64
@@ -234,8 +234,10 @@ class TraceBuffers:
     ordered: also hold a processing order (vor_order_rays) and its workspace."""
 
     def __init__(self, N: int, seg_stride: int = 0, total_segments: int = 0, spill_chunks: int = 0,
-                 device="cuda", counters=True, ordered=False):
+                 device="cuda", counters=True, ordered=False, locate_first=True):
         self.N = N
+        # scratch for the start-cell pass (vor_trace_out.start_cell)
+        self.start_cell = torch.empty(max(N, 1), dtype=torch.int32, device=device) if locate_first else None
         self.tau = torch.empty(N, dtype=torch.float64, device=device)
         self.n_seg = torch.empty(N, dtype=torch.int32, device=device)
         self.status = torch.empty(N, dtype=torch.uint8, device=device)
@@ -282,6 +284,8 @@ class TraceBuffers:
             o.spill_chunks = self.spill_chunks
         if use_order and self.order is not None:
             o.ray_order = self.order.data_ptr()
+        if self.start_cell is not None:
+            o.start_cell = self.start_cell.data_ptr()
         return o
 
 
@@ -295,10 +299,12 @@ def order_rays(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, order: tor
 
 def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: Optional[torch.Tensor],
                bufs: TraceBuffers, kappa: float = 1.0, mode: str = "fp64", max_steps: int = 0,
-               eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, stream=None) -> None:
+               eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, start_given: bool = False,
+               stream=None) -> None:
     """Enqueue one vor_trace into preallocated buffers (no allocation, no
     sync); with ``ordered`` the rays are first put in coherent order by
-    vor_order_rays (buffers made with ordered=True)."""
+    vor_order_rays (buffers made with ordered=True). ``start_given``: the
+    buffers' start cells are those of an earlier call on the same rays."""
     n = origins.shape[0]
     if origins.dtype != torch.float64 or dirs.dtype != torch.float64 or not origins.is_contiguous() \
             or not dirs.is_contiguous() or origins.shape != dirs.shape or n != bufs.N:
@@ -308,8 +314,11 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
     if ordered:
         if bufs.order is None:
             raise ValueError("buffers were made without ordered=True")
-        order_rays(grid, origins, dirs, bufs.order, bufs.order_ws, stream=stream)
-    opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 0)
+        if not start_given:   # the start cells were located in the earlier call's order
+            order_rays(grid, origins, dirs, bufs.order, bufs.order_ws, stream=stream)
+    if start_given and bufs.start_cell is None:
+        raise ValueError("start_given needs buffers made with locate_first=True")
+    opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 1 if start_given else 0)
     out = bufs.struct(use_order=ordered)
     _check(load().vor_trace(grid.handle, _ptr(origins), _ptr(dirs), n, _ptr(density), float(kappa),
                             ctypes.byref(opts), ctypes.byref(out), _stream(stream)), "vor_trace")
@@ -317,30 +326,34 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
 
 def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str = "fp64",
           segments: str = "exact", seg_stride: int = 64, spill_chunks: int = 0, max_steps: int = 0,
-          eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, stream=None) -> dict:
+          eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, locate_first: bool = True,
+          stream=None) -> dict:
     """Paths of N rays. ``segments``: "none" (tau only), "stride" (a window
     of ``seg_stride`` slots per ray; longer paths continue in up to
     ``spill_chunks`` chained spill chunks, or report RAY_OVERFLOW), or
     "exact" (a tau-only counting pass, a scan, then a pass that writes every
-    segment at its CSR offset). Returns a dict of device tensors."""
+    segment at its CSR offset). ``locate_first``: start cells in a pass of
+    their own (vor_trace_out.start_cell) rather than at each ray's start.
+    Returns a dict of device tensors."""
     o = _dev_f64(origins, 3)
     d = _dev_f64(dirs, 3)
     rho = None if density is None else _dev_f64(density).reshape(-1)
     n = o.shape[0]
     kw = dict(kappa=kappa, mode=mode, max_steps=max_steps, eps_mix=eps_mix, persistent=persistent, ordered=ordered,
               stream=stream)
+    lf = dict(ordered=ordered, locate_first=locate_first)
     if segments == "none":
-        b = TraceBuffers(n, ordered=ordered)
+        b = TraceBuffers(n, **lf)
         trace_into(grid, o, d, rho, b, **kw)
     elif segments == "stride":
-        b = TraceBuffers(n, seg_stride=seg_stride, spill_chunks=spill_chunks, ordered=ordered)
+        b = TraceBuffers(n, seg_stride=seg_stride, spill_chunks=spill_chunks, **lf)
         trace_into(grid, o, d, rho, b, **kw)
     elif segments == "exact":
-        b0 = TraceBuffers(n, ordered=ordered)
+        b0 = TraceBuffers(n, **lf)
         trace_into(grid, o, d, rho, b0, **kw)
         off = exclusive_scan(b0.n_seg, stream=stream)
         total = int(off[-1].item())
-        b = TraceBuffers(n, total_segments=max(total, 1), ordered=ordered)
+        b = TraceBuffers(n, total_segments=max(total, 1), **lf)
         b.ray_off = off
         trace_into(grid, o, d, rho, b, **kw)
     else:

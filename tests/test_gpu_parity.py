@@ -150,6 +150,47 @@ def test_ray_order_is_a_permutation_and_changes_nothing(vrt):
         assert np.array_equal(ca, cb) and np.array_equal(la, lb)
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_start_cell_pass_changes_nothing(vrt, cube, persistent):
+    """Start cells located at each ray's start and in a pass of their own
+    (vor_trace_out.start_cell) give identical results, matching the oracle."""
+    import torch
+    w, grid, ref = cube
+    kw = dict(mode="mixed", segments="exact", persistent=persistent, ordered=True)
+    a = vrt.trace(grid, w.origins, w.dirs, w.density, locate_first=False, **kw)
+    b = vrt.trace(grid, w.origins, w.dirs, w.density, locate_first=True, **kw)
+    for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+        assert torch.equal(a[k], b[k]), k
+    st = compare(gpu_paths(b), ref, TOL["mixed"])
+    assert st["clean"] > 0.99 * w.N
+
+
+def test_start_cells_reused_across_calls(vrt):
+    """A point source (one origin for every ray, in coherent order: one
+    cooperative search per wave) plus scattered origins; the start cells of
+    the first call, reused by a second call with another kappa
+    (opts.start_given), give the same paths and tau scaled by kappa."""
+    import torch
+    w = W.flared_disc(M=50_000, N=100_000, seed=31)
+    grid = vrt.build_grid(w.sites, w.box)
+    o = torch.as_tensor(w.origins, device="cuda")
+    d = torch.as_tensor(w.dirs, device="cuda")
+    rho = torch.as_tensor(w.density, device="cuda")
+    ref = vrt.trace(grid, o, d, rho, mode="mixed", segments="none", persistent=True, locate_first=False)
+    b = vrt.TraceBuffers(w.N, ordered=True)
+    vrt.trace_into(grid, o, d, rho, b, mode="mixed", persistent=True, ordered=True)
+    torch.cuda.synchronize()
+    assert torch.equal(b.tau, ref["tau"]) and torch.equal(b.n_seg, ref["n_seg"])
+    assert torch.equal(b.status, ref["status"])
+    tau1 = b.tau.clone()
+    vrt.trace_into(grid, o, d, rho, b, kappa=2.0, mode="mixed", persistent=True, ordered=True, start_given=True)
+    torch.cuda.synchronize()
+    assert torch.equal(b.n_seg, ref["n_seg"])
+    assert torch.equal(b.tau, 2.0 * tau1)      # kappa is a power of two: exact
+    n_src = int((torch.linalg.norm(o, dim=1) == 0).sum())
+    assert n_src > 10_000                       # the point-source half exercises the cooperative search
+
+
 def test_mixed_equals_fp64_bitwise(vrt):
     w = W.exp_disc(M=20_000, N=200_000, seed=77)
     grid = vrt.build_grid(w.sites, w.box)
