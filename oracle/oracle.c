@@ -149,7 +149,8 @@ int oracle_locate(const double *sites, int64_t M, const double *box,
  * together with the start-cell gap of oracle_locate divided by L.
  *
  * Outputs per ray (any may be NULL except nseg): segments at
- * seg_cell/seg_len[ray * cap + i] for i < cap, nseg (true count even past
+ * seg_cell/seg_len[ray * cap + i] for i < cap, with seg_end the position
+ * s* (from the origin) where each segment ends, nseg (true count even past
  * cap), tau, chord = L, status, n_near, min_gap, cell0 = start cell.
  * Returns 0, or 1 on bad arguments.
  */
@@ -157,7 +158,7 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
                  const double *rho, double kappa,
                  const double *origins, const double *dirs, int64_t N,
                  double eta, int64_t cap,
-                 int32_t *seg_cell, double *seg_len,
+                 int32_t *seg_cell, double *seg_len, double *seg_end,
                  int32_t *nseg, double *tau, double *chord, int32_t *status,
                  int32_t *n_near, double *min_gap, int32_t *cell0)
 {
@@ -255,6 +256,7 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
                     if (count < cap && seg_cell) {
                         seg_cell[ray * cap + count] = (int32_t)m;
                         if (seg_len) seg_len[ray * cap + count] = len;
+                        if (seg_end) seg_end[ray * cap + count] = best;
                     }
                     if (rho) t += kappa * rho[m] * len;
                     ++count;

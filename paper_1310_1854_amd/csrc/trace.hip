@@ -256,8 +256,9 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
             continue;
         }
         ++wit;
+        const bool more = live && ray_step<MODE, SEGS>(A.G, A.I, R, S, A.O);
         if (live) {
-            if (!ray_step<MODE, SEGS>(A.G, A.I, R, S, A.O)) {
+            if (!more) {
 #if VRT_DEFER_FINISH
                 pending = true;
 #else

@@ -168,10 +168,11 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
 }
 
 // Mixed-precision exit search. Returns the winning record index (-1: the
-// chord end), with redo set when the step was decided in FP64 (then best is
-// the FP64 crossing); otherwise j1 is the winner's internal index and the
-// caller computes its FP64 crossing from the site (fetched together with the
-// winner's row). Either way the result equals exit_fp64's.
+// chord end, best = L), with redo set when the step was decided in FP64
+// (then best is the FP64 crossing); otherwise j1 is the winner's internal
+// index and the caller computes its FP64 crossing from the site (fetched
+// together with the winner's row). Either way the result equals
+// exit_fp64's.
 //
 // Each plane is ranked in FP32 from its stored offset n = p_j - p_m
 // (rounded once to FP32), the current point q = r - p_m and k (both
@@ -196,48 +197,89 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
 // arithmetic as exit_fp64); otherwise the step is redone in FP64.
 // Records are loaded a whole batch at a time, unconditionally (the record
 // arrays are padded for the last row); entries past the row end are masked.
+// The current point and direction of a ray in FP32, with the constants of
+// the mixed-mode bound (below).
+struct Query32 {
+    float qx, qy, qz, qa;   // q = r - p_m and |q|
+    float kx, ky, kz;
+    float c1, c2, e_abs;    // 1.5 eps, 0.5 eps, FP64 allowance
+};
+
+__device__ __forceinline__ Query32 query32(const double pm[3], const double r0[3], const double k[3], double s_c,
+                                           float eps, float e_abs)
+{
+    double q64[3];
+    for (int a = 0; a < 3; ++a) q64[a] = (r0[a] + s_c * k[a]) - pm[a];
+    Query32 Q;
+    Q.qx = (float)q64[0];
+    Q.qy = (float)q64[1];
+    Q.qz = (float)q64[2];
+    Q.kx = (float)k[0];
+    Q.ky = (float)k[1];
+    Q.kz = (float)k[2];
+    Q.qa = sqrtf(Q.qx * Q.qx + Q.qy * Q.qy + Q.qz * Q.qz);
+    Q.c1 = 1.5f * eps;
+    Q.c2 = 0.5f * eps;
+    Q.e_abs = e_abs;
+    return Q;
+}
+
+// The wall (the chord end L) relative to the current point, and its bound.
+__device__ __forceinline__ void wall32(double L, double s_c, float e_abs, float &tw, float &ew)
+{
+    tw = (float)(L - s_c);
+    ew = 2.0f * 5.9604645e-8f * fabsf(tw) + e_abs;
+}
+
+// FP32 crossing t of one plane and its error bound err (see exit_mixed);
+// pos: the plane is approached and the bound holds; maybe: it may be
+// approached in FP64 (nearly parallel) when pos is false.
+__device__ __forceinline__ void plane_bound32(const Rec32 &r, const Query32 &Q, float &t, float &err, bool &pos,
+                                              bool &maybe)
+{
+    const float u = 5.9604645e-8f;   // 2^-24
+    const float nx = r.nx, ny = r.ny, nz = r.nz;
+    const float den = fmaf(nx, Q.kx, fmaf(ny, Q.ky, nz * Q.kz));
+    const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+    const float nq = fmaf(nx, Q.qx, fmaf(ny, Q.qy, nz * Q.qz));
+    const float num = fmaf(0.5f, nn, -nq);
+    const float n1 = fabsf(nx) + fabsf(ny) + fabsf(nz);
+    const float d = 8.0f * u * n1;
+    pos = den > fmaxf(2.0f * d, 1.17549435e-38f);
+    maybe = den > -d;
+    const float rc = __builtin_amdgcn_rcpf(den);
+    t = num * rc;
+    const float at = fabsf(t);
+    const float sq = Q.qa + at;
+    const float E = fmaf(Q.c2 * sq, sq, fmaf(Q.c1, nn, Q.e_abs * n1));
+    err = fmaf(E, rc, 6.0f * u * at);
+}
+
 __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const Rec32 *__restrict__ rec32, int2 rw,
                                           const double pm[3], const double r0[3], const double k[3], double L,
                                           double s_c, float eps, float e_abs, double &best, bool &redo, int32_t &j1)
 {
-    double q64[3];
-    for (int a = 0; a < 3; ++a) q64[a] = (r0[a] + s_c * k[a]) - pm[a];
-    const float qx = (float)q64[0], qy = (float)q64[1], qz = (float)q64[2];
-    const float kx = (float)k[0], ky = (float)k[1], kz = (float)k[2];
-    const float qa = sqrtf(qx * qx + qy * qy + qz * qz);
-    const float u = 5.9604645e-8f;   // 2^-24
-    const float c1 = 1.5f * eps, c2 = 0.5f * eps, cd = 8.0f * u, ct = 6.0f * u;
+    const Query32 Q = query32(pm, r0, k, s_c, eps, e_abs);
     const float inf = __builtin_huge_valf();
-    const float tw = (float)(L - s_c);   // the wall, relative to the current point
-    const float ew = 2.0f * u * fabsf(tw) + e_abs;
+    float tw, ew;
+    wall32(L, s_c, e_abs, tw, ew);
     float t1 = tw, hi1 = tw + ew;       // best estimate and its upper bound
     int e1 = -1;
     float lo_a = tw - ew, lo_b = inf;   // two smallest lower bounds
     int ia = -1;
     const int end = rw.x + rw.y;
     for (int e0 = rw.x; e0 < end; e0 += kBatch32) {
-        VRT_DIAG_COUNT(0);
         Rec32 r[kBatch32];
 #pragma unroll
         for (int v = 0; v < kBatch32; ++v) r[v] = rec32[e0 + v];   // past the row end: padding or the next row, masked
 #pragma unroll
         for (int v = 0; v < kBatch32; ++v) {
             const bool in = e0 + v < end;
-            const float nx = r[v].nx, ny = r[v].ny, nz = r[v].nz;
-            const float den = fmaf(nx, kx, fmaf(ny, ky, nz * kz));
-            const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-            const float nq = fmaf(nx, qx, fmaf(ny, qy, nz * qz));
-            const float num = fmaf(0.5f, nn, -nq);
-            const float n1 = fabsf(nx) + fabsf(ny) + fabsf(nz);
-            const float d = cd * n1;
-            const bool pos = in && den > fmaxf(2.0f * d, 1.17549435e-38f);
-            const bool maybe = in && den > -d;
-            const float rc = __builtin_amdgcn_rcpf(den);
-            const float t = num * rc;
-            const float at = fabsf(t);
-            const float sq = qa + at;
-            const float E = fmaf(c2 * sq, sq, fmaf(c1, nn, e_abs * n1));
-            const float err = fmaf(E, rc, ct * at);
+            float t, err;
+            bool pos, maybe;
+            plane_bound32(r[v], Q, t, err, pos, maybe);
+            pos = pos && in;
+            maybe = maybe && in;
             const float lo = pos ? t - err : (maybe ? -inf : inf);
             // branch-free updates of the winner and of the two smallest lower bounds
             const bool w = pos && t < t1;
@@ -339,8 +381,6 @@ __device__ __forceinline__ void ray_begin_at(const GridRef &G, RayState &R, int3
     R.rw = G.rows[m];
 }
 
-// One exit-point step (Sect. 2.2). Returns false once the path has ended.
-// The next cell's row is fetched in the same round trip as its site.
 // Slot of segment idx of the ray: its window, else its current spill chunk;
 // null when the spill is exhausted or absent.
 __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState &R, int64_t idx, bool &spill)
@@ -442,8 +482,9 @@ __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState 
 #endif
 }
 
-template <int MODE, bool SEGS>
-__device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, const SegOut &O)
+// First part of a step: false once the path has ended (at the wall, or at
+// the step limit, which sets the status).
+__device__ __forceinline__ bool ray_step_begin(const GridRef &G, RayState &R, RayStats &S)
 {
     if (!(R.L > 0.0)) return false;
     if (S.steps > G.max_steps) {
@@ -451,15 +492,25 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
         return false;
     }
     ++S.steps;
-    const int2 rw = R.rw;
-    S.recs += rw.y;
-    double best;
+    S.recs += R.rw.y;
+    return true;
+}
+
+// Rest of a step, given the exit search's result: record index win (-1: the
+// chord end), best = the FP64 crossing when redo (or when win < 0), else the
+// winner's internal index j1 (its FP64 crossing is computed here from the
+// site, fetched with the winner's row). Emits the segment, accumulates tau,
+// moves to the next cell; the no-exit fallback of Sect. 2.2 when the current
+// point lies beyond a plane of the cell. Returns false once the path ended.
+template <int MODE, bool SEGS>
+__device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, RayState &R, RayStats &S,
+                                             const SegOut &O, int win, double best, bool redo, int32_t j1)
+{
     int32_t wj = -1, wuid = 0;
     double wx = 0.0, wy = 0.0, wz = 0.0;
     int2 wrow = make_int2(0, 0);
-    if (MODE == VOR_MODE_FP64) {
-        int win = exit_fp64(G.rec64, rw, R.pm, R.r0, R.k, R.L, best);
-        if (win >= 0) {
+    if (win >= 0) {
+        if (MODE == VOR_MODE_FP64 || redo) {
             const Rec64 w = G.rec64[win];
             wj = w.j;
             wuid = w.uid;
@@ -467,32 +518,16 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
             wy = w.y;
             wz = w.z;
             wrow = G.rows[wj];
-        }
-    } else {
-        bool redo;
-        int32_t j1 = -1;
-        int win = exit_mixed(G.rec64, G.rec32, rw, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs, best, redo, j1);
-        S.nredo += redo ? 1 : 0;
-        if (win >= 0) {
-            if (redo) {
-                const Rec64 w = G.rec64[win];
-                wj = w.j;
-                wuid = w.uid;
-                wx = w.x;
-                wy = w.y;
-                wz = w.z;
-                wrow = G.rows[wj];
-            } else {
-                wj = j1;
-                const Site w = G.sites[wj];
-                wrow = G.rows[wj];
-                wuid = (int32_t)w.uid;
-                wx = w.x;
-                wy = w.y;
-                wz = w.z;
-                double den;
-                best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
-            }
+        } else {
+            wj = j1;
+            const Site w = G.sites[wj];
+            wrow = G.rows[wj];
+            wuid = (int32_t)w.uid;
+            wx = w.x;
+            wy = w.y;
+            wz = w.z;
+            double den;
+            best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
         }
     }
     double len = best - R.s_c;
@@ -529,6 +564,25 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
     R.pm[2] = wz;
     R.rw = wrow;
     return true;
+}
+
+// One exit-point step (Sect. 2.2) with the exit search done by this lane
+// alone. Returns false once the path has ended.
+template <int MODE, bool SEGS>
+__device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, const SegOut &O)
+{
+    if (!ray_step_begin(G, R, S)) return false;
+    double best;
+    bool redo = false;
+    int32_t j1 = -1;
+    int win;
+    if (MODE == VOR_MODE_FP64) {
+        win = exit_fp64(G.rec64, R.rw, R.pm, R.r0, R.k, R.L, best);
+    } else {
+        win = exit_mixed(G.rec64, G.rec32, R.rw, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs, best, redo, j1);
+        S.nredo += redo ? 1 : 0;
+    }
+    return ray_step_end<MODE, SEGS>(G, I, R, S, O, win, best, redo, j1);
 }
 
 }  // namespace vrt

@@ -191,6 +191,35 @@ def test_start_cells_reused_across_calls(vrt):
     assert n_src > 10_000                       # the point-source half exercises the cooperative search
 
 
+def test_long_rows_rank_per_lane(vrt):
+    """Rows too long for one wave's cooperative ranking (a central cell with
+    ~200 faces, every ray starting in it) are ranked per lane; the results
+    still equal FP64's and the oracle's."""
+    import torch
+    rng = np.random.default_rng(41)
+    u = rng.normal(size=(200, 3))
+    shell = 0.5 * u / np.linalg.norm(u, axis=1)[:, None]
+    bg = W.uniform_in_box(rng, 3000, [-1, -1, -1, 1, 1, 1])
+    bg = bg[np.linalg.norm(bg, axis=1) > 0.65]
+    sites = np.concatenate([[[0.0, 0.0, 0.0]], shell, bg])
+    box = [-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]
+    grid = vrt.build_grid(sites, box)
+    assert grid.info()["max_row"] >= 150
+    n = 4096
+    o = np.tile([[1e-3, -2e-3, 5e-4]], (n, 1))
+    d = W.isotropic_dirs(rng, n)
+    rho = rng.uniform(0.5, 2.0, len(sites))
+    a = vrt.trace(grid, o, d, rho, mode="mixed", segments="exact", persistent=True, ordered=True)
+    b = vrt.trace(grid, o, d, rho, mode="fp64", segments="exact")
+    for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+        assert torch.equal(a[k], b[k]), k
+    ref = oracle.trace(sites, box, rho, o[:512], d[:512], cap=64)
+    p = gpu_paths(a)
+    st = compare(p, ref, TOL["mixed"])      # the first 512 rays
+    assert st["clean"] > 0.99 * 512
+    assert int(p["seg_cell"][int(p["ray_off"][0])]) == 0     # every path starts in the central cell
+
+
 def test_mixed_equals_fp64_bitwise(vrt):
     w = W.exp_disc(M=20_000, N=200_000, seed=77)
     grid = vrt.build_grid(w.sites, w.box)
