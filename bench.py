@@ -86,10 +86,14 @@ WORKLOADS = {
     "clumpy": dict(cfg=3, mode="mixed", stride=128, spill_chunks_per_ray=1.0, ordered=True, persistent=True,
                    cpu_rays=60),
     "uniform_cube": dict(cfg=0, mode="fp64", stride=64, spill_chunks_per_ray=0.25, ordered=True, cpu_rays=10000),
+    # the same disc with transport: each ray stops where tau reaches -ln u (seeded u), and both per-cell
+    # tallies are deposited; kappa = 1e-3 puts the mean optical depth of the full paths near 0.9
+    "flared_disc_transport": dict(cfg=2, mode="mixed", stride=128, spill_chunks_per_ray=0.5, ordered=True,
+                                  persistent=True, cpu_rays=240, transport=True, kappa=1e-3),
 }
 
 
-def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str) -> float:
+def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str, transport: bool = False) -> float:
     """Bytes the method must move for one launch, from the kernel counters
     c = [segments, fallbacks, fp64 re-decisions, steps, records, ...].
     Per step: the row range (8 B) and, per neighbour record read, its index
@@ -97,10 +101,13 @@ def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str) -> float:
     winner's FP64 site, 24 B, and the FP64 records of re-decided steps).
     Per segment: the cell density (8 B) and the output (4 B cell + 8 B
     length). Per ray: origin and direction (48 B), tau, count and status
-    (13 B)."""
+    (13 B). With transport, per segment two tally updates (read and write
+    8 B each) and per ray tau_stop, the interaction cell and distance (20 B)."""
     seg, redo, steps, recs = float(c[0]), float(c[2]), float(c[3]), float(c[4])
     per_step_recs = recs / max(steps, 1.0)
     b = 8.0 * steps + 20.0 * seg + 61.0 * n_rays
+    if transport:
+        b += 32.0 * seg + 20.0 * n_rays
     if mode == "fp64":
         b += 28.0 * recs
     else:
@@ -110,7 +117,22 @@ def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str) -> float:
 
 def make_buffers(vrt, N, spec, torch, chunks=None):
     chunks = int(N * spec["spill_chunks_per_ray"]) + 1 if chunks is None else int(chunks)
-    return vrt.TraceBuffers(N, seg_stride=spec["stride"], spill_chunks=chunks, ordered=spec.get("ordered", False))
+    b = vrt.TraceBuffers(N, seg_stride=spec["stride"], spill_chunks=chunks, ordered=spec.get("ordered", False),
+                         stops=spec.get("transport", False))
+    b.transport = None
+    return b
+
+
+def add_transport(bufs, spec, torch, M, seed=20131854 + 77):
+    """Transport inputs and outputs of a workload with transport: tau_stop =
+    -ln u per ray (seeded), zeroed per-cell tallies."""
+    if not spec.get("transport"):
+        return
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    u = torch.rand(bufs.N, generator=g, dtype=torch.float64)
+    bufs.transport = dict(tau_stop=(-torch.log1p(-u)).to("cuda"),
+                          tally_len=torch.zeros(M, dtype=torch.float64, device="cuda"),
+                          tally_abs=torch.zeros(M, dtype=torch.float64, device="cuda"))
 
 
 def prepare_buffers(vrt, torch, grid, o, d, rho, spec, mode=None):
@@ -122,6 +144,7 @@ def prepare_buffers(vrt, torch, grid, o, d, rho, spec, mode=None):
     chunks = int(N * spec["spill_chunks_per_ray"]) + 1
     while True:
         bufs = make_buffers(vrt, N, spec, torch, chunks)
+        add_transport(bufs, spec, torch, grid.M)
         step(vrt, grid, o, d, rho, bufs, spec, mode)
         torch.cuda.synchronize()
         asked = int(bufs.work[1].item())
@@ -141,9 +164,10 @@ def step(vrt, grid, o, d, rho, bufs, spec, mode, reuse_order=False):
         vrt.order_rays(grid, o, d, bufs.order, bufs.order_ws)
     opts = vrt.TraceOpts(vrt.MODES[mode], 0, 0.0, 1 if spec.get("persistent", False) else 0,
                          1 if reuse_order else 0)
-    out = bufs.struct(use_order=ordered)
-    rc = vrt.load().vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(d), o.shape[0], vrt._ptr(rho), 1.0,
-                              vrt.ctypes.byref(opts), vrt.ctypes.byref(out), vrt._stream())
+    out = bufs.struct(use_order=ordered, **(getattr(bufs, "transport", None) or {}))
+    rc = vrt.load().vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(d), o.shape[0], vrt._ptr(rho),
+                              float(spec.get("kappa", 1.0)), vrt.ctypes.byref(opts), vrt.ctypes.byref(out),
+                              vrt._stream())
     if rc != vrt.VOR_OK:
         raise vrt.VorError(rc, "vor_trace")
 
@@ -339,7 +363,7 @@ def main(argv=None):
                      reuse_order=True)
     kc = bufs.counters.cpu().numpy().astype(np.float64) / args.roofline_reps
     k_avg = float(np.mean(k_ms))
-    alg = algorithmic_bytes(kc, w.N, mode)
+    alg = algorithmic_bytes(kc, w.N, mode, bool(spec.get("transport")))
     achieved = alg / (k_avg / 1e3) / 1e9
     recs_per_step = kc[4] / max(kc[3], 1)
 
@@ -414,9 +438,42 @@ def main(argv=None):
         result["accuracy"] = {"oracle_sample_rays": int(sub.N), "near_tie_rays": int((ref["n_near"] > 0).sum()),
                               "cell_sequence_mismatches": mism, "max_len_err_rel_chord": max_dl,
                               "max_tau_err_rel": max_dt}
+        if spec.get("transport"):
+            from oracle import transport as T
+            idx = np.asarray(sub.meta["ray_index"])
+            ts = bufs.transport["tau_stop"].cpu().numpy()[idx]
+            it = T.interactions(ref, w.density, float(spec["kappa"]), ts)
+            g_cell = bufs.stop_cell.cpu().numpy()[idx]
+            g_s = bufs.stop_s.cpu().numpy()[idx]
+            clean = (ref["n_near"] == 0) & (ref["status"] == 0)
+            result["accuracy"]["stop_cell_mismatches"] = int((g_cell != it["cell"])[clean].sum())
+            result["accuracy"]["max_stop_s_err_rel_chord"] = float(
+                np.max(np.abs(g_s - it["s"])[clean] / ref["chord"][clean])) if clean.any() else 0.0
+    if spec.get("transport"):
+        result["transport"] = transport_check(vrt, torch, grid, o, d, rho, bufs, spec, mode)
     print(json.dumps(result), flush=True)
     if args.copy_calibration:
         copy_calibration(torch)
+
+
+def transport_check(vrt, torch, grid, o, d, rho, bufs, spec, mode):
+    """One more launch with zeroed tallies: the fraction of packages that
+    interact, the absorbed luminosity of all paths against its closed form
+    (the sum of 1 - exp(-tau) over the cut paths) and the path-length tally
+    against the summed path lengths."""
+    tr = bufs.transport
+    tr["tally_len"].zero_()
+    tr["tally_abs"].zero_()
+    step(vrt, grid, o, d, rho, bufs, spec, mode)
+    torch.cuda.synchronize()
+    ok = bufs.status == 0
+    want = float((-torch.expm1(-bufs.tau))[ok].sum())
+    got = float(tr["tally_abs"].sum())
+    path = float(bufs.stop_s[ok].sum())     # length of every (cut) path: the path-length tally's total
+    tl = float(tr["tally_len"].sum())
+    return {"kappa": spec["kappa"], "interacting_fraction": float((bufs.stop_cell[ok] >= 0).double().mean()),
+            "absorbed_total": got, "absorbed_closed_form": want, "absorbed_rel_err": abs(got - want) / want,
+            "tally_len_total": tl, "path_length_total": path, "tally_len_rel_err": abs(tl - path) / path}
 
 
 def copy_calibration(torch, mib: int = 512, reps: int = 3):

@@ -184,6 +184,23 @@ typedef struct {
                                in a pass of their own before the traversal (faster, mostly with the
                                persistent kernel) and left here (internal cell indices, -1 for rays
                                without a path) for reuse through opts.start_given */
+    /* Transport along the paths (optional; the photon-package transport that the paths serve, Sect. 3.4).
+     * Interaction points: with tau_k the optical depth after the k-th segment (summed as above), a path
+     * stops in the first cell m_k with kappa rho_m > 0 and tau_k >= tau_stop[i], at distance
+     * s_{k-1} + (tau_stop - tau_{k-1}) / (kappa rho_m) from the origin; its last segment is cut there,
+     * tau and n_seg describe the cut path. tau_stop <= 0 stops at the origin, in the start cell, before
+     * any segment. Tallies: per cell (user order), accumulated over the calls (never zeroed here),
+     *   tally_len[m] += w l,   tally_abs[m] += w exp(-tau before the segment) (1 - exp(-kappa rho_m l))
+     * for every segment (m, l) of the (cut) path, w = weight[i] or 1; the absorbed fractions of one path
+     * sum to w (1 - exp(-tau)). Floating-point atomics: the order of the sums is not fixed. */
+    const double *tau_stop; /* [N] or NULL: the optical depth at which each path stops (e.g. -ln u) */
+    int32_t *stop_cell;     /* [N], required with tau_stop: cell of the interaction point (user index),
+                               -1 when the path reaches the wall first or has no path */
+    double *stop_s;         /* [N] or NULL, with tau_stop only: distance of the interaction point from the
+                               origin; the chord L when the path reached the wall */
+    double *tally_len;      /* [M] or NULL */
+    double *tally_abs;      /* [M] or NULL */
+    const double *weight;   /* [N] or NULL (weights 1); only with a tally */
 } vor_trace_out;
 
 /*

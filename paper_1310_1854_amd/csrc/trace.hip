@@ -30,6 +30,7 @@ struct TraceArgs {
     unsigned long long *counters;
     int64_t *work;        // [0] persistent queue head, [1] spill chunks asked for, [2] rays past their window
     int32_t *start;       // start cell (internal) of every ray from k_start_cells, or null: located at ray start
+    Extras X;             // interaction points and tallies (kernels with EXT only)
 };
 
 #ifndef VRT_REFILL_MIN
@@ -74,9 +75,10 @@ __device__ __forceinline__ void ray_window(const TraceArgs &A, int64_t ray, RayS
 }
 
 // Results of a finished ray.
-template <bool SEGS>
+template <bool SEGS, bool EXT>
 __device__ __forceinline__ void ray_finish(const TraceArgs &A, int64_t ray, RayState &R, const RayStats &S)
 {
+    if (EXT) ray_extras_finish(A.X, ray, R);
     if (SEGS) finish_segments(A.O, R, S.cnt);
     if (SEGS && S.cnt > R.cap) {
         if (A.work) atomicAdd((unsigned long long *)&A.work[2], 1ull);
@@ -105,6 +107,7 @@ __device__ __forceinline__ void flush_counters(const TraceArgs &A, const RayStat
     }
 }
 
+template <bool EXT>
 __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RayState &R)
 {
     R.st = ray_setup(A.G, A.I, ray, R.r0, R.k, R.L);
@@ -115,6 +118,7 @@ __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RaySt
     } else {
         R.L = 0.0;
     }
+    if (EXT) ray_extras_begin(A.X, ray, R);
 }
 
 // nearest_site for a point shared by the whole wave: the sites of each
@@ -185,7 +189,7 @@ __global__ void __launch_bounds__(256) k_start_cells(TraceArgs A)
 }
 
 // One ray per lane.
-template <int MODE, bool SEGS>
+template <int MODE, bool SEGS, bool EXT>
 __global__ void __launch_bounds__(256) VRT_OCC k_trace(TraceArgs A)
 {
     const int64_t lane_ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -194,10 +198,10 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace(TraceArgs A)
         const int64_t ray = A.order ? (int64_t)A.order[lane_ray] : lane_ray;
         RayState R;
         ray_window<SEGS>(A, ray, R);
-        ray_start(A, ray, R);
-        while (ray_step<MODE, SEGS>(A.G, A.I, R, S, A.O)) {
+        ray_start<EXT>(A, ray, R);
+        while (ray_step<MODE, SEGS, EXT>(A.G, A.I, R, S, A.O, A.X)) {
         }
-        ray_finish<SEGS>(A, ray, R, S);
+        ray_finish<SEGS, EXT>(A, ray, R, S);
     }
     flush_counters(A, S);
 }
@@ -207,7 +211,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace(TraceArgs A)
 // none is busy); then they take the next rays from the work queue together
 // (one atomic per wave, ranks from the ballot) and start them side by side,
 // so the start-cell searches of the refilled lanes overlap.
-template <int MODE, bool SEGS>
+template <int MODE, bool SEGS, bool EXT>
 __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
 {
     const int lane = threadIdx.x & 63;
@@ -228,7 +232,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
             ++wref;
 #if VRT_DEFER_FINISH
             if (pending) {   // the ended rays of the wave write their results together
-                ray_finish<SEGS>(A, ray, R, S);
+                ray_finish<SEGS, EXT>(A, ray, R, S);
                 pending = false;
             }
 #endif
@@ -243,7 +247,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
                     ray = A.order ? (int64_t)A.order[q] : q;
                     S = RayStats();
                     ray_window<SEGS>(A, ray, R);
-                    ray_start(A, ray, R);
+                    ray_start<EXT>(A, ray, R);
                     live = true;
                 } else {
                     ray = -1;
@@ -256,13 +260,13 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
             continue;
         }
         ++wit;
-        const bool more = live && ray_step<MODE, SEGS>(A.G, A.I, R, S, A.O);
+        const bool more = live && ray_step<MODE, SEGS, EXT>(A.G, A.I, R, S, A.O, A.X);
         if (live) {
             if (!more) {
 #if VRT_DEFER_FINISH
                 pending = true;
 #else
-                ray_finish<SEGS>(A, ray, R, S);
+                ray_finish<SEGS, EXT>(A, ray, R, S);
 #endif
                 T.cnt += S.cnt;
                 T.nfb += S.nfb;
@@ -274,7 +278,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
         }
     }
 #if VRT_DEFER_FINISH
-    if (pending) ray_finish<SEGS>(A, ray, R, S);
+    if (pending) ray_finish<SEGS, EXT>(A, ray, R, S);
 #endif
     flush_counters(A, T);
     if (A.counters && (threadIdx.x & 63) == 0) {
@@ -349,6 +353,37 @@ extern "C" vor_status vor_locate(const vor_grid *G, const double *pts, int64_t N
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
+// Launch of the trace kernel: one ray per lane, or persistent waves (as
+// many blocks as fit on the device at once).
+template <int MODE, bool SEGS, bool EXT>
+vor_status launch_trace_ext(const TraceArgs &A, bool persistent, hipStream_t st)
+{
+    const int T = 256;
+    if (persistent) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return VOR_EDEVICE;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_persistent<MODE, SEGS, EXT>, T, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        const int64_t blocks = std::min<int64_t>((int64_t)cus * per_cu, (A.N + T - 1) / T);
+        hipLaunchKernelGGL((k_trace_persistent<MODE, SEGS, EXT>), dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                           dim3(T), 0, st, A);
+    } else {
+        hipLaunchKernelGGL((k_trace<MODE, SEGS, EXT>), dim3((unsigned)((A.N + T - 1) / T)), dim3(T), 0, st, A);
+    }
+    return VOR_OK;
+}
+
+template <int MODE, bool SEGS>
+vor_status launch_trace(const TraceArgs &A, bool ext, bool persistent, hipStream_t st)
+{
+    return ext ? launch_trace_ext<MODE, SEGS, true>(A, persistent, st)
+               : launch_trace_ext<MODE, SEGS, false>(A, persistent, st);
+}
+
 extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const double *dirs, int64_t N,
                                 const double *density, double kappa, const vor_trace_opts *opts,
                                 const vor_trace_out *out, void *stream)
@@ -372,6 +407,9 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     const bool persistent = opts && opts->persistent;
     if (persistent && !out->work) return VOR_EINVAL;
     if (opts && opts->start_given && !out->start_cell) return VOR_EINVAL;
+    if (!out->tau_stop != !out->stop_cell) return VOR_EINVAL;   // interaction points: input and cell output together
+    if (out->stop_s && !out->tau_stop) return VOR_EINVAL;
+    if (out->weight && !out->tally_len && !out->tally_abs) return VOR_EINVAL;
     const Grid &g = vrt_grid_of(G);
     if (mode == VOR_MODE_MIXED && !mixed_mode_fits(g)) return VOR_EINVAL;
     TraceArgs A;
@@ -400,6 +438,12 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     A.O.spill_chunks = out->spill_chunks;
     A.O.chunk_head = out->work ? (unsigned long long *)&out->work[1] : nullptr;
     A.start = out->start_cell;
+    A.X.tau_stop = out->tau_stop;
+    A.X.weight = out->weight;
+    A.X.tally_len = out->tally_len;
+    A.X.tally_abs = out->tally_abs;
+    A.X.stop_cell = out->stop_cell;
+    A.X.stop_s = out->stop_s;
     hipStream_t st = (hipStream_t)stream;
     const int T = 256;
     if (A.work) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, A.work, 4);
@@ -409,39 +453,13 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
         int64_t nb = std::min<int64_t>((N + T - 1) / T, 65535);
         hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)nb), dim3(T), 0, st, A.O.spill_first, N, (int64_t)-1);
     }
-    dim3 block(T);
-    if (persistent) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return VOR_EDEVICE;
-        hipError_t e;
-        if (mode == VOR_MODE_FP64)
-            e = segs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_persistent<VOR_MODE_FP64, true>, T, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_persistent<VOR_MODE_FP64, false>, T, 0);
-        else
-            e = segs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_persistent<VOR_MODE_MIXED, true>, T, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_persistent<VOR_MODE_MIXED, false>, T, 0);
-        if (e != hipSuccess || per_cu < 1) per_cu = 1;
-        int64_t blocks = std::min<int64_t>((int64_t)cus * per_cu, (N + T - 1) / T);
-        dim3 grid((unsigned)std::max<int64_t>(blocks, 1));
-        if (mode == VOR_MODE_FP64) {
-            if (segs) hipLaunchKernelGGL((k_trace_persistent<VOR_MODE_FP64, true>), grid, block, 0, st, A);
-            else hipLaunchKernelGGL((k_trace_persistent<VOR_MODE_FP64, false>), grid, block, 0, st, A);
-        } else {
-            if (segs) hipLaunchKernelGGL((k_trace_persistent<VOR_MODE_MIXED, true>), grid, block, 0, st, A);
-            else hipLaunchKernelGGL((k_trace_persistent<VOR_MODE_MIXED, false>), grid, block, 0, st, A);
-        }
-    } else {
-        dim3 grid((unsigned)((N + T - 1) / T));
-        if (mode == VOR_MODE_FP64) {
-            if (segs) hipLaunchKernelGGL((k_trace<VOR_MODE_FP64, true>), grid, block, 0, st, A);
-            else hipLaunchKernelGGL((k_trace<VOR_MODE_FP64, false>), grid, block, 0, st, A);
-        } else {
-            if (segs) hipLaunchKernelGGL((k_trace<VOR_MODE_MIXED, true>), grid, block, 0, st, A);
-            else hipLaunchKernelGGL((k_trace<VOR_MODE_MIXED, false>), grid, block, 0, st, A);
-        }
-    }
+    const bool ext = A.X.tau_stop || A.X.tally_len || A.X.tally_abs;
+    const vor_status rc = mode == VOR_MODE_FP64
+                              ? (segs ? launch_trace<VOR_MODE_FP64, true>(A, ext, persistent, st)
+                                      : launch_trace<VOR_MODE_FP64, false>(A, ext, persistent, st))
+                              : (segs ? launch_trace<VOR_MODE_MIXED, true>(A, ext, persistent, st)
+                                      : launch_trace<VOR_MODE_MIXED, false>(A, ext, persistent, st));
+    if (rc != VOR_OK) return rc;
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 

@@ -71,6 +71,25 @@ inline bool mixed_mode_fits(const Grid &g)
     return true;
 }
 
+// Optional transport outputs of a trace; all null when unused.
+//   tau_stop  [N] the optical depth at which each path stops (the package
+//             interacts there), or null for paths to the wall;
+//   stop_cell [N] cell (user index) of the interaction point, -1 if the
+//             path reached the wall first;  stop_s [N] its distance from the
+//             origin (the chord L on escape), may be null;
+//   tally_len, tally_abs [M] (user order, accumulated): w * length and
+//             w * exp(-tau before) * (1 - exp(-kappa rho length)) per cell
+//             along each path (cut at the interaction point);
+//   weight    [N] w of each ray, or null (1).
+struct Extras {
+    const double *tau_stop;
+    const double *weight;
+    double *tally_len;
+    double *tally_abs;
+    int32_t *stop_cell;
+    double *stop_s;
+};
+
 inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
 {
     GridRef G;
@@ -350,6 +369,8 @@ struct RayState {
 #endif
     int32_t m, uid;
     uint8_t st;
+    double tstop, wgt, stop_s;   // transport outputs (kernels with Extras only)
+    int32_t stop_uid;            // cell of the interaction point, -1 none yet
 };
 
 __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R)
@@ -502,9 +523,38 @@ __device__ __forceinline__ bool ray_step_begin(const GridRef &G, RayState &R, Ra
 // site, fetched with the winner's row). Emits the segment, accumulates tau,
 // moves to the next cell; the no-exit fallback of Sect. 2.2 when the current
 // point lies beyond a plane of the cell. Returns false once the path ended.
-template <int MODE, bool SEGS>
+// Tallies of a segment of length l in the current cell (kr = kappa rho),
+// with R.tau the optical depth before it.
+__device__ __forceinline__ void deposit(const Extras &X, const RayState &R, double l, double kr)
+{
+    if (X.tally_len) atomicAdd(&X.tally_len[R.uid], R.wgt * l);
+    if (X.tally_abs) atomicAdd(&X.tally_abs[R.uid], R.wgt * exp(-R.tau) * -expm1(-(kr * l)));
+}
+
+// Transport set-up of a ray that has started (status known, start cell set).
+__device__ __forceinline__ void ray_extras_begin(const Extras &X, int64_t ray, RayState &R)
+{
+    R.tstop = X.tau_stop ? X.tau_stop[ray] : 0.0;
+    R.wgt = X.weight ? X.weight[ray] : 1.0;
+    R.stop_uid = -1;
+    R.stop_s = 0.0;
+    if (X.tau_stop && R.st == RAY_OK && R.tstop <= 0.0) {   // used up at the origin: no segment
+        R.stop_uid = R.uid;
+        R.L = 0.0;
+    }
+}
+
+__device__ __forceinline__ void ray_extras_finish(const Extras &X, int64_t ray, const RayState &R)
+{
+    if (!X.tau_stop) return;
+    X.stop_cell[ray] = R.stop_uid;
+    if (X.stop_s) X.stop_s[ray] = R.stop_uid >= 0 ? R.stop_s : R.L;
+}
+
+template <int MODE, bool SEGS, bool EXT = false>
 __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, RayState &R, RayStats &S,
-                                             const SegOut &O, int win, double best, bool redo, int32_t j1)
+                                             const SegOut &O, int win, double best, bool redo, int32_t j1,
+                                             const Extras &X)
 {
     int32_t wj = -1, wuid = 0;
     double wx = 0.0, wy = 0.0, wz = 0.0;
@@ -532,6 +582,23 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
     }
     double len = best - R.s_c;
     if (len > 0.0) {
+        if (EXT) {
+            const double kr = I.density ? I.kappa * I.density[R.uid] : 0.0;
+            if (X.tau_stop) {
+                const double tn = R.tau + kr * len;
+                if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
+                    const double lp = (R.tstop - R.tau) / kr;
+                    if (SEGS) store_segment(O, R, S.cnt, R.uid, lp);
+                    deposit(X, R, lp, kr);
+                    R.tau = R.tau + kr * lp;
+                    ++S.cnt;
+                    R.stop_uid = R.uid;
+                    R.stop_s = R.s_c + lp;
+                    return false;
+                }
+            }
+            deposit(X, R, len, kr);
+        }
         if (SEGS) store_segment(O, R, S.cnt, R.uid, len);
         if (I.density) R.tau += I.kappa * I.density[R.uid] * len;
         ++S.cnt;
@@ -568,8 +635,9 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
 
 // One exit-point step (Sect. 2.2) with the exit search done by this lane
 // alone. Returns false once the path has ended.
-template <int MODE, bool SEGS>
-__device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, const SegOut &O)
+template <int MODE, bool SEGS, bool EXT = false>
+__device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, const SegOut &O,
+                                         const Extras &X = Extras{})
 {
     if (!ray_step_begin(G, R, S)) return false;
     double best;
@@ -582,7 +650,7 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
         win = exit_mixed(G.rec64, G.rec32, R.rw, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs, best, redo, j1);
         S.nredo += redo ? 1 : 0;
     }
-    return ray_step_end<MODE, SEGS>(G, I, R, S, O, win, best, redo, j1);
+    return ray_step_end<MODE, SEGS, EXT>(G, I, R, S, O, win, best, redo, j1, X);
 }
 
 }  // namespace vrt

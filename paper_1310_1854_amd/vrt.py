@@ -59,7 +59,9 @@ class TraceOut(ctypes.Structure):
                 ("seg_stride", ctypes.c_int64), ("ray_off", ctypes.c_void_p), ("counters", ctypes.c_void_p),
                 ("work", ctypes.c_void_p), ("spill_first", ctypes.c_void_p), ("spill_next", ctypes.c_void_p),
                 ("spill_cell", ctypes.c_void_p), ("spill_len", ctypes.c_void_p), ("spill_chunks", ctypes.c_int64),
-                ("ray_order", ctypes.c_void_p), ("start_cell", ctypes.c_void_p)]
+                ("ray_order", ctypes.c_void_p), ("start_cell", ctypes.c_void_p),
+                ("tau_stop", ctypes.c_void_p), ("stop_cell", ctypes.c_void_p), ("stop_s", ctypes.c_void_p),
+                ("tally_len", ctypes.c_void_p), ("tally_abs", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
 
 
 SPILL_CHUNK = 64
@@ -234,8 +236,11 @@ class TraceBuffers:
     ordered: also hold a processing order (vor_order_rays) and its workspace."""
 
     def __init__(self, N: int, seg_stride: int = 0, total_segments: int = 0, spill_chunks: int = 0,
-                 device="cuda", counters=True, ordered=False, locate_first=True):
+                 device="cuda", counters=True, ordered=False, locate_first=True, stops=False):
         self.N = N
+        # interaction points (vor_trace_out.stop_cell / stop_s), filled when a trace is given tau_stop
+        self.stop_cell = torch.empty(max(N, 1), dtype=torch.int32, device=device) if stops else None
+        self.stop_s = torch.empty(max(N, 1), dtype=torch.float64, device=device) if stops else None
         # scratch for the start-cell pass (vor_trace_out.start_cell)
         self.start_cell = torch.empty(max(N, 1), dtype=torch.int32, device=device) if locate_first else None
         self.tau = torch.empty(N, dtype=torch.float64, device=device)
@@ -264,8 +269,18 @@ class TraceBuffers:
             self.order = torch.empty(max(N, 1), dtype=torch.int32, device=device)
             self.order_ws = torch.empty(int(load().vor_order_workspace_bytes(N)), dtype=torch.uint8, device=device)
 
-    def struct(self, use_order: bool = False) -> TraceOut:
+    def struct(self, use_order: bool = False, tau_stop=None, tally_len=None, tally_abs=None,
+               weight=None) -> TraceOut:
         o = TraceOut()
+        if tau_stop is not None:
+            if self.stop_cell is None:
+                raise ValueError("buffers were made without stops=True")
+            o.tau_stop = tau_stop.data_ptr()
+            o.stop_cell = self.stop_cell.data_ptr()
+            o.stop_s = self.stop_s.data_ptr()
+        o.tally_len = tally_len.data_ptr() if tally_len is not None else None
+        o.tally_abs = tally_abs.data_ptr() if tally_abs is not None else None
+        o.weight = weight.data_ptr() if weight is not None else None
         o.tau = self.tau.data_ptr()
         o.n_seg = self.n_seg.data_ptr()
         o.status = self.status.data_ptr()
@@ -297,14 +312,27 @@ def order_rays(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, order: tor
                                  workspace.numel(), _stream(stream)), "vor_order_rays")
 
 
+def n_rays(origins) -> int:
+    return int(origins.shape[0])
+
+
 def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: Optional[torch.Tensor],
                bufs: TraceBuffers, kappa: float = 1.0, mode: str = "fp64", max_steps: int = 0,
                eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, start_given: bool = False,
+               tau_stop: Optional[torch.Tensor] = None, tally_len: Optional[torch.Tensor] = None,
+               tally_abs: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None,
                stream=None) -> None:
     """Enqueue one vor_trace into preallocated buffers (no allocation, no
     sync); with ``ordered`` the rays are first put in coherent order by
     vor_order_rays (buffers made with ordered=True). ``start_given``: the
-    buffers' start cells are those of an earlier call on the same rays."""
+    buffers' start cells are those of an earlier call on the same rays.
+    ``tau_stop`` (float64 [N], buffers made with stops=True): interaction
+    points; ``tally_len`` / ``tally_abs`` (float64 [M], accumulated) and
+    ``weight`` (float64 [N]): per-cell tallies."""
+    for name, t, size in (("tau_stop", tau_stop, n_rays(origins)), ("weight", weight, n_rays(origins)),
+                          ("tally_len", tally_len, grid.M), ("tally_abs", tally_abs, grid.M)):
+        if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != size):
+            raise ValueError(f"{name} must be a contiguous float64 tensor of {size} values")
     n = origins.shape[0]
     if origins.dtype != torch.float64 or dirs.dtype != torch.float64 or not origins.is_contiguous() \
             or not dirs.is_contiguous() or origins.shape != dirs.shape or n != bufs.N:
@@ -319,7 +347,8 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
     if start_given and bufs.start_cell is None:
         raise ValueError("start_given needs buffers made with locate_first=True")
     opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 1 if start_given else 0)
-    out = bufs.struct(use_order=ordered)
+    out = bufs.struct(use_order=ordered, tau_stop=tau_stop, tally_len=tally_len, tally_abs=tally_abs,
+                      weight=weight)
     _check(load().vor_trace(grid.handle, _ptr(origins), _ptr(dirs), n, _ptr(density), float(kappa),
                             ctypes.byref(opts), ctypes.byref(out), _stream(stream)), "vor_trace")
 
@@ -327,21 +356,27 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
 def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str = "fp64",
           segments: str = "exact", seg_stride: int = 64, spill_chunks: int = 0, max_steps: int = 0,
           eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, locate_first: bool = True,
-          stream=None) -> dict:
+          tau_stop=None, weight=None, tallies: bool = False, stream=None) -> dict:
     """Paths of N rays. ``segments``: "none" (tau only), "stride" (a window
     of ``seg_stride`` slots per ray; longer paths continue in up to
     ``spill_chunks`` chained spill chunks, or report RAY_OVERFLOW), or
     "exact" (a tau-only counting pass, a scan, then a pass that writes every
     segment at its CSR offset). ``locate_first``: start cells in a pass of
     their own (vor_trace_out.start_cell) rather than at each ray's start.
-    Returns a dict of device tensors."""
+    ``tau_stop``: interaction points (stop_cell, stop_s); ``tallies``: the
+    per-cell tallies tally_len and tally_abs (with ``weight``). Returns a
+    dict of device tensors."""
     o = _dev_f64(origins, 3)
     d = _dev_f64(dirs, 3)
     rho = None if density is None else _dev_f64(density).reshape(-1)
     n = o.shape[0]
+    ts = None if tau_stop is None else _dev_f64(tau_stop).reshape(-1)
+    wt = None if weight is None else _dev_f64(weight).reshape(-1)
+    t_len = torch.zeros(grid.M, dtype=torch.float64, device="cuda") if tallies else None
+    t_abs = torch.zeros(grid.M, dtype=torch.float64, device="cuda") if tallies else None
     kw = dict(kappa=kappa, mode=mode, max_steps=max_steps, eps_mix=eps_mix, persistent=persistent, ordered=ordered,
-              stream=stream)
-    lf = dict(ordered=ordered, locate_first=locate_first)
+              stream=stream, tau_stop=ts, weight=wt, tally_len=t_len, tally_abs=t_abs)
+    lf = dict(ordered=ordered, locate_first=locate_first, stops=ts is not None)
     if segments == "none":
         b = TraceBuffers(n, **lf)
         trace_into(grid, o, d, rho, b, **kw)
@@ -350,7 +385,7 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
         trace_into(grid, o, d, rho, b, **kw)
     elif segments == "exact":
         b0 = TraceBuffers(n, **lf)
-        trace_into(grid, o, d, rho, b0, **kw)
+        trace_into(grid, o, d, rho, b0, **dict(kw, tally_len=None, tally_abs=None, weight=None))   # counting pass
         off = exclusive_scan(b0.n_seg, stream=stream)
         total = int(off[-1].item())
         b = TraceBuffers(n, total_segments=max(total, 1), **lf)
@@ -359,6 +394,10 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
     else:
         raise ValueError("segments must be none, stride or exact")
     res = dict(tau=b.tau, n_seg=b.n_seg, status=b.status, n_fallback=b.n_fallback, counters=b.counters, work=b.work)
+    if ts is not None:
+        res.update(stop_cell=b.stop_cell, stop_s=b.stop_s)
+    if tallies:
+        res.update(tally_len=t_len, tally_abs=t_abs)
     if b.seg_cell is not None:
         res.update(seg_cell=b.seg_cell, seg_len=b.seg_len)
         res["ray_off"] = b.ray_off if b.ray_off is not None else \

@@ -1,0 +1,108 @@
+"""GPU parity of the transport outputs of vor_trace (interaction points and
+per-cell tallies) against the oracle's definitions (oracle/transport.py),
+on the same seeded rays. Interaction cells, segment counts and the cut
+paths are decided in FP64 on both sides (mixed mode reproduces FP64), so
+they must match exactly, and the interaction distance to rounding-free
+equality; tallies are sums of floating-point atomics in no fixed order,
+compared to 1e-12 of the largest per-cell total."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import transport as T
+from paper_1310_1854_amd import workloads as W
+from pathcmp import gpu_paths
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1310_1854_amd import vrt
+    vrt.load()
+    w = W.uniform_cube(M=1000, N=6000, seed=808)
+    rng = np.random.default_rng(809)
+    ts = -np.log(rng.uniform(size=w.N)) * 3.0
+    ts[:50] = 0.0                     # used up at the origin
+    ts[50:60] = -1.0
+    ts[60:80] = 1e9                   # never used up
+    wt = rng.uniform(0.25, 4.0, w.N)
+    res = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, kappa=1.5, cap=96)
+    ref = T.interactions(res, w.density, 1.5, ts)
+    t_len, t_abs = T.tallies(res, w.density, 1.5, w.M, weight=wt, tau_stop=ts)
+    return vrt, torch, w, vrt.build_grid(w.sites, w.box), ts, wt, res, ref, (t_len, t_abs)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_interaction_points_and_tallies(env, mode, persistent):
+    vrt, torch, w, grid, ts, wt, res, ref, (t_len, t_abs) = env
+    out = vrt.trace(grid, w.origins, w.dirs, w.density, kappa=1.5, mode=mode, segments="exact",
+                    persistent=persistent, ordered=persistent, tau_stop=ts, weight=wt, tallies=True)
+    p = gpu_paths(out)
+    cell = out["stop_cell"].cpu().numpy()
+    s = out["stop_s"].cpu().numpy()
+    clean = (res["status"] == 0) & (res["n_near"] == 0)
+    assert clean.sum() > 0.95 * w.N
+    assert np.array_equal(cell[clean], ref["cell"][clean])
+    assert np.array_equal(p["n_seg"][clean], ref["nseg"][clean])
+    assert np.array_equal(s[clean], ref["s"][clean])          # same FP64 expressions on both sides
+    assert np.array_equal(p["tau"][clean], ref["tau"][clean])
+    for r in np.nonzero(clean)[0][:2000]:
+        n = int(p["n_seg"][r])
+        o = int(p["ray_off"][r])
+        assert np.array_equal(p["seg_cell"][o:o + n], res["seg_cell"][r, :n])
+        want = res["seg_len"][r, :n].copy()
+        if not np.isnan(ref["last_len"][r]):
+            want[n - 1] = ref["last_len"][r]
+        assert np.array_equal(p["seg_len"][o:o + n], want)
+    c60 = clean[:60]
+    assert np.array_equal(cell[:60][c60], res["cell0"][:60][c60])   # tau_stop <= 0: the start cell, no segment
+    assert np.all(s[:60] == 0.0) and np.all(p["n_seg"][:60] == 0)
+    assert np.all(cell[60:80] == -1) and np.array_equal(s[60:80], res["chord"][60:80])
+    # tallies over all rays: a near-tie ray may list a sliver (< 1e-9 of its chord) in another cell
+    n_near = int((res["n_near"] > 0).sum())
+    g_len = out["tally_len"].cpu().numpy()
+    g_abs = out["tally_abs"].cpu().numpy()
+    sliver = 1e-9 * 4.0 * float(res["chord"].max()) * 1.5 * float(w.density.max())
+    assert np.max(np.abs(g_len - t_len)) <= 1e-12 * t_len.max() + n_near * 1e-9 * 4.0 * float(res["chord"].max())
+    assert np.max(np.abs(g_abs - t_abs)) <= 1e-12 * t_abs.max() + n_near * sliver
+
+
+def test_tallies_accumulate_and_telescope(env):
+    """Two calls accumulate; the absorbed fractions of each path sum to
+    w (1 - exp(-tau)) over the whole batch (a property at any size)."""
+    vrt, torch, w, grid, ts, wt, res, ref, _ = env
+    t_len = torch.zeros(w.M, dtype=torch.float64, device="cuda")
+    t_abs = torch.zeros(w.M, dtype=torch.float64, device="cuda")
+    o = torch.as_tensor(w.origins, device="cuda")
+    d = torch.as_tensor(w.dirs, device="cuda")
+    rho = torch.as_tensor(w.density, device="cuda")
+    wtt = torch.as_tensor(wt, device="cuda")
+    b = vrt.TraceBuffers(w.N, ordered=True)
+    for _ in range(2):
+        vrt.trace_into(grid, o, d, rho, b, kappa=1.5, mode="mixed", persistent=True, ordered=True,
+                       tally_len=t_len, tally_abs=t_abs, weight=wtt)
+    torch.cuda.synchronize()
+    tau = b.tau.cpu().numpy()
+    ok = b.status.cpu().numpy() == 0
+    want = 2.0 * (wt * -np.expm1(-tau))[ok].sum()
+    assert abs(float(t_abs.sum()) - want) <= 1e-11 * want
+
+
+def test_transport_argument_errors(env):
+    vrt, torch, w, grid, ts, wt, res, ref, _ = env
+    o = torch.as_tensor(w.origins[:10], device="cuda")
+    b = vrt.TraceBuffers(10)
+    out = b.struct()
+    out.tau_stop = torch.zeros(10, dtype=torch.float64, device="cuda").data_ptr()   # no stop_cell
+    lib = vrt.load()
+    import ctypes
+    rc = lib.vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(o), 10, None, 1.0, None, ctypes.byref(out), vrt._stream())
+    assert rc == vrt.VOR_EINVAL
+    out = b.struct()
+    out.weight = torch.ones(10, dtype=torch.float64, device="cuda").data_ptr()       # weights without a tally
+    rc = lib.vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(o), 10, None, 1.0, None, ctypes.byref(out), vrt._stream())
+    assert rc == vrt.VOR_EINVAL
