@@ -117,6 +117,16 @@ void vor_grid_free(vor_grid *grid);
 vor_status vor_grid_get_info(const vor_grid *grid, vor_grid_info *info);
 
 /*
+ * Diagnostic: keeps only the first `keep` entries (internal order) of the
+ * neighbour list of site `site` (user index), so that the table misses
+ * faces of that cell and paths through it take the no-exit fallback of
+ * Sect. 2.2 (advance a small distance, locate the point again). Paths are
+ * no longer exact after this; it exists to test that recovery. Synchronous;
+ * VOR_EINVAL for a bad site or a negative keep.
+ */
+vor_status vor_grid_truncate_row(vor_grid *grid, int64_t site, int32_t keep);
+
+/*
  * vor_grid_neighbors -- the neighbour lists of Sect. 2.2 item 3 in CSR form,
  * user order, walls as negative codes (Sect. 2.2: walls are special
  * negative indices). Row i lists, in increasing order, the neighbour cells

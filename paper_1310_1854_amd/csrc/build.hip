@@ -573,5 +573,21 @@ extern "C" vor_status vor_grid_neighbors(const vor_grid *G, int64_t *row_ptr, in
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
+extern "C" vor_status vor_grid_truncate_row(vor_grid *G, int64_t site, int32_t keep)
+{
+    if (!G || site < 0 || site >= G->g.M || keep < 0) return VOR_EINVAL;
+    Grid &g = G->g;
+    int32_t i = 0;
+    int2 rw;
+    if (hipMemcpy(&i, g.inv_perm + site, sizeof(i), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&rw, g.rows + i, sizeof(rw), hipMemcpyDeviceToHost) != hipSuccess)
+        return VOR_EDEVICE;
+    if (keep < rw.y) {
+        rw.y = keep;
+        if (hipMemcpy(g.rows + i, &rw, sizeof(rw), hipMemcpyHostToDevice) != hipSuccess) return VOR_EDEVICE;
+    }
+    return VOR_OK;
+}
+
 // accessor for the other translation units
 const vrt::Grid &vrt_grid_of(const vor_grid *G) { return G->g; }

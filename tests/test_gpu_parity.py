@@ -220,6 +220,48 @@ def test_long_rows_rank_per_lane(vrt):
     assert int(p["seg_cell"][int(p["ray_off"][0])]) == 0     # every path starts in the central cell
 
 
+def test_no_exit_fallback_recovers(vrt):
+    """Sect. 2.2's no-exit fallback: faces removed from the table of some
+    cells (vor_grid_truncate_row) make paths through them miss exits; the
+    step that then finds the current point beyond a plane advances a small
+    distance and locates the point again. Paths that never meet a damaged
+    cell are unchanged; the others still end at the wall with status OK and
+    their full length (the advances excepted); FP64 and mixed mode take the
+    same decisions. (A path left in a wrong cell while moving away from every
+    plane it has passed is not caught: the fallback fires on an exit behind
+    the current point, so the cells listed after the damage may differ.)"""
+    import torch
+    w = W.uniform_cube(M=1000, N=10_000, seed=61)
+    grid = vrt.build_grid(w.sites, w.box)
+    damaged = np.argsort(np.linalg.norm(w.sites, axis=1))[:40]   # cells near the centre
+    for s in damaged:
+        grid.truncate_row(int(s), 4)
+    a = vrt.trace(grid, w.origins, w.dirs, w.density, mode="fp64", segments="exact")
+    b = vrt.trace(grid, w.origins, w.dirs, w.density, mode="mixed", segments="exact", persistent=True,
+                  ordered=True)
+    for k in ("tau", "n_seg", "status", "n_fallback", "ray_off", "seg_cell", "seg_len"):
+        assert torch.equal(a[k], b[k]), k
+    p = gpu_paths(a)
+    ref = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    nfb = p["n_fallback"]
+    assert nfb.sum() > 100 and int(a["counters"][1].item()) == nfb.sum()
+    assert np.all(p["status"] == 0)
+    eps = 1e-12 * float(np.linalg.norm(np.array(w.box[3:]) - np.array(w.box[:3])))
+    dset = set(damaged.tolist())
+    n_clean = 0
+    for r in range(w.N):
+        cells, lens = p["seg_cell"][p["ray_off"][r]:p["ray_off"][r + 1]], p["seg_len"][p["ray_off"][r]:p["ray_off"][r + 1]]
+        L = ref["chord"][r]
+        n = int(ref["nseg"][r])
+        if ref["n_near"][r] == 0 and not (set(ref["seg_cell"][r, :n].tolist()) & dset):
+            assert nfb[r] == 0 and list(cells) == list(ref["seg_cell"][r, :n])   # never meets a damaged cell
+            n_clean += 1
+            continue
+        # every advance of the fallback is left out of the segments (R6)
+        assert abs(lens.sum() + nfb[r] * eps - L) <= 1e-9 * L, r
+    assert n_clean > 0.3 * w.N
+
+
 def test_mixed_equals_fp64_bitwise(vrt):
     w = W.exp_disc(M=20_000, N=200_000, seed=77)
     grid = vrt.build_grid(w.sites, w.box)
