@@ -55,7 +55,7 @@ def _bind(lib):
     lib.oracle_locate.argtypes = [P, I64, P, P, I64, P, P]
     lib.oracle_locate.restype = ctypes.c_int
     lib.oracle_trace.argtypes = [P, I64, P, P, ctypes.c_double, P, P, I64,
-                                 ctypes.c_double, I64, P, P, P, P, P, P, P, P, P, P]
+                                 ctypes.c_double, I64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int, P]
     lib.oracle_trace.restype = ctypes.c_int
     lib.oracle_faces.argtypes = [P, I64, P, P, I64, I64, P, P, P, P]
     lib.oracle_faces.restype = ctypes.c_int
@@ -117,11 +117,12 @@ def locate(sites, box, pts, lib=None):
 
 
 def trace(sites, box, density, origins, dirs, kappa=1.0, cap=256, eta=ETA, segments=True,
-          lib=None):
+          lib=None, enter=False):
     """Paths by brute force. Returns a dict of numpy arrays: nseg, tau, chord,
-    status, n_near, min_gap, cell0 and, if ``segments``, seg_cell / seg_len /
-    seg_end (where each segment ends, measured from the origin) of shape
-    (N, cap) (entries past nseg are undefined)."""
+    status, n_near, min_gap, cell0, start_s and, if ``segments``, seg_cell /
+    seg_len / seg_end (where each segment ends, measured from the origin) of
+    shape (N, cap) (entries past nseg are undefined). ``enter``: rays from
+    outside the box start where they enter it (start_s)."""
     sites = _f64(sites, (-1, 3))
     box = _f64(box, (6,))
     origins = _f64(origins, (-1, 3))
@@ -131,7 +132,7 @@ def trace(sites, box, density, origins, dirs, kappa=1.0, cap=256, eta=ETA, segme
     out = dict(
         nseg=np.zeros(N, np.int32), tau=np.zeros(N), chord=np.zeros(N),
         status=np.zeros(N, np.int32), n_near=np.zeros(N, np.int32),
-        min_gap=np.zeros(N), cell0=np.zeros(N, np.int32))
+        min_gap=np.zeros(N), cell0=np.zeros(N, np.int32), start_s=np.zeros(N))
     sc = sl = se = None
     if segments:
         sc = np.full((N, cap), -7, np.int32)
@@ -140,7 +141,8 @@ def trace(sites, box, density, origins, dirs, kappa=1.0, cap=256, eta=ETA, segme
     rc = _load(lib).oracle_trace(
         _p(sites), sites.shape[0], _p(box), _p(rho), float(kappa), _p(origins), _p(dirs), N,
         float(eta), int(cap), _p(sc), _p(sl), _p(se), _p(out["nseg"]), _p(out["tau"]), _p(out["chord"]),
-        _p(out["status"]), _p(out["n_near"]), _p(out["min_gap"]), _p(out["cell0"]))
+        _p(out["status"]), _p(out["n_near"]), _p(out["min_gap"]), _p(out["cell0"]), 1 if enter else 0,
+        _p(out["start_s"]))
     if rc:
         raise ValueError("oracle_trace: bad arguments")
     if segments:

@@ -148,10 +148,17 @@ int oracle_locate(const double *sites, int64_t M, const double *box,
  * n_near, and min_gap holds the smallest (s(2) - s(1)) / L over the path
  * together with the start-cell gap of oracle_locate divided by L.
  *
+ * With enter != 0 a ray whose origin lies outside the box starts where it
+ * enters the box: s0 = the largest over the axes of the distance to the
+ * near wall (the walls it moves towards, Eq. 5 turned round); it misses the
+ * box (status OUTSIDE) unless s0 < L. The start cell is then the nearest
+ * site to r0 + s0 k, and crossings are still measured from r0.
+ *
  * Outputs per ray (any may be NULL except nseg): segments at
  * seg_cell/seg_len[ray * cap + i] for i < cap, with seg_end the position
  * s* (from the origin) where each segment ends, nseg (true count even past
- * cap), tau, chord = L, status, n_near, min_gap, cell0 = start cell.
+ * cap), tau, chord = L, status, n_near, min_gap, cell0 = start cell,
+ * start_s = s0 (0 for origins inside the box).
  * Returns 0, or 1 on bad arguments.
  */
 int oracle_trace(const double *sites, int64_t M, const double *box,
@@ -160,7 +167,8 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
                  double eta, int64_t cap,
                  int32_t *seg_cell, double *seg_len, double *seg_end,
                  int32_t *nseg, double *tau, double *chord, int32_t *status,
-                 int32_t *n_near, double *min_gap, int32_t *cell0)
+                 int32_t *n_near, double *min_gap, int32_t *cell0,
+                 int enter, double *start_s)
 {
     if (M <= 0 || N < 0 || !nseg) return 1;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -173,9 +181,11 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
         double t = 0.0, L = 0.0, gmin = INFINITY;
         int32_t start = -1;
 
+        double s0 = 0.0;                     /* where the path starts, measured from r0 */
+        const int outside = !inside_box(box, r0);
         if (!(knorm > 0.0) || !isfinite(knorm)) {
             st = ST_BADDIR;
-        } else if (!inside_box(box, r0)) {
+        } else if (outside && !enter) {
             st = ST_OUTSIDE;
         }
         if (st == ST_OK) {
@@ -191,11 +201,36 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
                     if (s < L) L = s;
                 }
             }
+            if (outside) {
+                /* a ray from outside enters the box where it has crossed the
+                 * near wall of every axis (Sect. 2.2 notes the method extends
+                 * to such rays); it misses the box if that is not before L */
+                for (int a = 0; a < 3; ++a) {
+                    if (k[a] > 0.0) {
+                        double s = (box[a] - r0[a]) / k[a];
+                        if (s > s0) s0 = s;
+                    } else if (k[a] < 0.0) {
+                        double s = (box[a + 3] - r0[a]) / k[a];
+                        if (s > s0) s0 = s;
+                    } else if (r0[a] < box[a] || r0[a] > box[a + 3]) {
+                        s0 = INFINITY;
+                    }
+                }
+                if (!(s0 < L)) {
+                    st = ST_OUTSIDE;
+                    L = 0.0;
+                }
+            }
+        }
+        if (st == ST_OK) {
+            double q[3] = {r0[0], r0[1], r0[2]};   /* the start point */
+            if (outside)
+                for (int a = 0; a < 3; ++a) q[a] = r0[a] + s0 * k[a];
             /* start cell: nearest site, right-continuous tie rule */
             double d1 = INFINITY, d2 = INFINITY;
             int64_t m = -1, second = -1;
             for (int64_t j = 0; j < M; ++j) {
-                double d = dist2(r0, sites + 3 * j);
+                double d = dist2(q, sites + 3 * j);
                 if (d < d1) {
                     d2 = d1; second = m;
                     d1 = d; m = j;
@@ -216,7 +251,7 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
                 if (g <= eta) ++near;
             }
 
-            double s_c = 0.0;
+            double s_c = s0;
             int64_t steps = 0;
             const double *pm = sites + 3 * m;
             while (L > 0.0) {
@@ -275,6 +310,7 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
         if (n_near) n_near[ray] = near;
         if (min_gap) min_gap[ray] = gmin;
         if (cell0) cell0[ray] = start;
+        if (start_s) start_s[ray] = s0;
     }
     return 0;
 }

@@ -14,7 +14,8 @@ lengths l_1..l_n and end positions s_1..s_n measured from the origin, as
   m_k with kappa rho_{m_k} > 0 and tau_k >= tau_stop, at the distance
   s_{k-1} + (tau_stop - tau_{k-1}) / (kappa rho_{m_k}) from the origin
   (s_0 = 0); the path is cut there, its last segment shortened to that
-  point. A non-positive tau_stop interacts at the origin, in the start cell,
+  point. A non-positive tau_stop interacts where the path starts (the
+  origin, or where a ray from outside enters the box), in the start cell,
   before any segment; a package that reaches the wall first escapes (cell
   -1, distance L).
 
@@ -35,13 +36,14 @@ import math
 import numpy as np
 
 
-def interaction(cells, lens, ends, rho, kappa, tau_stop, cell0, chord):
-    """Interaction point of one path: (cell, distance, number of segments
-    kept, tau at the end, length of the last kept segment)."""
+def interaction(cells, lens, ends, rho, kappa, tau_stop, cell0, chord, s0=0.0):
+    """Interaction point of one path starting at distance s0 from the origin
+    (0 unless it entered the box from outside): (cell, distance, number of
+    segments kept, tau at the end, length of the last kept segment)."""
     if tau_stop <= 0.0:
-        return int(cell0), 0.0, 0, 0.0, None
+        return int(cell0), s0, 0, 0.0, None
     tau = 0.0
-    s_prev = 0.0
+    s_prev = s0
     for k in range(len(cells)):
         m = int(cells[k])
         kr = kappa * rho[m]
@@ -68,7 +70,8 @@ def interactions(res, rho, kappa, tau_stop):
             continue
         n = int(res["nseg"][i])
         c, s, k, t, lp = interaction(res["seg_cell"][i, :n], res["seg_len"][i, :n], res["seg_end"][i, :n], rho,
-                                     kappa, float(tau_stop[i]), res["cell0"][i], res["chord"][i])
+                                     kappa, float(tau_stop[i]), res["cell0"][i], res["chord"][i],
+                                     float(res["start_s"][i]))
         out["cell"][i], out["s"][i], out["nseg"][i], out["tau"][i] = c, s, k, t
         if lp is not None:
             out["last_len"][i] = lp
@@ -91,7 +94,7 @@ def tallies(res, rho, kappa, M, weight=None, tau_stop=None):
         cells, lens = res["seg_cell"][i, :n], res["seg_len"][i, :n]
         if tau_stop is not None:
             c, s, k, t, lp = interaction(cells, lens, res["seg_end"][i, :n], rho, kappa, float(tau_stop[i]),
-                                         res["cell0"][i], res["chord"][i])
+                                         res["cell0"][i], res["chord"][i], float(res["start_s"][i]))
             n = k
             lens = np.array(lens[:n], dtype=np.float64)
             if lp is not None:

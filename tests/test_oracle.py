@@ -342,3 +342,48 @@ def test_mean_neighbour_count_uniform(oracle_lib):
     res, _ = oracle.faces(w.sites, w.box, cells)
     counts = np.array([len(s) for s in _face_sets(res, (2.0 / 4000 ** (1 / 3)) ** 2)])
     assert abs(counts.mean() - 15.54) < 0.5, counts.mean()
+
+
+# --------------------------------------------------------------------------
+# rays from outside the box (Sect. 2.2 notes the method extends to them)
+# --------------------------------------------------------------------------
+
+def test_entering_rays_closed_form(oracle_lib):
+    # one cell, the box [0,1]^3: from (-1, 0.5, 0.5) along +x the ray enters at s = 1, leaves at s = 2;
+    # along -x it never meets the box; grazing the x = 1 face from outside it misses too
+    o = oracle.trace([[0.5, 0.5, 0.5]], [0, 0, 0, 1, 1, 1], [3.0],
+                     [[-1.0, 0.5, 0.5], [-1.0, 0.5, 0.5], [2.0, 1.5, 0.5]], [[1, 0, 0], [-1, 0, 0], [-1, 0, 0]],
+                     cap=4, enter=True)
+    cells, lens = oracle.segments_of(o, 0)
+    assert list(cells) == [0] and lens[0] == 1.0 and o["tau"][0] == 3.0
+    assert o["start_s"][0] == 1.0 and o["chord"][0] == 2.0
+    assert list(o["status"][1:]) == [oracle.ST_OUTSIDE, oracle.ST_OUTSIDE]
+    # the three-slab case from outside: r0 = (0.25, 0.5, 0.25) - 1.25 (0.8, 0, 0.6) = (-0.75, 0.5, -0.5).
+    # Near walls: x = 0 at s = 0.75/0.8 = 0.9375, z = 0 at 0.5/0.6 = 0.833...; it enters through x = 0 at
+    # 0.9375 (the later one), crosses x = 1 at 1.75/0.8 = 2.1875 and leaves through z = 1 at 1.5/0.6 = 2.5
+    o = oracle.trace([[0.5, 0.5, 0.5], [1.5, 0.5, 0.5], [3.5, 0.5, 0.5]], [0, 0, 0, 4, 1, 1], [2.0, 3.0, 5.0],
+                     [[-0.75, 0.5, -0.5]], [[4.0, 0.0, 3.0]], cap=8, enter=True)
+    cells, lens = oracle.segments_of(o, 0)
+    assert list(cells) == [0, 1]
+    assert abs(o["start_s"][0] - 0.9375) < 1e-15 and abs(o["chord"][0] - 2.5) < 1e-15
+    assert np.allclose(lens, [1.25, 0.3125], rtol=0, atol=1e-15)
+    assert abs(o["tau"][0] - (2.0 * 1.25 + 3.0 * 0.3125)) < 1e-14
+
+
+def test_entering_equals_starting_at_the_entry_point(oracle_lib):
+    w = W.uniform_cube(M=400, N=300, seed=4246)
+    k = w.dirs / np.linalg.norm(w.dirs, axis=1)[:, None]
+    outside = w.origins - 4.0 * k                  # 4 units back along the ray: outside the cube [-1, 1]^3
+    a = oracle.trace(w.sites, w.box, w.density, outside, k, cap=64, enter=True)
+    assert np.all(a["status"] == 0) and np.all(a["start_s"] > 0)
+    entry = outside + a["start_s"][:, None] * k     # on the wall, up to rounding (just outside is entered at once)
+    b = oracle.trace(w.sites, w.box, w.density, entry, k, cap=64, enter=True)
+    ok = (a["n_near"] == 0) & (b["n_near"] == 0)
+    assert ok.sum() > 0.9 * w.N
+    for r in np.nonzero(ok)[0]:
+        ca, la = oracle.segments_of(a, r)
+        cb, lb = oracle.segments_of(b, r)
+        assert list(ca) == list(cb)
+        assert np.max(np.abs(la - lb)) <= 1e-12 * a["chord"][r]
+    assert np.allclose(a["chord"][ok] - a["start_s"][ok], b["chord"][ok] - b["start_s"][ok], rtol=0, atol=1e-12)
+    assert np.all(b["start_s"] < 1e-12)

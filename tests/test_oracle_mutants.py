@@ -38,7 +38,10 @@ MUTANTS = {
                             "double den = n0 * k[0] + n1 * k[1] + n2 * k[1];"),
     "tau_uses_position": ("if (rho) t += kappa * rho[m] * len;", "if (rho) t += kappa * rho[m] * best;"),
     "tau_wrong_cell": ("if (rho) t += kappa * rho[m] * len;", "if (rho) t += kappa * rho[win < 0 ? m : win] * len;"),
-    "chord_wrong_wall": ("double s = (box[a + 3] - r0[a]) / k[a];", "double s = (box[a] - r0[a]) / k[a];"),
+    "chord_wrong_wall": ("double s = (box[a + 3] - r0[a]) / k[a];\n                    if (s < L)",
+                         "double s = (box[a] - r0[a]) / k[a];\n                    if (s < L)"),
+    "entry_wrong_wall": ("double s = (box[a] - r0[a]) / k[a];\n                        if (s > s0)",
+                         "double s = (box[a + 3] - r0[a]) / k[a];\n                        if (s > s0)"),
     "position_not_advanced": ("s_c = best;", ";"),
     "locate_second_nearest": ("cell[q] = (int32_t)b1;", "cell[q] = (int32_t)b2;"),
     "clip_plane_offset": ("double b = v3dot(a, v3scale(v3add(pk, pi), 0.5));",
@@ -126,8 +129,16 @@ def _pins(lib):
         res, vol = oracle.faces(W.cubic_lattice(3, N=1).sites, [0, 0, 0, 3, 3, 3], [13], lib=lib)
         return sorted(int(j) for j, a in zip(*res[0]) if a > 1e-9) == [4, 10, 12, 14, 16, 22]
 
+    def entering():
+        # one cell, the box [0,1]^3: from (-1, 0.5, 0.5) along +x the ray enters at s = 1 and leaves at s = 2
+        o = oracle.trace([[0.5, 0.5, 0.5]], [0, 0, 0, 1, 1, 1], [3.0], [[-1.0, 0.5, 0.5]], [[1.0, 0.0, 0.0]],
+                         cap=4, lib=lib, enter=True)
+        cells, lens = oracle.segments_of(o, 0)
+        return (list(cells) == [0] and lens[0] == 1.0 and o["start_s"][0] == 1.0 and o["chord"][0] == 2.0
+                and o["tau"][0] == 3.0)
+
     for name, fn in [("golden", golden), ("lattice", lattice), ("exact", exact),
-                     ("invariants", invariants), ("locate", locate), ("faces", faces)]:
+                     ("invariants", invariants), ("locate", locate), ("faces", faces), ("entering", entering)]:
         check(name, fn)
     return failed
 
