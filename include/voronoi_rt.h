@@ -158,6 +158,12 @@ typedef struct {
     int32_t start_given;    /* 1: out->start_cell already holds the start cells of these rays, left there by
                                an earlier call on the same grid with the same origins (another density,
                                kappa or mode); the start-cell pass is skipped */
+    int32_t enter;          /* 1: a ray whose origin lies outside the box (Sect. 2.2 notes the method extends
+                               to such rays) starts where it enters the box: s0 = the largest over the axes of
+                               the distance to the near wall; distances stay measured from the origin, the
+                               start cell is C(r0 + s0 k); a ray that misses the box (s0 >= L) or has a
+                               non-finite origin gets VOR_RAY_OUTSIDE. 0: every origin outside the box is
+                               VOR_RAY_OUTSIDE */
 } vor_trace_opts;
 
 /* Outputs of vor_trace. All pointers are device memory; tau and n_seg are required. */

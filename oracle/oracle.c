@@ -185,7 +185,7 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
         const int outside = !inside_box(box, r0);
         if (!(knorm > 0.0) || !isfinite(knorm)) {
             st = ST_BADDIR;
-        } else if (outside && !enter) {
+        } else if (outside && (!enter || !isfinite(r0[0]) || !isfinite(r0[1]) || !isfinite(r0[2]))) {
             st = ST_OUTSIDE;
         }
         if (st == ST_OK) {

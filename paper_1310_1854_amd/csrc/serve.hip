@@ -181,13 +181,14 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     lenp = rq.seg_len;
                     vec4 = (rq.seg_cell && rq.seg_stride % 4 == 0) ? 1 : 0;
                     S = RayStats();
-                    R.st = ray_setup(G, rq.in, ray, R.r0, R.k, R.L);
+                    double s0;
+                    R.st = ray_setup<false>(G, rq.in, ray, R.r0, R.k, R.L, s0);
                     R.tau = 0.0;
                     R.chunk = -1;
                     R.ray = (int32_t)ray;
                     R.base = ray * rq.seg_stride;
                     R.cap = rq.seg_cell ? rq.seg_stride : 0;
-                    if (R.st == RAY_OK) ray_begin(G, R);
+                    if (R.st == RAY_OK) ray_begin(G, R, s0);
                     else R.L = 0.0;
                     live = true;
                 }
@@ -629,6 +630,7 @@ vor_status vor_server_submit(vor_server *S, int32_t grid, const double *origins,
     r.in.dirs = dirs;
     r.in.density = density;
     r.in.kappa = kappa;
+    r.in.enter = 0;
     r.seg_stride = seg_stride;
     r.bytes = bytes;
     r.t_submit = clk::now();

@@ -110,13 +110,15 @@ __device__ __forceinline__ void flush_counters(const TraceArgs &A, const RayStat
 template <bool EXT>
 __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RayState &R)
 {
-    R.st = ray_setup(A.G, A.I, ray, R.r0, R.k, R.L);
+    double s0;
+    R.st = ray_setup<EXT>(A.G, A.I, ray, R.r0, R.k, R.L, s0);
     R.tau = 0.0;
     if (R.st == RAY_OK) {
-        if (A.start) ray_begin_at(A.G, R, A.start[ray]);
-        else ray_begin(A.G, R);
+        if (A.start) ray_begin_at(A.G, R, A.start[ray], s0);
+        else ray_begin(A.G, R, s0);
     } else {
         R.L = 0.0;
+        R.s_c = 0.0;
     }
     if (EXT) ray_extras_begin(A.X, ray, R);
 }
@@ -178,13 +180,15 @@ __global__ void __launch_bounds__(256) k_start_cells(TraceArgs A)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < A.N;
     const int64_t ray = valid ? (A.order ? (int64_t)A.order[i] : i) : 0;
-    double r0[3] = {0.0, 0.0, 0.0}, k[3], L;
-    const uint8_t st = valid ? ray_setup(A.G, A.I, ray, r0, k, L) : (uint8_t)RAY_BADDIR;
-    const double q0 = __shfl(r0[0], 0, 64), q1 = __shfl(r0[1], 0, 64), q2 = __shfl(r0[2], 0, 64);
-    const bool same = valid && st == RAY_OK && r0[0] == q0 && r0[1] == q1 && r0[2] == q2;
+    double r0[3] = {0.0, 0.0, 0.0}, k[3] = {1.0, 0.0, 0.0}, L, s0 = 0.0;
+    const uint8_t st = valid ? ray_setup(A.G, A.I, ray, r0, k, L, s0) : (uint8_t)RAY_BADDIR;
+    double q[3];
+    start_point(r0, k, s0, q);
+    const double q0 = __shfl(q[0], 0, 64), q1 = __shfl(q[1], 0, 64), q2 = __shfl(q[2], 0, 64);
+    const bool same = valid && st == RAY_OK && q[0] == q0 && q[1] == q1 && q[2] == q2;
     int32_t m = -1;
-    if (__ballot(true) == ~0ull && __ballot(same) == ~0ull) m = nearest_site_wave(A.G.grid, r0, nullptr);
-    else if (valid && st == RAY_OK) m = nearest_site(A.G.grid, r0, nullptr);
+    if (__ballot(true) == ~0ull && __ballot(same) == ~0ull) m = nearest_site_wave(A.G.grid, q, nullptr);
+    else if (valid && st == RAY_OK) m = nearest_site(A.G.grid, q, nullptr);
     if (valid) A.start[ray] = (st == RAY_OK) ? m : -1;
 }
 
@@ -418,6 +422,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     A.I.dirs = dirs;
     A.I.density = density;
     A.I.kappa = kappa;
+    A.I.enter = opts ? opts->enter : 0;
     A.N = N;
     A.tau = out->tau;
     A.n_seg = out->n_seg;
@@ -453,7 +458,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
         int64_t nb = std::min<int64_t>((N + T - 1) / T, 65535);
         hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)nb), dim3(T), 0, st, A.O.spill_first, N, (int64_t)-1);
     }
-    const bool ext = A.X.tau_stop || A.X.tally_len || A.X.tally_abs;
+    const bool ext = A.X.tau_stop || A.X.tally_len || A.X.tally_abs || A.I.enter;   // kernels with the optional features
     const vor_status rc = mode == VOR_MODE_FP64
                               ? (segs ? launch_trace<VOR_MODE_FP64, true>(A, ext, persistent, st)
                                       : launch_trace<VOR_MODE_FP64, false>(A, ext, persistent, st))

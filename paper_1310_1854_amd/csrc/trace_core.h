@@ -36,6 +36,7 @@ struct RayIn {
     const double *dirs;
     const double *density;
     double kappa;
+    int32_t enter;     // rays from outside the box start where they enter it
 };
 
 // Where segments go: a window per ray, then (optionally) a chain of spill
@@ -327,8 +328,14 @@ struct RayStats {
 };
 
 // Ray set-up: normalised direction, chord length L (Eq. 5 on every axis),
-// status. Returns false when the ray has no path.
-__device__ __forceinline__ uint8_t ray_setup(const GridRef &G, const RayIn &I, int64_t ray, double r0[3], double k[3], double &L)
+// status, and s0, where the path starts (0, or with I.enter the distance at
+// which a ray from outside enters the box: the largest over the axes of the
+// distance to the near wall; it misses the box unless s0 < L).
+// ENTER = false compiles the entry out (the kernels without the optional
+// features, whose registers it would cost): every origin outside is OUTSIDE.
+template <bool ENTER = true>
+__device__ __forceinline__ uint8_t ray_setup(const GridRef &G, const RayIn &I, int64_t ray, double r0[3], double k[3],
+                                             double &L, double &s0)
 {
     for (int a = 0; a < 3; ++a) {
         r0[a] = I.origins[3 * ray + a];
@@ -339,8 +346,10 @@ __device__ __forceinline__ uint8_t ray_setup(const GridRef &G, const RayIn &I, i
     for (int a = 0; a < 3; ++a)
         if (!(r0[a] >= G.lo[a] && r0[a] <= G.hi[a])) inside = false;
     L = 0.0;
+    s0 = 0.0;
     if (!(kn > 0.0) || !isfinite(kn)) return RAY_BADDIR;
-    if (!inside) return RAY_OUTSIDE;
+    if (!inside && (!ENTER || !I.enter || !isfinite(r0[0]) || !isfinite(r0[1]) || !isfinite(r0[2])))
+        return RAY_OUTSIDE;
     for (int a = 0; a < 3; ++a) k[a] /= kn;
     L = 1e308 * 10.0;
     for (int a = 0; a < 3; ++a) {
@@ -352,7 +361,31 @@ __device__ __forceinline__ uint8_t ray_setup(const GridRef &G, const RayIn &I, i
             if (s < L) L = s;
         }
     }
+    if (ENTER && !inside) {
+        for (int a = 0; a < 3; ++a) {
+            if (k[a] > 0.0) {
+                double s = (G.lo[a] - r0[a]) / k[a];
+                if (s > s0) s0 = s;
+            } else if (k[a] < 0.0) {
+                double s = (G.hi[a] - r0[a]) / k[a];
+                if (s > s0) s0 = s;
+            } else if (r0[a] < G.lo[a] || r0[a] > G.hi[a]) {
+                s0 = 1e308 * 10.0;
+            }
+        }
+        if (!(s0 < L)) {
+            L = 0.0;
+            s0 = 0.0;
+            return RAY_OUTSIDE;
+        }
+    }
     return RAY_OK;
+}
+
+// The point where the path starts.
+__device__ __forceinline__ void start_point(const double r0[3], const double k[3], double s0, double q[3])
+{
+    for (int a = 0; a < 3; ++a) q[a] = s0 > 0.0 ? r0[a] + s0 * k[a] : r0[a];
 }
 
 // Per-lane state of a ray in flight.
@@ -373,12 +406,14 @@ struct RayState {
     int32_t stop_uid;            // cell of the interaction point, -1 none yet
 };
 
-__device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R)
+__device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R, double s0)
 {
-    R.s_c = 0.0;
+    R.s_c = s0;
     R.tau = 0.0;
     int32_t uid;
-    int32_t m = nearest_site(G.grid, R.r0, &uid);
+    double q[3];
+    start_point(R.r0, R.k, s0, q);
+    int32_t m = nearest_site(G.grid, q, &uid);
     Site sm = G.sites[m];
     R.m = m;
     R.uid = uid;
@@ -389,9 +424,9 @@ __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R)
 }
 
 // Start in cell m (internal index), found beforehand by nearest_site.
-__device__ __forceinline__ void ray_begin_at(const GridRef &G, RayState &R, int32_t m)
+__device__ __forceinline__ void ray_begin_at(const GridRef &G, RayState &R, int32_t m, double s0)
 {
-    R.s_c = 0.0;
+    R.s_c = s0;
     R.tau = 0.0;
     const Site sm = G.sites[m];
     R.m = m;
@@ -538,8 +573,9 @@ __device__ __forceinline__ void ray_extras_begin(const Extras &X, int64_t ray, R
     R.wgt = X.weight ? X.weight[ray] : 1.0;
     R.stop_uid = -1;
     R.stop_s = 0.0;
-    if (X.tau_stop && R.st == RAY_OK && R.tstop <= 0.0) {   // used up at the origin: no segment
+    if (X.tau_stop && R.st == RAY_OK && R.tstop <= 0.0) {   // used up where the path starts: no segment
         R.stop_uid = R.uid;
+        R.stop_s = R.s_c;
         R.L = 0.0;
     }
 }

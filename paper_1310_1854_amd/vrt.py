@@ -50,7 +50,7 @@ class GridInfo(ctypes.Structure):
 
 class TraceOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_steps", ctypes.c_int32), ("eps_mix", ctypes.c_double),
-                ("persistent", ctypes.c_int32), ("start_given", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("start_given", ctypes.c_int32), ("enter", ctypes.c_int32)]
 
 
 class TraceOut(ctypes.Structure):
@@ -328,7 +328,7 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
                eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, start_given: bool = False,
                tau_stop: Optional[torch.Tensor] = None, tally_len: Optional[torch.Tensor] = None,
                tally_abs: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None,
-               stream=None) -> None:
+               enter: bool = False, stream=None) -> None:
     """Enqueue one vor_trace into preallocated buffers (no allocation, no
     sync); with ``ordered`` the rays are first put in coherent order by
     vor_order_rays (buffers made with ordered=True). ``start_given``: the
@@ -353,7 +353,8 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
             order_rays(grid, origins, dirs, bufs.order, bufs.order_ws, stream=stream)
     if start_given and bufs.start_cell is None:
         raise ValueError("start_given needs buffers made with locate_first=True")
-    opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 1 if start_given else 0)
+    opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 1 if start_given else 0,
+                     1 if enter else 0)
     out = bufs.struct(use_order=ordered, tau_stop=tau_stop, tally_len=tally_len, tally_abs=tally_abs,
                       weight=weight)
     _check(load().vor_trace(grid.handle, _ptr(origins), _ptr(dirs), n, _ptr(density), float(kappa),
@@ -363,7 +364,7 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
 def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str = "fp64",
           segments: str = "exact", seg_stride: int = 64, spill_chunks: int = 0, max_steps: int = 0,
           eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, locate_first: bool = True,
-          tau_stop=None, weight=None, tallies: bool = False, stream=None) -> dict:
+          tau_stop=None, weight=None, tallies: bool = False, enter: bool = False, stream=None) -> dict:
     """Paths of N rays. ``segments``: "none" (tau only), "stride" (a window
     of ``seg_stride`` slots per ray; longer paths continue in up to
     ``spill_chunks`` chained spill chunks, or report RAY_OVERFLOW), or
@@ -371,8 +372,9 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
     segment at its CSR offset). ``locate_first``: start cells in a pass of
     their own (vor_trace_out.start_cell) rather than at each ray's start.
     ``tau_stop``: interaction points (stop_cell, stop_s); ``tallies``: the
-    per-cell tallies tally_len and tally_abs (with ``weight``). Returns a
-    dict of device tensors."""
+    per-cell tallies tally_len and tally_abs (with ``weight``); ``enter``:
+    rays from outside the box start where they enter it. Returns a dict of
+    device tensors."""
     o = _dev_f64(origins, 3)
     d = _dev_f64(dirs, 3)
     rho = None if density is None else _dev_f64(density).reshape(-1)
@@ -382,7 +384,7 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
     t_len = torch.zeros(grid.M, dtype=torch.float64, device="cuda") if tallies else None
     t_abs = torch.zeros(grid.M, dtype=torch.float64, device="cuda") if tallies else None
     kw = dict(kappa=kappa, mode=mode, max_steps=max_steps, eps_mix=eps_mix, persistent=persistent, ordered=ordered,
-              stream=stream, tau_stop=ts, weight=wt, tally_len=t_len, tally_abs=t_abs)
+              stream=stream, tau_stop=ts, weight=wt, tally_len=t_len, tally_abs=t_abs, enter=enter)
     lf = dict(ordered=ordered, locate_first=locate_first, stops=ts is not None)
     if segments == "none":
         b = TraceBuffers(n, **lf)

@@ -262,6 +262,47 @@ def test_no_exit_fallback_recovers(vrt):
     assert n_clean > 0.3 * w.N
 
 
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_rays_from_outside_enter_the_box(vrt, mode, persistent):
+    """opts.enter: rays from outside start where they enter the box
+    (distances from the origin); rays that miss it, or point away, are
+    OUTSIDE; origins inside are unaffected. Against the oracle's entry."""
+    w = W.uniform_cube(M=1000, N=6000, seed=71)
+    k = w.dirs / np.linalg.norm(w.dirs, axis=1)[:, None]
+    o = w.origins - 4.0 * k                  # outside, heading for the cube
+    d = k.copy()
+    o[:1000] = w.origins[:1000]              # inside
+    d[1000:1500] = -k[1000:1500]             # outside, heading away: misses
+    o[1500:1600, 0] = 3.0                    # outside, moving parallel to the x walls: misses
+    d[1500:1600, 0] = 0.0
+    ref = oracle.trace(w.sites, w.box, w.density, o, d, cap=64, enter=True)
+    assert (ref["status"] == oracle.ST_OUTSIDE).sum() >= 600 and (ref["start_s"] > 0).sum() > 4000
+    out = vrt.trace(vrt_grid(vrt, w), o, d, w.density, mode=mode, segments="exact", persistent=persistent,
+                    ordered=persistent, enter=True)
+    p = gpu_paths(out)
+    st = compare(p, ref, TOL[mode])
+    assert st["clean"] > 0.95 * (ref["status"] == 0).sum()
+    if mode == "fp64":
+        assert st["max_len_diff"] == 0.0 and st["max_tau_diff"] == 0.0
+    # interaction where the path starts for tau_stop <= 0: at the entry point
+    ts = np.zeros(w.N)
+    out = vrt.trace(vrt_grid(vrt, w), o, d, w.density, mode=mode, segments="none", persistent=persistent,
+                    enter=True, tau_stop=ts)
+    ok = ref["status"] == 0
+    assert np.array_equal(out["stop_s"].cpu().numpy()[ok], ref["start_s"][ok])
+
+
+_GRIDS = {}
+
+
+def vrt_grid(vrt, w):
+    key = (w.name, w.M, float(w.sites[0, 0]))
+    if key not in _GRIDS:
+        _GRIDS[key] = vrt.build_grid(w.sites, w.box)
+    return _GRIDS[key]
+
+
 def test_mixed_equals_fp64_bitwise(vrt):
     w = W.exp_disc(M=20_000, N=200_000, seed=77)
     grid = vrt.build_grid(w.sites, w.box)
