@@ -117,6 +117,14 @@ void vor_grid_free(vor_grid *grid);
 vor_status vor_grid_get_info(const vor_grid *grid, vor_grid_info *info);
 
 /*
+ * vor_grid_volumes -- the volume of every clipped cell (Sect. 2.1: the box
+ * cut by the bisector half-spaces), from the builder's own clipped
+ * polyhedra: the sum over the faces of the cone volumes h * area / 3 from
+ * the site. volume: device, M doubles, user order. Asynchronous on `stream`.
+ */
+vor_status vor_grid_volumes(const vor_grid *grid, double *volume, void *stream);
+
+/*
  * Diagnostic: keeps only the first `keep` entries (internal order) of the
  * neighbour list of site `site` (user index), so that the table misses
  * faces of that cell and paths through it take the no-exit fallback of

@@ -99,6 +99,7 @@ struct ClipArgs {
     int32_t *retry;           // [M] sites whose cell needs the large capacity
     int32_t *n_retry;
     int *err;
+    double *volume;           // [M] cell volumes
 };
 
 // First pass: one wave per site with a small cell in LDS; cells that run
@@ -108,8 +109,10 @@ __global__ void __launch_bounds__(64) k_clip(ClipArgs A)
     __shared__ WaveCellSmall cell;
     const int64_t i = blockIdx.x;
     uint8_t wm = 0;
-    int n = wclip_site(cell, A.sites, A.grid, A.box, i, A.nbr + i * kMaxNbr, kMaxNbr, &wm);
+    double vol = 0.0;
+    int n = wclip_site(cell, A.sites, A.grid, A.box, i, A.nbr + i * kMaxNbr, kMaxNbr, &wm, &vol);
     if (threadIdx.x == 0) {
+        A.volume[i] = vol;
         if (n == -ERR_CAPACITY) {
             A.retry[atomicAdd(A.n_retry, 1)] = (int32_t)i;
             n = 0;
@@ -129,8 +132,10 @@ __global__ void __launch_bounds__(64) k_clip_big(ClipArgs A, int32_t *__restrict
     const int k = blockIdx.x;
     const int64_t i = A.retry[k];
     uint8_t wm = 0;
-    int n = wclip_site(cell, A.sites, A.grid, A.box, i, big_nbr + (int64_t)k * kMaxNbrBig, kMaxNbrBig, &wm);
+    double vol = 0.0;
+    int n = wclip_site(cell, A.sites, A.grid, A.box, i, big_nbr + (int64_t)k * kMaxNbrBig, kMaxNbrBig, &wm, &vol);
     if (threadIdx.x == 0) {
+        A.volume[i] = vol;
         slot[i] = k;
         if (n < 0) {
             atomicOr(A.err, -n);
@@ -365,6 +370,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     g.perm = dalloc<int32_t>(M, rc, keep);
     g.inv_perm = dalloc<int32_t>(M, rc, keep);
     g.wall_mask = dalloc<uint8_t>(M, rc, keep);
+    g.volume = dalloc<double>(M, rc, keep);
     g.bucket_sites = dalloc<Site>(M, rc, keep);
 
     // bucket grid dimensions: about `occ` sites per bucket, cube-like buckets
@@ -444,6 +450,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     ca.retry = retry;
     ca.n_retry = err + 2;
     ca.err = err;
+    ca.volume = g.volume;
     if (hipMemsetAsync(slot, 0xff, sizeof(int32_t) * M, st) != hipSuccess) return fail(VOR_EDEVICE);
     hipLaunchKernelGGL(k_clip, dim3((unsigned)M), dim3(64), 0, st, ca);
     if (hipGetLastError() != hipSuccess) return fail(VOR_EDEVICE);
@@ -522,7 +529,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     g.max_row = mrow;
 
     for (void *p : tmp) (void)hipFree(p);
-    g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2)) + (B + 1) * 4 +
+    g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + sizeof(double)) + (B + 1) * 4 +
                      (g.nnz + kRecPad) * (int64_t)(sizeof(Rec64) + sizeof(Rec32));
     g.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = G;
@@ -534,7 +541,8 @@ extern "C" void vor_grid_free(vor_grid *G)
     if (!G) return;
     (void)hipDeviceSynchronize();
     Grid &g = G->g;
-    void *ptrs[] = {g.sites, g.perm, g.inv_perm, g.rows, g.rec64, g.rec32, g.wall_mask, g.bucket_start, g.bucket_sites};
+    void *ptrs[] = {g.sites, g.perm, g.inv_perm, g.rows, g.rec64, g.rec32, g.wall_mask, g.volume, g.bucket_start,
+                    g.bucket_sites};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete G;
@@ -587,6 +595,23 @@ extern "C" vor_status vor_grid_truncate_row(vor_grid *G, int64_t site, int32_t k
         if (hipMemcpy(g.rows + i, &rw, sizeof(rw), hipMemcpyHostToDevice) != hipSuccess) return VOR_EDEVICE;
     }
     return VOR_OK;
+}
+
+__global__ void k_export_volumes(const int32_t *__restrict__ perm, const double *__restrict__ vol, int64_t M,
+                                 double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) out[perm[i]] = vol[i];
+}
+
+extern "C" vor_status vor_grid_volumes(const vor_grid *G, double *volume, void *stream)
+{
+    if (!G || !volume) return VOR_EINVAL;
+    const Grid &g = G->g;
+    const int T = 256;
+    hipLaunchKernelGGL(k_export_volumes, dim3(blocks_for(g.M, T)), dim3(T), 0, (hipStream_t)stream, g.perm, g.volume,
+                       g.M, volume);
+    return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
 // accessor for the other translation units

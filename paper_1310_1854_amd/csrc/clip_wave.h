@@ -367,9 +367,44 @@ __device__ void sort_candidates(C &c, int n)
 // Clip site i's cell. Writes the neighbour indices to nbr (capacity
 // max_nbr) and the wall mask to *walls; returns the count or -ERR_*.
 // All lanes of the wave call it with the same i.
+// Volume of the clipped cell (nt vertices), by the whole wave. The cell is
+// the union of the cones from the site (the origin here) to its faces, so
+// V = sum over faces x of (h_x / 3) * area_x, with h_x = d_x / |n_x| the
+// distance of plane x from the site. Around face x the vertices come in a
+// cyclic order: from vertex t = (x, y, z) (oriented) the next is the vertex
+// holding the reversed edge (y, x), the other end of the polyhedron edge
+// between faces x and y; so 2 area_x = |sum over the face's vertices of
+// n_x / |n_x| . (v_t x v_next)|, with one orientation for every face.
+template <class C>
+__device__ double wcell_volume(const C &c, int nt)
+{
+    double acc = 0.0;
+    for (int t = lane_id(); t < nt; t += 64) {
+        const uint32_t u = c.tri[t];
+        const int corner[3] = {(int)(u & 255), (int)((u >> 8) & 255), (int)((u >> 16) & 255)};
+        for (int e = 0; e < 3; ++e) {
+            const int x = corner[e], y = corner[(e + 1) % 3];
+            int t2 = -1;
+            for (int s = 0; s < nt && t2 < 0; ++s) {
+                const uint32_t w = c.tri[s];
+                const int a = w & 255, b = (w >> 8) & 255, cc = (w >> 16) & 255;
+                if ((a == y && b == x) || (b == y && cc == x) || (cc == y && a == x)) t2 = s;
+            }
+            if (t2 < 0) continue;   // cannot happen in a closed cell
+            const double cx = c.vy[t] * c.vz[t2] - c.vz[t] * c.vy[t2];
+            const double cy = c.vz[t] * c.vx[t2] - c.vx[t] * c.vz[t2];
+            const double cz = c.vx[t] * c.vy[t2] - c.vy[t] * c.vx[t2];
+            const double nn = c.nx[x] * c.nx[x] + c.ny[x] * c.ny[x] + c.nz[x] * c.nz[x];
+            acc += c.d[x] / nn * (c.nx[x] * cx + c.ny[x] * cy + c.nz[x] * cz);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    return fabs(acc) / 6.0;
+}
+
 template <class C>
 __device__ int wclip_site(C &c, const Site *__restrict__ sites, const BucketGridView &grid, const BoxArg &box,
-                          int64_t i, int32_t *nbr, int max_nbr, uint8_t *walls)
+                          int64_t i, int32_t *nbr, int max_nbr, uint8_t *walls, double *volume = nullptr)
 {
     const int l = lane_id();
     const uint64_t lt = lanemask_lt();
@@ -447,6 +482,7 @@ __device__ int wclip_site(C &c, const Site *__restrict__ sites, const BucketGrid
         if (lb * lb > 4.0 * r2 * (1.0 + 1e-9)) break;
     }
     if (err) return -err;
+    if (volume) *volume = wcell_volume(c, nt);
     // faces: plane slots some vertex still uses
     constexpr int W = (C::kPlanes + 63) / 64;
     uint64_t used[W];

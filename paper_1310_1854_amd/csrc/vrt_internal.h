@@ -57,6 +57,7 @@ struct Grid {
     Rec64 *rec64 = nullptr;         // [nnz + kRecPad]
     Rec32 *rec32 = nullptr;         // [nnz + kRecPad]
     uint8_t *wall_mask = nullptr;   // [M] bit w set if wall -(w+1) is a face
+    double *volume = nullptr;       // [M] volume of each clipped cell
     int32_t *bucket_start = nullptr;// [B + 1]
     Site *bucket_sites = nullptr;   // [M] sites grouped by bucket (uid holds the internal index)
     double build_ms = 0;

@@ -29,7 +29,7 @@ EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_nei
            "vor_trace", "vor_order_rays", "vor_order_workspace_bytes", "vor_exclusive_scan", "vor_status_str", "vor_version",
            "vor_server_create", "vor_server_submit", "vor_server_poll", "vor_server_wait", "vor_server_result",
            "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy",
-           "vor_server_next_done", "vor_grid_truncate_row"]
+           "vor_server_next_done", "vor_grid_truncate_row", "vor_grid_volumes"]
 
 
 class VorError(RuntimeError):
@@ -95,6 +95,8 @@ def load(path: str = None):
     lib.vor_grid_free.restype = None
     lib.vor_grid_get_info.argtypes = [P, ctypes.POINTER(GridInfo)]
     lib.vor_grid_get_info.restype = ctypes.c_int
+    lib.vor_grid_volumes.argtypes = [P, P, P]
+    lib.vor_grid_volumes.restype = ctypes.c_int
     lib.vor_grid_truncate_row.argtypes = [P, I64, I32]
     lib.vor_grid_truncate_row.restype = ctypes.c_int
     lib.vor_grid_neighbors.argtypes = [P, P, P, P]
@@ -188,6 +190,12 @@ class Grid:
         col = torch.empty(max(inf["nnz_with_walls"], 1), dtype=torch.int32, device="cuda")
         _check(load().vor_grid_neighbors(self._h, _ptr(row_ptr), _ptr(col), _stream(stream)), "vor_grid_neighbors")
         return row_ptr, col[: inf["nnz_with_walls"]]
+
+    def volumes(self, stream=None) -> torch.Tensor:
+        """Volume of every cell (user order), from the builder's clipped cells."""
+        out = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        _check(load().vor_grid_volumes(self.handle, _ptr(out), _stream(stream)), "vor_grid_volumes")
+        return out
 
     def truncate_row(self, site: int, keep: int) -> None:
         """Diagnostic (vor_grid_truncate_row): drop faces of one cell from the

@@ -340,6 +340,27 @@ def _rows(rp, col, i):
 
 
 @pytest.mark.parametrize("case", ["cube", "disc_small", "lattice"])
+def test_cell_volumes_vs_oracle(vrt, case):
+    """Cell volumes from the builder's polyhedra against the oracle's
+    (clipped face polygons), and their sum against the box."""
+    if case == "cube":
+        w = W.uniform_cube(M=1500, N=1, seed=12)
+    elif case == "disc_small":
+        w = W.flared_disc(M=3000, N=1, seed=13)
+    else:
+        w = W.cubic_lattice(5, N=1)
+    grid = vrt.build_grid(w.sites, w.box)
+    vol = grid.volumes().cpu().numpy()
+    _, ref = oracle.faces(w.sites, w.box, np.arange(w.M), cap=512)
+    box = np.asarray(w.box, float)
+    total = float(np.prod(box[3:] - box[:3]))
+    assert abs(vol.sum() - total) <= 1e-10 * total
+    assert np.max(np.abs(vol - ref) / ref) <= 1e-9
+    if case == "lattice":
+        assert np.allclose(vol, total / w.M, rtol=1e-12, atol=0)   # every lattice cell is the same cuboid
+
+
+@pytest.mark.parametrize("case", ["cube", "disc_small", "lattice"])
 def test_neighbour_lists_vs_oracle_faces(vrt, case):
     if case == "cube":
         w = W.uniform_cube(M=1500, N=1, seed=12)
