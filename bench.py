@@ -17,7 +17,8 @@ roofline.traffic is the trace kernel's HBM traffic per launch from the
 committed hardware-counter summary (profiles/), reported only while the
 kernel sources still hash to the value recorded there (else null).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload flared_disc|exp_disc|clumpy|uniform_cube|serving]
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+                    [--workload flared_disc|exp_disc|clumpy|uniform_cube|flared_disc_transport|serving|grid_quality]
 """
 from __future__ import annotations
 
@@ -204,6 +205,61 @@ def cpu_baseline(w, spec, oracle):
                           sample=f"{n} of the {w.N} rays (seeded subsample), {crossings} crossings in {dt:.1f} s")
 
 
+def grid_quality(args, torch, vrt, workloads):
+    """Grid quality (Sect. 3.3, the Table 1 method): the theoretical density
+    rho_t and the gridded density rho_g (the density of the cell that holds
+    the point, i.e. at its site) at 10^7 points uniform over the box;
+    quality = the standard deviation of rho_t - rho_g. The hot part is
+    vor_locate over the points (timed with HIP events). For each disc the
+    sites drawn from the density (the workload's placement) are compared
+    with as many uniform sites. The cells of 2000 of the points are checked
+    against the oracle's brute-force locate."""
+    import oracle
+    n_pts = 10_000_000
+    out = {}
+    for name, cfg in (("exp_disc", 1), ("flared_disc", 2)):
+        w = workloads.make_config(cfg)
+        field = workloads.DENSITY_FIELDS[name]
+        pts = workloads.grid_quality_points(w.box, n_pts)
+        rho_t = field(pts)
+        dev_pts = torch.as_tensor(pts, device="cuda")
+        cell = torch.empty(n_pts, dtype=torch.int32, device="cuda")
+        res = {}
+        for placement in ("density", "uniform"):
+            sites = w.sites if placement == "density" else workloads.uniform_in_box(
+                np.random.default_rng(7), w.M, w.box)
+            rho_site = field(sites)
+            grid = vrt.build_grid(sites, w.box)
+            vrt.load().vor_locate(grid.handle, vrt._ptr(dev_pts), n_pts, vrt._ptr(cell), vrt._stream())
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                vrt.load().vor_locate(grid.handle, vrt._ptr(dev_pts), n_pts, vrt._ptr(cell), vrt._stream())
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            c = cell.cpu().numpy()
+            diff = rho_t - rho_site[c]
+            sample = slice(0, 2_000)
+            ref, _ = oracle.locate(sites, w.box, pts[sample])
+            res[placement] = {"sigma": float(diff.std()), "sigma_rel_mean": float(diff.std() / rho_t.mean()),
+                              "locate_ms": ms, "points_per_s": n_pts / (ms / 1e3),
+                              "oracle_cell_mismatches": int((ref != c[sample]).sum())}
+            print(f"[bench] grid quality {name} {placement}: {res[placement]}", file=sys.stderr, flush=True)
+            grid.free()
+        res["uniform_over_density_sigma"] = res["uniform"]["sigma"] / res["density"]["sigma"]
+        out[name] = dict(sites=w.M, points=n_pts, **res)
+    best = out["flared_disc"]["density"]
+    result = {"metric": "grid quality: std of rho_t - rho_g at uniform points (Sect. 3.3); locate points/s",
+              "value": best["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+              "ms_per_step": best["locate_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": "f64", "data": "synthetic",
+              "config": {"workload": "grid quality: 10^7 uniform points located on the 10^5-site exponential "
+                                     "disc and the 10^6-site flared disc"}, "grids": out}
+    print(json.dumps(result), flush=True)
+
+
 def serving(args, torch, vrt, workloads):
     """Serving mix: three resident grids (10^4, 10^5, 10^6 sites shaped like
     the uniform cube, the exponential disc and the flared disc), Poisson
@@ -298,7 +354,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="flared_disc", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--workload", default="flared_disc", choices=sorted(WORKLOADS) + ["serving", "grid_quality"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=5)
@@ -320,6 +376,9 @@ def main(argv=None):
     if args.workload == "serving":
         torch.cuda.set_device(0)
         return serving(args, torch, vrt, workloads)
+    if args.workload == "grid_quality":
+        torch.cuda.set_device(0)
+        return grid_quality(args, torch, vrt, workloads)
     spec = WORKLOADS[args.workload]
     mode = spec["mode"]
     torch.cuda.set_device(0)

@@ -335,6 +335,18 @@ def serving_requests(n_req: int, grids, rate_hz: float, seed: int = SEED_BASE + 
     return reqs
 
 
+def grid_quality_points(box, n: int, seed: int = SEED_BASE + 6) -> np.ndarray:
+    """n points uniform over the box: where the theoretical and the gridded
+    density are compared (the grid-quality measure of Sect. 3.3)."""
+    return uniform_in_box(np.random.default_rng(seed), n, box)
+
+
+DENSITY_FIELDS = {
+    "exp_disc": exp_disc_density,
+    "flared_disc": flared_disc_density,
+}
+
+
 CONFIGS = {
     0: uniform_cube,
     1: exp_disc,

@@ -331,6 +331,25 @@ def test_locate_matches_oracle(vrt, cfg):
     assert np.array_equal(cell[20_011:20_511], np.arange(500))
 
 
+def test_grid_quality_measure(vrt):
+    """The grid-quality measure of Sect. 3.3 (std of rho_t - rho_g at uniform
+    points, rho_g the density of the cell holding the point) from the GPU's
+    locate equals the oracle's exactly; sites drawn from the density
+    represent it better than as many uniform sites."""
+    sig = {}
+    for placement in ("density", "uniform"):
+        w = W.exp_disc(M=20_000, N=1, seed=91)
+        sites = w.sites if placement == "density" else W.uniform_in_box(np.random.default_rng(5), w.M, w.box)
+        pts = W.grid_quality_points(w.box, 20_000, seed=92)
+        rho_t = W.exp_disc_density(pts)
+        rho_s = W.exp_disc_density(sites)
+        cell = vrt.locate(vrt.build_grid(sites, w.box), pts).cpu().numpy()
+        ref, _ = oracle.locate(sites, w.box, pts)
+        assert np.array_equal(cell, ref)
+        sig[placement] = float(np.std(rho_t - rho_s[cell]))
+    assert sig["density"] < sig["uniform"]
+
+
 # --------------------------------------------------------------------------
 # neighbour lists against the oracle's brute-force faces
 # --------------------------------------------------------------------------
