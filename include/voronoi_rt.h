@@ -160,8 +160,8 @@ vor_status vor_locate(const vor_grid *grid, const double *pts, int64_t N, int32_
 typedef struct {
     int32_t mode;           /* VOR_MODE_FP64 (default) or VOR_MODE_MIXED */
     int32_t max_steps;      /* per-ray cap on cell moves; 0 = M + 16 */
-    double eps_mix;         /* mixed mode: relative rounding allowance of the FP32 crossing bound; 0 = 2^-19,
-                               else in [2^-19, 0.25] (larger values only redo more steps in FP64) */
+    double eps_mix;         /* mixed mode: relative rounding allowance of the FP32 crossing bound; 0 = 2^-20,
+                               else in [2^-20, 0.25] (larger values only redo more steps in FP64) */
     int32_t persistent;     /* 1: persistent kernel whose waves refill finished lanes from a work queue */
     int32_t start_given;    /* 1: out->start_cell already holds the start cells of these rays, left there by
                                an earlier call on the same grid with the same origins (another density,

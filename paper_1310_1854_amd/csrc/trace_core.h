@@ -59,9 +59,9 @@ struct SegOut {
     unsigned long long *chunk_head; // chunks handed out
 };
 
-// Smallest accepted eps of the mixed-mode bound (2^-19): 2.6 times what the
-// first-order rounding analysis needs.
-constexpr double kEpsMixMin = 1.9073486328125e-06;
+// Smallest accepted eps of the mixed-mode bound (2^-20 = 16u): twice what
+// the rounding analysis of exit_mixed needs.
+constexpr double kEpsMixMin = 9.5367431640625e-07;
 
 // Mixed mode keeps offsets, points and bounds in FP32: the box must lie
 // well inside the FP32 range.
@@ -199,17 +199,24 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
 // rounded to FP32), with one hardware reciprocal (error <= 1 ulp) for
 // 1/(n.k) and a bound on how far the FP32 crossing t can be from the one
 // exit_fp64 computes:
-//   err = [eps (1.5 |n|^2 + 0.5 (|q| + |t|)^2) + e_abs |n|_1] / (n.k) + 6u |t|
-// (u = 2^-24). eps >= 12u covers the rounding of n, q, k and of the
-// products and sums (fused or not) to first order (|n|(|q|+|t|) <= (|n|^2 + (|q|+|t|)^2)/2 turns
-// the cross terms into this form); 6u |t| covers the reciprocal, the
-// product and the roundings of t - err and t + err; e_abs |n|_1 / (n.k)
+//   err = [eps (0.375 |n|^2 + 0.75 |n|_1 (|q| + |t|)) + e_abs |n|_1] / (n.k) + 7u |t|
+// (u = 2^-24). Rounding n, q and k to FP32 and the three-term fused dot
+// products leave |d(n.n)| <= 5u |n|^2, |d(n.q)| <= 5u |n||q| and
+// |d(n.k)| <= 5u |n| (also <= 5u |n|_1), so the FP32 t differs from the
+// exact one by at most F [2.5u |n|^2 + 5u |n| (|q| + |t|)] / (n.k) plus
+// 4.2u F |t| (the rounding of the numerator, the reciprocal and the
+// product), where F = 1 / (1 - |d(n.k)| / (n.k) - 1.2u) accounts for using
+// the FP32 n.k and t. The FP32 n.k is trusted only above 4d, d = 8u |n|_1
+// (the largest error of n.k, with room), so F <= 1.19: at eps = 16u the
+// two eps terms are twice the 3u |n|^2 and 6u |n| (|q| + |t|) needed
+// (|n|_1 >= |n|), and 7u |t| covers 5u |t| plus the rounding of t - err
+// and t + err. The cross term is kept linear in |t|: nearly parallel
+// planes have a large t, and a bound quadratic in |t| would send their
+// lower bounds below zero and force needless FP64 steps. e_abs |n|_1 / (n.k)
 // covers the FP64 roundings of exit_fp64 itself (2^-48 times twice the
-// largest box coordinate plus the box diagonal). The error of the FP32 n.k
-// is at most d = 8u |n|_1; planes with n.k > 2d have an FP64 n.k > 0 and a
-// first-order bound that holds (the relative error of n.k is below 1/2 and
-// eps is 2.6 times the first-order need); planes with n.k <= -d have an
-// FP64 n.k <= 0 and are skipped as exit_fp64 skips them; a plane in between
+// largest box coordinate plus the box diagonal). Planes with n.k > 4d have
+// an FP64 n.k > 0 and this bound; planes with n.k <= -d have an FP64
+// n.k <= 0 and are skipped as exit_fp64 skips them; a plane in between
 // (nearly parallel to the ray) gets lower bound -inf and forces the FP64
 // decision. If the upper bound of the best candidate is below the lower
 // bound of every other one (the wall included), the FP32 ranking is certain
@@ -222,7 +229,7 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
 struct Query32 {
     float qx, qy, qz, qa;   // q = r - p_m and |q|
     float kx, ky, kz;
-    float c1, c2, e_abs;    // 1.5 eps, 0.5 eps, FP64 allowance
+    float c1, c2, e_abs;    // 0.375 eps, 0.75 eps, FP64 allowance
 };
 
 __device__ __forceinline__ Query32 query32(const double pm[3], const double r0[3], const double k[3], double s_c,
@@ -238,8 +245,8 @@ __device__ __forceinline__ Query32 query32(const double pm[3], const double r0[3
     Q.ky = (float)k[1];
     Q.kz = (float)k[2];
     Q.qa = sqrtf(Q.qx * Q.qx + Q.qy * Q.qy + Q.qz * Q.qz);
-    Q.c1 = 1.5f * eps;
-    Q.c2 = 0.5f * eps;
+    Q.c1 = 0.375f * eps;
+    Q.c2 = 0.75f * eps;
     Q.e_abs = e_abs;
     return Q;
 }
@@ -265,14 +272,14 @@ __device__ __forceinline__ void plane_bound32(const Rec32 &r, const Query32 &Q, 
     const float num = fmaf(0.5f, nn, -nq);
     const float n1 = fabsf(nx) + fabsf(ny) + fabsf(nz);
     const float d = 8.0f * u * n1;
-    pos = den > fmaxf(2.0f * d, 1.17549435e-38f);
+    pos = den > fmaxf(4.0f * d, 1.17549435e-38f);
     maybe = den > -d;
     const float rc = __builtin_amdgcn_rcpf(den);
     t = num * rc;
     const float at = fabsf(t);
     const float sq = Q.qa + at;
-    const float E = fmaf(Q.c2 * sq, sq, fmaf(Q.c1, nn, Q.e_abs * n1));
-    err = fmaf(E, rc, 6.0f * u * at);
+    const float E = fmaf(Q.c1, nn, n1 * fmaf(Q.c2, sq, Q.e_abs));
+    err = fmaf(E, rc, 7.0f * u * at);
 }
 
 __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const Rec32 *__restrict__ rec32, int2 rw,
