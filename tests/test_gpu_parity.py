@@ -314,6 +314,71 @@ def test_mixed_equals_fp64_bitwise(vrt):
     assert b["counters"][2].item() > 0      # some steps were re-decided in FP64
 
 
+def _grazing_dirs(rng, nhat, tilts):
+    """Unit directions perpendicular to nhat, tilted towards it by a tilt
+    drawn from tilts with a random sign (nhat: unit normals, one a row)."""
+    a = rng.normal(size=nhat.shape)
+    perp = a - (a * nhat).sum(1, keepdims=True) * nhat
+    perp /= np.linalg.norm(perp, axis=1, keepdims=True)
+    tilt = tilts[rng.integers(0, len(tilts), len(nhat))] * rng.choice([-1.0, 1.0], len(nhat))
+    return np.ascontiguousarray(perp + tilt[:, None] * nhat)
+
+
+# tilts around the band where the FP32 n.k of a face is not trusted (about
+# 1e-6 of |n|) and the one where the FP32 crossing of a face the ray runs
+# along is far off and has a wide bound
+GRAZING_TILTS = np.array([0.0, 1e-9, 1e-7, 5e-7, 2e-6, 1e-5, 1e-4, 1e-3])
+
+
+def _mixed_vs_fp64(vrt, grid, w):
+    import torch
+    a = vrt.trace(grid, w.origins, w.dirs, w.density, mode="fp64", segments="exact")
+    b = vrt.trace(grid, w.origins, w.dirs, w.density, mode="mixed", segments="exact")
+    for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+        assert torch.equal(a[k], b[k]), k
+    return gpu_paths(a), int(b["counters"][2].item())
+
+
+def test_mixed_equals_fp64_on_grazing_rays(vrt):
+    """Rays that run nearly parallel to a face: every step is either decided
+    in FP64 or certified by the FP32 bound, so the mixed paths equal the FP64
+    ones bit for bit, and the FP64 paths equal the oracle's (Sect. 2.2)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(1310)
+    # random sites; each ray starts between a site and its nearest neighbour
+    # (a Voronoi neighbour), 1e-9 to 0.1 of their distance off the bisector
+    # plane, and runs nearly parallel to that plane
+    w = W.uniform_cube(M=3000, N=1, seed=4301)
+    _, nb = cKDTree(w.sites).query(w.sites, k=2)
+    n_r = 4000
+    i = rng.integers(0, w.M, n_r)
+    nvec = w.sites[nb[i, 1]] - w.sites[i]
+    nhat = nvec / np.linalg.norm(nvec, axis=1, keepdims=True)
+    off = 10.0 ** rng.uniform(-9, -1, n_r)
+    w.origins = np.ascontiguousarray(w.sites[i] + (0.5 - off)[:, None] * nvec)
+    w.dirs = _grazing_dirs(rng, nhat, GRAZING_TILTS)
+    grid = vrt.build_grid(w.sites, w.box)
+    p, redo = _mixed_vs_fp64(vrt, grid, w)
+    assert redo > 0                          # the untrusted band was hit
+    ref = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    st = compare(p, ref, TOL["fp64"])
+    assert st["max_len_diff"] == 0.0 and st["max_tau_diff"] == 0.0
+    assert st["clean"] > 0.8 * n_r          # the rest start within 1e-9 of a face (near-ties)
+
+    # the cubic lattice: rays nearly along its faces from random points
+    w = W.cubic_lattice(8, N=3000, seed=4302)
+    axes = np.eye(3)[rng.integers(0, 3, w.N)]
+    w.dirs = _grazing_dirs(rng, axes, GRAZING_TILTS)
+    grid = vrt.build_grid(w.sites, w.box)
+    p, redo = _mixed_vs_fp64(vrt, grid, w)
+    assert redo > 0
+    for r in range(w.N):
+        c, l, L = lattice_path(w.meta["xs"], w.meta["ys"], w.meta["zs"], w.box, w.origins[r], w.dirs[r])
+        o, n = int(p["ray_off"][r]), int(p["n_seg"][r])
+        assert list(p["seg_cell"][o:o + n]) == c, r
+        assert np.max(np.abs(p["seg_len"][o:o + n] - np.array(l))) <= 1e-12 * L, r
+
+
 # --------------------------------------------------------------------------
 # locate
 # --------------------------------------------------------------------------
