@@ -187,49 +187,52 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
     return win;
 }
 
-// Mixed-precision exit search. Returns the winning record index (-1: the
-// chord end, best = L), with redo set when the step was decided in FP64
-// (then best is the FP64 crossing); otherwise j1 is the winner's internal
-// index and the caller computes its FP64 crossing from the site (fetched
-// together with the winner's row). Either way the result equals
-// exit_fp64's.
+// Mixed-precision exit search. Returns -1 when the chord end wins
+// (best = L), else a non-negative value; redo is set when the step was
+// decided in FP64 (then the return value is the winning record index and
+// best the FP64 crossing); otherwise j1 is the winner's internal index and
+// the caller computes its FP64 crossing from the site (fetched together
+// with the winner's row). Either way the result equals exit_fp64's.
 //
 // Each plane is ranked in FP32 from its stored offset n = p_j - p_m
 // (rounded once to FP32), the current point q = r - p_m and k (both
-// rounded to FP32), with one hardware reciprocal (error <= 1 ulp) for
-// 1/(n.k) and a bound on how far the FP32 crossing t can be from the one
-// exit_fp64 computes:
-//   err = [eps (0.375 |n|^2 + 0.75 |n|_1 (|q| + |t|)) + e_abs |n|_1] / (n.k) + 7u |t|
-// (u = 2^-24). Rounding n, q and k to FP32 and the three-term fused dot
-// products leave |d(n.n)| <= 5u |n|^2, |d(n.q)| <= 5u |n||q| and
-// |d(n.k)| <= 5u |n| (also <= 5u |n|_1), so the FP32 t differs from the
-// exact one by at most F [2.5u |n|^2 + 5u |n| (|q| + |t|)] / (n.k) plus
-// 4.2u F |t| (the rounding of the numerator, the reciprocal and the
-// product), where F = 1 / (1 - |d(n.k)| / (n.k) - 1.2u) accounts for using
-// the FP32 n.k and t. The FP32 n.k is trusted only above 4d, d = 8u |n|_1
-// (the largest error of n.k, with room), so F <= 1.19: at eps = 16u the
-// two eps terms are twice the 3u |n|^2 and 6u |n| (|q| + |t|) needed
-// (|n|_1 >= |n|), and 7u |t| covers 5u |t| plus the rounding of t - err
-// and t + err. The cross term is kept linear in |t|: nearly parallel
-// planes have a large t, and a bound quadratic in |t| would send their
-// lower bounds below zero and force needless FP64 steps. e_abs |n|_1 / (n.k)
-// covers the FP64 roundings of exit_fp64 itself (2^-48 times twice the
-// largest box coordinate plus the box diagonal). Planes with n.k > 4d have
-// an FP64 n.k > 0 and this bound; planes with n.k <= -d have an FP64
-// n.k <= 0 and are skipped as exit_fp64 skips them; a plane in between
-// (nearly parallel to the ray) gets lower bound -inf and forces the FP64
-// decision. If the upper bound of the best candidate is below the lower
-// bound of every other one (the wall included), the FP32 ranking is certain
-// and only the winner's crossing is recomputed in FP64 (from its site, same
-// arithmetic as exit_fp64); otherwise the step is redone in FP64.
+// rounded to FP32): t = n.(n/2 - q) / (n.k), with n/2 - q formed by one
+// fused operation per axis and one hardware reciprocal (error <= 1 ulp) for
+// 1/(n.k), and a bound on how far t can be from the crossing exit_fp64
+// computes:
+//   err = |n|_1 [c (|q| + |t|) + e_abs] / (n.k),   c = 3 eps
+// (u = 2^-24; eps >= 16u). First order, the roundings of n, q, k, of n/2 - q
+// and of the two three-term fused dot products move the numerator by at
+// most 3u |n|^2 + 6u |n||q| and n.k by at most 5u |n| (also 5u |n|_1). The
+// crossing point x = q + t k lies on the plane, n.x = |n|^2 / 2, so
+// |n|^2 <= 2 |n| (|q| + |t|), and the error of t is at most
+// 12u |n| (|q| + |t|) / (n.k) plus 3u |t| (reciprocal and product) --
+// measured against the exact t; with the FP32 n.k trusted only above 4d,
+// d = 8u |n|_1 (above the largest error of n.k), 12u |n| / (n.k) <= 0.38,
+// so against the FP32 t it is at most 19.3u |n| (|q| + |t|) / (n.k) +
+// 4.9u |t|. As |n| / (n.k) >= 1 the last term folds into the first, and
+// with the roundings of the bound itself and of t - err, t + err the need
+// is 25.2u |n| (|q| + |t|) / (n.k): c = 48u covers it 1.9 times over
+// (|n|_1 >= |n|). The bound is linear in |t|: nearly parallel planes have a
+// large t and must not get a wide bound. e_abs |n|_1 / (n.k) covers the
+// FP64 roundings of exit_fp64 itself (2^-48 times twice the largest box
+// coordinate plus the box diagonal). Planes with n.k > 4d have an FP64
+// n.k > 0 and this bound; planes with n.k <= -4d have an FP64 n.k <= 0 and
+// are skipped as exit_fp64 skips them; a plane in between (nearly parallel
+// to the ray) forces the FP64 decision. 4d has a floor of the smallest
+// normal float, so planes with a tiny n fall in between too. If the upper
+// bound of the best candidate is below the lower bound of every other one
+// (the wall included), the FP32 ranking is certain and only the winner's
+// crossing is recomputed in FP64 (from its site, same arithmetic as
+// exit_fp64); otherwise the step is redone in FP64.
 // Records are loaded a whole batch at a time, unconditionally (the record
 // arrays are padded for the last row); entries past the row end are masked.
 // The current point and direction of a ray in FP32, with the constants of
-// the mixed-mode bound (below).
+// the mixed-mode bound.
 struct Query32 {
-    float qx, qy, qz, qa;   // q = r - p_m and |q|
+    float qx, qy, qz;       // q = r - p_m
     float kx, ky, kz;
-    float c1, c2, e_abs;    // 0.375 eps, 0.75 eps, FP64 allowance
+    float c, a;             // 3 eps and c |q| + e_abs (the FP64 allowance)
 };
 
 __device__ __forceinline__ Query32 query32(const double pm[3], const double r0[3], const double k[3], double s_c,
@@ -244,10 +247,8 @@ __device__ __forceinline__ Query32 query32(const double pm[3], const double r0[3
     Q.kx = (float)k[0];
     Q.ky = (float)k[1];
     Q.kz = (float)k[2];
-    Q.qa = sqrtf(Q.qx * Q.qx + Q.qy * Q.qy + Q.qz * Q.qz);
-    Q.c1 = 0.375f * eps;
-    Q.c2 = 0.75f * eps;
-    Q.e_abs = e_abs;
+    Q.c = 3.0f * eps;
+    Q.a = fmaf(Q.c, sqrtf(Q.qx * Q.qx + Q.qy * Q.qy + Q.qz * Q.qz), e_abs);
     return Q;
 }
 
@@ -264,22 +265,17 @@ __device__ __forceinline__ void wall32(double L, double s_c, float e_abs, float 
 __device__ __forceinline__ void plane_bound32(const Rec32 &r, const Query32 &Q, float &t, float &err, bool &pos,
                                               bool &maybe)
 {
-    const float u = 5.9604645e-8f;   // 2^-24
     const float nx = r.nx, ny = r.ny, nz = r.nz;
     const float den = fmaf(nx, Q.kx, fmaf(ny, Q.ky, nz * Q.kz));
-    const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-    const float nq = fmaf(nx, Q.qx, fmaf(ny, Q.qy, nz * Q.qz));
-    const float num = fmaf(0.5f, nn, -nq);
+    const float wx = fmaf(0.5f, nx, -Q.qx), wy = fmaf(0.5f, ny, -Q.qy), wz = fmaf(0.5f, nz, -Q.qz);
+    const float num = fmaf(nx, wx, fmaf(ny, wy, nz * wz));
     const float n1 = fabsf(nx) + fabsf(ny) + fabsf(nz);
-    const float d = 8.0f * u * n1;
-    pos = den > fmaxf(4.0f * d, 1.17549435e-38f);
-    maybe = den > -d;
+    const float d4 = fmaf(32.0f * 5.9604645e-8f, n1, 1.17549435e-38f);   // 4d, floored
+    pos = den > d4;
+    maybe = den > -d4;
     const float rc = __builtin_amdgcn_rcpf(den);
     t = num * rc;
-    const float at = fabsf(t);
-    const float sq = Q.qa + at;
-    const float E = fmaf(Q.c1, nn, n1 * fmaf(Q.c2, sq, Q.e_abs));
-    err = fmaf(E, rc, 7.0f * u * at);
+    err = (n1 * rc) * fmaf(Q.c, fabsf(t), Q.a);
 }
 
 __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const Rec32 *__restrict__ rec32, int2 rw,
@@ -290,44 +286,45 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const
     const float inf = __builtin_huge_valf();
     float tw, ew;
     wall32(L, s_c, e_abs, tw, ew);
-    float t1 = tw, hi1 = tw + ew;       // best estimate and its upper bound
-    int e1 = -1;
-    float lo_a = tw - ew, lo_b = inf;   // two smallest lower bounds
-    int ia = -1;
+    float t1 = tw, err1 = ew;           // best estimate and its bound (the wall to begin with)
+    j1 = -1;
+    float lo_a = tw - ew, lo_b = inf;   // the two smallest lower bounds, lo_a <= lo_b
+    bool graze = false;                 // a nearly parallel plane was met
     const int end = rw.x + rw.y;
     for (int e0 = rw.x; e0 < end; e0 += kBatch32) {
         Rec32 r[kBatch32];
 #pragma unroll
         for (int v = 0; v < kBatch32; ++v) r[v] = rec32[e0 + v];   // past the row end: padding or the next row, masked
+        const int rem = end - e0;
 #pragma unroll
         for (int v = 0; v < kBatch32; ++v) {
-            const bool in = e0 + v < end;
+            const bool in = v < rem;
             float t, err;
             bool pos, maybe;
             plane_bound32(r[v], Q, t, err, pos, maybe);
             pos = pos && in;
-            maybe = maybe && in;
-            const float lo = pos ? t - err : (maybe ? -inf : inf);
+            graze = graze || (maybe && in && !pos);
+            const float lo = pos ? t - err : inf;
             // branch-free updates of the winner and of the two smallest lower bounds
             const bool w = pos && t < t1;
             t1 = w ? t : t1;
-            hi1 = w ? t + err : hi1;
-            e1 = w ? e0 + v : e1;
+            err1 = w ? err : err1;
             j1 = w ? r[v].j : j1;
-            const bool b1 = lo < lo_a, b2 = lo < lo_b;
-            lo_b = b1 ? lo_a : (b2 ? lo : lo_b);
-            lo_a = b1 ? lo : lo_a;
-            ia = b1 ? e0 + v : ia;
+            lo_b = __builtin_amdgcn_fmed3f(lo_a, lo_b, lo);
+            lo_a = fminf(lo_a, lo);
         }
     }
-    const float lo_other = (ia == e1) ? lo_b : lo_a;
-    if (!(hi1 < lo_other)) {
+    // the winner's own lower bound, computed as in the loop; the smallest
+    // lower bound of the others is lo_b if the winner holds the smallest
+    const float lo1 = t1 - err1;
+    const float lo_other = (lo1 == lo_a) ? lo_b : lo_a;
+    if (graze || !(t1 + err1 < lo_other)) {
         redo = true;
         return exit_fp64(rec64, rw, pm, r0, k, L, best);
     }
     redo = false;
-    if (e1 < 0) best = L;
-    return e1;
+    if (j1 < 0) best = L;
+    return j1 < 0 ? -1 : 0;
 }
 
 struct RayStats {
