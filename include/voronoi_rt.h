@@ -42,7 +42,8 @@ typedef enum {
     VOR_EOUTSIDE = 3,   /* a site lies outside the box or is not finite */
     VOR_ENOMEM = 4,     /* a device allocation failed */
     VOR_EDEVICE = 5,    /* a HIP runtime call or kernel launch failed */
-    VOR_ECAPACITY = 6,  /* a cell needs more faces than the builder's fixed capacity */
+    VOR_ECAPACITY = 6,  /* a cell needs more faces than the builder's fixed capacity, or the neighbour
+                           tables exceed 2^31 16-byte slots */
     VOR_EBUDGET = 7,    /* a serving request exceeds the memory budget */
     VOR_ETIMEOUT = 8    /* a wait ran out of time; the request is still pending */
 } vor_status;
@@ -71,6 +72,9 @@ typedef struct vor_grid vor_grid;
 
 /* Segments per spill chunk (see vor_trace_out). */
 #define VOR_SPILL_CHUNK 64
+
+/* Control words of a trace (vor_trace_out.work). */
+#define VOR_WORK_WORDS 16
 
 /* Options of vor_build_grid; zero-initialised fields take the defaults. */
 typedef struct {
@@ -188,7 +192,9 @@ typedef struct {
                                      neighbour records read, wave iterations and refills of the persistent
                                      kernel (steps / (64 x iterations) is its lane utilisation), 1 reserved;
                                      may be NULL */
-    int64_t *work;          /* [4] control words, required for persistent mode and spill; zeroed by the call */
+    int64_t *work;          /* [VOR_WORK_WORDS] device control words, required for persistent mode and spill;
+                               zeroed by the call. work[2] ends as the number of rays whose path continued
+                               past its window; the others are the work queues and chunk counter. */
     /* Spill (stride mode only, all NULL to disable): a ray whose path is
      * longer than seg_stride keeps its first seg_stride segments in its
      * window and continues in a chain of chunks of VOR_SPILL_CHUNK slots in

@@ -48,6 +48,15 @@ struct TraceArgs {
 #define VRT_OCC
 #endif
 constexpr int kRefillMin = VRT_REFILL_MIN;   // idle lanes that trigger a refill in the persistent kernel
+// Work queues of the persistent kernel: the processing order is cut into
+// kParts contiguous parts, one per XCD (workgroups are dispatched to the
+// XCDs in turn, so block b runs on XCD b mod kParts). The waves of an XCD
+// take rays from their own part first, so the rays in flight on it are
+// neighbours in the coherent order and share its L2; a wave whose part has
+// run out moves on to the next part. Queue heads: work[kHead0 + p].
+constexpr int kParts = 8;
+constexpr int kHead0 = 8;
+static_assert(kHead0 + kParts <= VOR_WORK_WORDS, "work queue heads must fit the control words");
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
 {
@@ -212,9 +221,11 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace(TraceArgs A)
 
 // Persistent waves: every lane keeps a ray in flight. Lanes whose ray has
 // ended wait until at least kRefillMin of the wave's lanes are idle (or
-// none is busy); then they take the next rays from the work queue together
-// (one atomic per wave, ranks from the ballot) and start them side by side,
-// so the start-cell searches of the refilled lanes overlap.
+// none is busy); then they take the next rays from the work queue of their
+// part of the processing order together (one atomic per wave, ranks from
+// the ballot) and start them side by side. A wave that finds its current
+// part exhausted moves to the next one; after finding all kParts parts
+// exhausted (exhaustion is permanent) the queue is drained for it.
 template <int MODE, bool SEGS, bool EXT>
 __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
 {
@@ -224,8 +235,9 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
     RayState R;
     int64_t ray = -1;
     bool live = false;
-    unsigned long long *head = (unsigned long long *)&A.work[0];
-    bool drained = false;   // wave-uniform: the queue has run out
+    unsigned long long *heads = (unsigned long long *)&A.work[kHead0];
+    int part = (int)(blockIdx.x % kParts), exhausted = 0;   // wave-uniform: current part, parts found empty
+    bool drained = false;   // wave-uniform: every part has run out
     bool pending = false;   // this lane's ray has ended and its results are not yet written
     unsigned int wit = 0, wref = 0;   // wave-uniform: iterations with a live lane, refills
     for (;;) {
@@ -242,12 +254,14 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
 #endif
             int n = __popcll(want);
             int leader = __ffsll((long long)want) - 1;
+            const int64_t p0 = A.N * part / kParts, p1 = A.N * (part + 1) / kParts;
             unsigned long long base0 = 0;
-            if (lane == leader) base0 = atomicAdd(head, (unsigned long long)n);
+            if (lane == leader) base0 = atomicAdd(&heads[part], (unsigned long long)n);
             base0 = __shfl(base0, leader, 64);
             if (need) {
-                int64_t q = (int64_t)(base0 + __popcll(want & lt));
-                if (q < A.N) {
+                const unsigned long long r = base0 + __popcll(want & lt);
+                const int64_t q = r < (unsigned long long)(p1 - p0) ? p0 + (int64_t)r : A.N;
+                if (q < p1) {
                     ray = A.order ? (int64_t)A.order[q] : q;
                     S = RayStats();
                     ray_window<SEGS>(A, ray, R);
@@ -257,7 +271,10 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
                     ray = -1;
                 }
             }
-            drained = __ballot(need && ray < 0) != 0ull;
+            if (__ballot(need && ray < 0) != 0ull) {   // this part has run out
+                part = part + 1 == kParts ? 0 : part + 1;
+                drained = ++exhausted == kParts;
+            }
         }
         if (__ballot(live) == 0ull) {
             if (drained) break;   // the queue is drained and every ray has ended
@@ -451,7 +468,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     A.X.stop_s = out->stop_s;
     hipStream_t st = (hipStream_t)stream;
     const int T = 256;
-    if (A.work) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, A.work, 4);
+    if (A.work) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, A.work, VOR_WORK_WORDS);
     if (A.start && !(opts && opts->start_given))
         hipLaunchKernelGGL(k_start_cells, dim3((unsigned)((N + T - 1) / T)), dim3(T), 0, st, A);
     if (spill) {

@@ -64,7 +64,8 @@ class TraceOut(ctypes.Structure):
                 ("tally_len", ctypes.c_void_p), ("tally_abs", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
 
 
-SPILL_CHUNK = 64
+SPILL_CHUNK = 64     # VOR_SPILL_CHUNK
+WORK_WORDS = 16      # VOR_WORK_WORDS
 
 
 class ServerStats(ctypes.Structure):
@@ -269,7 +270,7 @@ class TraceBuffers:
         self.seg_len = torch.empty(max(nslots, 1), dtype=torch.float64, device=device) if want_segs else None
         self.ray_off: Optional[torch.Tensor] = None
         self.counters = torch.zeros(8, dtype=torch.int64, device=device) if counters else None
-        self.work = torch.zeros(4, dtype=torch.int64, device=device)
+        self.work = torch.zeros(WORK_WORDS, dtype=torch.int64, device=device)
         self.spill_chunks = int(spill_chunks) if self.seg_stride > 0 else 0
         if self.spill_chunks > 0:
             self.spill_first = torch.empty(N, dtype=torch.int64, device=device)

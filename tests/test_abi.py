@@ -32,6 +32,16 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
+def test_binding_constants_match_the_header():
+    from paper_1310_1854_amd import vrt
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define (VOR_\w+) (\d+)", text))
+    assert int(defs["VOR_SPILL_CHUNK"]) == vrt.SPILL_CHUNK
+    assert int(defs["VOR_WORK_WORDS"]) == vrt.WORK_WORDS
+    import torch
+    assert vrt.TraceBuffers(10, device="cpu").work.numel() == vrt.WORK_WORDS
+
+
 def test_library_exports_every_declared_symbol(lib):
     from paper_1310_1854_amd import vrt
     names = _declared()
