@@ -245,7 +245,7 @@ __device__ __forceinline__ int wave_max_int(int v)
 
 __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__restrict__ col,
                                const int32_t *__restrict__ total, const int32_t *__restrict__ start, int64_t M,
-                               int2 *__restrict__ rows, Rec64 *__restrict__ r64, Rec32 *__restrict__ r32,
+                               int2 *__restrict__ rows, Rec64 *__restrict__ r64, Rec32 *__restrict__ blk,
                                int *__restrict__ max_row)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -255,6 +255,16 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
         int s0 = start[i];
         rows[i] = make_int2(s0, n);
         const Site si = sites[i];
+        const int32_t bo = block_of(make_int2(s0, n), (int32_t)i);
+        BlockHdr h;
+        h.x = si.x;
+        h.y = si.y;
+        h.z = si.z;
+        h.uid = (int32_t)si.uid;
+        h.j = (int32_t)i;
+        h.len = n;
+        h.pad[0] = h.pad[1] = h.pad[2] = 0;
+        *reinterpret_cast<BlockHdr *>(blk + bo) = h;
         for (int e = 0; e < n; ++e) {
             int32_t j = col[s0 + e];
             const Site sj = sites[j];
@@ -265,12 +275,12 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
             a.j = j;
             a.uid = (int32_t)sj.uid;
             r64[s0 + e] = a;
-            Rec32 b;
-            b.nx = (float)(sj.x - si.x);
-            b.ny = (float)(sj.y - si.y);
-            b.nz = (float)(sj.z - si.z);
-            b.j = j;
-            r32[s0 + e] = b;
+            Rec32 r;
+            r.nx = (float)(sj.x - si.x);
+            r.ny = (float)(sj.y - si.y);
+            r.nz = (float)(sj.z - si.z);
+            r.blk = block_of(make_int2(start[j], 0), j);
+            blk[bo + kHdrSlots + e] = r;
         }
     }
     int m = wave_max_int(n);
@@ -505,16 +515,19 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
                        extra);
     hipLaunchKernelGGL(k_row_sort, dim3(blocks_for(M, T)), dim3(T), 0, st, col, start, total, M);
 
+    // cell blocks are addressed by 32-bit slot offsets
+    const int64_t nslots = g.nnz + (int64_t)kHdrSlots * M;
+    if (nslots + kRecPad > 0x7fffffffLL) return fail(VOR_ECAPACITY);
     g.rows = dalloc<int2>(M, rc, keep);
     g.rec64 = dalloc<Rec64>(g.nnz + kRecPad, rc, keep);
-    g.rec32 = dalloc<Rec32>(g.nnz + kRecPad, rc, keep);
+    g.blk = dalloc<Rec32>(nslots + kRecPad, rc, keep);
     if (rc != VOR_OK) return fail(rc);
     if (hipMemsetAsync(g.rec64 + g.nnz, 0, sizeof(Rec64) * kRecPad, st) != hipSuccess ||
-        hipMemsetAsync(g.rec32 + g.nnz, 0, sizeof(Rec32) * kRecPad, st) != hipSuccess)
+        hipMemsetAsync(g.blk + nslots, 0, sizeof(Rec32) * kRecPad, st) != hipSuccess)
         return fail(VOR_EDEVICE);
     hdr = err + 1;   // longest row
     hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, col, total, start, M, g.rows,
-                       g.rec64, g.rec32, hdr);
+                       g.rec64, g.blk, hdr);
     // size of the export with walls
     hipLaunchKernelGGL(k_export_counts, dim3(blocks_for(M, T)), dim3(T), 0, st, g.inv_perm, g.rows, g.wall_mask, M,
                        total);
@@ -530,7 +543,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
 
     for (void *p : tmp) (void)hipFree(p);
     g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + sizeof(double)) + (B + 1) * 4 +
-                     (g.nnz + kRecPad) * (int64_t)(sizeof(Rec64) + sizeof(Rec32));
+                     (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Rec32);
     g.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = G;
     return VOR_OK;
@@ -541,7 +554,7 @@ extern "C" void vor_grid_free(vor_grid *G)
     if (!G) return;
     (void)hipDeviceSynchronize();
     Grid &g = G->g;
-    void *ptrs[] = {g.sites, g.perm, g.inv_perm, g.rows, g.rec64, g.rec32, g.wall_mask, g.volume, g.bucket_start,
+    void *ptrs[] = {g.sites, g.perm, g.inv_perm, g.rows, g.rec64, g.blk, g.wall_mask, g.volume, g.bucket_start,
                     g.bucket_sites};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -592,7 +605,10 @@ extern "C" vor_status vor_grid_truncate_row(vor_grid *G, int64_t site, int32_t k
         return VOR_EDEVICE;
     if (keep < rw.y) {
         rw.y = keep;
-        if (hipMemcpy(g.rows + i, &rw, sizeof(rw), hipMemcpyHostToDevice) != hipSuccess) return VOR_EDEVICE;
+        BlockHdr *h = reinterpret_cast<BlockHdr *>(g.blk + block_of(rw, i));
+        if (hipMemcpy(g.rows + i, &rw, sizeof(rw), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(&h->len, &keep, sizeof(keep), hipMemcpyHostToDevice) != hipSuccess)
+            return VOR_EDEVICE;
     }
     return VOR_OK;
 }

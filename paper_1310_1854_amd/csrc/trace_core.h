@@ -21,7 +21,7 @@ struct GridRef {
     const Site *sites;
     const int2 *rows;
     const Rec64 *rec64;
-    const Rec32 *rec32;
+    const Rec32 *blk;     // cell blocks (BlockHdr + Rec32 records)
     BucketGridView grid;
     double lo[3], hi[3];
     int32_t max_steps;
@@ -97,7 +97,7 @@ inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
     G.sites = g.sites;
     G.rows = g.rows;
     G.rec64 = g.rec64;
-    G.rec32 = g.rec32;
+    G.blk = g.blk;
     G.grid = bucket_view(g);
     double diag = 0.0, cmax = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -189,10 +189,11 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
 
 // Mixed-precision exit search. Returns -1 when the chord end wins
 // (best = L), else a non-negative value; redo is set when the step was
-// decided in FP64 (then the return value is the winning record index and
-// best the FP64 crossing); otherwise j1 is the winner's internal index and
-// the caller computes its FP64 crossing from the site (fetched together
-// with the winner's row). Either way the result equals exit_fp64's.
+// decided in FP64 (then the return value is the winning record index in
+// rec64 and best the FP64 crossing); otherwise j1 is the offset of the
+// winner's cell block and the caller computes its FP64 crossing from the
+// site in the block header. Either way the result equals exit_fp64's. The
+// current cell's records are blk[b + kHdrSlots ...], rw its row in rec64.
 //
 // Each plane is ranked in FP32 from its stored offset n = p_j - p_m
 // (rounded once to FP32), the current point q = r - p_m and k (both
@@ -278,9 +279,10 @@ __device__ __forceinline__ void plane_bound32(const Rec32 &r, const Query32 &Q, 
     err = (n1 * rc) * fmaf(Q.c, fabsf(t), Q.a);
 }
 
-__device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const Rec32 *__restrict__ rec32, int2 rw,
-                                          const double pm[3], const double r0[3], const double k[3], double L,
-                                          double s_c, float eps, float e_abs, double &best, bool &redo, int32_t &j1)
+__device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 rw, const Rec32 *__restrict__ blk,
+                                          int32_t b, const double pm[3], const double r0[3], const double k[3],
+                                          double L, double s_c, float eps, float e_abs, double &best, bool &redo,
+                                          int32_t &j1)
 {
     const Query32 Q = query32(pm, r0, k, s_c, eps, e_abs);
     const float inf = __builtin_huge_valf();
@@ -290,11 +292,11 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const
     j1 = -1;
     float lo_a = tw - ew, lo_b = inf;   // the two smallest lower bounds, lo_a <= lo_b
     bool graze = false;                 // a nearly parallel plane was met
-    const int end = rw.x + rw.y;
-    for (int e0 = rw.x; e0 < end; e0 += kBatch32) {
+    const int end = b + kHdrSlots + rw.y;
+    for (int e0 = b + kHdrSlots; e0 < end; e0 += kBatch32) {
         Rec32 r[kBatch32];
 #pragma unroll
-        for (int v = 0; v < kBatch32; ++v) r[v] = rec32[e0 + v];   // past the row end: padding or the next row, masked
+        for (int v = 0; v < kBatch32; ++v) r[v] = blk[e0 + v];   // past the row end: padding or the next block, masked
         const int rem = end - e0;
 #pragma unroll
         for (int v = 0; v < kBatch32; ++v) {
@@ -309,7 +311,7 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, const
             const bool w = pos && t < t1;
             t1 = w ? t : t1;
             err1 = w ? err : err1;
-            j1 = w ? r[v].j : j1;
+            j1 = w ? r[v].blk : j1;
             lo_b = __builtin_amdgcn_fmed3f(lo_a, lo_b, lo);
             lo_a = fminf(lo_a, lo);
         }
@@ -405,6 +407,7 @@ struct RayState {
     double l0, l1, l2, l3;
 #endif
     int32_t m, uid;
+    int32_t b;            // offset of the current cell's block (mixed mode)
     uint8_t st;
     double tstop, wgt, stop_s;   // transport outputs (kernels with Extras only)
     int32_t stop_uid;            // cell of the interaction point, -1 none yet
@@ -425,6 +428,7 @@ __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R, double 
     R.pm[1] = sm.y;
     R.pm[2] = sm.z;
     R.rw = G.rows[m];
+    R.b = block_of(R.rw, m);
 }
 
 // Start in cell m (internal index), found beforehand by nearest_site.
@@ -439,6 +443,7 @@ __device__ __forceinline__ void ray_begin_at(const GridRef &G, RayState &R, int3
     R.pm[1] = sm.y;
     R.pm[2] = sm.z;
     R.rw = G.rows[m];
+    R.b = block_of(R.rw, m);
 }
 
 // Slot of segment idx of the ray: its window, else its current spill chunk;
@@ -558,8 +563,8 @@ __device__ __forceinline__ bool ray_step_begin(const GridRef &G, RayState &R, Ra
 
 // Rest of a step, given the exit search's result: record index win (-1: the
 // chord end), best = the FP64 crossing when redo (or when win < 0), else the
-// winner's internal index j1 (its FP64 crossing is computed here from the
-// site, fetched with the winner's row). Emits the segment, accumulates tau,
+// block offset j1 of the winner (its FP64 crossing is computed here from the
+// site in the block header). Emits the segment, accumulates tau,
 // moves to the next cell; the no-exit fallback of Sect. 2.2 when the current
 // point lies beyond a plane of the cell. Returns false once the path ended.
 // Tallies of a segment of length l in the current cell (kr = kappa rho),
@@ -609,13 +614,13 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             wz = w.z;
             wrow = G.rows[wj];
         } else {
-            wj = j1;
-            const Site w = G.sites[wj];
-            wrow = G.rows[wj];
-            wuid = (int32_t)w.uid;
-            wx = w.x;
-            wy = w.y;
-            wz = w.z;
+            const BlockHdr h = *reinterpret_cast<const BlockHdr *>(G.blk + j1);
+            wj = h.j;
+            wrow = make_int2(j1 - kHdrSlots * h.j, h.len);
+            wuid = h.uid;
+            wx = h.x;
+            wy = h.y;
+            wz = h.z;
             double den;
             best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
         }
@@ -661,6 +666,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
         R.pm[1] = sm.y;
         R.pm[2] = sm.z;
         R.rw = G.rows[R.m];
+        R.b = block_of(R.rw, R.m);
         return true;
     }
     if (wj < 0) return false;
@@ -670,6 +676,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
     R.pm[1] = wy;
     R.pm[2] = wz;
     R.rw = wrow;
+    R.b = block_of(wrow, wj);
     return true;
 }
 
@@ -687,7 +694,8 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
     if (MODE == VOR_MODE_FP64) {
         win = exit_fp64(G.rec64, R.rw, R.pm, R.r0, R.k, R.L, best);
     } else {
-        win = exit_mixed(G.rec64, G.rec32, R.rw, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs, best, redo, j1);
+        win = exit_mixed(G.rec64, R.rw, G.blk, R.b, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs, best, redo,
+                         j1);
         S.nredo += redo ? 1 : 0;
     }
     return ray_step_end<MODE, SEGS, EXT>(G, I, R, S, O, win, best, redo, j1, X);

@@ -21,11 +21,28 @@ struct __align__(32) Rec64 {
 };
 
 // FP32 neighbour record of the mixed-precision search: the offset
-// p_j - p_m rounded to FP32 and the neighbour's internal index.
+// p_j - p_m rounded to FP32 and the offset of the neighbour's cell block.
 struct __align__(16) Rec32 {
     float nx, ny, nz;
-    int32_t j;
+    int32_t blk;
 };
+
+// Cell blocks of the mixed-precision search, one per cell in internal
+// order, 16-byte slots: a header of kHdrSlots slots, then the cell's row as
+// Rec32 records. What a step needs of the cell it moves into (its FP64
+// site, indices and row) thus lies in the lines of its first records. The
+// block of cell j starts at slot rows[j].x + kHdrSlots * j.
+constexpr int kHdrSlots = 3;
+struct __align__(16) BlockHdr {
+    double x, y, z;   // the site
+    int32_t uid;      // user index
+    int32_t j;        // internal index
+    int32_t len;      // records that follow
+    int32_t pad[3];
+};
+static_assert(sizeof(BlockHdr) == 16 * kHdrSlots, "a block header fills kHdrSlots slots");
+
+__host__ __device__ inline int32_t block_of(int2 row, int32_t j) { return row.x + kHdrSlots * j; }
 
 // Site in internal order with its user index (the w slot holds the index
 // bits so that one 32-byte load fetches both).
@@ -53,9 +70,9 @@ struct Grid {
     Site *sites = nullptr;          // [M]
     int32_t *perm = nullptr;        // [M] internal -> user
     int32_t *inv_perm = nullptr;    // [M] user -> internal
-    int2 *rows = nullptr;           // [M] {start, count} into rec64/rec32
+    int2 *rows = nullptr;           // [M] {start, count} into rec64
     Rec64 *rec64 = nullptr;         // [nnz + kRecPad]
-    Rec32 *rec32 = nullptr;         // [nnz + kRecPad]
+    Rec32 *blk = nullptr;           // [nnz + kHdrSlots M + kRecPad] cell blocks (headers and FP32 records)
     uint8_t *wall_mask = nullptr;   // [M] bit w set if wall -(w+1) is a face
     double *volume = nullptr;       // [M] volume of each clipped cell
     int32_t *bucket_start = nullptr;// [B + 1]
