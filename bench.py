@@ -56,12 +56,23 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(workload: str):
-    """(bytes per launch, summary path) of the trace kernel's HBM traffic from
-    the counter summary, or (None, reason) when there is none for this
+    """(bytes per launch, summary path, L2 hit rate) of the trace kernel from
+    the counter summary, or (None, reason, None) when there is none for this
     workload or the kernel sources have changed since it was taken."""
+    traffic, src, fields = _traffic_fields(workload)
+    hit = None
+    if traffic is not None and "l2_hit_rate" in fields:
+        try:
+            hit = float(fields["l2_hit_rate"])
+        except ValueError:
+            pass
+    return traffic, src, hit
+
+
+def _traffic_fields(workload: str):
     path = os.path.join(ROOT, TRAFFIC_SUMMARY)
     if not os.path.exists(path):
-        return None, "no counter summary"
+        return None, "no counter summary", {}
     fields = {}
     with open(path) as fh:
         for line in fh:
@@ -69,13 +80,13 @@ def measured_traffic(workload: str):
                 k, v = line[2:].split(": ", 1)
                 fields[k.strip()] = v.strip().strip("`")
     if fields.get("workload") != workload:
-        return None, "counter summary is for another workload"
+        return None, "counter summary is for another workload", fields
     if fields.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None, "kernel sources changed since the counters were taken"
+        return None, "kernel sources changed since the counters were taken", fields
     try:
-        return float(fields["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY
+        return float(fields["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY, fields
     except (KeyError, ValueError):
-        return None, "counter summary lacks traffic_bytes_per_launch"
+        return None, "counter summary lacks traffic_bytes_per_launch", fields
 
 # Launch configuration per workload: mode, segment window per ray, spill
 # chunks (of 64 segments) per ray, coherent ray order, persistent kernel.
@@ -438,7 +449,8 @@ def main(argv=None):
     same_tau = bool(torch.equal(fb.tau, tau_mixed))
     same_nseg = bool(torch.equal(fb.n_seg, nseg_mixed))
 
-    traffic, traffic_src = measured_traffic(args.workload)
+    traffic, traffic_src, l2_hit = measured_traffic(args.workload)
+    copy_bw = copy_bandwidth(torch)
 
     result = {
         "metric": METRIC,
@@ -472,7 +484,8 @@ def main(argv=None):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_trace_persistent" if spec.get("persistent") else "k_trace",
                      "kernel_avg_ms": k_avg, "algorithmic_bytes": alg, "traffic_source": traffic_src,
-                     "kernel_source_sha256_16": kernel_source_hash()},
+                     "kernel_source_sha256_16": kernel_source_hash(), "l2_hit_rate": l2_hit,
+                     "copy_bw": copy_bw, "frac_of_copy": achieved / copy_bw},
     }
     if not args.no_cpu:
         import oracle
@@ -533,6 +546,26 @@ def transport_check(vrt, torch, grid, o, d, rho, bufs, spec, mode):
     return {"kappa": spec["kappa"], "interacting_fraction": float((bufs.stop_cell[ok] >= 0).double().mean()),
             "absorbed_total": got, "absorbed_closed_form": want, "absorbed_rel_err": abs(got - want) / want,
             "tally_len_total": tl, "path_length_total": path, "tally_len_rel_err": abs(tl - path) / path}
+
+
+def copy_bandwidth(torch, mib: int = 1024, reps: int = 5) -> float:
+    """Device copy bandwidth in GB/s (bytes read + written per second) of a
+    plain streaming kernel: scaling of mib MiB of float64, event-timed (a
+    multiplication, so that the negations of copy_calibration stay apart in
+    the counter runs)."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 3.0, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(src, 3.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * n * 8 / (ms / 1e3) / 1e9
 
 
 def copy_calibration(torch, mib: int = 512, reps: int = 3):
