@@ -57,7 +57,7 @@ def _bind(lib):
     lib.oracle_trace.argtypes = [P, I64, P, P, ctypes.c_double, P, P, I64,
                                  ctypes.c_double, I64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int, P]
     lib.oracle_trace.restype = ctypes.c_int
-    lib.oracle_faces.argtypes = [P, I64, P, P, I64, I64, P, P, P, P]
+    lib.oracle_faces.argtypes = [P, I64, P, P, I64, I64, P, P, P, P, P]
     lib.oracle_faces.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_get_threads.restype = ctypes.c_int
@@ -152,9 +152,11 @@ def trace(sites, box, density, origins, dirs, kappa=1.0, cap=256, eta=ETA, segme
     return out
 
 
-def faces(sites, box, cells, cap=128, lib=None):
+def faces(sites, box, cells, cap=128, lib=None, bboxes=False):
     """Faces of the listed cells: list of (nbr int32[], area float64[]) and
-    volumes float64[]. Neighbour >= 0 is a site index, -1..-6 a wall."""
+    volumes float64[]; with bboxes=True also the cells' bounding boxes
+    (n x 6: xmin, ymin, zmin, xmax, ymax, zmax, from the face corners).
+    Neighbour >= 0 is a site index, -1..-6 a wall."""
     sites = _f64(sites, (-1, 3))
     box = _f64(box, (6,))
     cells = np.ascontiguousarray(cells, dtype=np.int64)
@@ -163,14 +165,15 @@ def faces(sites, box, cells, cap=128, lib=None):
     area = np.zeros((n, cap))
     nface = np.zeros(n, np.int32)
     vol = np.zeros(n)
+    bb = np.zeros((n, 6)) if bboxes else None
     rc = _load(lib).oracle_faces(_p(sites), sites.shape[0], _p(box), _p(cells), n, cap,
-                              _p(nbr), _p(area), _p(nface), _p(vol))
+                              _p(nbr), _p(area), _p(nface), _p(vol), None if bb is None else _p(bb))
     if rc:
         raise ValueError("oracle_faces: bad arguments or out of memory")
     if np.any(nface > cap):
         raise ValueError("oracle_faces: face capacity exceeded")
     res = [(nbr[q, :nface[q]].copy(), area[q, :nface[q]].copy()) for q in range(n)]
-    return res, vol
+    return (res, vol, bb) if bboxes else (res, vol)
 
 
 def segments_of(out, ray):

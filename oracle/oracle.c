@@ -322,7 +322,9 @@ int oracle_trace(const double *sites, int64_t M, const double *box,
  * the half-spaces {x : |x - p_i| <= |x - p_k|} of every other site k. What is
  * left is the face of the clipped cell on that plane; j (or the wall) is a
  * face neighbour when the face has positive area. The cell volume is the sum
- * over faces of area * (distance from p_i to the face plane) / 3.
+ * over faces of area * (distance from p_i to the face plane) / 3. The
+ * cell is convex, so its bounding box is that of its vertices (Sect. 2.3),
+ * the corners of its faces.
  * ------------------------------------------------------------------------- */
 
 typedef struct { double x, y, z; } v3;
@@ -371,10 +373,11 @@ static int cmp_dj(const void *a, const void *b)
     return (x->j < y->j) ? -1 : (x->j > y->j);
 }
 
-/* face of cell i on the plane {x : nrm.x = off}, clipped by box and all sites */
+/* face of cell i on the plane {x : nrm.x = off}, clipped by box and all
+ * sites; a face of positive area widens bb (min xyz, max xyz) to its corners */
 static double face_area(const double *sites, int64_t M, const double *box, int64_t i,
                         v3 nrm, double off, int skip_wall, int64_t skip_site,
-                        const dj_t *order, v3 *buf0, v3 *buf1)
+                        const dj_t *order, v3 *buf0, v3 *buf1, double *bb)
 {
     double nn = sqrt(v3dot(nrm, nrm));
     v3 nh = v3scale(nrm, 1.0 / nn);
@@ -416,7 +419,17 @@ static double face_area(const double *sites, int64_t M, const double *box, int64
         n = clip_poly(cur, n, nxt, a, b);
         v3 *t = cur; cur = nxt; nxt = t;
     }
-    return poly_area(cur, n);
+    double ar = poly_area(cur, n);
+    if (ar > 0.0) {
+        for (int e = 0; e < n; ++e) {
+            const double xyz[3] = {cur[e].x, cur[e].y, cur[e].z};
+            for (int a = 0; a < 3; ++a) {
+                if (xyz[a] < bb[a]) bb[a] = xyz[a];
+                if (xyz[a] > bb[a + 3]) bb[a + 3] = xyz[a];
+            }
+        }
+    }
+    return ar;
 }
 
 /*
@@ -424,11 +437,13 @@ static double face_area(const double *sites, int64_t M, const double *box, int64
  * nbr[q*cap + f] holds the neighbour index (>= 0) or wall code (-1..-6) of
  * face f, area[q*cap + f] its area (> 0), nface[q] the face count and
  * volume[q] the cell volume. Faces beyond cap are counted in nface and
- * volume but not stored. Returns 0, or 1 on bad arguments.
+ * volume but not stored. If bbox != NULL, bbox[6q..6q+5] receives the
+ * bounding box of the cell {xmin, ymin, zmin, xmax, ymax, zmax}: the extreme
+ * coordinates of its face corners. Returns 0, or 1 on bad arguments.
  */
 int oracle_faces(const double *sites, int64_t M, const double *box,
                  const int64_t *cells, int64_t ncells, int64_t cap,
-                 int32_t *nbr, double *area, int32_t *nface, double *volume)
+                 int32_t *nbr, double *area, int32_t *nface, double *volume, double *bbox)
 {
     if (M <= 0 || ncells < 0) return 1;
     int bad = 0;
@@ -456,12 +471,13 @@ int oracle_faces(const double *sites, int64_t M, const double *box,
             qsort(order, (size_t)(M - 1), sizeof(dj_t), cmp_dj);
             int32_t nf = 0;
             double vol = 0.0;
+            double bb[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
             for (int64_t o2 = 0; o2 < M - 1; ++o2) {
                 int64_t j = order[o2].j;
                 v3 pj = {sites[3 * j], sites[3 * j + 1], sites[3 * j + 2]};
                 v3 a = v3sub(pj, pi);
                 double b = v3dot(a, v3scale(v3add(pj, pi), 0.5));
-                double ar = face_area(sites, M, box, i, a, b, -1, j, order, b0, b1);
+                double ar = face_area(sites, M, box, i, a, b, -1, j, order, b0, b1, bb);
                 if (ar > 0.0) {
                     if (nf < cap) {
                         nbr[q * cap + nf] = (int32_t)j;
@@ -477,7 +493,7 @@ int oracle_faces(const double *sites, int64_t M, const double *box,
                 double b;
                 if (wl % 2 == 0) { (&an.x)[ax] = -1.0; b = -box[ax]; }
                 else { (&an.x)[ax] = 1.0; b = box[ax + 3]; }
-                double ar = face_area(sites, M, box, i, an, b, wl, -1, order, b0, b1);
+                double ar = face_area(sites, M, box, i, an, b, wl, -1, order, b0, b1, bb);
                 if (ar > 0.0) {
                     if (nf < cap) {
                         nbr[q * cap + nf] = -(wl + 1);
@@ -490,6 +506,8 @@ int oracle_faces(const double *sites, int64_t M, const double *box,
             }
             nface[q] = nf;
             volume[q] = vol;
+            if (bbox)
+                for (int a = 0; a < 6; ++a) bbox[6 * q + a] = bb[a];
         }
         free(order);
         free(b0);

@@ -332,6 +332,82 @@ def test_faces_cubic_lattice_closed_form(oracle_lib):
         assert np.allclose([a for a in ar if a > 1e-9], 1.0, atol=1e-12)
 
 
+def test_bbox_single_site_and_lattices(oracle_lib):
+    # one site: the cell is the box
+    _, _, bb = oracle.faces([[0.3, 0.6, 0.2]], [0, 0, 0, 1, 2, 3], [0], bboxes=True)
+    assert np.allclose(bb[0], [0, 0, 0, 1, 2, 3], rtol=0, atol=1e-12)   # corners from clipped faces: rounding
+    # dyadic cubic lattice: cell (i, j, k) is the unit cube at (i, j, k)
+    n = 4
+    w = W.cubic_lattice(n, N=1)
+    _, _, bb = oracle.faces(w.sites, w.box, np.arange(w.M), bboxes=True)
+    for idx in range(w.M):
+        i, j, k = idx // (n * n), (idx // n) % n, idx % n
+        assert np.allclose(bb[idx], [i, j, k, i + 1, j + 1, k + 1], rtol=0, atol=1e-13)
+    # random tensor lattice: cuboids between the midpoints of neighbouring coordinates
+    w = W.random_tensor_lattice((4, 3, 5), N=1)
+    _, _, bb = oracle.faces(w.sites, w.box, np.arange(w.M), bboxes=True)
+    axes = [np.asarray(w.meta[c]) for c in ("xs", "ys", "zs")]
+    walls = [np.concatenate([[w.box[a]], 0.5 * (axes[a][1:] + axes[a][:-1]), [w.box[a + 3]]]) for a in range(3)]
+    for idx in range(w.M):
+        ijk = (idx // (3 * 5), (idx // 5) % 3, idx % 5)
+        want = [walls[a][ijk[a]] for a in range(3)] + [walls[a][ijk[a] + 1] for a in range(3)]
+        assert np.allclose(bb[idx], want, rtol=0, atol=1e-12)
+
+
+def _brute_vertices(sites, box, i):
+    """Vertices of cell i by brute force: every point where three of its
+    bounding planes (bisectors with all other sites, box walls) meet, kept
+    when it lies in the box and no site is nearer than p_i."""
+    import itertools
+    p = sites[i]
+    planes = []
+    for j in range(len(sites)):
+        if j != i:
+            n = sites[j] - p
+            planes.append((n, n @ (0.5 * (sites[j] + p))))
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 1.0
+        planes.append((-e, -box[a]))
+        planes.append((e, box[a + 3]))
+    out = []
+    for (a1, b1), (a2, b2), (a3, b3) in itertools.combinations(planes, 3):
+        A = np.array([a1, a2, a3])
+        if abs(np.linalg.det(A)) < 1e-12:
+            continue
+        x = np.linalg.solve(A, [b1, b2, b3])
+        if np.any(x < box[:3] - 1e-9) or np.any(x > box[3:] + 1e-9):
+            continue
+        d = ((sites - x) ** 2).sum(1)
+        if d[i] <= d.min() * (1 + 1e-9) + 1e-12:
+            out.append(x)
+    return np.array(out)
+
+
+def test_bbox_equals_brute_force_vertices(oracle_lib):
+    rng = np.random.default_rng(41)
+    box = np.array([-1.0, -1.0, -1.0, 1.0, 1.0, 1.0])
+    for M in (2, 5, 9):
+        sites = rng.uniform(-1, 1, (M, 3))
+        _, _, bb = oracle.faces(sites, box, np.arange(M), bboxes=True)
+        for i in range(M):
+            v = _brute_vertices(sites, box, i)
+            want = np.concatenate([v.min(0), v.max(0)])
+            assert np.allclose(bb[i], want, rtol=0, atol=1e-9), (M, i)
+
+
+def test_bbox_holds_the_points_of_its_cell(oracle_lib):
+    w = W.uniform_cube(M=300, N=1, seed=42)
+    _, _, bb = oracle.faces(w.sites, w.box, np.arange(w.M), bboxes=True)
+    pts = np.random.default_rng(43).uniform(-1, 1, (20000, 3))
+    cell, _ = oracle.locate(w.sites, w.box, pts)
+    b = bb[cell]
+    assert np.all(pts >= b[:, :3] - 1e-12) and np.all(pts <= b[:, 3:] + 1e-12)
+    # each site lies in its own box, and the boxes cover the whole domain
+    assert np.all(w.sites >= bb[:, :3]) and np.all(w.sites <= bb[:, 3:])
+    assert np.allclose(bb[:, :3].min(0), w.box[:3]) and np.allclose(bb[:, 3:].max(0), w.box[3:])
+
+
 def test_mean_neighbour_count_uniform(oracle_lib):
     """Poisson-Voronoi cells have 15.54 face neighbours on average (Sect. 2.1,
     literature value). Averaged over cells far from the walls of a

@@ -47,6 +47,8 @@ MUTANTS = {
     "clip_plane_offset": ("double b = v3dot(a, v3scale(v3add(pk, pi), 0.5));",
                           "double b = v3dot(a, v3scale(v3add(pk, pi), 0.25));"),
     "face_volume_height": ("vol += ar * (0.5 * sqrt(v3dot(a, a))) / 3.0;", "vol += ar * (sqrt(v3dot(a, a))) / 3.0;"),
+    "bbox_max_slot": ("if (xyz[a] > bb[a + 3]) bb[a + 3] = xyz[a];", "if (xyz[a] > bb[a + 3]) bb[a] = xyz[a];"),
+    "bbox_min_compare": ("if (xyz[a] < bb[a]) bb[a] = xyz[a];", "if (xyz[a] > bb[a]) bb[a] = xyz[a];"),
 }
 
 
@@ -137,8 +139,15 @@ def _pins(lib):
         return (list(cells) == [0] and lens[0] == 1.0 and o["start_s"][0] == 1.0 and o["chord"][0] == 2.0
                 and o["tau"][0] == 3.0)
 
-    for name, fn in [("golden", golden), ("lattice", lattice), ("exact", exact),
-                     ("invariants", invariants), ("locate", locate), ("faces", faces), ("entering", entering)]:
+    def bboxes():
+        n = 3
+        w = W.cubic_lattice(n, N=1)
+        _, _, bb = oracle.faces(w.sites, w.box, np.arange(w.M), lib=lib, bboxes=True)
+        want = np.array([[i, j, k, i + 1, j + 1, k + 1] for i in range(n) for j in range(n) for k in range(n)], float)
+        return np.allclose(bb, want, rtol=0, atol=1e-12)
+
+    for name, fn in [("golden", golden), ("lattice", lattice), ("exact", exact), ("invariants", invariants),
+                     ("locate", locate), ("faces", faces), ("entering", entering), ("bboxes", bboxes)]:
         check(name, fn)
     return failed
 
