@@ -221,10 +221,13 @@ def grid_quality(args, torch, vrt, workloads):
     rho_t and the gridded density rho_g (the density of the cell that holds
     the point, i.e. at its site) at 10^7 points uniform over the box;
     quality = the standard deviation of rho_t - rho_g. The hot part is
-    vor_locate over the points (timed with HIP events). For each disc the
-    sites drawn from the density (the workload's placement) are compared
-    with as many uniform sites. The cells of 2000 of the points are checked
-    against the oracle's brute-force locate."""
+    locating the points (timed with HIP events), with both structures: the
+    bucket grid of sites (vor_locate) and the paper's block lists from the
+    cells' bounding boxes (vor_locate_blocks, Sect. 2.3); both must give the
+    same cell for every point. For each disc the sites drawn from the density
+    (the workload's placement) are compared with as many uniform sites. The
+    cells of 2000 of the points are checked against the oracle's brute-force
+    locate."""
     import oracle
     n_pts = 10_000_000
     out = {}
@@ -240,29 +243,41 @@ def grid_quality(args, torch, vrt, workloads):
             sites = w.sites if placement == "density" else workloads.uniform_in_box(
                 np.random.default_rng(7), w.M, w.box)
             rho_site = field(sites)
-            grid = vrt.build_grid(sites, w.box)
-            vrt.load().vor_locate(grid.handle, vrt._ptr(dev_pts), n_pts, vrt._ptr(cell), vrt._stream())
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(3):
-                vrt.load().vor_locate(grid.handle, vrt._ptr(dev_pts), n_pts, vrt._ptr(cell), vrt._stream())
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / 3
+            grid = vrt.build_grid(sites, w.box, block_lists=True)
+            info = grid.info()
+
+            def timed(fn):
+                fn(grid.handle, vrt._ptr(dev_pts), n_pts, vrt._ptr(cell), vrt._stream())
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(3):
+                    fn(grid.handle, vrt._ptr(dev_pts), n_pts, vrt._ptr(cell), vrt._stream())
+                e1.record()
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / 3
+
+            ms_blocks = timed(vrt.load().vor_locate_blocks)
+            c_blocks = cell.cpu().numpy()
+            ms = timed(vrt.load().vor_locate)
             c = cell.cpu().numpy()
             diff = rho_t - rho_site[c]
             sample = slice(0, 2_000)
             ref, _ = oracle.locate(sites, w.box, pts[sample])
+            nblk = int(np.prod(info["block_dims"]))
             res[placement] = {"sigma": float(diff.std()), "sigma_rel_mean": float(diff.std() / rho_t.mean()),
                               "locate_ms": ms, "points_per_s": n_pts / (ms / 1e3),
-                              "oracle_cell_mismatches": int((ref != c[sample]).sum())}
+                              "oracle_cell_mismatches": int((ref != c[sample]).sum()),
+                              "block_lists": {"locate_ms": ms_blocks, "points_per_s": n_pts / (ms_blocks / 1e3),
+                                              "blocks": nblk, "mean_cells_per_block": info["block_entries"] / nblk,
+                                              "cells_differing_from_vor_locate": int((c_blocks != c).sum())}}
             print(f"[bench] grid quality {name} {placement}: {res[placement]}", file=sys.stderr, flush=True)
             grid.free()
         res["uniform_over_density_sigma"] = res["uniform"]["sigma"] / res["density"]["sigma"]
         out[name] = dict(sites=w.M, points=n_pts, **res)
-    best = out["flared_disc"]["density"]
-    result = {"metric": "grid quality: std of rho_t - rho_g at uniform points (Sect. 3.3); locate points/s",
+    best = out["flared_disc"]["density"]["block_lists"]
+    result = {"metric": "grid quality: std of rho_t - rho_g at uniform points (Sect. 3.3); locate points/s "
+                        "(block lists of Sect. 2.3)",
               "value": best["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": 3, "warmup": 1,
               "ms_per_step": best["locate_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
               "dtype": "f64", "data": "synthetic",

@@ -79,6 +79,10 @@ typedef struct vor_grid vor_grid;
 /* Options of vor_build_grid; zero-initialised fields take the defaults. */
 typedef struct {
     double bucket_occupancy;  /* mean sites per bucket of the uniform site grid (default 2) */
+    int32_t block_lists;      /* 1: also build the locate structure of Sect. 2.3 (blocks of a regular grid,
+                                 each listing the cells whose bounding box overlaps it) and keep the cells'
+                                 bounding boxes, for vor_locate_blocks and vor_grid_bboxes; 0: not */
+    double block_occupancy;   /* with block_lists: about M / block_occupancy blocks (default 1) */
 } vor_build_opts;
 
 /* Facts about a built grid, filled by vor_grid_get_info. */
@@ -91,6 +95,8 @@ typedef struct {
     double box[6];
     double build_ms;          /* wall time of vor_build_grid */
     int64_t device_bytes;     /* device memory held by the grid */
+    int32_t block_dims[3];    /* blocks of the Sect. 2.3 locate structure (0 if not built) */
+    int64_t block_entries;    /* total length of its cell lists */
 } vor_grid_info;
 
 /*
@@ -129,6 +135,15 @@ vor_status vor_grid_get_info(const vor_grid *grid, vor_grid_info *info);
 vor_status vor_grid_volumes(const vor_grid *grid, double *volume, void *stream);
 
 /*
+ * vor_grid_bboxes -- the bounding box of every clipped cell (Sect. 2.3: from
+ * its vertices, the cell being convex), as the builder computed it.
+ *   bbox  device, M x 6 doubles {xmin, ymin, zmin, xmax, ymax, zmax}, user order.
+ * VOR_EINVAL unless the grid was built with opts.block_lists = 1.
+ * Asynchronous on `stream`.
+ */
+vor_status vor_grid_bboxes(const vor_grid *grid, double *bbox, void *stream);
+
+/*
  * Diagnostic: keeps only the first `keep` entries (internal order) of the
  * neighbour list of site `site` (user index), so that the table misses
  * faces of that cell and paths through it take the no-exit fallback of
@@ -159,6 +174,19 @@ vor_status vor_grid_neighbors(const vor_grid *grid, int64_t *row_ptr, int32_t *c
  * Asynchronous on `stream`; allocates nothing.
  */
 vor_status vor_locate(const vor_grid *grid, const double *pts, int64_t N, int32_t *cell, void *stream);
+
+/*
+ * vor_locate_blocks -- C(r) as Sect. 2.3 builds it: -1 outside the closed
+ * box (step 1); else the block of the regular grid holding the point
+ * (step 2), the cells listed for that block -- those whose bounding box,
+ * widened by 1e-9 of its extent, overlaps it (step 3) -- and the nearest of
+ * their sites by squared distance, equal distances going to the lowest index
+ * (step 4). Same result as vor_locate.
+ *   pts   device, N x 3.     cell  device, N int32.    N >= 0.
+ * VOR_EINVAL unless the grid was built with opts.block_lists = 1.
+ * Asynchronous on `stream`; allocates nothing.
+ */
+vor_status vor_locate_blocks(const vor_grid *grid, const double *pts, int64_t N, int32_t *cell, void *stream);
 
 /* Options of vor_trace; zero-initialised fields take the defaults. */
 typedef struct {

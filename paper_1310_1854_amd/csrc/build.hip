@@ -100,6 +100,7 @@ struct ClipArgs {
     int32_t *n_retry;
     int *err;
     double *volume;           // [M] cell volumes
+    double *bbox;             // [6 M] cell bounding boxes, or null
 };
 
 // First pass: one wave per site with a small cell in LDS; cells that run
@@ -109,10 +110,13 @@ __global__ void __launch_bounds__(64) k_clip(ClipArgs A)
     __shared__ WaveCellSmall cell;
     const int64_t i = blockIdx.x;
     uint8_t wm = 0;
-    double vol = 0.0;
-    int n = wclip_site(cell, A.sites, A.grid, A.box, i, A.nbr + i * kMaxNbr, kMaxNbr, &wm, &vol);
+    double vol = 0.0, bb[6];
+    int n = wclip_site(cell, A.sites, A.grid, A.box, i, A.nbr + i * kMaxNbr, kMaxNbr, &wm, &vol,
+                       A.bbox ? bb : nullptr);
     if (threadIdx.x == 0) {
         A.volume[i] = vol;
+        if (A.bbox && n >= 0)
+            for (int a = 0; a < 6; ++a) A.bbox[6 * i + a] = bb[a];
         if (n == -ERR_CAPACITY) {
             A.retry[atomicAdd(A.n_retry, 1)] = (int32_t)i;
             n = 0;
@@ -132,10 +136,13 @@ __global__ void __launch_bounds__(64) k_clip_big(ClipArgs A, int32_t *__restrict
     const int k = blockIdx.x;
     const int64_t i = A.retry[k];
     uint8_t wm = 0;
-    double vol = 0.0;
-    int n = wclip_site(cell, A.sites, A.grid, A.box, i, big_nbr + (int64_t)k * kMaxNbrBig, kMaxNbrBig, &wm, &vol);
+    double vol = 0.0, bb[6];
+    int n = wclip_site(cell, A.sites, A.grid, A.box, i, big_nbr + (int64_t)k * kMaxNbrBig, kMaxNbrBig, &wm, &vol,
+                       A.bbox ? bb : nullptr);
     if (threadIdx.x == 0) {
         A.volume[i] = vol;
+        if (A.bbox && n >= 0)
+            for (int a = 0; a < 6; ++a) A.bbox[6 * i + a] = bb[a];
         slot[i] = k;
         if (n < 0) {
             atomicOr(A.err, -n);
@@ -144,6 +151,55 @@ __global__ void __launch_bounds__(64) k_clip_big(ClipArgs A, int32_t *__restrict
         A.cnt[i] = n;
         A.walls[i] = wm;
     }
+}
+
+// The paper's locate structure (Sect. 2.3): a regular grid of blocks over
+// the box; block k lists every cell whose bounding box overlaps it. The box
+// of cell i is widened by 1e-9 of its extent (plus 1e-12 of the domain's)
+// on each side, so that rounding in its vertices cannot drop a block the
+// cell reaches. Blocks are numbered (x * ny + y) * nz + z.
+struct LocArgs {
+    const double *bbox;   // [6 M] internal order
+    int64_t M;
+    double lo[3], inv_h[3], ext[3];
+    int32_t dims[3];
+};
+
+__device__ __forceinline__ void loc_range(const LocArgs &A, int64_t i, int b0[3], int b1[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const double lo = A.bbox[6 * i + a], hi = A.bbox[6 * i + a + 3];
+        const double m = 1e-9 * (hi - lo) + 1e-12 * A.ext[a];
+        b0[a] = bucket_coord(lo - m, A.lo[a], A.inv_h[a], A.dims[a]);
+        b1[a] = bucket_coord(hi + m, A.lo[a], A.inv_h[a], A.dims[a]);
+    }
+}
+
+__global__ void k_loc_count(LocArgs A, int32_t *__restrict__ cnt, unsigned long long *__restrict__ total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.M) return;
+    int b0[3], b1[3];
+    loc_range(A, i, b0, b1);
+    for (int x = b0[0]; x <= b1[0]; ++x)
+        for (int y = b0[1]; y <= b1[1]; ++y)
+            for (int z = b0[2]; z <= b1[2]; ++z) atomicAdd(&cnt[((int64_t)x * A.dims[1] + y) * A.dims[2] + z], 1);
+    atomicAdd(total, (unsigned long long)(b1[0] - b0[0] + 1) * (b1[1] - b0[1] + 1) * (b1[2] - b0[2] + 1));
+}
+
+__global__ void k_loc_fill(LocArgs A, const int32_t *__restrict__ start, int32_t *__restrict__ cursor,
+                           int32_t *__restrict__ cells)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.M) return;
+    int b0[3], b1[3];
+    loc_range(A, i, b0, b1);
+    for (int x = b0[0]; x <= b1[0]; ++x)
+        for (int y = b0[1]; y <= b1[1]; ++y)
+            for (int z = b0[2]; z <= b1[2]; ++z) {
+                const int64_t k = ((int64_t)x * A.dims[1] + y) * A.dims[2] + z;
+                cells[start[k] + atomicAdd(&cursor[k], 1)] = (int32_t)i;
+            }
 }
 
 // Directed lists -> CSR (dir_start from a scan of cnt). slot[i] >= 0 marks a
@@ -349,6 +405,9 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(box[a]) || !std::isfinite(box[a + 3]) || !(box[a] < box[a + 3])) return VOR_EINVAL;
     double occ = (opts && opts->bucket_occupancy > 0) ? opts->bucket_occupancy : 2.0;
+    const bool want_loc = opts && opts->block_lists;
+    const double locc = (opts && opts->block_occupancy > 0) ? opts->block_occupancy : 1.0;
+    if (opts && (opts->block_lists < 0 || opts->block_lists > 1 || !(opts->block_occupancy >= 0))) return VOR_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
 
@@ -382,6 +441,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     g.wall_mask = dalloc<uint8_t>(M, rc, keep);
     g.volume = dalloc<double>(M, rc, keep);
     g.bucket_sites = dalloc<Site>(M, rc, keep);
+    if (want_loc) g.bbox = dalloc<double>((size_t)M * 6, rc, keep);
 
     // bucket grid dimensions: about `occ` sites per bucket, cube-like buckets
     double vol = (box[3] - box[0]) * (box[4] - box[1]) * (box[5] - box[2]);
@@ -461,6 +521,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     ca.n_retry = err + 2;
     ca.err = err;
     ca.volume = g.volume;
+    ca.bbox = g.bbox;
     if (hipMemsetAsync(slot, 0xff, sizeof(int32_t) * M, st) != hipSuccess) return fail(VOR_EDEVICE);
     hipLaunchKernelGGL(k_clip, dim3((unsigned)M), dim3(64), 0, st, ca);
     if (hipGetLastError() != hipSuccess) return fail(VOR_EDEVICE);
@@ -541,9 +602,52 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     g.nnz_walls = nnzw;
     g.max_row = mrow;
 
+    if (want_loc) {
+        // blocks: about M / locc of them, cube-like
+        LocArgs la;
+        la.bbox = g.bbox;
+        la.M = M;
+        const double hl = std::cbrt(vol * locc / (double)M);
+        int64_t K = 1;
+        for (int a = 0; a < 3; ++a) {
+            const double e = box[a + 3] - box[a];
+            const int n = std::max(1, std::min((int)std::ceil(e / hl), 1024));
+            g.loc_dims[a] = la.dims[a] = n;
+            g.loc_inv_h[a] = la.inv_h[a] = n / e;
+            la.lo[a] = box[a];
+            la.ext[a] = e;
+            K *= n;
+        }
+        if (K >= 0x7fffffffLL) return fail(VOR_ECAPACITY);
+        int32_t *lcnt = dalloc<int32_t>(K, rc, tmp);
+        unsigned long long *ltot = dalloc<unsigned long long>(1, rc, tmp);
+        g.loc_start = dalloc<int32_t>(K + 1, rc, keep);
+        if (rc != VOR_OK) return fail(rc);
+        if (hipMemsetAsync(lcnt, 0, sizeof(int32_t) * K, st) != hipSuccess ||
+            hipMemsetAsync(ltot, 0, sizeof(unsigned long long), st) != hipSuccess)
+            return fail(VOR_EDEVICE);
+        hipLaunchKernelGGL(k_loc_count, dim3(blocks_for(M, T)), dim3(T), 0, st, la, lcnt, ltot);
+        unsigned long long entries = 0;
+        if (hipMemcpyAsync(&entries, ltot, sizeof(entries), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
+            return fail(VOR_EDEVICE);
+        if (entries >= 0x7fffffffULL) return fail(VOR_ECAPACITY);
+        rc = vrt_scan_i32_to_i32(lcnt, K, g.loc_start, st);
+        if (rc != VOR_OK) return fail(rc);
+        g.loc_cells = dalloc<int32_t>(std::max<unsigned long long>(entries, 1), rc, keep);
+        if (rc != VOR_OK) return fail(rc);
+        if (hipMemsetAsync(lcnt, 0, sizeof(int32_t) * K, st) != hipSuccess) return fail(VOR_EDEVICE);
+        hipLaunchKernelGGL(k_loc_fill, dim3(blocks_for(M, T)), dim3(T), 0, st, la, g.loc_start, lcnt, g.loc_cells);
+        if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) return fail(VOR_EDEVICE);
+        g.loc_entries = (int64_t)entries;
+    }
+
     for (void *p : tmp) (void)hipFree(p);
     g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + sizeof(double)) + (B + 1) * 4 +
                      (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Rec32);
+    if (want_loc)
+        g.device_bytes += (int64_t)M * 6 * (int64_t)sizeof(double) +
+                          ((int64_t)g.loc_dims[0] * g.loc_dims[1] * g.loc_dims[2] + 1 + g.loc_entries) * 4;
     g.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = G;
     return VOR_OK;
@@ -555,7 +659,7 @@ extern "C" void vor_grid_free(vor_grid *G)
     (void)hipDeviceSynchronize();
     Grid &g = G->g;
     void *ptrs[] = {g.sites, g.perm, g.inv_perm, g.rows, g.rec64, g.blk, g.wall_mask, g.volume, g.bucket_start,
-                    g.bucket_sites};
+                    g.bucket_sites, g.bbox, g.loc_start, g.loc_cells};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete G;
@@ -573,6 +677,8 @@ extern "C" vor_status vor_grid_get_info(const vor_grid *G, vor_grid_info *info)
     for (int a = 0; a < 6; ++a) info->box[a] = g.box[a];
     info->build_ms = g.build_ms;
     info->device_bytes = g.device_bytes;
+    for (int a = 0; a < 3; ++a) info->block_dims[a] = g.loc_dims[a];
+    info->block_entries = g.loc_entries;
     return VOR_OK;
 }
 
@@ -611,6 +717,25 @@ extern "C" vor_status vor_grid_truncate_row(vor_grid *G, int64_t site, int32_t k
             return VOR_EDEVICE;
     }
     return VOR_OK;
+}
+
+__global__ void k_export_bboxes(const int32_t *__restrict__ perm, const double *__restrict__ bb, int64_t M,
+                                double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int64_t u = perm[i];
+    for (int a = 0; a < 6; ++a) out[6 * u + a] = bb[6 * i + a];
+}
+
+extern "C" vor_status vor_grid_bboxes(const vor_grid *G, double *bbox, void *stream)
+{
+    if (!G || !bbox || !G->g.bbox) return VOR_EINVAL;
+    const Grid &g = G->g;
+    const int T = 256;
+    hipLaunchKernelGGL(k_export_bboxes, dim3(blocks_for(g.M, T)), dim3(T), 0, (hipStream_t)stream, g.perm, g.bbox,
+                       g.M, bbox);
+    return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
 __global__ void k_export_volumes(const int32_t *__restrict__ perm, const double *__restrict__ vol, int64_t M,

@@ -402,9 +402,35 @@ __device__ double wcell_volume(const C &c, int nt)
     return fabs(acc) / 6.0;
 }
 
+// Bounding box of the clipped cell from its vertices (Sect. 2.3: the cell
+// is convex), absolute coordinates {xmin, ymin, zmin, xmax, ymax, zmax};
+// every lane gets it.
+template <class C>
+__device__ void wcell_bbox(const C &c, int nt, const double p[3], double bb[6])
+{
+    double lo[3] = {__builtin_huge_val(), __builtin_huge_val(), __builtin_huge_val()};
+    double hi[3] = {-__builtin_huge_val(), -__builtin_huge_val(), -__builtin_huge_val()};
+    for (int t = lane_id(); t < nt; t += 64) {
+        const double v[3] = {c.vx[t], c.vy[t], c.vz[t]};
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], v[a]);
+            hi[a] = fmax(hi[a], v[a]);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], off, 64));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], off, 64));
+        }
+        bb[a] = p[a] + lo[a];
+        bb[a + 3] = p[a] + hi[a];
+    }
+}
+
 template <class C>
 __device__ int wclip_site(C &c, const Site *__restrict__ sites, const BucketGridView &grid, const BoxArg &box,
-                          int64_t i, int32_t *nbr, int max_nbr, uint8_t *walls, double *volume = nullptr)
+                          int64_t i, int32_t *nbr, int max_nbr, uint8_t *walls, double *volume = nullptr,
+                          double *bbox = nullptr)
 {
     const int l = lane_id();
     const uint64_t lt = lanemask_lt();
@@ -483,6 +509,7 @@ __device__ int wclip_site(C &c, const Site *__restrict__ sites, const BucketGrid
     }
     if (err) return -err;
     if (volume) *volume = wcell_volume(c, nt);
+    if (bbox) wcell_bbox(c, nt, p, bbox);
     // faces: plane slots some vertex still uses
     constexpr int W = (C::kPlanes + 63) / 64;
     uint64_t used[W];

@@ -359,7 +359,73 @@ __global__ void __launch_bounds__(256) k_locate(BucketGridView g, double lo0, do
     cell[i] = uid;
 }
 
+// C(r) through the paper's block lists (Sect. 2.3, steps 1-4): outside the
+// closed box -1; else the block holding the point, then the nearest site
+// among the cells listed for that block (equal distances: the lowest user
+// index). The cell holding the point is listed there, so this is the
+// nearest site of all.
+struct LocView {
+    double lo[3], hi[3], inv_h[3];
+    int32_t dims[3];
+    const int32_t *start;
+    const int32_t *cells;
+    const Site *sites;
+};
+
+__global__ void __launch_bounds__(256) k_locate_blocks(LocView L, const double *__restrict__ pts, int64_t N,
+                                                       int32_t *__restrict__ cell)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double q[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+    if (!(q[0] >= L.lo[0] && q[0] <= L.hi[0] && q[1] >= L.lo[1] && q[1] <= L.hi[1] && q[2] >= L.lo[2] &&
+          q[2] <= L.hi[2])) {
+        cell[i] = -1;
+        return;
+    }
+    int b[3];
+    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], L.lo[a], L.inv_h[a], L.dims[a]);
+    const int64_t k = ((int64_t)b[0] * L.dims[1] + b[1]) * L.dims[2] + b[2];
+    double best = __builtin_huge_val();
+    int32_t best_u = -1;
+    for (int s = L.start[k]; s < L.start[k + 1]; ++s) {
+        const Site p = L.sites[L.cells[s]];
+        const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const int32_t u = (int32_t)p.uid;
+        if (d2 < best || (d2 == best && u < best_u)) {
+            best = d2;
+            best_u = u;
+        }
+    }
+    cell[i] = best_u;
+}
+
 }  // namespace
+
+extern "C" vor_status vor_locate_blocks(const vor_grid *G, const double *pts, int64_t N, int32_t *cell,
+                                        void *stream)
+{
+    if (!G || N < 0 || (N > 0 && (!pts || !cell))) return VOR_EINVAL;
+    const Grid &g = vrt_grid_of(G);
+    if (!g.loc_start) return VOR_EINVAL;
+    if (N == 0) return VOR_OK;
+    const int T = 256;
+    const int64_t blocks = (N + T - 1) / T;
+    if (blocks > 0x7fffffff) return VOR_EINVAL;
+    LocView L;
+    for (int a = 0; a < 3; ++a) {
+        L.lo[a] = g.box[a];
+        L.hi[a] = g.box[a + 3];
+        L.inv_h[a] = g.loc_inv_h[a];
+        L.dims[a] = g.loc_dims[a];
+    }
+    L.start = g.loc_start;
+    L.cells = g.loc_cells;
+    L.sites = g.sites;
+    hipLaunchKernelGGL(k_locate_blocks, dim3((unsigned)blocks), dim3(T), 0, (hipStream_t)stream, L, pts, N, cell);
+    return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
+}
 
 extern "C" vor_status vor_locate(const vor_grid *G, const double *pts, int64_t N, int32_t *cell, void *stream)
 {

@@ -77,6 +77,15 @@ struct Grid {
     double *volume = nullptr;       // [M] volume of each clipped cell
     int32_t *bucket_start = nullptr;// [B + 1]
     Site *bucket_sites = nullptr;   // [M] sites grouped by bucket (uid holds the internal index)
+    // the paper's locate structure (Sect. 2.3), built on request: a regular
+    // grid of blocks over the box, each listing the cells whose bounding box
+    // overlaps it
+    double *bbox = nullptr;         // [6 M] cell bounding boxes {min xyz, max xyz}
+    int32_t loc_dims[3] = {0, 0, 0};
+    double loc_inv_h[3] = {0, 0, 0};
+    int32_t *loc_start = nullptr;   // [K + 1] list of block k: loc_cells[loc_start[k] .. loc_start[k+1])
+    int32_t *loc_cells = nullptr;   // internal cell indices
+    int64_t loc_entries = 0;
     double build_ms = 0;
     int64_t device_bytes = 0;
     int device = 0;

@@ -29,7 +29,8 @@ EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_nei
            "vor_trace", "vor_order_rays", "vor_order_workspace_bytes", "vor_exclusive_scan", "vor_status_str", "vor_version",
            "vor_server_create", "vor_server_submit", "vor_server_poll", "vor_server_wait", "vor_server_result",
            "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy",
-           "vor_server_next_done", "vor_grid_truncate_row", "vor_grid_volumes"]
+           "vor_server_next_done", "vor_grid_truncate_row", "vor_grid_volumes", "vor_grid_bboxes",
+           "vor_locate_blocks"]
 
 
 class VorError(RuntimeError):
@@ -39,13 +40,15 @@ class VorError(RuntimeError):
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("bucket_occupancy", ctypes.c_double)]
+    _fields_ = [("bucket_occupancy", ctypes.c_double), ("block_lists", ctypes.c_int32),
+                ("block_occupancy", ctypes.c_double)]
 
 
 class GridInfo(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int64), ("nnz", ctypes.c_int64), ("nnz_with_walls", ctypes.c_int64),
                 ("max_row", ctypes.c_int32), ("dims", ctypes.c_int32 * 3), ("box", ctypes.c_double * 6),
-                ("build_ms", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("build_ms", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("block_dims", ctypes.c_int32 * 3), ("block_entries", ctypes.c_int64)]
 
 
 class TraceOpts(ctypes.Structure):
@@ -104,6 +107,10 @@ def load(path: str = None):
     lib.vor_grid_neighbors.restype = ctypes.c_int
     lib.vor_locate.argtypes = [P, P, I64, P, P]
     lib.vor_locate.restype = ctypes.c_int
+    lib.vor_locate_blocks.argtypes = [P, P, I64, P, P]
+    lib.vor_locate_blocks.restype = ctypes.c_int
+    lib.vor_grid_bboxes.argtypes = [P, P, P]
+    lib.vor_grid_bboxes.restype = ctypes.c_int
     lib.vor_trace.argtypes = [P, P, P, I64, P, D, ctypes.POINTER(TraceOpts), ctypes.POINTER(TraceOut), P]
     lib.vor_trace.restype = ctypes.c_int
     lib.vor_order_rays.argtypes = [P, P, P, I64, P, P, I64, P]
@@ -182,7 +189,8 @@ class Grid:
         inf = GridInfo()
         _check(load().vor_grid_get_info(self._h, ctypes.byref(inf)), "vor_grid_get_info")
         return dict(n_sites=inf.n_sites, nnz=inf.nnz, nnz_with_walls=inf.nnz_with_walls, max_row=inf.max_row,
-                    dims=list(inf.dims), box=list(inf.box), build_ms=inf.build_ms, device_bytes=inf.device_bytes)
+                    dims=list(inf.dims), box=list(inf.box), build_ms=inf.build_ms, device_bytes=inf.device_bytes,
+                    block_dims=list(inf.block_dims), block_entries=inf.block_entries)
 
     def neighbors(self, stream=None):
         """(row_ptr int64[M+1], col int32[nnz]) in user order, walls as -1..-6."""
@@ -196,6 +204,13 @@ class Grid:
         """Volume of every cell (user order), from the builder's clipped cells."""
         out = torch.empty(self.M, dtype=torch.float64, device="cuda")
         _check(load().vor_grid_volumes(self.handle, _ptr(out), _stream(stream)), "vor_grid_volumes")
+        return out
+
+    def bboxes(self, stream=None) -> torch.Tensor:
+        """Bounding box of every cell (user order, M x 6: min xyz, max xyz);
+        needs a grid built with block_lists=True."""
+        out = torch.empty((self.M, 6), dtype=torch.float64, device="cuda")
+        _check(load().vor_grid_bboxes(self.handle, _ptr(out), _stream(stream)), "vor_grid_bboxes")
         return out
 
     def truncate_row(self, site: int, keep: int) -> None:
@@ -215,10 +230,13 @@ class Grid:
             pass
 
 
-def build_grid(sites, box: Sequence[float], bucket_occupancy: float = 0.0, stream=None) -> Grid:
+def build_grid(sites, box: Sequence[float], bucket_occupancy: float = 0.0, block_lists: bool = False,
+               block_occupancy: float = 0.0, stream=None) -> Grid:
+    """vor_build_grid; block_lists also builds the block-list locate
+    structure (vor_locate_blocks) and keeps the cells' bounding boxes."""
     sites_d = _dev_f64(sites, 3)
     box_h = (ctypes.c_double * 6)(*[float(b) for b in box])
-    opts = BuildOpts(float(bucket_occupancy))
+    opts = BuildOpts(float(bucket_occupancy), 1 if block_lists else 0, float(block_occupancy))
     h = ctypes.c_void_p()
     _check(load().vor_build_grid(_ptr(sites_d), sites_d.shape[0], box_h, ctypes.byref(opts), _stream(stream),
                                  ctypes.byref(h)), "vor_build_grid")
@@ -230,6 +248,15 @@ def locate(grid: Grid, pts, out: Optional[torch.Tensor] = None, stream=None) -> 
     n = p.shape[0]
     cell = out if out is not None else torch.empty(n, dtype=torch.int32, device="cuda")
     _check(load().vor_locate(grid.handle, _ptr(p), n, _ptr(cell), _stream(stream)), "vor_locate")
+    return cell
+
+
+def locate_blocks(grid: Grid, pts, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """vor_locate_blocks: C(r) through the block lists of Sect. 2.3."""
+    p = _dev_f64(pts, 3)
+    n = p.shape[0]
+    cell = out if out is not None else torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(load().vor_locate_blocks(grid.handle, _ptr(p), n, _ptr(cell), _stream(stream)), "vor_locate_blocks")
     return cell
 
 

@@ -77,9 +77,15 @@ def test_argument_errors_before_device_work(lib):
     # no box, no out
     assert lib.vor_build_grid(fake, 10, None, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
     assert lib.vor_build_grid(fake, 10, box, None, None, None) == vrt.VOR_EINVAL
+    # bad options of the block-list locate structure
+    for bl, bo in [(2, 0.0), (-1, 0.0), (1, -1.0), (1, float("nan"))]:
+        opts = vrt.BuildOpts(0.0, bl, bo)
+        assert lib.vor_build_grid(fake, 10, box, ctypes.byref(opts), None, ctypes.byref(out)) == vrt.VOR_EINVAL
     # calls on a missing grid
     cell = (ctypes.c_int32 * 10)()
     assert lib.vor_locate(None, fake, 10, cell, None) == vrt.VOR_EINVAL
+    assert lib.vor_locate_blocks(None, fake, 10, cell, None) == vrt.VOR_EINVAL
+    assert lib.vor_grid_bboxes(None, fake, None) == vrt.VOR_EINVAL
     o = vrt.TraceOut()
     assert lib.vor_trace(None, fake, fake, 10, None, 1.0, None, ctypes.byref(o), None) == vrt.VOR_EINVAL
     info = vrt.GridInfo()

@@ -111,3 +111,19 @@ def test_full_size_in_bench_configuration(vrt, name):
     for c in cells:
         for a, b in zip(c[:-1], c[1:]):
             assert b in col[rp[a]:rp[a + 1]]
+
+
+def test_locate_blocks_full_size(vrt):
+    """The paper's block-list locate on the 10^6-site flared disc: the same
+    cell as the bucket-grid locate for 2x10^6 uniform points and every site,
+    and the oracle's cell on a sample."""
+    w = W.make_config(2)
+    grid = vrt.build_grid(w.sites, w.box, block_lists=True)
+    rng = np.random.default_rng(71)
+    pts = np.concatenate([rng.uniform(w.box[:3], w.box[3:], (2_000_000, 3)), w.sites])
+    a = vrt.locate_blocks(grid, pts).cpu().numpy()
+    b = vrt.locate(grid, pts).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert np.array_equal(a[2_000_000:], np.arange(w.M))
+    ref, _ = oracle.locate(w.sites, w.box, pts[:2000])
+    assert np.array_equal(a[:2000], ref)

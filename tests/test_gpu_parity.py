@@ -396,6 +396,73 @@ def test_locate_matches_oracle(vrt, cfg):
     assert np.array_equal(cell[20_011:20_511], np.arange(500))
 
 
+# --------------------------------------------------------------------------
+# the paper's locate structure: cell bounding boxes and block lists
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["cube", "disc", "lattice"])
+def test_bboxes_vs_oracle(vrt, case):
+    w = {"cube": lambda: W.uniform_cube(M=2000, N=1, seed=61),
+         "disc": lambda: W.exp_disc(M=3000, N=1, seed=62),
+         "lattice": lambda: W.random_tensor_lattice((6, 5, 7), N=1)}[case]()
+    grid = vrt.build_grid(w.sites, w.box, block_lists=True)
+    got = grid.bboxes().cpu().numpy()
+    _, _, want = oracle.faces(w.sites, w.box, np.arange(w.M), bboxes=True)
+    ext = want[:, 3:] - want[:, :3]
+    tol = 1e-10 * ext.max(1, keepdims=True) + 1e-13 * (w.box[3:] - w.box[:3]).max()
+    assert np.all(np.abs(got[:, :3] - want[:, :3]) <= tol)
+    assert np.all(np.abs(got[:, 3:] - want[:, 3:]) <= tol)
+    info = grid.info()
+    assert info["block_entries"] >= w.M and min(info["block_dims"]) >= 1
+
+
+def _locate_points(w, rng, n=20000):
+    """Uniform points, the sites themselves, points on the bisector plane of
+    a site and its nearest neighbour (ties), the box's corners and faces
+    (the box is closed) and points outside."""
+    from scipy.spatial import cKDTree
+    lo, hi = w.box[:3], w.box[3:]
+    mids = np.zeros((0, 3))
+    if w.M >= 2:
+        _, nb = cKDTree(w.sites).query(w.sites, k=2)
+        mids = 0.5 * (w.sites + w.sites[nb[:, 1]])
+    corners = np.array([[(hi if (c >> a) & 1 else lo)[a] for a in range(3)] for c in range(8)])
+    face = rng.uniform(lo, hi, (200, 3))
+    ax = rng.integers(0, 3, 200)
+    face[np.arange(200), ax] = np.where(rng.random(200) < 0.5, lo[ax], hi[ax])
+    outside = rng.uniform(lo - (hi - lo), hi + (hi - lo), (500, 3))
+    return np.concatenate([rng.uniform(lo, hi, (n, 3)), w.sites, mids, corners, face, outside])
+
+
+@pytest.mark.parametrize("occ", [0.25, 1.0, 8.0])
+@pytest.mark.parametrize("case", ["cube", "disc", "lattice", "one"])
+def test_locate_blocks_matches_oracle(vrt, case, occ):
+    rng = np.random.default_rng(63)
+    w = {"cube": lambda: W.uniform_cube(M=1500, N=1, seed=64),
+         "disc": lambda: W.exp_disc(M=20000, N=1, seed=65),
+         "lattice": lambda: W.cubic_lattice(6, N=1),
+         "one": lambda: W.uniform_cube(M=1, N=1, seed=66)}[case]()
+    grid = vrt.build_grid(w.sites, w.box, block_lists=True, block_occupancy=occ)
+    pts = _locate_points(w, rng)
+    if case == "lattice":   # points on the cell walls and edges: exact ties between lattice cells
+        pts = np.concatenate([pts, rng.integers(0, 7, (3000, 3)).astype(float),
+                              rng.integers(0, 13, (3000, 3)) * 0.5])
+    got = vrt.locate_blocks(grid, pts).cpu().numpy()
+    want, _ = oracle.locate(w.sites, w.box, pts)
+    assert np.array_equal(got, want)
+    assert np.array_equal(got, vrt.locate(grid, pts).cpu().numpy())
+
+
+def test_locate_blocks_needs_the_lists(vrt):
+    w = W.uniform_cube(M=100, N=1, seed=67)
+    grid = vrt.build_grid(w.sites, w.box)
+    assert grid.info()["block_entries"] == 0
+    for call in (lambda: vrt.locate_blocks(grid, w.sites), grid.bboxes):
+        with pytest.raises(vrt.VorError) as e:
+            call()
+        assert e.value.code == vrt.VOR_EINVAL
+
+
 def test_grid_quality_measure(vrt):
     """The grid-quality measure of Sect. 3.3 (std of rho_t - rho_g at uniform
     points, rho_g the density of the cell holding the point) from the GPU's
