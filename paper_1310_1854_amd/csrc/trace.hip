@@ -15,8 +15,96 @@ const vrt::Grid &vrt_grid_of(const vor_grid *G);
 
 namespace {
 
+// C(r) through the paper's block lists (Sect. 2.3, steps 2-4), for a point
+// inside the closed box: the block holding the point, then the nearest site
+// among the cells listed for that block (equal distances: the lowest user
+// index). The cell holding the point is listed there, so this is the
+// nearest site of all. Returns the internal index (-1 for an empty list,
+// which a point inside the box cannot meet) and the user index in *uid.
+struct LocView {
+    double lo[3], hi[3], inv_h[3];
+    int32_t dims[3];
+    const int32_t *start;   // null: the grid has no block lists
+    const int32_t *cells;
+    const Site *sites;
+};
+
+LocView loc_view(const Grid &g)
+{
+    LocView L;
+    for (int a = 0; a < 3; ++a) {
+        L.lo[a] = g.box[a];
+        L.hi[a] = g.box[a + 3];
+        L.inv_h[a] = g.loc_inv_h[a];
+        L.dims[a] = g.loc_dims[a];
+    }
+    L.start = g.loc_start;
+    L.cells = g.loc_cells;
+    L.sites = g.sites;
+    return L;
+}
+
+__device__ __forceinline__ int32_t nearest_in_blocks(const LocView &L, const double q[3], int32_t *uid)
+{
+    int b[3];
+    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], L.lo[a], L.inv_h[a], L.dims[a]);
+    const int64_t k = ((int64_t)b[0] * L.dims[1] + b[1]) * L.dims[2] + b[2];
+    double best = __builtin_huge_val();
+    int32_t best_u = -1, best_m = -1;
+    for (int s = L.start[k]; s < L.start[k + 1]; ++s) {
+        const int32_t m = L.cells[s];
+        const Site p = L.sites[m];
+        const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const int32_t u = (int32_t)p.uid;
+        if (d2 < best || (d2 == best && u < best_u)) {
+            best = d2;
+            best_u = u;
+            best_m = m;
+        }
+    }
+    *uid = best_u;
+    return best_m;
+}
+
+// The same search by a whole wave for one point shared by its 64 lanes:
+// the lanes take the list in turn, then the best (distance, user index) is
+// reduced across the wave. Returns the internal index on every lane.
+__device__ __forceinline__ int32_t nearest_in_blocks_wave(const LocView &L, const double q[3])
+{
+    int b[3];
+    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], L.lo[a], L.inv_h[a], L.dims[a]);
+    const int64_t k = ((int64_t)b[0] * L.dims[1] + b[1]) * L.dims[2] + b[2];
+    double best = __builtin_huge_val();
+    int32_t best_u = 0x7fffffff, best_m = -1;
+    for (int s = L.start[k] + (int)(threadIdx.x & 63); s < L.start[k + 1]; s += 64) {
+        const int32_t m = L.cells[s];
+        const Site p = L.sites[m];
+        const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const int32_t u = (int32_t)p.uid;
+        if (d2 < best || (d2 == best && u < best_u)) {
+            best = d2;
+            best_u = u;
+            best_m = m;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int32_t ou = __shfl_xor(best_u, off, 64);
+        const int32_t om = __shfl_xor(best_m, off, 64);
+        if (ob < best || (ob == best && ou < best_u)) {
+            best = ob;
+            best_u = ou;
+            best_m = om;
+        }
+    }
+    return best_m;
+}
+
 struct TraceArgs {
     GridRef G;
+    LocView loc;          // the grid's block lists (loc.start null if it has none)
     RayIn I;
     SegOut O;
     int64_t N;
@@ -28,7 +116,7 @@ struct TraceArgs {
     const int64_t *ray_off;
     const int32_t *order;
     unsigned long long *counters;
-    int64_t *work;        // [0] persistent queue head, [1] spill chunks asked for, [2] rays past their window
+    int64_t *work;        // [1] spill chunks asked for, [2] rays past their window, [kHead0 ..] work queues
     int32_t *start;       // start cell (internal) of every ray from k_start_cells, or null: located at ray start
     Extras X;             // interaction points and tallies (kernels with EXT only)
 };
@@ -195,9 +283,17 @@ __global__ void __launch_bounds__(256) k_start_cells(TraceArgs A)
     start_point(r0, k, s0, q);
     const double q0 = __shfl(q[0], 0, 64), q1 = __shfl(q[1], 0, 64), q2 = __shfl(q[2], 0, 64);
     const bool same = valid && st == RAY_OK && q[0] == q0 && q[1] == q1 && q[2] == q2;
-    int32_t m = -1;
-    if (__ballot(true) == ~0ull && __ballot(same) == ~0ull) m = nearest_site_wave(A.G.grid, q, nullptr);
-    else if (valid && st == RAY_OK) m = nearest_site(A.G.grid, q, nullptr);
+    int32_t m = -1, uid;
+    const bool shared = __ballot(true) == ~0ull && __ballot(same) == ~0ull;
+    if (A.loc.start) {   // the paper's block lists: one short list per ray, or one per wave
+        if (shared) m = nearest_in_blocks_wave(A.loc, q);
+        else if (valid && st == RAY_OK) m = nearest_in_blocks(A.loc, q, &uid);
+        if (valid && st == RAY_OK && m < 0) m = nearest_site(A.G.grid, q, nullptr);   // empty list: not in the box
+    } else if (shared) {
+        m = nearest_site_wave(A.G.grid, q, nullptr);
+    } else if (valid && st == RAY_OK) {
+        m = nearest_site(A.G.grid, q, nullptr);
+    }
     if (valid) A.start[ray] = (st == RAY_OK) ? m : -1;
 }
 
@@ -359,19 +455,6 @@ __global__ void __launch_bounds__(256) k_locate(BucketGridView g, double lo0, do
     cell[i] = uid;
 }
 
-// C(r) through the paper's block lists (Sect. 2.3, steps 1-4): outside the
-// closed box -1; else the block holding the point, then the nearest site
-// among the cells listed for that block (equal distances: the lowest user
-// index). The cell holding the point is listed there, so this is the
-// nearest site of all.
-struct LocView {
-    double lo[3], hi[3], inv_h[3];
-    int32_t dims[3];
-    const int32_t *start;
-    const int32_t *cells;
-    const Site *sites;
-};
-
 __global__ void __launch_bounds__(256) k_locate_blocks(LocView L, const double *__restrict__ pts, int64_t N,
                                                        int32_t *__restrict__ cell)
 {
@@ -383,22 +466,9 @@ __global__ void __launch_bounds__(256) k_locate_blocks(LocView L, const double *
         cell[i] = -1;
         return;
     }
-    int b[3];
-    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], L.lo[a], L.inv_h[a], L.dims[a]);
-    const int64_t k = ((int64_t)b[0] * L.dims[1] + b[1]) * L.dims[2] + b[2];
-    double best = __builtin_huge_val();
-    int32_t best_u = -1;
-    for (int s = L.start[k]; s < L.start[k + 1]; ++s) {
-        const Site p = L.sites[L.cells[s]];
-        const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const int32_t u = (int32_t)p.uid;
-        if (d2 < best || (d2 == best && u < best_u)) {
-            best = d2;
-            best_u = u;
-        }
-    }
-    cell[i] = best_u;
+    int32_t uid;
+    nearest_in_blocks(L, q, &uid);
+    cell[i] = uid;
 }
 
 }  // namespace
@@ -413,16 +483,7 @@ extern "C" vor_status vor_locate_blocks(const vor_grid *G, const double *pts, in
     const int T = 256;
     const int64_t blocks = (N + T - 1) / T;
     if (blocks > 0x7fffffff) return VOR_EINVAL;
-    LocView L;
-    for (int a = 0; a < 3; ++a) {
-        L.lo[a] = g.box[a];
-        L.hi[a] = g.box[a + 3];
-        L.inv_h[a] = g.loc_inv_h[a];
-        L.dims[a] = g.loc_dims[a];
-    }
-    L.start = g.loc_start;
-    L.cells = g.loc_cells;
-    L.sites = g.sites;
+    const LocView L = loc_view(g);
     hipLaunchKernelGGL(k_locate_blocks, dim3((unsigned)blocks), dim3(T), 0, (hipStream_t)stream, L, pts, N, cell);
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
@@ -501,6 +562,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     if (mode == VOR_MODE_MIXED && !mixed_mode_fits(g)) return VOR_EINVAL;
     TraceArgs A;
     A.G = grid_ref(g, opts ? opts->max_steps : 0, opts ? opts->eps_mix : 0.0);
+    A.loc = loc_view(g);
     A.I.origins = origins;
     A.I.dirs = dirs;
     A.I.density = density;

@@ -32,7 +32,7 @@ def test_full_size_in_bench_configuration(vrt, name):
     spec = bench.WORKLOADS[name]
     w = W.make_config(spec["cfg"])
     print(f"[fullsize] {name}: {w.M} sites, {w.N} rays", flush=True)
-    grid = vrt.build_grid(w.sites, w.box)
+    grid = bench.build_grid(vrt, w)
     o = torch.as_tensor(w.origins, device="cuda").contiguous()
     d = torch.as_tensor(w.dirs, device="cuda").contiguous()
     rho = torch.as_tensor(w.density, device="cuda").contiguous()

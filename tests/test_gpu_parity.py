@@ -453,6 +453,22 @@ def test_locate_blocks_matches_oracle(vrt, case, occ):
     assert np.array_equal(got, vrt.locate(grid, pts).cpu().numpy())
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_trace_with_block_lists_changes_nothing(vrt, persistent):
+    """A grid with block lists locates the start cells through them; every
+    output equals the trace on the same grid without them."""
+    import torch
+    w = W.flared_disc(M=20000, N=20000, seed=68)
+    o = w.origins.copy()
+    o[:500] = w.origins[:500] + 3000.0 * w.dirs[:500]   # from outside, entering
+    kw = dict(mode="mixed", segments="exact", persistent=persistent, ordered=True, enter=True)
+    a = vrt.trace(vrt.build_grid(w.sites, w.box), o, w.dirs, w.density, **kw)
+    b = vrt.trace(vrt.build_grid(w.sites, w.box, block_lists=True), o, w.dirs, w.density, **kw)
+    for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+        assert torch.equal(a[k], b[k]), k
+    assert int((a["status"] == 0).sum()) > 19000
+
+
 def test_locate_blocks_needs_the_lists(vrt):
     w = W.uniform_cube(M=100, N=1, seed=67)
     grid = vrt.build_grid(w.sites, w.box)
