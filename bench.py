@@ -487,7 +487,9 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32+f64" if mode == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.M} sites, {w.N} rays, {mode} mode",
+        "config": {"workload": f"{args.workload}: {w.M} sites, {w.N} rays, {mode} mode"
+                               + (f", kappa {spec['kappa']}, interaction points and both tallies"
+                                  if spec.get("transport") else ""),
                    "sites": w.M, "rays": w.N, "mode": mode, "seg_stride": spec["stride"],
                    "ordered": bool(spec.get("ordered", False)),
                    "persistent": bool(spec.get("persistent", False))},

@@ -315,6 +315,45 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace(TraceArgs A)
     flush_counters(A, S);
 }
 
+// Tally deposits of the wave's lanes (at most one each, from their last
+// step), added where the wave is converged: the lanes depositing into the
+// same cell as the first pending lane sum their values across the wave and
+// one of them updates the tallies -- a cell met by many rays at once, such
+// as one next to a point source, then takes one atomic per wave instead of
+// one per lane. Up to VRT_DEP_ROUNDS such groups are formed (while a group
+// has two lanes or more); the other lanes update directly.
+#ifndef VRT_DEP_ROUNDS
+#define VRT_DEP_ROUNDS 4
+#endif
+__device__ __forceinline__ void flush_deposits(const Extras &X, RayState &R)
+{
+    bool direct = R.dep_uid >= 0;
+    const int lane = threadIdx.x & 63;
+    for (int round = 0; round < VRT_DEP_ROUNDS; ++round) {
+        const uint64_t pend = __ballot(direct);
+        if (pend == 0ull) break;
+        const int leader = __ffsll((long long)pend) - 1;
+        const int32_t luid = __shfl(R.dep_uid, leader, 64);
+        const bool same = direct && R.dep_uid == luid;
+        if (__popcll(__ballot(same)) < 2) break;
+        double vl = same ? R.dep_len : 0.0, va = same ? R.dep_abs : 0.0;
+        for (int off = 32; off > 0; off >>= 1) {
+            vl += __shfl_xor(vl, off, 64);
+            va += __shfl_xor(va, off, 64);
+        }
+        if (lane == leader) {
+            if (X.tally_len) atomicAdd(&X.tally_len[luid], vl);
+            if (X.tally_abs) atomicAdd(&X.tally_abs[luid], va);
+        }
+        direct = direct && !same;
+    }
+    if (direct) {
+        if (X.tally_len) atomicAdd(&X.tally_len[R.dep_uid], R.dep_len);
+        if (X.tally_abs) atomicAdd(&X.tally_abs[R.dep_uid], R.dep_abs);
+    }
+    R.dep_uid = -1;
+}
+
 // Persistent waves: every lane keeps a ray in flight. Lanes whose ray has
 // ended wait until at least kRefillMin of the wave's lanes are idle (or
 // none is busy); then they take the next rays from the work queue of their
@@ -329,6 +368,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     RayStats S, T;   // S: current ray, T: totals of this lane
     RayState R;
+    R.dep_uid = -1;   // no deferred deposit before the first ray
     int64_t ray = -1;
     bool live = false;
     unsigned long long *heads = (unsigned long long *)&A.work[kHead0];
@@ -377,7 +417,8 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
             continue;
         }
         ++wit;
-        const bool more = live && ray_step<MODE, SEGS, EXT>(A.G, A.I, R, S, A.O, A.X);
+        const bool more = live && ray_step<MODE, SEGS, EXT, EXT>(A.G, A.I, R, S, A.O, A.X);
+        if (EXT && (A.X.tally_len || A.X.tally_abs)) flush_deposits(A.X, R);
         if (live) {
             if (!more) {
 #if VRT_DEFER_FINISH

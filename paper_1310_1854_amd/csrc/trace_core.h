@@ -411,6 +411,8 @@ struct RayState {
     uint8_t st;
     double tstop, wgt, stop_s;   // transport outputs (kernels with Extras only)
     int32_t stop_uid;            // cell of the interaction point, -1 none yet
+    int32_t dep_uid;             // deferred tally deposit of the last step: cell, -1 none
+    double dep_len, dep_abs;     // ... and its two values
 };
 
 __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R, double s0)
@@ -567,12 +569,27 @@ __device__ __forceinline__ bool ray_step_begin(const GridRef &G, RayState &R, Ra
 // site in the block header). Emits the segment, accumulates tau,
 // moves to the next cell; the no-exit fallback of Sect. 2.2 when the current
 // point lies beyond a plane of the cell. Returns false once the path ended.
+// The absorbed fraction exp(-tau) (1 - exp(-dt)), kept out of line: inlined,
+// the FP64 exp and expm1 raise the traversal kernel's register count past
+// what three waves per SIMD allow.
+__device__ __noinline__ double absorbed_fraction(double tau, double dt) { return exp(-tau) * -expm1(-dt); }
+
 // Tallies of a segment of length l in the current cell (kr = kappa rho),
-// with R.tau the optical depth before it.
-__device__ __forceinline__ void deposit(const Extras &X, const RayState &R, double l, double kr)
+// with R.tau the optical depth before it: added at once, or (DEFER) kept in
+// R.dep_* for the caller to add where the wave is converged.
+template <bool DEFER>
+__device__ __forceinline__ void deposit(const Extras &X, RayState &R, double l, double kr)
 {
-    if (X.tally_len) atomicAdd(&X.tally_len[R.uid], R.wgt * l);
-    if (X.tally_abs) atomicAdd(&X.tally_abs[R.uid], R.wgt * exp(-R.tau) * -expm1(-(kr * l)));
+    const double vl = R.wgt * l;
+    const double va = X.tally_abs ? R.wgt * absorbed_fraction(R.tau, kr * l) : 0.0;
+    if (DEFER) {
+        R.dep_uid = R.uid;
+        R.dep_len = vl;
+        R.dep_abs = va;
+    } else {
+        if (X.tally_len) atomicAdd(&X.tally_len[R.uid], vl);
+        if (X.tally_abs) atomicAdd(&X.tally_abs[R.uid], va);
+    }
 }
 
 // Transport set-up of a ray that has started (status known, start cell set).
@@ -582,6 +599,7 @@ __device__ __forceinline__ void ray_extras_begin(const Extras &X, int64_t ray, R
     R.wgt = X.weight ? X.weight[ray] : 1.0;
     R.stop_uid = -1;
     R.stop_s = 0.0;
+    R.dep_uid = -1;
     if (X.tau_stop && R.st == RAY_OK && R.tstop <= 0.0) {   // used up where the path starts: no segment
         R.stop_uid = R.uid;
         R.stop_s = R.s_c;
@@ -596,7 +614,7 @@ __device__ __forceinline__ void ray_extras_finish(const Extras &X, int64_t ray, 
     if (X.stop_s) X.stop_s[ray] = R.stop_uid >= 0 ? R.stop_s : R.L;
 }
 
-template <int MODE, bool SEGS, bool EXT = false>
+template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false>
 __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, RayState &R, RayStats &S,
                                              const SegOut &O, int win, double best, bool redo, int32_t j1,
                                              const Extras &X)
@@ -634,7 +652,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                 if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
                     const double lp = (R.tstop - R.tau) / kr;
                     if (SEGS) store_segment(O, R, S.cnt, R.uid, lp);
-                    deposit(X, R, lp, kr);
+                    deposit<DEFER>(X, R, lp, kr);
                     R.tau = R.tau + kr * lp;
                     ++S.cnt;
                     R.stop_uid = R.uid;
@@ -642,7 +660,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                     return false;
                 }
             }
-            deposit(X, R, len, kr);
+            deposit<DEFER>(X, R, len, kr);
         }
         if (SEGS) store_segment(O, R, S.cnt, R.uid, len);
         if (I.density) R.tau += I.kappa * I.density[R.uid] * len;
@@ -682,7 +700,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
 
 // One exit-point step (Sect. 2.2) with the exit search done by this lane
 // alone. Returns false once the path has ended.
-template <int MODE, bool SEGS, bool EXT = false>
+template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false>
 __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, const SegOut &O,
                                          const Extras &X = Extras{})
 {
@@ -698,7 +716,7 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
                          j1);
         S.nredo += redo ? 1 : 0;
     }
-    return ray_step_end<MODE, SEGS, EXT>(G, I, R, S, O, win, best, redo, j1, X);
+    return ray_step_end<MODE, SEGS, EXT, DEFER>(G, I, R, S, O, win, best, redo, j1, X);
 }
 
 }  // namespace vrt
