@@ -106,3 +106,32 @@ def test_transport_argument_errors(env):
     out.weight = torch.ones(10, dtype=torch.float64, device="cuda").data_ptr()       # weights without a tally
     rc = lib.vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(o), 10, None, 1.0, None, ctypes.byref(out), vrt._stream())
     assert rc == vrt.VOR_EINVAL
+
+
+def test_tallies_from_a_point_source(env):
+    """Rays from one point, as from a star: the lanes of a wave deposit into
+    the same cells at once, so the persistent kernel gathers their deposits
+    per wave before its atomics. Its tallies must equal those of one ray per
+    lane (direct atomics) and the oracle's, to rounding of the sums."""
+    vrt, torch = env[0], env[1]
+    w = W.flared_disc(M=20000, N=12000, seed=810)
+    w.origins = np.zeros_like(w.origins)
+    w.origins[8000:] = w.sites[7]                    # a second source at a site
+    rng = np.random.default_rng(811)
+    ts = -np.log(rng.uniform(size=w.N)) * 0.5
+    grid = vrt.build_grid(w.sites, w.box)
+    outs = [vrt.trace(grid, w.origins, w.dirs, w.density, kappa=1e-2, mode="mixed", segments="none",
+                      persistent=p, ordered=p, tau_stop=ts, tallies=True) for p in (True, False)]
+    res = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, kappa=1e-2, cap=256)
+    assert int((res["status"] == 4).sum()) == 0
+    t_len, t_abs = T.tallies(res, w.density, 1e-2, w.M, tau_stop=ts)
+    assert int((t_len > 0).sum()) > 1000
+    n_near = int((res["n_near"] > 0).sum())
+    L = float(res["chord"].max())
+    for out in outs:
+        g_len = out["tally_len"].cpu().numpy()
+        g_abs = out["tally_abs"].cpu().numpy()
+        assert np.max(np.abs(g_len - t_len)) <= 1e-12 * t_len.max() + n_near * 1e-9 * L
+        assert np.max(np.abs(g_abs - t_abs)) <= 1e-12 * t_abs.max() + n_near * 1e-9 * L * 1e-2 * float(w.density.max())
+    a, b = (o["tally_len"].cpu().numpy() for o in outs)
+    assert np.max(np.abs(a - b)) <= 1e-12 * a.max()
