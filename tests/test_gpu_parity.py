@@ -636,6 +636,61 @@ def test_edge_cases(vrt):
     assert np.array_equal(only["tau"], full["tau"]) and np.array_equal(only["n_seg"], full["n_seg"])
 
 
+def _degenerate_case(name, rng):
+    """(sites, box) of a geometrically degenerate grid."""
+    if name == "coplanar":        # every site in z = 0: the cells are prisms
+        xy = rng.uniform(-1, 1, (300, 2))
+        return np.column_stack([xy, np.zeros(300)]), np.array([-1.0, -1, -1, 1, 1, 1])
+    if name == "collinear":       # every site on the x axis: the cells are slabs
+        return np.column_stack([np.sort(rng.uniform(-1, 1, 40)), np.zeros(40), np.zeros(40)]), \
+            np.array([-1.0, -1, -1, 1, 1, 1])
+    if name == "walls":           # sites on the walls, edges and corners of the box
+        p = rng.uniform(-1, 1, (400, 3))
+        ax = rng.integers(0, 3, 400)
+        p[np.arange(400), ax] = np.where(rng.random(400) < 0.5, -1.0, 1.0)
+        corners = np.array([[x, y, z] for x in (-1.0, 1.0) for y in (-1.0, 1.0) for z in (-1.0, 1.0)])
+        return np.concatenate([p, corners]), np.array([-1.0, -1, -1, 1, 1, 1])
+    if name == "offset":          # a unit box far from the origin
+        c = 1e6
+        return c + rng.uniform(-1, 1, (500, 3)), np.array([c - 1, c - 1, c - 1, c + 1, c + 1, c + 1])
+    if name == "tiny":            # a box of side 1e-6
+        return rng.uniform(0, 1e-6, (500, 3)), np.array([0.0, 0, 0, 1e-6, 1e-6, 1e-6])
+    if name == "flat":            # a box 10^6 times longer than it is thick
+        box = np.array([0.0, 0, 0, 1000, 1, 1e-3])
+        return rng.uniform(box[:3], box[3:], (500, 3)), box
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("name", ["coplanar", "collinear", "walls", "offset", "tiny", "flat"])
+def test_degenerate_geometry(vrt, name):
+    import torch
+    rng = np.random.default_rng(90 + len(name))
+    sites, box = _degenerate_case(name, rng)
+    M, N = len(sites), 3000
+    dens = rng.uniform(0.5, 2.0, M)
+    o = rng.uniform(box[:3], box[3:], (N, 3))
+    o[:200] = sites[rng.integers(0, M, 200)]                    # from sites
+    d = rng.normal(size=(N, 3))
+    d[200:400] = np.eye(3)[rng.integers(0, 3, 200)] * rng.choice([-1.0, 1.0], (200, 1))   # along the axes
+    grid = vrt.build_grid(sites, box, block_lists=True)
+    ref = oracle.trace(sites, box, dens, o, d, cap=1024)
+    assert not np.any(ref["status"] == oracle.ST_OVERFLOW)
+    a = vrt.trace(grid, o, d, dens, mode="fp64", segments="exact")
+    st = compare(gpu_paths(a), ref, TOL["fp64"])
+    assert st["max_len_diff"] == 0.0 and st["max_tau_diff"] == 0.0
+    assert st["clean"] > 0.5 * N
+    for persistent in (False, True):
+        b = vrt.trace(grid, o, d, dens, mode="mixed", segments="exact", persistent=persistent, ordered=persistent)
+        for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+            assert torch.equal(a[k], b[k]), (k, persistent)
+    pts = np.concatenate([rng.uniform(box[:3], box[3:], (5000, 3)), sites])
+    want, _ = oracle.locate(sites, box, pts)
+    assert np.array_equal(vrt.locate_blocks(grid, pts).cpu().numpy(), want)
+    assert np.array_equal(vrt.locate(grid, pts).cpu().numpy(), want)
+    vol = grid.volumes().cpu().numpy()
+    assert abs(vol.sum() - np.prod(box[3:] - box[:3])) <= 1e-9 * np.prod(box[3:] - box[:3])
+
+
 def test_build_errors(vrt):
     box = [-1, -1, -1, 1, 1, 1]
     with pytest.raises(vrt.VorError) as e:
