@@ -18,7 +18,8 @@ committed hardware-counter summary (profiles/), reported only while the
 kernel sources still hash to the value recorded there (else null).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-                    [--workload flared_disc|exp_disc|clumpy|uniform_cube|flared_disc_transport|serving|grid_quality]
+                    [--workload flared_disc|exp_disc|clumpy|uniform_cube|flared_disc_transport|serving|
+                                serving_precision|grid_quality]
 """
 from __future__ import annotations
 
@@ -293,6 +294,59 @@ def grid_quality(args, torch, vrt, workloads):
     print(json.dumps(result), flush=True)
 
 
+def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False):
+    """Submit the requests at the given offsets (seconds from the start) to a
+    fresh server, reap them in completion order, and return the wall time,
+    crossings, p50/p99 latency and (keep) every request's tau."""
+    import threading
+
+    srv = vrt.Server(grids, budget_bytes=budget)
+    lat = [None] * len(reqs)
+    taus = [None] * len(reqs)
+    done = threading.Event()
+    lock = threading.Lock()
+    index = {}
+
+    def reaper():
+        nfin = 0
+        while nfin < len(reqs):
+            rid = srv.next_done(1.0)
+            if rid is None:
+                continue
+            with lock:   # the submitter records the id under the same lock
+                i = index[rid]
+            lat[i] = srv.latency(rid)
+            if keep:
+                taus[i] = srv.result(rid)["tau"]   # the release below waits for this copy
+            srv.release(rid)
+            nfin += 1
+        done.set()
+
+    th = threading.Thread(target=reaper, daemon=True)
+    t0 = time.perf_counter()
+    th.start()
+    for i, r in enumerate(reqs):
+        wait = t0 + offsets[i] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        with lock:
+            rid = srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=stride)
+            index[rid] = i
+    if not done.wait(600):
+        raise RuntimeError("serving run did not finish within 600 s")
+    t1 = time.perf_counter()
+    st = srv.stats()
+    while st["running"]:   # crossings are counted when a launch ends
+        time.sleep(0.001)
+        st = srv.stats()
+    srv.close()
+    lat = np.array(lat, dtype=np.float64)
+    out = dict(seconds=t1 - t0, crossings=st["crossings"], rate=st["crossings"] / (t1 - t0),
+               p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+               launches=st["launches"], redecisions=st["fp64_redecisions"])
+    return (out, taus) if keep else out
+
+
 def serving(args, torch, vrt, workloads):
     """Serving mix: three resident grids (10^4, 10^5, 10^6 sites shaped like
     the uniform cube, the exponential disc and the flared disc), Poisson
@@ -300,8 +354,6 @@ def serving(args, torch, vrt, workloads):
     chosen uniformly, accuracy class 50/50 FP64/mixed, 1 GiB of output
     budget. First the saturated rate (every request submitted at once), then
     offered loads of 0.5, 0.8 and 0.95 of it; value = crossings/s at 0.8."""
-    import threading
-
     grids_w = workloads.serving_grids()
     grids = [vrt.build_grid(w.sites, w.box) for w in grids_w]
     rhos = [torch.as_tensor(w.density, device="cuda") for w in grids_w]
@@ -315,52 +367,9 @@ def serving(args, torch, vrt, workloads):
     total_rays = sum(r["o"].shape[0] for r in reqs)
 
     def run(offsets):
-        srv = vrt.Server(grids, budget_bytes=budget)
-        lat = [None] * len(reqs)
-        ids = [None] * len(reqs)
-        done = threading.Event()
-        lock = threading.Lock()
+        return run_server(vrt, grids, rhos, reqs, offsets, stride, budget)
 
-        index = {}
-
-        def reaper():
-            nfin = 0
-            while nfin < len(reqs):
-                rid = srv.next_done(1.0)
-                if rid is None:
-                    continue
-                with lock:   # the submitter records the id under the same lock
-                    i = index[rid]
-                lat[i] = srv.latency(rid)
-                srv.release(rid)
-                nfin += 1
-            done.set()
-
-        th = threading.Thread(target=reaper, daemon=True)
-        t0 = time.perf_counter()
-        th.start()
-        for i, r in enumerate(reqs):
-            wait = t0 + offsets[i] - time.perf_counter()
-            if wait > 0:
-                time.sleep(wait)
-            with lock:
-                rid = srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=stride)
-                ids[i] = rid
-                index[rid] = i
-        if not done.wait(600):
-            raise RuntimeError("serving run did not finish within 600 s")
-        t1 = time.perf_counter()
-        st = srv.stats()
-        while st["running"]:   # crossings are counted when a launch ends
-            time.sleep(0.001)
-            st = srv.stats()
-        srv.close()
-        lat = np.array(lat, dtype=np.float64)
-        return dict(seconds=t1 - t0, crossings=st["crossings"], rate=st["crossings"] / (t1 - t0),
-                    p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                    launches=st["launches"], redecisions=st["fp64_redecisions"])
-
-    warm = run(np.zeros(len(reqs)))
+    run(np.zeros(len(reqs)))   # warm-up
     sat = run(np.zeros(len(reqs)))
     req_rate_sat = len(reqs) / sat["seconds"]
     loads = {}
@@ -382,13 +391,89 @@ def serving(args, torch, vrt, workloads):
     print(json.dumps(result), flush=True)
 
 
+def serving_precision(args, torch, vrt, workloads):
+    """The mixed-precision serving tracer against the plain FP64 GPU tracer on
+    the 10^6-site flared disc (the serving mix's large grid). The same
+    requests (log-uniform sizes in [256, 65536] rays from random sites,
+    isotropic) are served all-FP64 and all-mixed, every request submitted at
+    once (saturated) and at an offered load of 0.8 of that; beside them
+    vor_trace runs the same rays in one persistent launch, in FP64 and mixed,
+    with the same 32-slot windows. Every request's tau must be identical
+    between the two serving runs and equal to vor_trace's (mixed mode
+    reproduces FP64: equal accuracy). The serving kernel's HBM rate is the
+    algorithmic bytes of the same paths (the counters of the mixed vor_trace
+    launch) over the serving wall time; value = the mixed serving rate."""
+    g = workloads.serving_grids()[2]
+    grid = vrt.build_grid(g.sites, g.box)
+    rho = torch.as_tensor(g.density, device="cuda")
+    stride, budget = 32, int(args.budget_gib * (1 << 30))
+    base = workloads.serving_requests(args.requests, [g], rate_hz=1.0)
+    reqs = [dict(grid=0, mode=None, o=torch.as_tensor(r["origins"], device="cuda"),
+                 d=torch.as_tensor(r["dirs"], device="cuda"), t=r["t"]) for r in base]
+    sizes = [r["o"].shape[0] for r in reqs]
+    zeros = np.zeros(len(reqs))
+    served, taus = {}, {}
+    for mode in ("fp64", "mixed"):
+        for r in reqs:
+            r["mode"] = mode
+        run_server(vrt, [grid], [rho], reqs, zeros, stride, budget)   # warm-up
+        sat, taus[mode] = run_server(vrt, [grid], [rho], reqs, zeros, stride, budget, keep=True)
+        gaps = np.array([r["t"] for r in reqs]) / (0.8 * len(reqs) / sat["seconds"])
+        served[mode] = {"saturated": sat, "load_0.8": run_server(vrt, [grid], [rho], reqs, gaps, stride, budget)}
+        print(f"[bench] serving {mode}: {served[mode]}", file=sys.stderr, flush=True)
+    same = all(torch.equal(a, b) for a, b in zip(taus["fp64"], taus["mixed"]))
+
+    # the plain tracer on the same rays, one launch each
+    O = torch.cat([r["o"] for r in reqs]).contiguous()
+    D = torch.cat([r["d"] for r in reqs]).contiguous()
+    N = O.shape[0]
+    plain = {}
+    for mode, ordered in (("fp64", False), ("mixed", False), ("mixed_ordered", True)):
+        spec = {"mode": "mixed", "stride": stride, "spill_chunks_per_ray": 0.0, "persistent": True,
+                "ordered": ordered}
+        bufs = make_buffers(vrt, N, spec, torch, chunks=0)   # 32-slot windows, no spill, as the requests
+        mode = "mixed" if ordered else mode
+        key = "mixed_ordered" if ordered else mode
+        run_steps(vrt, torch, grid, O, D, rho, bufs, spec, mode, 1, timed=False)
+        bufs.counters.zero_()
+        ms = float(np.mean(run_steps(vrt, torch, grid, O, D, rho, bufs, spec, mode, 3, timed=True)))
+        c = bufs.counters.cpu().numpy().astype(np.float64) / 3
+        plain[key] = {"ms": ms, "rate": c[0] / (ms / 1e3), "counters": c}
+        if key == "mixed":
+            tau_plain = bufs.tau.clone()
+    splits = np.cumsum([0] + sizes)
+    equal_plain = all(torch.equal(taus["mixed"][i], tau_plain[splits[i]:splits[i + 1]]) for i in range(len(reqs)))
+    alg = algorithmic_bytes(plain["mixed"]["counters"], N, "mixed", False)
+    sat_m = served["mixed"]["saturated"]
+    serving_gbs = alg / sat_m["seconds"] / 1e9
+    result = {
+        "metric": METRIC, "value": sat_m["rate"], "unit": "crossings/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 1, "ms_per_step": sat_m["seconds"] * 1e3 / len(reqs), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serving precision: {len(reqs)} requests of 256-65536 rays ({N} rays) on the "
+                               f"1e6-site flared disc, all submitted at once, mixed vs FP64, "
+                               f"{args.budget_gib:g} GiB output budget",
+                   "requests": len(reqs), "rays": N, "budget_gib": args.budget_gib},
+        "p50_ms": sat_m["p50_ms"], "p99_ms": sat_m["p99_ms"],
+        "served": served,
+        "plain_tracer": {m: {"ms": v["ms"], "rate": v["rate"]} for m, v in plain.items()},
+        "mixed_serving_over_fp64_serving": sat_m["rate"] / served["fp64"]["saturated"]["rate"],
+        "mixed_serving_over_plain_fp64": sat_m["rate"] / plain["fp64"]["rate"],
+        "tau_identical_fp64_vs_mixed_serving": same, "tau_serving_equals_plain": equal_plain,
+        "serving_roofline": {"bound": "hbm", "achieved": serving_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": serving_gbs / HBM_PEAK_GBS, "algorithmic_bytes": alg},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="flared_disc", choices=sorted(WORKLOADS) + ["serving", "grid_quality"])
+    ap.add_argument("--workload", default="flared_disc", choices=sorted(WORKLOADS) + ["serving", "serving_precision", "grid_quality"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
+    ap.add_argument("--budget-gib", type=float, default=8.0, help="serving_precision: output budget (GiB)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -409,6 +494,9 @@ def main(argv=None):
     if args.workload == "serving":
         torch.cuda.set_device(0)
         return serving(args, torch, vrt, workloads)
+    if args.workload == "serving_precision":
+        torch.cuda.set_device(0)
+        return serving_precision(args, torch, vrt, workloads)
     if args.workload == "grid_quality":
         torch.cuda.set_device(0)
         return grid_quality(args, torch, vrt, workloads)

@@ -376,11 +376,16 @@ vor_status vor_server_result(vor_server *srv, int64_t req_id, vor_trace_out *out
 
 /* Copy a finished request's outputs into caller buffers (device; any may be
  * NULL; seg_cell/seg_len hold n * seg_stride entries), asynchronously on
- * `stream`. */
+ * `stream`. A later vor_server_release waits for these copies: the memory
+ * returns to the budget only once they have run. */
 vor_status vor_server_copy_result(vor_server *srv, int64_t req_id, double *tau, int32_t *n_seg, uint8_t *status,
                                   int32_t *seg_cell, double *seg_len, void *stream);
 
-/* Return a finished request's outputs to the budget. */
+/* Return a finished request's outputs to the budget: at once, or, if copies
+ * from vor_server_copy_result are still running, as soon as the last of them
+ * has finished (the call itself does not wait). The device pointers of
+ * vor_server_result must not be used after this call; work on them must
+ * have completed before it. */
 vor_status vor_server_release(vor_server *srv, int64_t req_id);
 
 vor_status vor_server_get_stats(vor_server *srv, vor_server_stats *stats);

@@ -274,6 +274,14 @@ struct Request {
     uint8_t *status = nullptr;
     int32_t *seg_cell = nullptr;
     double *seg_len = nullptr;
+    hipEvent_t copied = nullptr;   // recorded after the caller's last vor_server_copy_result
+};
+
+// Output memory of a released request whose copies may still be running:
+// it returns to the budget once `copied` has completed.
+struct PendingFree {
+    hipEvent_t copied;
+    size_t off, bytes;
 };
 
 struct Launch {
@@ -327,6 +335,7 @@ struct vor_server {
     int64_t launches_done = 0;
     int launches_running = 0;
     std::deque<int64_t> done_queue;   // completed requests not yet taken by vor_server_next_done
+    std::vector<PendingFree> pending_frees;
     clk::time_point t0;
 
     bool arena_alloc(size_t bytes, size_t &off)
@@ -500,6 +509,24 @@ struct vor_server {
         return any;
     }
 
+    // Released outputs whose copies have finished go back to the budget.
+    bool reap_frees_locked()
+    {
+        bool any = false;
+        for (size_t q = 0; q < pending_frees.size();) {
+            if (hipEventQuery(pending_frees[q].copied) == hipSuccess) {
+                arena_free(pending_frees[q].off, pending_frees[q].bytes);
+                (void)hipEventDestroy(pending_frees[q].copied);
+                pending_frees[q] = pending_frees.back();
+                pending_frees.pop_back();
+                any = true;
+            } else {
+                ++q;
+            }
+        }
+        return any;
+    }
+
     // The launch's kernel has ended: every request in it is complete.
     void complete_locked(Launch &L)
     {
@@ -532,6 +559,7 @@ struct vor_server {
                     progress = true;
                 }
             }
+            if (!pending_frees.empty() && reap_frees_locked()) progress = true;
             if (progress) cv.notify_all();
             admit_locked();
             for (auto &L : launches) {
@@ -541,7 +569,7 @@ struct vor_server {
                 }
             }
             if (!progress) {
-                if (launches_running > 0) {
+                if (launches_running > 0 || !pending_frees.empty()) {
                     lk.unlock();
                     std::this_thread::sleep_for(std::chrono::microseconds(20));
                     lk.lock();
@@ -715,9 +743,9 @@ vor_status vor_server_copy_result(vor_server *S, int64_t req, double *tau, int32
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->reqs.find(req);
     if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
-    const Request &r = it->second;
+    Request &r = it->second;
     hipStream_t st = (hipStream_t)stream;
-    bool ok = true;
+    bool ok = r.copied || hipEventCreateWithFlags(&r.copied, hipEventDisableTiming) == hipSuccess;
     if (tau) ok = ok && hipMemcpyAsync(tau, r.tau, r.n * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
     if (n_seg) ok = ok && hipMemcpyAsync(n_seg, r.n_seg, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, st) == hipSuccess;
     if (status) ok = ok && hipMemcpyAsync(status, r.status, r.n, hipMemcpyDeviceToDevice, st) == hipSuccess;
@@ -726,6 +754,7 @@ vor_status vor_server_copy_result(vor_server *S, int64_t req, double *tau, int32
         if (seg_cell) ok = ok && hipMemcpyAsync(seg_cell, r.seg_cell, ns * sizeof(int32_t), hipMemcpyDeviceToDevice, st) == hipSuccess;
         if (seg_len) ok = ok && hipMemcpyAsync(seg_len, r.seg_len, ns * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
     }
+    ok = ok && hipEventRecord(r.copied, st) == hipSuccess;   // release waits for this
     return ok ? VOR_OK : VOR_EDEVICE;
 }
 
@@ -735,7 +764,12 @@ vor_status vor_server_release(vor_server *S, int64_t req)
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->reqs.find(req);
     if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
-    S->arena_free(it->second.off, it->second.bytes);
+    if (it->second.copied && hipEventQuery(it->second.copied) != hipSuccess) {
+        S->pending_frees.push_back(PendingFree{it->second.copied, it->second.off, it->second.bytes});
+    } else {
+        if (it->second.copied) (void)hipEventDestroy(it->second.copied);
+        S->arena_free(it->second.off, it->second.bytes);
+    }
     S->reqs.erase(it);
     // ids of released requests are skipped by vor_server_next_done; drop
     // them once they make up most of its queue (callers that only wait/poll)
@@ -789,6 +823,16 @@ void vor_server_destroy(vor_server *S)
         if (L.d_head) (void)hipFree(L.d_head);
         if (L.d_counters) (void)hipFree(L.d_counters);
     }
+    // copies of outputs still running finish before the arena goes
+    for (auto &f : S->pending_frees) {
+        (void)hipEventSynchronize(f.copied);
+        (void)hipEventDestroy(f.copied);
+    }
+    for (auto &kv : S->reqs)
+        if (kv.second.copied) {
+            (void)hipEventSynchronize(kv.second.copied);
+            (void)hipEventDestroy(kv.second.copied);
+        }
     if (S->arena) (void)hipFree(S->arena);
     if (S->d_grids) (void)hipFree(S->d_grids);
     delete S;

@@ -206,3 +206,69 @@ def test_completion_queue_and_early_completion(env):
         assert torch.equal(ref["seg_cell"].view(n, stride)[mask], a["seg_cell"].view(n, stride)[mask])
         assert torch.equal(ref["seg_len"].view(n, stride)[mask], a["seg_len"].view(n, stride)[mask])
     assert st["completed"] == len(ids) and st["running"] == 0
+
+
+def test_release_waits_for_copies(env):
+    """Outputs copied with vor_server_copy_result and released at once stay
+    intact until the copy has run. The budget holds one request, the copy
+    stream is held back by a bounded spin kernel, and the next request needs
+    the same memory: it is admitted only after the copy, so the copy reads
+    the first request's results."""
+    vrt, torch, ws, grids, rhos = env
+    w = ws[2]
+    rng = np.random.default_rng(12)
+    n, stride = 20000, 16
+
+    def rays():
+        o = np.ascontiguousarray(w.sites[rng.integers(0, w.M, n)])
+        return torch.as_tensor(o, device="cuda"), torch.as_tensor(W.isotropic_dirs(rng, n), device="cuda")
+
+    (oa, da), (ob, db) = rays(), rays()
+    one = n * (8 + 4 + 1) + n * stride * (4 + 8) + 4096
+    srv = vrt.Server(grids[2:], budget_bytes=int(1.5 * one))
+    s = torch.cuda.Stream()
+    try:
+        ra = srv.submit(0, oa, da, rhos[2], mode="mixed", seg_stride=stride)
+        srv.wait(ra, 120)
+        with torch.cuda.stream(s):
+            torch.cuda._sleep(50_000_000)          # tens of ms: the copy runs after it
+        res_a = srv.result(ra, stream=s)
+        srv.release(ra)
+        rb = srv.submit(0, ob, db, rhos[2], mode="mixed", seg_stride=stride)
+        srv.wait(rb, 120)
+        res_b = srv.result(rb)
+        torch.cuda.synchronize()
+        srv.release(rb)
+        s.synchronize()
+    finally:
+        srv.close()
+    for (o, d), res in (((oa, da), res_a), ((ob, db), res_b)):
+        ref = vrt.trace(grids[2], o, d, rhos[2], mode="mixed", segments="stride", seg_stride=stride)
+        assert torch.equal(ref["tau"], res["tau"]) and torch.equal(ref["n_seg"], res["n_seg"])
+        assert torch.equal(ref["status"], res["status"])
+
+
+def test_serving_on_grids_with_block_lists(env):
+    """Grids built with the block lists of Sect. 2.3 serve like any other:
+    every result equals vor_trace on the same grid and on the grid without
+    the lists."""
+    vrt, torch, ws, grids, rhos = env
+    lgrids = [vrt.build_grid(w.sites, w.box, block_lists=True) for w in ws]
+    reqs = _requests(ws, 12, seed=13)
+    srv = vrt.Server(lgrids, budget_bytes=1 << 30)
+    try:
+        ids = [srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=24) for r in reqs]
+        res = []
+        for rid in ids:
+            srv.wait(rid, 120)
+            res.append(srv.result(rid))
+        torch.cuda.synchronize()
+        for rid in ids:
+            srv.release(rid)
+    finally:
+        srv.close()
+    for r, a in zip(reqs, res):
+        for g in (lgrids[r["grid"]], grids[r["grid"]]):
+            ref = vrt.trace(g, r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], segments="stride", seg_stride=24)
+            assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
+            assert torch.equal(ref["status"], a["status"])
