@@ -272,3 +272,4 @@ def test_serving_on_grids_with_block_lists(env):
             ref = vrt.trace(g, r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], segments="stride", seg_stride=24)
             assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
             assert torch.equal(ref["status"], a["status"])
+
