@@ -218,6 +218,7 @@ __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RaySt
         R.s_c = 0.0;
     }
     if (EXT) ray_extras_begin(A.X, ray, R);
+    settle_start(R);
 }
 
 // nearest_site for a point shared by the whole wave: the sites of each

@@ -415,6 +415,38 @@ struct RayState {
     double dep_len, dep_abs;     // ... and its two values
 };
 
+// Takes the wait for a loaded value here. The hardware counts a lane's
+// loads and stores in one in-order counter, and where paths of a step merge
+// the compiler waits for every load still outstanding on any of them: a
+// value first used after the segment store would then hold the step until
+// the store has completed as well.
+template <class T>
+__device__ __forceinline__ void settle(T &v)
+{
+    asm volatile("" : "+v"(v));
+}
+
+// The state a ray starts its first step with, settled (the loads of its
+// set-up and start cell are waited for before the step, not after its
+// first segment store).
+__device__ __forceinline__ void settle_start(RayState &R)
+{
+    for (int a = 0; a < 3; ++a) {
+        settle(R.r0[a]);
+        settle(R.k[a]);
+        settle(R.pm[a]);
+    }
+    settle(R.rw.x);
+    settle(R.rw.y);
+    settle(R.L);
+    settle(R.s_c);
+    settle(R.m);
+    settle(R.uid);
+    settle(R.b);
+    settle(R.base);
+    settle(R.cap);
+}
+
 __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R, double s0)
 {
     R.s_c = s0;
@@ -619,6 +651,10 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                                              const SegOut &O, int win, double best, bool redo, int32_t j1,
                                              const Extras &X)
 {
+    // The current cell's density, loaded before the winner's header or
+    // record so that one wait covers both (loaded after the segment store,
+    // its wait would also hold the step until the store completed).
+    double rho = I.density ? I.density[R.uid] : 0.0;
     int32_t wj = -1, wuid = 0;
     double wx = 0.0, wy = 0.0, wz = 0.0;
     int2 wrow = make_int2(0, 0);
@@ -631,6 +667,13 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             wy = w.y;
             wz = w.z;
             wrow = G.rows[wj];
+            settle(wj);
+            settle(wuid);
+            settle(wx);
+            settle(wy);
+            settle(wz);
+            settle(wrow.x);
+            settle(wrow.y);
         } else {
             const BlockHdr h = *reinterpret_cast<const BlockHdr *>(G.blk + j1);
             wj = h.j;
@@ -643,10 +686,11 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
         }
     }
+    settle(rho);
     double len = best - R.s_c;
     if (len > 0.0) {
         if (EXT) {
-            const double kr = I.density ? I.kappa * I.density[R.uid] : 0.0;
+            const double kr = I.density ? I.kappa * rho : 0.0;
             if (X.tau_stop) {
                 const double tn = R.tau + kr * len;
                 if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
@@ -662,8 +706,8 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             }
             deposit<DEFER>(X, R, len, kr);
         }
+        if (I.density) R.tau += I.kappa * rho * len;   // before the store: its wait then holds no store
         if (SEGS) store_segment(O, R, S.cnt, R.uid, len);
-        if (I.density) R.tau += I.kappa * I.density[R.uid] * len;
         ++S.cnt;
         R.s_c = best;
     } else if (len < -1e-9 * R.L) {
@@ -684,6 +728,11 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
         R.pm[1] = sm.y;
         R.pm[2] = sm.z;
         R.rw = G.rows[R.m];
+        settle(R.pm[0]);
+        settle(R.pm[1]);
+        settle(R.pm[2]);
+        settle(R.rw.x);
+        settle(R.rw.y);
         R.b = block_of(R.rw, R.m);
         return true;
     }
