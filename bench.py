@@ -59,8 +59,12 @@ def kernel_source_hash() -> str:
 def build_grid(vrt, w):
     """The grid as the benchmark builds it (set-up, outside the timed steps):
     the neighbour table and the paper's block lists (Sect. 2.3), which the
-    start-cell pass of each trace uses."""
-    return vrt.build_grid(w.sites, w.box, block_lists=True)
+    start-cell pass of each trace uses, and the workload's density field
+    bound to it (vor_grid_bind_density), which the steps read."""
+    import torch
+    grid = vrt.build_grid(w.sites, w.box, block_lists=True)
+    grid.bind_density(torch.as_tensor(w.density, dtype=torch.float64, device="cuda").contiguous())
+    return grid
 
 
 def measured_traffic(workload: str):
@@ -182,10 +186,11 @@ def step(vrt, grid, o, d, rho, bufs, spec, mode, reuse_order=False):
     ordered = spec.get("ordered", False)
     if ordered and not reuse_order:
         vrt.order_rays(grid, o, d, bufs.order, bufs.order_ws)
+    gd = spec.get("grid_density", True)   # the density bound to the grid at set-up (vor_grid_bind_density)
     opts = vrt.TraceOpts(vrt.MODES[mode], 0, 0.0, 1 if spec.get("persistent", False) else 0,
-                         1 if reuse_order else 0)
+                         1 if reuse_order else 0, 0, 1 if gd else 0)
     out = bufs.struct(use_order=ordered, **(getattr(bufs, "transport", None) or {}))
-    rc = vrt.load().vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(d), o.shape[0], vrt._ptr(rho),
+    rc = vrt.load().vor_trace(grid.handle, vrt._ptr(o), vrt._ptr(d), o.shape[0], vrt._ptr(None if gd else rho),
                               float(spec.get("kappa", 1.0)), vrt.ctypes.byref(opts), vrt.ctypes.byref(out),
                               vrt._stream())
     if rc != vrt.VOR_OK:
@@ -558,6 +563,12 @@ def main(argv=None):
     fp64_value = fc[0] / f_wall
     same_tau = bool(torch.equal(fb.tau, tau_mixed))
     same_nseg = bool(torch.equal(fb.n_seg, nseg_mixed))
+    # the bound density against the same field passed as an array (one more step)
+    density_check = None
+    if spec.get("grid_density", True):
+        run_steps(vrt, torch, grid, o, d, rho, bufs, dict(spec, grid_density=False), mode, 1, timed=False)
+        density_check = {"tau_bit_identical": bool(torch.equal(bufs.tau, tau_mixed)),
+                         "n_seg_identical": bool(torch.equal(bufs.n_seg, nseg_mixed))}
 
     traffic, traffic_src, l2_hit = measured_traffic(args.workload)
     copy_bw = copy_bandwidth(torch)
@@ -580,7 +591,8 @@ def main(argv=None):
                                   if spec.get("transport") else ""),
                    "sites": w.M, "rays": w.N, "mode": mode, "seg_stride": spec["stride"],
                    "ordered": bool(spec.get("ordered", False)),
-                   "persistent": bool(spec.get("persistent", False))},
+                   "persistent": bool(spec.get("persistent", False)),
+                   "density": "bound to the grid" if spec.get("grid_density", True) else "array per call"},
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),
         "crossings_per_step": crossings,
@@ -590,6 +602,7 @@ def main(argv=None):
         "fp64_value": fp64_value,
         "fp64_ms_per_step": f_wall * 1e3,
         "mixed_vs_fp64": {"tau_bit_identical": same_tau, "n_seg_identical": same_nseg},
+        "bound_vs_array_density": density_check,
         "grid": {"build_ms": info["build_ms"], "nnz": info["nnz"], "max_row": info["max_row"],
                  "device_bytes": info["device_bytes"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -144,6 +144,19 @@ vor_status vor_grid_volumes(const vor_grid *grid, double *volume, void *stream);
 vor_status vor_grid_bboxes(const vor_grid *grid, double *bbox, void *stream);
 
 /*
+ * vor_grid_bind_density -- keeps an exact copy of a density field (the rho_m
+ * of the optical depth, Sect. 2.2: tau = kappa * sum of rho_m l_m over the
+ * segments) inside the grid, beside each cell's site, for traces that ask
+ * for it with vor_trace_opts.grid_density = 1: a step then reads the density
+ * of its cell with the cell's other data instead of from a separate array.
+ *   density  device, M doubles, user order; read during the call only. NULL
+ *            removes the bound field.
+ * Asynchronous on `stream`; allocates nothing. Changes the grid: traces
+ * that overlap the call on another stream may see either field.
+ */
+vor_status vor_grid_bind_density(vor_grid *grid, const double *density, void *stream);
+
+/*
  * Diagnostic: keeps only the first `keep` entries (internal order) of the
  * neighbour list of site `site` (user index), so that the table misses
  * faces of that cell and paths through it take the no-exit fallback of
@@ -204,6 +217,9 @@ typedef struct {
                                start cell is C(r0 + s0 k); a ray that misses the box (s0 >= L) or has a
                                non-finite origin gets VOR_RAY_OUTSIDE. 0: every origin outside the box is
                                VOR_RAY_OUTSIDE */
+    int32_t grid_density;   /* 1: the densities are those bound to the grid by vor_grid_bind_density (the
+                               density argument must then be NULL); tau is the same as with that field
+                               passed as the density argument. VOR_EINVAL if none is bound */
 } vor_trace_opts;
 
 /* Outputs of vor_trace. All pointers are device memory; tau and n_seg are required. */

@@ -319,7 +319,8 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
         h.uid = (int32_t)si.uid;
         h.j = (int32_t)i;
         h.len = n;
-        h.pad[0] = h.pad[1] = h.pad[2] = 0;
+        h.pad = 0;
+        h.rho = 0.0;
         *reinterpret_cast<BlockHdr *>(blk + bo) = h;
         for (int e = 0; e < n; ++e) {
             int32_t j = col[s0 + e];
@@ -736,6 +737,27 @@ extern "C" vor_status vor_grid_bboxes(const vor_grid *G, double *bbox, void *str
     hipLaunchKernelGGL(k_export_bboxes, dim3(blocks_for(g.M, T)), dim3(T), 0, (hipStream_t)stream, g.perm, g.bbox,
                        g.M, bbox);
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
+}
+
+__global__ void k_bind_density(Rec32 *__restrict__ blk, const int2 *__restrict__ rows, const int32_t *__restrict__ perm,
+                               int64_t M, const double *__restrict__ density)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    BlockHdr *h = reinterpret_cast<BlockHdr *>(blk + block_of(rows[i], (int32_t)i));
+    h->rho = density ? density[perm[i]] : 0.0;
+}
+
+extern "C" vor_status vor_grid_bind_density(vor_grid *G, const double *density, void *stream)
+{
+    if (!G) return VOR_EINVAL;
+    Grid &g = G->g;
+    const int T = 256;
+    hipLaunchKernelGGL(k_bind_density, dim3(blocks_for(g.M, T)), dim3(T), 0, (hipStream_t)stream, g.blk, g.rows,
+                       g.perm, g.M, density);
+    if (hipGetLastError() != hipSuccess) return VOR_EDEVICE;
+    g.rho_bound = density ? 1 : 0;
+    return VOR_OK;
 }
 
 __global__ void k_export_volumes(const int32_t *__restrict__ perm, const double *__restrict__ vol, int64_t M,

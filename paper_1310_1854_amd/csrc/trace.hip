@@ -204,7 +204,7 @@ __device__ __forceinline__ void flush_counters(const TraceArgs &A, const RayStat
     }
 }
 
-template <bool EXT>
+template <bool EXT, int MODE>
 __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RayState &R)
 {
     double s0;
@@ -218,6 +218,7 @@ __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RaySt
         R.s_c = 0.0;
     }
     if (EXT) ray_extras_begin(A.X, ray, R);
+    R.rho = (MODE != VOR_MODE_FP64 && A.I.grid_rho && R.st == RAY_OK) ? block_rho(A.G, R.b) : 0.0;
     settle_start(R);
 }
 
@@ -308,7 +309,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace(TraceArgs A)
         const int64_t ray = A.order ? (int64_t)A.order[lane_ray] : lane_ray;
         RayState R;
         ray_window<SEGS>(A, ray, R);
-        ray_start<EXT>(A, ray, R);
+        ray_start<EXT, MODE>(A, ray, R);
         while (ray_step<MODE, SEGS, EXT>(A.G, A.I, R, S, A.O, A.X)) {
         }
         ray_finish<SEGS, EXT>(A, ray, R, S);
@@ -402,7 +403,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
                     ray = A.order ? (int64_t)A.order[q] : q;
                     S = RayStats();
                     ray_window<SEGS>(A, ray, R);
-                    ray_start<EXT>(A, ray, R);
+                    ray_start<EXT, MODE>(A, ray, R);
                     live = true;
                 } else {
                     ray = -1;
@@ -602,6 +603,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     if (out->weight && !out->tally_len && !out->tally_abs) return VOR_EINVAL;
     const Grid &g = vrt_grid_of(G);
     if (mode == VOR_MODE_MIXED && !mixed_mode_fits(g)) return VOR_EINVAL;
+    if (opts && opts->grid_density && (density || !g.rho_bound)) return VOR_EINVAL;
     TraceArgs A;
     A.G = grid_ref(g, opts ? opts->max_steps : 0, opts ? opts->eps_mix : 0.0);
     A.loc = loc_view(g);
@@ -610,6 +612,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     A.I.density = density;
     A.I.kappa = kappa;
     A.I.enter = opts ? opts->enter : 0;
+    A.I.grid_rho = (opts && opts->grid_density) ? 1 : 0;
     A.N = N;
     A.tau = out->tau;
     A.n_seg = out->n_seg;

@@ -37,6 +37,7 @@ struct RayIn {
     const double *density;
     double kappa;
     int32_t enter;     // rays from outside the box start where they enter it
+    int32_t grid_rho;  // densities from the cells' block headers (bound to the grid) instead of `density`
 };
 
 // Where segments go: a window per ray, then (optionally) a chain of spill
@@ -45,6 +46,9 @@ constexpr int kSpillChunk = VOR_SPILL_CHUNK;
 
 #ifndef VRT_VEC_STORE
 #define VRT_VEC_STORE 1
+#endif
+#ifndef VRT_NT_STORE
+#define VRT_NT_STORE 1
 #endif
 
 struct SegOut {
@@ -407,7 +411,8 @@ struct RayState {
     double l0, l1, l2, l3;
 #endif
     int32_t m, uid;
-    int32_t b;            // offset of the current cell's block (mixed mode)
+    int32_t b;            // offset of the current cell's block
+    double rho;           // the current cell's density from its block header (mixed mode with grid_rho)
     uint8_t st;
     double tstop, wgt, stop_s;   // transport outputs (kernels with Extras only)
     int32_t stop_uid;            // cell of the interaction point, -1 none yet
@@ -424,6 +429,12 @@ template <class T>
 __device__ __forceinline__ void settle(T &v)
 {
     asm volatile("" : "+v"(v));
+}
+
+// The density held in the header of the block at offset b.
+__device__ __forceinline__ double block_rho(const GridRef &G, int32_t b)
+{
+    return reinterpret_cast<const BlockHdr *>(G.blk + b)->rho;
 }
 
 // The state a ray starts its first step with, settled (the loads of its
@@ -443,6 +454,7 @@ __device__ __forceinline__ void settle_start(RayState &R)
     settle(R.m);
     settle(R.uid);
     settle(R.b);
+    settle(R.rho);
     settle(R.base);
     settle(R.cap);
 }
@@ -538,9 +550,17 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
             if (p >= 0) {
                 int32_t *cp = spill ? O.spill_cell : O.cell;
                 double *lp = spill ? O.spill_len : O.len;
+#if VRT_NT_STORE   // streaming: the segments are not read again here; the stores leave the L2 to the records
+                typedef int v4i __attribute__((ext_vector_type(4)));
+                typedef double v2d __attribute__((ext_vector_type(2)));
+                __builtin_nontemporal_store(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp + p));
+                __builtin_nontemporal_store(v2d{R.l0, R.l1}, reinterpret_cast<v2d *>(lp + p));
+                __builtin_nontemporal_store(v2d{R.l2, R.l3}, reinterpret_cast<v2d *>(lp + p + 2));
+#else
                 *reinterpret_cast<int4 *>(cp + p) = make_int4(R.c0, R.c1, R.c2, R.c3);
                 *reinterpret_cast<double2 *>(lp + p) = make_double2(R.l0, R.l1);
                 *reinterpret_cast<double2 *>(lp + p + 2) = make_double2(R.l2, R.l3);
+#endif
             }
         }
         return;
@@ -651,10 +671,16 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                                              const SegOut &O, int win, double best, bool redo, int32_t j1,
                                              const Extras &X)
 {
-    // The current cell's density, loaded before the winner's header or
-    // record so that one wait covers both (loaded after the segment store,
-    // its wait would also hold the step until the store completed).
-    double rho = I.density ? I.density[R.uid] : 0.0;
+    // The current cell's density. Bound to the grid: from the block headers
+    // (mixed mode: read with the cell's header when the ray entered it; FP64
+    // mode: from the current block's header). Else from the caller's array,
+    // loaded before the winner's header or record so that one wait covers
+    // both (loaded after the segment store, its wait would also hold the step
+    // until the store completed).
+    const bool has_rho = I.grid_rho || I.density;
+    double rho = 0.0, wrho = 0.0;
+    if (I.grid_rho) rho = (MODE == VOR_MODE_FP64) ? block_rho(G, R.b) : R.rho;
+    else if (I.density) rho = I.density[R.uid];
     int32_t wj = -1, wuid = 0;
     double wx = 0.0, wy = 0.0, wz = 0.0;
     int2 wrow = make_int2(0, 0);
@@ -682,15 +708,17 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             wx = h.x;
             wy = h.y;
             wz = h.z;
+            if (I.grid_rho) wrho = h.rho;
             double den;
             best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
+            settle(wrho);
         }
     }
     settle(rho);
     double len = best - R.s_c;
     if (len > 0.0) {
         if (EXT) {
-            const double kr = I.density ? I.kappa * rho : 0.0;
+            const double kr = has_rho ? I.kappa * rho : 0.0;
             if (X.tau_stop) {
                 const double tn = R.tau + kr * len;
                 if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
@@ -706,7 +734,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             }
             deposit<DEFER>(X, R, len, kr);
         }
-        if (I.density) R.tau += I.kappa * rho * len;   // before the store: its wait then holds no store
+        if (has_rho) R.tau += I.kappa * rho * len;   // before the store: its wait then holds no store
         if (SEGS) store_segment(O, R, S.cnt, R.uid, len);
         ++S.cnt;
         R.s_c = best;
@@ -734,6 +762,10 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
         settle(R.rw.x);
         settle(R.rw.y);
         R.b = block_of(R.rw, R.m);
+        if (MODE != VOR_MODE_FP64 && I.grid_rho) {
+            R.rho = block_rho(G, R.b);
+            settle(R.rho);
+        }
         return true;
     }
     if (wj < 0) return false;
@@ -744,6 +776,14 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
     R.pm[2] = wz;
     R.rw = wrow;
     R.b = block_of(wrow, wj);
+    if (MODE != VOR_MODE_FP64 && I.grid_rho) {
+        if (redo) {
+            R.rho = block_rho(G, R.b);
+            settle(R.rho);
+        } else {
+            R.rho = wrho;
+        }
+    }
     return true;
 }
 

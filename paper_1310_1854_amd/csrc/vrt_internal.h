@@ -38,7 +38,8 @@ struct __align__(16) BlockHdr {
     int32_t uid;      // user index
     int32_t j;        // internal index
     int32_t len;      // records that follow
-    int32_t pad[3];
+    int32_t pad;
+    double rho;       // the density bound to the grid (vor_grid_bind_density), 0 when none
 };
 static_assert(sizeof(BlockHdr) == 16 * kHdrSlots, "a block header fills kHdrSlots slots");
 
@@ -86,6 +87,7 @@ struct Grid {
     int32_t *loc_start = nullptr;   // [K + 1] list of block k: loc_cells[loc_start[k] .. loc_start[k+1])
     int32_t *loc_cells = nullptr;   // internal cell indices
     int64_t loc_entries = 0;
+    int32_t rho_bound = 0;          // a density is held in the block headers
     double build_ms = 0;
     int64_t device_bytes = 0;
     int device = 0;

@@ -30,7 +30,7 @@ EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_nei
            "vor_server_create", "vor_server_submit", "vor_server_poll", "vor_server_wait", "vor_server_result",
            "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy",
            "vor_server_next_done", "vor_grid_truncate_row", "vor_grid_volumes", "vor_grid_bboxes",
-           "vor_locate_blocks"]
+           "vor_locate_blocks", "vor_grid_bind_density"]
 
 
 class VorError(RuntimeError):
@@ -53,7 +53,8 @@ class GridInfo(ctypes.Structure):
 
 class TraceOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_steps", ctypes.c_int32), ("eps_mix", ctypes.c_double),
-                ("persistent", ctypes.c_int32), ("start_given", ctypes.c_int32), ("enter", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("start_given", ctypes.c_int32), ("enter", ctypes.c_int32),
+                ("grid_density", ctypes.c_int32)]
 
 
 class TraceOut(ctypes.Structure):
@@ -101,6 +102,8 @@ def load(path: str = None):
     lib.vor_grid_get_info.restype = ctypes.c_int
     lib.vor_grid_volumes.argtypes = [P, P, P]
     lib.vor_grid_volumes.restype = ctypes.c_int
+    lib.vor_grid_bind_density.argtypes = [P, P, P]
+    lib.vor_grid_bind_density.restype = ctypes.c_int
     lib.vor_grid_truncate_row.argtypes = [P, I64, I32]
     lib.vor_grid_truncate_row.restype = ctypes.c_int
     lib.vor_grid_neighbors.argtypes = [P, P, P, P]
@@ -212,6 +215,15 @@ class Grid:
         out = torch.empty((self.M, 6), dtype=torch.float64, device="cuda")
         _check(load().vor_grid_bboxes(self.handle, _ptr(out), _stream(stream)), "vor_grid_bboxes")
         return out
+
+    def bind_density(self, density: Optional[torch.Tensor], stream=None) -> None:
+        """vor_grid_bind_density: keep a copy of ``density`` (float64, one value
+        per site, user order) in the grid for traces with grid_density=True;
+        None removes it."""
+        if density is not None and (density.dtype != torch.float64 or not density.is_cuda
+                                    or not density.is_contiguous() or density.numel() != self.M):
+            raise ValueError("density must be a contiguous float64 CUDA tensor with one value per site")
+        _check(load().vor_grid_bind_density(self.handle, _ptr(density), _stream(stream)), "vor_grid_bind_density")
 
     def truncate_row(self, site: int, keep: int) -> None:
         """Diagnostic (vor_grid_truncate_row): drop faces of one cell from the
@@ -364,14 +376,15 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
                eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, start_given: bool = False,
                tau_stop: Optional[torch.Tensor] = None, tally_len: Optional[torch.Tensor] = None,
                tally_abs: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None,
-               enter: bool = False, stream=None) -> None:
+               enter: bool = False, grid_density: bool = False, stream=None) -> None:
     """Enqueue one vor_trace into preallocated buffers (no allocation, no
     sync); with ``ordered`` the rays are first put in coherent order by
     vor_order_rays (buffers made with ordered=True). ``start_given``: the
     buffers' start cells are those of an earlier call on the same rays.
     ``tau_stop`` (float64 [N], buffers made with stops=True): interaction
     points; ``tally_len`` / ``tally_abs`` (float64 [M], accumulated) and
-    ``weight`` (float64 [N]): per-cell tallies."""
+    ``weight`` (float64 [N]): per-cell tallies. ``grid_density``: the
+    densities bound with Grid.bind_density (``density`` must be None)."""
     for name, t, size in (("tau_stop", tau_stop, n_rays(origins)), ("weight", weight, n_rays(origins)),
                           ("tally_len", tally_len, grid.M), ("tally_abs", tally_abs, grid.M)):
         if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != size):
@@ -390,7 +403,7 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
     if start_given and bufs.start_cell is None:
         raise ValueError("start_given needs buffers made with locate_first=True")
     opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 1 if start_given else 0,
-                     1 if enter else 0)
+                     1 if enter else 0, 1 if grid_density else 0)
     out = bufs.struct(use_order=ordered, tau_stop=tau_stop, tally_len=tally_len, tally_abs=tally_abs,
                       weight=weight)
     _check(load().vor_trace(grid.handle, _ptr(origins), _ptr(dirs), n, _ptr(density), float(kappa),
@@ -400,7 +413,8 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
 def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str = "fp64",
           segments: str = "exact", seg_stride: int = 64, spill_chunks: int = 0, max_steps: int = 0,
           eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, locate_first: bool = True,
-          tau_stop=None, weight=None, tallies: bool = False, enter: bool = False, stream=None) -> dict:
+          tau_stop=None, weight=None, tallies: bool = False, enter: bool = False, grid_density: bool = False,
+          stream=None) -> dict:
     """Paths of N rays. ``segments``: "none" (tau only), "stride" (a window
     of ``seg_stride`` slots per ray; longer paths continue in up to
     ``spill_chunks`` chained spill chunks, or report RAY_OVERFLOW), or
@@ -409,8 +423,9 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
     their own (vor_trace_out.start_cell) rather than at each ray's start.
     ``tau_stop``: interaction points (stop_cell, stop_s); ``tallies``: the
     per-cell tallies tally_len and tally_abs (with ``weight``); ``enter``:
-    rays from outside the box start where they enter it. Returns a dict of
-    device tensors."""
+    rays from outside the box start where they enter it; ``grid_density``:
+    the densities bound with Grid.bind_density. Returns a dict of device
+    tensors."""
     o = _dev_f64(origins, 3)
     d = _dev_f64(dirs, 3)
     rho = None if density is None else _dev_f64(density).reshape(-1)
@@ -420,7 +435,8 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
     t_len = torch.zeros(grid.M, dtype=torch.float64, device="cuda") if tallies else None
     t_abs = torch.zeros(grid.M, dtype=torch.float64, device="cuda") if tallies else None
     kw = dict(kappa=kappa, mode=mode, max_steps=max_steps, eps_mix=eps_mix, persistent=persistent, ordered=ordered,
-              stream=stream, tau_stop=ts, weight=wt, tally_len=t_len, tally_abs=t_abs, enter=enter)
+              stream=stream, tau_stop=ts, weight=wt, tally_len=t_len, tally_abs=t_abs, enter=enter,
+              grid_density=grid_density)
     lf = dict(ordered=ordered, locate_first=locate_first, stops=ts is not None)
     if segments == "none":
         b = TraceBuffers(n, **lf)
