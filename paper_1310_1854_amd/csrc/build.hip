@@ -301,7 +301,7 @@ __device__ __forceinline__ int wave_max_int(int v)
 
 __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__restrict__ col,
                                const int32_t *__restrict__ total, const int32_t *__restrict__ start, int64_t M,
-                               int2 *__restrict__ rows, Rec64 *__restrict__ r64, Rec32 *__restrict__ blk,
+                               int2 *__restrict__ rows, Rec64 *__restrict__ r64, Slot *__restrict__ blk,
                                int *__restrict__ max_row)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,6 +322,8 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
         h.pad = 0;
         h.rho = 0.0;
         *reinterpret_cast<BlockHdr *>(blk + bo) = h;
+        float *rec = reinterpret_cast<float *>(blk + bo + kHdrSlots);   // n records of 3 floats
+        int32_t *nb = reinterpret_cast<int32_t *>(rec + 3 * n);          // then n block offsets
         for (int e = 0; e < n; ++e) {
             int32_t j = col[s0 + e];
             const Site sj = sites[j];
@@ -332,12 +334,10 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
             a.j = j;
             a.uid = (int32_t)sj.uid;
             r64[s0 + e] = a;
-            Rec32 r;
-            r.nx = (float)(sj.x - si.x);
-            r.ny = (float)(sj.y - si.y);
-            r.nz = (float)(sj.z - si.z);
-            r.blk = block_of(make_int2(start[j], 0), j);
-            blk[bo + kHdrSlots + e] = r;
+            rec[3 * e] = (float)(sj.x - si.x);
+            rec[3 * e + 1] = (float)(sj.y - si.y);
+            rec[3 * e + 2] = (float)(sj.z - si.z);
+            nb[e] = block_of(make_int2(start[j], 0), j);
         }
     }
     int m = wave_max_int(n);
@@ -582,10 +582,10 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     if (nslots + kRecPad > 0x7fffffffLL) return fail(VOR_ECAPACITY);
     g.rows = dalloc<int2>(M, rc, keep);
     g.rec64 = dalloc<Rec64>(g.nnz + kRecPad, rc, keep);
-    g.blk = dalloc<Rec32>(nslots + kRecPad, rc, keep);
+    g.blk = dalloc<Slot>(nslots + kRecPad, rc, keep);
     if (rc != VOR_OK) return fail(rc);
     if (hipMemsetAsync(g.rec64 + g.nnz, 0, sizeof(Rec64) * kRecPad, st) != hipSuccess ||
-        hipMemsetAsync(g.blk + nslots, 0, sizeof(Rec32) * kRecPad, st) != hipSuccess)
+        hipMemsetAsync(g.blk + nslots, 0, sizeof(Slot) * kRecPad, st) != hipSuccess)
         return fail(VOR_EDEVICE);
     hdr = err + 1;   // longest row
     hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, col, total, start, M, g.rows,
@@ -645,7 +645,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
 
     for (void *p : tmp) (void)hipFree(p);
     g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + sizeof(double)) + (B + 1) * 4 +
-                     (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Rec32);
+                     (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Slot);
     if (want_loc)
         g.device_bytes += (int64_t)M * 6 * (int64_t)sizeof(double) +
                           ((int64_t)g.loc_dims[0] * g.loc_dims[1] * g.loc_dims[2] + 1 + g.loc_entries) * 4;
@@ -711,6 +711,15 @@ extern "C" vor_status vor_grid_truncate_row(vor_grid *G, int64_t site, int32_t k
         hipMemcpy(&rw, g.rows + i, sizeof(rw), hipMemcpyDeviceToHost) != hipSuccess)
         return VOR_EDEVICE;
     if (keep < rw.y) {
+        // the block offsets follow the records: move the first keep of them
+        // to their place after the first keep records
+        float *rec = reinterpret_cast<float *>(g.blk + block_of(rw, i) + kHdrSlots);
+        std::vector<int32_t> nb(keep > 0 ? keep : 1);
+        if (keep > 0 && (hipMemcpy(nb.data(), rec + 3 * rw.y, sizeof(int32_t) * keep, hipMemcpyDeviceToHost) !=
+                             hipSuccess ||
+                         hipMemcpy(rec + 3 * keep, nb.data(), sizeof(int32_t) * keep, hipMemcpyHostToDevice) !=
+                             hipSuccess))
+            return VOR_EDEVICE;
         rw.y = keep;
         BlockHdr *h = reinterpret_cast<BlockHdr *>(g.blk + block_of(rw, i));
         if (hipMemcpy(g.rows + i, &rw, sizeof(rw), hipMemcpyHostToDevice) != hipSuccess ||
@@ -739,7 +748,7 @@ extern "C" vor_status vor_grid_bboxes(const vor_grid *G, double *bbox, void *str
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
-__global__ void k_bind_density(Rec32 *__restrict__ blk, const int2 *__restrict__ rows, const int32_t *__restrict__ perm,
+__global__ void k_bind_density(Slot *__restrict__ blk, const int2 *__restrict__ rows, const int32_t *__restrict__ perm,
                                int64_t M, const double *__restrict__ density)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -21,7 +21,7 @@ struct GridRef {
     const Site *sites;
     const int2 *rows;
     const Rec64 *rec64;
-    const Rec32 *blk;     // cell blocks (BlockHdr + Rec32 records)
+    const Slot *blk;     // cell blocks (header, FP32 records, neighbour block offsets)
     BucketGridView grid;
     double lo[3], hi[3];
     int32_t max_steps;
@@ -141,7 +141,8 @@ __device__ __forceinline__ void diag_count(int i)
 #endif
 constexpr int kBatch64 = VRT_BATCH64;   // FP64 records loaded together per lane
 constexpr int kBatch32 = VRT_BATCH32;   // FP32 records loaded together per lane
-static_assert(kBatch64 - 1 <= kRecPad && kBatch32 - 1 <= kRecPad, "a batch may read past a row end");
+static_assert(kBatch64 - 1 <= kRecPad && 12 * kBatch32 <= 16 * kRecPad, "a batch may read past a row end");
+static_assert(kBatch32 % 4 == 0, "a batch of FP32 records is a whole number of 16-byte loads");
 
 
 // Crossing of one bisector plane in FP64, measured from r0 (Eqs. 1-4):
@@ -197,7 +198,8 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
 // rec64 and best the FP64 crossing); otherwise j1 is the offset of the
 // winner's cell block and the caller computes its FP64 crossing from the
 // site in the block header. Either way the result equals exit_fp64's. The
-// current cell's records are blk[b + kHdrSlots ...], rw its row in rec64.
+// current cell's records (12-byte FP32 offsets, then the neighbours' block
+// offsets) start at blk[b + kHdrSlots], rw is its row in rec64.
 //
 // Each plane is ranked in FP32 from its stored offset n = p_j - p_m
 // (rounded once to FP32), the current point q = r - p_m and k (both
@@ -267,10 +269,9 @@ __device__ __forceinline__ void wall32(double L, double s_c, float e_abs, float 
 // FP32 crossing t of one plane and its error bound err (see exit_mixed);
 // pos: the plane is approached and the bound holds; maybe: it may be
 // approached in FP64 (nearly parallel) when pos is false.
-__device__ __forceinline__ void plane_bound32(const Rec32 &r, const Query32 &Q, float &t, float &err, bool &pos,
-                                              bool &maybe)
+__device__ __forceinline__ void plane_bound32(float nx, float ny, float nz, const Query32 &Q, float &t, float &err,
+                                              bool &pos, bool &maybe)
 {
-    const float nx = r.nx, ny = r.ny, nz = r.nz;
     const float den = fmaf(nx, Q.kx, fmaf(ny, Q.ky, nz * Q.kz));
     const float wx = fmaf(0.5f, nx, -Q.qx), wy = fmaf(0.5f, ny, -Q.qy), wz = fmaf(0.5f, nz, -Q.qz);
     const float num = fmaf(nx, wx, fmaf(ny, wy, nz * wz));
@@ -283,7 +284,7 @@ __device__ __forceinline__ void plane_bound32(const Rec32 &r, const Query32 &Q, 
     err = (n1 * rc) * fmaf(Q.c, fabsf(t), Q.a);
 }
 
-__device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 rw, const Rec32 *__restrict__ blk,
+__device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 rw, const Slot *__restrict__ blk,
                                           int32_t b, const double pm[3], const double r0[3], const double k[3],
                                           double L, double s_c, float eps, float e_abs, double &best, bool &redo,
                                           int32_t &j1)
@@ -293,21 +294,28 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 
     float tw, ew;
     wall32(L, s_c, e_abs, tw, ew);
     float t1 = tw, err1 = ew;           // best estimate and its bound (the wall to begin with)
-    j1 = -1;
+    int w1 = -1;                        // the winner's place in the row
     float lo_a = tw - ew, lo_b = inf;   // the two smallest lower bounds, lo_a <= lo_b
     bool graze = false;                 // a nearly parallel plane was met
-    const int end = b + kHdrSlots + rw.y;
-    for (int e0 = b + kHdrSlots; e0 < end; e0 += kBatch32) {
-        Rec32 r[kBatch32];
+    const int n = rw.y;
+    const float4 *rec = reinterpret_cast<const float4 *>(blk + b + kHdrSlots);   // 8 records = 6 float4
+    for (int e0 = 0; e0 < n; e0 += kBatch32) {
+        float f[3 * kBatch32];
 #pragma unroll
-        for (int v = 0; v < kBatch32; ++v) r[v] = blk[e0 + v];   // past the row end: padding or the next block, masked
-        const int rem = end - e0;
+        for (int u = 0; u < 3 * kBatch32 / 4; ++u) {   // past the row end: the block offsets, padding or the next block, masked
+            const float4 x = rec[3 * e0 / 4 + u];
+            f[4 * u] = x.x;
+            f[4 * u + 1] = x.y;
+            f[4 * u + 2] = x.z;
+            f[4 * u + 3] = x.w;
+        }
+        const int rem = n - e0;
 #pragma unroll
         for (int v = 0; v < kBatch32; ++v) {
             const bool in = v < rem;
             float t, err;
             bool pos, maybe;
-            plane_bound32(r[v], Q, t, err, pos, maybe);
+            plane_bound32(f[3 * v], f[3 * v + 1], f[3 * v + 2], Q, t, err, pos, maybe);
             pos = pos && in;
             graze = graze || (maybe && in && !pos);
             const float lo = pos ? t - err : inf;
@@ -315,7 +323,7 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 
             const bool w = pos && t < t1;
             t1 = w ? t : t1;
             err1 = w ? err : err1;
-            j1 = w ? r[v].blk : j1;
+            w1 = w ? e0 + v : w1;
             lo_b = __builtin_amdgcn_fmed3f(lo_a, lo_b, lo);
             lo_a = fminf(lo_a, lo);
         }
@@ -326,11 +334,18 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 
     const float lo_other = (lo1 == lo_a) ? lo_b : lo_a;
     if (graze || !(t1 + err1 < lo_other)) {
         redo = true;
+        j1 = -1;
         return exit_fp64(rec64, rw, pm, r0, k, L, best);
     }
     redo = false;
-    if (j1 < 0) best = L;
-    return j1 < 0 ? -1 : 0;
+    if (w1 < 0) {
+        j1 = -1;
+        best = L;
+        return -1;
+    }
+    // the winner's block offset, stored after the records
+    j1 = reinterpret_cast<const int32_t *>(reinterpret_cast<const float *>(rec) + 3 * n)[w1];
+    return 0;
 }
 
 struct RayStats {

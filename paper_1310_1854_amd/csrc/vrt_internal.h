@@ -20,18 +20,20 @@ struct __align__(32) Rec64 {
     int32_t uid;  // user index of the neighbour
 };
 
-// FP32 neighbour record of the mixed-precision search: the offset
-// p_j - p_m rounded to FP32 and the offset of the neighbour's cell block.
-struct __align__(16) Rec32 {
-    float nx, ny, nz;
-    int32_t blk;
+// The 16-byte slot of the cell blocks.
+struct __align__(16) Slot {
+    uint32_t w[4];
 };
 
 // Cell blocks of the mixed-precision search, one per cell in internal
-// order, 16-byte slots: a header of kHdrSlots slots, then the cell's row as
-// Rec32 records. What a step needs of the cell it moves into (its FP64
-// site, indices and row) thus lies in the lines of its first records. The
-// block of cell j starts at slot rows[j].x + kHdrSlots * j.
+// order, in 16-byte slots: a header of kHdrSlots slots, then the cell's row
+// of n neighbours as n FP32 records of 12 bytes (the offset p_j - p_m
+// rounded to FP32), then the n block offsets of those neighbours (int32):
+// 48 + 16 n bytes, so the block of cell j starts at slot
+// rows[j].x + kHdrSlots * j. The search reads the records only (8 of them
+// are 6 aligned 16-byte loads) and the block offset of the winner alone.
+// What a step needs of the cell it moves into (its FP64 site, indices, row
+// and bound density) lies in the lines of its first records.
 constexpr int kHdrSlots = 3;
 struct __align__(16) BlockHdr {
     double x, y, z;   // the site
@@ -73,7 +75,7 @@ struct Grid {
     int32_t *inv_perm = nullptr;    // [M] user -> internal
     int2 *rows = nullptr;           // [M] {start, count} into rec64
     Rec64 *rec64 = nullptr;         // [nnz + kRecPad]
-    Rec32 *blk = nullptr;           // [nnz + kHdrSlots M + kRecPad] cell blocks (headers and FP32 records)
+    Slot *blk = nullptr;           // [nnz + kHdrSlots M + kRecPad] cell blocks (headers, FP32 records, block offsets)
     uint8_t *wall_mask = nullptr;   // [M] bit w set if wall -(w+1) is a face
     double *volume = nullptr;       // [M] volume of each clipped cell
     int32_t *bucket_start = nullptr;// [B + 1]
