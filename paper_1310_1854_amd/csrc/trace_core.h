@@ -716,14 +716,17 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             settle(wrow.x);
             settle(wrow.y);
         } else {
-            const BlockHdr h = *reinterpret_cast<const BlockHdr *>(G.blk + j1);
-            wj = h.j;
-            wrow = make_int2(j1 - kHdrSlots * h.j, h.len);
-            wuid = h.uid;
-            wx = h.x;
-            wy = h.y;
-            wz = h.z;
-            if (I.grid_rho) wrho = h.rho;
+            // the header as its three 16-byte slots: {x, y}, {z, rho}, {uid, j, len, pad}
+            const double2 s0 = *reinterpret_cast<const double2 *>(G.blk + j1);
+            const double2 s1 = *reinterpret_cast<const double2 *>(G.blk + j1 + 1);
+            const int4 s2 = *reinterpret_cast<const int4 *>(G.blk + j1 + 2);
+            wx = s0.x;
+            wy = s0.y;
+            wz = s1.x;
+            if (I.grid_rho) wrho = s1.y;
+            wuid = s2.x;
+            wj = s2.y;
+            wrow = make_int2(j1 - kHdrSlots * wj, s2.z);
             double den;
             best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
             settle(wrho);

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #define VRT_HD __host__ __device__
@@ -37,13 +38,16 @@ struct __align__(16) Slot {
 constexpr int kHdrSlots = 3;
 struct __align__(16) BlockHdr {
     double x, y, z;   // the site
+    double rho;       // the density bound to the grid (vor_grid_bind_density), 0 when none
     int32_t uid;      // user index
     int32_t j;        // internal index
     int32_t len;      // records that follow
     int32_t pad;
-    double rho;       // the density bound to the grid (vor_grid_bind_density), 0 when none
 };
 static_assert(sizeof(BlockHdr) == 16 * kHdrSlots, "a block header fills kHdrSlots slots");
+static_assert(offsetof(BlockHdr, z) == 16 && offsetof(BlockHdr, rho) == 24 && offsetof(BlockHdr, uid) == 32 &&
+                  offsetof(BlockHdr, j) == 36 && offsetof(BlockHdr, len) == 40,
+              "the trace reads the header as three 16-byte slots");
 
 __host__ __device__ inline int32_t block_of(int2 row, int32_t j) { return row.x + kHdrSlots * j; }
 
