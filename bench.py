@@ -434,7 +434,9 @@ def serving_precision(args, torch, vrt, workloads):
     N = O.shape[0]
     plain = {}
     for mode, ordered in (("fp64", False), ("mixed", False), ("mixed_ordered", True)):
+        # densities from the array, as the requests pass them to the server
         spec = {"mode": "mixed", "stride": stride, "spill_chunks_per_ray": 0.0, "persistent": True,
+                "grid_density": False,
                 "ordered": ordered}
         bufs = make_buffers(vrt, N, spec, torch, chunks=0)   # 32-slot windows, no spill, as the requests
         mode = "mixed" if ordered else mode
