@@ -86,6 +86,8 @@ def test_argument_errors_before_device_work(lib):
     assert lib.vor_locate(None, fake, 10, cell, None) == vrt.VOR_EINVAL
     assert lib.vor_locate_blocks(None, fake, 10, cell, None) == vrt.VOR_EINVAL
     assert lib.vor_grid_bboxes(None, fake, None) == vrt.VOR_EINVAL
+    assert lib.vor_grid_bind_density(None, fake, None) == vrt.VOR_EINVAL
+    assert lib.vor_grid_bind_density(None, None, None) == vrt.VOR_EINVAL
     o = vrt.TraceOut()
     assert lib.vor_trace(None, fake, fake, 10, None, 1.0, None, ctypes.byref(o), None) == vrt.VOR_EINVAL
     info = vrt.GridInfo()
