@@ -299,10 +299,11 @@ def grid_quality(args, torch, vrt, workloads):
     print(json.dumps(result), flush=True)
 
 
-def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False):
+def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid_density=False):
     """Submit the requests at the given offsets (seconds from the start) to a
     fresh server, reap them in completion order, and return the wall time,
-    crossings, p50/p99 latency and (keep) every request's tau."""
+    crossings, p50/p99 latency and (keep) every request's tau. grid_density:
+    the requests use the densities bound to their grids instead of rhos."""
     import threading
 
     srv = vrt.Server(grids, budget_bytes=budget)
@@ -335,7 +336,8 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False):
         if wait > 0:
             time.sleep(wait)
         with lock:
-            rid = srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=stride)
+            rid = srv.submit(r["grid"], r["o"], r["d"], None if grid_density else rhos[r["grid"]], mode=r["mode"],
+                             seg_stride=stride, grid_density=grid_density)
             index[rid] = i
     if not done.wait(600):
         raise RuntimeError("serving run did not finish within 600 s")
@@ -362,6 +364,10 @@ def serving(args, torch, vrt, workloads):
     grids_w = workloads.serving_grids()
     grids = [vrt.build_grid(w.sites, w.box) for w in grids_w]
     rhos = [torch.as_tensor(w.density, device="cuda") for w in grids_w]
+    bound = args.serving_density == "grid"
+    if bound:
+        for g, r in zip(grids, rhos):
+            g.bind_density(r)   # set-up: the resident grids hold their density fields
     print(f"[bench] serving grids built: {[g.info()['build_ms'] for g in grids]} ms", file=sys.stderr, flush=True)
     n_req = args.requests
     stride = 32
@@ -372,7 +378,7 @@ def serving(args, torch, vrt, workloads):
     total_rays = sum(r["o"].shape[0] for r in reqs)
 
     def run(offsets):
-        return run_server(vrt, grids, rhos, reqs, offsets, stride, budget)
+        return run_server(vrt, grids, rhos, reqs, offsets, stride, budget, grid_density=bound)
 
     run(np.zeros(len(reqs)))   # warm-up
     sat = run(np.zeros(len(reqs)))
@@ -389,7 +395,9 @@ def serving(args, torch, vrt, workloads):
         "vs_baseline": None, "dtype": "f64 / f32+f64 (50/50 classes)", "data": "synthetic",
         "config": {"workload": f"serving: 3 resident grids (1e4, 1e5, 1e6 sites), {len(reqs)} Poisson requests "
                                f"of 256-65536 rays ({total_rays} rays), 50/50 FP64/mixed, 1 GiB output budget, "
-                               f"offered load 0.8 of saturation", "requests": len(reqs), "rays": total_rays},
+                               f"offered load 0.8 of saturation, densities "
+                               + ("bound to the grids" if bound else "passed per request"), "requests": len(reqs),
+                   "rays": total_rays},
         "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"],
         "saturated": sat, "loads": {str(k): v for k, v in loads.items()},
     }
@@ -481,6 +489,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="flared_disc", choices=sorted(WORKLOADS) + ["serving", "serving_precision", "grid_quality"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="serving_precision: output budget (GiB)")
+    ap.add_argument("--serving-density", choices=["grid", "array"], default="grid",
+                    help="serving: densities bound to the resident grids, or passed with every request")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",

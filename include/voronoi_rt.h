@@ -68,6 +68,11 @@ enum {
     VOR_MODE_MIXED = 1  /* FP32 plane tests, FP64 re-decision of close calls and FP64 winner */
 };
 
+/* Or'ed into vor_server_submit's mode: the request's densities are those
+ * bound to its grid by vor_grid_bind_density (its density argument must be
+ * NULL). */
+#define VOR_SERVE_GRID_DENSITY 0x100
+
 typedef struct vor_grid vor_grid;
 
 /* Segments per spill chunk (see vor_trace_out). */
@@ -146,9 +151,12 @@ vor_status vor_grid_bboxes(const vor_grid *grid, double *bbox, void *stream);
 /*
  * vor_grid_bind_density -- keeps an exact copy of a density field (the rho_m
  * of the optical depth, Sect. 2.2: tau = kappa * sum of rho_m l_m over the
- * segments) inside the grid, beside each cell's site, for traces that ask
- * for it with vor_trace_opts.grid_density = 1: a step then reads the density
- * of its cell with the cell's other data instead of from a separate array.
+ * segments) inside the grid, for traces that ask for it with
+ * vor_trace_opts.grid_density = 1 (and server requests with
+ * VOR_SERVE_GRID_DENSITY): beside each cell's site in its block, where a
+ * mixed-mode step reads it with the cell's other data, and in the grid's
+ * internal (spatial) order for FP64 mode, instead of from an array in user
+ * order. The grid holds the room for both copies from its build.
  *   density  device, M doubles, user order; read during the call only. NULL
  *            removes the bound field.
  * Asynchronous on `stream`; allocates nothing. Changes the grid: traces
@@ -365,9 +373,12 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
 
 /* Queue a request: n rays (origins, dirs: device, n x 3) on grid `grid`,
  * density (device, that grid's M sites, user order; may be NULL), mode
- * VOR_MODE_*, seg_stride segment slots per ray (0 = tau only). The inputs
- * are borrowed until the request is done. *req_id receives its handle.
- * VOR_EBUDGET if its outputs could never fit in the budget. */
+ * VOR_MODE_*, optionally or'ed with VOR_SERVE_GRID_DENSITY (then density
+ * must be NULL and the grid must hold a bound density when the request is
+ * submitted; rebinding it before the request is done is not allowed),
+ * seg_stride segment slots per ray (0 = tau only). The inputs are borrowed
+ * until the request is done. *req_id receives its handle. VOR_EINVAL for a
+ * bad argument; VOR_EBUDGET if its outputs could never fit in the budget. */
 vor_status vor_server_submit(vor_server *srv, int32_t grid, const double *origins, const double *dirs, int64_t n,
                              const double *density, double kappa, int32_t mode, int64_t seg_stride,
                              int64_t *req_id);

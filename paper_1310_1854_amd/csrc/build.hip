@@ -441,6 +441,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     g.inv_perm = dalloc<int32_t>(M, rc, keep);
     g.wall_mask = dalloc<uint8_t>(M, rc, keep);
     g.volume = dalloc<double>(M, rc, keep);
+    g.rho_int = dalloc<double>(M, rc, keep);
     g.bucket_sites = dalloc<Site>(M, rc, keep);
     if (want_loc) g.bbox = dalloc<double>((size_t)M * 6, rc, keep);
 
@@ -644,7 +645,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     }
 
     for (void *p : tmp) (void)hipFree(p);
-    g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + sizeof(double)) + (B + 1) * 4 +
+    g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + 2 * sizeof(double)) + (B + 1) * 4 +
                      (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Slot);
     if (want_loc)
         g.device_bytes += (int64_t)M * 6 * (int64_t)sizeof(double) +
@@ -660,7 +661,7 @@ extern "C" void vor_grid_free(vor_grid *G)
     (void)hipDeviceSynchronize();
     Grid &g = G->g;
     void *ptrs[] = {g.sites, g.perm, g.inv_perm, g.rows, g.rec64, g.blk, g.wall_mask, g.volume, g.bucket_start,
-                    g.bucket_sites, g.bbox, g.loc_start, g.loc_cells};
+                    g.bucket_sites, g.bbox, g.loc_start, g.loc_cells, g.rho_int};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete G;
@@ -749,12 +750,13 @@ extern "C" vor_status vor_grid_bboxes(const vor_grid *G, double *bbox, void *str
 }
 
 __global__ void k_bind_density(Slot *__restrict__ blk, const int2 *__restrict__ rows, const int32_t *__restrict__ perm,
-                               int64_t M, const double *__restrict__ density)
+                               int64_t M, const double *__restrict__ density, double *__restrict__ rho_int)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
-    BlockHdr *h = reinterpret_cast<BlockHdr *>(blk + block_of(rows[i], (int32_t)i));
-    h->rho = density ? density[perm[i]] : 0.0;
+    const double r = density ? density[perm[i]] : 0.0;
+    reinterpret_cast<BlockHdr *>(blk + block_of(rows[i], (int32_t)i))->rho = r;
+    rho_int[i] = r;
 }
 
 extern "C" vor_status vor_grid_bind_density(vor_grid *G, const double *density, void *stream)
@@ -763,7 +765,7 @@ extern "C" vor_status vor_grid_bind_density(vor_grid *G, const double *density, 
     Grid &g = G->g;
     const int T = 256;
     hipLaunchKernelGGL(k_bind_density, dim3(blocks_for(g.M, T)), dim3(T), 0, (hipStream_t)stream, g.blk, g.rows,
-                       g.perm, g.M, density);
+                       g.perm, g.M, density, g.rho_int);
     if (hipGetLastError() != hipSuccess) return VOR_EDEVICE;
     g.rho_bound = density ? 1 : 0;
     return VOR_OK;

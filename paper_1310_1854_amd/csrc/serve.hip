@@ -65,7 +65,7 @@ struct ChunkDev {
     int32_t req;    // index into the launch's request table
     int32_t first;  // first ray of the request in this chunk
     int32_t count;  // rays in the chunk (>= 1)
-    int32_t ctx;    // 2 * grid + (mode == mixed)
+    int32_t ctx;    // 4 * grid + 2 * (densities bound to the grid) + (mode == mixed)
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     cur_slot = fs;
                     if (p_ctx != ctx) {
                         ctx = p_ctx;
-                        G = grids[ctx >> 1];
+                        G = grids[ctx >> 2];
                     }
                     have_p = false;
                 }
@@ -188,8 +188,12 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     R.ray = (int32_t)ray;
                     R.base = ray * rq.seg_stride;
                     R.cap = rq.seg_cell ? rq.seg_stride : 0;
-                    if (R.st == RAY_OK) ray_begin(G, R, s0);
-                    else R.L = 0.0;
+                    if (R.st == RAY_OK) {
+                        ray_begin(G, R, s0);
+                        R.rho = (ctx & 3) == 3 ? block_rho(G, R.b) : 0.0;   // mixed mode carries it
+                    } else {
+                        R.L = 0.0;
+                    }
                     live = true;
                 }
                 const uint64_t taken = __ballot(mine);
@@ -205,7 +209,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
         }
         bool fin = false;
         if (live) {
-            const RayIn I{nullptr, nullptr, dens, kappa};
+            const RayIn I{nullptr, nullptr, dens, kappa, 0, (ctx >> 1) & 1};
             SegOut O{};
             O.cell = cellp;
             O.len = lenp;
@@ -314,6 +318,7 @@ size_t request_bytes(int64_t n, int64_t stride)
 
 struct vor_server {
     std::vector<GridRef> grid_refs;
+    std::vector<const vor_grid *> grids;
     GridRef *d_grids = nullptr;
     char *arena = nullptr;
     size_t budget = 0, used = 0;
@@ -451,7 +456,7 @@ struct vor_server {
             d.done = L.d_flags + q;
             L.h_remaining[q] = need;
             L.h_flags[q] = 0;
-            const int32_t ctx = 2 * r.grid + (r.mode == VOR_MODE_MIXED ? 1 : 0);
+            const int32_t ctx = 4 * r.grid + 2 * r.in.grid_rho + (r.mode == VOR_MODE_MIXED ? 1 : 0);
             for (int c = 0; c < need; ++c) {
                 ChunkDev &ch = L.h_chunks[nch++];
                 ch.req = q;
@@ -602,7 +607,10 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
     vor_server *S = new (std::nothrow) vor_server;
     if (!S) return VOR_ENOMEM;
     (void)hipGetDevice(&S->device);
-    for (int i = 0; i < n_grids; ++i) S->grid_refs.push_back(grid_ref(vrt_grid_of(grids[i]), 0, 0.0));
+    for (int i = 0; i < n_grids; ++i) {
+        S->grid_refs.push_back(grid_ref(vrt_grid_of(grids[i]), 0, 0.0));
+        S->grids.push_back(grids[i]);
+    }
     bool ok = hipMalloc(&S->d_grids, sizeof(GridRef) * n_grids) == hipSuccess &&
               hipMemcpy(S->d_grids, S->grid_refs.data(), sizeof(GridRef) * n_grids, hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc(&S->arena, (size_t)budget_bytes) == hipSuccess;
@@ -642,9 +650,12 @@ vor_status vor_server_submit(vor_server *S, int32_t grid, const double *origins,
                              const double *density, double kappa, int32_t mode, int64_t seg_stride, int64_t *req_id)
 {
     if (req_id) *req_id = 0;
+    const bool grid_rho = (mode & VOR_SERVE_GRID_DENSITY) != 0;
+    mode &= ~VOR_SERVE_GRID_DENSITY;
     if (!S || !req_id || grid < 0 || grid >= (int32_t)S->grid_refs.size() || n < 1 || n > 0x7fffffffLL ||
         !origins || !dirs || seg_stride < 0 || (mode != VOR_MODE_FP64 && mode != VOR_MODE_MIXED))
         return VOR_EINVAL;
+    if (grid_rho && (density || !vrt_grid_of(S->grids[grid]).rho_bound)) return VOR_EINVAL;
     size_t bytes = request_bytes(n, seg_stride);
     if (bytes > S->budget) return VOR_EBUDGET;
     std::lock_guard<std::mutex> lk(S->mu);
@@ -659,6 +670,7 @@ vor_status vor_server_submit(vor_server *S, int32_t grid, const double *origins,
     r.in.density = density;
     r.in.kappa = kappa;
     r.in.enter = 0;
+    r.in.grid_rho = grid_rho ? 1 : 0;
     r.seg_stride = seg_stride;
     r.bytes = bytes;
     r.t_submit = clk::now();

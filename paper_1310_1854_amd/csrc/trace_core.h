@@ -22,6 +22,7 @@ struct GridRef {
     const int2 *rows;
     const Rec64 *rec64;
     const Slot *blk;     // cell blocks (header, FP32 records, neighbour block offsets)
+    const double *rho_int;   // the density bound to the grid, internal order
     BucketGridView grid;
     double lo[3], hi[3];
     int32_t max_steps;
@@ -102,6 +103,7 @@ inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
     G.rows = g.rows;
     G.rec64 = g.rec64;
     G.blk = g.blk;
+    G.rho_int = g.rho_int;
     G.grid = bucket_view(g);
     double diag = 0.0, cmax = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -686,15 +688,16 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                                              const SegOut &O, int win, double best, bool redo, int32_t j1,
                                              const Extras &X)
 {
-    // The current cell's density. Bound to the grid: from the block headers
-    // (mixed mode: read with the cell's header when the ray entered it; FP64
-    // mode: from the current block's header). Else from the caller's array,
+    // The current cell's density. Bound to the grid: mixed mode read it with
+    // the cell's block header when the ray entered the cell; FP64 mode, which
+    // does not read the blocks, takes it from the copy in internal order,
+    // whose lines neighbouring cells share. Else from the caller's array,
     // loaded before the winner's header or record so that one wait covers
     // both (loaded after the segment store, its wait would also hold the step
     // until the store completed).
     const bool has_rho = I.grid_rho || I.density;
     double rho = 0.0, wrho = 0.0;
-    if (I.grid_rho) rho = (MODE == VOR_MODE_FP64) ? block_rho(G, R.b) : R.rho;
+    if (I.grid_rho) rho = (MODE == VOR_MODE_FP64) ? G.rho_int[R.m] : R.rho;
     else if (I.density) rho = I.density[R.uid];
     int32_t wj = -1, wuid = 0;
     double wx = 0.0, wy = 0.0, wz = 0.0;

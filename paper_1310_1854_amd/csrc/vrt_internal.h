@@ -93,7 +93,8 @@ struct Grid {
     int32_t *loc_start = nullptr;   // [K + 1] list of block k: loc_cells[loc_start[k] .. loc_start[k+1])
     int32_t *loc_cells = nullptr;   // internal cell indices
     int64_t loc_entries = 0;
-    int32_t rho_bound = 0;          // a density is held in the block headers
+    int32_t rho_bound = 0;          // a density is bound (block headers and rho_int)
+    double *rho_int = nullptr;      // [M] the bound density in internal order (FP64 mode reads it here)
     double build_ms = 0;
     int64_t device_bytes = 0;
     int device = 0;

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libvoronoi_rt.so")
 VOR_OK, VOR_EINVAL, VOR_EDUP, VOR_EOUTSIDE, VOR_ENOMEM, VOR_EDEVICE, VOR_ECAPACITY, VOR_EBUDGET, VOR_ETIMEOUT = range(9)
 RAY_OK, RAY_OUTSIDE, RAY_BADDIR, RAY_STEPLIMIT, RAY_OVERFLOW = range(5)
 MODES = {"fp64": 0, "mixed": 1}
+SERVE_GRID_DENSITY = 0x100   # or'ed into a server request's mode: the grid's bound densities
 
 # every symbol include/voronoi_rt.h declares
 EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_neighbors", "vor_locate",
@@ -514,13 +515,16 @@ class Server:
         self._keep = {}
 
     def submit(self, grid: int, origins: torch.Tensor, dirs: torch.Tensor, density: Optional[torch.Tensor] = None,
-               kappa: float = 1.0, mode: str = "fp64", seg_stride: int = 0) -> int:
+               kappa: float = 1.0, mode: str = "fp64", seg_stride: int = 0, grid_density: bool = False) -> int:
+        """Queue a request; ``grid_density``: use the densities bound to the
+        grid (Grid.bind_density) instead of ``density``, which must be None."""
         if origins.dtype != torch.float64 or dirs.dtype != torch.float64 or not origins.is_contiguous() \
                 or not dirs.is_contiguous() or origins.shape != dirs.shape:
             raise ValueError("origins/dirs must be contiguous float64 (N, 3) device tensors")
         rid = ctypes.c_int64()
+        m = MODES[mode] | (SERVE_GRID_DENSITY if grid_density else 0)
         _check(load().vor_server_submit(self._h, int(grid), _ptr(origins), _ptr(dirs), origins.shape[0],
-                                        _ptr(density), float(kappa), MODES[mode], int(seg_stride),
+                                        _ptr(density), float(kappa), m, int(seg_stride),
                                         ctypes.byref(rid)), "vor_server_submit")
         self._keep[rid.value] = (origins, dirs, density, int(seg_stride), origins.shape[0])
         return rid.value

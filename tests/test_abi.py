@@ -38,6 +38,7 @@ def test_binding_constants_match_the_header():
     defs = dict(re.findall(r"#define (VOR_\w+) (\d+)", text))
     assert int(defs["VOR_SPILL_CHUNK"]) == vrt.SPILL_CHUNK
     assert int(defs["VOR_WORK_WORDS"]) == vrt.WORK_WORDS
+    assert int(re.search(r"#define VOR_SERVE_GRID_DENSITY (0x[0-9a-fA-F]+)", text).group(1), 16) == vrt.SERVE_GRID_DENSITY
     import torch
     assert vrt.TraceBuffers(10, device="cpu").work.numel() == vrt.WORK_WORDS
 

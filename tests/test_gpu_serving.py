@@ -273,3 +273,46 @@ def test_serving_on_grids_with_block_lists(env):
             assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
             assert torch.equal(ref["status"], a["status"])
 
+
+
+def test_serving_with_densities_bound_to_the_grids(env):
+    """Requests that use the densities bound to their grid
+    (VOR_SERVE_GRID_DENSITY), mixed in one server with requests that pass the
+    same field as an array: every result is the same bit for bit, and equals
+    vor_trace. A request asking for a bound field on a grid without one, or
+    passing an array as well, is refused at submission."""
+    vrt, torch, ws, _, rhos = env
+    bgrids = [vrt.build_grid(w.sites, w.box) for w in ws]
+    for g, r in zip(bgrids[:2], rhos[:2]):
+        g.bind_density(r)                      # the third grid holds none
+    reqs = [r for r in _requests(ws, 30, seed=17) if r["grid"] < 2][:16]
+    srv = vrt.Server(bgrids, budget_bytes=1 << 30)
+    try:
+        ids = []
+        for r in reqs:
+            ids.append((srv.submit(r["grid"], r["o"], r["d"], None, mode=r["mode"], seg_stride=32,
+                                   grid_density=True),
+                        srv.submit(r["grid"], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], seg_stride=32)))
+        w = ws[2]
+        o = torch.as_tensor(w.sites[:64], device="cuda").contiguous()
+        with pytest.raises(vrt.VorError):
+            srv.submit(2, o, o, None, mode="mixed", grid_density=True)           # nothing bound
+        with pytest.raises(vrt.VorError):
+            srv.submit(0, o, o, rhos[0], mode="mixed", grid_density=True)        # both
+        res = []
+        for a, b in ids:
+            srv.wait(a, 120)
+            srv.wait(b, 120)
+            res.append((srv.result(a), srv.result(b)))
+        torch.cuda.synchronize()
+        for a, b in ids:
+            srv.release(a)
+            srv.release(b)
+    finally:
+        srv.close()
+    assert any(float(a["tau"].max()) > 0 for a, _ in res)
+    for r, (a, b) in zip(reqs, res):
+        assert _same(a, b)
+        ref = vrt.trace(bgrids[r["grid"]], r["o"], r["d"], None, mode=r["mode"], segments="stride", seg_stride=32,
+                        grid_density=True)
+        assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
