@@ -1,7 +1,8 @@
 """Register budgets of the traversal kernels, checked at compile time (no
 GPU): the persistent kernels without the optional features must keep the
 occupancy they are tuned for (mixed: 3 waves per SIMD, <= 168 VGPRs; FP64:
-4 waves, <= 128), since a few extra registers halve the rays in flight."""
+4 waves, <= 128; the transport kernels of both modes: 3 waves), since a few
+extra registers cut the rays in flight by a third or a half."""
 import os
 import re
 import shutil
@@ -16,6 +17,8 @@ pytestmark = pytest.mark.skipif(shutil.which("hipcc") is None, reason="needs hip
 WANT = {
     "_ZN12_GLOBAL__N_118k_trace_persistentILi1ELb1ELb0EEEvNS_9TraceArgsE": 3,   # mixed, segments
     "_ZN12_GLOBAL__N_118k_trace_persistentILi0ELb1ELb0EEEvNS_9TraceArgsE": 4,   # FP64, segments
+    "_ZN12_GLOBAL__N_118k_trace_persistentILi1ELb1ELb1EEEvNS_9TraceArgsE": 3,   # mixed, transport
+    "_ZN12_GLOBAL__N_118k_trace_persistentILi0ELb1ELb1EEEvNS_9TraceArgsE": 3,   # FP64, transport
 }
 
 
