@@ -1,8 +1,8 @@
 """Register budgets of the traversal kernels, checked at compile time (no
-GPU): the persistent kernels without the optional features must keep the
-occupancy they are tuned for (mixed: 3 waves per SIMD, <= 168 VGPRs; FP64:
-4 waves, <= 128; the transport kernels of both modes: 3 waves), since a few
-extra registers cut the rays in flight by a third or a half."""
+GPU): the persistent kernels must keep the occupancy they are tuned for
+(mixed: 3 waves per SIMD, <= 168 VGPRs; FP64: 4 waves, <= 128; the transport
+kernels of both modes: 3 waves), since a few extra registers cut the rays in
+flight by a third or a half."""
 import os
 import re
 import shutil
