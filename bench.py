@@ -215,6 +215,18 @@ def run_steps(vrt, torch, grid, o, d, rho, bufs, spec, mode, n, timed, reuse_ord
     return [a.elapsed_time(b) for a, b in times]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, spec, oracle):
     """The oracle (FP64 brute force over all sites) on a bounded sample of
     the same rays, with all host threads."""
@@ -226,7 +238,8 @@ def cpu_baseline(w, spec, oracle):
     dt = time.perf_counter() - t0
     crossings = int(ref["nseg"].sum())
     return sub, ref, dict(value=crossings / dt, unit="crossings/s", cores=threads, kind="oracle",
-                          sample=f"{n} of the {w.N} rays (seeded subsample), {crossings} crossings in {dt:.1f} s")
+                          sample=f"{n} of the {w.N} rays (seeded subsample), {crossings} crossings in {dt:.1f} s",
+                          host_cpus=os.cpu_count(), cpu_model=cpu_model())
 
 
 def grid_quality(args, torch, vrt, workloads):
@@ -611,6 +624,8 @@ def main(argv=None):
         "rays_past_window_per_step": spilled,
         "records_per_step": recs_per_step,
         "fp64_redecision_rate": c[2] / max(c[3], 1),
+        "fallback_rate": c[1] / max(c[0], 1),
+        "eps_mix": 2.0 ** -20,
         "fp64_value": fp64_value,
         "fp64_ms_per_step": f_wall * 1e3,
         "mixed_vs_fp64": {"tau_bit_identical": same_tau, "n_seg_identical": same_nseg},
