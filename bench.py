@@ -497,7 +497,7 @@ def serving_precision(args, torch, vrt, workloads):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)   # p50/p99 over at least 20 calls
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="flared_disc", choices=sorted(WORKLOADS) + ["serving", "serving_precision", "grid_quality"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")

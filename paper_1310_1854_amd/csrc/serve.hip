@@ -191,6 +191,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     if (R.st == RAY_OK) {
                         ray_begin(G, R, s0);
                         R.rho = (ctx & 3) == 3 ? block_rho(G, R.b) : 0.0;   // mixed mode carries it
+                        settle(R.rho);
                     } else {
                         R.L = 0.0;
                     }
