@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
     double kappa = 0.0;
     int32_t *cellp = nullptr;
     double *lenp = nullptr;
-    int vec4 = 0;
+    int vec = 0;
     RayState R;
     RayStats S, T;
     for (;;) {
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     kappa = rq.in.kappa;
                     cellp = rq.seg_cell;
                     lenp = rq.seg_len;
-                    vec4 = (rq.seg_cell && rq.seg_stride % 4 == 0) ? 1 : 0;
+                    vec = (rq.seg_cell && rq.seg_stride % 8 == 0) ? 1 : 0;
                     S = RayStats();
                     double s0;
                     R.st = ray_setup<false>(G, rq.in, ray, R.r0, R.k, R.L, s0);
@@ -214,11 +214,12 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
             SegOut O{};
             O.cell = cellp;
             O.len = lenp;
-            O.vec4 = vec4;
+            O.vec = vec;
             const bool more = (ctx & 1) ? ray_step<VOR_MODE_MIXED, true>(G, I, R, S, O)
                                         : ray_step<VOR_MODE_FP64, true>(G, I, R, S, O);
             if (!more) {
-                finish_segments(O, R, S.cnt);
+                if (ctx & 1) finish_segments<cells_per_store<VOR_MODE_MIXED, false>()>(O, R, S.cnt);
+                else finish_segments<cells_per_store<VOR_MODE_FP64, false>()>(O, R, S.cnt);
                 if (R.cap > 0 && R.st == RAY_OK && S.cnt > R.cap) R.st = RAY_OVERFLOW;
                 const ReqDev &rq = reqs[q];
                 rq.tau[ray] = R.tau;

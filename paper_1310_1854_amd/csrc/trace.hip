@@ -172,11 +172,11 @@ __device__ __forceinline__ void ray_window(const TraceArgs &A, int64_t ray, RayS
 }
 
 // Results of a finished ray.
-template <bool SEGS, bool EXT>
+template <bool SEGS, bool EXT, int MODE>
 __device__ __forceinline__ void ray_finish(const TraceArgs &A, int64_t ray, RayState &R, const RayStats &S)
 {
     if (EXT) ray_extras_finish(A.X, ray, R);
-    if (SEGS) finish_segments(A.O, R, S.cnt);
+    if (SEGS) finish_segments<cells_per_store<MODE, EXT>()>(A.O, R, S.cnt);
     if (SEGS && S.cnt > R.cap) {
         if (A.work) atomicAdd((unsigned long long *)&A.work[2], 1ull);
         if (R.st == RAY_OK && (!A.O.spill_cell || R.chunk == -2)) R.st = RAY_OVERFLOW;
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace(TraceArgs A)
         ray_start<EXT, MODE>(A, ray, R);
         while (ray_step<MODE, SEGS, EXT>(A.G, A.I, R, S, A.O, A.X)) {
         }
-        ray_finish<SEGS, EXT>(A, ray, R, S);
+        ray_finish<SEGS, EXT, MODE>(A, ray, R, S);
     }
     flush_counters(A, S);
 }
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
             ++wref;
 #if VRT_DEFER_FINISH
             if (pending) {   // the ended rays of the wave write their results together
-                ray_finish<SEGS, EXT>(A, ray, R, S);
+                ray_finish<SEGS, EXT, MODE>(A, ray, R, S);
                 pending = false;
             }
 #endif
@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
 #if VRT_DEFER_FINISH
                 pending = true;
 #else
-                ray_finish<SEGS, EXT>(A, ray, R, S);
+                ray_finish<SEGS, EXT, MODE>(A, ray, R, S);
 #endif
                 T.cnt += S.cnt;
                 T.nfb += S.nfb;
@@ -438,7 +438,7 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
         }
     }
 #if VRT_DEFER_FINISH
-    if (pending) ray_finish<SEGS, EXT>(A, ray, R, S);
+    if (pending) ray_finish<SEGS, EXT, MODE>(A, ray, R, S);
 #endif
     flush_counters(A, T);
     if (A.counters && (threadIdx.x & 63) == 0) {
@@ -625,7 +625,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     A.work = out->work;
     A.O.cell = out->seg_cell;
     A.O.len = out->seg_len;
-    A.O.vec4 = (out->seg_stride > 0 && out->seg_stride % 4 == 0) ? 1 : 0;
+    A.O.vec = (out->seg_stride > 0 && out->seg_stride % 8 == 0) ? 1 : 0;
     A.O.spill_cell = spill ? out->spill_cell : nullptr;
     A.O.spill_len = out->spill_len;
     A.O.spill_next = out->spill_next;

@@ -55,7 +55,7 @@ constexpr int kSpillChunk = VOR_SPILL_CHUNK;
 struct SegOut {
     int32_t *cell;                  // window slots
     double *len;
-    int vec4;                       // windows start on multiples of 4 slots: store 4 segments at a time
+    int vec;                        // windows start on multiples of 8 slots: cells stored 8, lengths 4 at a time
     int32_t *spill_cell;            // chunk c holds slots [c * kSpillChunk, (c + 1) * kSpillChunk)
     double *spill_len;
     int32_t *spill_next;            // next chunk of the same path, -1 at the end
@@ -424,8 +424,8 @@ struct RayState {
     int32_t chunk;        // current spill chunk, -1 none yet, -2 spill exhausted
     int32_t ray;
 #if VRT_VEC_STORE
-    int32_t c0, c1, c2, c3;   // the last four segments, oldest first, written 4 at a time
-    double l0, l1, l2, l3;
+    int32_t c0, c1, c2, c3, c4, c5, c6, c7;   // the last cells, oldest first, written 8 at a time (32 B)
+    double l0, l1, l2, l3;                    // the last lengths, written 4 at a time (32 B)
 #endif
     int32_t m, uid;
     int32_t b;            // offset of the current cell's block
@@ -525,6 +525,16 @@ __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState 
 // Store segment number idx of the ray: in its window, else in its spill
 // chain. A new chunk is taken when a path reaches the first slot of one;
 // lanes that do so in the same step share one atomic.
+// Cells written together per lane: 8 (one 32-byte unit) where the
+// registers allow it, in the mixed-mode kernels without the optional
+// features; 4 in the others, whose occupancy the 4 more registers would cut.
+template <int MODE, bool EXT>
+constexpr int cells_per_store()
+{
+    return (MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
+}
+
+template <int CG>
 __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int64_t idx, int32_t cell, double len)
 {
     if (idx >= R.cap && O.spill_cell) {
@@ -552,31 +562,53 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
         }
     }
 #if VRT_VEC_STORE
-    if (O.vec4) {
+    if (O.vec) {
+        // The lengths go out 4 at a time (32 B); the cells CG at a time, 32 B
+        // with CG = 8 (a 16-byte write is half of the memory's write unit,
+        // which costs the unit's read as well once the line leaves the L2
+        // before its other half is written).
         R.c0 = R.c1;
         R.c1 = R.c2;
         R.c2 = R.c3;
-        R.c3 = cell;
+        if (CG == 8) {
+            R.c3 = R.c4;
+            R.c4 = R.c5;
+            R.c5 = R.c6;
+            R.c6 = R.c7;
+            R.c7 = cell;
+        } else {
+            R.c3 = cell;
+        }
         R.l0 = R.l1;
         R.l1 = R.l2;
         R.l2 = R.l3;
         R.l3 = len;
         if ((idx & 3) == 3) {
             bool spill;
-            const int64_t p = segment_slot(O, R, idx - 3, spill);
+            const int64_t p = segment_slot(O, R, idx - 3, spill);   // groups of 8 never cross a window or chunk end
             if (p >= 0) {
                 int32_t *cp = spill ? O.spill_cell : O.cell;
                 double *lp = spill ? O.spill_len : O.len;
 #if VRT_NT_STORE   // streaming: the segments are not read again here; the stores leave the L2 to the records
                 typedef int v4i __attribute__((ext_vector_type(4)));
                 typedef double v2d __attribute__((ext_vector_type(2)));
-                __builtin_nontemporal_store(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp + p));
                 __builtin_nontemporal_store(v2d{R.l0, R.l1}, reinterpret_cast<v2d *>(lp + p));
                 __builtin_nontemporal_store(v2d{R.l2, R.l3}, reinterpret_cast<v2d *>(lp + p + 2));
+                if (CG == 4) {
+                    __builtin_nontemporal_store(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp + p));
+                } else if ((idx & 7) == 7) {
+                    __builtin_nontemporal_store(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp + p - 4));
+                    __builtin_nontemporal_store(v4i{R.c4, R.c5, R.c6, R.c7}, reinterpret_cast<v4i *>(cp + p));
+                }
 #else
-                *reinterpret_cast<int4 *>(cp + p) = make_int4(R.c0, R.c1, R.c2, R.c3);
                 *reinterpret_cast<double2 *>(lp + p) = make_double2(R.l0, R.l1);
                 *reinterpret_cast<double2 *>(lp + p + 2) = make_double2(R.l2, R.l3);
+                if (CG == 4) {
+                    *reinterpret_cast<int4 *>(cp + p) = make_int4(R.c0, R.c1, R.c2, R.c3);
+                } else if ((idx & 7) == 7) {
+                    *reinterpret_cast<int4 *>(cp + p - 4) = make_int4(R.c0, R.c1, R.c2, R.c3);
+                    *reinterpret_cast<int4 *>(cp + p) = make_int4(R.c4, R.c5, R.c6, R.c7);
+                }
 #endif
             }
         }
@@ -592,22 +624,24 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
 }
 
 // Write the segments still held back when a path of n segments ends.
+template <int CG>
 __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState &R, int64_t n)
 {
 #if VRT_VEC_STORE
-    if (!O.vec4) return;
-    const int rest = (int)(n & 3);
-    if (rest == 0) return;
-    const int32_t cs[4] = {R.c0, R.c1, R.c2, R.c3};
+    if (!O.vec) return;
+    const int rc = (int)(n & (CG - 1)), rl = (int)(n & 3);   // cells and lengths not yet written
+    if (rc == 0) return;
+    const int32_t cs[8] = {CG == 8 ? R.c0 : 0, CG == 8 ? R.c1 : 0, CG == 8 ? R.c2 : 0, CG == 8 ? R.c3 : 0,
+                           CG == 8 ? R.c4 : R.c0, CG == 8 ? R.c5 : R.c1, CG == 8 ? R.c6 : R.c2, CG == 8 ? R.c7 : R.c3};
     const double ls[4] = {R.l0, R.l1, R.l2, R.l3};
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        if (j < rest) {
+    for (int j = 0; j < 7; ++j) {
+        if (j < rc) {
             bool spill;
-            const int64_t p = segment_slot(O, R, n - rest + j, spill);
+            const int64_t p = segment_slot(O, R, n - rc + j, spill);
             if (p >= 0) {
-                (spill ? O.spill_cell : O.cell)[p] = cs[4 - rest + j];
-                (spill ? O.spill_len : O.len)[p] = ls[4 - rest + j];
+                (spill ? O.spill_cell : O.cell)[p] = cs[8 - rc + j];
+                if (j >= rc - rl) (spill ? O.spill_len : O.len)[p] = ls[4 - rc + j];
             }
         }
     }
@@ -744,7 +778,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                 const double tn = R.tau + kr * len;
                 if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
                     const double lp = (R.tstop - R.tau) / kr;
-                    if (SEGS) store_segment(O, R, S.cnt, R.uid, lp);
+                    if (SEGS) store_segment<cells_per_store<MODE, EXT>()>(O, R, S.cnt, R.uid, lp);
                     deposit<DEFER>(X, R, lp, kr);
                     R.tau = R.tau + kr * lp;
                     ++S.cnt;
@@ -756,7 +790,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             deposit<DEFER>(X, R, len, kr);
         }
         if (has_rho) R.tau += I.kappa * rho * len;   // before the store: its wait then holds no store
-        if (SEGS) store_segment(O, R, S.cnt, R.uid, len);
+        if (SEGS) store_segment<cells_per_store<MODE, EXT>()>(O, R, S.cnt, R.uid, len);
         ++S.cnt;
         R.s_c = best;
     } else if (len < -1e-9 * R.L) {

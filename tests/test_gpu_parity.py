@@ -735,3 +735,32 @@ def test_ragged_sizes_and_site_permutation(vrt):
     assert np.array_equal(p2["seg_len"], ref["seg_len"])
     assert np.array_equal(p2["seg_cell"], inv[ref["seg_cell"]])
     assert np.array_equal(p2["tau"], ref["tau"])
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_every_store_path_gives_the_exact_paths(vrt, cube, mode):
+    """Segment windows of every kind hold the same paths as the exact CSR
+    output: strides that are multiples of 8 (cells stored 8 at a time where
+    the kernel does so, lengths 4 at a time, the rest written when the path
+    ends), a multiple of 4 only and an odd one (one segment at a time), each
+    with paths longer than the window continuing in their spill chain."""
+    w, grid, _ = cube
+    n = 3000
+    o, d = w.origins[:n], w.dirs[:n]
+    ex = vrt.trace(grid, o, d, w.density, mode=mode, segments="exact", persistent=True, ordered=True)
+    ns = ex["n_seg"].cpu().numpy()
+    off = ex["ray_off"].cpu().numpy()
+    cells = ex["seg_cell"].cpu().numpy()
+    lens = ex["seg_len"].cpu().numpy()
+    assert len(set((ns % 8).tolist())) == 8          # every count of cells left over at the end
+    for stride in (8, 12, 16, 24, 7):
+        out = vrt.trace(grid, o, d, w.density, mode=mode, segments="stride", seg_stride=stride,
+                        spill_chunks=20000, persistent=True, ordered=True)
+        import torch
+        assert torch.equal(out["tau"], ex["tau"]) and torch.equal(out["n_seg"], ex["n_seg"])
+        assert int(out["work"][2].item()) == int((ns > stride).sum()) > 0
+        host = {}
+        for r in range(n):
+            c, l = vrt.ray_path(out, r, host)
+            assert np.array_equal(c, cells[off[r]:off[r + 1]]), (stride, r)
+            assert np.array_equal(l, lens[off[r]:off[r + 1]]), (stride, r)
