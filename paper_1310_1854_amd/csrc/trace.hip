@@ -176,7 +176,7 @@ template <bool SEGS, bool EXT, int MODE>
 __device__ __forceinline__ void ray_finish(const TraceArgs &A, int64_t ray, RayState &R, const RayStats &S)
 {
     if (EXT) ray_extras_finish(A.X, ray, R);
-    if (SEGS) finish_segments<cells_per_store<MODE, EXT>()>(A.O, R, S.cnt);
+    if (SEGS) finish_segments<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT>()>(A.O, R, S.cnt);
     if (SEGS && S.cnt > R.cap) {
         if (A.work) atomicAdd((unsigned long long *)&A.work[2], 1ull);
         if (R.st == RAY_OK && (!A.O.spill_cell || R.chunk == -2)) R.st = RAY_OVERFLOW;

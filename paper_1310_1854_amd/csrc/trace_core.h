@@ -425,7 +425,7 @@ struct RayState {
     int32_t ray;
 #if VRT_VEC_STORE
     int32_t c0, c1, c2, c3, c4, c5, c6, c7;   // the last cells, oldest first, written 8 at a time (32 B)
-    double l0, l1, l2, l3;                    // the last lengths, written 4 at a time (32 B)
+    double l0, l1, l2, l3, l4, l5, l6, l7;    // the last lengths, written LG at a time
 #endif
     int32_t m, uid;
     int32_t b;            // offset of the current cell's block
@@ -525,16 +525,22 @@ __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState 
 // Store segment number idx of the ray: in its window, else in its spill
 // chain. A new chunk is taken when a path reaches the first slot of one;
 // lanes that do so in the same step share one atomic.
-// Cells written together per lane: 8 (one 32-byte unit) where the
-// registers allow it, in the mixed-mode kernels without the optional
-// features; 4 in the others, whose occupancy the 4 more registers would cut.
+// Segments written together per lane: in the mixed-mode kernels without
+// the optional features, 8 cells (32 B) and 8 lengths (64 B) where the
+// registers allow it; in the others 4 of each (16 B and 32 B), since 12 more
+// registers would cut their occupancy.
 template <int MODE, bool EXT>
 constexpr int cells_per_store()
 {
     return (MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
 }
+template <int MODE, bool EXT>
+constexpr int lens_per_store()
+{
+    return (MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
+}
 
-template <int CG>
+template <int CG, int LG>
 __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int64_t idx, int32_t cell, double len)
 {
     if (idx >= R.cap && O.spill_cell) {
@@ -563,10 +569,10 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
     }
 #if VRT_VEC_STORE
     if (O.vec) {
-        // The lengths go out 4 at a time (32 B); the cells CG at a time, 32 B
-        // with CG = 8 (a 16-byte write is half of the memory's write unit,
-        // which costs the unit's read as well once the line leaves the L2
-        // before its other half is written).
+        // The cells go out CG and the lengths LG at a time: 32 and 64 B with
+        // CG = LG = 8 (a partial write of the memory's write unit costs the
+        // unit's read as well once the line leaves the L2 before the rest of
+        // it is written).
         R.c0 = R.c1;
         R.c1 = R.c2;
         R.c2 = R.c3;
@@ -582,8 +588,32 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
         R.l0 = R.l1;
         R.l1 = R.l2;
         R.l2 = R.l3;
-        R.l3 = len;
-        if ((idx & 3) == 3) {
+        if (LG == 8) {
+            R.l3 = R.l4;
+            R.l4 = R.l5;
+            R.l5 = R.l6;
+            R.l6 = R.l7;
+            R.l7 = len;
+        } else {
+            R.l3 = len;
+        }
+        if (LG == 8 && (idx & 7) == 7) {
+            bool spill;
+            const int64_t p = segment_slot(O, R, idx - 7, spill);
+            if (p >= 0) {
+                int32_t *cp = spill ? O.spill_cell : O.cell;
+                double *lp = spill ? O.spill_len : O.len;
+                typedef int v4i __attribute__((ext_vector_type(4)));
+                typedef double v2d __attribute__((ext_vector_type(2)));
+                __builtin_nontemporal_store(v2d{R.l0, R.l1}, reinterpret_cast<v2d *>(lp + p));
+                __builtin_nontemporal_store(v2d{R.l2, R.l3}, reinterpret_cast<v2d *>(lp + p + 2));
+                __builtin_nontemporal_store(v2d{R.l4, R.l5}, reinterpret_cast<v2d *>(lp + p + 4));
+                __builtin_nontemporal_store(v2d{R.l6, R.l7}, reinterpret_cast<v2d *>(lp + p + 6));
+                __builtin_nontemporal_store(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp + p));
+                __builtin_nontemporal_store(v4i{R.c4, R.c5, R.c6, R.c7}, reinterpret_cast<v4i *>(cp + p + 4));
+            }
+        }
+        if (LG == 4 && (idx & 3) == 3) {
             bool spill;
             const int64_t p = segment_slot(O, R, idx - 3, spill);   // groups of 8 never cross a window or chunk end
             if (p >= 0) {
@@ -624,16 +654,17 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
 }
 
 // Write the segments still held back when a path of n segments ends.
-template <int CG>
+template <int CG, int LG>
 __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState &R, int64_t n)
 {
 #if VRT_VEC_STORE
     if (!O.vec) return;
-    const int rc = (int)(n & (CG - 1)), rl = (int)(n & 3);   // cells and lengths not yet written
+    const int rc = (int)(n & (CG - 1)), rl = (int)(n & (LG - 1));   // cells and lengths not yet written
     if (rc == 0) return;
     const int32_t cs[8] = {CG == 8 ? R.c0 : 0, CG == 8 ? R.c1 : 0, CG == 8 ? R.c2 : 0, CG == 8 ? R.c3 : 0,
                            CG == 8 ? R.c4 : R.c0, CG == 8 ? R.c5 : R.c1, CG == 8 ? R.c6 : R.c2, CG == 8 ? R.c7 : R.c3};
-    const double ls[4] = {R.l0, R.l1, R.l2, R.l3};
+    const double ls[8] = {LG == 8 ? R.l0 : 0.0, LG == 8 ? R.l1 : 0.0, LG == 8 ? R.l2 : 0.0, LG == 8 ? R.l3 : 0.0,
+                          LG == 8 ? R.l4 : R.l0, LG == 8 ? R.l5 : R.l1, LG == 8 ? R.l6 : R.l2, LG == 8 ? R.l7 : R.l3};
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
         if (j < rc) {
@@ -641,7 +672,7 @@ __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState 
             const int64_t p = segment_slot(O, R, n - rc + j, spill);
             if (p >= 0) {
                 (spill ? O.spill_cell : O.cell)[p] = cs[8 - rc + j];
-                if (j >= rc - rl) (spill ? O.spill_len : O.len)[p] = ls[4 - rc + j];
+                if (j >= rc - rl) (spill ? O.spill_len : O.len)[p] = ls[8 - rc + j];
             }
         }
     }
@@ -778,7 +809,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                 const double tn = R.tau + kr * len;
                 if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
                     const double lp = (R.tstop - R.tau) / kr;
-                    if (SEGS) store_segment<cells_per_store<MODE, EXT>()>(O, R, S.cnt, R.uid, lp);
+                    if (SEGS) store_segment<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT>()>(O, R, S.cnt, R.uid, lp);
                     deposit<DEFER>(X, R, lp, kr);
                     R.tau = R.tau + kr * lp;
                     ++S.cnt;
@@ -790,7 +821,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             deposit<DEFER>(X, R, len, kr);
         }
         if (has_rho) R.tau += I.kappa * rho * len;   // before the store: its wait then holds no store
-        if (SEGS) store_segment<cells_per_store<MODE, EXT>()>(O, R, S.cnt, R.uid, len);
+        if (SEGS) store_segment<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT>()>(O, R, S.cnt, R.uid, len);
         ++S.cnt;
         R.s_c = best;
     } else if (len < -1e-9 * R.L) {
