@@ -215,10 +215,11 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
             O.cell = cellp;
             O.len = lenp;
             O.vec = vec;
-            const bool more = (ctx & 1) ? ray_step<VOR_MODE_MIXED, true>(G, I, R, S, O)
+            const bool more = (ctx & 1) ? ray_step<VOR_MODE_MIXED, true, false, false, false>(G, I, R, S, O)
                                         : ray_step<VOR_MODE_FP64, true>(G, I, R, S, O);
             if (!more) {
-                if (ctx & 1) finish_segments<cells_per_store<VOR_MODE_MIXED, false>(), lens_per_store<VOR_MODE_MIXED, false>()>(O, R, S.cnt);
+                if (ctx & 1) finish_segments<cells_per_store<VOR_MODE_MIXED, false>(), lens_per_store<VOR_MODE_MIXED, false, false>()>(
+                    O, R, S.cnt);
                 else finish_segments<cells_per_store<VOR_MODE_FP64, false>(), lens_per_store<VOR_MODE_FP64, false>()>(O, R, S.cnt);
                 if (R.cap > 0 && R.st == RAY_OK && S.cnt > R.cap) R.st = RAY_OVERFLOW;
                 const ReqDev &rq = reqs[q];

@@ -528,16 +528,17 @@ __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState 
 // Segments written together per lane: in the mixed-mode kernels without
 // the optional features, 8 cells (32 B) and 8 lengths (64 B) where the
 // registers allow it; in the others 4 of each (16 B and 32 B), since 12 more
-// registers would cut their occupancy.
+// registers would cut their occupancy. WIDE = false keeps 4 lengths (for the
+// serving kernel, which holds both the mixed and the FP64 step).
 template <int MODE, bool EXT>
 constexpr int cells_per_store()
 {
     return (MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
 }
-template <int MODE, bool EXT>
+template <int MODE, bool EXT, bool WIDE = true>
 constexpr int lens_per_store()
 {
-    return (MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
+    return (WIDE && MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
 }
 
 template <int CG, int LG>
@@ -748,7 +749,7 @@ __device__ __forceinline__ void ray_extras_finish(const Extras &X, int64_t ray, 
     if (X.stop_s) X.stop_s[ray] = R.stop_uid >= 0 ? R.stop_s : R.L;
 }
 
-template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false>
+template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false, bool WIDE = true>
 __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, RayState &R, RayStats &S,
                                              const SegOut &O, int win, double best, bool redo, int32_t j1,
                                              const Extras &X)
@@ -809,7 +810,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                 const double tn = R.tau + kr * len;
                 if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
                     const double lp = (R.tstop - R.tau) / kr;
-                    if (SEGS) store_segment<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT>()>(O, R, S.cnt, R.uid, lp);
+                    if (SEGS) store_segment<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT, WIDE>()>(O, R, S.cnt, R.uid, lp);
                     deposit<DEFER>(X, R, lp, kr);
                     R.tau = R.tau + kr * lp;
                     ++S.cnt;
@@ -821,7 +822,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             deposit<DEFER>(X, R, len, kr);
         }
         if (has_rho) R.tau += I.kappa * rho * len;   // before the store: its wait then holds no store
-        if (SEGS) store_segment<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT>()>(O, R, S.cnt, R.uid, len);
+        if (SEGS) store_segment<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT, WIDE>()>(O, R, S.cnt, R.uid, len);
         ++S.cnt;
         R.s_c = best;
     } else if (len < -1e-9 * R.L) {
@@ -875,7 +876,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
 
 // One exit-point step (Sect. 2.2) with the exit search done by this lane
 // alone. Returns false once the path has ended.
-template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false>
+template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false, bool WIDE = true>
 __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, const SegOut &O,
                                          const Extras &X = Extras{})
 {
@@ -891,7 +892,7 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
                          j1);
         S.nredo += redo ? 1 : 0;
     }
-    return ray_step_end<MODE, SEGS, EXT, DEFER>(G, I, R, S, O, win, best, redo, j1, X);
+    return ray_step_end<MODE, SEGS, EXT, DEFER, WIDE>(G, I, R, S, O, win, best, redo, j1, X);
 }
 
 }  // namespace vrt
