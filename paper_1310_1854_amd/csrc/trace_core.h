@@ -541,6 +541,21 @@ constexpr int lens_per_store()
     return (WIDE && MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
 }
 
+// 16 bytes of segment output: non-temporal (streaming) by default, since the
+// segments are not read again here and the stores should leave the L2 to the
+// records.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+template <class V>
+__device__ __forceinline__ void put16(V v, V *p)
+{
+#if VRT_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 template <int CG, int LG>
 __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int64_t idx, int32_t cell, double len)
 {
@@ -602,45 +617,30 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
             bool spill;
             const int64_t p = segment_slot(O, R, idx - 7, spill);
             if (p >= 0) {
-                int32_t *cp = spill ? O.spill_cell : O.cell;
-                double *lp = spill ? O.spill_len : O.len;
-                typedef int v4i __attribute__((ext_vector_type(4)));
-                typedef double v2d __attribute__((ext_vector_type(2)));
-                __builtin_nontemporal_store(v2d{R.l0, R.l1}, reinterpret_cast<v2d *>(lp + p));
-                __builtin_nontemporal_store(v2d{R.l2, R.l3}, reinterpret_cast<v2d *>(lp + p + 2));
-                __builtin_nontemporal_store(v2d{R.l4, R.l5}, reinterpret_cast<v2d *>(lp + p + 4));
-                __builtin_nontemporal_store(v2d{R.l6, R.l7}, reinterpret_cast<v2d *>(lp + p + 6));
-                __builtin_nontemporal_store(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp + p));
-                __builtin_nontemporal_store(v4i{R.c4, R.c5, R.c6, R.c7}, reinterpret_cast<v4i *>(cp + p + 4));
+                v2d *lp = reinterpret_cast<v2d *>((spill ? O.spill_len : O.len) + p);
+                v4i *cp = reinterpret_cast<v4i *>((spill ? O.spill_cell : O.cell) + p);
+                put16(v2d{R.l0, R.l1}, lp);
+                put16(v2d{R.l2, R.l3}, lp + 1);
+                put16(v2d{R.l4, R.l5}, lp + 2);
+                put16(v2d{R.l6, R.l7}, lp + 3);
+                put16(v4i{R.c0, R.c1, R.c2, R.c3}, cp);
+                put16(v4i{R.c4, R.c5, R.c6, R.c7}, cp + 1);
             }
         }
         if (LG == 4 && (idx & 3) == 3) {
             bool spill;
             const int64_t p = segment_slot(O, R, idx - 3, spill);   // groups of 8 never cross a window or chunk end
             if (p >= 0) {
-                int32_t *cp = spill ? O.spill_cell : O.cell;
-                double *lp = spill ? O.spill_len : O.len;
-#if VRT_NT_STORE   // streaming: the segments are not read again here; the stores leave the L2 to the records
-                typedef int v4i __attribute__((ext_vector_type(4)));
-                typedef double v2d __attribute__((ext_vector_type(2)));
-                __builtin_nontemporal_store(v2d{R.l0, R.l1}, reinterpret_cast<v2d *>(lp + p));
-                __builtin_nontemporal_store(v2d{R.l2, R.l3}, reinterpret_cast<v2d *>(lp + p + 2));
+                int32_t *cp = (spill ? O.spill_cell : O.cell) + p;
+                v2d *lp = reinterpret_cast<v2d *>((spill ? O.spill_len : O.len) + p);
+                put16(v2d{R.l0, R.l1}, lp);
+                put16(v2d{R.l2, R.l3}, lp + 1);
                 if (CG == 4) {
-                    __builtin_nontemporal_store(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp + p));
+                    put16(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp));
                 } else if ((idx & 7) == 7) {
-                    __builtin_nontemporal_store(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp + p - 4));
-                    __builtin_nontemporal_store(v4i{R.c4, R.c5, R.c6, R.c7}, reinterpret_cast<v4i *>(cp + p));
+                    put16(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp - 4));
+                    put16(v4i{R.c4, R.c5, R.c6, R.c7}, reinterpret_cast<v4i *>(cp));
                 }
-#else
-                *reinterpret_cast<double2 *>(lp + p) = make_double2(R.l0, R.l1);
-                *reinterpret_cast<double2 *>(lp + p + 2) = make_double2(R.l2, R.l3);
-                if (CG == 4) {
-                    *reinterpret_cast<int4 *>(cp + p) = make_int4(R.c0, R.c1, R.c2, R.c3);
-                } else if ((idx & 7) == 7) {
-                    *reinterpret_cast<int4 *>(cp + p - 4) = make_int4(R.c0, R.c1, R.c2, R.c3);
-                    *reinterpret_cast<int4 *>(cp + p) = make_int4(R.c4, R.c5, R.c6, R.c7);
-                }
-#endif
             }
         }
         return;
