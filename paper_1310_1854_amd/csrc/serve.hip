@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     kappa = rq.in.kappa;
                     cellp = rq.seg_cell;
                     lenp = rq.seg_len;
-                    vec = (rq.seg_cell && rq.seg_stride % 8 == 0) ? 1 : 0;
+                    vec = !rq.seg_cell ? 0 : rq.seg_stride % 16 == 0 ? 2 : rq.seg_stride % 8 == 0 ? 1 : 0;
                     S = RayStats();
                     double s0;
                     R.st = ray_setup<false>(G, rq.in, ray, R.r0, R.k, R.L, s0);
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
             const bool more = (ctx & 1) ? ray_step<VOR_MODE_MIXED, true, false, false, false>(G, I, R, S, O)
                                         : ray_step<VOR_MODE_FP64, true>(G, I, R, S, O);
             if (!more) {
-                if (ctx & 1) finish_segments<cells_per_store<VOR_MODE_MIXED, false>(), lens_per_store<VOR_MODE_MIXED, false, false>()>(
+                if (ctx & 1) finish_segments<cells_per_store<VOR_MODE_MIXED, false, false>(), lens_per_store<VOR_MODE_MIXED, false, false>()>(
                     O, R, S.cnt);
                 else finish_segments<cells_per_store<VOR_MODE_FP64, false>(), lens_per_store<VOR_MODE_FP64, false>()>(O, R, S.cnt);
                 if (R.cap > 0 && R.st == RAY_OK && S.cnt > R.cap) R.st = RAY_OVERFLOW;

@@ -625,7 +625,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     A.work = out->work;
     A.O.cell = out->seg_cell;
     A.O.len = out->seg_len;
-    A.O.vec = (out->seg_stride > 0 && out->seg_stride % 8 == 0) ? 1 : 0;
+    A.O.vec = out->seg_stride <= 0 ? 0 : out->seg_stride % 16 == 0 ? 2 : out->seg_stride % 8 == 0 ? 1 : 0;
     A.O.spill_cell = spill ? out->spill_cell : nullptr;
     A.O.spill_len = out->spill_len;
     A.O.spill_next = out->spill_next;

@@ -55,7 +55,7 @@ constexpr int kSpillChunk = VOR_SPILL_CHUNK;
 struct SegOut {
     int32_t *cell;                  // window slots
     double *len;
-    int vec;                        // windows start on multiples of 8 slots: cells stored 8, lengths 4 at a time
+    int vec;                        // windows start on multiples of 8 slots (1) or 16 (2): groups of segments stored together
     int32_t *spill_cell;            // chunk c holds slots [c * kSpillChunk, (c + 1) * kSpillChunk)
     double *spill_len;
     int32_t *spill_next;            // next chunk of the same path, -1 at the end
@@ -424,7 +424,8 @@ struct RayState {
     int32_t chunk;        // current spill chunk, -1 none yet, -2 spill exhausted
     int32_t ray;
 #if VRT_VEC_STORE
-    int32_t c0, c1, c2, c3, c4, c5, c6, c7;   // the last cells, oldest first, written 8 at a time (32 B)
+    int32_t c0, c1, c2, c3, c4, c5, c6, c7;   // the last cells, oldest first, written 4, 8 or 16 at a time
+    int32_t c8, c9, c10, c11, c12, c13, c14, c15;
     double l0, l1, l2, l3, l4, l5, l6, l7;    // the last lengths, written LG at a time
 #endif
     int32_t m, uid;
@@ -526,14 +527,16 @@ __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState 
 // chain. A new chunk is taken when a path reaches the first slot of one;
 // lanes that do so in the same step share one atomic.
 // Segments written together per lane: in the mixed-mode kernels without
-// the optional features, 8 cells (32 B) and 8 lengths (64 B) where the
-// registers allow it; in the others 4 of each (16 B and 32 B), since 12 more
-// registers would cut their occupancy. WIDE = false keeps 4 lengths (for the
-// serving kernel, which holds both the mixed and the FP64 step).
-template <int MODE, bool EXT>
+// the optional features, 16 cells (64 B) and 8 lengths (64 B) where the
+// registers allow it (windows on 16-slot boundaries; elsewhere these kernels
+// write each segment on its own); in the others 4 of each (16 B and 32 B), since
+// more registers would cut their occupancy. WIDE = false keeps 8 cells and
+// 4 lengths (for the serving kernel, which holds both the mixed and the FP64
+// step).
+template <int MODE, bool EXT, bool WIDE = true>
 constexpr int cells_per_store()
 {
-    return (MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
+    return (MODE != VOR_MODE_FP64 && !EXT) ? (WIDE ? 16 : 8) : 4;
 }
 template <int MODE, bool EXT, bool WIDE = true>
 constexpr int lens_per_store()
@@ -584,20 +587,32 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
         }
     }
 #if VRT_VEC_STORE
-    if (O.vec) {
-        // The cells go out CG and the lengths LG at a time: 32 and 64 B with
-        // CG = LG = 8 (a partial write of the memory's write unit costs the
+    if (O.vec >= (CG == 16 ? 2 : 1)) {
+        // The cells go out CG and the lengths LG at a time: 64 B each with
+        // CG = 16, LG = 8 (a partial write of the memory's write unit costs the
         // unit's read as well once the line leaves the L2 before the rest of
         // it is written).
         R.c0 = R.c1;
         R.c1 = R.c2;
         R.c2 = R.c3;
-        if (CG == 8) {
+        if (CG >= 8) {
             R.c3 = R.c4;
             R.c4 = R.c5;
             R.c5 = R.c6;
             R.c6 = R.c7;
-            R.c7 = cell;
+            if (CG == 16) {
+                R.c7 = R.c8;
+                R.c8 = R.c9;
+                R.c9 = R.c10;
+                R.c10 = R.c11;
+                R.c11 = R.c12;
+                R.c12 = R.c13;
+                R.c13 = R.c14;
+                R.c14 = R.c15;
+                R.c15 = cell;
+            } else {
+                R.c7 = cell;
+            }
         } else {
             R.c3 = cell;
         }
@@ -623,8 +638,15 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
                 put16(v2d{R.l2, R.l3}, lp + 1);
                 put16(v2d{R.l4, R.l5}, lp + 2);
                 put16(v2d{R.l6, R.l7}, lp + 3);
-                put16(v4i{R.c0, R.c1, R.c2, R.c3}, cp);
-                put16(v4i{R.c4, R.c5, R.c6, R.c7}, cp + 1);
+                if (CG == 8) {
+                    put16(v4i{R.c0, R.c1, R.c2, R.c3}, cp);
+                    put16(v4i{R.c4, R.c5, R.c6, R.c7}, cp + 1);
+                } else if ((idx & 15) == 15) {   // the group of 16 started 8 slots earlier
+                    put16(v4i{R.c0, R.c1, R.c2, R.c3}, cp - 2);
+                    put16(v4i{R.c4, R.c5, R.c6, R.c7}, cp - 1);
+                    put16(v4i{R.c8, R.c9, R.c10, R.c11}, cp);
+                    put16(v4i{R.c12, R.c13, R.c14, R.c15}, cp + 1);
+                }
             }
         }
         if (LG == 4 && (idx & 3) == 3) {
@@ -659,20 +681,27 @@ template <int CG, int LG>
 __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState &R, int64_t n)
 {
 #if VRT_VEC_STORE
-    if (!O.vec) return;
+    if (O.vec < (CG == 16 ? 2 : 1)) return;
     const int rc = (int)(n & (CG - 1)), rl = (int)(n & (LG - 1));   // cells and lengths not yet written
     if (rc == 0) return;
-    const int32_t cs[8] = {CG == 8 ? R.c0 : 0, CG == 8 ? R.c1 : 0, CG == 8 ? R.c2 : 0, CG == 8 ? R.c3 : 0,
-                           CG == 8 ? R.c4 : R.c0, CG == 8 ? R.c5 : R.c1, CG == 8 ? R.c6 : R.c2, CG == 8 ? R.c7 : R.c3};
+    // the held cells, right-aligned in 16 entries
+    int32_t cs[16] = {R.c0, R.c1, R.c2, R.c3, R.c4, R.c5, R.c6, R.c7, R.c8, R.c9, R.c10, R.c11, R.c12, R.c13, R.c14, R.c15};
+    if (CG == 8) {
+        const int32_t t[8] = {R.c0, R.c1, R.c2, R.c3, R.c4, R.c5, R.c6, R.c7};
+        for (int i = 0; i < 8; ++i) cs[8 + i] = t[i];
+    } else if (CG == 4) {
+        const int32_t t[4] = {R.c0, R.c1, R.c2, R.c3};
+        for (int i = 0; i < 4; ++i) cs[12 + i] = t[i];
+    }
     const double ls[8] = {LG == 8 ? R.l0 : 0.0, LG == 8 ? R.l1 : 0.0, LG == 8 ? R.l2 : 0.0, LG == 8 ? R.l3 : 0.0,
                           LG == 8 ? R.l4 : R.l0, LG == 8 ? R.l5 : R.l1, LG == 8 ? R.l6 : R.l2, LG == 8 ? R.l7 : R.l3};
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
+    for (int j = 0; j < CG - 1; ++j) {
         if (j < rc) {
             bool spill;
             const int64_t p = segment_slot(O, R, n - rc + j, spill);
             if (p >= 0) {
-                (spill ? O.spill_cell : O.cell)[p] = cs[8 - rc + j];
+                (spill ? O.spill_cell : O.cell)[p] = cs[16 - rc + j];
                 if (j >= rc - rl) (spill ? O.spill_len : O.len)[p] = ls[8 - rc + j];
             }
         }
@@ -810,7 +839,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                 const double tn = R.tau + kr * len;
                 if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
                     const double lp = (R.tstop - R.tau) / kr;
-                    if (SEGS) store_segment<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT, WIDE>()>(O, R, S.cnt, R.uid, lp);
+                    if (SEGS) store_segment<cells_per_store<MODE, EXT, WIDE>(), lens_per_store<MODE, EXT, WIDE>()>(O, R, S.cnt, R.uid, lp);
                     deposit<DEFER>(X, R, lp, kr);
                     R.tau = R.tau + kr * lp;
                     ++S.cnt;
@@ -822,7 +851,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             deposit<DEFER>(X, R, len, kr);
         }
         if (has_rho) R.tau += I.kappa * rho * len;   // before the store: its wait then holds no store
-        if (SEGS) store_segment<cells_per_store<MODE, EXT>(), lens_per_store<MODE, EXT, WIDE>()>(O, R, S.cnt, R.uid, len);
+        if (SEGS) store_segment<cells_per_store<MODE, EXT, WIDE>(), lens_per_store<MODE, EXT, WIDE>()>(O, R, S.cnt, R.uid, len);
         ++S.cnt;
         R.s_c = best;
     } else if (len < -1e-9 * R.L) {
