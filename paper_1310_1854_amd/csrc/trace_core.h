@@ -528,8 +528,8 @@ __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState 
 // lanes that do so in the same step share one atomic.
 // Segments written together per lane: in the mixed-mode kernels without
 // the optional features, 16 cells (64 B) and 8 lengths (64 B) where the
-// registers allow it (windows on 16-slot boundaries; elsewhere these kernels
-// write each segment on its own); in the others 4 of each (16 B and 32 B), since
+// registers allow it (on windows that start on 8- but not 16-slot
+// boundaries the cells go out 8 at a time); in the others 4 of each (16 B and 32 B), since
 // more registers would cut their occupancy. WIDE = false keeps 8 cells and
 // 4 lengths (for the serving kernel, which holds both the mixed and the FP64
 // step).
@@ -587,7 +587,7 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
         }
     }
 #if VRT_VEC_STORE
-    if (O.vec >= (CG == 16 ? 2 : 1)) {
+    if (O.vec) {
         // The cells go out CG and the lengths LG at a time: 64 B each with
         // CG = 16, LG = 8 (a partial write of the memory's write unit costs the
         // unit's read as well once the line leaves the L2 before the rest of
@@ -641,6 +641,9 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
                 if (CG == 8) {
                     put16(v4i{R.c0, R.c1, R.c2, R.c3}, cp);
                     put16(v4i{R.c4, R.c5, R.c6, R.c7}, cp + 1);
+                } else if (O.vec < 2) {          // windows on 8-slot boundaries only: the last 8 cells
+                    put16(v4i{R.c8, R.c9, R.c10, R.c11}, cp);
+                    put16(v4i{R.c12, R.c13, R.c14, R.c15}, cp + 1);
                 } else if ((idx & 15) == 15) {   // the group of 16 started 8 slots earlier
                     put16(v4i{R.c0, R.c1, R.c2, R.c3}, cp - 2);
                     put16(v4i{R.c4, R.c5, R.c6, R.c7}, cp - 1);
@@ -681,8 +684,9 @@ template <int CG, int LG>
 __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState &R, int64_t n)
 {
 #if VRT_VEC_STORE
-    if (O.vec < (CG == 16 ? 2 : 1)) return;
-    const int rc = (int)(n & (CG - 1)), rl = (int)(n & (LG - 1));   // cells and lengths not yet written
+    if (!O.vec) return;
+    const int cg = (CG == 16 && O.vec < 2) ? 8 : CG;                // 16 only on 16-slot windows
+    const int rc = (int)(n & (cg - 1)), rl = (int)(n & (LG - 1));   // cells and lengths not yet written
     if (rc == 0) return;
     // the held cells, right-aligned in 16 entries
     int32_t cs[16] = {R.c0, R.c1, R.c2, R.c3, R.c4, R.c5, R.c6, R.c7, R.c8, R.c9, R.c10, R.c11, R.c12, R.c13, R.c14, R.c15};
