@@ -276,8 +276,14 @@ def test_rays_from_outside_enter_the_box(vrt, mode, persistent):
     d[1000:1500] = -k[1000:1500]             # outside, heading away: misses
     o[1500:1600, 0] = 3.0                    # outside, moving parallel to the x walls: misses
     d[1500:1600, 0] = 0.0
+    # origins that are no point (NaN or infinite coordinates): no path, whichever way they head
+    bad = [float("nan"), float("inf"), -float("inf")]
+    for i in range(1600, 1660):
+        o[i, (i // 3) % 3] = bad[i % 3]
+    o[1660:1670] = float("nan")
     ref = oracle.trace(w.sites, w.box, w.density, o, d, cap=64, enter=True)
-    assert (ref["status"] == oracle.ST_OUTSIDE).sum() >= 600 and (ref["start_s"] > 0).sum() > 4000
+    assert np.all(ref["status"][1600:1670] == oracle.ST_OUTSIDE)
+    assert (ref["status"] == oracle.ST_OUTSIDE).sum() >= 670 and (ref["start_s"] > 0).sum() > 4000
     out = vrt.trace(vrt_grid(vrt, w), o, d, w.density, mode=mode, segments="exact", persistent=persistent,
                     ordered=persistent, enter=True)
     p = gpu_paths(out)
@@ -291,6 +297,8 @@ def test_rays_from_outside_enter_the_box(vrt, mode, persistent):
                     enter=True, tau_stop=ts)
     ok = ref["status"] == 0
     assert np.array_equal(out["stop_s"].cpu().numpy()[ok], ref["start_s"][ok])
+    assert np.all(out["status"].cpu().numpy()[1600:1670] == oracle.ST_OUTSIDE)
+    assert np.all(out["stop_cell"].cpu().numpy()[1600:1670] == -1)
 
 
 _GRIDS = {}

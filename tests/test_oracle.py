@@ -463,3 +463,89 @@ def test_entering_equals_starting_at_the_entry_point(oracle_lib):
         assert np.max(np.abs(la - lb)) <= 1e-12 * a["chord"][r]
     assert np.allclose(a["chord"][ok] - a["start_s"][ok], b["chord"][ok] - b["start_s"][ok], rtol=0, atol=1e-12)
     assert np.all(b["start_s"] < 1e-12)
+
+
+def test_nonfinite_origins_entering_are_outside(oracle_lib):
+    """A path starts at a point (Sect. 2.2); an origin with a NaN or infinite
+    coordinate is no point, so even a ray allowed to enter the box from
+    outside has no path: status OUTSIDE, no segment, tau 0, L 0. Each case
+    heads for the box along the axis of its bad coordinate, or along
+    another one, so that no ordering of the wall tests lets it through."""
+    nan, inf = float("nan"), float("inf")
+    origins = [[nan, 0.5, 0.5], [0.5, nan, 0.5], [0.5, 0.5, nan], [nan, nan, nan],
+               [inf, 0.5, 0.5], [-inf, 0.5, 0.5], [0.5, -inf, 0.5], [0.5, 0.5, inf],
+               [nan, 0.5, 0.5], [-inf, 0.5, 0.5]]
+    dirs = [[1, 0, 0], [0, 1, 0], [0, 0, -1], [1, 1, 1],
+            [-1, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, -1],
+            [0, 1, 0], [0, 0, 1]]
+    o = oracle.trace([[0.5, 0.5, 0.5], [0.25, 0.75, 0.5]], [0, 0, 0, 1, 1, 1], [2.0, 3.0], origins, dirs,
+                     cap=4, enter=True)
+    assert list(o["status"]) == [oracle.ST_OUTSIDE] * len(origins)
+    assert np.all(o["nseg"] == 0) and np.all(o["tau"] == 0.0) and np.all(o["chord"] == 0.0)
+    assert np.all(o["cell0"] == -1)
+
+
+def _golden_case(name):
+    g = json.load(open(os.path.join(HERE, "golden", "hand_paths.json")))
+    return next(c for c in g["cases"] if c["name"] == name)
+
+
+def _offset_vertex_ray(delta, scale=1.0):
+    """The golden 2 x 2 x 1 lattice ray through the edge x = y = 1, moved
+    sideways by delta in x. In the start cell it meets the face x = 1 at
+    (0.75 - delta) sqrt 2 and the bisector x + y = 2 with the diagonal site at
+    (0.75 - delta / 2) sqrt 2, a gap of (delta / 2) sqrt 2, with
+    L = (1.75 - delta) sqrt 2: the chord-relative gap is
+    (delta / 2) / (1.75 - delta). Everything is scaled by `scale`, which
+    leaves that ratio unchanged."""
+    c = _golden_case("lattice_vertex_crossing")
+    s = float(scale)
+    sites = np.array(c["sites"]) * s
+    box = np.array(c["box"], float) * s
+    r0 = (np.array(c["origin"]) + [delta, 0.0, 0.0]) * s
+    return oracle.trace(sites, box, c["density"], [r0], [c["dir"]], cap=8)
+
+
+def test_near_tie_classifier(oracle_lib):
+    """The near-tie flag (two smallest candidate crossings within eta L of
+    each other, or a start point within eta L of a cell boundary) marks the
+    rays whose cell list is not unique (several correct results). Pinned on
+    cases where the geometry fixes the answer."""
+    eta = oracle.ETA
+    # the ray through the edge where four cells meet: two planes at the same s
+    c = _golden_case("lattice_vertex_crossing")
+    o = oracle.trace(c["sites"], c["box"], c["density"], [c["origin"]], [c["dir"]], cap=8)
+    assert o["n_near"][0] >= 1 and o["min_gap"][0] == 0.0
+    # an origin on a bisector plane: equidistant from two sites at the start
+    c = _golden_case("origin_on_bisector_plane")
+    o = oracle.trace(c["sites"], c["box"], c["density"], [c["origin"]], [c["dir"]], cap=8)
+    assert o["n_near"][0] >= 1 and o["min_gap"][0] == 0.0
+    # a ray lying in a bisector plane: both cells hold the whole path
+    c = _golden_case("ray_inside_a_bisector_plane")
+    o = oracle.trace(c["sites"], c["box"], c["density"], [c["origin"]], [c["dir"]], cap=8)
+    assert o["n_near"][0] >= 1 and o["min_gap"][0] == 0.0
+    # the edge ray moved sideways so that its smallest gap is 1e-6 of the chord: not a near-tie
+    for scale in (1.0, 8192.0, 2.0 ** -20):
+        d = 2e-6 * 1.75
+        o = _offset_vertex_ray(d, scale)
+        assert o["n_near"][0] == 0, scale
+        assert abs(o["min_gap"][0] - 0.5 * d / (1.75 - d)) <= 1e-9 * d, (scale, o["min_gap"][0])
+        assert list(oracle.segments_of(o, 0)[0]) == [0, 2, 3]
+        # ... and with a gap of 1e-10 of the chord it is one, at any scale (the threshold is relative to L)
+        d = 2e-10 * 1.75
+        o = _offset_vertex_ray(d, scale)
+        assert o["n_near"][0] >= 1, scale
+        assert 0.0 < o["min_gap"][0] <= eta
+    # an origin 1e-6 L off a bisector plane is clean, 1e-11 L off it is a near-tie
+    c = _golden_case("origin_on_bisector_plane")
+    for off, near in ((1e-6, False), (1e-11, True)):
+        r0 = np.array(c["origin"]) + [off * c["chord"], 0.0, 0.0]
+        o = oracle.trace(c["sites"], c["box"], c["density"], [r0], [c["dir"]], cap=8)
+        assert (o["n_near"][0] > 0) == near, off
+        # the start gap is the distance to the plane x = 0 over L = 1 - x0 (up to the rounding of d2 - d1)
+        assert abs(o["min_gap"][0] - r0[0] / (1.0 - r0[0])) <= 1e-9 * r0[0] + 1e-16
+    # a generic ray in a uniform cube: flags only where the gap is small
+    w = W.uniform_cube(M=300, N=400, seed=4251)
+    o = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
+    assert np.array_equal(o["n_near"] > 0, o["min_gap"] <= eta)
+    assert (o["n_near"] > 0).sum() <= 2

@@ -14,6 +14,8 @@ its own library in a temporary directory; the shipped oracle is untouched.
 import json
 import math
 import os
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -49,7 +51,44 @@ MUTANTS = {
     "face_volume_height": ("vol += ar * (0.5 * sqrt(v3dot(a, a))) / 3.0;", "vol += ar * (sqrt(v3dot(a, a))) / 3.0;"),
     "bbox_max_slot": ("if (xyz[a] > bb[a + 3]) bb[a + 3] = xyz[a];", "if (xyz[a] > bb[a + 3]) bb[a] = xyz[a];"),
     "bbox_min_compare": ("if (xyz[a] < bb[a]) bb[a] = xyz[a];", "if (xyz[a] > bb[a]) bb[a] = xyz[a];"),
+    "nonfinite_origin_entered": ("} else if (outside && (!enter || !isfinite(r0[0]) || !isfinite(r0[1]) || !isfinite(r0[2]))) {",
+                                 "} else if (outside && !enter) {"),
+    "tie_gap_not_recorded": ("} else if (sj == best) {\n                        second_best = sj;\n",
+                             "} else if (sj == best) {\n"),
+    "start_gap_not_flagged": ("g /= L;\n                if (g < gmin) gmin = g;\n                if (g <= eta) ++near;",
+                              "g /= L;\n                if (g < gmin) gmin = g;"),
+    "near_gap_not_chord_relative": ("double g = (second_best - best) / L;", "double g = (second_best - best);"),
 }
+
+
+_NONFINITE_CHILD = """
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[2])
+import oracle
+lib = oracle.load_library(sys.argv[1])
+nan, inf = float("nan"), float("inf")
+org = [[nan, 0.5, 0.5], [0.5, nan, 0.5], [nan, nan, nan], [inf, 0.5, 0.5], [-inf, 0.5, 0.5]]
+dr = [[1, 0, 0], [0, 1, 0], [1, 1, 1], [-1, 0, 0], [1, 0, 0]]
+o = oracle.trace([[0.5, 0.5, 0.5], [0.25, 0.75, 0.5]], [0, 0, 0, 1, 1, 1], [2.0, 3.0], org, dr,
+                 cap=4, lib=lib, enter=True)
+ok = bool(np.all(o["status"] == oracle.ST_OUTSIDE) and np.all(o["nseg"] == 0))
+sys.exit(0 if ok else 1)
+"""
+
+
+def _nonfinite_in_child(lib) -> bool:
+    """The non-finite-origin pin in a process of its own: a mutant that lets
+    such a ray through reads outside the site array, which must not take
+    the test run with it. A crash or a hang counts as a failure."""
+    root = os.path.dirname(HERE)
+    try:
+        r = subprocess.run([sys.executable, "-c", _NONFINITE_CHILD, lib._name, root], timeout=120,
+                           stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL,
+                           env=dict(os.environ, OMP_NUM_THREADS="1"))
+    except subprocess.TimeoutExpired:
+        return False
+    return r.returncode == 0
 
 
 def _pins(lib):
@@ -146,8 +185,28 @@ def _pins(lib):
         want = np.array([[i, j, k, i + 1, j + 1, k + 1] for i in range(n) for j in range(n) for k in range(n)], float)
         return np.allclose(bb, want, rtol=0, atol=1e-12)
 
+    def nonfinite():
+        # origins that are no point have no path, also for rays allowed to enter from outside
+        return _nonfinite_in_child(lib)
+
+    def near_ties():
+        g = {c["name"]: c for c in json.load(open(os.path.join(HERE, "golden", "hand_paths.json")))["cases"]}
+        for name in ("lattice_vertex_crossing", "origin_on_bisector_plane"):
+            c = g[name]
+            o = oracle.trace(c["sites"], c["box"], c["density"], [c["origin"]], [c["dir"]], cap=8, lib=lib)
+            if not (o["n_near"][0] >= 1 and o["min_gap"][0] == 0.0):
+                return False
+        # the vertex ray moved sideways (chord-relative gap 1e-10), at a large scale
+        c = g["lattice_vertex_crossing"]
+        s = 8192.0
+        r0 = (np.array(c["origin"]) + [2e-10 * 1.75, 0.0, 0.0]) * s
+        o = oracle.trace(np.array(c["sites"]) * s, np.array(c["box"], float) * s, c["density"], [r0], [c["dir"]],
+                         cap=8, lib=lib)
+        return bool(o["n_near"][0] >= 1)
+
     for name, fn in [("golden", golden), ("lattice", lattice), ("exact", exact), ("invariants", invariants),
-                     ("locate", locate), ("faces", faces), ("entering", entering), ("bboxes", bboxes)]:
+                     ("locate", locate), ("faces", faces), ("entering", entering), ("bboxes", bboxes),
+                     ("nonfinite", nonfinite), ("near_ties", near_ties)]:
         check(name, fn)
     return failed
 
