@@ -312,16 +312,36 @@ def grid_quality(args, torch, vrt, workloads):
     print(json.dumps(result), flush=True)
 
 
-def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid_density=False):
+def spill_per_ray(vrt, torch, grid, o, d, stride):
+    """Mean spill chunks per ray that paths of these rays need past a window
+    of `stride` slots (a tau-only trace of a sample; set-up): sizes the
+    first spill pool of each served request."""
+    b = vrt.TraceBuffers(o.shape[0], locate_first=True)
+    vrt.trace_into(grid, o, d, None, b, mode="mixed", persistent=True)
+    torch.cuda.synchronize()
+    need = (b.n_seg.long() - stride).clamp(min=0)
+    return float(((need + vrt.SPILL_CHUNK - 1) // vrt.SPILL_CHUNK).double().mean())
+
+
+def request_chunks(n, per_ray):
+    """The first spill pool of a request of n rays: 25% over the mean need,
+    plus a few chunks (a pool too small costs a second run of the request)."""
+    return int(math.ceil(1.25 * per_ray * n)) + 8
+
+
+def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid_density=False, per_ray=None):
     """Submit the requests at the given offsets (seconds from the start) to a
     fresh server, reap them in completion order, and return the wall time,
-    crossings, p50/p99 latency and (keep) every request's tau. grid_density:
-    the requests use the densities bound to their grids instead of rhos."""
+    crossings, p50/p99 latency and (keep) every request's tau and statuses.
+    grid_density: the requests use the densities bound to their grids
+    instead of rhos. per_ray[g]: mean spill chunks per ray on grid g (the
+    requests' first spill pools); every path is stored whole."""
     import threading
 
     srv = vrt.Server(grids, budget_bytes=budget)
     lat = [None] * len(reqs)
     taus = [None] * len(reqs)
+    stats = [None] * len(reqs)
     done = threading.Event()
     lock = threading.Lock()
     index = {}
@@ -335,8 +355,10 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid
             with lock:   # the submitter records the id under the same lock
                 i = index[rid]
             lat[i] = srv.latency(rid)
-            if keep:
-                taus[i] = srv.result(rid)["tau"]   # the release below waits for this copy
+            if keep:   # the per-ray results (the release below waits for these copies)
+                res = srv.result(rid, paths=False)
+                taus[i] = res["tau"]
+                stats[i] = res["status"]
             srv.release(rid)
             nfin += 1
         done.set()
@@ -348,9 +370,11 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid
         wait = t0 + offsets[i] - time.perf_counter()
         if wait > 0:
             time.sleep(wait)
+        n = r["o"].shape[0]
+        chunks = request_chunks(n, per_ray[r["grid"]]) if stride > 0 else 0
         with lock:
             rid = srv.submit(r["grid"], r["o"], r["d"], None if grid_density else rhos[r["grid"]], mode=r["mode"],
-                             seg_stride=stride, grid_density=grid_density)
+                             seg_stride=stride, spill_chunks=chunks, grid_density=grid_density)
             index[rid] = i
     if not done.wait(600):
         raise RuntimeError("serving run did not finish within 600 s")
@@ -363,7 +387,13 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid
     lat = np.array(lat, dtype=np.float64)
     out = dict(seconds=t1 - t0, crossings=st["crossings"], rate=st["crossings"] / (t1 - t0),
                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-               launches=st["launches"], redecisions=st["fp64_redecisions"])
+               launches=st["launches"], redecisions=st["fp64_redecisions"], reruns=st["reruns"])
+    if keep:
+        import torch
+        counts = torch.bincount(torch.cat(stats).long(), minlength=5).cpu().tolist()
+        if counts[vrt.RAY_OVERFLOW] or counts[vrt.RAY_STEPLIMIT]:
+            raise RuntimeError(f"served paths incomplete: status counts {counts}")
+        out["status_counts"] = counts
     return (out, taus) if keep else out
 
 
@@ -389,12 +419,20 @@ def serving(args, torch, vrt, workloads):
     reqs = [dict(grid=r["grid"], mode=["fp64", "mixed"][r["mode"]], o=torch.as_tensor(r["origins"], device="cuda"),
                  d=torch.as_tensor(r["dirs"], device="cuda"), t=r["t"]) for r in base]
     total_rays = sum(r["o"].shape[0] for r in reqs)
+    per_ray = []
+    for gi, g in enumerate(grids):
+        mine = [r for r in reqs if r["grid"] == gi][:40]
+        o = torch.cat([r["o"] for r in mine]).contiguous()
+        d = torch.cat([r["d"] for r in mine]).contiguous()
+        per_ray.append(spill_per_ray(vrt, torch, g, o, d, stride))
+    print(f"[bench] spill chunks per ray past {stride}-slot windows: {per_ray}", file=sys.stderr, flush=True)
 
-    def run(offsets):
-        return run_server(vrt, grids, rhos, reqs, offsets, stride, budget, grid_density=bound)
+    def run(offsets, keep=False):
+        return run_server(vrt, grids, rhos, reqs, offsets, stride, budget, grid_density=bound, per_ray=per_ray,
+                          keep=keep)
 
     run(np.zeros(len(reqs)))   # warm-up
-    sat = run(np.zeros(len(reqs)))
+    sat, _ = run(np.zeros(len(reqs)), keep=True)
     req_rate_sat = len(reqs) / sat["seconds"]
     loads = {}
     for f in (0.5, 0.8, 0.95):
@@ -408,88 +446,116 @@ def serving(args, torch, vrt, workloads):
         "vs_baseline": None, "dtype": "f64 / f32+f64 (50/50 classes)", "data": "synthetic",
         "config": {"workload": f"serving: 3 resident grids (1e4, 1e5, 1e6 sites), {len(reqs)} Poisson requests "
                                f"of 256-65536 rays ({total_rays} rays), 50/50 FP64/mixed, 1 GiB output budget, "
+                               f"whole paths ({stride}-slot windows and spill chains), "
                                f"offered load 0.8 of saturation, densities "
                                + ("bound to the grids" if bound else "passed per request"), "requests": len(reqs),
-                   "rays": total_rays},
+                   "rays": total_rays, "seg_stride": stride, "spill_chunks_per_ray_estimate": per_ray},
         "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"],
         "saturated": sat, "loads": {str(k): v for k, v in loads.items()},
     }
     print(json.dumps(result), flush=True)
 
 
-def serving_precision(args, torch, vrt, workloads):
+def serving_precision_result(torch, vrt, workloads, n_requests, budget_gib, with_load=True):
     """The mixed-precision serving tracer against the plain FP64 GPU tracer on
     the 10^6-site flared disc (the serving mix's large grid). The same
     requests (log-uniform sizes in [256, 65536] rays from random sites,
     isotropic) are served all-FP64 and all-mixed, every request submitted at
-    once (saturated) and at an offered load of 0.8 of that; beside them
-    vor_trace runs the same rays in one persistent launch, in FP64 and mixed,
-    with the same 32-slot windows. Every request's tau must be identical
-    between the two serving runs and equal to vor_trace's (mixed mode
-    reproduces FP64: equal accuracy). The serving kernel's HBM rate is the
-    algorithmic bytes of the same paths (the counters of the mixed vor_trace
-    launch) over the serving wall time; value = the mixed serving rate."""
+    once (saturated) and (with_load) at an offered load of 0.8 of that, with
+    whole paths: 32-slot windows and spill chains from each request's pool.
+    Beside them vor_trace runs the same rays in one persistent launch, with
+    the same windows and a spill sized for every path, in FP64 and mixed, in
+    submission order and in the coherent order of vor_order_rays. Every
+    request's tau must be identical between the two serving runs and equal
+    to vor_trace's (mixed mode reproduces FP64: equal accuracy), and no
+    served ray may end without its whole path. The serving kernel's HBM
+    rate is the algorithmic bytes of the same paths (the counters of the
+    mixed vor_trace launch, which stores every segment as the server does)
+    over the serving wall time."""
     g = workloads.serving_grids()[2]
     grid = vrt.build_grid(g.sites, g.box)
     rho = torch.as_tensor(g.density, device="cuda")
-    stride, budget = 32, int(args.budget_gib * (1 << 30))
-    base = workloads.serving_requests(args.requests, [g], rate_hz=1.0)
+    stride, budget = 32, int(budget_gib * (1 << 30))
+    base = workloads.serving_requests(n_requests, [g], rate_hz=1.0)
     reqs = [dict(grid=0, mode=None, o=torch.as_tensor(r["origins"], device="cuda"),
                  d=torch.as_tensor(r["dirs"], device="cuda"), t=r["t"]) for r in base]
     sizes = [r["o"].shape[0] for r in reqs]
+    O = torch.cat([r["o"] for r in reqs]).contiguous()
+    D = torch.cat([r["d"] for r in reqs]).contiguous()
+    N = O.shape[0]
+    per_ray = [spill_per_ray(vrt, torch, grid, O[:200_000], D[:200_000], stride)]
     zeros = np.zeros(len(reqs))
     served, taus = {}, {}
     for mode in ("fp64", "mixed"):
         for r in reqs:
             r["mode"] = mode
-        run_server(vrt, [grid], [rho], reqs, zeros, stride, budget)   # warm-up
-        sat, taus[mode] = run_server(vrt, [grid], [rho], reqs, zeros, stride, budget, keep=True)
-        gaps = np.array([r["t"] for r in reqs]) / (0.8 * len(reqs) / sat["seconds"])
-        served[mode] = {"saturated": sat, "load_0.8": run_server(vrt, [grid], [rho], reqs, gaps, stride, budget)}
+        kw = dict(per_ray=per_ray)
+        run_server(vrt, [grid], [rho], reqs, zeros, stride, budget, **kw)   # warm-up
+        sat, taus[mode] = run_server(vrt, [grid], [rho], reqs, zeros, stride, budget, keep=True, **kw)
+        served[mode] = {"saturated": sat}
+        if with_load:
+            gaps = np.array([r["t"] for r in reqs]) / (0.8 * len(reqs) / sat["seconds"])
+            served[mode]["load_0.8"] = run_server(vrt, [grid], [rho], reqs, gaps, stride, budget, **kw)
         print(f"[bench] serving {mode}: {served[mode]}", file=sys.stderr, flush=True)
     same = all(torch.equal(a, b) for a, b in zip(taus["fp64"], taus["mixed"]))
 
-    # the plain tracer on the same rays, one launch each
-    O = torch.cat([r["o"] for r in reqs]).contiguous()
-    D = torch.cat([r["d"] for r in reqs]).contiguous()
-    N = O.shape[0]
+    # the plain tracer on the same rays, one launch each, whole paths
     plain = {}
-    for mode, ordered in (("fp64", False), ("mixed", False), ("mixed_ordered", True)):
+    tau_plain = None
+    for key, mode, ordered in (("fp64", "fp64", False), ("fp64_ordered", "fp64", True),
+                               ("mixed", "mixed", False), ("mixed_ordered", "mixed", True)):
         # densities from the array, as the requests pass them to the server
-        spec = {"mode": "mixed", "stride": stride, "spill_chunks_per_ray": 0.0, "persistent": True,
-                "grid_density": False,
-                "ordered": ordered}
-        bufs = make_buffers(vrt, N, spec, torch, chunks=0)   # 32-slot windows, no spill, as the requests
-        mode = "mixed" if ordered else mode
-        key = "mixed_ordered" if ordered else mode
-        run_steps(vrt, torch, grid, O, D, rho, bufs, spec, mode, 1, timed=False)
+        spec = {"mode": mode, "stride": stride, "spill_chunks_per_ray": 1.25 * per_ray[0], "persistent": True,
+                "grid_density": False, "ordered": ordered}
+        bufs = prepare_buffers(vrt, torch, grid, O, D, rho, spec, mode)
         bufs.counters.zero_()
         ms = float(np.mean(run_steps(vrt, torch, grid, O, D, rho, bufs, spec, mode, 3, timed=True)))
         c = bufs.counters.cpu().numpy().astype(np.float64) / 3
+        st = np.bincount(bufs.status.cpu().numpy(), minlength=5)
+        if st[vrt.RAY_OVERFLOW] or st[vrt.RAY_STEPLIMIT]:
+            raise RuntimeError(f"plain tracer output incomplete: {st.tolist()}")
         plain[key] = {"ms": ms, "rate": c[0] / (ms / 1e3), "counters": c}
         if key == "mixed":
             tau_plain = bufs.tau.clone()
+        del bufs
     splits = np.cumsum([0] + sizes)
     equal_plain = all(torch.equal(taus["mixed"][i], tau_plain[splits[i]:splits[i + 1]]) for i in range(len(reqs)))
     alg = algorithmic_bytes(plain["mixed"]["counters"], N, "mixed", False)
     sat_m = served["mixed"]["saturated"]
     serving_gbs = alg / sat_m["seconds"] / 1e9
-    result = {
-        "metric": METRIC, "value": sat_m["rate"], "unit": "crossings/s", "n_gpus": 1, "steps": len(reqs),
-        "warmup": 1, "ms_per_step": sat_m["seconds"] * 1e3 / len(reqs), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"serving precision: {len(reqs)} requests of 256-65536 rays ({N} rays) on the "
-                               f"1e6-site flared disc, all submitted at once, mixed vs FP64, "
-                               f"{args.budget_gib:g} GiB output budget",
-                   "requests": len(reqs), "rays": N, "budget_gib": args.budget_gib},
-        "p50_ms": sat_m["p50_ms"], "p99_ms": sat_m["p99_ms"],
+    best_fp64 = max(plain["fp64"]["rate"], plain["fp64_ordered"]["rate"])
+    return {
+        "rate": sat_m["rate"], "seconds": sat_m["seconds"], "p50_ms": sat_m["p50_ms"], "p99_ms": sat_m["p99_ms"],
+        "requests": len(reqs), "rays": N, "budget_gib": budget_gib, "seg_stride": stride,
+        "spill_chunks_per_ray_estimate": per_ray[0],
         "served": served,
         "plain_tracer": {m: {"ms": v["ms"], "rate": v["rate"]} for m, v in plain.items()},
         "mixed_serving_over_fp64_serving": sat_m["rate"] / served["fp64"]["saturated"]["rate"],
         "mixed_serving_over_plain_fp64": sat_m["rate"] / plain["fp64"]["rate"],
-        "tau_identical_fp64_vs_mixed_serving": same, "tau_serving_equals_plain": equal_plain,
-        "serving_roofline": {"bound": "hbm", "achieved": serving_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": serving_gbs / HBM_PEAK_GBS, "algorithmic_bytes": alg},
+        "mixed_serving_over_best_plain_fp64": sat_m["rate"] / best_fp64,
+        "accuracy": {"tau_identical_fp64_vs_mixed_serving": same, "tau_serving_equals_plain": equal_plain,
+                     "overflow_rays": sat_m["status_counts"][vrt.RAY_OVERFLOW] +
+                     served["fp64"]["saturated"]["status_counts"][vrt.RAY_OVERFLOW]},
+        "roofline": {"bound": "hbm", "achieved": serving_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": serving_gbs / HBM_PEAK_GBS, "algorithmic_bytes": alg},
+    }
+
+
+def serving_precision(args, torch, vrt, workloads):
+    """The serving_precision workload on its own line; value = the mixed
+    serving rate (saturated)."""
+    r = serving_precision_result(torch, vrt, workloads, args.requests, args.budget_gib)
+    result = {
+        "metric": METRIC, "value": r["rate"], "unit": "crossings/s", "n_gpus": 1, "steps": r["requests"],
+        "warmup": 1, "ms_per_step": r["seconds"] * 1e3 / r["requests"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serving precision: {r['requests']} requests of 256-65536 rays ({r['rays']} rays) "
+                               f"on the 1e6-site flared disc, all submitted at once, mixed vs FP64, whole paths, "
+                               f"{args.budget_gib:g} GiB output budget",
+                   "requests": r["requests"], "rays": r["rays"], "budget_gib": args.budget_gib},
+        "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+        "serving_roofline": r["roofline"],
+        **{k: v for k, v in r.items() if k not in ("rate", "seconds", "p50_ms", "p99_ms", "roofline")},
     }
     print(json.dumps(result), flush=True)
 

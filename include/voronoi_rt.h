@@ -346,9 +346,15 @@ vor_status vor_exclusive_scan(const int32_t *counts, int64_t N, int64_t *offsets
  * retire. A request is complete as soon as its own rays are (the kernel
  * raises a flag in host memory), not when its launch ends. Every ray is
  * computed by the same code as vor_trace, so its result does not depend on
- * the other requests. Paths follow Sect. 2.2 as in vor_trace; segments go to
- * a fixed window of seg_stride slots per ray (longer paths report
- * VOR_RAY_OVERFLOW with their full count and tau).
+ * the other requests. Paths follow Sect. 2.2 as in vor_trace and are whole
+ * (every cell to the wall): a ray's first seg_stride segments go to its
+ * window and the rest to a chain of spill chunks of VOR_SPILL_CHUNK slots
+ * from the request's own pool of spill_chunks chunks, taken as the path
+ * grows. If the pool runs out for some ray, the request is traced again,
+ * ahead of every waiting request, with exactly the chunks its segment counts
+ * need (the paths are the same, so the second run cannot run out); its
+ * results are those of that run. vor_server_copy_result returns the paths
+ * as compact rows.
  * ------------------------------------------------------------------------- */
 typedef struct vor_server vor_server;
 
@@ -363,6 +369,7 @@ typedef struct {
     int64_t budget_bytes;      /* output memory budget */
     int64_t used_bytes;        /* held by admitted, unreleased requests */
     double uptime_s;
+    int64_t reruns;            /* requests traced a second time because their spill chunks ran out */
 } vor_server_stats;
 
 /* Create a server over n_grids built grids (host array of handles; the grids
@@ -376,19 +383,27 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
  * VOR_MODE_*, optionally or'ed with VOR_SERVE_GRID_DENSITY (then density
  * must be NULL and the grid must hold a bound density when the request is
  * submitted; rebinding it before the request is done is not allowed),
- * seg_stride segment slots per ray (0 = tau only). The inputs are borrowed
- * until the request is done. *req_id receives its handle. VOR_EINVAL for a
- * bad argument; VOR_EBUDGET if its outputs could never fit in the budget. */
+ * seg_stride segment slots per ray (0 = tau only) and a first pool of
+ * spill_chunks chunks for the segments past the windows (0 with seg_stride
+ * 0; a pool too small costs a second run of the request, not segments).
+ * The request is traced only after the work enqueued on `stream` (the
+ * submitter's stream, a hipStream_t; NULL = the null stream) before this
+ * call, so inputs still being written there are waited for. The inputs are
+ * borrowed until the request is done. *req_id receives its handle.
+ * VOR_EINVAL for a bad argument; VOR_EBUDGET if its outputs could never fit
+ * in the budget (the first pool counts; a second run whose exact pool does
+ * not fit ends the request with VOR_EBUDGET from vor_server_wait). */
 vor_status vor_server_submit(vor_server *srv, int32_t grid, const double *origins, const double *dirs, int64_t n,
                              const double *density, double kappa, int32_t mode, int64_t seg_stride,
-                             int64_t *req_id);
+                             int64_t spill_chunks, void *stream, int64_t *req_id);
 
 /* *done = 1 once the request's outputs are complete; they are then visible
  * to work on any stream and to copies to the host, even while the launch
  * that computed them is still running. */
 vor_status vor_server_poll(vor_server *srv, int64_t req_id, int32_t *done);
 
-/* Block until the request is done or timeout_s passes (VOR_ETIMEOUT). */
+/* Block until the request is done or timeout_s passes (VOR_ETIMEOUT).
+ * Returns the request's own error once it is done (VOR_OK normally). */
 vor_status vor_server_wait(vor_server *srv, int64_t req_id, double timeout_s);
 
 /* Completion queue: *req_id receives the next request that has completed
@@ -396,17 +411,23 @@ vor_status vor_server_wait(vor_server *srv, int64_t req_id, double timeout_s);
  * timeout_s (VOR_ETIMEOUT, *req_id = 0, if none completes). */
 vor_status vor_server_next_done(vor_server *srv, double timeout_s, int64_t *req_id);
 
-/* Device pointers of a finished request's outputs (tau, n_seg, status,
- * seg_cell, seg_len with seg_stride; server-owned until release) and its
- * latency from submission to completion in seconds. */
+/* Device pointers of a finished request's outputs (tau, n_seg, status; with
+ * seg_stride the windows seg_cell/seg_len and the spill chain spill_first,
+ * spill_next, spill_cell, spill_len, spill_chunks, laid out as in
+ * vor_trace_out; server-owned until release) and its latency from
+ * submission to completion in seconds. */
 vor_status vor_server_result(vor_server *srv, int64_t req_id, vor_trace_out *out, double *latency_s);
 
 /* Copy a finished request's outputs into caller buffers (device; any may be
- * NULL; seg_cell/seg_len hold n * seg_stride entries), asynchronously on
- * `stream`. A later vor_server_release waits for these copies: the memory
+ * NULL), asynchronously on `stream`: tau, n_seg, status (n each) and, for a
+ * request with segments, the whole paths as compact rows -- ray i's
+ * segments at [ray_off[i], ray_off[i] + n_seg[i]) of seg_cell/seg_len, with
+ * ray_off (device, n + 1 int64) the exclusive scan of the request's counts
+ * (vor_exclusive_scan of n_seg) and seg_cell/seg_len holding ray_off[n]
+ * entries. A later vor_server_release waits for these copies: the memory
  * returns to the budget only once they have run. */
 vor_status vor_server_copy_result(vor_server *srv, int64_t req_id, double *tau, int32_t *n_seg, uint8_t *status,
-                                  int32_t *seg_cell, double *seg_len, void *stream);
+                                  const int64_t *ray_off, int32_t *seg_cell, double *seg_len, void *stream);
 
 /* Return a finished request's outputs to the budget: at once, or, if copies
  * from vor_server_copy_result are still running, as soon as the last of them

@@ -57,8 +57,17 @@ struct ReqDev {
     int32_t *seg_cell;
     double *seg_len;
     int64_t seg_stride;
+    SpillPool spill;      // the request's spill chunks (seg_stride > 0): paths longer than the window continue there
     int32_t *remaining;   // chunks of the request not yet complete (device memory)
-    int32_t *done;        // completion flag (host memory, device address)
+    int32_t *overflow;    // rays whose spill chunks ran out (device memory)
+    int32_t *done;        // completion flag (host memory, device address): 1 complete, 2 rerun with exact spill
+};
+
+// Per-request counters of a launch, zeroed when it starts.
+struct ReqCount {
+    unsigned long long spill_head;   // spill chunks handed out
+    int32_t overflow;
+    int32_t pad;
 };
 
 struct ChunkDev {
@@ -79,13 +88,20 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // Every ray of chunk slot's request chunk has been written by this wave:
 // make the writes visible device-wide, count the chunk off its request, and
 // the wave that completes the request's last chunk raises its flag in host
-// memory (release at system scope, so the flag is seen after the data).
+// memory (release at system scope, so the flag is seen after the data): 1
+// when every path is whole, 2 when some ray found its request's spill
+// chunks used up (the host then runs the request again with exactly the
+// chunks its counts need). The overflow counts of other waves are ordered
+// before their chunk counts, which this wave's fetch-add acquires.
 __device__ __forceinline__ void chunk_complete(const ReqDev *__restrict__ reqs, int q)
 {
     __threadfence();
     if ((threadIdx.x & 63) == 0) {
         const int prev = __hip_atomic_fetch_add(reqs[q].remaining, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == 1) __hip_atomic_store(reqs[q].done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (prev == 1) {
+            const int ovf = __hip_atomic_load(reqs[q].overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(reqs[q].done, ovf ? 2 : 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 
@@ -180,11 +196,12 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     cellp = rq.seg_cell;
                     lenp = rq.seg_len;
                     vec = !rq.seg_cell ? 0 : rq.seg_stride % 16 == 0 ? 2 : rq.seg_stride % 8 == 0 ? 1 : 0;
+                    if (rq.spill.first) rq.spill.first[ray] = -1;   // no chunk yet (taking one overwrites it)
                     S = RayStats();
                     double s0;
                     R.st = ray_setup<false>(G, rq.in, ray, R.r0, R.k, R.L, s0);
                     R.tau = 0.0;
-                    R.chunk = -1;
+                    R.chunk = rq.seg_cell ? -1 : -2;   // tau only: no spill chunk is ever taken
                     R.ray = (int32_t)ray;
                     R.base = ray * rq.seg_stride;
                     R.cap = rq.seg_cell ? rq.seg_stride : 0;
@@ -215,14 +232,18 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
             O.cell = cellp;
             O.len = lenp;
             O.vec = vec;
-            const bool more = (ctx & 1) ? ray_step<VOR_MODE_MIXED, true, false, false, false>(G, I, R, S, O)
-                                        : ray_step<VOR_MODE_FP64, true>(G, I, R, S, O);
+            O.pool = &reqs[q].spill;
+            const bool more = (ctx & 1) ? ray_step<VOR_MODE_MIXED, true, false, false, false, true>(G, I, R, S, O)
+                                        : ray_step<VOR_MODE_FP64, true, false, false, true, true>(G, I, R, S, O);
             if (!more) {
-                if (ctx & 1) finish_segments<cells_per_store<VOR_MODE_MIXED, false, false>(), lens_per_store<VOR_MODE_MIXED, false, false>()>(
+                if (ctx & 1) finish_segments<cells_per_store<VOR_MODE_MIXED, false, false>(), lens_per_store<VOR_MODE_MIXED, false, false>(), true>(
                     O, R, S.cnt);
-                else finish_segments<cells_per_store<VOR_MODE_FP64, false>(), lens_per_store<VOR_MODE_FP64, false>()>(O, R, S.cnt);
-                if (R.cap > 0 && R.st == RAY_OK && S.cnt > R.cap) R.st = RAY_OVERFLOW;
+                else finish_segments<cells_per_store<VOR_MODE_FP64, false>(), lens_per_store<VOR_MODE_FP64, false>(), true>(O, R, S.cnt);
                 const ReqDev &rq = reqs[q];
+                if (R.cap > 0 && R.st == RAY_OK && S.cnt > R.cap && R.chunk == -2) {   // its spill chunks ran out
+                    R.st = RAY_OVERFLOW;
+                    atomicAdd(rq.overflow, 1);
+                }
                 rq.tau[ray] = R.tau;
                 rq.n_seg[ray] = S.cnt;
                 rq.status[ray] = R.st;
@@ -254,10 +275,44 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
     }
 }
 
-__global__ void k_zero_launch(unsigned int *head, unsigned long long *counters)
+__global__ void k_zero_launch(unsigned int *head, unsigned long long *counters, ReqCount *rc, int n_req)
 {
     if (threadIdx.x == 0) *head = 0;
     if (threadIdx.x < 4) counters[threadIdx.x] = 0;
+    for (int q = threadIdx.x; q < n_req; q += blockDim.x) rc[q] = ReqCount{0ull, 0, 0};
+}
+
+// Whole paths of a request into compact rows (Sect. 2.2: a path is every
+// cell to the wall): ray i's segments, from its window and then its chain
+// of spill chunks, go to [ray_off[i], ray_off[i] + n_seg[i]).
+__global__ void __launch_bounds__(256) k_gather_paths(const int32_t *__restrict__ n_seg, int64_t n,
+                                                      const int32_t *__restrict__ wcell,
+                                                      const double *__restrict__ wlen, int64_t stride,
+                                                      const int64_t *__restrict__ first,
+                                                      const int32_t *__restrict__ next,
+                                                      const int32_t *__restrict__ pcell,
+                                                      const double *__restrict__ plen,
+                                                      const int64_t *__restrict__ ray_off, int32_t *__restrict__ cell,
+                                                      double *__restrict__ len)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t cnt = n_seg[i];
+    const int64_t o = ray_off[i];
+    const int64_t w = cnt < stride ? cnt : stride;
+    for (int64_t j = 0; j < w; ++j) {
+        cell[o + j] = wcell[i * stride + j];
+        len[o + j] = wlen[i * stride + j];
+    }
+    int64_t c = cnt > stride ? first[i] : -1;
+    for (int64_t j = w; j < cnt && c >= 0; j += kSpillChunk) {
+        const int64_t e = (cnt - j) < kSpillChunk ? (cnt - j) : kSpillChunk;
+        for (int64_t t = 0; t < e; ++t) {
+            cell[o + j + t] = pcell[c * kSpillChunk + t];
+            len[o + j + t] = plen[c * kSpillChunk + t];
+        }
+        c = next[c];
+    }
 }
 
 using clk = std::chrono::steady_clock;
@@ -271,9 +326,12 @@ struct Request {
     int64_t n = 0;
     RayIn in{};
     int64_t seg_stride = 0;
+    int64_t spill_chunks = 0;
     size_t bytes = 0;
     size_t off = 0;   // arena offset
     ReqState state = Q_WAIT;
+    vor_status err = VOR_OK;
+    int runs = 0;     // launches that traced the request (2 when its spill chunks were sized again)
     clk::time_point t_submit, t_admit, t_done;
     // device outputs (in the arena)
     double *tau = nullptr;
@@ -281,6 +339,11 @@ struct Request {
     uint8_t *status = nullptr;
     int32_t *seg_cell = nullptr;
     double *seg_len = nullptr;
+    int64_t *spill_first = nullptr;
+    int32_t *spill_next = nullptr;
+    int32_t *spill_cell = nullptr;
+    double *spill_len = nullptr;
+    hipEvent_t ready = nullptr;    // recorded on the submitter's stream: the inputs are written
     hipEvent_t copied = nullptr;   // recorded after the caller's last vor_server_copy_result
 };
 
@@ -302,6 +365,7 @@ struct Launch {
     ReqDev *h_reqs = nullptr, *d_reqs = nullptr;
     ChunkDev *h_chunks = nullptr, *d_chunks = nullptr;
     int32_t *h_remaining = nullptr, *d_remaining = nullptr;
+    ReqCount *d_count = nullptr;                      // per-request spill counter and overflow count
     int32_t *h_flags = nullptr, *d_flags = nullptr;   // host memory, mapped for the device
     unsigned int *d_head = nullptr;
     unsigned long long *d_counters = nullptr;
@@ -310,10 +374,18 @@ struct Launch {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t request_bytes(int64_t n, int64_t stride)
+// Output memory of a request: tau, counts and statuses; with a window of
+// `stride` slots per ray also the windows, the first spill chunk of every
+// ray and `chunks` spill chunks (links, cells, lengths).
+size_t request_bytes(int64_t n, int64_t stride, int64_t chunks)
 {
     size_t b = align_up(n * sizeof(double)) + align_up(n * sizeof(int32_t)) + align_up(n);
-    if (stride > 0) b += align_up((size_t)n * stride * sizeof(int32_t)) + align_up((size_t)n * stride * sizeof(double));
+    if (stride > 0) {
+        b += align_up((size_t)n * stride * sizeof(int32_t)) + align_up((size_t)n * stride * sizeof(double));
+        b += align_up((size_t)n * sizeof(int64_t)) + align_up((size_t)chunks * sizeof(int32_t)) +
+             align_up((size_t)chunks * kSpillChunk * sizeof(int32_t)) +
+             align_up((size_t)chunks * kSpillChunk * sizeof(double));
+    }
     return b;
 }
 
@@ -337,8 +409,12 @@ struct vor_server {
     int device = 0;
     int blocks = 1;
     vor_status fault = VOR_OK;
+    hipStream_t aux = nullptr;   // the scheduler's own copies (segment counts of requests run again)
+    int32_t *h_counts = nullptr; // staging for those counts
+    int64_t h_counts_len = 0;
     // statistics
     int64_t n_done = 0;
+    int64_t reruns = 0;
     unsigned long long crossings = 0, redecisions = 0, fallbacks = 0;
     int64_t launches_done = 0;
     int launches_running = 0;
@@ -399,6 +475,14 @@ struct vor_server {
                 r.seg_cell = (int32_t *)p;
                 p += align_up((size_t)r.n * r.seg_stride * sizeof(int32_t));
                 r.seg_len = (double *)p;
+                p += align_up((size_t)r.n * r.seg_stride * sizeof(double));
+                r.spill_first = (int64_t *)p;
+                p += align_up((size_t)r.n * sizeof(int64_t));
+                r.spill_next = (int32_t *)p;
+                p += align_up((size_t)r.spill_chunks * sizeof(int32_t));
+                r.spill_cell = (int32_t *)p;
+                p += align_up((size_t)r.spill_chunks * kSpillChunk * sizeof(int32_t));
+                r.spill_len = (double *)p;
             }
             r.state = Q_ADMITTED;
             r.t_admit = clk::now();
@@ -455,8 +539,12 @@ struct vor_server {
             d.seg_cell = r.seg_cell;
             d.seg_len = r.seg_len;
             d.seg_stride = r.seg_stride;
+            d.spill = SpillPool{r.spill_cell, r.spill_len, r.spill_next, r.spill_first, r.spill_chunks,
+                                &L.d_count[q].spill_head};
             d.remaining = L.d_remaining + q;
+            d.overflow = &L.d_count[q].overflow;
             d.done = L.d_flags + q;
+            ++r.runs;
             L.h_remaining[q] = need;
             L.h_flags[q] = 0;
             const int32_t ctx = 4 * r.grid + 2 * r.in.grid_rho + (r.mode == VOR_MODE_MIXED ? 1 : 0);
@@ -472,11 +560,17 @@ struct vor_server {
         const int nreq = (int)L.reqs.size();
         L.seen.assign(nreq, 0);
         L.open = nreq;
-        bool ok = hipMemcpyAsync(L.d_reqs, L.h_reqs, sizeof(ReqDev) * nreq, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
+        bool ok = true;
+        // the launch starts once every request's inputs are written on its submitter's stream
+        for (int64_t id : L.reqs) {
+            Request &r = reqs[id];
+            if (r.ready) ok = ok && hipStreamWaitEvent(L.stream, r.ready, 0) == hipSuccess;
+        }
+        ok = ok && hipMemcpyAsync(L.d_reqs, L.h_reqs, sizeof(ReqDev) * nreq, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
                   hipMemcpyAsync(L.d_chunks, L.h_chunks, sizeof(ChunkDev) * nch, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
                   hipMemcpyAsync(L.d_remaining, L.h_remaining, sizeof(int32_t) * nreq, hipMemcpyHostToDevice,
                                  L.stream) == hipSuccess;
-        hipLaunchKernelGGL(k_zero_launch, dim3(1), dim3(64), 0, L.stream, L.d_head, L.d_counters);
+        hipLaunchKernelGGL(k_zero_launch, dim3(1), dim3(256), 0, L.stream, L.d_head, L.d_counters, L.d_count, nreq);
         int nb = std::max(1, std::min(blocks, (nch + 3) / 4));
         hipLaunchKernelGGL(k_serve, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks, nch, L.d_head,
                            L.d_counters);
@@ -499,6 +593,59 @@ struct vor_server {
         done_queue.push_back(id);
     }
 
+    // A request some of whose rays found its spill chunks used up: every ray
+    // has its full segment count, so the chunks its paths need are known
+    // exactly. Its outputs go back to the budget and it waits again, at the
+    // head of the queue, with that many chunks; the second run cannot run
+    // out (the paths are the same). A request whose exact need exceeds the
+    // budget ends with VOR_EBUDGET.
+    void rerun_locked(int64_t id, clk::time_point now)
+    {
+        auto it = reqs.find(id);
+        if (it == reqs.end() || it->second.state != Q_RUNNING) return;
+        Request &r = it->second;
+        int64_t need = 0;
+        if (h_counts_len < r.n) {
+            if (h_counts) (void)hipHostFree(h_counts);
+            h_counts = nullptr;
+            h_counts_len = 0;
+            if (hipHostMalloc((void **)&h_counts, sizeof(int32_t) * r.n, hipHostMallocDefault) != hipSuccess) {
+                fault = VOR_ENOMEM;
+                return;
+            }
+            h_counts_len = r.n;
+        }
+        if (hipMemcpyAsync(h_counts, r.n_seg, sizeof(int32_t) * r.n, hipMemcpyDeviceToHost, aux) != hipSuccess ||
+            hipStreamSynchronize(aux) != hipSuccess) {
+            fault = VOR_EDEVICE;
+            return;
+        }
+        for (int64_t i = 0; i < r.n; ++i)
+            if (h_counts[i] > r.seg_stride) need += (h_counts[i] - r.seg_stride + kSpillChunk - 1) / kSpillChunk;
+        arena_free(r.off, r.bytes);
+        r.spill_chunks = need;
+        r.bytes = request_bytes(r.n, r.seg_stride, need);
+        r.tau = nullptr;
+        r.n_seg = nullptr;
+        r.status = nullptr;
+        r.seg_cell = nullptr;
+        r.seg_len = nullptr;
+        r.spill_first = nullptr;
+        r.spill_next = nullptr;
+        r.spill_cell = nullptr;
+        r.spill_len = nullptr;
+        ++reruns;
+        if (r.bytes > budget) {
+            r.err = VOR_EBUDGET;
+            r.bytes = 0;
+            r.state = Q_RUNNING;   // so that mark_done_locked takes it
+            mark_done_locked(id, now);
+            return;
+        }
+        r.state = Q_WAIT;
+        waiting.push_front(id);
+    }
+
     // Requests whose flag the kernel has raised. Returns true if any.
     bool poll_flags_locked(Launch &L)
     {
@@ -507,10 +654,12 @@ struct vor_server {
         const auto now = clk::now();
         for (size_t q = 0; q < L.reqs.size(); ++q) {
             if (L.seen[q]) continue;
-            if (__atomic_load_n(&L.h_flags[q], __ATOMIC_ACQUIRE) != 0) {
+            const int32_t f = __atomic_load_n(&L.h_flags[q], __ATOMIC_ACQUIRE);
+            if (f != 0) {
                 L.seen[q] = 1;
                 --L.open;
-                mark_done_locked(L.reqs[q], now);
+                if (f == 2) rerun_locked(L.reqs[q], now);
+                else mark_done_locked(L.reqs[q], now);
                 any = true;
             }
         }
@@ -535,7 +684,8 @@ struct vor_server {
         return any;
     }
 
-    // The launch's kernel has ended: every request in it is complete.
+    // The launch's kernel has ended: every request in it is complete (the
+    // flags of all of them are visible now).
     void complete_locked(Launch &L)
     {
         poll_flags_locked(L);
@@ -628,11 +778,13 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
                            hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
              hipHostGetDevicePointer((void **)&L.d_flags, L.h_flags, 0) == hipSuccess &&
              hipMalloc(&L.d_remaining, sizeof(int32_t) * kMaxLaunchReqs) == hipSuccess &&
+             hipMalloc(&L.d_count, sizeof(ReqCount) * kMaxLaunchReqs) == hipSuccess &&
              hipMalloc(&L.d_reqs, sizeof(ReqDev) * kMaxLaunchReqs) == hipSuccess &&
              hipMalloc(&L.d_chunks, sizeof(ChunkDev) * kMaxLaunchChunks) == hipSuccess &&
              hipMalloc(&L.d_head, sizeof(unsigned int)) == hipSuccess &&
              hipMalloc(&L.d_counters, 4 * sizeof(unsigned long long)) == hipSuccess;
     }
+    ok = ok && hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking) == hipSuccess;
     int cus = 0, per_cu = 0;
     ok = ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess &&
          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve, 256, 0) == hipSuccess;
@@ -650,19 +802,31 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
 }
 
 vor_status vor_server_submit(vor_server *S, int32_t grid, const double *origins, const double *dirs, int64_t n,
-                             const double *density, double kappa, int32_t mode, int64_t seg_stride, int64_t *req_id)
+                             const double *density, double kappa, int32_t mode, int64_t seg_stride,
+                             int64_t spill_chunks, void *stream, int64_t *req_id)
 {
     if (req_id) *req_id = 0;
     const bool grid_rho = (mode & VOR_SERVE_GRID_DENSITY) != 0;
     mode &= ~VOR_SERVE_GRID_DENSITY;
     if (!S || !req_id || grid < 0 || grid >= (int32_t)S->grid_refs.size() || n < 1 || n > 0x7fffffffLL ||
-        !origins || !dirs || seg_stride < 0 || (mode != VOR_MODE_FP64 && mode != VOR_MODE_MIXED))
+        !origins || !dirs || seg_stride < 0 || (mode != VOR_MODE_FP64 && mode != VOR_MODE_MIXED) ||
+        spill_chunks < 0 || spill_chunks > 0x7fffffffLL || (seg_stride == 0 && spill_chunks != 0))
         return VOR_EINVAL;
     if (grid_rho && (density || !vrt_grid_of(S->grids[grid]).rho_bound)) return VOR_EINVAL;
-    size_t bytes = request_bytes(n, seg_stride);
+    size_t bytes = request_bytes(n, seg_stride, spill_chunks);
     if (bytes > S->budget) return VOR_EBUDGET;
+    // the launch that traces the request waits for what the submitter's stream has enqueued so far
+    hipEvent_t ready = nullptr;
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return VOR_EDEVICE;
+    if (hipEventRecord(ready, (hipStream_t)stream) != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        return VOR_EDEVICE;
+    }
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->fault != VOR_OK) return S->fault;
+    if (S->fault != VOR_OK) {
+        (void)hipEventDestroy(ready);
+        return S->fault;
+    }
     Request r;
     r.id = S->next_id++;
     r.grid = grid;
@@ -675,7 +839,9 @@ vor_status vor_server_submit(vor_server *S, int32_t grid, const double *origins,
     r.in.enter = 0;
     r.in.grid_rho = grid_rho ? 1 : 0;
     r.seg_stride = seg_stride;
+    r.spill_chunks = spill_chunks;
     r.bytes = bytes;
+    r.ready = ready;
     r.t_submit = clk::now();
     S->reqs[r.id] = r;
     S->waiting.push_back(r.id);
@@ -702,11 +868,11 @@ vor_status vor_server_wait(vor_server *S, int64_t req, double timeout_s)
     for (;;) {
         auto it = S->reqs.find(req);
         if (it == S->reqs.end() || it->second.state == Q_RELEASED) return VOR_EINVAL;
-        if (it->second.state == Q_DONE) return VOR_OK;
+        if (it->second.state == Q_DONE) return it->second.err;
         if (S->fault != VOR_OK) return S->fault;
         if (S->cv.wait_until(lk, deadline) == std::cv_status::timeout && clk::now() >= deadline) {
             auto it2 = S->reqs.find(req);
-            return (it2 != S->reqs.end() && it2->second.state == Q_DONE) ? VOR_OK : VOR_ETIMEOUT;
+            return (it2 != S->reqs.end() && it2->second.state == Q_DONE) ? it2->second.err : VOR_ETIMEOUT;
         }
     }
 }
@@ -740,6 +906,8 @@ vor_status vor_server_result(vor_server *S, int64_t req, vor_trace_out *out, dou
     auto it = S->reqs.find(req);
     if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
     const Request &r = it->second;
+    if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
+    if (r.err != VOR_OK) return r.err;
     *out = vor_trace_out{};
     out->tau = r.tau;
     out->n_seg = r.n_seg;
@@ -747,27 +915,35 @@ vor_status vor_server_result(vor_server *S, int64_t req, vor_trace_out *out, dou
     out->seg_cell = r.seg_cell;
     out->seg_len = r.seg_len;
     out->seg_stride = r.seg_stride;
-    if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
+    out->spill_first = r.spill_first;
+    out->spill_next = r.spill_next;
+    out->spill_cell = r.spill_cell;
+    out->spill_len = r.spill_len;
+    out->spill_chunks = r.spill_chunks;
     return VOR_OK;
 }
 
 vor_status vor_server_copy_result(vor_server *S, int64_t req, double *tau, int32_t *n_seg, uint8_t *status,
-                                  int32_t *seg_cell, double *seg_len, void *stream)
+                                  const int64_t *ray_off, int32_t *seg_cell, double *seg_len, void *stream)
 {
     if (!S) return VOR_EINVAL;
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->reqs.find(req);
     if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
     Request &r = it->second;
+    if (r.err != VOR_OK) return r.err;
+    if ((seg_cell || seg_len) && (!seg_cell || !seg_len || !ray_off || r.seg_stride <= 0)) return VOR_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     bool ok = r.copied || hipEventCreateWithFlags(&r.copied, hipEventDisableTiming) == hipSuccess;
     if (tau) ok = ok && hipMemcpyAsync(tau, r.tau, r.n * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
     if (n_seg) ok = ok && hipMemcpyAsync(n_seg, r.n_seg, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, st) == hipSuccess;
     if (status) ok = ok && hipMemcpyAsync(status, r.status, r.n, hipMemcpyDeviceToDevice, st) == hipSuccess;
-    if (r.seg_stride > 0) {
-        size_t ns = (size_t)r.n * r.seg_stride;
-        if (seg_cell) ok = ok && hipMemcpyAsync(seg_cell, r.seg_cell, ns * sizeof(int32_t), hipMemcpyDeviceToDevice, st) == hipSuccess;
-        if (seg_len) ok = ok && hipMemcpyAsync(seg_len, r.seg_len, ns * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
+    if (seg_cell) {
+        const int T = 256;
+        hipLaunchKernelGGL(k_gather_paths, dim3((unsigned)((r.n + T - 1) / T)), dim3(T), 0, st, r.n_seg, r.n, r.seg_cell,
+                           r.seg_len, r.seg_stride, r.spill_first, r.spill_next, r.spill_cell, r.spill_len, ray_off,
+                           seg_cell, seg_len);
+        ok = ok && hipGetLastError() == hipSuccess;
     }
     ok = ok && hipEventRecord(r.copied, st) == hipSuccess;   // release waits for this
     return ok ? VOR_OK : VOR_EDEVICE;
@@ -779,12 +955,15 @@ vor_status vor_server_release(vor_server *S, int64_t req)
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->reqs.find(req);
     if (it == S->reqs.end() || it->second.state != Q_DONE) return VOR_EINVAL;
-    if (it->second.copied && hipEventQuery(it->second.copied) != hipSuccess) {
+    if (it->second.bytes == 0) {   // ended with an error: holds no memory
+        if (it->second.copied) (void)hipEventDestroy(it->second.copied);
+    } else if (it->second.copied && hipEventQuery(it->second.copied) != hipSuccess) {
         S->pending_frees.push_back(PendingFree{it->second.copied, it->second.off, it->second.bytes});
     } else {
         if (it->second.copied) (void)hipEventDestroy(it->second.copied);
         S->arena_free(it->second.off, it->second.bytes);
     }
+    if (it->second.ready) (void)hipEventDestroy(it->second.ready);
     S->reqs.erase(it);
     // ids of released requests are skipped by vor_server_next_done; drop
     // them once they make up most of its queue (callers that only wait/poll)
@@ -812,6 +991,7 @@ vor_status vor_server_get_stats(vor_server *S, vor_server_stats *st)
     st->budget_bytes = (int64_t)S->budget;
     st->used_bytes = (int64_t)S->used;
     st->uptime_s = std::chrono::duration<double>(clk::now() - S->t0).count();
+    st->reruns = S->reruns;
     return S->fault;
 }
 
@@ -833,6 +1013,7 @@ void vor_server_destroy(vor_server *S)
         if (L.h_remaining) (void)hipHostFree(L.h_remaining);
         if (L.h_flags) (void)hipHostFree(L.h_flags);
         if (L.d_remaining) (void)hipFree(L.d_remaining);
+        if (L.d_count) (void)hipFree(L.d_count);
         if (L.d_reqs) (void)hipFree(L.d_reqs);
         if (L.d_chunks) (void)hipFree(L.d_chunks);
         if (L.d_head) (void)hipFree(L.d_head);
@@ -843,11 +1024,18 @@ void vor_server_destroy(vor_server *S)
         (void)hipEventSynchronize(f.copied);
         (void)hipEventDestroy(f.copied);
     }
-    for (auto &kv : S->reqs)
+    for (auto &kv : S->reqs) {
         if (kv.second.copied) {
             (void)hipEventSynchronize(kv.second.copied);
             (void)hipEventDestroy(kv.second.copied);
         }
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+    }
+    if (S->aux) {
+        (void)hipStreamSynchronize(S->aux);
+        (void)hipStreamDestroy(S->aux);
+    }
+    if (S->h_counts) (void)hipHostFree(S->h_counts);
     if (S->arena) (void)hipFree(S->arena);
     if (S->d_grids) (void)hipFree(S->d_grids);
     delete S;

@@ -52,6 +52,18 @@ constexpr int kSpillChunk = VOR_SPILL_CHUNK;
 #define VRT_NT_STORE 1
 #endif
 
+// A pool of spill chunks read from memory by the lane that needs it: in the
+// serving kernel the lanes of one wave may hold rays of different requests,
+// each with a pool of its own (the same layout as SegOut's spill arrays).
+struct SpillPool {
+    int32_t *cell;
+    double *len;
+    int32_t *next;
+    int64_t *first;
+    int64_t chunks;
+    unsigned long long *head;
+};
+
 struct SegOut {
     int32_t *cell;                  // window slots
     double *len;
@@ -62,6 +74,7 @@ struct SegOut {
     int64_t *spill_first;           // first chunk of each ray, -1 if none
     int64_t spill_chunks;           // capacity in chunks
     unsigned long long *chunk_head; // chunks handed out
+    const SpillPool *pool;          // LP kernels: this lane's pool instead of the spill arrays above
 };
 
 // Smallest accepted eps of the mixed-mode bound (2^-20 = 16u): twice what
@@ -512,6 +525,7 @@ __device__ __forceinline__ void ray_begin_at(const GridRef &G, RayState &R, int3
 
 // Slot of segment idx of the ray: its window, else its current spill chunk;
 // null when the spill is exhausted or absent.
+template <bool LP = false>
 __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState &R, int64_t idx, bool &spill)
 {
     if (idx < R.cap) {
@@ -519,8 +533,36 @@ __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState 
         return R.base + idx;
     }
     spill = true;
-    if (!O.spill_cell || R.chunk < 0) return -1;
+    if ((!LP && !O.spill_cell) || R.chunk < 0) return -1;
     return (int64_t)R.chunk * kSpillChunk + (idx - R.cap) % kSpillChunk;
+}
+
+// The arrays a slot from segment_slot indexes.
+template <bool LP>
+__device__ __forceinline__ int32_t *slot_cells(const SegOut &O, bool spill)
+{
+    return spill ? (LP ? O.pool->cell : O.spill_cell) : O.cell;
+}
+template <bool LP>
+__device__ __forceinline__ double *slot_lens(const SegOut &O, bool spill)
+{
+    return spill ? (LP ? O.pool->len : O.spill_len) : O.len;
+}
+
+// A new spill chunk for the ray from this lane's own pool (LP kernels):
+// chunks are taken one at a time by atomics on the pool's counter, lanes of
+// a wave serving different pools. -2 when the pool has run out.
+__device__ __forceinline__ void take_pool_chunk(const SpillPool *pool, RayState &R)
+{
+    const unsigned long long c = atomicAdd(pool->head, 1ull);
+    if ((int64_t)c < pool->chunks) {
+        pool->next[c] = -1;
+        if (R.chunk < 0) pool->first[R.ray] = (int64_t)c;
+        else pool->next[R.chunk] = (int32_t)c;
+        R.chunk = (int32_t)c;
+    } else {
+        R.chunk = -2;
+    }
 }
 
 // Store segment number idx of the ray: in its window, else in its spill
@@ -559,10 +601,12 @@ __device__ __forceinline__ void put16(V v, V *p)
 #endif
 }
 
-template <int CG, int LG>
+template <int CG, int LG, bool LP = false>
 __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int64_t idx, int32_t cell, double len)
 {
-    if (idx >= R.cap && O.spill_cell) {
+    if (LP) {
+        if (idx >= R.cap && ((idx - R.cap) % kSpillChunk) == 0 && R.chunk != -2) take_pool_chunk(O.pool, R);
+    } else if (idx >= R.cap && O.spill_cell) {
         const int64_t k = idx - R.cap;
         const bool need = (k % kSpillChunk) == 0 && R.chunk != -2;
         const uint64_t bal = __ballot(need);
@@ -630,10 +674,10 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
         }
         if (LG == 8 && (idx & 7) == 7) {
             bool spill;
-            const int64_t p = segment_slot(O, R, idx - 7, spill);
+            const int64_t p = segment_slot<LP>(O, R, idx - 7, spill);
             if (p >= 0) {
-                v2d *lp = reinterpret_cast<v2d *>((spill ? O.spill_len : O.len) + p);
-                v4i *cp = reinterpret_cast<v4i *>((spill ? O.spill_cell : O.cell) + p);
+                v2d *lp = reinterpret_cast<v2d *>(slot_lens<LP>(O, spill) + p);
+                v4i *cp = reinterpret_cast<v4i *>(slot_cells<LP>(O, spill) + p);
                 put16(v2d{R.l0, R.l1}, lp);
                 put16(v2d{R.l2, R.l3}, lp + 1);
                 put16(v2d{R.l4, R.l5}, lp + 2);
@@ -654,10 +698,10 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
         }
         if (LG == 4 && (idx & 3) == 3) {
             bool spill;
-            const int64_t p = segment_slot(O, R, idx - 3, spill);   // groups of 8 never cross a window or chunk end
+            const int64_t p = segment_slot<LP>(O, R, idx - 3, spill);   // groups of 8 never cross a window or chunk end
             if (p >= 0) {
-                int32_t *cp = (spill ? O.spill_cell : O.cell) + p;
-                v2d *lp = reinterpret_cast<v2d *>((spill ? O.spill_len : O.len) + p);
+                int32_t *cp = slot_cells<LP>(O, spill) + p;
+                v2d *lp = reinterpret_cast<v2d *>(slot_lens<LP>(O, spill) + p);
                 put16(v2d{R.l0, R.l1}, lp);
                 put16(v2d{R.l2, R.l3}, lp + 1);
                 if (CG == 4) {
@@ -672,15 +716,15 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
     }
 #endif
     bool spill;
-    const int64_t p = segment_slot(O, R, idx, spill);
+    const int64_t p = segment_slot<LP>(O, R, idx, spill);
     if (p >= 0) {
-        (spill ? O.spill_cell : O.cell)[p] = cell;
-        (spill ? O.spill_len : O.len)[p] = len;
+        slot_cells<LP>(O, spill)[p] = cell;
+        slot_lens<LP>(O, spill)[p] = len;
     }
 }
 
 // Write the segments still held back when a path of n segments ends.
-template <int CG, int LG>
+template <int CG, int LG, bool LP = false>
 __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState &R, int64_t n)
 {
 #if VRT_VEC_STORE
@@ -703,10 +747,10 @@ __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState 
     for (int j = 0; j < CG - 1; ++j) {
         if (j < rc) {
             bool spill;
-            const int64_t p = segment_slot(O, R, n - rc + j, spill);
+            const int64_t p = segment_slot<LP>(O, R, n - rc + j, spill);
             if (p >= 0) {
-                (spill ? O.spill_cell : O.cell)[p] = cs[16 - rc + j];
-                if (j >= rc - rl) (spill ? O.spill_len : O.len)[p] = ls[8 - rc + j];
+                slot_cells<LP>(O, spill)[p] = cs[16 - rc + j];
+                if (j >= rc - rl) slot_lens<LP>(O, spill)[p] = ls[8 - rc + j];
             }
         }
     }
@@ -782,7 +826,7 @@ __device__ __forceinline__ void ray_extras_finish(const Extras &X, int64_t ray, 
     if (X.stop_s) X.stop_s[ray] = R.stop_uid >= 0 ? R.stop_s : R.L;
 }
 
-template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false, bool WIDE = true>
+template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false, bool WIDE = true, bool LP = false>
 __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, RayState &R, RayStats &S,
                                              const SegOut &O, int win, double best, bool redo, int32_t j1,
                                              const Extras &X)
@@ -843,7 +887,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                 const double tn = R.tau + kr * len;
                 if (kr > 0.0 && tn >= R.tstop) {   // the package interacts in this cell
                     const double lp = (R.tstop - R.tau) / kr;
-                    if (SEGS) store_segment<cells_per_store<MODE, EXT, WIDE>(), lens_per_store<MODE, EXT, WIDE>()>(O, R, S.cnt, R.uid, lp);
+                    if (SEGS) store_segment<cells_per_store<MODE, EXT, WIDE>(), lens_per_store<MODE, EXT, WIDE>(), LP>(O, R, S.cnt, R.uid, lp);
                     deposit<DEFER>(X, R, lp, kr);
                     R.tau = R.tau + kr * lp;
                     ++S.cnt;
@@ -855,7 +899,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             deposit<DEFER>(X, R, len, kr);
         }
         if (has_rho) R.tau += I.kappa * rho * len;   // before the store: its wait then holds no store
-        if (SEGS) store_segment<cells_per_store<MODE, EXT, WIDE>(), lens_per_store<MODE, EXT, WIDE>()>(O, R, S.cnt, R.uid, len);
+        if (SEGS) store_segment<cells_per_store<MODE, EXT, WIDE>(), lens_per_store<MODE, EXT, WIDE>(), LP>(O, R, S.cnt, R.uid, len);
         ++S.cnt;
         R.s_c = best;
     } else if (len < -1e-9 * R.L) {
@@ -909,7 +953,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
 
 // One exit-point step (Sect. 2.2) with the exit search done by this lane
 // alone. Returns false once the path has ended.
-template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false, bool WIDE = true>
+template <int MODE, bool SEGS, bool EXT = false, bool DEFER = false, bool WIDE = true, bool LP = false>
 __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RayState &R, RayStats &S, const SegOut &O,
                                          const Extras &X = Extras{})
 {
@@ -925,7 +969,7 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
                          j1);
         S.nredo += redo ? 1 : 0;
     }
-    return ray_step_end<MODE, SEGS, EXT, DEFER, WIDE>(G, I, R, S, O, win, best, redo, j1, X);
+    return ray_step_end<MODE, SEGS, EXT, DEFER, WIDE, LP>(G, I, R, S, O, win, best, redo, j1, X);
 }
 
 }  // namespace vrt

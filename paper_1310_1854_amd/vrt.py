@@ -77,7 +77,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("crossings", ctypes.c_int64), ("fp64_redecisions", ctypes.c_int64),
                 ("fallbacks", ctypes.c_int64), ("launches", ctypes.c_int64), ("running", ctypes.c_int64),
                 ("waiting", ctypes.c_int64),
-                ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64), ("uptime_s", ctypes.c_double)]
+                ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64), ("uptime_s", ctypes.c_double),
+                ("reruns", ctypes.c_int64)]
 
 
 _lib = None
@@ -129,7 +130,7 @@ def load(path: str = None):
     lib.vor_version.restype = ctypes.c_char_p
     lib.vor_server_create.argtypes = [ctypes.POINTER(P), I32, I64, ctypes.POINTER(P)]
     lib.vor_server_create.restype = ctypes.c_int
-    lib.vor_server_submit.argtypes = [P, I32, P, P, I64, P, D, I32, I64, ctypes.POINTER(I64)]
+    lib.vor_server_submit.argtypes = [P, I32, P, P, I64, P, D, I32, I64, I64, P, ctypes.POINTER(I64)]
     lib.vor_server_submit.restype = ctypes.c_int
     lib.vor_server_poll.argtypes = [P, I64, ctypes.POINTER(I32)]
     lib.vor_server_poll.restype = ctypes.c_int
@@ -139,7 +140,7 @@ def load(path: str = None):
     lib.vor_server_next_done.restype = ctypes.c_int
     lib.vor_server_result.argtypes = [P, I64, ctypes.POINTER(TraceOut), ctypes.POINTER(D)]
     lib.vor_server_result.restype = ctypes.c_int
-    lib.vor_server_copy_result.argtypes = [P, I64, P, P, P, P, P, P]
+    lib.vor_server_copy_result.argtypes = [P, I64, P, P, P, P, P, P, P]
     lib.vor_server_copy_result.restype = ctypes.c_int
     lib.vor_server_release.argtypes = [P, I64]
     lib.vor_server_release.restype = ctypes.c_int
@@ -372,6 +373,12 @@ def n_rays(origins) -> int:
     return int(origins.shape[0])
 
 
+def _check_density(density: Optional[torch.Tensor], grid: "Grid") -> None:
+    if density is not None and (density.dtype != torch.float64 or not density.is_cuda
+                                or not density.is_contiguous() or density.numel() != grid.M):
+        raise ValueError("density must be a contiguous float64 device tensor with one value per site")
+
+
 def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: Optional[torch.Tensor],
                bufs: TraceBuffers, kappa: float = 1.0, mode: str = "fp64", max_steps: int = 0,
                eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, start_given: bool = False,
@@ -388,14 +395,16 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
     densities bound with Grid.bind_density (``density`` must be None)."""
     for name, t, size in (("tau_stop", tau_stop, n_rays(origins)), ("weight", weight, n_rays(origins)),
                           ("tally_len", tally_len, grid.M), ("tally_abs", tally_abs, grid.M)):
-        if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != size):
-            raise ValueError(f"{name} must be a contiguous float64 tensor of {size} values")
+        if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+                              or t.numel() != size):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of {size} values")
     n = origins.shape[0]
     if origins.dtype != torch.float64 or dirs.dtype != torch.float64 or not origins.is_contiguous() \
             or not dirs.is_contiguous() or origins.shape != dirs.shape or n != bufs.N:
         raise ValueError("origins/dirs must be contiguous float64 (N, 3) tensors matching the buffers")
-    if density is not None and (density.dtype != torch.float64 or density.numel() != grid.M):
-        raise ValueError("density must be float64 with one value per site")
+    if not origins.is_cuda or not dirs.is_cuda:
+        raise ValueError("origins/dirs must be device tensors")
+    _check_density(density, grid)
     if ordered:
         if bufs.order is None:
             raise ValueError("buffers were made without ordered=True")
@@ -515,18 +524,29 @@ class Server:
         self._keep = {}
 
     def submit(self, grid: int, origins: torch.Tensor, dirs: torch.Tensor, density: Optional[torch.Tensor] = None,
-               kappa: float = 1.0, mode: str = "fp64", seg_stride: int = 0, grid_density: bool = False) -> int:
+               kappa: float = 1.0, mode: str = "fp64", seg_stride: int = 0, spill_chunks: Optional[int] = None,
+               grid_density: bool = False, stream=None) -> int:
         """Queue a request; ``grid_density``: use the densities bound to the
-        grid (Grid.bind_density) instead of ``density``, which must be None."""
+        grid (Grid.bind_density) instead of ``density``, which must be None.
+        ``spill_chunks``: the first pool of spill chunks for segments past
+        the windows (None: one chunk per 8 rays); a pool too small only
+        costs a second run of the request. The request waits for the work
+        already enqueued on ``stream`` (default: the current stream)."""
         if origins.dtype != torch.float64 or dirs.dtype != torch.float64 or not origins.is_contiguous() \
-                or not dirs.is_contiguous() or origins.shape != dirs.shape:
+                or not dirs.is_contiguous() or origins.dim() != 2 or origins.shape[1] != 3 \
+                or origins.shape != dirs.shape or not origins.is_cuda or not dirs.is_cuda:
             raise ValueError("origins/dirs must be contiguous float64 (N, 3) device tensors")
+        if 0 <= grid < len(self.grids):   # (a grid that does not exist is the library's VOR_EINVAL)
+            _check_density(density, self.grids[grid])
+        n = origins.shape[0]
+        stride = int(seg_stride)
+        chunks = 0 if stride <= 0 else (n // 8 + 1 if spill_chunks is None else int(spill_chunks))
         rid = ctypes.c_int64()
         m = MODES[mode] | (SERVE_GRID_DENSITY if grid_density else 0)
-        _check(load().vor_server_submit(self._h, int(grid), _ptr(origins), _ptr(dirs), origins.shape[0],
-                                        _ptr(density), float(kappa), m, int(seg_stride),
-                                        ctypes.byref(rid)), "vor_server_submit")
-        self._keep[rid.value] = (origins, dirs, density, int(seg_stride), origins.shape[0])
+        _check(load().vor_server_submit(self._h, int(grid), _ptr(origins), _ptr(dirs), n, _ptr(density),
+                                        float(kappa), m, stride, chunks, _stream(stream), ctypes.byref(rid)),
+               "vor_server_submit")
+        self._keep[rid.value] = (origins, dirs, density, stride, n)
         return rid.value
 
     def poll(self, req: int) -> bool:
@@ -553,18 +573,28 @@ class Server:
         _check(load().vor_server_result(self._h, req, ctypes.byref(o), ctypes.byref(lat)), "vor_server_result")
         return lat.value
 
-    def result(self, req: int, stream=None) -> dict:
-        """Copy the request's outputs into new tensors."""
+    def result(self, req: int, stream=None, paths: bool = True) -> dict:
+        """Copy the request's outputs into new tensors: tau, n_seg, status
+        and, for a request with segments (unless ``paths`` is False), its
+        whole paths as compact rows (ray_off, seg_cell, seg_len: ray i's
+        segments at [ray_off[i], ray_off[i + 1]))."""
         _, _, _, stride, n = self._keep[req]
         res = dict(tau=torch.empty(n, dtype=torch.float64, device="cuda"),
                    n_seg=torch.empty(n, dtype=torch.int32, device="cuda"),
                    status=torch.empty(n, dtype=torch.uint8, device="cuda"))
-        if stride > 0:
-            res["seg_cell"] = torch.empty(n * stride, dtype=torch.int32, device="cuda")
-            res["seg_len"] = torch.empty(n * stride, dtype=torch.float64, device="cuda")
-        _check(load().vor_server_copy_result(self._h, req, _ptr(res["tau"]), _ptr(res["n_seg"]), _ptr(res["status"]),
-                                             _ptr(res.get("seg_cell")), _ptr(res.get("seg_len")), _stream(stream)),
-               "vor_server_copy_result")
+        lib = load()
+        if stride > 0 and paths:
+            _check(lib.vor_server_copy_result(self._h, req, None, _ptr(res["n_seg"]), None, None, None, None,
+                                              _stream(stream)), "vor_server_copy_result")
+            off = exclusive_scan(res["n_seg"], stream=stream)
+            (stream if stream is not None else torch.cuda.current_stream()).synchronize()   # the total is read here
+            total = int(off[-1].item())
+            res["ray_off"] = off
+            res["seg_cell"] = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+            res["seg_len"] = torch.empty(max(total, 1), dtype=torch.float64, device="cuda")
+        _check(lib.vor_server_copy_result(self._h, req, _ptr(res["tau"]), _ptr(res["n_seg"]), _ptr(res["status"]),
+                                          _ptr(res.get("ray_off")), _ptr(res.get("seg_cell")),
+                                          _ptr(res.get("seg_len")), _stream(stream)), "vor_server_copy_result")
         res["seg_stride"] = stride
         return res
 

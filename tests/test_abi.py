@@ -127,7 +127,9 @@ def test_server_argument_errors_before_device_work(lib):
     assert lib.vor_server_create(arr, 0, 1 << 20, ctypes.byref(out)) == vrt.VOR_EINVAL
     rid = ctypes.c_int64(5)
     fake = (ctypes.c_double * 30)()
-    assert lib.vor_server_submit(None, 0, fake, fake, 10, None, 1.0, 0, 0, ctypes.byref(rid)) == vrt.VOR_EINVAL
+    assert lib.vor_server_submit(None, 0, fake, fake, 10, None, 1.0, 0, 0, 0, None, ctypes.byref(rid)) == vrt.VOR_EINVAL
+    assert rid.value == 0
+    assert lib.vor_server_copy_result(None, 1, None, None, None, None, None, None, None) == vrt.VOR_EINVAL
     done = ctypes.c_int32()
     assert lib.vor_server_poll(None, 1, ctypes.byref(done)) == vrt.VOR_EINVAL
     assert lib.vor_server_wait(None, 1, 0.1) == vrt.VOR_EINVAL

@@ -1,15 +1,22 @@
 """Serving: resident grids, budgeted admission, continuous batching.
 
+Served paths are whole (every cell to the wall, Sect. 2.2): windows, then
+chains of spill chunks from each request's pool, returned as compact rows.
 Each request's result must be the same alone and in a mix of requests on
-different grids and precision classes, and the same as vor_trace of the
-same rays; admission never exceeds the budget; a request that can never
-fit is rejected; requests are admitted first-in-first-out."""
+different grids and precision classes, the same as vor_trace of the same
+rays, and equal to the oracle's paths; a request whose spill pool runs out
+is traced again with an exact pool and still returns whole paths;
+admission never exceeds the budget; a request that can never fit is
+rejected; requests are admitted first-in-first-out; a request waits for
+inputs still being written on its submitter's stream."""
 import time
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_1310_1854_amd import workloads as W
+from pathcmp import compare
 
 pytestmark = pytest.mark.gpu
 
@@ -46,15 +53,29 @@ def _requests(ws, n_req, seed, lo=256, hi=8192):
 
 
 def _same(a, b):
-    """Equal per-ray results and equal segments in every written slot (slots
-    past a ray's count are not written and hold whatever was there)."""
+    """Equal per-ray results and equal whole paths (compact rows)."""
     import torch
     if not all(torch.equal(a[k], b[k]) for k in ("tau", "n_seg", "status")):
         return False
-    stride = a["seg_stride"]
-    n = a["tau"].numel()
-    mask = torch.arange(stride, device="cuda")[None, :] < a["n_seg"].clamp(max=stride)[:, None]
-    return all(torch.equal(a[k].view(n, stride)[mask], b[k].view(n, stride)[mask]) for k in ("seg_cell", "seg_len"))
+    if ("ray_off" in a) != ("ray_off" in b):
+        return False
+    if "ray_off" not in a:
+        return True
+    if not torch.equal(a["ray_off"], b["ray_off"]):
+        return False
+    t = int(a["ray_off"][-1])
+    return all(torch.equal(a[k][:t], b[k][:t]) for k in ("seg_cell", "seg_len"))
+
+
+def _ref(vrt, grid, o, d, rho, mode, **kw):
+    """vor_trace of the same rays with exact rows (a counting pass, then the paths)."""
+    return vrt.trace(grid, o, d, rho, mode=mode, segments="exact", **kw)
+
+
+def _whole(res):
+    """Every ray of a served result ended without running out of room."""
+    import torch
+    return not bool((res["status"] == 4).any())
 
 
 def _idle_stats(srv, timeout=60.0):
@@ -93,16 +114,8 @@ def test_alone_equals_in_the_mix_equals_vor_trace(env):
         srv.close()
     for r, a, m in zip(reqs, alone, mixed):
         assert _same(a, m)
-        ref = vrt.trace(grids[r["grid"]], r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], segments="stride",
-                        seg_stride=stride)
-        assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
-        assert torch.equal(ref["status"], a["status"])
-        # the first min(n_seg, stride) slots of every ray agree
-        ns = a["n_seg"].clamp(max=stride)
-        mask = torch.arange(stride, device="cuda")[None, :] < ns[:, None]
-        n = r["o"].shape[0]
-        assert torch.equal(ref["seg_cell"].view(n, stride)[mask], a["seg_cell"].view(n, stride)[mask])
-        assert torch.equal(ref["seg_len"].view(n, stride)[mask], a["seg_len"].view(n, stride)[mask])
+        assert _whole(a)
+        assert _same(_ref(vrt, grids[r["grid"]], r["o"], r["d"], rhos[r["grid"]], r["mode"]), a)
     assert st["completed"] == 2 * len(reqs)
     assert st["crossings"] == 2 * sum(int(a["n_seg"].sum()) for a in alone)
 
@@ -111,7 +124,7 @@ def test_budget_admission_and_rejection(env):
     vrt, torch, ws, grids, rhos = env
     reqs = _requests(ws, 40, seed=6, lo=2000, hi=20000)
     stride = 64
-    per_ray = 8 + 4 + 1 + stride * 12
+    per_ray = 8 + 4 + 1 + stride * 12 + 8 + (4 + 64 * 12) // 8   # with the default pool of a chunk per 8 rays
     budget = 30_000 * per_ray + (1 << 20)   # room for about one large request at a time
     srv = vrt.Server(grids, budget_bytes=budget)
     try:
@@ -197,14 +210,8 @@ def test_completion_queue_and_early_completion(env):
     large = [ids[0], ids[1], ids[3]]
     assert min(lat[r] for r in small) <= max(lat[r] for r in large)
     for (o, d), rid in zip(reqs, ids):
-        ref = vrt.trace(grids[2], o, d, rhos[2], mode="mixed", segments="stride", seg_stride=stride)
-        a = got[rid]
-        assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
-        assert torch.equal(ref["status"], a["status"])
-        n = o.shape[0]
-        mask = torch.arange(stride, device="cuda")[None, :] < a["n_seg"].clamp(max=stride)[:, None]
-        assert torch.equal(ref["seg_cell"].view(n, stride)[mask], a["seg_cell"].view(n, stride)[mask])
-        assert torch.equal(ref["seg_len"].view(n, stride)[mask], a["seg_len"].view(n, stride)[mask])
+        assert _whole(got[rid])
+        assert _same(_ref(vrt, grids[2], o, d, rhos[2], "mixed"), got[rid])
     assert st["completed"] == len(ids) and st["running"] == 0
 
 
@@ -224,28 +231,29 @@ def test_release_waits_for_copies(env):
         return torch.as_tensor(o, device="cuda"), torch.as_tensor(W.isotropic_dirs(rng, n), device="cuda")
 
     (oa, da), (ob, db) = rays(), rays()
-    one = n * (8 + 4 + 1) + n * stride * (4 + 8) + 4096
+    chunks = 2 * n                  # more than these paths need: no second run
+    one = n * (8 + 4 + 1) + n * stride * (4 + 8) + n * 8 + chunks * (4 + 64 * 12) + 8 * 256
     srv = vrt.Server(grids[2:], budget_bytes=int(1.5 * one))
     s = torch.cuda.Stream()
     try:
-        ra = srv.submit(0, oa, da, rhos[2], mode="mixed", seg_stride=stride)
+        ra = srv.submit(0, oa, da, rhos[2], mode="mixed", seg_stride=stride, spill_chunks=chunks)
         srv.wait(ra, 120)
         with torch.cuda.stream(s):
             torch.cuda._sleep(50_000_000)          # tens of ms: the copy runs after it
-        res_a = srv.result(ra, stream=s)
+        res_a = srv.result(ra, stream=s, paths=False)   # per-ray results, queued behind the spin
         srv.release(ra)
-        rb = srv.submit(0, ob, db, rhos[2], mode="mixed", seg_stride=stride)
+        rb = srv.submit(0, ob, db, rhos[2], mode="mixed", seg_stride=stride, spill_chunks=chunks)
         srv.wait(rb, 120)
         res_b = srv.result(rb)
         torch.cuda.synchronize()
         srv.release(rb)
         s.synchronize()
+        assert srv.stats()["reruns"] == 0
     finally:
         srv.close()
-    for (o, d), res in (((oa, da), res_a), ((ob, db), res_b)):
-        ref = vrt.trace(grids[2], o, d, rhos[2], mode="mixed", segments="stride", seg_stride=stride)
-        assert torch.equal(ref["tau"], res["tau"]) and torch.equal(ref["n_seg"], res["n_seg"])
-        assert torch.equal(ref["status"], res["status"])
+    ref = _ref(vrt, grids[2], oa, da, rhos[2], "mixed")
+    assert all(torch.equal(ref[k], res_a[k]) for k in ("tau", "n_seg", "status"))
+    assert _same(_ref(vrt, grids[2], ob, db, rhos[2], "mixed"), res_b)
 
 
 def test_serving_on_grids_with_block_lists(env):
@@ -269,9 +277,7 @@ def test_serving_on_grids_with_block_lists(env):
         srv.close()
     for r, a in zip(reqs, res):
         for g in (lgrids[r["grid"]], grids[r["grid"]]):
-            ref = vrt.trace(g, r["o"], r["d"], rhos[r["grid"]], mode=r["mode"], segments="stride", seg_stride=24)
-            assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
-            assert torch.equal(ref["status"], a["status"])
+            assert _same(_ref(vrt, g, r["o"], r["d"], rhos[r["grid"]], r["mode"]), a)
 
 
 
@@ -313,6 +319,108 @@ def test_serving_with_densities_bound_to_the_grids(env):
     assert any(float(a["tau"].max()) > 0 for a, _ in res)
     for r, (a, b) in zip(reqs, res):
         assert _same(a, b)
-        ref = vrt.trace(bgrids[r["grid"]], r["o"], r["d"], None, mode=r["mode"], segments="stride", seg_stride=32,
-                        grid_density=True)
-        assert torch.equal(ref["tau"], a["tau"]) and torch.equal(ref["n_seg"], a["n_seg"])
+        assert _same(_ref(vrt, bgrids[r["grid"]], r["o"], r["d"], None, r["mode"], grid_density=True), a)
+
+
+def test_served_paths_equal_the_oracle(env):
+    """Served paths against the oracle, element by element (Sect. 2.2): a
+    seeded sample of rays on every resident grid, in both precision classes,
+    through windows of 8 slots so that most paths continue in spill chunks;
+    half of the requests start with a pool of one chunk, too small, and are
+    traced again with an exact pool. No ray ends without its whole path."""
+    vrt, torch, ws, grids, rhos = env
+    rng = np.random.default_rng(23)
+    stride, n = 8, 120
+    reqs = []
+    for g, w in enumerate(ws):
+        for mode in ("fp64", "mixed"):
+            for chunks in (1, 4 * n):
+                if g == 0:
+                    o = W.uniform_in_box(rng, n, w.box)
+                else:
+                    o = np.ascontiguousarray(w.sites[rng.integers(0, w.M, n)])
+                reqs.append(dict(grid=g, mode=mode, chunks=chunks, o=o, d=W.isotropic_dirs(rng, n)))
+    srv = vrt.Server(grids, budget_bytes=1 << 30)
+    try:
+        ids = [srv.submit(r["grid"], torch.as_tensor(r["o"], device="cuda"), torch.as_tensor(r["d"], device="cuda"),
+                          rhos[r["grid"]], mode=r["mode"], seg_stride=stride, spill_chunks=r["chunks"])
+               for r in reqs]
+        res = []
+        for rid in ids:
+            srv.wait(rid, 120)
+            res.append(srv.result(rid))
+        torch.cuda.synchronize()
+        for rid in ids:
+            srv.release(rid)
+        st = _idle_stats(srv)
+    finally:
+        srv.close()
+    assert st["reruns"] >= 1
+    longest = 0
+    for r, a in zip(reqs, res):
+        w = ws[r["grid"]]
+        assert _whole(a)
+        ref = oracle.trace(w.sites, w.box, w.density, r["o"], r["d"], cap=4096)
+        p = {k: a[k].cpu().numpy() for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len")}
+        longest = max(longest, int(p["n_seg"].max()))
+        st = compare(p, ref, {"fp64": 1e-12, "mixed": 1e-5}[r["mode"]])
+        assert st["clean"] >= 0.9 * n, st
+    assert longest > stride + 64   # paths that needed a window and more than one spill chunk
+
+
+def test_pool_too_small_is_traced_again(env):
+    """A request with no spill chunks at all: its long paths run out, the
+    request is traced again with exactly the chunks its counts need, and
+    returns the same whole paths as vor_trace."""
+    vrt, torch, ws, grids, rhos = env
+    rng = np.random.default_rng(29)
+    w = ws[2]
+    n = 3000
+    o = torch.as_tensor(np.ascontiguousarray(w.sites[rng.integers(0, w.M, n)]), device="cuda")
+    d = torch.as_tensor(W.isotropic_dirs(rng, n), device="cuda")
+    srv = vrt.Server(grids, budget_bytes=1 << 30)
+    try:
+        rid = srv.submit(2, o, d, rhos[2], mode="mixed", seg_stride=16, spill_chunks=0)
+        srv.wait(rid, 120)
+        a = srv.result(rid)
+        torch.cuda.synchronize()
+        srv.release(rid)
+        st = _idle_stats(srv)
+    finally:
+        srv.close()
+    assert st["reruns"] == 1 and st["completed"] == 1
+    assert int((a["n_seg"] > 16).sum()) > 0.5 * n
+    assert _whole(a)
+    assert _same(_ref(vrt, grids[2], o, d, rhos[2], "mixed"), a)
+
+
+def test_request_waits_for_inputs_on_its_stream(env):
+    """Inputs written by device work still queued on the submitter's stream
+    when the request is submitted: the server's launch waits for that work
+    (an event recorded at submission), so the request traces the new inputs,
+    not what the buffers held before."""
+    vrt, torch, ws, grids, rhos = env
+    rng = np.random.default_rng(31)
+    w = ws[1]
+    n = 4000
+    o_new = torch.as_tensor(np.ascontiguousarray(w.sites[rng.integers(0, w.M, n)]), device="cuda")
+    d_new = torch.as_tensor(W.isotropic_dirs(rng, n), device="cuda")
+    o = torch.zeros_like(o_new)                 # the origin of the box's symmetry plane: a valid start
+    d = torch.zeros_like(d_new)                 # zero directions: BADDIR if read too early
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    srv = vrt.Server(grids, budget_bytes=1 << 30)
+    try:
+        with torch.cuda.stream(s):
+            torch.cuda._sleep(50_000_000)       # tens of ms of spinning ahead of the writes
+            o.copy_(o_new)
+            d.copy_(d_new)
+        rid = srv.submit(1, o, d, rhos[1], mode="mixed", seg_stride=32, stream=s)
+        srv.wait(rid, 120)
+        a = srv.result(rid)
+        torch.cuda.synchronize()
+        srv.release(rid)
+    finally:
+        srv.close()
+    assert not bool((a["status"] == 2).any())
+    assert _same(_ref(vrt, grids[1], o_new, d_new, rhos[1], "mixed"), a)

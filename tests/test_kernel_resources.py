@@ -2,7 +2,8 @@
 GPU): the persistent kernels must keep the occupancy they are tuned for
 (mixed: 3 waves per SIMD, <= 168 VGPRs; FP64: 4 waves, <= 128; the transport
 kernels of both modes: 3 waves), since a few extra registers cut the rays in
-flight by a third or a half."""
+flight by a third or a half. No traversal kernel may spill to scratch
+memory: a spill costs a slowdown and nothing else would show it."""
 import os
 import re
 import shutil
@@ -32,7 +33,7 @@ def _occupancy(src_name, tmp_path):
     r = subprocess.run(["hipcc", "-c"] + flags + ["--cuda-device-only", src, "-o", str(tmp_path / "t.o"),
                         "-Rpass-analysis=kernel-resource-usage"], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
-    occ, vgpr = {}, {}
+    occ, vgpr, scratch = {}, {}, {}
     name = None
     for line in r.stderr.splitlines():
         m = re.search(r"Function Name: (\S+)", line)
@@ -44,21 +45,29 @@ def _occupancy(src_name, tmp_path):
         m = re.search(r" VGPRs: (\d+)", line)
         if m and name:
             vgpr[name] = int(m.group(1))
-    return occ, vgpr
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name:
+            scratch[name] = int(m.group(1))
+    return occ, vgpr, scratch
 
 
 def test_persistent_kernels_keep_their_occupancy(tmp_path):
-    occ, _ = _occupancy("trace.hip", tmp_path)
+    occ, _, scratch = _occupancy("trace.hip", tmp_path)
     for k, want in WANT.items():
         assert k in occ, f"{k} not compiled"
         assert occ[k] >= want, f"{k}: occupancy {occ[k]} < {want} waves per SIMD"
+    traversal = [k for k in scratch if "k_trace" in k]
+    assert len(traversal) >= 16, traversal
+    for k in traversal:
+        assert scratch[k] == 0, f"{k}: {scratch[k]} bytes of scratch per lane"
 
 
 def test_serving_kernel_keeps_its_occupancy(tmp_path):
-    occ, vgpr = _occupancy("serve.hip", tmp_path)
+    occ, vgpr, scratch = _occupancy("serve.hip", tmp_path)
     for short, want in WANT_SERVE.items():
         names = [k for k in occ if short in k]
         assert names, f"{short} not compiled"
         for k in names:
             assert occ[k] >= want, f"{k}: occupancy {occ[k]} < {want} waves per SIMD"
             assert vgpr[k] <= MAX_VGPR_SERVE, f"{k}: {vgpr[k]} VGPRs > {MAX_VGPR_SERVE}"
+            assert scratch[k] == 0, f"{k}: {scratch[k]} bytes of scratch per lane"
