@@ -46,7 +46,7 @@ constexpr int kChunkMin = 64;          // rays per chunk, at least ...
 constexpr int kChunkMax = 4096;        // ... and at most
 constexpr int kChunksPerWave = 4;      // target chunks per wave of a launch
 constexpr int kStreams = 3;
-constexpr int kSlots = 4;              // chunks a wave may have open at once
+constexpr int kSlots = 64;             // chunks a wave may have open at once: one per lane, so a refill never waits
 constexpr int kServeRefillMin = 48;    // idle lanes that trigger a refill
 
 struct ReqDev {
@@ -86,25 +86,41 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Every ray of chunk slot's request chunk has been written by this wave:
-// make the writes visible device-wide, count the chunk off its request, and
-// the wave that completes the request's last chunk raises its flag in host
-// memory (release at system scope, so the flag is seen after the data): 1
-// when every path is whole, 2 when some ray found its request's spill
-// chunks used up (the host then runs the request again with exactly the
-// chunks its counts need). The overflow counts of other waves are ordered
-// before their chunk counts, which this wave's fetch-add acquires.
+// make the writes visible device-wide (a release fence: the wave's L2
+// writes back, nothing is invalidated), count the chunk off its request,
+// and the wave that completes the request's last chunk -- after an acquire
+// fence, once per request -- raises its flag in host memory (release at
+// system scope, so the flag is seen after the data): 1 when every path is
+// whole, 2 when some ray found its request's spill chunks used up (the host
+// then runs the request again with exactly the chunks its counts need). The
+// overflow counts of other waves precede their release fences and chunk
+// counts, which the acquire fence after the last count takes in. (A full
+// fence or an acquire-release count here invalidated the L2 of the wave's
+// XCD at every chunk.)
 __device__ __forceinline__ void chunk_complete(const ReqDev *__restrict__ reqs, int q)
 {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if ((threadIdx.x & 63) == 0) {
-        const int prev = __hip_atomic_fetch_add(reqs[q].remaining, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const int prev = __hip_atomic_fetch_add(reqs[q].remaining, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const int ovf = __hip_atomic_load(reqs[q].overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(reqs[q].done, ovf ? 2 : 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }
 
+#ifndef VRT_SERVE_WIDE
+#define VRT_SERVE_WIDE 0
+#endif
+// Store groups of the serving kernels (see cells_per_store): the mixed
+// kernel keeps 8 cells and 4 lengths unless VRT_SERVE_WIDE.
+constexpr bool kServeWide = VRT_SERVE_WIDE != 0;
+
+// The serving kernel of one precision class (MODE): a launch runs the
+// kernel of each class over the chunks of that class, so each holds the
+// registers of one step only.
+template <int MODE>
 __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids, const ReqDev *__restrict__ reqs,
                                                const ChunkDev *__restrict__ chunks, int n_chunks,
                                                unsigned int *__restrict__ head,
@@ -118,14 +134,17 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
     int cur_req = -1, cur_first = 0, cur_left = 0, cur_slot = 0;   // chunk being handed out
     int p_req = -1, p_first = 0, p_count = 0, p_ctx = -1;         // chunk taken, not yet started
     bool have_p = false, drained = false;
-    int slot_req[kSlots], slot_left[kSlots];   // open chunks: request, rays not yet finished
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        slot_req[s] = -1;
-        slot_left[s] = 0;
-    }
+    // Open chunks of each wave of the block, in LDS: request, rays not yet
+    // finished (0: the slot is free). Lane s owns slot s when searching.
+    __shared__ int32_t s_req[4][kSlots], s_left[4][kSlots];
+    int32_t *slot_req = s_req[threadIdx.x >> 6];
+    int32_t *slot_left = s_left[threadIdx.x >> 6];
+    slot_req[lane] = -1;
+    slot_left[lane] = 0;
+    __builtin_amdgcn_wave_barrier();   // the wave's lanes exchange slot data through LDS: keep its accesses in order
     // Per-lane state.
     bool live = false;
+    bool pending = false;   // the lane's ray has ended; its results are written at the next refill
     int slot = -1, q = -1;
     int64_t ray = 0;
     const double *dens = nullptr;
@@ -140,6 +159,42 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
         const uint64_t want = __ballot(need);
         uint64_t busy = ~want & __ballot(true);
         if (want && (__popcll(want) >= kServeRefillMin || busy == 0ull)) {
+            // The rays that ended since the last refill write their results together (one pass for the
+            // wave instead of one per ray) and are counted off their chunks.
+            if (__ballot(pending)) {
+                if (pending) {
+                    SegOut O{};
+                    O.cell = cellp;
+                    O.len = lenp;
+                    O.vec = vec;
+                    O.pool = &reqs[q].spill;
+                    finish_segments<cells_per_store<MODE, false, kServeWide>(), lens_per_store<MODE, false, kServeWide>(),
+                                    true>(O, R, S.cnt);
+                    const ReqDev &rq = reqs[q];
+                    if (R.cap > 0 && R.st == RAY_OK && S.cnt > R.cap && R.chunk == -2) {   // its spill chunks ran out
+                        R.st = RAY_OVERFLOW;
+                        atomicAdd(rq.overflow, 1);
+                    }
+                    rq.tau[ray] = R.tau;
+                    rq.n_seg[ray] = S.cnt;
+                    rq.status[ray] = R.st;
+                }
+                // count the ended rays off their chunks, one chunk at a time
+                for (uint64_t left = __ballot(pending); left; left = __ballot(pending)) {
+                    const int leader = __ffsll((long long)left) - 1;
+                    const int s = uniform(__shfl(slot, leader, 64));
+                    const uint64_t grp = __ballot(pending && slot == s);
+                    int rest = 0;
+                    if (lane == leader) {
+                        rest = slot_left[s] - __popcll(grp);
+                        slot_left[s] = rest;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    rest = uniform(__shfl(rest, leader, 64));
+                    if (rest == 0) chunk_complete(reqs, uniform(slot_req[s]));
+                    pending = pending && slot != s;
+                }
+            }
             uint64_t pend = want;
             // Each pass starts a chunk or hands out rays; eight passes serve
             // every idle lane but in the rarest cases (the rest wait).
@@ -162,17 +217,14 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                         have_p = true;
                     }
                     if (p_ctx != ctx && busy != 0ull) break;   // let the other context's rays finish first
-                    int fs = -1;
-#pragma unroll
-                    for (int s = kSlots - 1; s >= 0; --s)
-                        if (slot_left[s] == 0) fs = s;
-                    if (fs < 0) break;                          // every slot open: wait for one to close
-#pragma unroll
-                    for (int s = 0; s < kSlots; ++s)
-                        if (s == fs) {
-                            slot_req[s] = p_req;
-                            slot_left[s] = p_count;
-                        }
+                    const uint64_t free = __ballot(slot_left[lane] == 0);
+                    if (free == 0ull) break;                    // every slot open (cannot happen with a slot per lane)
+                    const int fs = __ffsll((long long)free) - 1;
+                    if (lane == fs) {
+                        slot_req[fs] = p_req;
+                        slot_left[fs] = p_count;
+                    }
+                    __builtin_amdgcn_wave_barrier();
                     cur_req = p_req;
                     cur_first = p_first;
                     cur_left = p_count;
@@ -206,8 +258,8 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     R.base = ray * rq.seg_stride;
                     R.cap = rq.seg_cell ? rq.seg_stride : 0;
                     if (R.st == RAY_OK) {
-                        ray_begin(G, R, s0);
-                        R.rho = (ctx & 3) == 3 ? block_rho(G, R.b) : 0.0;   // mixed mode carries it
+                        ray_begin_at(G, R, rq.n_seg[ray], s0);   // start cell from the launch's start pass
+                        R.rho = (MODE == VOR_MODE_MIXED && (ctx & 2)) ? block_rho(G, R.b) : 0.0;   // mixed mode carries it
                         settle(R.rho);
                     } else {
                         R.L = 0.0;
@@ -225,7 +277,6 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
             if (drained && !have_p && cur_left == 0) break;   // queue drained, every ray ended
             continue;
         }
-        bool fin = false;
         if (live) {
             const RayIn I{nullptr, nullptr, dens, kappa, 0, (ctx >> 1) & 1};
             SegOut O{};
@@ -233,35 +284,13 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
             O.len = lenp;
             O.vec = vec;
             O.pool = &reqs[q].spill;
-            const bool more = (ctx & 1) ? ray_step<VOR_MODE_MIXED, true, false, false, false, true>(G, I, R, S, O)
-                                        : ray_step<VOR_MODE_FP64, true, false, false, true, true>(G, I, R, S, O);
+            const bool more = ray_step<MODE, true, false, false, kServeWide, true>(G, I, R, S, O);
             if (!more) {
-                if (ctx & 1) finish_segments<cells_per_store<VOR_MODE_MIXED, false, false>(), lens_per_store<VOR_MODE_MIXED, false, false>(), true>(
-                    O, R, S.cnt);
-                else finish_segments<cells_per_store<VOR_MODE_FP64, false>(), lens_per_store<VOR_MODE_FP64, false>(), true>(O, R, S.cnt);
-                const ReqDev &rq = reqs[q];
-                if (R.cap > 0 && R.st == RAY_OK && S.cnt > R.cap && R.chunk == -2) {   // its spill chunks ran out
-                    R.st = RAY_OVERFLOW;
-                    atomicAdd(rq.overflow, 1);
-                }
-                rq.tau[ray] = R.tau;
-                rq.n_seg[ray] = S.cnt;
-                rq.status[ray] = R.st;
                 T.cnt += S.cnt;
                 T.nfb += S.nfb;
                 T.nredo += S.nredo;
                 live = false;
-                fin = true;
-            }
-        }
-        if (__ballot(fin)) {
-#pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int n = __popcll(__ballot(fin && slot == s));
-                if (n) {
-                    slot_left[s] -= n;
-                    if (slot_left[s] == 0) chunk_complete(reqs, slot_req[s]);
-                }
+                pending = true;
             }
         }
     }
@@ -275,9 +304,37 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
     }
 }
 
+// The start cells C(r0) (Sect. 2.3) of every ray of a launch, ahead of the
+// traversal (as vor_trace's start pass): block c locates the rays of chunk c
+// side by side and leaves each internal cell index (-1 for a ray without a
+// path) in its request's n_seg slot, which the traversal reads at the ray's
+// start and overwrites with the segment count at its end.
+__global__ void __launch_bounds__(256) k_serve_start(const GridRef *__restrict__ grids,
+                                                     const ReqDev *__restrict__ reqs,
+                                                     const ChunkDev *__restrict__ chunks, int n_chunks)
+{
+    const int c = blockIdx.x;
+    if (c >= n_chunks) return;
+    const ChunkDev ch = chunks[c];
+    const ReqDev &rq = reqs[ch.req];
+    const GridRef &G = grids[ch.ctx >> 2];
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+        const int64_t ray = (int64_t)ch.first + i;
+        double r0[3], k[3], L, s0;
+        const uint8_t st = ray_setup<false>(G, rq.in, ray, r0, k, L, s0);
+        int32_t m = -1;
+        if (st == RAY_OK) {
+            double q[3];
+            start_point(r0, k, s0, q);
+            m = nearest_site(G.grid, q, nullptr);
+        }
+        rq.n_seg[ray] = m;
+    }
+}
+
 __global__ void k_zero_launch(unsigned int *head, unsigned long long *counters, ReqCount *rc, int n_req)
 {
-    if (threadIdx.x == 0) *head = 0;
+    if (threadIdx.x < 2) head[threadIdx.x] = 0;
     if (threadIdx.x < 4) counters[threadIdx.x] = 0;
     for (int q = threadIdx.x; q < n_req; q += blockDim.x) rc[q] = ReqCount{0ull, 0, 0};
 }
@@ -367,24 +424,27 @@ struct Launch {
     int32_t *h_remaining = nullptr, *d_remaining = nullptr;
     ReqCount *d_count = nullptr;                      // per-request spill counter and overflow count
     int32_t *h_flags = nullptr, *d_flags = nullptr;   // host memory, mapped for the device
-    unsigned int *d_head = nullptr;
+    unsigned int *d_head = nullptr;                   // chunk queue heads of the FP64 and the mixed kernel
     unsigned long long *d_counters = nullptr;
     unsigned long long *h_counters = nullptr;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Chunks of kSpillChunk slots that the windows of a request take: its spill
+// chunks follow them in the same arrays.
+int64_t window_chunks(int64_t n, int64_t stride) { return (n * stride + kSpillChunk - 1) / kSpillChunk; }
+
 // Output memory of a request: tau, counts and statuses; with a window of
-// `stride` slots per ray also the windows, the first spill chunk of every
-// ray and `chunks` spill chunks (links, cells, lengths).
+// `stride` slots per ray also the windows followed by `chunks` spill chunks
+// (cells, lengths), the chunks' links and the first chunk of every ray.
 size_t request_bytes(int64_t n, int64_t stride, int64_t chunks)
 {
     size_t b = align_up(n * sizeof(double)) + align_up(n * sizeof(int32_t)) + align_up(n);
     if (stride > 0) {
-        b += align_up((size_t)n * stride * sizeof(int32_t)) + align_up((size_t)n * stride * sizeof(double));
-        b += align_up((size_t)n * sizeof(int64_t)) + align_up((size_t)chunks * sizeof(int32_t)) +
-             align_up((size_t)chunks * kSpillChunk * sizeof(int32_t)) +
-             align_up((size_t)chunks * kSpillChunk * sizeof(double));
+        const size_t slots = (size_t)(window_chunks(n, stride) + chunks) * kSpillChunk;
+        b += align_up(slots * sizeof(int32_t)) + align_up(slots * sizeof(double));
+        b += align_up((size_t)n * sizeof(int64_t)) + align_up((size_t)chunks * sizeof(int32_t));
     }
     return b;
 }
@@ -407,7 +467,8 @@ struct vor_server {
     std::thread worker;
     std::atomic<bool> stop{false};
     int device = 0;
-    int blocks = 1;
+    int blocks = 1;     // resident blocks of the mixed serving kernel
+    int blocks64 = 1;   // ... and of the FP64 one
     vor_status fault = VOR_OK;
     hipStream_t aux = nullptr;   // the scheduler's own copies (segment counts of requests run again)
     int32_t *h_counts = nullptr; // staging for those counts
@@ -472,17 +533,17 @@ struct vor_server {
             r.status = (uint8_t *)p;
             p += align_up(r.n);
             if (r.seg_stride > 0) {
+                const int64_t wc = window_chunks(r.n, r.seg_stride);
+                const size_t slots = (size_t)(wc + r.spill_chunks) * kSpillChunk;
                 r.seg_cell = (int32_t *)p;
-                p += align_up((size_t)r.n * r.seg_stride * sizeof(int32_t));
+                p += align_up(slots * sizeof(int32_t));
                 r.seg_len = (double *)p;
-                p += align_up((size_t)r.n * r.seg_stride * sizeof(double));
+                p += align_up(slots * sizeof(double));
                 r.spill_first = (int64_t *)p;
                 p += align_up((size_t)r.n * sizeof(int64_t));
                 r.spill_next = (int32_t *)p;
-                p += align_up((size_t)r.spill_chunks * sizeof(int32_t));
-                r.spill_cell = (int32_t *)p;
-                p += align_up((size_t)r.spill_chunks * kSpillChunk * sizeof(int32_t));
-                r.spill_len = (double *)p;
+                r.spill_cell = r.seg_cell + wc * kSpillChunk;   // the spill chunks follow the windows
+                r.spill_len = r.seg_len + wc * kSpillChunk;
             }
             r.state = Q_ADMITTED;
             r.t_admit = clk::now();
@@ -522,11 +583,12 @@ struct vor_server {
         }
         L.reqs.resize(keep);
         if (L.reqs.empty()) return;   // cannot happen: the requests need at most kMaxLaunchChunks / 2 + kMaxLaunchReqs chunks
+        // precision class first (each class has a kernel of its own), then grid
         std::stable_sort(L.reqs.begin(), L.reqs.end(), [this](int64_t x, int64_t y) {
             const Request &a = reqs[x], &b = reqs[y];
-            return (2 * a.grid + a.mode) < (2 * b.grid + b.mode);
+            return (a.mode != b.mode) ? a.mode < b.mode : a.grid < b.grid;
         });
-        int nch = 0;
+        int nch = 0, n64 = 0;   // chunks, and those of FP64 requests (first)
         for (size_t qi = 0; qi < L.reqs.size(); ++qi) {
             Request &r = reqs[L.reqs[qi]];
             const int q = (int)qi;
@@ -539,8 +601,8 @@ struct vor_server {
             d.seg_cell = r.seg_cell;
             d.seg_len = r.seg_len;
             d.seg_stride = r.seg_stride;
-            d.spill = SpillPool{r.spill_cell, r.spill_len, r.spill_next, r.spill_first, r.spill_chunks,
-                                &L.d_count[q].spill_head};
+            d.spill = SpillPool{r.spill_next, r.spill_first, r.spill_chunks,
+                                r.seg_stride > 0 ? window_chunks(r.n, r.seg_stride) : 0, &L.d_count[q].spill_head};
             d.remaining = L.d_remaining + q;
             d.overflow = &L.d_count[q].overflow;
             d.done = L.d_flags + q;
@@ -548,6 +610,7 @@ struct vor_server {
             L.h_remaining[q] = need;
             L.h_flags[q] = 0;
             const int32_t ctx = 4 * r.grid + 2 * r.in.grid_rho + (r.mode == VOR_MODE_MIXED ? 1 : 0);
+            if (r.mode == VOR_MODE_FP64) n64 += need;
             for (int c = 0; c < need; ++c) {
                 ChunkDev &ch = L.h_chunks[nch++];
                 ch.req = q;
@@ -571,9 +634,17 @@ struct vor_server {
                   hipMemcpyAsync(L.d_remaining, L.h_remaining, sizeof(int32_t) * nreq, hipMemcpyHostToDevice,
                                  L.stream) == hipSuccess;
         hipLaunchKernelGGL(k_zero_launch, dim3(1), dim3(256), 0, L.stream, L.d_head, L.d_counters, L.d_count, nreq);
-        int nb = std::max(1, std::min(blocks, (nch + 3) / 4));
-        hipLaunchKernelGGL(k_serve, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks, nch, L.d_head,
-                           L.d_counters);
+        hipLaunchKernelGGL(k_serve_start, dim3(nch), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks, nch);
+        if (n64 > 0) {
+            const int nb = std::max(1, std::min(blocks64, (n64 + 3) / 4));
+            hipLaunchKernelGGL(k_serve<VOR_MODE_FP64>, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks,
+                               n64, L.d_head, L.d_counters);
+        }
+        if (nch > n64) {
+            const int nb = std::max(1, std::min(blocks, (nch - n64 + 3) / 4));
+            hipLaunchKernelGGL(k_serve<VOR_MODE_MIXED>, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs,
+                               L.d_chunks + n64, nch - n64, L.d_head + 1, L.d_counters);
+        }
         ok = ok && hipGetLastError() == hipSuccess &&
              hipMemcpyAsync(L.h_counters, L.d_counters, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                             L.stream) == hipSuccess &&
@@ -781,18 +852,20 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
              hipMalloc(&L.d_count, sizeof(ReqCount) * kMaxLaunchReqs) == hipSuccess &&
              hipMalloc(&L.d_reqs, sizeof(ReqDev) * kMaxLaunchReqs) == hipSuccess &&
              hipMalloc(&L.d_chunks, sizeof(ChunkDev) * kMaxLaunchChunks) == hipSuccess &&
-             hipMalloc(&L.d_head, sizeof(unsigned int)) == hipSuccess &&
+             hipMalloc(&L.d_head, 2 * sizeof(unsigned int)) == hipSuccess &&
              hipMalloc(&L.d_counters, 4 * sizeof(unsigned long long)) == hipSuccess;
     }
     ok = ok && hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking) == hipSuccess;
-    int cus = 0, per_cu = 0;
+    int cus = 0, per_cu = 0, per_cu64 = 0;
     ok = ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess &&
-         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve, 256, 0) == hipSuccess;
+         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve<VOR_MODE_MIXED>, 256, 0) == hipSuccess &&
+         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_serve<VOR_MODE_FP64>, 256, 0) == hipSuccess;
     if (!ok) {
         vor_server_destroy(S);
         return VOR_ENOMEM;
     }
     S->blocks = std::max(1, cus * std::max(1, per_cu));
+    S->blocks64 = std::max(1, cus * std::max(1, per_cu64));
     S->budget = (size_t)budget_bytes;
     S->free_blocks[0] = S->budget;
     S->t0 = clk::now();

@@ -52,15 +52,18 @@ constexpr int kSpillChunk = VOR_SPILL_CHUNK;
 #define VRT_NT_STORE 1
 #endif
 
-// A pool of spill chunks read from memory by the lane that needs it: in the
-// serving kernel the lanes of one wave may hold rays of different requests,
-// each with a pool of its own (the same layout as SegOut's spill arrays).
+// A pool of spill chunks read from memory by the lane that takes a chunk: in
+// the serving kernel the lanes of one wave may hold rays of different
+// requests, each with a pool of its own. The pool's chunks lie in the
+// window arrays themselves, after the windows: chunk k of the pool holds
+// slots [(base_chunk + k) * kSpillChunk, ...) of SegOut's cell and len, so
+// a lane stores its spill segments through the window pointers it already
+// holds. first and next hold pool-relative chunk numbers k.
 struct SpillPool {
-    int32_t *cell;
-    double *len;
     int32_t *next;
     int64_t *first;
     int64_t chunks;
+    int64_t base_chunk;
     unsigned long long *head;
 };
 
@@ -74,7 +77,7 @@ struct SegOut {
     int64_t *spill_first;           // first chunk of each ray, -1 if none
     int64_t spill_chunks;           // capacity in chunks
     unsigned long long *chunk_head; // chunks handed out
-    const SpillPool *pool;          // LP kernels: this lane's pool instead of the spill arrays above
+    const SpillPool *pool;          // LP kernels: this lane's pool (in cell and len) instead of the spill arrays above
 };
 
 // Smallest accepted eps of the mixed-mode bound (2^-20 = 16u): twice what
@@ -537,31 +540,51 @@ __device__ __forceinline__ int64_t segment_slot(const SegOut &O, const RayState 
     return (int64_t)R.chunk * kSpillChunk + (idx - R.cap) % kSpillChunk;
 }
 
-// The arrays a slot from segment_slot indexes.
+// The arrays a slot from segment_slot indexes (LP: the pool's chunks follow
+// the windows in the same arrays).
 template <bool LP>
 __device__ __forceinline__ int32_t *slot_cells(const SegOut &O, bool spill)
 {
-    return spill ? (LP ? O.pool->cell : O.spill_cell) : O.cell;
+    return (spill && !LP) ? O.spill_cell : O.cell;
 }
 template <bool LP>
 __device__ __forceinline__ double *slot_lens(const SegOut &O, bool spill)
 {
-    return spill ? (LP ? O.pool->len : O.spill_len) : O.len;
+    return (spill && !LP) ? O.spill_len : O.len;
 }
 
-// A new spill chunk for the ray from this lane's own pool (LP kernels):
-// chunks are taken one at a time by atomics on the pool's counter, lanes of
-// a wave serving different pools. -2 when the pool has run out.
-__device__ __forceinline__ void take_pool_chunk(const SpillPool *pool, RayState &R)
+// New spill chunks for the lanes that need one (need), each from its own
+// pool (LP kernels, whose lanes may serve different pools): the lanes that
+// share the first pending lane's pool take theirs with one atomic on the
+// pool's counter, ranked by the ballot, and so on until every lane has one
+// (or found its pool used up: chunk -2).
+__device__ __forceinline__ void take_pool_chunks(const SpillPool *pool, RayState &R, bool need)
 {
-    const unsigned long long c = atomicAdd(pool->head, 1ull);
-    if ((int64_t)c < pool->chunks) {
-        pool->next[c] = -1;
-        if (R.chunk < 0) pool->first[R.ray] = (int64_t)c;
-        else pool->next[R.chunk] = (int32_t)c;
-        R.chunk = (int32_t)c;
-    } else {
-        R.chunk = -2;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const unsigned long long me = (unsigned long long)(uintptr_t)pool;
+    bool pend = need;
+    for (uint64_t left = __ballot(pend); left; left = __ballot(pend)) {
+        const int leader = __ffsll((long long)left) - 1;
+        const unsigned long long lp = __shfl(me, leader, 64);
+        const bool same = pend && me == lp;
+        const uint64_t grp = __ballot(same);
+        unsigned long long b = 0;
+        if (lane == leader) b = atomicAdd(pool->head, (unsigned long long)__popcll(grp));
+        b = __shfl(b, leader, 64);
+        if (same) {
+            const unsigned long long c = b + __popcll(grp & lt);
+            if ((int64_t)c < pool->chunks) {
+                const int64_t c0 = pool->base_chunk;
+                pool->next[c] = -1;
+                if (R.chunk < 0) pool->first[R.ray] = (int64_t)c;
+                else pool->next[R.chunk - c0] = (int32_t)c;
+                R.chunk = (int32_t)(c0 + (int64_t)c);   // in the window arrays' chunk numbering
+            } else {
+                R.chunk = -2;
+            }
+            pend = false;
+        }
     }
 }
 
@@ -605,7 +628,8 @@ template <int CG, int LG, bool LP = false>
 __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int64_t idx, int32_t cell, double len)
 {
     if (LP) {
-        if (idx >= R.cap && ((idx - R.cap) % kSpillChunk) == 0 && R.chunk != -2) take_pool_chunk(O.pool, R);
+        const bool need = idx >= R.cap && ((idx - R.cap) % kSpillChunk) == 0 && R.chunk != -2;
+        if (__ballot(need)) take_pool_chunks(O.pool, R, need);
     } else if (idx >= R.cap && O.spill_cell) {
         const int64_t k = idx - R.cap;
         const bool need = (k % kSpillChunk) == 0 && R.chunk != -2;

@@ -21,7 +21,7 @@ WANT = {
     "_ZN12_GLOBAL__N_118k_trace_persistentILi1ELb1ELb1EEEvNS_9TraceArgsE": 3,   # mixed, transport
     "_ZN12_GLOBAL__N_118k_trace_persistentILi0ELb1ELb1EEEvNS_9TraceArgsE": 3,   # FP64, transport
 }
-WANT_SERVE = {"k_serve": 3}   # the serving kernel (both steps, mixed and FP64)
+WANT_SERVE = {"k_serve": 3}   # the serving kernels (one per precision class)
 # Its register budget: at the 168-register ceiling (with 8-length store
 # groups) it still had 3 waves, but served 23% slower.
 MAX_VGPR_SERVE = 160
