@@ -104,6 +104,22 @@ typedef struct {
     int64_t block_entries;    /* total length of its cell lists */
 } vor_grid_info;
 
+/* Device memory for a grid's arrays, e.g. from a framework's caching
+ * allocator. alloc returns `bytes` bytes of device memory usable in work
+ * ordered on `stream` (the stream passed to vor_build_grid), or NULL when it
+ * has none (vor_build_grid then fails with VOR_ENOMEM); free takes back a
+ * block alloc gave, with its size. Both are called on the calling host
+ * thread only: alloc and free during vor_build_grid (free for its
+ * temporaries, after the stream has synchronised), free again in
+ * vor_grid_free (after the device has synchronised) for the grid's own
+ * arrays. ctx is passed through. The struct is copied into the grid; the
+ * functions and ctx must stay valid until vor_grid_free. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx, void *stream);
+    void (*free)(void *ptr, size_t bytes, void *ctx, void *stream);
+    void *ctx;
+} vor_allocator;
+
 /*
  * vor_build_grid -- setup phase of Sect. 2.2 (items 1-3): keeps the box and
  * the sites and derives each site's neighbour list. The neighbours of site i
@@ -116,14 +132,17 @@ typedef struct {
  *   sites  device, M x 3, user order; read during the call only.
  *   M      number of sites, >= 1 and < 2^31.
  *   box    host, 6 doubles, xmin < xmax etc.; every site must lie inside.
- *   opts   host, may be NULL.
- *   out    host; receives the grid on VOR_OK, NULL otherwise.
+ *   opts       host, may be NULL.
+ *   allocator  host, may be NULL (hipMalloc and hipFree): where the grid's
+ *              device memory comes from (see vor_allocator).
+ *   out        host; receives the grid on VOR_OK, NULL otherwise.
  * Errors: VOR_EINVAL, VOR_EOUTSIDE (a site outside the box or not finite),
  * VOR_EDUP (coincident sites), VOR_ENOMEM, VOR_ECAPACITY, VOR_EDEVICE.
  * Synchronises `stream` before returning.
  */
 vor_status vor_build_grid(const double *sites, int64_t M, const double *box,
-                          const vor_build_opts *opts, void *stream, vor_grid **out);
+                          const vor_build_opts *opts, const vor_allocator *allocator, void *stream,
+                          vor_grid **out);
 
 /* Releases every device array of the grid (synchronises the device first). NULL is a no-op. */
 void vor_grid_free(vor_grid *grid);
@@ -163,16 +182,6 @@ vor_status vor_grid_bboxes(const vor_grid *grid, double *bbox, void *stream);
  * that overlap the call on another stream may see either field.
  */
 vor_status vor_grid_bind_density(vor_grid *grid, const double *density, void *stream);
-
-/*
- * Diagnostic: keeps only the first `keep` entries (internal order) of the
- * neighbour list of site `site` (user index), so that the table misses
- * faces of that cell and paths through it take the no-exit fallback of
- * Sect. 2.2 (advance a small distance, locate the point again). Paths are
- * no longer exact after this; it exists to test that recovery. Synchronous;
- * VOR_EINVAL for a bad site or a negative keep.
- */
-vor_status vor_grid_truncate_row(vor_grid *grid, int64_t site, int32_t keep);
 
 /*
  * vor_grid_neighbors -- the neighbour lists of Sect. 2.2 item 3 in CSR form,
@@ -228,6 +237,10 @@ typedef struct {
     int32_t grid_density;   /* 1: the densities are those bound to the grid by vor_grid_bind_density (the
                                density argument must then be NULL); tau is the same as with that field
                                passed as the density argument. VOR_EINVAL if none is bound */
+    double eps_fb;          /* the no-exit fallback's advance (Sect. 2.2: move the point a small distance
+                               along the ray, then locate it again), a distance; 0 = 1e-12 times the box
+                               diagonal. The advance is not part of any segment, so such a path's lengths
+                               sum to L - n_fallback * eps_fb. VOR_EINVAL if negative or not finite */
 } vor_trace_opts;
 
 /* Outputs of vor_trace. All pointers are device memory; tau and n_seg are required. */

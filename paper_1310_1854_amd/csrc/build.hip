@@ -14,6 +14,7 @@
 #include <cmath>
 #include <vector>
 
+#include "../../include/voronoi_rt_diag.h"
 #include "clip_wave.h"
 
 using namespace vrt;
@@ -377,16 +378,42 @@ __global__ void k_export_fill(const int32_t *__restrict__ inv_perm, const int32_
         if ((walls[i] >> w) & 1) out[n++] = -(w + 1);
 }
 
+// Device memory of a grid: from the caller's allocator when one is given
+// (e.g. a framework's caching allocator), else hipMalloc.
+struct DevBlock {
+    void *p;
+    size_t bytes;
+};
+
+struct DevAlloc {
+    vor_allocator a{};
+    bool custom = false;
+    void *stream = nullptr;
+    void *get(size_t bytes) const
+    {
+        if (custom) return a.alloc(bytes, a.ctx, stream);
+        void *p = nullptr;
+        return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+    }
+    void put(const DevBlock &b) const
+    {
+        if (!b.p) return;
+        if (custom) a.free(b.p, b.bytes, a.ctx, stream);
+        else (void)hipFree(b.p);
+    }
+};
+
 template <typename T>
-T *dalloc(size_t n, vor_status &st, std::vector<void *> &track)
+T *dalloc(size_t n, vor_status &st, std::vector<DevBlock> &track, const DevAlloc &A)
 {
-    void *p = nullptr;
     if (st != VOR_OK) return nullptr;
-    if (hipMalloc(&p, n * sizeof(T) > 0 ? n * sizeof(T) : 1) != hipSuccess) {
+    const size_t bytes = n * sizeof(T) > 0 ? n * sizeof(T) : 1;
+    void *p = A.get(bytes);
+    if (!p) {
         st = VOR_ENOMEM;
         return nullptr;
     }
-    track.push_back(p);
+    track.push_back(DevBlock{p, bytes});
     return (T *)p;
 }
 
@@ -396,13 +423,16 @@ unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1
 
 struct vor_grid {
     vrt::Grid g;
+    DevAlloc alloc;                 // where its arrays came from
+    std::vector<DevBlock> owned;    // ... and the arrays, returned by vor_grid_free
 };
 
 extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const double *box, const vor_build_opts *opts,
-                                     void *stream, vor_grid **out)
+                                     const vor_allocator *allocator, void *stream, vor_grid **out)
 {
     if (out) *out = nullptr;
     if (!sites || !box || !out || M < 1 || M >= 0x7fffffffLL) return VOR_EINVAL;
+    if (allocator && (!allocator->alloc || !allocator->free)) return VOR_EINVAL;
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(box[a]) || !std::isfinite(box[a + 3]) || !(box[a] < box[a + 3])) return VOR_EINVAL;
     double occ = (opts && opts->bucket_occupancy > 0) ? opts->bucket_occupancy : 2.0;
@@ -415,12 +445,20 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     vor_grid *G = new (std::nothrow) vor_grid;
     if (!G) return VOR_ENOMEM;
     Grid &g = G->g;
+    G->alloc.custom = allocator != nullptr;
+    if (allocator) G->alloc.a = *allocator;
+    G->alloc.stream = stream;
+    const DevAlloc &A = G->alloc;
     (void)hipGetDevice(&g.device);
+    if (hipDeviceGetAttribute(&g.cus, hipDeviceAttributeMultiprocessorCount, g.device) != hipSuccess || g.cus < 1) {
+        delete G;
+        return VOR_EDEVICE;
+    }
     g.M = M;
     for (int a = 0; a < 6; ++a) g.box[a] = box[a];
 
     vor_status rc = VOR_OK;
-    std::vector<void *> tmp, keep;
+    std::vector<DevBlock> tmp, &keep = G->owned;
     BoxArg ba;
     for (int a = 0; a < 3; ++a) {
         ba.lo[a] = box[a];
@@ -430,20 +468,20 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     double hscale = (double)(1 << kHilbertBits) / ext;
 
     int64_t hist_len = vrt_radix_hist_len(M);
-    uint32_t *keys = dalloc<uint32_t>(M, rc, tmp);
-    int32_t *vals = dalloc<int32_t>(M, rc, tmp);
-    uint32_t *keys2 = dalloc<uint32_t>(M, rc, tmp);
-    int32_t *vals2 = dalloc<int32_t>(M, rc, tmp);
-    int32_t *hist = dalloc<int32_t>(2 * hist_len + 1, rc, tmp);
-    int *err = dalloc<int>(4, rc, tmp);
-    g.sites = dalloc<Site>(M, rc, keep);
-    g.perm = dalloc<int32_t>(M, rc, keep);
-    g.inv_perm = dalloc<int32_t>(M, rc, keep);
-    g.wall_mask = dalloc<uint8_t>(M, rc, keep);
-    g.volume = dalloc<double>(M, rc, keep);
-    g.rho_int = dalloc<double>(M, rc, keep);
-    g.bucket_sites = dalloc<Site>(M, rc, keep);
-    if (want_loc) g.bbox = dalloc<double>((size_t)M * 6, rc, keep);
+    uint32_t *keys = dalloc<uint32_t>(M, rc, tmp, A);
+    int32_t *vals = dalloc<int32_t>(M, rc, tmp, A);
+    uint32_t *keys2 = dalloc<uint32_t>(M, rc, tmp, A);
+    int32_t *vals2 = dalloc<int32_t>(M, rc, tmp, A);
+    int32_t *hist = dalloc<int32_t>(2 * hist_len + 1, rc, tmp, A);
+    int *err = dalloc<int>(4, rc, tmp, A);
+    g.sites = dalloc<Site>(M, rc, keep, A);
+    g.perm = dalloc<int32_t>(M, rc, keep, A);
+    g.inv_perm = dalloc<int32_t>(M, rc, keep, A);
+    g.wall_mask = dalloc<uint8_t>(M, rc, keep, A);
+    g.volume = dalloc<double>(M, rc, keep, A);
+    g.rho_int = dalloc<double>(M, rc, keep, A);
+    g.bucket_sites = dalloc<Site>(M, rc, keep, A);
+    if (want_loc) g.bbox = dalloc<double>((size_t)M * 6, rc, keep, A);
 
     // bucket grid dimensions: about `occ` sites per bucket, cube-like buckets
     double vol = (box[3] - box[0]) * (box[4] - box[1]) * (box[5] - box[2]);
@@ -458,22 +496,22 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
         g.inv_h[a] = n / e;
         B *= n;
     }
-    int32_t *bcount = dalloc<int32_t>(B, rc, tmp);
-    g.bucket_start = dalloc<int32_t>(B + 1, rc, keep);
-    int32_t *nbr0 = dalloc<int32_t>((size_t)M * kMaxNbr, rc, tmp);
-    int32_t *cnt0 = dalloc<int32_t>(M, rc, tmp);
-    int32_t *retry = dalloc<int32_t>(M, rc, tmp);
-    int32_t *slot = dalloc<int32_t>(M, rc, tmp);
-    int32_t *dir_start = dalloc<int32_t>(M + 1, rc, tmp);
-    int32_t *extra = dalloc<int32_t>(M, rc, tmp);
-    int32_t *total = dalloc<int32_t>(M, rc, tmp);
-    int32_t *start = dalloc<int32_t>(M + 1, rc, tmp);
+    int32_t *bcount = dalloc<int32_t>(B, rc, tmp, A);
+    g.bucket_start = dalloc<int32_t>(B + 1, rc, keep, A);
+    int32_t *nbr0 = dalloc<int32_t>((size_t)M * kMaxNbr, rc, tmp, A);
+    int32_t *cnt0 = dalloc<int32_t>(M, rc, tmp, A);
+    int32_t *retry = dalloc<int32_t>(M, rc, tmp, A);
+    int32_t *slot = dalloc<int32_t>(M, rc, tmp, A);
+    int32_t *dir_start = dalloc<int32_t>(M + 1, rc, tmp, A);
+    int32_t *extra = dalloc<int32_t>(M, rc, tmp, A);
+    int32_t *total = dalloc<int32_t>(M, rc, tmp, A);
+    int32_t *start = dalloc<int32_t>(M + 1, rc, tmp, A);
     int *hdr = nullptr;
 
     auto fail = [&](vor_status s) {
         (void)hipStreamSynchronize(st);
-        for (void *p : tmp) (void)hipFree(p);
-        for (void *p : keep) (void)hipFree(p);
+        for (const DevBlock &b : tmp) A.put(b);
+        for (const DevBlock &b : keep) A.put(b);
         delete G;
         return s;
     };
@@ -536,7 +574,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     const int n_retry = hflags[2];
     int32_t *big_nbr = nullptr;
     if (n_retry > 0) {
-        big_nbr = dalloc<int32_t>((size_t)n_retry * kMaxNbrBig, rc, tmp);
+        big_nbr = dalloc<int32_t>((size_t)n_retry * kMaxNbrBig, rc, tmp, A);
         if (rc != VOR_OK) return fail(rc);
         hipLaunchKernelGGL(k_clip_big, dim3((unsigned)n_retry), dim3(64), 0, st, ca, big_nbr, slot);
         if (hipMemcpyAsync(hflags, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -554,7 +592,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     if (hipMemcpyAsync(&nnz_dir, dir_start + M, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(VOR_EDEVICE);
-    int32_t *dir_col = dalloc<int32_t>(std::max<int32_t>(nnz_dir, 1), rc, tmp);
+    int32_t *dir_col = dalloc<int32_t>(std::max<int32_t>(nnz_dir, 1), rc, tmp, A);
     if (rc != VOR_OK) return fail(rc);
     hipLaunchKernelGGL(k_gather_dir, dim3(blocks_for(M, T)), dim3(T), 0, st, nbr0, cnt0, dir_start, slot, M, big_nbr,
                        dir_col);
@@ -570,7 +608,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
         hipStreamSynchronize(st) != hipSuccess)
         return fail(VOR_EDEVICE);
     g.nnz = nnz32;
-    int32_t *col = dalloc<int32_t>(std::max<int32_t>(nnz32, 1), rc, tmp);
+    int32_t *col = dalloc<int32_t>(std::max<int32_t>(nnz32, 1), rc, tmp, A);
     if (rc != VOR_OK) return fail(rc);
     hipLaunchKernelGGL(k_copy_rows, dim3(blocks_for(M, T)), dim3(T), 0, st, dir_col, dir_start, cnt0, start, M, col,
                        extra);
@@ -581,9 +619,9 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     // cell blocks are addressed by 32-bit slot offsets
     const int64_t nslots = g.nnz + (int64_t)kHdrSlots * M;
     if (nslots + kRecPad > 0x7fffffffLL) return fail(VOR_ECAPACITY);
-    g.rows = dalloc<int2>(M, rc, keep);
-    g.rec64 = dalloc<Rec64>(g.nnz + kRecPad, rc, keep);
-    g.blk = dalloc<Slot>(nslots + kRecPad, rc, keep);
+    g.rows = dalloc<int2>(M, rc, keep, A);
+    g.rec64 = dalloc<Rec64>(g.nnz + kRecPad, rc, keep, A);
+    g.blk = dalloc<Slot>(nslots + kRecPad, rc, keep, A);
     if (rc != VOR_OK) return fail(rc);
     if (hipMemsetAsync(g.rec64 + g.nnz, 0, sizeof(Rec64) * kRecPad, st) != hipSuccess ||
         hipMemsetAsync(g.blk + nslots, 0, sizeof(Slot) * kRecPad, st) != hipSuccess)
@@ -621,9 +659,9 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
             K *= n;
         }
         if (K >= 0x7fffffffLL) return fail(VOR_ECAPACITY);
-        int32_t *lcnt = dalloc<int32_t>(K, rc, tmp);
-        unsigned long long *ltot = dalloc<unsigned long long>(1, rc, tmp);
-        g.loc_start = dalloc<int32_t>(K + 1, rc, keep);
+        int32_t *lcnt = dalloc<int32_t>(K, rc, tmp, A);
+        unsigned long long *ltot = dalloc<unsigned long long>(1, rc, tmp, A);
+        g.loc_start = dalloc<int32_t>(K + 1, rc, keep, A);
         if (rc != VOR_OK) return fail(rc);
         if (hipMemsetAsync(lcnt, 0, sizeof(int32_t) * K, st) != hipSuccess ||
             hipMemsetAsync(ltot, 0, sizeof(unsigned long long), st) != hipSuccess)
@@ -636,7 +674,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
         if (entries >= 0x7fffffffULL) return fail(VOR_ECAPACITY);
         rc = vrt_scan_i32_to_i32(lcnt, K, g.loc_start, st);
         if (rc != VOR_OK) return fail(rc);
-        g.loc_cells = dalloc<int32_t>(std::max<unsigned long long>(entries, 1), rc, keep);
+        g.loc_cells = dalloc<int32_t>(std::max<unsigned long long>(entries, 1), rc, keep, A);
         if (rc != VOR_OK) return fail(rc);
         if (hipMemsetAsync(lcnt, 0, sizeof(int32_t) * K, st) != hipSuccess) return fail(VOR_EDEVICE);
         hipLaunchKernelGGL(k_loc_fill, dim3(blocks_for(M, T)), dim3(T), 0, st, la, g.loc_start, lcnt, g.loc_cells);
@@ -644,7 +682,9 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
         g.loc_entries = (int64_t)entries;
     }
 
-    for (void *p : tmp) (void)hipFree(p);
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(VOR_EDEVICE);
+    for (const DevBlock &b : tmp) A.put(b);
+    tmp.clear();
     g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + 2 * sizeof(double)) + (B + 1) * 4 +
                      (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Slot);
     if (want_loc)
@@ -659,11 +699,7 @@ extern "C" void vor_grid_free(vor_grid *G)
 {
     if (!G) return;
     (void)hipDeviceSynchronize();
-    Grid &g = G->g;
-    void *ptrs[] = {g.sites, g.perm, g.inv_perm, g.rows, g.rec64, g.blk, g.wall_mask, g.volume, g.bucket_start,
-                    g.bucket_sites, g.bbox, g.loc_start, g.loc_cells, g.rho_int};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    for (const DevBlock &b : G->owned) G->alloc.put(b);
     delete G;
 }
 

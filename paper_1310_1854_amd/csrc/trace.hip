@@ -544,21 +544,31 @@ extern "C" vor_status vor_locate(const vor_grid *G, const double *pts, int64_t N
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
-// Launch of the trace kernel: one ray per lane, or persistent waves (as
-// many blocks as fit on the device at once).
+// Resident blocks per compute unit of a persistent trace kernel (a property
+// of the compiled kernel: queried once per process).
 template <int MODE, bool SEGS, bool EXT>
-vor_status launch_trace_ext(const TraceArgs &A, bool persistent, hipStream_t st)
+int persistent_blocks_per_cu()
+{
+    static const int per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<MODE, SEGS, EXT>, 256, 0) !=
+                hipSuccess ||
+            n < 1)
+            n = 1;
+        return n;
+    }();
+    return per_cu;
+}
+
+// Launch of the trace kernel: one ray per lane, or persistent waves (as
+// many blocks as fit on the device at once; cus = the grid's device's
+// compute units, read when the grid was built).
+template <int MODE, bool SEGS, bool EXT>
+vor_status launch_trace_ext(const TraceArgs &A, bool persistent, int cus, hipStream_t st)
 {
     const int T = 256;
     if (persistent) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return VOR_EDEVICE;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_persistent<MODE, SEGS, EXT>, T, 0) !=
-                hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
+        const int per_cu = persistent_blocks_per_cu<MODE, SEGS, EXT>();
         const int64_t blocks = std::min<int64_t>((int64_t)cus * per_cu, (A.N + T - 1) / T);
         hipLaunchKernelGGL((k_trace_persistent<MODE, SEGS, EXT>), dim3((unsigned)std::max<int64_t>(blocks, 1)),
                            dim3(T), 0, st, A);
@@ -569,10 +579,10 @@ vor_status launch_trace_ext(const TraceArgs &A, bool persistent, hipStream_t st)
 }
 
 template <int MODE, bool SEGS>
-vor_status launch_trace(const TraceArgs &A, bool ext, bool persistent, hipStream_t st)
+vor_status launch_trace(const TraceArgs &A, bool ext, bool persistent, int cus, hipStream_t st)
 {
-    return ext ? launch_trace_ext<MODE, SEGS, true>(A, persistent, st)
-               : launch_trace_ext<MODE, SEGS, false>(A, persistent, st);
+    return ext ? launch_trace_ext<MODE, SEGS, true>(A, persistent, cus, st)
+               : launch_trace_ext<MODE, SEGS, false>(A, persistent, cus, st);
 }
 
 extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const double *dirs, int64_t N,
@@ -595,6 +605,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     if (mode != VOR_MODE_FP64 && mode != VOR_MODE_MIXED) return VOR_EINVAL;
     if (opts && (opts->max_steps < 0 || !(opts->eps_mix == 0.0 || (opts->eps_mix >= kEpsMixMin && opts->eps_mix <= 0.25))))
         return VOR_EINVAL;
+    if (opts && !(opts->eps_fb >= 0.0 && opts->eps_fb < 1e300)) return VOR_EINVAL;   // NaN, negative or infinite
     const bool persistent = opts && opts->persistent;
     if (persistent && !out->work) return VOR_EINVAL;
     if (opts && opts->start_given && !out->start_cell) return VOR_EINVAL;
@@ -606,6 +617,7 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     if (opts && opts->grid_density && (density || !g.rho_bound)) return VOR_EINVAL;
     TraceArgs A;
     A.G = grid_ref(g, opts ? opts->max_steps : 0, opts ? opts->eps_mix : 0.0);
+    if (opts && opts->eps_fb > 0.0) A.G.eps_fb = opts->eps_fb;
     A.loc = loc_view(g);
     A.I.origins = origins;
     A.I.dirs = dirs;
@@ -650,10 +662,10 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     }
     const bool ext = A.X.tau_stop || A.X.tally_len || A.X.tally_abs || A.I.enter;   // kernels with the optional features
     const vor_status rc = mode == VOR_MODE_FP64
-                              ? (segs ? launch_trace<VOR_MODE_FP64, true>(A, ext, persistent, st)
-                                      : launch_trace<VOR_MODE_FP64, false>(A, ext, persistent, st))
-                              : (segs ? launch_trace<VOR_MODE_MIXED, true>(A, ext, persistent, st)
-                                      : launch_trace<VOR_MODE_MIXED, false>(A, ext, persistent, st));
+                              ? (segs ? launch_trace<VOR_MODE_FP64, true>(A, ext, persistent, g.cus, st)
+                                      : launch_trace<VOR_MODE_FP64, false>(A, ext, persistent, g.cus, st))
+                              : (segs ? launch_trace<VOR_MODE_MIXED, true>(A, ext, persistent, g.cus, st)
+                                      : launch_trace<VOR_MODE_MIXED, false>(A, ext, persistent, g.cus, st));
     if (rc != VOR_OK) return rc;
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }

@@ -98,6 +98,7 @@ struct Grid {
     double build_ms = 0;
     int64_t device_bytes = 0;
     int device = 0;
+    int cus = 0;                    // compute units of that device (sizes the persistent launches)
 };
 
 // Per-ray status codes (same values as VOR_RAY_*).

@@ -55,7 +55,34 @@ class GridInfo(ctypes.Structure):
 class TraceOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_steps", ctypes.c_int32), ("eps_mix", ctypes.c_double),
                 ("persistent", ctypes.c_int32), ("start_given", ctypes.c_int32), ("enter", ctypes.c_int32),
-                ("grid_density", ctypes.c_int32)]
+                ("grid_density", ctypes.c_int32), ("eps_fb", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """vor_allocator: device memory for a grid's arrays."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+def torch_allocator() -> Allocator:
+    """A vor_allocator over torch's caching allocator: the grid's arrays come
+    from (and go back to) the same pool as torch's tensors. Keep the returned
+    object alive as long as any grid built with it (Grid does)."""
+    def _alloc(nbytes, ctx, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except RuntimeError:   # out of memory: the library reports VOR_ENOMEM
+            return None
+
+    def _free(ptr, nbytes, ctx, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    a._keep = (_alloc, _free)
+    return a
 
 
 class TraceOut(ctypes.Structure):
@@ -96,7 +123,7 @@ def load(path: str = None):
         raise RuntimeError(f"libvoronoi_rt.so not built at {path}; run paper_1310_1854_amd.build_lib")
     lib = ctypes.CDLL(path)
     P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
-    lib.vor_build_grid.argtypes = [P, I64, P, P, P, ctypes.POINTER(P)]
+    lib.vor_build_grid.argtypes = [P, I64, P, P, P, P, ctypes.POINTER(P)]
     lib.vor_build_grid.restype = ctypes.c_int
     lib.vor_grid_free.argtypes = [P]
     lib.vor_grid_free.restype = None
@@ -181,10 +208,11 @@ def _dev_f64(x, shape_last=None, device=None) -> torch.Tensor:
 class Grid:
     """A built grid (owns the library's vor_grid)."""
 
-    def __init__(self, handle: int, M: int, box):
+    def __init__(self, handle: int, M: int, box, allocator: Optional[Allocator] = None):
         self._h = ctypes.c_void_p(handle)
         self.M = M
         self.box = [float(b) for b in box]
+        self._allocator = allocator   # its callbacks must outlive the grid
 
     @property
     def handle(self):
@@ -245,16 +273,19 @@ class Grid:
 
 
 def build_grid(sites, box: Sequence[float], bucket_occupancy: float = 0.0, block_lists: bool = False,
-               block_occupancy: float = 0.0, stream=None) -> Grid:
+               block_occupancy: float = 0.0, allocator: Optional[Allocator] = None, stream=None) -> Grid:
     """vor_build_grid; block_lists also builds the block-list locate
-    structure (vor_locate_blocks) and keeps the cells' bounding boxes."""
+    structure (vor_locate_blocks) and keeps the cells' bounding boxes;
+    allocator (e.g. torch_allocator()): where the grid's device memory
+    comes from (default hipMalloc)."""
     sites_d = _dev_f64(sites, 3)
     box_h = (ctypes.c_double * 6)(*[float(b) for b in box])
     opts = BuildOpts(float(bucket_occupancy), 1 if block_lists else 0, float(block_occupancy))
     h = ctypes.c_void_p()
-    _check(load().vor_build_grid(_ptr(sites_d), sites_d.shape[0], box_h, ctypes.byref(opts), _stream(stream),
+    _check(load().vor_build_grid(_ptr(sites_d), sites_d.shape[0], box_h, ctypes.byref(opts),
+                                 None if allocator is None else ctypes.byref(allocator), _stream(stream),
                                  ctypes.byref(h)), "vor_build_grid")
-    return Grid(h.value, sites_d.shape[0], box)
+    return Grid(h.value, sites_d.shape[0], box, allocator)
 
 
 def locate(grid: Grid, pts, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -384,7 +415,7 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
                eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, start_given: bool = False,
                tau_stop: Optional[torch.Tensor] = None, tally_len: Optional[torch.Tensor] = None,
                tally_abs: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None,
-               enter: bool = False, grid_density: bool = False, stream=None) -> None:
+               enter: bool = False, grid_density: bool = False, eps_fb: float = 0.0, stream=None) -> None:
     """Enqueue one vor_trace into preallocated buffers (no allocation, no
     sync); with ``ordered`` the rays are first put in coherent order by
     vor_order_rays (buffers made with ordered=True). ``start_given``: the
@@ -413,7 +444,7 @@ def trace_into(grid: Grid, origins: torch.Tensor, dirs: torch.Tensor, density: O
     if start_given and bufs.start_cell is None:
         raise ValueError("start_given needs buffers made with locate_first=True")
     opts = TraceOpts(MODES[mode], int(max_steps), float(eps_mix), 1 if persistent else 0, 1 if start_given else 0,
-                     1 if enter else 0, 1 if grid_density else 0)
+                     1 if enter else 0, 1 if grid_density else 0, float(eps_fb))
     out = bufs.struct(use_order=ordered, tau_stop=tau_stop, tally_len=tally_len, tally_abs=tally_abs,
                       weight=weight)
     _check(load().vor_trace(grid.handle, _ptr(origins), _ptr(dirs), n, _ptr(density), float(kappa),
@@ -424,7 +455,7 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
           segments: str = "exact", seg_stride: int = 64, spill_chunks: int = 0, max_steps: int = 0,
           eps_mix: float = 0.0, persistent: bool = False, ordered: bool = False, locate_first: bool = True,
           tau_stop=None, weight=None, tallies: bool = False, enter: bool = False, grid_density: bool = False,
-          stream=None) -> dict:
+          eps_fb: float = 0.0, stream=None) -> dict:
     """Paths of N rays. ``segments``: "none" (tau only), "stride" (a window
     of ``seg_stride`` slots per ray; longer paths continue in up to
     ``spill_chunks`` chained spill chunks, or report RAY_OVERFLOW), or
@@ -434,8 +465,9 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
     ``tau_stop``: interaction points (stop_cell, stop_s); ``tallies``: the
     per-cell tallies tally_len and tally_abs (with ``weight``); ``enter``:
     rays from outside the box start where they enter it; ``grid_density``:
-    the densities bound with Grid.bind_density. Returns a dict of device
-    tensors."""
+    the densities bound with Grid.bind_density; ``eps_fb``: the no-exit
+    fallback's advance (0: 1e-12 of the box diagonal). Returns a dict of
+    device tensors."""
     o = _dev_f64(origins, 3)
     d = _dev_f64(dirs, 3)
     rho = None if density is None else _dev_f64(density).reshape(-1)
@@ -446,7 +478,7 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
     t_abs = torch.zeros(grid.M, dtype=torch.float64, device="cuda") if tallies else None
     kw = dict(kappa=kappa, mode=mode, max_steps=max_steps, eps_mix=eps_mix, persistent=persistent, ordered=ordered,
               stream=stream, tau_stop=ts, weight=wt, tally_len=t_len, tally_abs=t_abs, enter=enter,
-              grid_density=grid_density)
+              grid_density=grid_density, eps_fb=eps_fb)
     lf = dict(ordered=ordered, locate_first=locate_first, stops=ts is not None)
     if segments == "none":
         b = TraceBuffers(n, **lf)

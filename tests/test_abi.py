@@ -8,12 +8,16 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "voronoi_rt.h")
+DIAG_HEADER = os.path.join(ROOT, "include", "voronoi_rt_diag.h")
 
 
-def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(vor_\w+)\s*\(", text)))
+def _declared(headers=(HEADER, DIAG_HEADER)):
+    names = set()
+    for h in headers:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(vor_\w+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +30,8 @@ def lib():
 
 
 def test_header_declares_the_boundary():
-    names = _declared()
+    names = _declared((HEADER,))
+    assert "vor_grid_truncate_row" not in names   # the diagnostic hook lives in voronoi_rt_diag.h
     for n in ["vor_build_grid", "vor_locate", "vor_trace", "vor_grid_free", "vor_grid_neighbors",
               "vor_grid_get_info", "vor_exclusive_scan", "vor_status_str", "vor_version"]:
         assert n in names
@@ -65,23 +70,26 @@ def test_argument_errors_before_device_work(lib):
     fake = (ctypes.c_double * 30)()
     out = ctypes.c_void_p(1234)
     # no sites
-    assert lib.vor_build_grid(None, 10, box, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert lib.vor_build_grid(None, 10, box, None, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
     assert out.value is None
     # no sites count
-    assert lib.vor_build_grid(fake, 0, box, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
-    assert lib.vor_build_grid(fake, -5, box, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert lib.vor_build_grid(fake, 0, box, None, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert lib.vor_build_grid(fake, -5, box, None, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
     # empty or inverted box, non-finite box
     for b in [(0, -1, -1, 0, 1, 1), (1, -1, -1, -1, 1, 1), (float("nan"), -1, -1, 1, 1, 1),
               (-1, -1, -1, float("inf"), 1, 1)]:
         bb = (ctypes.c_double * 6)(*b)
-        assert lib.vor_build_grid(fake, 10, bb, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+        assert lib.vor_build_grid(fake, 10, bb, None, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
     # no box, no out
-    assert lib.vor_build_grid(fake, 10, None, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
-    assert lib.vor_build_grid(fake, 10, box, None, None, None) == vrt.VOR_EINVAL
+    assert lib.vor_build_grid(fake, 10, None, None, None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    assert lib.vor_build_grid(fake, 10, box, None, None, None, None) == vrt.VOR_EINVAL
     # bad options of the block-list locate structure
     for bl, bo in [(2, 0.0), (-1, 0.0), (1, -1.0), (1, float("nan"))]:
         opts = vrt.BuildOpts(0.0, bl, bo)
-        assert lib.vor_build_grid(fake, 10, box, ctypes.byref(opts), None, ctypes.byref(out)) == vrt.VOR_EINVAL
+        assert lib.vor_build_grid(fake, 10, box, ctypes.byref(opts), None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    # an allocator without its functions
+    bad = vrt.Allocator()
+    assert lib.vor_build_grid(fake, 10, box, None, ctypes.byref(bad), None, ctypes.byref(out)) == vrt.VOR_EINVAL
     # calls on a missing grid
     cell = (ctypes.c_int32 * 10)()
     assert lib.vor_locate(None, fake, 10, cell, None) == vrt.VOR_EINVAL

@@ -260,6 +260,53 @@ def test_no_exit_fallback_recovers(vrt):
         # every advance of the fallback is left out of the segments (R6)
         assert abs(lens.sum() + nfb[r] * eps - L) <= 1e-9 * L, r
     assert n_clean > 0.3 * w.N
+    # a larger advance (opts.eps_fb): the paths still reach the wall, each advance missing from the lengths
+    big = 1e-6
+    c = vrt.trace(grid, w.origins, w.dirs, w.density, mode="mixed", segments="exact", persistent=True,
+                  ordered=True, eps_fb=big)
+    pc = gpu_paths(c)
+    assert np.all(pc["status"] == 0) and pc["n_fallback"].sum() > 100
+    total = int(pc["ray_off"][-1])
+    tot = np.bincount(np.repeat(np.arange(w.N), pc["n_seg"]), weights=pc["seg_len"][:total], minlength=w.N)
+    hit = pc["n_fallback"] > 0
+    assert np.all(np.abs(tot[hit] + pc["n_fallback"][hit] * big - ref["chord"][hit]) <= 1e-9 * ref["chord"][hit])
+    # clean paths do not depend on it
+    clean = pc["n_fallback"] == 0
+    assert np.array_equal(pc["n_seg"][clean], p["n_seg"][clean])
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(vrt.VorError):
+            vrt.trace(grid, w.origins[:10], w.dirs[:10], w.density, segments="none", eps_fb=bad)
+
+
+def test_grid_from_torch_allocator(vrt):
+    """vor_build_grid with a caller allocator (here torch's caching
+    allocator through vor_allocator): the grid's memory is torch's, counted
+    by it and given back at vor_grid_free, and the grid traces the same
+    paths as one built with hipMalloc."""
+    import torch
+    w = W.exp_disc(M=20_000, N=3000, seed=63)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    alloc = vrt.torch_allocator()
+    g1 = vrt.build_grid(w.sites, w.box, block_lists=True, allocator=alloc)
+    held = torch.cuda.memory_allocated() - before
+    info = g1.info()
+    assert held >= 0.9 * info["device_bytes"], (held, info["device_bytes"])
+    g0 = vrt.build_grid(w.sites, w.box, block_lists=True)
+    for mode in ("fp64", "mixed"):
+        a = vrt.trace(g0, w.origins, w.dirs, w.density, mode=mode, segments="exact", persistent=True, ordered=True)
+        b = vrt.trace(g1, w.origins, w.dirs, w.density, mode=mode, segments="exact", persistent=True, ordered=True)
+        for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+            assert torch.equal(a[k], b[k]), (mode, k)
+        del a, b
+    r0, c0 = g0.neighbors()
+    r1, c1 = g1.neighbors()
+    assert torch.equal(r0, r1) and torch.equal(c0, c1)
+    torch.cuda.synchronize()
+    mid = torch.cuda.memory_allocated()
+    g1.free()
+    assert mid - torch.cuda.memory_allocated() >= 0.9 * info["device_bytes"]
+    g0.free()
 
 
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
