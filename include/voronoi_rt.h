@@ -42,8 +42,9 @@ typedef enum {
     VOR_EOUTSIDE = 3,   /* a site lies outside the box or is not finite */
     VOR_ENOMEM = 4,     /* a device allocation failed */
     VOR_EDEVICE = 5,    /* a HIP runtime call or kernel launch failed */
-    VOR_ECAPACITY = 6,  /* a cell needs more faces than the builder's fixed capacity, or the neighbour
-                           tables exceed 2^31 16-byte slots */
+    VOR_ECAPACITY = 6,  /* a cell needs more faces than the builder's fixed capacity, the neighbour
+                           tables exceed 2^31 16-byte slots, or vor_trace_noalloc got more rays than
+                           VOR_NOALLOC_MAX_RAYS */
     VOR_EBUDGET = 7,    /* a serving request exceeds the memory budget */
     VOR_ETIMEOUT = 8    /* a wait ran out of time; the request is still pending */
 } vor_status;
@@ -323,6 +324,31 @@ typedef struct {
 vor_status vor_trace(const vor_grid *grid, const double *origins, const double *dirs, int64_t N,
                      const double *density, double kappa, const vor_trace_opts *opts,
                      const vor_trace_out *out, void *stream);
+
+/* Rays per vor_trace_noalloc call. */
+#define VOR_NOALLOC_MAX_RAYS (1 << 22)
+
+/*
+ * vor_trace_noalloc -- vor_trace for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation. The control words of the work queues and the spill
+ * (vor_trace_out.work) and the start-cell scratch (vor_trace_out.start_cell)
+ * come from a fixed array inside the library, 16 MiB per GPU (the control
+ * words, then the start cells of up to VOR_NOALLOC_MAX_RAYS rays), which
+ * each GPU the library runs on holds until the process ends; the caller
+ * passes the inputs and outputs as to vor_trace, with out->work and
+ * out->start_cell NULL and opts->start_given 0 (VOR_EINVAL otherwise).
+ * Every call on a GPU uses that GPU's one array: calls ordered on one
+ * stream are safe, calls that overlap on one GPU (other streams, other
+ * threads) race and corrupt each other's paths. The first call on a device
+ * looks up the array's address there (hipGetSymbolAddress) with that device
+ * current. Allocates nothing.
+ * Errors: those of vor_trace; VOR_ECAPACITY for N > VOR_NOALLOC_MAX_RAYS;
+ * VOR_EDEVICE if the array cannot be reached.
+ */
+vor_status vor_trace_noalloc(const vor_grid *grid, const double *origins, const double *dirs, int64_t N,
+                             const double *density, double kappa, const vor_trace_opts *opts,
+                             const vor_trace_out *out, void *stream);
 
 /*
  * vor_order_rays -- a processing order for a batch of rays that keeps

@@ -7,6 +7,8 @@
 // overlap the whole step is redone in FP64, otherwise only the winner's
 // crossing is recomputed in FP64. Either way the emitted values are the FP64
 // ones.
+#include <mutex>
+
 #include "trace_core.h"
 
 using namespace vrt;
@@ -670,6 +672,55 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
+// ---------------------------------------------------------------------------
+// vor_trace_noalloc: vor_trace with its scratch (the control words of the
+// work queues and spill, then the start cells of up to VOR_NOALLOC_MAX_RAYS
+// rays) in a fixed array of the library instead of caller buffers. Each GPU
+// holds its own copy of the array; host code reaches it only through the
+// device address hipGetSymbolAddress returns for that GPU, taken once per
+// device on its first call there (the array's name in host code is a
+// host-side stand-in, not that address).
+constexpr int64_t kNoAllocWords = VOR_WORK_WORDS + (VOR_NOALLOC_MAX_RAYS + 1) / 2;
+static __device__ __align__(256) int64_t scratch[kNoAllocWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's scratch array (the current device).
+vor_status device_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return VOR_EDEVICE;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VOR_EDEVICE;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return VOR_OK;
+}
+}  // namespace
+
+extern "C" vor_status vor_trace_noalloc(const vor_grid *G, const double *origins, const double *dirs, int64_t N,
+                                        const double *density, double kappa, const vor_trace_opts *opts,
+                                        const vor_trace_out *out, void *stream)
+{
+    if (!G || !out || N < 0) return VOR_EINVAL;
+    if (out->work || out->start_cell || (opts && opts->start_given)) return VOR_EINVAL;   // the library's own scratch
+    if (N > VOR_NOALLOC_MAX_RAYS) return VOR_ECAPACITY;
+    if (N == 0) return VOR_OK;
+    void *sp = nullptr;
+    const vor_status rc = device_scratch(&sp);
+    if (rc != VOR_OK) return rc;
+    vor_trace_out o = *out;
+    o.work = reinterpret_cast<int64_t *>(sp);                        // zeroed by vor_trace's first kernel
+    o.start_cell = reinterpret_cast<int32_t *>(o.work + VOR_WORK_WORDS);   // written by its start pass
+    return vor_trace(G, origins, dirs, N, density, kappa, opts, &o, stream);
+}
+
 extern "C" int64_t vor_order_workspace_bytes(int64_t N)
 {
     if (N < 0) return -1;
@@ -718,7 +769,7 @@ extern "C" const char *vor_status_str(vor_status s)
     case VOR_EOUTSIDE: return "site outside the box or not finite";
     case VOR_ENOMEM: return "device allocation failed";
     case VOR_EDEVICE: return "HIP runtime or launch failure";
-    case VOR_ECAPACITY: return "cell exceeds the builder's face capacity";
+    case VOR_ECAPACITY: return "capacity exceeded (a cell's faces, the neighbour tables, or vor_trace_noalloc's rays)";
     case VOR_EBUDGET: return "request exceeds the memory budget";
     case VOR_ETIMEOUT: return "timed out";
     }

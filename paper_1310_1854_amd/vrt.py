@@ -31,7 +31,8 @@ EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_nei
            "vor_server_create", "vor_server_submit", "vor_server_poll", "vor_server_wait", "vor_server_result",
            "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy",
            "vor_server_next_done", "vor_grid_truncate_row", "vor_grid_volumes", "vor_grid_bboxes",
-           "vor_locate_blocks", "vor_grid_bind_density"]
+           "vor_locate_blocks", "vor_grid_bind_density", "vor_trace_noalloc"]
+NOALLOC_MAX_RAYS = 1 << 22   # VOR_NOALLOC_MAX_RAYS
 
 
 class VorError(RuntimeError):
@@ -145,6 +146,8 @@ def load(path: str = None):
     lib.vor_grid_bboxes.restype = ctypes.c_int
     lib.vor_trace.argtypes = [P, P, P, I64, P, D, ctypes.POINTER(TraceOpts), ctypes.POINTER(TraceOut), P]
     lib.vor_trace.restype = ctypes.c_int
+    lib.vor_trace_noalloc.argtypes = [P, P, P, I64, P, D, ctypes.POINTER(TraceOpts), ctypes.POINTER(TraceOut), P]
+    lib.vor_trace_noalloc.restype = ctypes.c_int
     lib.vor_order_rays.argtypes = [P, P, P, I64, P, P, I64, P]
     lib.vor_order_rays.restype = ctypes.c_int
     lib.vor_order_workspace_bytes.argtypes = [I64]
