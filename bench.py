@@ -104,7 +104,7 @@ def _traffic_fields(workload: str):
 # chunks (of 64 segments) per ray, coherent ray order, persistent kernel.
 WORKLOADS = {
     "flared_disc": dict(cfg=2, mode="mixed", stride=128, spill_chunks_per_ray=0.5, ordered=True, persistent=True,
-                        cpu_rays=240),
+                        cpu_rays=1000),
     "exp_disc": dict(cfg=1, mode="mixed", stride=128, spill_chunks_per_ray=0.25, ordered=True, persistent=True,
                      cpu_rays=600),
     "clumpy": dict(cfg=3, mode="mixed", stride=128, spill_chunks_per_ray=1.0, ordered=True, persistent=True,
@@ -229,9 +229,10 @@ def cpu_model() -> str:
 
 def cpu_baseline(w, spec, oracle):
     """The oracle (FP64 brute force over all sites) on a bounded sample of
-    the same rays, with all host threads."""
+    the same rays (both origin classes in equal parts where the workload has
+    two), with all host threads."""
     n = min(spec["cpu_rays"], w.N)
-    sub = w.subsample(n, seed=123)
+    sub = w.subsample(n, seed=123, split=w.meta.get("n_central"))
     threads = oracle.get_threads()
     t0 = time.perf_counter()
     ref = oracle.trace(w.sites, w.box, w.density, sub.origins, sub.dirs, cap=4096, segments=True)

@@ -43,11 +43,18 @@ class Workload:
     def N(self) -> int:
         return int(self.origins.shape[0])
 
-    def subsample(self, n: int, seed: int = 7) -> "Workload":
-        """Same grid, a seeded subset of ``n`` rays (for CPU-side checks)."""
+    def subsample(self, n: int, seed: int = 7, split: int = None) -> "Workload":
+        """Same grid, a seeded subset of ``n`` rays (for CPU-side checks).
+        With ``split``, n // 2 rays from [0, split) and the rest from
+        [split, N) (e.g. the flared disc's central and site-origin rays)."""
         n = min(int(n), self.N)
         rng = np.random.default_rng(seed)
-        idx = np.sort(rng.choice(self.N, size=n, replace=False))
+        if split is None:
+            idx = np.sort(rng.choice(self.N, size=n, replace=False))
+        else:
+            a = rng.choice(split, size=min(n // 2, split), replace=False)
+            b = split + rng.choice(self.N - split, size=min(n - a.size, self.N - split), replace=False)
+            idx = np.sort(np.concatenate([a, b]))
         return dataclasses.replace(
             self, origins=np.ascontiguousarray(self.origins[idx]),
             dirs=np.ascontiguousarray(self.dirs[idx]),

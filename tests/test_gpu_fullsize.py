@@ -2,7 +2,13 @@
 launch configuration bench.py times (mode, stride window, spill,
 persistent), checked against the oracle on a seeded sample of rays and by
 properties that hold for every ray (total length = chord, statuses, mixed
-equal to FP64, consecutive cells are listed neighbours)."""
+equal to FP64 segment for segment, consecutive cells are listed
+neighbours). Samples: 10^4 rays on the exponential disc, 2x10^3 on the
+flared disc (10^3 from the central source, 10^3 from sites), 500 on the
+clumpy medium; near-tie rays in them are checked for being one of the
+correct paths."""
+import time
+
 import numpy as np
 import pytest
 
@@ -13,7 +19,7 @@ from pathcmp import compare
 
 pytestmark = pytest.mark.gpu
 
-SAMPLE = {"exp_disc": 300, "flared_disc": 60, "clumpy": 16}
+SAMPLE = {"exp_disc": 10_000, "flared_disc": 2_000, "clumpy": 500}
 TOL = {"fp64": 1e-12, "mixed": 1e-5}
 
 
@@ -77,17 +83,25 @@ def test_full_size_in_bench_configuration(vrt, name):
     rel = (tot - L).abs() / L.clamp_min(1e-300)
     assert float(rel.max()) <= 1e-12, float(rel.max())
 
-    # mixed mode returns exactly the FP64 results on every ray
+    # mixed mode returns exactly the FP64 results on every ray, segment for segment (exact rows)
     if spec["mode"] == "mixed":
-        f = vrt.TraceBuffers(w.N)
-        vrt.trace_into(grid, o, d, rho, f, mode="fp64")
+        kw = dict(segments="exact", persistent=True, ordered=True)
+        a = vrt.trace(grid, o, d, rho, mode="fp64", **kw)
+        b = vrt.trace(grid, o, d, rho, mode="mixed", **kw)
         torch.cuda.synchronize()
-        assert torch.equal(f.tau, bufs.tau) and torch.equal(f.n_seg, bufs.n_seg)
+        assert torch.equal(a["tau"], bufs.tau) and torch.equal(a["n_seg"], bufs.n_seg)
+        for key in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+            assert torch.equal(a[key], b[key]), key
+        del a, b
 
     # a seeded sample against the oracle, segment by segment
-    sub = w.subsample(SAMPLE[name], seed=99)
+    split = w.meta.get("n_central")
+    sub = w.subsample(SAMPLE[name], seed=99, split=split)
     ridx = sub.meta["ray_index"]
+    t0 = time.perf_counter()
     ref = oracle.trace(w.sites, w.box, w.density, sub.origins, sub.dirs, cap=8192)
+    print(f"[fullsize] {name}: oracle on {sub.N} rays, {int(ref['nseg'].sum())} crossings, "
+          f"{time.perf_counter() - t0:.1f} s", flush=True)
     n_all = n_seg.cpu().numpy()
     res = dict(n_seg=bufs.n_seg, seg_cell=bufs.seg_cell, seg_len=bufs.seg_len, seg_stride=stride,
                ray_off=torch.arange(0, (w.N + 1) * stride, stride, device="cuda"), spill_first=bufs.spill_first,
@@ -101,16 +115,21 @@ def test_full_size_in_bench_configuration(vrt, name):
         off.append(off[-1] + len(c))
     p = dict(tau=bufs.tau.cpu().numpy()[ridx], n_seg=n_all[ridx], status=status[ridx],
              seg_cell=np.concatenate(cells), seg_len=np.concatenate(lens), ray_off=np.array(off))
-    st = compare(p, ref, TOL[spec["mode"]])
-    print(f"[fullsize] {name}: {st}", flush=True)
-    assert st["clean"] >= 0.9 * len(ridx)
-
-    # consecutive cells of the sampled paths are neighbours in the grid's lists
     rp, col = grid.neighbors()
     rp, col = rp.cpu().numpy(), col.cpu().numpy()
-    for c in cells:
-        for a, b in zip(c[:-1], c[1:]):
-            assert b in col[rp[a]:rp[a + 1]]
+    geo = dict(sites=w.sites, box=w.box, density=w.density, kappa=w.kappa, origins=sub.origins, dirs=sub.dirs,
+               nbr=(rp, col))
+    st = compare(p, ref, TOL[spec["mode"]], geo=geo)
+    print(f"[fullsize] {name}: {st}", flush=True)
+    assert st["clean"] >= 0.9 * len(ridx)
+    if split is not None:   # both origin classes are in the sample
+        assert (ridx < split).sum() == len(ridx) // 2
+
+    # consecutive cells of the sampled paths free of near-ties are neighbours in the grid's lists
+    for i, c in enumerate(cells):
+        if ref["n_near"][i] == 0:
+            for a, b in zip(c[:-1], c[1:]):
+                assert b in col[rp[a]:rp[a + 1]]
 
 
 def test_locate_blocks_full_size(vrt):

@@ -33,6 +33,13 @@ def vrt():
     return v
 
 
+def _geo(grid, w, origins, dirs):
+    """What pathcmp needs to check near-tie paths for validity."""
+    rp, col = grid.neighbors()
+    return dict(sites=w.sites, box=w.box, density=w.density, kappa=w.kappa, origins=origins, dirs=dirs,
+                nbr=(rp.cpu().numpy(), col.cpu().numpy()))
+
+
 def _trace(vrt, grid, w, mode, segments="exact", **kw):
     out = vrt.trace(grid, w.origins, w.dirs, w.density, kappa=w.kappa, mode=mode, segments=segments, **kw)
     return gpu_paths(out)
@@ -115,7 +122,7 @@ def test_uniform_cube_all_rays(vrt, cube, mode, segments, persistent, ordered):
             off.append(off[-1] + len(c))
         p.update(seg_cell=np.concatenate(cells), seg_len=np.concatenate(lens), ray_off=np.array(off))
         assert int(out["work"][2].item()) == int((p["n_seg"] > 8).sum()) > 0
-    st = compare(p, ref, TOL[mode])
+    st = compare(p, ref, TOL[mode], geo=_geo(grid, w, w.origins, w.dirs))
     assert st["clean"] > 0.99 * w.N
     if mode == "fp64":
         assert st["max_len_diff"] == 0.0 and st["max_tau_diff"] == 0.0
@@ -334,7 +341,7 @@ def test_rays_from_outside_enter_the_box(vrt, mode, persistent):
     out = vrt.trace(vrt_grid(vrt, w), o, d, w.density, mode=mode, segments="exact", persistent=persistent,
                     ordered=persistent, enter=True)
     p = gpu_paths(out)
-    st = compare(p, ref, TOL[mode])
+    st = compare(p, ref, TOL[mode], geo=_geo(vrt_grid(vrt, w), w, o, d))
     assert st["clean"] > 0.95 * (ref["status"] == 0).sum()
     if mode == "fp64":
         assert st["max_len_diff"] == 0.0 and st["max_tau_diff"] == 0.0
@@ -416,9 +423,10 @@ def test_mixed_equals_fp64_on_grazing_rays(vrt):
     p, redo = _mixed_vs_fp64(vrt, grid, w)
     assert redo > 0                          # the untrusted band was hit
     ref = oracle.trace(w.sites, w.box, w.density, w.origins, w.dirs, cap=64)
-    st = compare(p, ref, TOL["fp64"])
+    st = compare(p, ref, TOL["fp64"], geo=_geo(grid, w, w.origins, w.dirs))
     assert st["max_len_diff"] == 0.0 and st["max_tau_diff"] == 0.0
-    assert st["clean"] > 0.8 * n_r          # the rest start within 1e-9 of a face (near-ties)
+    assert st["clean"] > 0.8 * n_r          # the rest start within 1e-9 of a face (near-ties) ...
+    assert st["near_segments"] > 0          # ... and are checked for being correct paths
 
     # the cubic lattice: rays nearly along its faces from random points
     w = W.cubic_lattice(8, N=3000, seed=4302)
