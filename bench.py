@@ -45,7 +45,10 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1310_1854_amd/csrc/trace.hip", "paper_1310_1854_amd/csrc/trace_core.h",
                   "paper_1310_1854_amd/csrc/vrt_internal.h", "include/voronoi_rt.h",
                   "paper_1310_1854_amd/build_lib.py")
-TRAFFIC_SUMMARY = "profiles/k_trace_flared_disc_1e6_mixed_traffic.md"
+# Counter summaries of the trace kernel per workload (profiles/).
+TRAFFIC_SUMMARIES = {"flared_disc": "profiles/k_trace_flared_disc_1e6_mixed_traffic.md",
+                     "exp_disc": "profiles/k_trace_exp_disc_1e5_mixed_traffic.md",
+                     "clumpy": "profiles/k_trace_clumpy_4e6_mixed_traffic.md"}
 
 
 def kernel_source_hash() -> str:
@@ -82,8 +85,9 @@ def measured_traffic(workload: str):
 
 
 def _traffic_fields(workload: str):
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
-    if not os.path.exists(path):
+    rel = TRAFFIC_SUMMARIES.get(workload)
+    path = os.path.join(ROOT, rel) if rel else None
+    if not path or not os.path.exists(path):
         return None, "no counter summary", {}
     fields = {}
     with open(path) as fh:
@@ -96,7 +100,7 @@ def _traffic_fields(workload: str):
     if fields.get("kernel_source_sha256_16") != kernel_source_hash():
         return None, "kernel sources changed since the counters were taken", fields
     try:
-        return float(fields["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY, fields
+        return float(fields["traffic_bytes_per_launch"]), rel, fields
     except (KeyError, ValueError):
         return None, "counter summary lacks traffic_bytes_per_launch", fields
 
@@ -106,10 +110,11 @@ WORKLOADS = {
     "flared_disc": dict(cfg=2, mode="mixed", stride=128, spill_chunks_per_ray=0.5, ordered=True, persistent=True,
                         cpu_rays=1000),
     "exp_disc": dict(cfg=1, mode="mixed", stride=128, spill_chunks_per_ray=0.25, ordered=True, persistent=True,
-                     cpu_rays=600),
+                     cpu_rays=600, cpu_rays_configs=600),
     "clumpy": dict(cfg=3, mode="mixed", stride=128, spill_chunks_per_ray=1.0, ordered=True, persistent=True,
-                   cpu_rays=60),
-    "uniform_cube": dict(cfg=0, mode="fp64", stride=64, spill_chunks_per_ray=0.25, ordered=True, cpu_rays=10000),
+                   cpu_rays=60, cpu_rays_configs=60),
+    "uniform_cube": dict(cfg=0, mode="fp64", stride=64, spill_chunks_per_ray=0.25, ordered=True, cpu_rays=10000,
+                         cpu_rays_configs=10000),
     # the same disc with transport: each ray stops where tau reaches -ln u (seeded u), and both per-cell
     # tallies are deposited; kappa = 1e-3 puts the mean optical depth of the full paths near 0.9
     "flared_disc_transport": dict(cfg=2, mode="mixed", stride=128, spill_chunks_per_ray=0.5, ordered=True,
@@ -572,6 +577,10 @@ def main(argv=None):
     ap.add_argument("--serving-density", choices=["grid", "array"], default="grid",
                     help="serving: densities bound to the resident grids, or passed with every request")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="default workload only: leave out the other configurations' block")
+    ap.add_argument("--config-requests", type=int, default=600,
+                    help="requests of the serving-precision entry of the configurations block")
     ap.add_argument("--roofline-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, three elementwise copies of 512 MiB (float64 negation) whose "
@@ -597,9 +606,55 @@ def main(argv=None):
     if args.workload == "grid_quality":
         torch.cuda.set_device(0)
         return grid_quality(args, torch, vrt, workloads)
-    spec = WORKLOADS[args.workload]
-    mode = spec["mode"]
     torch.cuda.set_device(0)
+    result = measure(args, torch, vrt, workloads, args.workload, args.steps, args.warmup, args.roofline_reps,
+                     with_cpu=not args.no_cpu)
+    if args.workload == "flared_disc" and not args.no_configs:
+        # the other configurations on the same line: their own rates, rooflines and accuracy
+        cfgs = {}
+        for name in ("exp_disc", "clumpy", "uniform_cube"):
+            torch.cuda.empty_cache()
+            cfgs[name] = measure(args, torch, vrt, workloads, name, 5, 1, 3, with_cpu=not args.no_cpu,
+                                 cpu_rays=WORKLOADS[name]["cpu_rays_configs"])
+            print(f"[bench] {name}: {cfgs[name]['value']:.3e} crossings/s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        cfgs["serving_precision"] = serving_precision_result(torch, vrt, workloads, args.config_requests, 32.0,
+                                                             with_load=False)
+        print(f"[bench] serving precision: {cfgs['serving_precision']['rate']:.3e} crossings/s", file=sys.stderr,
+              flush=True)
+        result["configs"] = cfgs
+    result["paper_context"] = PAPER_TABLE2
+    print(json.dumps(result), flush=True)
+    if args.copy_calibration:
+        copy_calibration(torch)
+
+
+# The paper's own timing (Table 2, Sect. 3.4), quoted as context: the time
+# per Voronoi cell crossing of its CPU implementation on one core of a
+# desktop computer (model not stated), whole photon-shooting phase divided
+# by the cells crossed; and the octree grid's time on the same models.
+PAPER_TABLE2 = {
+    "source": "Table 2 (Sect. 3.4): time per cell crossing, one core of a desktop computer, CPU model and "
+              "precision not stated; elapsed time of the whole photon-shooting phase / cells crossed",
+    "voronoi_ns_per_crossing": {"torus_monochromatic": 693, "torus_panchromatic": 1006,
+                                "spiral_monochromatic": 903, "spiral_panchromatic": 1095},
+    "octree_ns_per_crossing": {"torus_monochromatic": 219, "torus_panchromatic": 400,
+                               "spiral_monochromatic": 309, "spiral_panchromatic": 442},
+    "voronoi_crossings_per_s_one_core": [1e9 / 1095, 1e9 / 693],
+    "cells": {"torus": "about 950,000, uniform", "spiral": "about 1,350,000, density-weighted"},
+}
+
+
+def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, with_cpu, cpu_rays=None):
+    """One workload of WORKLOADS: warmup, then `steps` timed steps; the trace
+    kernel alone for the roofline; FP64 on the same batch; the oracle on a
+    sample (with_cpu). Returns the result dict."""
+    spec = WORKLOADS[name]
+    if cpu_rays is not None:
+        spec = dict(spec, cpu_rays=cpu_rays)
+    args = argparse.Namespace(**dict(vars(args), workload=name, steps=steps, warmup=warmup,
+                                     roofline_reps=roofline_reps, no_cpu=not with_cpu))
+    mode = spec["mode"]
     t0 = time.perf_counter()
     w = workloads.make_config(spec["cfg"])
     print(f"[bench] workload {w.name}: {w.M} sites, {w.N} rays ({time.perf_counter() - t0:.1f} s)",
@@ -742,9 +797,11 @@ def main(argv=None):
                 np.max(np.abs(g_s - it["s"])[clean] / ref["chord"][clean])) if clean.any() else 0.0
     if spec.get("transport"):
         result["transport"] = transport_check(vrt, torch, grid, o, d, rho, bufs, spec, mode)
-    print(json.dumps(result), flush=True)
-    if args.copy_calibration:
-        copy_calibration(torch)
+    del bufs, fb
+    grid.free()
+    return result
+
+
 
 
 def transport_check(vrt, torch, grid, o, d, rho, bufs, spec, mode):

@@ -827,3 +827,56 @@ def test_every_store_path_gives_the_exact_paths(vrt, cube, mode):
             c, l = vrt.ray_path(out, r, host)
             assert np.array_equal(c, cells[off[r]:off[r + 1]]), (stride, r)
             assert np.array_equal(l, lens[off[r]:off[r + 1]]), (stride, r)
+
+
+def _host_paths(out, n):
+    """Every ray's (cells, lengths) of a stride-window trace result: its
+    window, then its spill chain (arrays copied to the host once)."""
+    stride = out["seg_stride"]
+    ns = out["n_seg"].cpu().numpy()
+    wc = out["seg_cell"].cpu().numpy()[:n * stride].reshape(n, stride)
+    wl = out["seg_len"].cpu().numpy()[:n * stride].reshape(n, stride)
+    first = out["spill_first"].cpu().numpy()
+    nxt = out["spill_next"].cpu().numpy()
+    sc, sl = out["spill_cell"].cpu().numpy(), out["spill_len"].cpu().numpy()
+    ch = 64
+    paths = []
+    for r in range(n):
+        k = int(ns[r])
+        cs, ls = [wc[r, :min(k, stride)]], [wl[r, :min(k, stride)]]
+        c, left = int(first[r]), k - stride
+        while left > 0:
+            assert c >= 0, r
+            m = min(left, ch)
+            cs.append(sc[c * ch:c * ch + m])
+            ls.append(sl[c * ch:c * ch + m])
+            left -= m
+            c = int(nxt[c])
+        paths.append((np.concatenate(cs), np.concatenate(ls)))
+    return paths
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_store_groups_on_long_paths(vrt, mode):
+    """Paths of about 30 segments (a 10^5-site cube) through windows of 16,
+    32, 40 and 48 slots: cells stored 16 at a time on 16-slot windows (also
+    beyond the first group of a window), 8 at a time on 8-slot ones, every
+    count of cells left over at a path's end (mod 16), and paths past the
+    window continuing in spill chains -- all equal to the exact CSR output."""
+    import torch
+    w = W.uniform_cube(M=100_000, N=4000, seed=4311)
+    grid = vrt_grid(vrt, w)
+    ex = vrt.trace(grid, w.origins, w.dirs, w.density, mode=mode, segments="exact", persistent=True, ordered=True)
+    ns = ex["n_seg"].cpu().numpy()
+    off = ex["ray_off"].cpu().numpy()
+    cells = ex["seg_cell"].cpu().numpy()
+    lens = ex["seg_len"].cpu().numpy()
+    assert len(set((ns % 16).tolist())) == 16          # every count of cells held back at the end
+    for stride in (16, 32, 40, 48):
+        out = vrt.trace(grid, w.origins, w.dirs, w.density, mode=mode, segments="stride", seg_stride=stride,
+                        spill_chunks=20000, persistent=True, ordered=True)
+        assert torch.equal(out["tau"], ex["tau"]) and torch.equal(out["n_seg"], ex["n_seg"])
+        assert int(out["work"][2].item()) == int((ns > stride).sum()) > 0
+        for r, (c, l) in enumerate(_host_paths(out, w.N)):
+            assert np.array_equal(c, cells[off[r]:off[r + 1]]), (stride, r)
+            assert np.array_equal(l, lens[off[r]:off[r + 1]]), (stride, r)
