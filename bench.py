@@ -745,6 +745,7 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
         "crossings_per_step": crossings,
         "rays_past_window_per_step": spilled,
         "records_per_step": recs_per_step,
+        "lane_utilization": kc[3] / (64.0 * kc[5]) if kc[5] > 0 else None,
         "fp64_redecision_rate": c[2] / max(c[3], 1),
         "fallback_rate": c[1] / max(c[0], 1),
         "eps_mix": 2.0 ** -20,

@@ -352,10 +352,16 @@ vor_status vor_trace_noalloc(const vor_grid *grid, const double *origins, const 
 
 /*
  * vor_order_rays -- a processing order for a batch of rays that keeps
- * neighbouring lanes on neighbouring paths: rays sorted by the Hilbert
- * index of their origin (10 bits per axis over the grid's box) and, among
- * equal origins, of their direction. Pass it as vor_trace_out.ray_order;
- * results do not depend on the order, only the speed does.
+ * neighbouring lanes on neighbouring paths and starts long paths first: the
+ * rays sorted by the Hilbert index of their origin (10 bits per axis over
+ * the grid's box) and, among equal origins, of their direction, cut into 8
+ * contiguous parts (the parts a persistent trace gives its XCDs), and inside
+ * each part grouped by the length of their chord (the distance to the wall
+ * they head for, Eq. 5 on every axis; 8 groups ranked over the batch), the
+ * longest first, keeping that order within a group (batches of fewer than
+ * 2^17 rays keep the first order alone). Pass it as
+ * vor_trace_out.ray_order; results do not depend on the order, only the
+ * speed does.
  *   origins, dirs  device, N x 3.   order  device, N int32 (a permutation).
  *   workspace      device, at least vor_order_workspace_bytes(N) bytes.
  * Asynchronous; allocates nothing.

@@ -450,27 +450,64 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
 }
 
 // Sort keys of a ray: Hilbert index of its origin (10 bits per axis over the
-// box) and of its direction ((k/|k| + 1)/2 over the unit cube).
+// box) and of its direction ((k/|k| + 1)/2 over the unit cube), and its
+// chord -- the distance to the wall it heads for (Eq. 5 on every axis) --
+// as a 16-bit key that is smallest for the longest chords (0 for rays
+// without one).
+struct OrderBox {
+    double lo[3], hi[3], scale[3], diag;
+};
+
 __global__ void k_ray_keys(const double *__restrict__ origins, const double *__restrict__ dirs, int64_t N,
-                           double lo0, double lo1, double lo2, double s0, double s1, double s2,
-                           uint32_t *__restrict__ okey, uint32_t *__restrict__ dkey, int32_t *__restrict__ idx)
+                           OrderBox B, uint32_t *__restrict__ okey, uint32_t *__restrict__ dkey,
+                           uint32_t *__restrict__ lkey, int32_t *__restrict__ idx)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const double lo[3] = {lo0, lo1, lo2}, sc[3] = {s0, s1, s2};
     uint32_t qo[3], qd[3];
     double k[3] = {dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
     double kn = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
     if (!(kn > 0.0) || !isfinite(kn)) kn = 1.0;
+    double L = 1e308 * 10.0;
     for (int a = 0; a < 3; ++a) {
-        double f = (origins[3 * i + a] - lo[a]) * sc[a];
-        double g = (k[a] / kn + 1.0) * 512.0;
+        const double r = origins[3 * i + a];
+        const double ka = k[a] / kn;
+        double f = (r - B.lo[a]) * B.scale[a];
+        double g = (ka + 1.0) * 512.0;
         qo[a] = (uint32_t)(f > 0.0 ? (f < 1023.0 ? f : 1023.0) : 0.0);
         qd[a] = (uint32_t)(g > 0.0 ? (g < 1023.0 ? g : 1023.0) : 0.0);
+        if (ka > 0.0) L = fmin(L, (B.hi[a] - r) / ka);
+        else if (ka < 0.0) L = fmin(L, (B.lo[a] - r) / ka);
     }
+    const double frac = (L > 0.0 && L < 1e300) ? fmin(L / B.diag, 1.0) : 0.0;   // NaN origins give 0
     okey[i] = hilbert_key(qo[0], qo[1], qo[2]);
     dkey[i] = hilbert_key(qd[0], qd[1], qd[2]);
+    lkey[i] = (uint32_t)((1.0 - frac) * 65535.0 + 0.5);
     idx[i] = (int32_t)i;
+}
+
+// The chord bin of every ray from its rank in chord order (order = the rays
+// sorted longest chord first): bin = rank * bins / N.
+__global__ void k_rank_bins(const int32_t *__restrict__ order, int64_t N, int bins, uint32_t *__restrict__ bin)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < N) bin[order[r]] = (uint32_t)((r * bins) / N);
+}
+
+// The final sort key of the ray at rank r of the coherent order: its part
+// of the order (the contiguous part a persistent launch gives one XCD),
+// then its chord bin.
+__global__ void k_part_bin_key(const int32_t *__restrict__ order, const uint32_t *__restrict__ bin, int64_t N,
+                               int parts, int bins, uint32_t *__restrict__ key)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < N) key[r] = (uint32_t)((r * parts) / N) * (uint32_t)bins + bin[order[r]];
+}
+
+__global__ void k_iota(int32_t *__restrict__ idx, int64_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) idx[i] = (int32_t)i;
 }
 
 __global__ void k_zero_i64(int64_t *p, int n)
@@ -721,11 +758,23 @@ extern "C" vor_status vor_trace_noalloc(const vor_grid *G, const double *origins
     return vor_trace(G, origins, dirs, N, density, kappa, opts, &o, stream);
 }
 
+// The processing order: the coherent order (origin, then direction) cut
+// into the kParts contiguous parts that a persistent launch hands to its
+// XCDs; inside each part the rays fall in kChordBins groups by chord length
+// (ranked over the whole batch), the longest first, each group in coherent
+// order. Long paths then start early and the end of a part is left to short
+// ones, which shortens the drain where only a few lanes of a wave still
+// work; the parts keep their spatial coherence.
+constexpr int kChordBins = 8;
+// Below this many rays a launch is too short for a drain to matter (and is
+// launch-bound): the order is the coherent one alone.
+constexpr int64_t kChordBinsMinRays = 1 << 17;
+
 extern "C" int64_t vor_order_workspace_bytes(int64_t N)
 {
     if (N < 0) return -1;
     int64_t hl = vrt_radix_hist_len(N);
-    return 4 * N * (int64_t)sizeof(uint32_t) + (2 * hl + 1) * (int64_t)sizeof(int32_t) + 1024;
+    return 6 * N * (int64_t)sizeof(uint32_t) + (2 * hl + 1) * (int64_t)sizeof(int32_t) + 1024;
 }
 
 extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, const double *dirs, int64_t N,
@@ -741,22 +790,45 @@ extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, c
     uint32_t *dkey = okey + N;
     uint32_t *ktmp = dkey + N;
     int32_t *vtmp = (int32_t *)(ktmp + N);
-    int64_t hl = vrt_radix_hist_len(N);
-    int32_t *hist = vtmp + N;
-    (void)hl;
-    double sc[3];
-    for (int a = 0; a < 3; ++a) sc[a] = 1024.0 / (g.box[a + 3] - g.box[a]);
+    uint32_t *lkey = (uint32_t *)(vtmp + N);
+    uint32_t *bins = lkey + N;
+    int32_t *hist = (int32_t *)(bins + N);
+    const int64_t hl = vrt_radix_hist_len(N);
+    OrderBox B;
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        B.lo[a] = g.box[a];
+        B.hi[a] = g.box[a + 3];
+        B.scale[a] = 1024.0 / (g.box[a + 3] - g.box[a]);
+        d2 += (g.box[a + 3] - g.box[a]) * (g.box[a + 3] - g.box[a]);
+    }
+    B.diag = sqrt(d2);
     const int T = 256;
-    hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((N + T - 1) / T)), dim3(T), 0, st, origins, dirs, N, g.box[0],
-                       g.box[1], g.box[2], sc[0], sc[1], sc[2], okey, dkey, order);
+    const unsigned nb = (unsigned)((N + T - 1) / T);
+    hipLaunchKernelGGL(k_ray_keys, dim3(nb), dim3(T), 0, st, origins, dirs, N, B, okey, dkey, lkey, order);
+    const bool chords = N >= kChordBinsMinRays;
+    vor_status rc = VOR_OK;
+    if (chords) {   // chord bins: rank by chord, longest first
+        rc = vrt_radix_sort_pairs(lkey, order, ktmp, vtmp, N, 16, hist, hl, st);
+        if (rc != VOR_OK) return rc;
+        hipLaunchKernelGGL(k_rank_bins, dim3(nb), dim3(T), 0, st, order, N, kChordBins, bins);
+        hipLaunchKernelGGL(k_iota, dim3(nb), dim3(T), 0, st, order, N);
+    }
     // by direction, then stably by origin: rays from one place in similar directions end up together
-    vor_status rc = vrt_radix_sort_pairs(dkey, order, ktmp, vtmp, N, 30, hist, vrt_radix_hist_len(N), st);
+    rc = vrt_radix_sort_pairs(dkey, order, ktmp, vtmp, N, 30, hist, hl, st);
     if (rc != VOR_OK) return rc;
     // the origin keys must follow the same permutation before the second sort
     rc = vrt_gather_u32(okey, order, N, ktmp, st);
     if (rc != VOR_OK) return rc;
-    rc = vrt_radix_sort_pairs(ktmp, order, okey, vtmp, N, 30, hist, vrt_radix_hist_len(N), st);
+    rc = vrt_radix_sort_pairs(ktmp, order, okey, vtmp, N, 30, hist, hl, st);
     if (rc != VOR_OK) return rc;
+    // then stably by (part of the order, chord bin)
+    static_assert(kParts * kChordBins <= 256, "one 8-bit pass sorts by part and bin");
+    if (chords) {
+        hipLaunchKernelGGL(k_part_bin_key, dim3(nb), dim3(T), 0, st, order, bins, N, kParts, kChordBins, lkey);
+        rc = vrt_radix_sort_pairs(lkey, order, ktmp, vtmp, N, 8, hist, hl, st);
+        if (rc != VOR_OK) return rc;
+    }
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
