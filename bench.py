@@ -248,6 +248,38 @@ def cpu_baseline(w, spec, oracle):
                           host_cpus=os.cpu_count(), cpu_model=cpu_model())
 
 
+def paper_algorithm_baseline(vrt, torch, grid, w, bufs, oracle, n_max=100_000):
+    """The paper's own neighbour-list path loop on the host (oracle/nbtrace.c,
+    FP64; Sect. 2.2 with a running point), timed on one core and on all host
+    cores, on a seeded sample of the same rays: the like-for-like CPU
+    counterpart of the paper's single-core timing (Table 2). Its neighbour
+    lists and start cells are those the GPU built and located (the paper
+    times the path loop, not the set-up). Also reported: how many rays it
+    gives the GPU's segment count (its running point rounds differently, so
+    near-ties may resolve otherwise)."""
+    n = min(n_max, w.N)
+    sub = w.subsample(n, seed=321, split=w.meta.get("n_central"))
+    rp, col = grid.neighbors()
+    rp, col = rp.cpu().numpy(), col.cpu().numpy()
+    start = vrt.locate(grid, sub.origins).cpu().numpy()
+    res = {}
+    for label, threads in (("one_core", 1), ("all_cores", os.cpu_count() or 1)):
+        t0 = time.perf_counter()
+        out = oracle.nbtrace(w.sites, w.box, rp, col, w.density, sub.origins, sub.dirs, start, kappa=w.kappa,
+                             threads=threads)
+        dt = time.perf_counter() - t0
+        c = int(out["nseg"].sum())
+        res[label] = {"value": c / dt, "unit": "crossings/s", "cores": threads, "ns_per_crossing": dt / c * 1e9,
+                      "seconds": dt}
+    gpu_n = bufs.n_seg.cpu().numpy()[np.asarray(sub.meta["ray_index"])]
+    res.update(kind="the paper's neighbour-list path loop on the host (FP64, running point; neighbour lists and "
+                    "start cells from the GPU build), labelled baseline, not the oracle",
+               rays=int(n), crossings=int(out["nseg"].sum()), no_exit_events=int(out["fails"].sum()),
+               rays_with_the_gpu_count=float(np.mean(out["nseg"] == gpu_n)),
+               paper_table2_ns_per_crossing_one_core=[693, 1095])
+    return res
+
+
 def grid_quality(args, torch, vrt, workloads):
     """Grid quality (Sect. 3.3, the Table 1 method): the theoretical density
     rho_t and the gridded density rho_g (the density of the cell that holds
@@ -765,6 +797,7 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
     if not args.no_cpu:
         import oracle
         sub, ref, cpu = cpu_baseline(w, spec, oracle)
+        cpu["paper_algorithm"] = paper_algorithm_baseline(vrt, torch, grid, w, bufs, oracle)
         result["cpu_baseline"] = cpu
         # accuracy on the sample: the same rays through the library
         res = vrt.trace(grid, sub.origins, sub.dirs, w.density, mode=mode, segments="exact")

@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
 of the benchmark use this package; the product library never does, and this
 package imports nothing from it.
 
-Three independent CPU implementations live here:
+Three independent CPU implementations of the path definition live here,
+and beside them a baseline for timing only:
 
 * ``oracle.c`` (loaded through ctypes): FP64 brute force over all sites --
   nearest-site location, paths with optical depth and near-tie flags, and
@@ -13,6 +14,10 @@ Three independent CPU implementations live here:
   crossings (tiny inputs only).
 * ``dda.py``: closed-form paths through tensor-product lattices, whose
   Voronoi cells are cuboids.
+* ``nbtrace.c`` (baseline, not an oracle): the paper's own neighbour-list
+  path loop in FP64 on the CPU, on one or several cores, timed beside the
+  GPU for the comparison with the paper's single-core timing; checked
+  against the oracle in tests/test_nbtrace.py.
 """
 from __future__ import annotations
 
@@ -42,11 +47,49 @@ def compile_oracle(src: str, out: str) -> str:
     return out
 
 
+_NB_SRC = os.path.join(_HERE, "nbtrace.c")
+_NB_LIB = os.path.join(_HERE, "libnbtrace.so")
+_nblib = None
+
+
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so."""
+    """Compile oracle.c into liboracle.so (and the nbtrace.c baseline)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         compile_oracle(_SRC, _LIB)
+    if force or not os.path.exists(_NB_LIB) or os.path.getmtime(_NB_LIB) < os.path.getmtime(_NB_SRC):
+        compile_oracle(_NB_SRC, _NB_LIB)
     return _LIB
+
+
+def nbtrace(sites, box, row_ptr, col, density, origins, dirs, start, kappa=1.0, threads=0):
+    """The paper's neighbour-list path loop on the CPU (nbtrace.c): per-ray
+    segment counts, tau and no-exit events. row_ptr/col: neighbour lists
+    (walls -1..-6); start: the start cell of every ray (< 0: no path)."""
+    global _nblib
+    if _nblib is None:
+        if not os.path.exists(_NB_LIB) or os.path.getmtime(_NB_LIB) < os.path.getmtime(_NB_SRC):
+            compile_oracle(_NB_SRC, _NB_LIB)
+        lib = ctypes.CDLL(_NB_LIB)
+        P, I64 = ctypes.c_void_p, ctypes.c_int64
+        lib.nbtrace_paths.argtypes = [P, I64, P, P, P, P, ctypes.c_double, P, P, P, I64, ctypes.c_int, P, P, P]
+        lib.nbtrace_paths.restype = ctypes.c_int
+        _nblib = lib
+    sites = _f64(sites, (-1, 3))
+    box = _f64(box, (6,))
+    origins = _f64(origins, (-1, 3))
+    dirs = _f64(dirs, (-1, 3))
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    st = np.ascontiguousarray(start, dtype=np.int32)
+    rho = None if density is None else _f64(density, (-1,))
+    N = origins.shape[0]
+    out = dict(nseg=np.zeros(N, np.int32), tau=np.zeros(N), fails=np.zeros(N, np.int32))
+    rc = _nblib.nbtrace_paths(_p(sites), sites.shape[0], _p(box), _p(rp), _p(cl), _p(rho), float(kappa),
+                              _p(origins), _p(dirs), _p(st), N, int(threads), _p(out["nseg"]), _p(out["tau"]),
+                              _p(out["fails"]))
+    if rc:
+        raise ValueError("nbtrace_paths: bad arguments")
+    return out
 
 
 def _bind(lib):
