@@ -59,13 +59,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# Record layout of the benchmark grids ("auto", "fp32", "compact"; --records).
+RECORDS = "auto"
+
+
 def build_grid(vrt, w):
     """The grid as the benchmark builds it (set-up, outside the timed steps):
     the neighbour table and the paper's block lists (Sect. 2.3), which the
     start-cell pass of each trace uses, and the workload's density field
     bound to it (vor_grid_bind_density), which the steps read."""
     import torch
-    grid = vrt.build_grid(w.sites, w.box, block_lists=True)
+    grid = vrt.build_grid(w.sites, w.box, block_lists=True, records=RECORDS)
     grid.bind_density(torch.as_tensor(w.density, dtype=torch.float64, device="cuda").contiguous())
     return grid
 
@@ -122,12 +126,14 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str, transport: bool = False) -> float:
+def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str, transport: bool = False,
+                      compact: bool = False) -> float:
     """Bytes the method must move for one launch, from the kernel counters
     c = [segments, fallbacks, fp64 re-decisions, steps, records, ...].
     Per step: the row range (8 B) and, per neighbour record read, its index
-    and site (4 + 24 B in FP64; 4 + 12 B FP32 offset in mixed mode, plus the
-    winner's FP64 site, 24 B, and the FP64 records of re-decided steps).
+    and site (4 + 24 B in FP64; 4 + 12 B FP32 offset in mixed mode, or
+    4 + 8 B over compact records, plus the winner's FP64 site, 24 B, and the
+    FP64 records of re-decided steps).
     Per segment: the cell density (8 B) and the output (4 B cell + 8 B
     length). Per ray: origin and direction (48 B), tau, count and status
     (13 B). With transport, per segment two tally updates (read and write
@@ -140,7 +146,7 @@ def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str, transport: bool = F
     if mode == "fp64":
         b += 28.0 * recs
     else:
-        b += 16.0 * recs + 24.0 * steps + 28.0 * redo * per_step_recs
+        b += (12.0 if compact else 16.0) * recs + 24.0 * steps + 28.0 * redo * per_step_recs
     return b
 
 
@@ -452,7 +458,7 @@ def serving(args, torch, vrt, workloads):
     print(f"[bench] serving grids built: {[g.info()['build_ms'] for g in grids]} ms", file=sys.stderr, flush=True)
     n_req = args.requests
     stride = 32
-    budget = 1 << 30
+    budget = int(args.mix_budget_gib * (1 << 30))
     base = workloads.serving_requests(n_req, grids_w, rate_hz=1.0)
     reqs = [dict(grid=r["grid"], mode=["fp64", "mixed"][r["mode"]], o=torch.as_tensor(r["origins"], device="cuda"),
                  d=torch.as_tensor(r["dirs"], device="cuda"), t=r["t"]) for r in base]
@@ -483,7 +489,8 @@ def serving(args, torch, vrt, workloads):
         "warmup": 1, "ms_per_step": main["seconds"] * 1e3 / len(reqs), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 / f32+f64 (50/50 classes)", "data": "synthetic",
         "config": {"workload": f"serving: 3 resident grids (1e4, 1e5, 1e6 sites), {len(reqs)} Poisson requests "
-                               f"of 256-65536 rays ({total_rays} rays), 50/50 FP64/mixed, 1 GiB output budget, "
+                               f"of 256-65536 rays ({total_rays} rays), 50/50 FP64/mixed, "
+                               f"{args.mix_budget_gib:g} GiB output budget, "
                                f"whole paths ({stride}-slot windows and spill chains), "
                                f"offered load 0.8 of saturation, densities "
                                + ("bound to the grids" if bound else "passed per request"), "requests": len(reqs),
@@ -606,9 +613,12 @@ def main(argv=None):
     ap.add_argument("--workload", default="flared_disc", choices=sorted(WORKLOADS) + ["serving", "serving_precision", "grid_quality"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="serving_precision: output budget (GiB)")
+    ap.add_argument("--mix-budget-gib", type=float, default=1.0, help="serving: output budget (GiB)")
     ap.add_argument("--serving-density", choices=["grid", "array"], default="grid",
                     help="serving: densities bound to the resident grids, or passed with every request")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--records", choices=["auto", "fp32", "compact"], default="auto",
+                    help="record layout of the traced grids (auto: compact for tables beyond the last-level cache)")
     ap.add_argument("--no-configs", action="store_true",
                     help="default workload only: leave out the other configurations' block")
     ap.add_argument("--config-requests", type=int, default=600,
@@ -618,6 +628,8 @@ def main(argv=None):
                     help="after the run, three elementwise copies of 512 MiB (float64 negation) whose "
                          "hardware counters calibrate the trace kernel's")
     args = ap.parse_args(argv)
+    global RECORDS
+    RECORDS = args.records
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -727,7 +739,7 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
                      reuse_order=True)
     kc = bufs.counters.cpu().numpy().astype(np.float64) / args.roofline_reps
     k_avg = float(np.mean(k_ms))
-    alg = algorithmic_bytes(kc, w.N, mode, bool(spec.get("transport")))
+    alg = algorithmic_bytes(kc, w.N, mode, bool(spec.get("transport")), info.get("record_layout") == "compact")
     achieved = alg / (k_avg / 1e3) / 1e9
     recs_per_step = kc[4] / max(kc[3], 1)
 
@@ -771,7 +783,8 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
                    "sites": w.M, "rays": w.N, "mode": mode, "seg_stride": spec["stride"],
                    "ordered": bool(spec.get("ordered", False)),
                    "persistent": bool(spec.get("persistent", False)),
-                   "density": "bound to the grid" if spec.get("grid_density", True) else "array per call"},
+                   "density": "bound to the grid" if spec.get("grid_density", True) else "array per call",
+                   "records": info.get("record_layout")},
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),
         "crossings_per_step": crossings,

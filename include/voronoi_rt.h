@@ -89,7 +89,15 @@ typedef struct {
                                  each listing the cells whose bounding box overlaps it) and keep the cells'
                                  bounding boxes, for vor_locate_blocks and vor_grid_bboxes; 0: not */
     double block_occupancy;   /* with block_lists: about M / block_occupancy blocks (default 1) */
+    int32_t record_layout;    /* the neighbour records that mixed-mode traces read (results are the same either
+                                 way): VOR_RECORDS_AUTO (0, default: compact when the FP32 table would exceed
+                                 512 MiB, i.e. would not stay in the last-level cache), VOR_RECORDS_FP32 (12-byte
+                                 records: each neighbour offset p_j - p_m rounded to FP32) or VOR_RECORDS_COMPACT
+                                 (8-byte records: the offset as three 21-bit integers against a power-of-two
+                                 scale per cell) */
 } vor_build_opts;
+
+enum { VOR_RECORDS_AUTO = 0, VOR_RECORDS_FP32 = 1, VOR_RECORDS_COMPACT = 2 };
 
 /* Facts about a built grid, filled by vor_grid_get_info. */
 typedef struct {
@@ -103,6 +111,7 @@ typedef struct {
     int64_t device_bytes;     /* device memory held by the grid */
     int32_t block_dims[3];    /* blocks of the Sect. 2.3 locate structure (0 if not built) */
     int64_t block_entries;    /* total length of its cell lists */
+    int32_t record_layout;    /* VOR_RECORDS_FP32 or VOR_RECORDS_COMPACT, as built */
 } vor_grid_info;
 
 /* Device memory for a grid's arrays, e.g. from a framework's caching

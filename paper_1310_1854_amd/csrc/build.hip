@@ -300,10 +300,26 @@ __device__ __forceinline__ int wave_max_int(int v)
     return v;
 }
 
+// Slots of a compact block: the header, then 12 bytes per neighbour
+// (8-byte record + 4-byte block offset), rounded up to whole slots.
+__global__ void k_compact_slots(const int32_t *__restrict__ total, int64_t M, int32_t *__restrict__ slots)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) slots[i] = kHdrSlots + (3 * total[i] + 3) / 4;
+}
+
+// The cell blocks and the FP64 records. Block i starts at blk_off[i]
+// (compact) or block_of(row, i); each header records the start of the
+// cell's FP64 row. FP32 blocks hold the offsets p_j - p_m rounded to FP32;
+// compact blocks hold them as 21-bit integers against the cell's scale
+// 2^(E - 19), E the smallest exponent with every offset component below
+// 2^E (so |q| <= 2^19), but at least e_min, so that the box in the cell's
+// units stays far inside the FP32 range; rounding to the nearest integer
+// leaves each component within half a unit of the scale.
 __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__restrict__ col,
                                const int32_t *__restrict__ total, const int32_t *__restrict__ start, int64_t M,
                                int2 *__restrict__ rows, Rec64 *__restrict__ r64, Slot *__restrict__ blk,
-                               int *__restrict__ max_row)
+                               const int32_t *__restrict__ blk_off, int e_min, int *__restrict__ max_row)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int n = 0;
@@ -312,19 +328,31 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
         int s0 = start[i];
         rows[i] = make_int2(s0, n);
         const Site si = sites[i];
-        const int32_t bo = block_of(make_int2(s0, n), (int32_t)i);
+        const int32_t bo = blk_off ? blk_off[i] : block_of(make_int2(s0, n), (int32_t)i);
+        int E = 0;
+        if (blk_off) {
+            double mc = 0.0;
+            for (int e = 0; e < n; ++e) {
+                const Site sj = sites[col[s0 + e]];
+                mc = fmax(mc, fmax(fabs(sj.x - si.x), fmax(fabs(sj.y - si.y), fabs(sj.z - si.z))));
+            }
+            E = mc > 0.0 ? ilogb(mc) + 1 : e_min;
+            E = E < e_min ? e_min : (E > 127 ? 127 : E);
+        }
         BlockHdr h;
         h.x = si.x;
         h.y = si.y;
         h.z = si.z;
         h.uid = (int32_t)si.uid;
         h.j = (int32_t)i;
-        h.len = n;
-        h.pad = 0;
+        h.len = n | (blk_off ? (E + kScaleBias) << 24 : 0);
+        h.row = s0;
         h.rho = 0.0;
         *reinterpret_cast<BlockHdr *>(blk + bo) = h;
-        float *rec = reinterpret_cast<float *>(blk + bo + kHdrSlots);   // n records of 3 floats
-        int32_t *nb = reinterpret_cast<int32_t *>(rec + 3 * n);          // then n block offsets
+        float *rec = reinterpret_cast<float *>(blk + bo + kHdrSlots);           // FP32: n records of 3 floats
+        uint2 *crec = reinterpret_cast<uint2 *>(blk + bo + kHdrSlots);          // compact: n records of 8 bytes
+        int32_t *nb = blk_off ? reinterpret_cast<int32_t *>(crec + n) : reinterpret_cast<int32_t *>(rec + 3 * n);
+        const double sc = ldexp(1.0, kQShift - E);
         for (int e = 0; e < n; ++e) {
             int32_t j = col[s0 + e];
             const Site sj = sites[j];
@@ -335,10 +363,20 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
             a.j = j;
             a.uid = (int32_t)sj.uid;
             r64[s0 + e] = a;
-            rec[3 * e] = (float)(sj.x - si.x);
-            rec[3 * e + 1] = (float)(sj.y - si.y);
-            rec[3 * e + 2] = (float)(sj.z - si.z);
-            nb[e] = block_of(make_int2(start[j], 0), j);
+            if (blk_off) {
+                const uint64_t m21 = (1ull << kQBits) - 1;
+                const uint64_t qx = (uint64_t)(int64_t)rint((sj.x - si.x) * sc) & m21;
+                const uint64_t qy = (uint64_t)(int64_t)rint((sj.y - si.y) * sc) & m21;
+                const uint64_t qz = (uint64_t)(int64_t)rint((sj.z - si.z) * sc) & m21;
+                const uint64_t v = qx | (qy << kQBits) | (qz << (2 * kQBits));
+                crec[e] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+                nb[e] = blk_off[j];
+            } else {
+                rec[3 * e] = (float)(sj.x - si.x);
+                rec[3 * e + 1] = (float)(sj.y - si.y);
+                rec[3 * e + 2] = (float)(sj.z - si.z);
+                nb[e] = block_of(make_int2(start[j], 0), j);
+            }
         }
     }
     int m = wave_max_int(n);
@@ -421,6 +459,21 @@ unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1
 
 }  // namespace
 
+// Cell blocks of more than this many bytes in the FP32 layout do not stay in
+// the last-level cache; the automatic layout makes them compact.
+constexpr int64_t kCompactAutoBytes = 512ll << 20;
+
+// The smallest scale exponent of a compact block: 2^40 below the box
+// diagonal, so that points of the box in a cell's units stay below 2^60
+// (their squares inside the FP32 range); and at least -126.
+static int compact_min_exp(const double box[6])
+{
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) d2 += (box[a + 3] - box[a]) * (box[a + 3] - box[a]);
+    const int e = d2 > 0.0 ? ilogb(sqrt(d2)) - 40 : -126;
+    return e < -126 ? -126 : (e > 127 ? 127 : e);
+}
+
 struct vor_grid {
     vrt::Grid g;
     DevAlloc alloc;                 // where its arrays came from
@@ -439,6 +492,8 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     const bool want_loc = opts && opts->block_lists;
     const double locc = (opts && opts->block_occupancy > 0) ? opts->block_occupancy : 1.0;
     if (opts && (opts->block_lists < 0 || opts->block_lists > 1 || !(opts->block_occupancy >= 0))) return VOR_EINVAL;
+    const int layout = opts ? opts->record_layout : VOR_RECORDS_AUTO;
+    if (layout < VOR_RECORDS_AUTO || layout > VOR_RECORDS_COMPACT) return VOR_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
 
@@ -616,8 +671,23 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
                        extra);
     hipLaunchKernelGGL(k_row_sort, dim3(blocks_for(M, T)), dim3(T), 0, st, col, start, total, M);
 
-    // cell blocks are addressed by 32-bit slot offsets
-    const int64_t nslots = g.nnz + (int64_t)kHdrSlots * M;
+    // cell blocks are addressed by 32-bit slot offsets; FP32 blocks take
+    // kHdrSlots + n slots, compact ones kHdrSlots + ceil(3n / 4)
+    int64_t nslots = g.nnz + (int64_t)kHdrSlots * M;
+    if (nslots + kRecPad > 0x7fffffffLL) return fail(VOR_ECAPACITY);   // compact blocks take no more slots
+    g.compact = layout == VOR_RECORDS_COMPACT || (layout == VOR_RECORDS_AUTO && nslots * 16 > kCompactAutoBytes);
+    if (g.compact) {
+        g.blk_off = dalloc<int32_t>(M + 1, rc, keep, A);
+        if (rc != VOR_OK) return fail(rc);
+        hipLaunchKernelGGL(k_compact_slots, dim3(blocks_for(M, T)), dim3(T), 0, st, total, M, slot);
+        rc = vrt_scan_i32_to_i32(slot, M, g.blk_off, st);
+        if (rc != VOR_OK) return fail(rc);
+        int32_t ns = 0;
+        if (hipMemcpyAsync(&ns, g.blk_off + M, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(VOR_EDEVICE);
+        nslots = ns;
+    }
     if (nslots + kRecPad > 0x7fffffffLL) return fail(VOR_ECAPACITY);
     g.rows = dalloc<int2>(M, rc, keep, A);
     g.rec64 = dalloc<Rec64>(g.nnz + kRecPad, rc, keep, A);
@@ -628,7 +698,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
         return fail(VOR_EDEVICE);
     hdr = err + 1;   // longest row
     hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, col, total, start, M, g.rows,
-                       g.rec64, g.blk, hdr);
+                       g.rec64, g.blk, g.blk_off, compact_min_exp(g.box), hdr);
     // size of the export with walls
     hipLaunchKernelGGL(k_export_counts, dim3(blocks_for(M, T)), dim3(T), 0, st, g.inv_perm, g.rows, g.wall_mask, M,
                        total);
@@ -686,7 +756,8 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     for (const DevBlock &b : tmp) A.put(b);
     tmp.clear();
     g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + 2 * sizeof(double)) + (B + 1) * 4 +
-                     (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Slot);
+                     (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Slot) +
+                     (g.compact ? (M + 1) * 4 : 0);
     if (want_loc)
         g.device_bytes += (int64_t)M * 6 * (int64_t)sizeof(double) +
                           ((int64_t)g.loc_dims[0] * g.loc_dims[1] * g.loc_dims[2] + 1 + g.loc_entries) * 4;
@@ -717,6 +788,7 @@ extern "C" vor_status vor_grid_get_info(const vor_grid *G, vor_grid_info *info)
     info->device_bytes = g.device_bytes;
     for (int a = 0; a < 3; ++a) info->block_dims[a] = g.loc_dims[a];
     info->block_entries = g.loc_entries;
+    info->record_layout = g.compact ? VOR_RECORDS_COMPACT : VOR_RECORDS_FP32;
     return VOR_OK;
 }
 
@@ -748,19 +820,26 @@ extern "C" vor_status vor_grid_truncate_row(vor_grid *G, int64_t site, int32_t k
         hipMemcpy(&rw, g.rows + i, sizeof(rw), hipMemcpyDeviceToHost) != hipSuccess)
         return VOR_EDEVICE;
     if (keep < rw.y) {
-        // the block offsets follow the records: move the first keep of them
-        // to their place after the first keep records
-        float *rec = reinterpret_cast<float *>(g.blk + block_of(rw, i) + kHdrSlots);
+        // the block offsets follow the records (12 or 8 bytes each): move the
+        // first keep of them to their place after the first keep records
+        int32_t bo = block_of(rw, i);
+        if (g.compact && hipMemcpy(&bo, g.blk_off + i, sizeof(bo), hipMemcpyDeviceToHost) != hipSuccess)
+            return VOR_EDEVICE;
+        char *rec = reinterpret_cast<char *>(g.blk + bo + kHdrSlots);
+        const int rbytes = g.compact ? 8 : 12;
         std::vector<int32_t> nb(keep > 0 ? keep : 1);
-        if (keep > 0 && (hipMemcpy(nb.data(), rec + 3 * rw.y, sizeof(int32_t) * keep, hipMemcpyDeviceToHost) !=
+        if (keep > 0 && (hipMemcpy(nb.data(), rec + rbytes * rw.y, sizeof(int32_t) * keep, hipMemcpyDeviceToHost) !=
                              hipSuccess ||
-                         hipMemcpy(rec + 3 * keep, nb.data(), sizeof(int32_t) * keep, hipMemcpyHostToDevice) !=
+                         hipMemcpy(rec + rbytes * keep, nb.data(), sizeof(int32_t) * keep, hipMemcpyHostToDevice) !=
                              hipSuccess))
             return VOR_EDEVICE;
+        BlockHdr *h = reinterpret_cast<BlockHdr *>(g.blk + bo);
+        int32_t len = 0;
+        if (hipMemcpy(&len, &h->len, sizeof(len), hipMemcpyDeviceToHost) != hipSuccess) return VOR_EDEVICE;
+        len = (len & ~kLenMask) | keep;   // the scale exponent stays
         rw.y = keep;
-        BlockHdr *h = reinterpret_cast<BlockHdr *>(g.blk + block_of(rw, i));
         if (hipMemcpy(g.rows + i, &rw, sizeof(rw), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(&h->len, &keep, sizeof(keep), hipMemcpyHostToDevice) != hipSuccess)
+            hipMemcpy(&h->len, &len, sizeof(len), hipMemcpyHostToDevice) != hipSuccess)
             return VOR_EDEVICE;
     }
     return VOR_OK;
@@ -785,13 +864,15 @@ extern "C" vor_status vor_grid_bboxes(const vor_grid *G, double *bbox, void *str
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
-__global__ void k_bind_density(Slot *__restrict__ blk, const int2 *__restrict__ rows, const int32_t *__restrict__ perm,
-                               int64_t M, const double *__restrict__ density, double *__restrict__ rho_int)
+__global__ void k_bind_density(Slot *__restrict__ blk, const int2 *__restrict__ rows,
+                               const int32_t *__restrict__ blk_off, const int32_t *__restrict__ perm, int64_t M,
+                               const double *__restrict__ density, double *__restrict__ rho_int)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     const double r = density ? density[perm[i]] : 0.0;
-    reinterpret_cast<BlockHdr *>(blk + block_of(rows[i], (int32_t)i))->rho = r;
+    const int32_t bo = blk_off ? blk_off[i] : block_of(rows[i], (int32_t)i);
+    reinterpret_cast<BlockHdr *>(blk + bo)->rho = r;
     rho_int[i] = r;
 }
 
@@ -801,7 +882,7 @@ extern "C" vor_status vor_grid_bind_density(vor_grid *G, const double *density, 
     Grid &g = G->g;
     const int T = 256;
     hipLaunchKernelGGL(k_bind_density, dim3(blocks_for(g.M, T)), dim3(T), 0, (hipStream_t)stream, g.blk, g.rows,
-                       g.perm, g.M, density, g.rho_int);
+                       g.blk_off, g.perm, g.M, density, g.rho_int);
     if (hipGetLastError() != hipSuccess) return VOR_EDEVICE;
     g.rho_bound = density ? 1 : 0;
     return VOR_OK;

@@ -258,8 +258,8 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     R.base = ray * rq.seg_stride;
                     R.cap = rq.seg_cell ? rq.seg_stride : 0;
                     if (R.st == RAY_OK) {
-                        ray_begin_at(G, R, rq.n_seg[ray], s0);   // start cell from the launch's start pass
-                        R.rho = (MODE == VOR_MODE_MIXED && (ctx & 2)) ? block_rho(G, R.b) : 0.0;   // mixed mode carries it
+                        ray_begin_at<MODE>(G, R, rq.n_seg[ray], s0);   // start cell from the launch's start pass
+                        R.rho = (MODE != VOR_MODE_FP64 && (ctx & 2)) ? block_rho(G, R.b) : 0.0;   // mixed mode carries it
                         settle(R.rho);
                     } else {
                         R.L = 0.0;
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) k_serve_start(const GridRef *__restrict__
 
 __global__ void k_zero_launch(unsigned int *head, unsigned long long *counters, ReqCount *rc, int n_req)
 {
-    if (threadIdx.x < 2) head[threadIdx.x] = 0;
+    if (threadIdx.x < 3) head[threadIdx.x] = 0;
     if (threadIdx.x < 4) counters[threadIdx.x] = 0;
     for (int q = threadIdx.x; q < n_req; q += blockDim.x) rc[q] = ReqCount{0ull, 0, 0};
 }
@@ -424,7 +424,7 @@ struct Launch {
     int32_t *h_remaining = nullptr, *d_remaining = nullptr;
     ReqCount *d_count = nullptr;                      // per-request spill counter and overflow count
     int32_t *h_flags = nullptr, *d_flags = nullptr;   // host memory, mapped for the device
-    unsigned int *d_head = nullptr;                   // chunk queue heads of the FP64 and the mixed kernel
+    unsigned int *d_head = nullptr;                   // chunk queue heads of the FP64, mixed and compact kernels
     unsigned long long *d_counters = nullptr;
     unsigned long long *h_counters = nullptr;
 };
@@ -468,6 +468,7 @@ struct vor_server {
     std::atomic<bool> stop{false};
     int device = 0;
     int blocks = 1;     // resident blocks of the mixed serving kernel
+    int blocks_c = 1;   // ... of the one for grids with compact records
     int blocks64 = 1;   // ... and of the FP64 one
     vor_status fault = VOR_OK;
     hipStream_t aux = nullptr;   // the scheduler's own copies (segment counts of requests run again)
@@ -554,6 +555,13 @@ struct vor_server {
     // Launch every admitted request that is not yet running on a free stream.
     // Requests are grouped by context (grid, precision class) so that a wave
     // rarely has to switch; chunks are sized for a few per wave.
+    // The kernel a request's chunks run in: 0 FP64, 1 mixed, 2 mixed over a
+    // grid with compact records.
+    int kernel_class(const Request &r) const
+    {
+        return r.mode == VOR_MODE_FP64 ? 0 : (grid_refs[r.grid].blk_off ? 2 : 1);
+    }
+
     void launch_locked(Launch &L)
     {
         L.reqs.clear();
@@ -583,12 +591,13 @@ struct vor_server {
         }
         L.reqs.resize(keep);
         if (L.reqs.empty()) return;   // cannot happen: the requests need at most kMaxLaunchChunks / 2 + kMaxLaunchReqs chunks
-        // precision class first (each class has a kernel of its own), then grid
+        // kernel class first (FP64, mixed, mixed over compact records: each
+        // has a kernel of its own), then grid
         std::stable_sort(L.reqs.begin(), L.reqs.end(), [this](int64_t x, int64_t y) {
-            const Request &a = reqs[x], &b = reqs[y];
-            return (a.mode != b.mode) ? a.mode < b.mode : a.grid < b.grid;
+            const int ka = kernel_class(reqs[x]), kb = kernel_class(reqs[y]);
+            return (ka != kb) ? ka < kb : reqs[x].grid < reqs[y].grid;
         });
-        int nch = 0, n64 = 0;   // chunks, and those of FP64 requests (first)
+        int nch = 0, ncls[3] = {0, 0, 0};   // chunks, and those of each kernel class
         for (size_t qi = 0; qi < L.reqs.size(); ++qi) {
             Request &r = reqs[L.reqs[qi]];
             const int q = (int)qi;
@@ -610,7 +619,7 @@ struct vor_server {
             L.h_remaining[q] = need;
             L.h_flags[q] = 0;
             const int32_t ctx = 4 * r.grid + 2 * r.in.grid_rho + (r.mode == VOR_MODE_MIXED ? 1 : 0);
-            if (r.mode == VOR_MODE_FP64) n64 += need;
+            ncls[kernel_class(r)] += need;
             for (int c = 0; c < need; ++c) {
                 ChunkDev &ch = L.h_chunks[nch++];
                 ch.req = q;
@@ -635,15 +644,20 @@ struct vor_server {
                                  L.stream) == hipSuccess;
         hipLaunchKernelGGL(k_zero_launch, dim3(1), dim3(256), 0, L.stream, L.d_head, L.d_counters, L.d_count, nreq);
         hipLaunchKernelGGL(k_serve_start, dim3(nch), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks, nch);
-        if (n64 > 0) {
-            const int nb = std::max(1, std::min(blocks64, (n64 + 3) / 4));
+        if (ncls[0] > 0) {
+            const int nb = std::max(1, std::min(blocks64, (ncls[0] + 3) / 4));
             hipLaunchKernelGGL(k_serve<VOR_MODE_FP64>, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks,
-                               n64, L.d_head, L.d_counters);
+                               ncls[0], L.d_head, L.d_counters);
         }
-        if (nch > n64) {
-            const int nb = std::max(1, std::min(blocks, (nch - n64 + 3) / 4));
+        if (ncls[1] > 0) {
+            const int nb = std::max(1, std::min(blocks, (ncls[1] + 3) / 4));
             hipLaunchKernelGGL(k_serve<VOR_MODE_MIXED>, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs,
-                               L.d_chunks + n64, nch - n64, L.d_head + 1, L.d_counters);
+                               L.d_chunks + ncls[0], ncls[1], L.d_head + 1, L.d_counters);
+        }
+        if (ncls[2] > 0) {
+            const int nb = std::max(1, std::min(blocks_c, (ncls[2] + 3) / 4));
+            hipLaunchKernelGGL(k_serve<kModeCompact>, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs,
+                               L.d_chunks + ncls[0] + ncls[1], ncls[2], L.d_head + 2, L.d_counters);
         }
         ok = ok && hipGetLastError() == hipSuccess &&
              hipMemcpyAsync(L.h_counters, L.d_counters, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
@@ -852,13 +866,14 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
              hipMalloc(&L.d_count, sizeof(ReqCount) * kMaxLaunchReqs) == hipSuccess &&
              hipMalloc(&L.d_reqs, sizeof(ReqDev) * kMaxLaunchReqs) == hipSuccess &&
              hipMalloc(&L.d_chunks, sizeof(ChunkDev) * kMaxLaunchChunks) == hipSuccess &&
-             hipMalloc(&L.d_head, 2 * sizeof(unsigned int)) == hipSuccess &&
+             hipMalloc(&L.d_head, 3 * sizeof(unsigned int)) == hipSuccess &&
              hipMalloc(&L.d_counters, 4 * sizeof(unsigned long long)) == hipSuccess;
     }
     ok = ok && hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking) == hipSuccess;
-    int cus = 0, per_cu = 0, per_cu64 = 0;
+    int cus = 0, per_cu = 0, per_cu64 = 0, per_cu_c = 0;
     ok = ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess &&
          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve<VOR_MODE_MIXED>, 256, 0) == hipSuccess &&
+         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_c, k_serve<kModeCompact>, 256, 0) == hipSuccess &&
          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_serve<VOR_MODE_FP64>, 256, 0) == hipSuccess;
     if (!ok) {
         vor_server_destroy(S);
@@ -866,6 +881,7 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
     }
     S->blocks = std::max(1, cus * std::max(1, per_cu));
     S->blocks64 = std::max(1, cus * std::max(1, per_cu64));
+    S->blocks_c = std::max(1, cus * std::max(1, per_cu_c));
     S->budget = (size_t)budget_bytes;
     S->free_blocks[0] = S->budget;
     S->t0 = clk::now();

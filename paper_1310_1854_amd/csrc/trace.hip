@@ -213,8 +213,8 @@ __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RaySt
     R.st = ray_setup<EXT>(A.G, A.I, ray, R.r0, R.k, R.L, s0);
     R.tau = 0.0;
     if (R.st == RAY_OK) {
-        if (A.start) ray_begin_at(A.G, R, A.start[ray], s0);
-        else ray_begin(A.G, R, s0);
+        if (A.start) ray_begin_at<MODE>(A.G, R, A.start[ray], s0);
+        else ray_begin<MODE>(A.G, R, s0);
     } else {
         R.L = 0.0;
         R.s_c = 0.0;
@@ -703,6 +703,8 @@ extern "C" vor_status vor_trace(const vor_grid *G, const double *origins, const 
     const vor_status rc = mode == VOR_MODE_FP64
                               ? (segs ? launch_trace<VOR_MODE_FP64, true>(A, ext, persistent, g.cus, st)
                                       : launch_trace<VOR_MODE_FP64, false>(A, ext, persistent, g.cus, st))
+                          : g.compact ? (segs ? launch_trace<kModeCompact, true>(A, ext, persistent, g.cus, st)
+                                              : launch_trace<kModeCompact, false>(A, ext, persistent, g.cus, st))
                               : (segs ? launch_trace<VOR_MODE_MIXED, true>(A, ext, persistent, g.cus, st)
                                       : launch_trace<VOR_MODE_MIXED, false>(A, ext, persistent, g.cus, st));
     if (rc != VOR_OK) return rc;

@@ -21,7 +21,8 @@ struct GridRef {
     const Site *sites;
     const int2 *rows;
     const Rec64 *rec64;
-    const Slot *blk;     // cell blocks (header, FP32 records, neighbour block offsets)
+    const Slot *blk;     // cell blocks (header, FP32 or compact records, neighbour block offsets)
+    const int32_t *blk_off;  // compact blocks: where each cell's block starts (null: FP32 blocks, block_of)
     const double *rho_int;   // the density bound to the grid, internal order
     BucketGridView grid;
     double lo[3], hi[3];
@@ -80,6 +81,10 @@ struct SegOut {
     const SpillPool *pool;          // LP kernels: this lane's pool (in cell and len) instead of the spill arrays above
 };
 
+// The kernels' MODE: VOR_MODE_FP64, VOR_MODE_MIXED, or kModeCompact, mixed
+// mode over a grid with compact records (vrt::Grid::compact).
+constexpr int kModeCompact = 2;
+
 // Smallest accepted eps of the mixed-mode bound (2^-20 = 16u): twice what
 // the rounding analysis of exit_mixed needs.
 constexpr double kEpsMixMin = 9.5367431640625e-07;
@@ -119,6 +124,7 @@ inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
     G.rows = g.rows;
     G.rec64 = g.rec64;
     G.blk = g.blk;
+    G.blk_off = g.compact ? g.blk_off : nullptr;
     G.rho_int = g.rho_int;
     G.grid = bucket_view(g);
     double diag = 0.0, cmax = 0.0;
@@ -284,6 +290,64 @@ __device__ __forceinline__ void wall32(double L, double s_c, float e_abs, float 
     ew = 2.0f * 5.9604645e-8f * fabsf(tw) + e_abs;
 }
 
+// The current point of a ray in a compact cell's scaled units (offsets
+// times qs = 2^(19 - E)), with the constants of the bound: as query32, plus
+// aq, the quantisation term's part that depends on the point alone.
+struct Query32q {
+    float qx, qy, qz;
+    float kx, ky, kz;
+    float c, a, aq;
+};
+
+__device__ __forceinline__ Query32q query32q(const double pm[3], const double r0[3], const double k[3], double s_c,
+                                             float eps, float e_abs_s, double qs)
+{
+    double q64[3];
+    for (int a = 0; a < 3; ++a) q64[a] = ((r0[a] + s_c * k[a]) - pm[a]) * qs;
+    Query32q Q;
+    Q.qx = (float)q64[0];
+    Q.qy = (float)q64[1];
+    Q.qz = (float)q64[2];
+    Q.kx = (float)k[0];
+    Q.ky = (float)k[1];
+    Q.kz = (float)k[2];
+    Q.c = 3.0f * eps;
+    Q.a = fmaf(Q.c, sqrtf(Q.qx * Q.qx + Q.qy * Q.qy + Q.qz * Q.qz), e_abs_s);
+    Q.aq = 0.6667f * (fabsf(Q.qx) + fabsf(Q.qy) + fabsf(Q.qz) + 0.75f);
+    return Q;
+}
+
+// The crossing of one plane of a compact cell (see exit_mixed): the stored
+// offset n is exact in the scaled units and lies within half a unit of the
+// true offset per component. With D = n.k and N = n.(n/2 - q), that moves
+// N by at most (|n|_1 + 3/4 + |q|_1) / 2 and D by at most sqrt(3)/2 < 0.87,
+// so t = N / D moves by at most (|dN| + |t_n| |dD|) / D_true, t_n the exact
+// crossing of the stored plane. With D trusted above 4 (8u |n|_1 + 0.875)
+// (so D_true >= 3/4 D, D >= 3.5) and |t_n| <= |t| + e, e the FP32 rounding
+// bound of plane_bound32 (whose derivation holds for the exact offsets it is
+// given here), that is at most
+//   (4/3) ((|n|_1 + |q|_1 + 3/4) / 2 + 0.866 |t|) / D + 0.33 e,
+// so err = 1.34 e + (0.6667 (|n|_1 + |q|_1 + 3/4) + 1.16 |t|) / D, the
+// rounded coefficients covering the reciprocal's error. The grazing band
+// widens by the same 0.875 of D, so a plane below -4 (...) has an FP64
+// n.k < 0 as before. Offsets that round to nearly nothing (tiny against the
+// cell's largest) fall in the band and force the FP64 decision.
+__device__ __forceinline__ void plane_bound32q(float nx, float ny, float nz, const Query32q &Q, float &t,
+                                               float &err, bool &pos, bool &maybe)
+{
+    const float den = fmaf(nx, Q.kx, fmaf(ny, Q.ky, nz * Q.kz));
+    const float wx = fmaf(0.5f, nx, -Q.qx), wy = fmaf(0.5f, ny, -Q.qy), wz = fmaf(0.5f, nz, -Q.qz);
+    const float num = fmaf(nx, wx, fmaf(ny, wy, nz * wz));
+    const float n1 = fabsf(nx) + fabsf(ny) + fabsf(nz);
+    const float d4 = fmaf(32.0f * 5.9604645e-8f, n1, 3.5f);   // 4 (8u |n|_1 + 0.87), floored well above 0
+    pos = den > d4;
+    maybe = den > -d4;
+    const float rc = __builtin_amdgcn_rcpf(den);
+    t = num * rc;
+    const float e = (n1 * rc) * fmaf(Q.c, fabsf(t), Q.a);
+    err = fmaf(1.34f, e, rc * fmaf(1.16f, fabsf(t), fmaf(0.6667f, n1, Q.aq)));
+}
+
 // FP32 crossing t of one plane and its error bound err (see exit_mixed);
 // pos: the plane is approached and the bound holds; maybe: it may be
 // approached in FP64 (nearly parallel) when pos is false.
@@ -300,6 +364,77 @@ __device__ __forceinline__ void plane_bound32(float nx, float ny, float nz, cons
     const float rc = __builtin_amdgcn_rcpf(den);
     t = num * rc;
     err = (n1 * rc) * fmaf(Q.c, fabsf(t), Q.a);
+}
+
+// The mixed-mode exit search over a compact cell block: the same ranking
+// and certificate as exit_mixed, in the cell's scaled units (everything
+// times qs = 2^(19 - E), exact for a power of two), with each record decoded
+// exactly from its 21-bit integers and the quantisation term in each bound
+// (plane_bound32q). Eight records are four aligned 16-byte loads.
+__device__ __forceinline__ int exit_mixed_compact(const Rec64 *__restrict__ rec64, int2 rw,
+                                                  const Slot *__restrict__ blk, int32_t b, const double pm[3],
+                                                  const double r0[3], const double k[3], double L, double s_c,
+                                                  float eps, float e_abs, double &best, bool &redo, int32_t &j1,
+                                                  double qs)
+{
+    const float e_abs_s = (float)((double)e_abs * qs);
+    const Query32q Q = query32q(pm, r0, k, s_c, eps, e_abs_s, qs);
+    const float inf = __builtin_huge_valf();
+    const float tw = (float)((L - s_c) * qs);
+    const float ew = 2.0f * 5.9604645e-8f * fabsf(tw) + e_abs_s;
+    float t1 = tw, err1 = ew;
+    int w1 = -1;
+    float lo_a = tw - ew, lo_b = inf;
+    bool graze = false;
+    const int n = rw.y;
+    const uint4 *rec = reinterpret_cast<const uint4 *>(blk + b + kHdrSlots);   // 8 records = 4 uint4
+    for (int e0 = 0; e0 < n; e0 += kBatch32) {
+        uint32_t w[2 * kBatch32];
+#pragma unroll
+        for (int u = 0; u < kBatch32 / 2; ++u) {   // past the row end: block offsets, padding or the next block, masked
+            const uint4 x = rec[e0 / 2 + u];
+            w[4 * u] = x.x;
+            w[4 * u + 1] = x.y;
+            w[4 * u + 2] = x.z;
+            w[4 * u + 3] = x.w;
+        }
+        const int rem = n - e0;
+#pragma unroll
+        for (int v = 0; v < kBatch32; ++v) {
+            const bool in = v < rem;
+            const uint32_t lo = w[2 * v], hi = w[2 * v + 1];
+            const int32_t ix = __builtin_amdgcn_sbfe((int32_t)lo, 0, kQBits);
+            const int32_t iy = __builtin_amdgcn_sbfe((int32_t)__builtin_amdgcn_alignbit(hi, lo, kQBits), 0, kQBits);
+            const int32_t iz = __builtin_amdgcn_sbfe((int32_t)hi, 2 * kQBits - 32, kQBits);
+            float t, err;
+            bool pos, maybe;
+            plane_bound32q((float)ix, (float)iy, (float)iz, Q, t, err, pos, maybe);
+            pos = pos && in;
+            graze = graze || (maybe && in && !pos);
+            const float lo_t = pos ? t - err : inf;
+            const bool win = pos && t < t1;
+            t1 = win ? t : t1;
+            err1 = win ? err : err1;
+            w1 = win ? e0 + v : w1;
+            lo_b = __builtin_amdgcn_fmed3f(lo_a, lo_b, lo_t);
+            lo_a = fminf(lo_a, lo_t);
+        }
+    }
+    const float lo1 = t1 - err1;
+    const float lo_other = (lo1 == lo_a) ? lo_b : lo_a;
+    if (graze || !(t1 + err1 < lo_other)) {
+        redo = true;
+        j1 = -1;
+        return exit_fp64(rec64, rw, pm, r0, k, L, best);
+    }
+    redo = false;
+    if (w1 < 0) {
+        j1 = -1;
+        best = L;
+        return -1;
+    }
+    j1 = reinterpret_cast<const int32_t *>(reinterpret_cast<const uint2 *>(rec) + n)[w1];
+    return 0;
 }
 
 __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 rw, const Slot *__restrict__ blk,
@@ -446,6 +581,7 @@ struct RayState {
 #endif
     int32_t m, uid;
     int32_t b;            // offset of the current cell's block
+    int32_t qe;           // compact blocks: the current cell's scale exponent E
     double rho;           // the current cell's density from its block header (mixed mode with grid_rho)
     uint8_t st;
     double tstop, wgt, stop_s;   // transport outputs (kernels with Extras only)
@@ -471,6 +607,23 @@ __device__ __forceinline__ double block_rho(const GridRef &G, int32_t b)
     return reinterpret_cast<const BlockHdr *>(G.blk + b)->rho;
 }
 
+// The scale exponent E of a compact block from its header's length word.
+__device__ __forceinline__ int32_t scale_exp(int32_t lenword) { return (int32_t)((uint32_t)lenword >> 24) - kScaleBias; }
+
+// The block of the current cell R.m: where it starts (kept per cell for
+// compact blocks, else derived from the row) and, for compact blocks, its
+// scale exponent from the header. FP64 mode reads no blocks.
+template <int MODE>
+__device__ __forceinline__ void enter_block(const GridRef &G, RayState &R)
+{
+    if (MODE != kModeCompact) {
+        R.b = block_of(R.rw, R.m);
+        return;
+    }
+    R.b = G.blk_off[R.m];
+    R.qe = scale_exp(reinterpret_cast<const BlockHdr *>(G.blk + R.b)->len);
+}
+
 // The state a ray starts its first step with, settled (the loads of its
 // set-up and start cell are waited for before the step, not after its
 // first segment store).
@@ -493,6 +646,7 @@ __device__ __forceinline__ void settle_start(RayState &R)
     settle(R.cap);
 }
 
+template <int MODE>
 __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R, double s0)
 {
     R.s_c = s0;
@@ -508,10 +662,11 @@ __device__ __forceinline__ void ray_begin(const GridRef &G, RayState &R, double 
     R.pm[1] = sm.y;
     R.pm[2] = sm.z;
     R.rw = G.rows[m];
-    R.b = block_of(R.rw, m);
+    enter_block<MODE>(G, R);
 }
 
 // Start in cell m (internal index), found beforehand by nearest_site.
+template <int MODE>
 __device__ __forceinline__ void ray_begin_at(const GridRef &G, RayState &R, int32_t m, double s0)
 {
     R.s_c = s0;
@@ -523,7 +678,7 @@ __device__ __forceinline__ void ray_begin_at(const GridRef &G, RayState &R, int3
     R.pm[1] = sm.y;
     R.pm[2] = sm.z;
     R.rw = G.rows[m];
-    R.b = block_of(R.rw, m);
+    enter_block<MODE>(G, R);
 }
 
 // Slot of segment idx of the ray: its window, else its current spill chunk;
@@ -869,6 +1024,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
     int32_t wj = -1, wuid = 0;
     double wx = 0.0, wy = 0.0, wz = 0.0;
     int2 wrow = make_int2(0, 0);
+    int32_t wqe = 0;
     if (win >= 0) {
         if (MODE == VOR_MODE_FP64 || redo) {
             const Rec64 w = G.rec64[win];
@@ -886,7 +1042,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             settle(wrow.x);
             settle(wrow.y);
         } else {
-            // the header as its three 16-byte slots: {x, y}, {z, rho}, {uid, j, len, pad}
+            // the header as its three 16-byte slots: {x, y}, {z, rho}, {uid, j, len, row}
             const double2 s0 = *reinterpret_cast<const double2 *>(G.blk + j1);
             const double2 s1 = *reinterpret_cast<const double2 *>(G.blk + j1 + 1);
             const int4 s2 = *reinterpret_cast<const int4 *>(G.blk + j1 + 2);
@@ -896,7 +1052,12 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             if (I.grid_rho) wrho = s1.y;
             wuid = s2.x;
             wj = s2.y;
-            wrow = make_int2(j1 - kHdrSlots * wj, s2.z);
+            if (MODE == kModeCompact) {
+                wrow = make_int2(s2.w, s2.z & kLenMask);
+                wqe = scale_exp(s2.z);
+            } else {
+                wrow = make_int2(j1 - kHdrSlots * wj, s2.z);
+            }
             double den;
             best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
             settle(wrho);
@@ -949,7 +1110,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
         settle(R.pm[2]);
         settle(R.rw.x);
         settle(R.rw.y);
-        R.b = block_of(R.rw, R.m);
+        enter_block<MODE>(G, R);
         if (MODE != VOR_MODE_FP64 && I.grid_rho) {
             R.rho = block_rho(G, R.b);
             settle(R.rho);
@@ -963,14 +1124,19 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
     R.pm[1] = wy;
     R.pm[2] = wz;
     R.rw = wrow;
-    R.b = block_of(wrow, wj);
-    if (MODE != VOR_MODE_FP64 && I.grid_rho) {
-        if (redo) {
+    if (MODE == VOR_MODE_FP64) {
+        R.b = block_of(wrow, wj);   // not read in FP64 mode
+    } else if (redo) {
+        enter_block<MODE>(G, R);
+        if (I.grid_rho) {
             R.rho = block_rho(G, R.b);
             settle(R.rho);
-        } else {
-            R.rho = wrho;
         }
+        if (MODE == kModeCompact) settle(R.qe);
+    } else {
+        R.b = j1;
+        if (MODE == kModeCompact) R.qe = wqe;
+        if (I.grid_rho) R.rho = wrho;
     }
     return true;
 }
@@ -989,8 +1155,12 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
     if (MODE == VOR_MODE_FP64) {
         win = exit_fp64(G.rec64, R.rw, R.pm, R.r0, R.k, R.L, best);
     } else {
-        win = exit_mixed(G.rec64, R.rw, G.blk, R.b, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs, best, redo,
-                         j1);
+        if (MODE == kModeCompact)
+            win = exit_mixed_compact(G.rec64, R.rw, G.blk, R.b, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs,
+                                     best, redo, j1, ldexp(1.0, kQShift - R.qe));
+        else
+            win = exit_mixed(G.rec64, R.rw, G.blk, R.b, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs, best,
+                             redo, j1);
         S.nredo += redo ? 1 : 0;
     }
     return ray_step_end<MODE, SEGS, EXT, DEFER, WIDE, LP>(G, I, R, S, O, win, best, redo, j1, X);

@@ -35,15 +35,25 @@ struct __align__(16) Slot {
 // are 6 aligned 16-byte loads) and the block offset of the winner alone.
 // What a step needs of the cell it moves into (its FP64 site, indices, row
 // and bound density) lies in the lines of its first records.
+// A grid may instead use compact blocks (Grid::compact): the same header,
+// then n records of 8 bytes -- the offset p_j - p_m as three 21-bit signed
+// integers q (x in bits 0-20, y in 21-41, z in 42-62) with
+// p_j - p_m ~= q * 2^(E - 19), E the cell's scale exponent (the largest
+// offset component is below 2^E) -- then the n block offsets; each block is
+// padded to whole slots and its start is kept in Grid::blk_off.
 constexpr int kHdrSlots = 3;
 struct __align__(16) BlockHdr {
     double x, y, z;   // the site
     double rho;       // the density bound to the grid (vor_grid_bind_density), 0 when none
     int32_t uid;      // user index
     int32_t j;        // internal index
-    int32_t len;      // records that follow
-    int32_t pad;
+    int32_t len;      // records that follow (bits 0-23); compact blocks: E + 128 in bits 24-31
+    int32_t row;      // start of the cell's row of FP64 records (rows[j].x)
 };
+constexpr int32_t kLenMask = 0xffffff;
+constexpr int kScaleBias = 128;
+constexpr int kQBits = 21;     // bits per component of a compact record
+constexpr int kQShift = 19;    // q = rint(offset * 2^(19 - E)), |q| <= 2^19
 static_assert(sizeof(BlockHdr) == 16 * kHdrSlots, "a block header fills kHdrSlots slots");
 static_assert(offsetof(BlockHdr, z) == 16 && offsetof(BlockHdr, rho) == 24 && offsetof(BlockHdr, uid) == 32 &&
                   offsetof(BlockHdr, j) == 36 && offsetof(BlockHdr, len) == 40,
@@ -95,6 +105,8 @@ struct Grid {
     int64_t loc_entries = 0;
     int32_t rho_bound = 0;          // a density is bound (block headers and rho_int)
     double *rho_int = nullptr;      // [M] the bound density in internal order (FP64 mode reads it here)
+    int32_t compact = 0;            // cell blocks with 8-byte fixed-point records
+    int32_t *blk_off = nullptr;     // [M + 1] compact blocks: the slot where each cell's block starts
     double build_ms = 0;
     int64_t device_bytes = 0;
     int device = 0;

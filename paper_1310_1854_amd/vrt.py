@@ -43,14 +43,18 @@ class VorError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("bucket_occupancy", ctypes.c_double), ("block_lists", ctypes.c_int32),
-                ("block_occupancy", ctypes.c_double)]
+                ("block_occupancy", ctypes.c_double), ("record_layout", ctypes.c_int32)]
+
+
+RECORD_LAYOUTS = {"auto": 0, "fp32": 1, "compact": 2}
 
 
 class GridInfo(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int64), ("nnz", ctypes.c_int64), ("nnz_with_walls", ctypes.c_int64),
                 ("max_row", ctypes.c_int32), ("dims", ctypes.c_int32 * 3), ("box", ctypes.c_double * 6),
                 ("build_ms", ctypes.c_double), ("device_bytes", ctypes.c_int64),
-                ("block_dims", ctypes.c_int32 * 3), ("block_entries", ctypes.c_int64)]
+                ("block_dims", ctypes.c_int32 * 3), ("block_entries", ctypes.c_int64),
+                ("record_layout", ctypes.c_int32)]
 
 
 class TraceOpts(ctypes.Structure):
@@ -226,7 +230,8 @@ class Grid:
         _check(load().vor_grid_get_info(self._h, ctypes.byref(inf)), "vor_grid_get_info")
         return dict(n_sites=inf.n_sites, nnz=inf.nnz, nnz_with_walls=inf.nnz_with_walls, max_row=inf.max_row,
                     dims=list(inf.dims), box=list(inf.box), build_ms=inf.build_ms, device_bytes=inf.device_bytes,
-                    block_dims=list(inf.block_dims), block_entries=inf.block_entries)
+                    block_dims=list(inf.block_dims), block_entries=inf.block_entries,
+                    record_layout={1: "fp32", 2: "compact"}.get(inf.record_layout, inf.record_layout))
 
     def neighbors(self, stream=None):
         """(row_ptr int64[M+1], col int32[nnz]) in user order, walls as -1..-6."""
@@ -276,14 +281,19 @@ class Grid:
 
 
 def build_grid(sites, box: Sequence[float], bucket_occupancy: float = 0.0, block_lists: bool = False,
-               block_occupancy: float = 0.0, allocator: Optional[Allocator] = None, stream=None) -> Grid:
+               block_occupancy: float = 0.0, allocator: Optional[Allocator] = None, stream=None,
+               records: str = "auto") -> Grid:
     """vor_build_grid; block_lists also builds the block-list locate
     structure (vor_locate_blocks) and keeps the cells' bounding boxes;
     allocator (e.g. torch_allocator()): where the grid's device memory
-    comes from (default hipMalloc)."""
+    comes from (default hipMalloc); records: the layout of the records
+    mixed-mode traces read ("auto", "fp32" or "compact"; same results)."""
+    if records not in RECORD_LAYOUTS:
+        raise ValueError(f"records must be one of {sorted(RECORD_LAYOUTS)}")
     sites_d = _dev_f64(sites, 3)
     box_h = (ctypes.c_double * 6)(*[float(b) for b in box])
-    opts = BuildOpts(float(bucket_occupancy), 1 if block_lists else 0, float(block_occupancy))
+    opts = BuildOpts(float(bucket_occupancy), 1 if block_lists else 0, float(block_occupancy),
+                     RECORD_LAYOUTS[records])
     h = ctypes.c_void_p()
     _check(load().vor_build_grid(_ptr(sites_d), sites_d.shape[0], box_h, ctypes.byref(opts),
                                  None if allocator is None else ctypes.byref(allocator), _stream(stream),

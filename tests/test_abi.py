@@ -46,6 +46,11 @@ def test_binding_constants_match_the_header():
     assert int(re.search(r"#define VOR_SERVE_GRID_DENSITY (0x[0-9a-fA-F]+)", text).group(1), 16) == vrt.SERVE_GRID_DENSITY
     import torch
     assert vrt.TraceBuffers(10, device="cpu").work.numel() == vrt.WORK_WORDS
+    enum = re.search(r"enum \{ VOR_RECORDS_AUTO = (\d+), VOR_RECORDS_FP32 = (\d+), VOR_RECORDS_COMPACT = (\d+) \}", text)
+    assert [int(x) for x in enum.groups()] == [vrt.RECORD_LAYOUTS[k] for k in ("auto", "fp32", "compact")]
+    # the option and info structs end with the record layout, as in the header
+    assert vrt.BuildOpts.record_layout.offset == 24 and ctypes.sizeof(vrt.BuildOpts) == 32
+    assert vrt.GridInfo.record_layout.offset == ctypes.sizeof(vrt.GridInfo) - 8
 
 
 def test_library_exports_every_declared_symbol(lib):
@@ -86,6 +91,9 @@ def test_argument_errors_before_device_work(lib):
     # bad options of the block-list locate structure
     for bl, bo in [(2, 0.0), (-1, 0.0), (1, -1.0), (1, float("nan"))]:
         opts = vrt.BuildOpts(0.0, bl, bo)
+        assert lib.vor_build_grid(fake, 10, box, ctypes.byref(opts), None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
+    for layout in (-1, 3):   # record layouts: auto, fp32, compact
+        opts = vrt.BuildOpts(0.0, 0, 0.0, layout)
         assert lib.vor_build_grid(fake, 10, box, ctypes.byref(opts), None, None, ctypes.byref(out)) == vrt.VOR_EINVAL
     # an allocator without its functions
     bad = vrt.Allocator()

@@ -20,11 +20,15 @@ WANT = {
     "_ZN12_GLOBAL__N_118k_trace_persistentILi0ELb1ELb0EEEvNS_9TraceArgsE": 4,   # FP64, segments
     "_ZN12_GLOBAL__N_118k_trace_persistentILi1ELb1ELb1EEEvNS_9TraceArgsE": 3,   # mixed, transport
     "_ZN12_GLOBAL__N_118k_trace_persistentILi0ELb1ELb1EEEvNS_9TraceArgsE": 3,   # FP64, transport
+    "_ZN12_GLOBAL__N_118k_trace_persistentILi2ELb1ELb0EEEvNS_9TraceArgsE": 3,   # mixed over compact records
+    "_ZN12_GLOBAL__N_118k_trace_persistentILi2ELb1ELb1EEEvNS_9TraceArgsE": 3,   # ... transport
 }
-WANT_SERVE = {"k_serve": 3}   # the serving kernels (one per precision class)
-# Its register budget: at the 168-register ceiling (with 8-length store
-# groups) it still had 3 waves, but served 23% slower.
-MAX_VGPR_SERVE = 160
+WANT_SERVE = {"k_serve": 3}   # the serving kernels (one per kernel class)
+# The register budget of the FP64 and the mixed serving kernel: at the
+# 168-register ceiling (with 8-length store groups) the mixed one still had
+# 3 waves, but served 23% slower. The kernel for grids with compact records
+# (used only for tables too large for the last-level cache) keeps 3 waves.
+MAX_VGPR_SERVE = {"k_serveILi0E": 160, "k_serveILi1E": 160, "k_serveILi2E": 168}
 
 
 def _occupancy(src_name, tmp_path):
@@ -57,7 +61,7 @@ def test_persistent_kernels_keep_their_occupancy(tmp_path):
         assert k in occ, f"{k} not compiled"
         assert occ[k] >= want, f"{k}: occupancy {occ[k]} < {want} waves per SIMD"
     traversal = [k for k in scratch if "k_trace" in k]
-    assert len(traversal) >= 16, traversal
+    assert len(traversal) >= 24, traversal
     for k in traversal:
         assert scratch[k] == 0, f"{k}: {scratch[k]} bytes of scratch per lane"
 
@@ -69,5 +73,6 @@ def test_serving_kernel_keeps_its_occupancy(tmp_path):
         assert names, f"{short} not compiled"
         for k in names:
             assert occ[k] >= want, f"{k}: occupancy {occ[k]} < {want} waves per SIMD"
-            assert vgpr[k] <= MAX_VGPR_SERVE, f"{k}: {vgpr[k]} VGPRs > {MAX_VGPR_SERVE}"
+            cap = [v for c, v in MAX_VGPR_SERVE.items() if c in k] or [168]   # k_serve_start: any 3-wave budget
+            assert vgpr[k] <= cap[0], f"{k}: {vgpr[k]} VGPRs > {cap[0]}"
             assert scratch[k] == 0, f"{k}: {scratch[k]} bytes of scratch per lane"
