@@ -126,14 +126,14 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str, transport: bool = False,
-                      compact: bool = False) -> float:
+def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str, transport: bool = False) -> float:
     """Bytes the method must move for one launch, from the kernel counters
     c = [segments, fallbacks, fp64 re-decisions, steps, records, ...].
     Per step: the row range (8 B) and, per neighbour record read, its index
-    and site (4 + 24 B in FP64; 4 + 12 B FP32 offset in mixed mode, or
-    4 + 8 B over compact records, plus the winner's FP64 site, 24 B, and the
-    FP64 records of re-decided steps).
+    and site (4 + 24 B in FP64; 4 + 12 B FP32 offset in mixed mode, plus the
+    winner's FP64 site, 24 B, and the FP64 records of re-decided steps). The
+    figure belongs to the method, not to a layout: grids with compact 8-byte
+    records are charged the same.
     Per segment: the cell density (8 B) and the output (4 B cell + 8 B
     length). Per ray: origin and direction (48 B), tau, count and status
     (13 B). With transport, per segment two tally updates (read and write
@@ -146,7 +146,7 @@ def algorithmic_bytes(c: np.ndarray, n_rays: int, mode: str, transport: bool = F
     if mode == "fp64":
         b += 28.0 * recs
     else:
-        b += (12.0 if compact else 16.0) * recs + 24.0 * steps + 28.0 * redo * per_step_recs
+        b += 16.0 * recs + 24.0 * steps + 28.0 * redo * per_step_recs
     return b
 
 
@@ -739,7 +739,7 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
                      reuse_order=True)
     kc = bufs.counters.cpu().numpy().astype(np.float64) / args.roofline_reps
     k_avg = float(np.mean(k_ms))
-    alg = algorithmic_bytes(kc, w.N, mode, bool(spec.get("transport")), info.get("record_layout") == "compact")
+    alg = algorithmic_bytes(kc, w.N, mode, bool(spec.get("transport")))
     achieved = alg / (k_avg / 1e3) / 1e9
     recs_per_step = kc[4] / max(kc[3], 1)
 
