@@ -761,6 +761,8 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
         density_check = {"tau_bit_identical": bool(torch.equal(bufs.tau, tau_mixed)),
                          "n_seg_identical": bool(torch.equal(bufs.n_seg, nseg_mixed))}
 
+    del fb
+    exact = None if spec.get("transport") else exact_output(vrt, torch, grid, o, d, rho, bufs, spec, mode)
     traffic, traffic_src, l2_hit = measured_traffic(args.workload)
     copy_bw = copy_bandwidth(torch)
 
@@ -798,6 +800,7 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
         "fp64_ms_per_step": f_wall * 1e3,
         "mixed_vs_fp64": {"tau_bit_identical": same_tau, "n_seg_identical": same_nseg},
         "bound_vs_array_density": density_check,
+        "exact_output": exact,
         "grid": {"build_ms": info["build_ms"], "nnz": info["nnz"], "max_row": info["max_row"],
                  "device_bytes": info["device_bytes"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -844,11 +847,64 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
                 np.max(np.abs(g_s - it["s"])[clean] / ref["chord"][clean])) if clean.any() else 0.0
     if spec.get("transport"):
         result["transport"] = transport_check(vrt, torch, grid, o, d, rho, bufs, spec, mode)
-    del bufs, fb
+    del bufs
     grid.free()
     return result
 
 
+
+
+def exact_output(vrt, torch, grid, o, d, rho, bufs, spec, mode, reps=3):
+    """Every path whole, in compact rows (ray i's segments at
+    [ray_off[i], ray_off[i + 1])), two ways, wall time per batch including
+    the host's read of the total that sizes the rows: one traversal (a bench
+    step into the windows and spill chains), the scan and vor_gather_paths;
+    against a tau-only counting pass, the scan and a second traversal that
+    writes each segment at its offset. Checks that both give the same rows."""
+    N = o.shape[0]
+    gd = spec.get("grid_density", True)
+    dens = None if gd else rho
+    kw = dict(kappa=float(spec.get("kappa", 1.0)), mode=mode, persistent=bool(spec.get("persistent", False)),
+              ordered=bool(spec.get("ordered", False)), grid_density=gd)
+    one, two = [], []
+    cell1 = len1 = None
+    count = vrt.TraceBuffers(N, ordered=kw["ordered"])
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(vrt, grid, o, d, rho, bufs, spec, mode)
+        off = vrt.exclusive_scan(bufs.n_seg)
+        total = int(off[-1].item())
+        if cell1 is None:
+            cell1 = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+            len1 = torch.empty(max(total, 1), dtype=torch.float64, device="cuda")
+        vrt.gather_paths(bufs, off, cell1, len1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        vrt.trace_into(grid, o, d, dens, count, **kw)
+        off2 = vrt.exclusive_scan(count.n_seg)
+        total2 = int(off2[-1].item())
+        if r == 0:
+            fill = vrt.TraceBuffers(N, total_segments=max(total2, 1), ordered=kw["ordered"])
+        fill.ray_off = off2
+        if kw["ordered"]:   # the second traversal reuses the first one's order and start cells
+            fill.order.copy_(count.order)
+        fill.start_cell.copy_(count.start_cell)
+        vrt.trace_into(grid, o, d, dens, fill, start_given=True, **kw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r > 0:   # the first round allocates
+            one.append((t1 - t0) * 1e3)
+            two.append((t2 - t1) * 1e3)
+    same = total == total2 and bool(torch.equal(off, off2)) and bool(torch.equal(cell1[:total], fill.seg_cell[:total])) \
+        and bool(torch.equal(len1[:total], fill.seg_len[:total]))
+    del count, fill, cell1, len1
+    torch.cuda.empty_cache()
+    return {"one_traversal_ms": float(np.median(one)), "two_pass_ms": float(np.median(two)),
+            "segments": total, "rows_identical": same,
+            "how": "one traversal into windows + spill, scan, vor_gather_paths; vs counting pass, scan, second "
+                   "traversal into the offsets reusing the first one's order and start cells (host read of the "
+                   "total included in both)"}
 
 
 def transport_check(vrt, torch, grid, o, d, rho, bufs, spec, mode):

@@ -387,6 +387,30 @@ int64_t vor_order_workspace_bytes(int64_t N);
  */
 vor_status vor_exclusive_scan(const int32_t *counts, int64_t N, int64_t *offsets, void *stream);
 
+/*
+ * vor_gather_paths -- whole paths as compact rows (Sect. 2.2: a path is every
+ * cell it crosses, in order, to the wall) from a trace into segment windows:
+ * ray i's segments -- the first min(n_seg[i], seg_stride) slots of its window,
+ * then its chain of spill chunks -- go to [ray_off[i], ray_off[i] + n_seg[i])
+ * of seg_cell / seg_len. With ray_off = vor_exclusive_scan(n_seg) this gives
+ * the exact layout from one traversal, instead of a counting pass and a
+ * second traversal into ray_off.
+ *   n_seg, win_cell, win_len, spill_*   device, as the vor_trace_out of that
+ *                  trace (seg_stride > 0) left them; the four spill arrays
+ *                  are all NULL when the trace had no spill (then no ray may
+ *                  have more than seg_stride segments);
+ *   ray_off        device N + 1 int64; seg_cell / seg_len device, ray_off[N]
+ *                  entries each, written.
+ * A ray whose spill ran out (VOR_RAY_OVERFLOW) keeps only the segments that
+ * were stored; the rest of its row is left unwritten. Argument errors:
+ * VOR_EINVAL (N < 0, seg_stride <= 0, a missing array, some but not all
+ * spill arrays). Asynchronous on `stream`; allocates nothing.
+ */
+vor_status vor_gather_paths(const int32_t *n_seg, int64_t N, const int32_t *win_cell, const double *win_len,
+                            int64_t seg_stride, const int64_t *spill_first, const int32_t *spill_next,
+                            const int32_t *spill_cell, const double *spill_len, const int64_t *ray_off,
+                            int32_t *seg_cell, double *seg_len, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of path requests over resident grids.
  *

@@ -339,39 +339,6 @@ __global__ void k_zero_launch(unsigned int *head, unsigned long long *counters, 
     for (int q = threadIdx.x; q < n_req; q += blockDim.x) rc[q] = ReqCount{0ull, 0, 0};
 }
 
-// Whole paths of a request into compact rows (Sect. 2.2: a path is every
-// cell to the wall): ray i's segments, from its window and then its chain
-// of spill chunks, go to [ray_off[i], ray_off[i] + n_seg[i]).
-__global__ void __launch_bounds__(256) k_gather_paths(const int32_t *__restrict__ n_seg, int64_t n,
-                                                      const int32_t *__restrict__ wcell,
-                                                      const double *__restrict__ wlen, int64_t stride,
-                                                      const int64_t *__restrict__ first,
-                                                      const int32_t *__restrict__ next,
-                                                      const int32_t *__restrict__ pcell,
-                                                      const double *__restrict__ plen,
-                                                      const int64_t *__restrict__ ray_off, int32_t *__restrict__ cell,
-                                                      double *__restrict__ len)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t cnt = n_seg[i];
-    const int64_t o = ray_off[i];
-    const int64_t w = cnt < stride ? cnt : stride;
-    for (int64_t j = 0; j < w; ++j) {
-        cell[o + j] = wcell[i * stride + j];
-        len[o + j] = wlen[i * stride + j];
-    }
-    int64_t c = cnt > stride ? first[i] : -1;
-    for (int64_t j = w; j < cnt && c >= 0; j += kSpillChunk) {
-        const int64_t e = (cnt - j) < kSpillChunk ? (cnt - j) : kSpillChunk;
-        for (int64_t t = 0; t < e; ++t) {
-            cell[o + j + t] = pcell[c * kSpillChunk + t];
-            len[o + j + t] = plen[c * kSpillChunk + t];
-        }
-        c = next[c];
-    }
-}
-
 using clk = std::chrono::steady_clock;
 
 enum ReqState { Q_WAIT = 0, Q_ADMITTED, Q_RUNNING, Q_DONE, Q_RELEASED };
@@ -1027,13 +994,9 @@ vor_status vor_server_copy_result(vor_server *S, int64_t req, double *tau, int32
     if (tau) ok = ok && hipMemcpyAsync(tau, r.tau, r.n * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
     if (n_seg) ok = ok && hipMemcpyAsync(n_seg, r.n_seg, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, st) == hipSuccess;
     if (status) ok = ok && hipMemcpyAsync(status, r.status, r.n, hipMemcpyDeviceToDevice, st) == hipSuccess;
-    if (seg_cell) {
-        const int T = 256;
-        hipLaunchKernelGGL(k_gather_paths, dim3((unsigned)((r.n + T - 1) / T)), dim3(T), 0, st, r.n_seg, r.n, r.seg_cell,
-                           r.seg_len, r.seg_stride, r.spill_first, r.spill_next, r.spill_cell, r.spill_len, ray_off,
-                           seg_cell, seg_len);
-        ok = ok && hipGetLastError() == hipSuccess;
-    }
+    if (seg_cell)   // the request's chunks follow its windows in the same arrays (spill_cell / spill_len)
+        ok = ok && vrt_gather_paths(r.n_seg, r.n, r.seg_cell, r.seg_len, r.seg_stride, r.spill_first, r.spill_next,
+                                    r.spill_cell, r.spill_len, ray_off, seg_cell, seg_len, st) == VOR_OK;
     ok = ok && hipEventRecord(r.copied, st) == hipSuccess;   // release waits for this
     return ok ? VOR_OK : VOR_EDEVICE;
 }

@@ -834,6 +834,68 @@ extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, c
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
+// Whole paths as compact rows (Sect. 2.2: a path is every cell to the
+// wall), one wave per ray: its window's first min(n_seg, stride) slots,
+// then its chain of spill chunks (one chunk = one wave-wide copy), go to
+// [ray_off[i], ray_off[i] + n_seg[i]). Reads and writes of a row are
+// contiguous across the wave's lanes. A chain that ends early (a ray whose
+// spill ran out) leaves the rest of its row unwritten.
+__global__ void __launch_bounds__(256) k_gather_paths(const int32_t *__restrict__ n_seg, int64_t n,
+                                                      const int32_t *__restrict__ wcell,
+                                                      const double *__restrict__ wlen, int64_t stride,
+                                                      const int64_t *__restrict__ first,
+                                                      const int32_t *__restrict__ next,
+                                                      const int32_t *__restrict__ pcell,
+                                                      const double *__restrict__ plen,
+                                                      const int64_t *__restrict__ ray_off, int32_t *__restrict__ cell,
+                                                      double *__restrict__ len)
+{
+    static_assert(kSpillChunk == 64, "a spill chunk is one wave-wide copy");
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    const int64_t cnt = n_seg[i];
+    const int64_t o = ray_off[i];
+    const int64_t w = cnt < stride ? cnt : stride;
+    for (int64_t j = lane; j < w; j += 64) {
+        cell[o + j] = wcell[i * stride + j];
+        len[o + j] = wlen[i * stride + j];
+    }
+    int64_t c = (cnt > stride && first) ? first[i] : -1;
+    for (int64_t j = w; j < cnt && c >= 0; j += kSpillChunk) {
+        if (lane < cnt - j) {
+            cell[o + j + lane] = pcell[c * kSpillChunk + lane];
+            len[o + j + lane] = plen[c * kSpillChunk + lane];
+        }
+        c = next[c];
+    }
+}
+
+vor_status vrt_gather_paths(const int32_t *n_seg, int64_t n, const int32_t *wcell, const double *wlen, int64_t stride,
+                            const int64_t *first, const int32_t *next, const int32_t *pcell, const double *plen,
+                            const int64_t *ray_off, int32_t *cell, double *len, hipStream_t st)
+{
+    if (n == 0) return VOR_OK;
+    const int64_t blocks = (n + 3) / 4;
+    if (blocks > 0x7fffffffLL) return VOR_EINVAL;
+    hipLaunchKernelGGL(k_gather_paths, dim3((unsigned)blocks), dim3(256), 0, st, n_seg, n, wcell, wlen, stride, first,
+                       next, pcell, plen, ray_off, cell, len);
+    return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
+}
+
+extern "C" vor_status vor_gather_paths(const int32_t *n_seg, int64_t N, const int32_t *win_cell, const double *win_len,
+                                       int64_t seg_stride, const int64_t *spill_first, const int32_t *spill_next,
+                                       const int32_t *spill_cell, const double *spill_len, const int64_t *ray_off,
+                                       int32_t *seg_cell, double *seg_len, void *stream)
+{
+    const bool any_spill = spill_first || spill_next || spill_cell || spill_len;
+    const bool all_spill = spill_first && spill_next && spill_cell && spill_len;
+    if (N < 0 || seg_stride <= 0 || (any_spill && !all_spill)) return VOR_EINVAL;
+    if (N > 0 && (!n_seg || !win_cell || !win_len || !ray_off || !seg_cell || !seg_len)) return VOR_EINVAL;
+    return vrt_gather_paths(n_seg, N, win_cell, win_len, seg_stride, spill_first, spill_next, spill_cell, spill_len,
+                            ray_off, seg_cell, seg_len, (hipStream_t)stream);
+}
+
 extern "C" const char *vor_status_str(vor_status s)
 {
     switch (s) {

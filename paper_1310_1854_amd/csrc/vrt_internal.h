@@ -282,3 +282,7 @@ vor_status vrt_radix_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tm
 int64_t vrt_radix_hist_len(int64_t n);
 // dst[i] = src[idx[i]]
 vor_status vrt_gather_u32(const uint32_t *src, const int32_t *idx, int64_t n, uint32_t *dst, hipStream_t st);
+// trace.hip: whole paths from segment windows and spill chains into compact rows (vor_gather_paths)
+vor_status vrt_gather_paths(const int32_t *n_seg, int64_t n, const int32_t *wcell, const double *wlen, int64_t stride,
+                            const int64_t *first, const int32_t *next, const int32_t *pcell, const double *plen,
+                            const int64_t *ray_off, int32_t *cell, double *len, hipStream_t st);

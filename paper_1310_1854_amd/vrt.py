@@ -31,7 +31,7 @@ EXPORTS = ["vor_build_grid", "vor_grid_free", "vor_grid_get_info", "vor_grid_nei
            "vor_server_create", "vor_server_submit", "vor_server_poll", "vor_server_wait", "vor_server_result",
            "vor_server_copy_result", "vor_server_release", "vor_server_get_stats", "vor_server_destroy",
            "vor_server_next_done", "vor_grid_truncate_row", "vor_grid_volumes", "vor_grid_bboxes",
-           "vor_locate_blocks", "vor_grid_bind_density", "vor_trace_noalloc"]
+           "vor_locate_blocks", "vor_grid_bind_density", "vor_trace_noalloc", "vor_gather_paths"]
 NOALLOC_MAX_RAYS = 1 << 22   # VOR_NOALLOC_MAX_RAYS
 
 
@@ -158,6 +158,8 @@ def load(path: str = None):
     lib.vor_order_workspace_bytes.restype = ctypes.c_int64
     lib.vor_exclusive_scan.argtypes = [P, I64, P, P]
     lib.vor_exclusive_scan.restype = ctypes.c_int
+    lib.vor_gather_paths.argtypes = [P, I64, P, P, I64, P, P, P, P, P, P, P, P]
+    lib.vor_gather_paths.restype = ctypes.c_int
     lib.vor_status_str.argtypes = [ctypes.c_int]
     lib.vor_status_str.restype = ctypes.c_char_p
     lib.vor_version.argtypes = []
@@ -471,9 +473,13 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
           eps_fb: float = 0.0, stream=None) -> dict:
     """Paths of N rays. ``segments``: "none" (tau only), "stride" (a window
     of ``seg_stride`` slots per ray; longer paths continue in up to
-    ``spill_chunks`` chained spill chunks, or report RAY_OVERFLOW), or
-    "exact" (a tau-only counting pass, a scan, then a pass that writes every
-    segment at its CSR offset). ``locate_first``: start cells in a pass of
+    ``spill_chunks`` chained spill chunks, or report RAY_OVERFLOW), "exact"
+    (every path whole in compact rows: one traversal into windows of
+    ``seg_stride`` slots and a spill sized from ``spill_chunks``, traced
+    again with the spill it asked for if that was too small, then a scan
+    and vor_gather_paths; with ``tallies`` the two-pass route, so that no
+    tally is deposited twice), or "exact_two_pass" (a tau-only counting
+    pass, a scan, then a pass that writes every segment at its offset). ``locate_first``: start cells in a pass of
     their own (vor_trace_out.start_cell) rather than at each ray's start.
     ``tau_stop``: interaction points (stop_cell, stop_s); ``tallies``: the
     per-cell tallies tally_len and tally_abs (with ``weight``); ``enter``:
@@ -499,7 +505,25 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
     elif segments == "stride":
         b = TraceBuffers(n, seg_stride=seg_stride, spill_chunks=spill_chunks, **lf)
         trace_into(grid, o, d, rho, b, **kw)
-    elif segments == "exact":
+    elif segments == "exact" and not tallies:
+        chunks = spill_chunks if spill_chunks > 0 else n // 8 + 1
+        while True:
+            w = TraceBuffers(n, seg_stride=seg_stride, spill_chunks=chunks, **lf)
+            trace_into(grid, o, d, rho, w, **kw)
+            asked = int(w.work[1].item())
+            if asked <= chunks:
+                break
+            chunks = asked
+            del w
+        off = exclusive_scan(w.n_seg, stream=stream)
+        total = int(off[-1].item())
+        b = TraceBuffers(n, total_segments=max(total, 1), ordered=False, locate_first=False, counters=False)
+        b.tau, b.n_seg, b.status, b.n_fallback, b.counters, b.work = w.tau, w.n_seg, w.status, w.n_fallback, \
+            w.counters, w.work
+        b.stop_cell, b.stop_s = w.stop_cell, w.stop_s
+        b.ray_off = off
+        gather_paths(w, off, b.seg_cell, b.seg_len, stream=stream)
+    elif segments in ("exact", "exact_two_pass"):
         b0 = TraceBuffers(n, **lf)
         trace_into(grid, o, d, rho, b0, **dict(kw, tally_len=None, tally_abs=None, weight=None))   # counting pass
         off = exclusive_scan(b0.n_seg, stream=stream)
@@ -508,7 +532,7 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
         b.ray_off = off
         trace_into(grid, o, d, rho, b, **kw)
     else:
-        raise ValueError("segments must be none, stride or exact")
+        raise ValueError("segments must be none, stride, exact or exact_two_pass")
     res = dict(tau=b.tau, n_seg=b.n_seg, status=b.status, n_fallback=b.n_fallback, counters=b.counters, work=b.work)
     if ts is not None:
         res.update(stop_cell=b.stop_cell, stop_s=b.stop_s)
@@ -523,6 +547,27 @@ def trace(grid: Grid, origins, dirs, density=None, kappa: float = 1.0, mode: str
             res.update(spill_first=b.spill_first, spill_next=b.spill_next, spill_cell=b.spill_cell,
                        spill_len=b.spill_len)
     return res
+
+
+def gather_paths(bufs: "TraceBuffers", ray_off: torch.Tensor, seg_cell: torch.Tensor, seg_len: torch.Tensor,
+                 stream=None) -> None:
+    """vor_gather_paths: the whole paths of a trace into segment windows
+    (``bufs``, seg_stride > 0) as compact rows at ``ray_off`` (the exclusive
+    scan of bufs.n_seg)."""
+    if bufs.seg_stride <= 0 or bufs.seg_cell is None:
+        raise ValueError("gather_paths needs the buffers of a trace with segment windows")
+    n = bufs.N
+    if ray_off.dtype != torch.int64 or ray_off.numel() != n + 1 or not ray_off.is_cuda:
+        raise ValueError("ray_off must be a device int64 tensor of N + 1 offsets")
+    for t, dt in ((seg_cell, torch.int32), (seg_len, torch.float64)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("seg_cell / seg_len must be contiguous int32 / float64 device tensors")
+    sp = bufs.spill_chunks > 0
+    _check(load().vor_gather_paths(_ptr(bufs.n_seg), n, _ptr(bufs.seg_cell), _ptr(bufs.seg_len), bufs.seg_stride,
+                                   _ptr(bufs.spill_first) if sp else None, _ptr(bufs.spill_next) if sp else None,
+                                   _ptr(bufs.spill_cell) if sp else None, _ptr(bufs.spill_len) if sp else None,
+                                   _ptr(ray_off), _ptr(seg_cell), _ptr(seg_len), _stream(stream)),
+           "vor_gather_paths")
 
 
 def ray_path(res: dict, r: int, host: Optional[dict] = None):

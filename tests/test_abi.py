@@ -110,6 +110,13 @@ def test_argument_errors_before_device_work(lib):
     info = vrt.GridInfo()
     assert lib.vor_grid_get_info(None, ctypes.byref(info)) == vrt.VOR_EINVAL
     assert lib.vor_grid_neighbors(None, fake, cell, None) == vrt.VOR_EINVAL
+    g = lib.vor_gather_paths
+    assert g(fake, 10, fake, fake, 0, None, None, None, None, fake, fake, fake, None) == vrt.VOR_EINVAL   # stride 0
+    assert g(fake, -1, fake, fake, 8, None, None, None, None, fake, fake, fake, None) == vrt.VOR_EINVAL
+    assert g(fake, 10, fake, fake, 8, fake, None, None, None, fake, fake, fake, None) == vrt.VOR_EINVAL   # part of a spill
+    assert g(fake, 10, None, fake, 8, None, None, None, None, fake, fake, fake, None) == vrt.VOR_EINVAL
+    assert g(fake, 10, fake, fake, 8, None, None, None, None, None, fake, fake, None) == vrt.VOR_EINVAL
+    assert g(None, 0, None, None, 8, None, None, None, None, None, None, None, None) == vrt.VOR_OK       # nothing to do
     assert lib.vor_exclusive_scan(cell, -1, fake, None) == vrt.VOR_EINVAL
     assert lib.vor_exclusive_scan(None, 5, fake, None) == vrt.VOR_EINVAL
     lib.vor_grid_free(None)

@@ -880,3 +880,29 @@ def test_store_groups_on_long_paths(vrt, mode):
         for r, (c, l) in enumerate(_host_paths(out, w.N)):
             assert np.array_equal(c, cells[off[r]:off[r + 1]]), (stride, r)
             assert np.array_equal(l, lens[off[r]:off[r + 1]]), (stride, r)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_exact_paths_from_one_traversal(vrt, mode):
+    """segments="exact" traces once into windows and spill chains and then
+    gathers every path into compact rows (vor_gather_paths, one wave per
+    ray). It must give the two-pass route's rows bit for bit: with windows
+    that most paths outgrow, with a first spill too small (traced again with
+    the spill it asked for) and with windows few paths outgrow; and the
+    oracle's paths on a sample."""
+    import torch
+    w = W.flared_disc(M=20_000, N=20_000, seed=83)
+    grid = vrt.build_grid(w.sites, w.box)
+    kw = dict(kappa=w.kappa, mode=mode, persistent=True, ordered=True)
+    a = vrt.trace(grid, w.origins, w.dirs, w.density, segments="exact_two_pass", **kw)
+    ns = a["n_seg"].cpu().numpy()
+    assert (ns > 16).mean() > 0.5 and (ns > 64).sum() > 0
+    for stride, chunks in ((16, 0), (16, 1), (64, 0), (8, 3)):
+        b = vrt.trace(grid, w.origins, w.dirs, w.density, segments="exact", seg_stride=stride, spill_chunks=chunks,
+                      **kw)
+        for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+            assert torch.equal(a[k], b[k]), (k, stride, chunks)
+        assert b.get("seg_stride", 0) == 0
+    ref = oracle.trace(w.sites, w.box, w.density, w.origins[:300], w.dirs[:300], cap=1024)
+    st = compare(gpu_paths(b), ref, TOL[mode])
+    assert st["clean"] > 0.9 * 300 and st["max_len_diff"] <= TOL[mode]
