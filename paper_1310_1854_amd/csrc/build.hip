@@ -300,8 +300,9 @@ __device__ __forceinline__ int wave_max_int(int v)
     return v;
 }
 
-// Slots of a compact block: the header, then 12 bytes per neighbour
-// (8-byte record + 4-byte block offset), rounded up to whole slots.
+// Slots of a compact cell block: the header, then 12 bytes per neighbour
+// (8-byte record + block offset), rounded up to whole slots. (Blocks start
+// on any slot: starting them on 64- or 128-byte lines was measured slower.)
 __global__ void k_compact_slots(const int32_t *__restrict__ total, int64_t M, int32_t *__restrict__ slots)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,7 +320,8 @@ __global__ void k_compact_slots(const int32_t *__restrict__ total, int64_t M, in
 __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__restrict__ col,
                                const int32_t *__restrict__ total, const int32_t *__restrict__ start, int64_t M,
                                int2 *__restrict__ rows, Rec64 *__restrict__ r64, Slot *__restrict__ blk,
-                               const int32_t *__restrict__ blk_off, int e_min, int *__restrict__ max_row)
+                               const int32_t *__restrict__ blk_off, int compact, int e_min,
+                               int *__restrict__ max_row)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int n = 0;
@@ -330,7 +332,7 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
         const Site si = sites[i];
         const int32_t bo = blk_off ? blk_off[i] : block_of(make_int2(s0, n), (int32_t)i);
         int E = 0;
-        if (blk_off) {
+        if (compact) {
             double mc = 0.0;
             for (int e = 0; e < n; ++e) {
                 const Site sj = sites[col[s0 + e]];
@@ -345,13 +347,13 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
         h.z = si.z;
         h.uid = (int32_t)si.uid;
         h.j = (int32_t)i;
-        h.len = n | (blk_off ? (E + kScaleBias) << 24 : 0);
+        h.len = n | (compact ? (E + kScaleBias) << 24 : 0);
         h.row = s0;
         h.rho = 0.0;
         *reinterpret_cast<BlockHdr *>(blk + bo) = h;
         float *rec = reinterpret_cast<float *>(blk + bo + kHdrSlots);           // FP32: n records of 3 floats
         uint2 *crec = reinterpret_cast<uint2 *>(blk + bo + kHdrSlots);          // compact: n records of 8 bytes
-        int32_t *nb = blk_off ? reinterpret_cast<int32_t *>(crec + n) : reinterpret_cast<int32_t *>(rec + 3 * n);
+        int32_t *nb = compact ? reinterpret_cast<int32_t *>(crec + n) : reinterpret_cast<int32_t *>(rec + 3 * n);
         const double sc = ldexp(1.0, kQShift - E);
         for (int e = 0; e < n; ++e) {
             int32_t j = col[s0 + e];
@@ -363,20 +365,19 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
             a.j = j;
             a.uid = (int32_t)sj.uid;
             r64[s0 + e] = a;
-            if (blk_off) {
+            if (compact) {
                 const uint64_t m21 = (1ull << kQBits) - 1;
                 const uint64_t qx = (uint64_t)(int64_t)rint((sj.x - si.x) * sc) & m21;
                 const uint64_t qy = (uint64_t)(int64_t)rint((sj.y - si.y) * sc) & m21;
                 const uint64_t qz = (uint64_t)(int64_t)rint((sj.z - si.z) * sc) & m21;
                 const uint64_t v = qx | (qy << kQBits) | (qz << (2 * kQBits));
                 crec[e] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
-                nb[e] = blk_off[j];
             } else {
                 rec[3 * e] = (float)(sj.x - si.x);
                 rec[3 * e + 1] = (float)(sj.y - si.y);
                 rec[3 * e + 2] = (float)(sj.z - si.z);
-                nb[e] = block_of(make_int2(start[j], 0), j);
             }
+            nb[e] = blk_off ? blk_off[j] : block_of(make_int2(start[j], 0), j);
         }
     }
     int m = wave_max_int(n);
@@ -676,7 +677,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     int64_t nslots = g.nnz + (int64_t)kHdrSlots * M;
     if (nslots + kRecPad > 0x7fffffffLL) return fail(VOR_ECAPACITY);   // compact blocks take no more slots
     g.compact = layout == VOR_RECORDS_COMPACT || (layout == VOR_RECORDS_AUTO && nslots * 16 > kCompactAutoBytes);
-    if (g.compact) {
+    if (g.compact) {   // blocks not at rows[j].x + 3j: their starts are kept
         g.blk_off = dalloc<int32_t>(M + 1, rc, keep, A);
         if (rc != VOR_OK) return fail(rc);
         hipLaunchKernelGGL(k_compact_slots, dim3(blocks_for(M, T)), dim3(T), 0, st, total, M, slot);
@@ -698,7 +699,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
         return fail(VOR_EDEVICE);
     hdr = err + 1;   // longest row
     hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, col, total, start, M, g.rows,
-                       g.rec64, g.blk, g.blk_off, compact_min_exp(g.box), hdr);
+                       g.rec64, g.blk, g.blk_off, (int)g.compact, compact_min_exp(g.box), hdr);
     // size of the export with walls
     hipLaunchKernelGGL(k_export_counts, dim3(blocks_for(M, T)), dim3(T), 0, st, g.inv_perm, g.rows, g.wall_mask, M,
                        total);
@@ -757,7 +758,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     tmp.clear();
     g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + 2 * sizeof(double)) + (B + 1) * 4 +
                      (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Slot) +
-                     (g.compact ? (M + 1) * 4 : 0);
+                     (g.blk_off ? (M + 1) * 4 : 0);
     if (want_loc)
         g.device_bytes += (int64_t)M * 6 * (int64_t)sizeof(double) +
                           ((int64_t)g.loc_dims[0] * g.loc_dims[1] * g.loc_dims[2] + 1 + g.loc_entries) * 4;
@@ -823,7 +824,7 @@ extern "C" vor_status vor_grid_truncate_row(vor_grid *G, int64_t site, int32_t k
         // the block offsets follow the records (12 or 8 bytes each): move the
         // first keep of them to their place after the first keep records
         int32_t bo = block_of(rw, i);
-        if (g.compact && hipMemcpy(&bo, g.blk_off + i, sizeof(bo), hipMemcpyDeviceToHost) != hipSuccess)
+        if (g.blk_off && hipMemcpy(&bo, g.blk_off + i, sizeof(bo), hipMemcpyDeviceToHost) != hipSuccess)
             return VOR_EDEVICE;
         char *rec = reinterpret_cast<char *>(g.blk + bo + kHdrSlots);
         const int rbytes = g.compact ? 8 : 12;

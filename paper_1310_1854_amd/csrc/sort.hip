@@ -1,11 +1,13 @@
 // sort.hip -- stable LSD radix sort of (uint32 key, int32 value) pairs, 8
-// bits per pass. Used once per grid build to put the sites in Hilbert order.
+// bits per pass. Used by the grid build (sites in Hilbert order) and by the
+// coherent ray order.
 //
 // Per pass: a per-tile digit histogram (LDS atomics), an exclusive scan of
 // the digit-major histogram (digit d's slot for tile t lands after every
 // smaller digit and every earlier tile), and a stable scatter in which each
-// 64-lane wave ranks equal digits with eight ballots and the waves of a
-// block combine their per-digit counts through LDS.
+// 64-lane wave ranks equal digits with eight ballots, the waves of a block
+// combine their per-digit counts through LDS, and the tile is reordered in
+// LDS so that its runs of equal digits are written out contiguously.
 #include "vrt_internal.h"
 
 namespace {
@@ -30,47 +32,89 @@ __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint32_t *__restr
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Stable scatter of one tile: the tile's pairs are first put in digit order
+// in LDS (ranked round by round, in index order, as above), then written out
+// in that order, so that the lanes of a wave write runs of equal digits to
+// consecutive addresses instead of one scattered word each.
 __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__restrict__ kin,
                                                             const int32_t *__restrict__ vin, int64_t n, int shift,
                                                             const int32_t *__restrict__ off, int64_t ntiles,
                                                             uint32_t *__restrict__ kout, int32_t *__restrict__ vout)
 {
-    __shared__ int32_t run[256];
+    __shared__ int32_t run[256];        // next local slot of each digit
+    __shared__ int32_t loc[256];        // where each digit's run starts in the tile
     __shared__ int32_t wcnt[kWaves][256];
+    __shared__ uint32_t skey[kTile];
+    __shared__ int32_t sval[kTile];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    run[tid] = off[(int64_t)tid * ntiles + blockIdx.x];
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
+
+    // the tile's digit counts and their exclusive scan
+    run[tid] = 0;
+    __syncthreads();
+    for (int r = 0; r < kRounds; ++r) {
+        const int i = r * kThreads + tid;
+        if (i < cnt) atomicAdd(&run[(kin[base + i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    if (tid < 64) {   // one wave scans the 256 counts, 4 per lane
+        const int c0 = run[4 * lane], c1 = run[4 * lane + 1], c2 = run[4 * lane + 2], c3 = run[4 * lane + 3];
+        int v = c0 + c1 + c2 + c3;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(v, d, 64);
+            if (lane >= d) v += u;
+        }
+        const int e = v - (c0 + c1 + c2 + c3);
+        loc[4 * lane] = e;
+        loc[4 * lane + 1] = e + c0;
+        loc[4 * lane + 2] = e + c0 + c1;
+        loc[4 * lane + 3] = e + c0 + c1 + c2;
+    }
+    __syncthreads();
+    run[tid] = loc[tid];
+
+    // stable ranks into LDS, round by round
     for (int r = 0; r < kRounds; ++r) {
         for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
         __syncthreads();
-        int64_t idx = base + (int64_t)r * kThreads + tid;
-        bool valid = idx < n;
-        uint32_t key = valid ? kin[idx] : 0u;
-        int32_t val = valid ? vin[idx] : 0;
-        uint32_t d = (key >> shift) & 255u;
+        const int i = r * kThreads + tid;
+        const bool valid = i < cnt;
+        const uint32_t key = valid ? kin[base + i] : 0u;
+        const int32_t val = valid ? vin[base + i] : 0;
+        const uint32_t d = (key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < 8; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bal = __ballot(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
             peers &= bit ? bal : ~bal;
         }
-        int rank = __popcll(peers & lt);
+        const int rank = __popcll(peers & lt);
         if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
         __syncthreads();
         if (valid) {
             int pos = run[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            kout[pos] = key;
-            vout[pos] = val;
+            skey[pos] = key;
+            sval[pos] = val;
         }
         __syncthreads();
         int add = 0;
         for (int w = 0; w < kWaves; ++w) add += wcnt[w][tid];
         run[tid] += add;
         __syncthreads();
+    }
+
+    // out in digit order: slot j of digit d goes after the digit's earlier tiles
+    for (int j = tid; j < cnt; j += kThreads) {
+        const uint32_t key = skey[j];
+        const uint32_t d = (key >> shift) & 255u;
+        const int64_t pos = (int64_t)off[(int64_t)d * ntiles + blockIdx.x] + (j - loc[d]);
+        kout[pos] = key;
+        vout[pos] = sval[j];
     }
 }
 

@@ -22,7 +22,7 @@ struct GridRef {
     const int2 *rows;
     const Rec64 *rec64;
     const Slot *blk;     // cell blocks (header, FP32 or compact records, neighbour block offsets)
-    const int32_t *blk_off;  // compact blocks: where each cell's block starts (null: FP32 blocks, block_of)
+    const int32_t *blk_off;  // where each cell's block starts when the grid keeps it (compact blocks; null: block_of)
     const double *rho_int;   // the density bound to the grid, internal order
     BucketGridView grid;
     double lo[3], hi[3];
@@ -124,7 +124,7 @@ inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
     G.rows = g.rows;
     G.rec64 = g.rec64;
     G.blk = g.blk;
-    G.blk_off = g.compact ? g.blk_off : nullptr;
+    G.blk_off = g.blk_off;
     G.rho_int = g.rho_int;
     G.grid = bucket_view(g);
     double diag = 0.0, cmax = 0.0;
@@ -610,14 +610,14 @@ __device__ __forceinline__ double block_rho(const GridRef &G, int32_t b)
 // The scale exponent E of a compact block from its header's length word.
 __device__ __forceinline__ int32_t scale_exp(int32_t lenword) { return (int32_t)((uint32_t)lenword >> 24) - kScaleBias; }
 
-// The block of the current cell R.m: where it starts (kept per cell for
-// compact blocks, else derived from the row) and, for compact blocks, its
-// scale exponent from the header. FP64 mode reads no blocks.
+// The block of the current cell R.m: where it starts (kept per cell when
+// the grid has the starts, else derived from the row) and, for compact
+// blocks, its scale exponent from the header. FP64 mode reads no blocks.
 template <int MODE>
 __device__ __forceinline__ void enter_block(const GridRef &G, RayState &R)
 {
     if (MODE != kModeCompact) {
-        R.b = block_of(R.rw, R.m);
+        R.b = (MODE != VOR_MODE_FP64 && G.blk_off) ? G.blk_off[R.m] : block_of(R.rw, R.m);
         return;
     }
     R.b = G.blk_off[R.m];
@@ -1042,7 +1042,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             settle(wrow.x);
             settle(wrow.y);
         } else {
-            // the header as its three 16-byte slots: {x, y}, {z, rho}, {uid, j, len, row}
+            // the header as its three 16-byte slots: {x, y}, {z, rho}, {uid, j, len, row start}
             const double2 s0 = *reinterpret_cast<const double2 *>(G.blk + j1);
             const double2 s1 = *reinterpret_cast<const double2 *>(G.blk + j1 + 1);
             const int4 s2 = *reinterpret_cast<const int4 *>(G.blk + j1 + 2);
@@ -1056,7 +1056,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                 wrow = make_int2(s2.w, s2.z & kLenMask);
                 wqe = scale_exp(s2.z);
             } else {
-                wrow = make_int2(j1 - kHdrSlots * wj, s2.z);
+                wrow = make_int2(s2.w, s2.z);
             }
             double den;
             best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
