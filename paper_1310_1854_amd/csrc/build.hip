@@ -384,6 +384,48 @@ __global__ void k_fill_records(const Site *__restrict__ sites, const int32_t *__
     if ((threadIdx.x & 63) == 0) atomicMax(max_row, m);
 }
 
+// Slots of an FP64 cell block: the header, then 28 bytes per neighbour (its
+// FP64 site and block offset), rounded up to whole slots.
+__global__ void k_fp64_slots(const int2 *__restrict__ rows, int64_t M, int32_t *__restrict__ slots)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) slots[i] = kHdrSlots + (7 * rows[i].y + 3) / 4;
+}
+
+// FP64 cell blocks, what FP64-mode steps read: the header of the mixed-mode
+// blocks, then the cell's n neighbour sites in FP64 (24 bytes each, in the
+// row's order: ascending internal index), then the n neighbours' block
+// offsets. Block i starts at blk64_off[i].
+__global__ void k_fill_blk64(const Site *__restrict__ sites, const int2 *__restrict__ rows,
+                             const Rec64 *__restrict__ r64, const int32_t *__restrict__ blk64_off, int64_t M,
+                             Slot *__restrict__ blk64)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int2 rw = rows[i];
+    const int32_t bo = blk64_off[i];
+    const Site si = sites[i];
+    BlockHdr h;
+    h.x = si.x;
+    h.y = si.y;
+    h.z = si.z;
+    h.rho = 0.0;
+    h.uid = (int32_t)si.uid;
+    h.j = (int32_t)i;
+    h.len = rw.y;
+    h.row = rw.x;
+    *reinterpret_cast<BlockHdr *>(blk64 + bo) = h;
+    double *rec = reinterpret_cast<double *>(blk64 + bo + kHdrSlots);
+    int32_t *nb = reinterpret_cast<int32_t *>(rec + 3 * rw.y);
+    for (int e = 0; e < rw.y; ++e) {
+        const Rec64 a = r64[rw.x + e];
+        rec[3 * e] = a.x;
+        rec[3 * e + 1] = a.y;
+        rec[3 * e + 2] = a.z;
+        nb[e] = blk64_off[a.j];
+    }
+}
+
 __global__ void k_export_counts(const int32_t *__restrict__ inv_perm, const int2 *__restrict__ rows,
                                 const uint8_t *__restrict__ walls, int64_t M, int32_t *__restrict__ cnt)
 {
@@ -700,6 +742,23 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     hdr = err + 1;   // longest row
     hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, col, total, start, M, g.rows,
                        g.rec64, g.blk, g.blk_off, (int)g.compact, compact_min_exp(g.box), hdr);
+    // the FP64 blocks: at most 4 + 7n/4 slots per cell
+    if ((int64_t)4 * M + 2 * g.nnz + kRecPad > 0x7fffffffLL) return fail(VOR_ECAPACITY);
+    g.blk64_off = dalloc<int32_t>(M + 1, rc, keep, A);
+    if (rc != VOR_OK) return fail(rc);
+    hipLaunchKernelGGL(k_fp64_slots, dim3(blocks_for(M, T)), dim3(T), 0, st, g.rows, M, slot);
+    rc = vrt_scan_i32_to_i32(slot, M, g.blk64_off, st);
+    if (rc != VOR_OK) return fail(rc);
+    int32_t ns64 = 0;
+    if (hipMemcpyAsync(&ns64, g.blk64_off + M, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VOR_EDEVICE);
+    g.nslots64 = ns64;
+    g.blk64 = dalloc<Slot>((int64_t)ns64 + kRecPad, rc, keep, A);
+    if (rc != VOR_OK) return fail(rc);
+    if (hipMemsetAsync(g.blk64 + ns64, 0, sizeof(Slot) * kRecPad, st) != hipSuccess) return fail(VOR_EDEVICE);
+    hipLaunchKernelGGL(k_fill_blk64, dim3(blocks_for(M, T)), dim3(T), 0, st, g.sites, g.rows, g.rec64, g.blk64_off, M,
+                       g.blk64);
     // size of the export with walls
     hipLaunchKernelGGL(k_export_counts, dim3(blocks_for(M, T)), dim3(T), 0, st, g.inv_perm, g.rows, g.wall_mask, M,
                        total);
@@ -758,7 +817,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
     tmp.clear();
     g.device_bytes = (int64_t)M * (sizeof(Site) * 2 + 4 * 2 + 1 + sizeof(int2) + 2 * sizeof(double)) + (B + 1) * 4 +
                      (g.nnz + kRecPad) * (int64_t)sizeof(Rec64) + (nslots + kRecPad) * (int64_t)sizeof(Slot) +
-                     (g.blk_off ? (M + 1) * 4 : 0);
+                     (g.blk_off ? (M + 1) * 4 : 0) + (g.nslots64 + kRecPad) * (int64_t)sizeof(Slot) + (M + 1) * 4;
     if (want_loc)
         g.device_bytes += (int64_t)M * 6 * (int64_t)sizeof(double) +
                           ((int64_t)g.loc_dims[0] * g.loc_dims[1] * g.loc_dims[2] + 1 + g.loc_entries) * 4;
@@ -838,9 +897,20 @@ extern "C" vor_status vor_grid_truncate_row(vor_grid *G, int64_t site, int32_t k
         int32_t len = 0;
         if (hipMemcpy(&len, &h->len, sizeof(len), hipMemcpyDeviceToHost) != hipSuccess) return VOR_EDEVICE;
         len = (len & ~kLenMask) | keep;   // the scale exponent stays
+        // the same in the FP64 block (24-byte records)
+        int32_t bo64 = 0;
+        if (hipMemcpy(&bo64, g.blk64_off + i, sizeof(bo64), hipMemcpyDeviceToHost) != hipSuccess) return VOR_EDEVICE;
+        char *rec64 = reinterpret_cast<char *>(g.blk64 + bo64 + kHdrSlots);
+        if (keep > 0 && (hipMemcpy(nb.data(), rec64 + 24 * rw.y, sizeof(int32_t) * keep, hipMemcpyDeviceToHost) !=
+                             hipSuccess ||
+                         hipMemcpy(rec64 + 24 * keep, nb.data(), sizeof(int32_t) * keep, hipMemcpyHostToDevice) !=
+                             hipSuccess))
+            return VOR_EDEVICE;
+        BlockHdr *h64 = reinterpret_cast<BlockHdr *>(g.blk64 + bo64);
         rw.y = keep;
         if (hipMemcpy(g.rows + i, &rw, sizeof(rw), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(&h->len, &len, sizeof(len), hipMemcpyHostToDevice) != hipSuccess)
+            hipMemcpy(&h->len, &len, sizeof(len), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(&h64->len, &keep, sizeof(keep), hipMemcpyHostToDevice) != hipSuccess)
             return VOR_EDEVICE;
     }
     return VOR_OK;
@@ -865,15 +935,17 @@ extern "C" vor_status vor_grid_bboxes(const vor_grid *G, double *bbox, void *str
     return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
 }
 
-__global__ void k_bind_density(Slot *__restrict__ blk, const int2 *__restrict__ rows,
-                               const int32_t *__restrict__ blk_off, const int32_t *__restrict__ perm, int64_t M,
-                               const double *__restrict__ density, double *__restrict__ rho_int)
+__global__ void k_bind_density(Slot *__restrict__ blk, Slot *__restrict__ blk64, const int2 *__restrict__ rows,
+                               const int32_t *__restrict__ blk_off, const int32_t *__restrict__ blk64_off,
+                               const int32_t *__restrict__ perm, int64_t M, const double *__restrict__ density,
+                               double *__restrict__ rho_int)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     const double r = density ? density[perm[i]] : 0.0;
     const int32_t bo = blk_off ? blk_off[i] : block_of(rows[i], (int32_t)i);
     reinterpret_cast<BlockHdr *>(blk + bo)->rho = r;
+    reinterpret_cast<BlockHdr *>(blk64 + blk64_off[i])->rho = r;
     rho_int[i] = r;
 }
 
@@ -882,8 +954,8 @@ extern "C" vor_status vor_grid_bind_density(vor_grid *G, const double *density, 
     if (!G) return VOR_EINVAL;
     Grid &g = G->g;
     const int T = 256;
-    hipLaunchKernelGGL(k_bind_density, dim3(blocks_for(g.M, T)), dim3(T), 0, (hipStream_t)stream, g.blk, g.rows,
-                       g.blk_off, g.perm, g.M, density, g.rho_int);
+    hipLaunchKernelGGL(k_bind_density, dim3(blocks_for(g.M, T)), dim3(T), 0, (hipStream_t)stream, g.blk, g.blk64,
+                       g.rows, g.blk_off, g.blk64_off, g.perm, g.M, density, g.rho_int);
     if (hipGetLastError() != hipSuccess) return VOR_EDEVICE;
     g.rho_bound = density ? 1 : 0;
     return VOR_OK;

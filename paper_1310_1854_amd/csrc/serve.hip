@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     R.cap = rq.seg_cell ? rq.seg_stride : 0;
                     if (R.st == RAY_OK) {
                         ray_begin_at<MODE>(G, R, rq.n_seg[ray], s0);   // start cell from the launch's start pass
-                        R.rho = (MODE != VOR_MODE_FP64 && (ctx & 2)) ? block_rho(G, R.b) : 0.0;   // mixed mode carries it
+                        R.rho = (MODE != VOR_MODE_FP64 && (ctx & 2)) ? block_rho<MODE>(G, R.b) : 0.0;   // mixed mode carries it
                         settle(R.rho);
                     } else {
                         R.L = 0.0;

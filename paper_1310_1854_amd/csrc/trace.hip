@@ -220,7 +220,7 @@ __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RaySt
         R.s_c = 0.0;
     }
     if (EXT) ray_extras_begin(A.X, ray, R);
-    R.rho = (MODE != VOR_MODE_FP64 && A.I.grid_rho && R.st == RAY_OK) ? block_rho(A.G, R.b) : 0.0;
+    R.rho = (MODE != VOR_MODE_FP64 && A.I.grid_rho && R.st == RAY_OK) ? block_rho<MODE>(A.G, R.b) : 0.0;
     settle_start(R);
 }
 

@@ -23,6 +23,8 @@ struct GridRef {
     const Rec64 *rec64;
     const Slot *blk;     // cell blocks (header, FP32 or compact records, neighbour block offsets)
     const int32_t *blk_off;  // where each cell's block starts when the grid keeps it (compact blocks; null: block_of)
+    const Slot *blk64;       // FP64 cell blocks (header, FP64 neighbour sites, block offsets): FP64-mode steps
+    const int32_t *blk64_off;
     const double *rho_int;   // the density bound to the grid, internal order
     BucketGridView grid;
     double lo[3], hi[3];
@@ -125,6 +127,8 @@ inline GridRef grid_ref(const Grid &g, int32_t max_steps, double eps_mix)
     G.rec64 = g.rec64;
     G.blk = g.blk;
     G.blk_off = g.blk_off;
+    G.blk64 = g.blk64;
+    G.blk64_off = g.blk64_off;
     G.rho_int = g.rho_int;
     G.grid = bucket_view(g);
     double diag = 0.0, cmax = 0.0;
@@ -214,6 +218,49 @@ __device__ __forceinline__ int exit_fp64(const Rec64 *__restrict__ rec, int2 rw,
         }
     }
     return win;
+}
+
+// The FP64 exit search over the current cell's FP64 block (offset b, n
+// records): exit_fp64's arithmetic and tie rules on the neighbour sites read
+// from the block, 4 at a time as 6 aligned 16-byte loads (entries past the
+// row end -- the block offsets, padding or the next block -- masked). A row
+// lists its neighbours by ascending internal index, so the last tie rule
+// (the lower index) is the earlier record. Returns the winner's place in the
+// row, or -1 when the chord end comes first; the crossing in best.
+__device__ __forceinline__ int exit_fp64_blk(const Slot *__restrict__ blk64, int32_t b, int n, const double pm[3],
+                                             const double r0[3], const double k[3], double L, double &best)
+{
+    static_assert(kBatch64 == 4, "a batch of 4 FP64 sites is 6 aligned 16-byte loads");
+    best = L;
+    double best_den = 1e308 * 10.0;
+    int win = -1;
+    const double2 *rec = reinterpret_cast<const double2 *>(blk64 + b + kHdrSlots);
+    for (int e0 = 0; e0 < n; e0 += 4) {
+        VRT_DIAG_COUNT(1);
+        double q[12];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+            const double2 x = rec[3 * e0 / 2 + u];
+            q[2 * u] = x.x;
+            q[2 * u + 1] = x.y;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double den;
+            const double sj = cross_fp64(q[3 * u], q[3 * u + 1], q[3 * u + 2], pm, r0, k, den);
+            const bool take = e0 + u < n && den > 0.0 && (sj < best || (sj == best && win >= 0 && den > best_den));
+            best = take ? sj : best;
+            best_den = take ? den : best_den;
+            win = take ? e0 + u : win;
+        }
+    }
+    return win;
+}
+
+// The block offsets that follow the n FP64 sites of the FP64 block at b.
+__device__ __forceinline__ const int32_t *fp64_block_offsets(const Slot *blk64, int32_t b, int n)
+{
+    return reinterpret_cast<const int32_t *>(reinterpret_cast<const double *>(blk64 + b + kHdrSlots) + 3 * n);
 }
 
 // Mixed-precision exit search. Returns -1 when the chord end wins
@@ -601,10 +648,12 @@ __device__ __forceinline__ void settle(T &v)
     asm volatile("" : "+v"(v));
 }
 
-// The density held in the header of the block at offset b.
+// The density held in the header of the block at offset b (FP64 mode: of
+// the FP64 block).
+template <int MODE>
 __device__ __forceinline__ double block_rho(const GridRef &G, int32_t b)
 {
-    return reinterpret_cast<const BlockHdr *>(G.blk + b)->rho;
+    return reinterpret_cast<const BlockHdr *>((MODE == VOR_MODE_FP64 ? G.blk64 : G.blk) + b)->rho;
 }
 
 // The scale exponent E of a compact block from its header's length word.
@@ -612,12 +661,16 @@ __device__ __forceinline__ int32_t scale_exp(int32_t lenword) { return (int32_t)
 
 // The block of the current cell R.m: where it starts (kept per cell when
 // the grid has the starts, else derived from the row) and, for compact
-// blocks, its scale exponent from the header. FP64 mode reads no blocks.
+// blocks, its scale exponent from the header. FP64 mode: its FP64 block.
 template <int MODE>
 __device__ __forceinline__ void enter_block(const GridRef &G, RayState &R)
 {
+    if (MODE == VOR_MODE_FP64) {
+        R.b = G.blk64_off[R.m];
+        return;
+    }
     if (MODE != kModeCompact) {
-        R.b = (MODE != VOR_MODE_FP64 && G.blk_off) ? G.blk_off[R.m] : block_of(R.rw, R.m);
+        R.b = G.blk_off ? G.blk_off[R.m] : block_of(R.rw, R.m);
         return;
     }
     R.b = G.blk_off[R.m];
@@ -1011,12 +1064,13 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
                                              const Extras &X)
 {
     // The current cell's density. Bound to the grid: mixed mode read it with
-    // the cell's block header when the ray entered the cell; FP64 mode, which
-    // does not read the blocks, takes it from the copy in internal order,
-    // whose lines neighbouring cells share. Else from the caller's array,
-    // loaded before the winner's header or record so that one wait covers
-    // both (loaded after the segment store, its wait would also hold the step
-    // until the store completed).
+    // the cell's block header when the ray entered the cell; FP64 mode takes
+    // it from the copy in internal order, whose lines neighbouring cells
+    // share (carried in registers it would cost the FP64 kernel its fourth
+    // wave per SIMD). Else from the caller's array, loaded before the
+    // winner's header or record so that one wait covers both (loaded after
+    // the segment store, its wait would also hold the step until the store
+    // completed).
     const bool has_rho = I.grid_rho || I.density;
     double rho = 0.0, wrho = 0.0;
     if (I.grid_rho) rho = (MODE == VOR_MODE_FP64) ? G.rho_int[R.m] : R.rho;
@@ -1026,7 +1080,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
     int2 wrow = make_int2(0, 0);
     int32_t wqe = 0;
     if (win >= 0) {
-        if (MODE == VOR_MODE_FP64 || redo) {
+        if (MODE != VOR_MODE_FP64 && redo) {
             const Rec64 w = G.rec64[win];
             wj = w.j;
             wuid = w.uid;
@@ -1042,14 +1096,18 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             settle(wrow.x);
             settle(wrow.y);
         } else {
-            // the header as its three 16-byte slots: {x, y}, {z, rho}, {uid, j, len, row start}
-            const double2 s0 = *reinterpret_cast<const double2 *>(G.blk + j1);
-            const double2 s1 = *reinterpret_cast<const double2 *>(G.blk + j1 + 1);
-            const int4 s2 = *reinterpret_cast<const int4 *>(G.blk + j1 + 2);
+            // the winner's block header as its three 16-byte slots: {x, y}, {z, rho},
+            // {uid, j, len, row start}; in FP64 mode its FP64 block, whose offset
+            // follows the current block's records
+            const Slot *B = (MODE == VOR_MODE_FP64) ? G.blk64 : G.blk;
+            if (MODE == VOR_MODE_FP64) j1 = fp64_block_offsets(G.blk64, R.b, R.rw.y)[win];
+            const double2 s0 = *reinterpret_cast<const double2 *>(B + j1);
+            const double2 s1 = *reinterpret_cast<const double2 *>(B + j1 + 1);
+            const int4 s2 = *reinterpret_cast<const int4 *>(B + j1 + 2);
             wx = s0.x;
             wy = s0.y;
             wz = s1.x;
-            if (I.grid_rho) wrho = s1.y;
+            if (MODE != VOR_MODE_FP64 && I.grid_rho) wrho = s1.y;
             wuid = s2.x;
             wj = s2.y;
             if (MODE == kModeCompact) {
@@ -1058,8 +1116,10 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
             } else {
                 wrow = make_int2(s2.w, s2.z);
             }
-            double den;
-            best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
+            if (MODE != VOR_MODE_FP64) {   // FP64 mode found it in the search
+                double den;
+                best = cross_fp64(wx, wy, wz, R.pm, R.r0, R.k, den);
+            }
             settle(wrho);
         }
     }
@@ -1112,7 +1172,7 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
         settle(R.rw.y);
         enter_block<MODE>(G, R);
         if (MODE != VOR_MODE_FP64 && I.grid_rho) {
-            R.rho = block_rho(G, R.b);
+            R.rho = block_rho<MODE>(G, R.b);
             settle(R.rho);
         }
         return true;
@@ -1125,11 +1185,11 @@ __device__ __forceinline__ bool ray_step_end(const GridRef &G, const RayIn &I, R
     R.pm[2] = wz;
     R.rw = wrow;
     if (MODE == VOR_MODE_FP64) {
-        R.b = block_of(wrow, wj);   // not read in FP64 mode
+        R.b = j1;
     } else if (redo) {
         enter_block<MODE>(G, R);
         if (I.grid_rho) {
-            R.rho = block_rho(G, R.b);
+            R.rho = block_rho<MODE>(G, R.b);
             settle(R.rho);
         }
         if (MODE == kModeCompact) settle(R.qe);
@@ -1153,7 +1213,7 @@ __device__ __forceinline__ bool ray_step(const GridRef &G, const RayIn &I, RaySt
     int32_t j1 = -1;
     int win;
     if (MODE == VOR_MODE_FP64) {
-        win = exit_fp64(G.rec64, R.rw, R.pm, R.r0, R.k, R.L, best);
+        win = exit_fp64_blk(G.blk64, R.b, R.rw.y, R.pm, R.r0, R.k, R.L, best);
     } else {
         if (MODE == kModeCompact)
             win = exit_mixed_compact(G.rec64, R.rw, G.blk, R.b, R.pm, R.r0, R.k, R.L, R.s_c, G.eps_mix, G.eps_abs,

@@ -107,6 +107,11 @@ struct Grid {
     double *rho_int = nullptr;      // [M] the bound density in internal order (FP64 mode reads it here)
     int32_t compact = 0;            // cell blocks with 8-byte fixed-point records
     int32_t *blk_off = nullptr;     // [M + 1] compact blocks: the slot where each cell's block starts
+    // FP64 cell blocks (FP64-mode steps): the same header, then the n
+    // neighbour sites in FP64 (24 bytes each), then their FP64 block offsets
+    Slot *blk64 = nullptr;          // [nslots64 + kRecPad]
+    int32_t *blk64_off = nullptr;   // [M + 1] where each cell's FP64 block starts
+    int64_t nslots64 = 0;
     double build_ms = 0;
     int64_t device_bytes = 0;
     int device = 0;
