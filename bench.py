@@ -43,6 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # The sources the trace kernel is compiled from: a traffic figure measured
 # on another version of them is not reported.
 KERNEL_SOURCES = ("paper_1310_1854_amd/csrc/trace.hip", "paper_1310_1854_amd/csrc/trace_core.h",
+                  "paper_1310_1854_amd/csrc/locate_core.h",
                   "paper_1310_1854_amd/csrc/vrt_internal.h", "include/voronoi_rt.h",
                   "paper_1310_1854_amd/build_lib.py")
 # Counter summaries of the trace kernel per workload (profiles/).
@@ -375,8 +376,11 @@ def request_chunks(n, per_ray):
 
 def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid_density=False, per_ray=None):
     """Submit the requests at the given offsets (seconds from the start) to a
-    fresh server, reap them in completion order, and return the wall time,
-    crossings, p50/p99 latency and (keep) every request's tau and statuses.
+    fresh server, reap them in completion order, and return the wall time
+    from the first submission to the last completion (each request's
+    submission time plus its latency as the server measured it, so that the
+    client's reaping -- result copies included -- does not count), crossings,
+    p50/p99 latency and (keep) every request's tau and statuses.
     grid_density: the requests use the densities bound to their grids
     instead of rhos. per_ray[g]: mean spill chunks per ray on grid g (the
     requests' first spill pools); every path is stored whole."""
@@ -384,6 +388,7 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid
 
     srv = vrt.Server(grids, budget_bytes=budget)
     lat = [None] * len(reqs)
+    t_sub = [None] * len(reqs)
     taus = [None] * len(reqs)
     stats = [None] * len(reqs)
     done = threading.Event()
@@ -417,12 +422,13 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid
         n = r["o"].shape[0]
         chunks = request_chunks(n, per_ray[r["grid"]]) if stride > 0 else 0
         with lock:
+            t_sub[i] = time.perf_counter()
             rid = srv.submit(r["grid"], r["o"], r["d"], None if grid_density else rhos[r["grid"]], mode=r["mode"],
                              seg_stride=stride, spill_chunks=chunks, grid_density=grid_density)
             index[rid] = i
     if not done.wait(600):
         raise RuntimeError("serving run did not finish within 600 s")
-    t1 = time.perf_counter()
+    t1 = max(a + b for a, b in zip(t_sub, lat))   # the last completion
     st = srv.stats()
     while st["running"]:   # crossings are counted when a launch ends
         time.sleep(0.001)
@@ -507,7 +513,8 @@ def serving_precision_result(torch, vrt, workloads, n_requests, budget_gib, with
     requests (log-uniform sizes in [256, 65536] rays from random sites,
     isotropic) are served all-FP64 and all-mixed, every request submitted at
     once (saturated) and (with_load) at an offered load of 0.8 of that, with
-    whole paths: 32-slot windows and spill chains from each request's pool.
+    whole paths: 32-slot windows and spill chains from each request's pool,
+    the density field bound to the resident grid (every leg reads it there).
     Beside them vor_trace runs the same rays in one persistent launch, with
     the same windows and a spill sized for every path, in FP64 and mixed, in
     submission order and in the coherent order of vor_order_rays. Every
@@ -520,6 +527,7 @@ def serving_precision_result(torch, vrt, workloads, n_requests, budget_gib, with
     g = workloads.serving_grids()[2]
     grid = vrt.build_grid(g.sites, g.box)
     rho = torch.as_tensor(g.density, device="cuda")
+    grid.bind_density(rho)   # a resident grid carries its density field; every leg below reads it there
     stride, budget = 32, int(budget_gib * (1 << 30))
     base = workloads.serving_requests(n_requests, [g], rate_hz=1.0)
     reqs = [dict(grid=0, mode=None, o=torch.as_tensor(r["origins"], device="cuda"),
@@ -534,7 +542,7 @@ def serving_precision_result(torch, vrt, workloads, n_requests, budget_gib, with
     for mode in ("fp64", "mixed"):
         for r in reqs:
             r["mode"] = mode
-        kw = dict(per_ray=per_ray)
+        kw = dict(per_ray=per_ray, grid_density=True)
         run_server(vrt, [grid], [rho], reqs, zeros, stride, budget, **kw)   # warm-up
         sat, taus[mode] = run_server(vrt, [grid], [rho], reqs, zeros, stride, budget, keep=True, **kw)
         served[mode] = {"saturated": sat}
@@ -549,9 +557,9 @@ def serving_precision_result(torch, vrt, workloads, n_requests, budget_gib, with
     tau_plain = None
     for key, mode, ordered in (("fp64", "fp64", False), ("fp64_ordered", "fp64", True),
                                ("mixed", "mixed", False), ("mixed_ordered", "mixed", True)):
-        # densities from the array, as the requests pass them to the server
+        # densities bound to the grid, as the served requests read them
         spec = {"mode": mode, "stride": stride, "spill_chunks_per_ray": 1.25 * per_ray[0], "persistent": True,
-                "grid_density": False, "ordered": ordered}
+                "grid_density": True, "ordered": ordered}
         bufs = prepare_buffers(vrt, torch, grid, O, D, rho, spec, mode)
         bufs.counters.zero_()
         ms = float(np.mean(run_steps(vrt, torch, grid, O, D, rho, bufs, spec, mode, 3, timed=True)))
@@ -617,11 +625,14 @@ def main(argv=None):
     ap.add_argument("--serving-density", choices=["grid", "array"], default="grid",
                     help="serving: densities bound to the resident grids, or passed with every request")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the exact-output comparison (its extra trace launches would mix into a profile of "
+                         "the trace kernel)")
     ap.add_argument("--records", choices=["auto", "fp32", "compact"], default="auto",
                     help="record layout of the traced grids (auto: compact for tables beyond the last-level cache)")
     ap.add_argument("--no-configs", action="store_true",
                     help="default workload only: leave out the other configurations' block")
-    ap.add_argument("--config-requests", type=int, default=600,
+    ap.add_argument("--config-requests", type=int, default=2000,
                     help="requests of the serving-precision entry of the configurations block")
     ap.add_argument("--roofline-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -762,7 +773,8 @@ def measure(args, torch, vrt, workloads, name, steps, warmup, roofline_reps, wit
                          "n_seg_identical": bool(torch.equal(bufs.n_seg, nseg_mixed))}
 
     del fb
-    exact = None if spec.get("transport") else exact_output(vrt, torch, grid, o, d, rho, bufs, spec, mode)
+    exact = None if (spec.get("transport") or args.no_exact) else \
+        exact_output(vrt, torch, grid, o, d, rho, bufs, spec, mode)
     traffic, traffic_src, l2_hit = measured_traffic(args.workload)
     copy_bw = copy_bandwidth(torch)
 

@@ -32,6 +32,7 @@
 #include <thread>
 #include <vector>
 
+#include "locate_core.h"
 #include "trace_core.h"
 
 using namespace vrt;
@@ -121,7 +122,8 @@ constexpr bool kServeWide = VRT_SERVE_WIDE != 0;
 // kernel of each class over the chunks of that class, so each holds the
 // registers of one step only.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids, const ReqDev *__restrict__ reqs,
+__global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids, const LocView *__restrict__ locs,
+                                               const ReqDev *__restrict__ reqs,
                                                const ChunkDev *__restrict__ chunks, int n_chunks,
                                                unsigned int *__restrict__ head,
                                                unsigned long long *__restrict__ counters)
@@ -238,6 +240,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                 const int take = min(__popcll(pend), cur_left);
                 const int rank = __popcll(pend & lt);
                 const bool mine = ((pend >> lane) & 1ull) && rank < take;
+                double s0 = 0.0;
                 if (mine) {
                     const ReqDev &rq = reqs[cur_req];
                     q = cur_req;
@@ -250,21 +253,30 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     vec = !rq.seg_cell ? 0 : rq.seg_stride % 16 == 0 ? 2 : rq.seg_stride % 8 == 0 ? 1 : 0;
                     if (rq.spill.first) rq.spill.first[ray] = -1;   // no chunk yet (taking one overwrites it)
                     S = RayStats();
-                    double s0;
                     R.st = ray_setup<false>(G, rq.in, ray, R.r0, R.k, R.L, s0);
                     R.tau = 0.0;
                     R.chunk = rq.seg_cell ? -1 : -2;   // tau only: no spill chunk is ever taken
                     R.ray = (int32_t)ray;
                     R.base = ray * rq.seg_stride;
                     R.cap = rq.seg_cell ? rq.seg_stride : 0;
-                    if (R.st == RAY_OK) {
-                        ray_begin_at<MODE>(G, R, rq.n_seg[ray], s0);   // start cell from the launch's start pass
-                        R.rho = (MODE != VOR_MODE_FP64 && (ctx & 2)) ? block_rho<MODE>(G, R.b) : 0.0;   // mixed mode carries it
-                        settle(R.rho);
-                    } else {
-                        R.L = 0.0;
+                }
+                // the start cells C(r0) (Sect. 2.3) of the rays just handed out, side by side
+                // (every lane takes part: one cooperative search when all 64 share a point)
+                {
+                    double qp[3] = {0.0, 0.0, 0.0};
+                    if (mine) start_point(R.r0, R.k, s0, qp);
+                    const bool ok = mine && R.st == RAY_OK;
+                    const int32_t m0 = start_cell(G.grid, locs[ctx >> 2], qp, ok);
+                    if (mine) {
+                        if (ok) {
+                            ray_begin_at<MODE>(G, R, m0, s0);
+                            R.rho = (MODE != VOR_MODE_FP64 && (ctx & 2)) ? block_rho<MODE>(G, R.b) : 0.0;   // mixed mode carries it
+                            settle(R.rho);
+                        } else {
+                            R.L = 0.0;
+                        }
+                        live = true;
                     }
-                    live = true;
                 }
                 const uint64_t taken = __ballot(mine);
                 pend &= ~taken;
@@ -304,34 +316,6 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
     }
 }
 
-// The start cells C(r0) (Sect. 2.3) of every ray of a launch, ahead of the
-// traversal (as vor_trace's start pass): block c locates the rays of chunk c
-// side by side and leaves each internal cell index (-1 for a ray without a
-// path) in its request's n_seg slot, which the traversal reads at the ray's
-// start and overwrites with the segment count at its end.
-__global__ void __launch_bounds__(256) k_serve_start(const GridRef *__restrict__ grids,
-                                                     const ReqDev *__restrict__ reqs,
-                                                     const ChunkDev *__restrict__ chunks, int n_chunks)
-{
-    const int c = blockIdx.x;
-    if (c >= n_chunks) return;
-    const ChunkDev ch = chunks[c];
-    const ReqDev &rq = reqs[ch.req];
-    const GridRef &G = grids[ch.ctx >> 2];
-    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
-        const int64_t ray = (int64_t)ch.first + i;
-        double r0[3], k[3], L, s0;
-        const uint8_t st = ray_setup<false>(G, rq.in, ray, r0, k, L, s0);
-        int32_t m = -1;
-        if (st == RAY_OK) {
-            double q[3];
-            start_point(r0, k, s0, q);
-            m = nearest_site(G.grid, q, nullptr);
-        }
-        rq.n_seg[ray] = m;
-    }
-}
-
 __global__ void k_zero_launch(unsigned int *head, unsigned long long *counters, ReqCount *rc, int n_req)
 {
     if (threadIdx.x < 3) head[threadIdx.x] = 0;
@@ -368,6 +352,7 @@ struct Request {
     int32_t *spill_cell = nullptr;
     double *spill_len = nullptr;
     hipEvent_t ready = nullptr;    // recorded on the submitter's stream: the inputs are written
+    hipStream_t src = nullptr;     // that stream
     hipEvent_t copied = nullptr;   // recorded after the caller's last vor_server_copy_result
 };
 
@@ -422,6 +407,7 @@ struct vor_server {
     std::vector<GridRef> grid_refs;
     std::vector<const vor_grid *> grids;
     GridRef *d_grids = nullptr;
+    LocView *d_locs = nullptr;         // each grid's block lists (start cells; null lists: the bucket grid)
     char *arena = nullptr;
     size_t budget = 0, used = 0;
     std::map<size_t, size_t> free_blocks;   // offset -> size
@@ -600,30 +586,37 @@ struct vor_server {
         L.seen.assign(nreq, 0);
         L.open = nreq;
         bool ok = true;
-        // the launch starts once every request's inputs are written on its submitter's stream
-        for (int64_t id : L.reqs) {
-            Request &r = reqs[id];
-            if (r.ready) ok = ok && hipStreamWaitEvent(L.stream, r.ready, 0) == hipSuccess;
+        // the launch starts once every request's inputs are written on its submitter's
+        // stream: the newest of a stream's events covers the earlier ones
+        {
+            std::map<hipStream_t, const Request *> newest;
+            for (int64_t id : L.reqs) {
+                const Request &r = reqs[id];
+                if (!r.ready) continue;
+                const Request *&m = newest[r.src];
+                if (!m || r.id > m->id) m = &r;
+            }
+            for (const auto &kv : newest) ok = ok && hipStreamWaitEvent(L.stream, kv.second->ready, 0) == hipSuccess;
         }
         ok = ok && hipMemcpyAsync(L.d_reqs, L.h_reqs, sizeof(ReqDev) * nreq, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
                   hipMemcpyAsync(L.d_chunks, L.h_chunks, sizeof(ChunkDev) * nch, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
                   hipMemcpyAsync(L.d_remaining, L.h_remaining, sizeof(int32_t) * nreq, hipMemcpyHostToDevice,
                                  L.stream) == hipSuccess;
         hipLaunchKernelGGL(k_zero_launch, dim3(1), dim3(256), 0, L.stream, L.d_head, L.d_counters, L.d_count, nreq);
-        hipLaunchKernelGGL(k_serve_start, dim3(nch), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks, nch);
         if (ncls[0] > 0) {
             const int nb = std::max(1, std::min(blocks64, (ncls[0] + 3) / 4));
-            hipLaunchKernelGGL(k_serve<VOR_MODE_FP64>, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs, L.d_chunks,
+            hipLaunchKernelGGL(k_serve<VOR_MODE_FP64>, dim3(nb), dim3(256), 0, L.stream, d_grids, d_locs, L.d_reqs,
+                               L.d_chunks,
                                ncls[0], L.d_head, L.d_counters);
         }
         if (ncls[1] > 0) {
             const int nb = std::max(1, std::min(blocks, (ncls[1] + 3) / 4));
-            hipLaunchKernelGGL(k_serve<VOR_MODE_MIXED>, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs,
+            hipLaunchKernelGGL(k_serve<VOR_MODE_MIXED>, dim3(nb), dim3(256), 0, L.stream, d_grids, d_locs, L.d_reqs,
                                L.d_chunks + ncls[0], ncls[1], L.d_head + 1, L.d_counters);
         }
         if (ncls[2] > 0) {
             const int nb = std::max(1, std::min(blocks_c, (ncls[2] + 3) / 4));
-            hipLaunchKernelGGL(k_serve<kModeCompact>, dim3(nb), dim3(256), 0, L.stream, d_grids, L.d_reqs,
+            hipLaunchKernelGGL(k_serve<kModeCompact>, dim3(nb), dim3(256), 0, L.stream, d_grids, d_locs, L.d_reqs,
                                L.d_chunks + ncls[0] + ncls[1], ncls[2], L.d_head + 2, L.d_counters);
         }
         ok = ok && hipGetLastError() == hipSuccess &&
@@ -816,8 +809,12 @@ vor_status vor_server_create(const vor_grid *const *grids, int32_t n_grids, int6
         S->grid_refs.push_back(grid_ref(vrt_grid_of(grids[i]), 0, 0.0));
         S->grids.push_back(grids[i]);
     }
+    std::vector<LocView> locs;
+    for (int i = 0; i < n_grids; ++i) locs.push_back(loc_view(vrt_grid_of(grids[i])));
     bool ok = hipMalloc(&S->d_grids, sizeof(GridRef) * n_grids) == hipSuccess &&
               hipMemcpy(S->d_grids, S->grid_refs.data(), sizeof(GridRef) * n_grids, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMalloc(&S->d_locs, sizeof(LocView) * n_grids) == hipSuccess &&
+              hipMemcpy(S->d_locs, locs.data(), sizeof(LocView) * n_grids, hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc(&S->arena, (size_t)budget_bytes) == hipSuccess;
     for (auto &L : S->launches) {
         ok = ok && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess &&
@@ -898,6 +895,7 @@ vor_status vor_server_submit(vor_server *S, int32_t grid, const double *origins,
     r.spill_chunks = spill_chunks;
     r.bytes = bytes;
     r.ready = ready;
+    r.src = (hipStream_t)stream;
     r.t_submit = clk::now();
     S->reqs[r.id] = r;
     S->waiting.push_back(r.id);
@@ -1090,6 +1088,7 @@ void vor_server_destroy(vor_server *S)
     if (S->h_counts) (void)hipHostFree(S->h_counts);
     if (S->arena) (void)hipFree(S->arena);
     if (S->d_grids) (void)hipFree(S->d_grids);
+    if (S->d_locs) (void)hipFree(S->d_locs);
     delete S;
 }
 

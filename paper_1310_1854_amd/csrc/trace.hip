@@ -10,99 +10,13 @@
 #include <mutex>
 
 #include "trace_core.h"
+#include "locate_core.h"
 
 using namespace vrt;
 
 const vrt::Grid &vrt_grid_of(const vor_grid *G);
 
 namespace {
-
-// C(r) through the paper's block lists (Sect. 2.3, steps 2-4), for a point
-// inside the closed box: the block holding the point, then the nearest site
-// among the cells listed for that block (equal distances: the lowest user
-// index). The cell holding the point is listed there, so this is the
-// nearest site of all. Returns the internal index (-1 for an empty list,
-// which a point inside the box cannot meet) and the user index in *uid.
-struct LocView {
-    double lo[3], hi[3], inv_h[3];
-    int32_t dims[3];
-    const int32_t *start;   // null: the grid has no block lists
-    const int32_t *cells;
-    const Site *sites;
-};
-
-LocView loc_view(const Grid &g)
-{
-    LocView L;
-    for (int a = 0; a < 3; ++a) {
-        L.lo[a] = g.box[a];
-        L.hi[a] = g.box[a + 3];
-        L.inv_h[a] = g.loc_inv_h[a];
-        L.dims[a] = g.loc_dims[a];
-    }
-    L.start = g.loc_start;
-    L.cells = g.loc_cells;
-    L.sites = g.sites;
-    return L;
-}
-
-__device__ __forceinline__ int32_t nearest_in_blocks(const LocView &L, const double q[3], int32_t *uid)
-{
-    int b[3];
-    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], L.lo[a], L.inv_h[a], L.dims[a]);
-    const int64_t k = ((int64_t)b[0] * L.dims[1] + b[1]) * L.dims[2] + b[2];
-    double best = __builtin_huge_val();
-    int32_t best_u = -1, best_m = -1;
-    for (int s = L.start[k]; s < L.start[k + 1]; ++s) {
-        const int32_t m = L.cells[s];
-        const Site p = L.sites[m];
-        const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const int32_t u = (int32_t)p.uid;
-        if (d2 < best || (d2 == best && u < best_u)) {
-            best = d2;
-            best_u = u;
-            best_m = m;
-        }
-    }
-    *uid = best_u;
-    return best_m;
-}
-
-// The same search by a whole wave for one point shared by its 64 lanes:
-// the lanes take the list in turn, then the best (distance, user index) is
-// reduced across the wave. Returns the internal index on every lane.
-__device__ __forceinline__ int32_t nearest_in_blocks_wave(const LocView &L, const double q[3])
-{
-    int b[3];
-    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], L.lo[a], L.inv_h[a], L.dims[a]);
-    const int64_t k = ((int64_t)b[0] * L.dims[1] + b[1]) * L.dims[2] + b[2];
-    double best = __builtin_huge_val();
-    int32_t best_u = 0x7fffffff, best_m = -1;
-    for (int s = L.start[k] + (int)(threadIdx.x & 63); s < L.start[k + 1]; s += 64) {
-        const int32_t m = L.cells[s];
-        const Site p = L.sites[m];
-        const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const int32_t u = (int32_t)p.uid;
-        if (d2 < best || (d2 == best && u < best_u)) {
-            best = d2;
-            best_u = u;
-            best_m = m;
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int32_t ou = __shfl_xor(best_u, off, 64);
-        const int32_t om = __shfl_xor(best_m, off, 64);
-        if (ob < best || (ob == best && ou < best_u)) {
-            best = ob;
-            best_u = ou;
-            best_m = om;
-        }
-    }
-    return best_m;
-}
 
 struct TraceArgs {
     GridRef G;
@@ -224,53 +138,6 @@ __device__ __forceinline__ void ray_start(const TraceArgs &A, int64_t ray, RaySt
     settle_start(R);
 }
 
-// nearest_site for a point shared by the whole wave: the sites of each
-// bucket are split over the 64 lanes, and after each shell the lanes agree
-// on the lexicographic minimum of (squared distance, user index). The
-// shells visited, the distances and the minimum are those of nearest_site.
-__device__ int32_t nearest_site_wave(const BucketGridView &g, const double q[3], int32_t *uid_out)
-{
-    const int lane = threadIdx.x & 63;
-    int b[3];
-    for (int a = 0; a < 3; ++a) b[a] = bucket_coord(q[a], g.lo[a], g.inv_h[a], g.dims[a]);
-    double best = 1e308 * 10.0;
-    int32_t best_i = -1;
-    int32_t best_u = 0x7fffffff;
-    for (int r = 0;; ++r) {
-        for_shell(g, b, r, [&](int bk) {
-            const int s0 = g.start[bk], s1 = g.start[bk + 1];
-            for (int s = s0 + lane; s < s1; s += 64) {
-                const Site p = g.items[s];
-                const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
-                const double d = dx * dx + dy * dy + dz * dz;
-                const int32_t idx = (int32_t)(p.uid & 0xffffffff);
-                const int32_t uid = (int32_t)(p.uid >> 32);
-                if (d < best || (d == best && uid < best_u)) {
-                    best = d;
-                    best_i = idx;
-                    best_u = uid;
-                }
-            }
-        });
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int32_t ou = __shfl_xor(best_u, off, 64);
-            const int32_t oi = __shfl_xor(best_i, off, 64);
-            if (ob < best || (ob == best && ou < best_u)) {
-                best = ob;
-                best_u = ou;
-                best_i = oi;
-            }
-        }
-        const double lb = shell_bound(g, q, b, r);
-        if (lb < 0.0) break;
-        const double lb2 = lb * lb * (1.0 - 1e-12);
-        if (best < lb2) break;
-    }
-    if (uid_out) *uid_out = best_u;
-    return best_i;
-}
-
 // The start cell C(r0) of every ray (Sect. 2.3), in processing order, ahead
 // of the traversal: the ring searches of neighbouring lanes run side by side
 // here instead of interrupting the persistent waves at every refill. A wave
@@ -285,20 +152,8 @@ __global__ void __launch_bounds__(256) k_start_cells(TraceArgs A)
     const uint8_t st = valid ? ray_setup(A.G, A.I, ray, r0, k, L, s0) : (uint8_t)RAY_BADDIR;
     double q[3];
     start_point(r0, k, s0, q);
-    const double q0 = __shfl(q[0], 0, 64), q1 = __shfl(q[1], 0, 64), q2 = __shfl(q[2], 0, 64);
-    const bool same = valid && st == RAY_OK && q[0] == q0 && q[1] == q1 && q[2] == q2;
-    int32_t m = -1, uid;
-    const bool shared = __ballot(true) == ~0ull && __ballot(same) == ~0ull;
-    if (A.loc.start) {   // the paper's block lists: one short list per ray, or one per wave
-        if (shared) m = nearest_in_blocks_wave(A.loc, q);
-        else if (valid && st == RAY_OK) m = nearest_in_blocks(A.loc, q, &uid);
-        if (valid && st == RAY_OK && m < 0) m = nearest_site(A.G.grid, q, nullptr);   // empty list: not in the box
-    } else if (shared) {
-        m = nearest_site_wave(A.G.grid, q, nullptr);
-    } else if (valid && st == RAY_OK) {
-        m = nearest_site(A.G.grid, q, nullptr);
-    }
-    if (valid) A.start[ray] = (st == RAY_OK) ? m : -1;
+    const int32_t m = start_cell(A.G.grid, A.loc, q, valid && st == RAY_OK);
+    if (valid) A.start[ray] = m;
 }
 
 // One ray per lane.
