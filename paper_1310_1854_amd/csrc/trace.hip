@@ -313,6 +313,21 @@ struct OrderBox {
     double lo[3], hi[3], scale[3], diag;
 };
 
+#ifndef VRT_ORDER_KEY_BITS
+#define VRT_ORDER_KEY_BITS 30
+#endif
+#ifndef VRT_CHORD_KEY_BITS
+#define VRT_CHORD_KEY_BITS 8
+#endif
+// Bits of the origin and direction keys of the coherent order (the leading
+// bits of 30-bit Hilbert keys: coarser cells), and of the chord key, which
+// only has to rank the rays into a few chord groups (one sort pass). Keys
+// of 24 and 18 bits were measured: the sort saves a pass per key, the trace
+// kernel loses about as much to coarser coherence.
+constexpr int kOrderKeyBits = VRT_ORDER_KEY_BITS;
+constexpr int kChordKeyBits = VRT_CHORD_KEY_BITS;
+static_assert(kOrderKeyBits % 3 == 0 && kOrderKeyBits <= 30 && kChordKeyBits <= 16, "key widths");
+
 __global__ void k_ray_keys(const double *__restrict__ origins, const double *__restrict__ dirs, int64_t N,
                            OrderBox B, uint32_t *__restrict__ okey, uint32_t *__restrict__ dkey,
                            uint32_t *__restrict__ lkey, int32_t *__restrict__ idx)
@@ -335,9 +350,9 @@ __global__ void k_ray_keys(const double *__restrict__ origins, const double *__r
         else if (ka < 0.0) L = fmin(L, (B.lo[a] - r) / ka);
     }
     const double frac = (L > 0.0 && L < 1e300) ? fmin(L / B.diag, 1.0) : 0.0;   // NaN origins give 0
-    okey[i] = hilbert_key(qo[0], qo[1], qo[2]);
-    dkey[i] = hilbert_key(qd[0], qd[1], qd[2]);
-    lkey[i] = (uint32_t)((1.0 - frac) * 65535.0 + 0.5);
+    okey[i] = hilbert_key(qo[0], qo[1], qo[2]) >> (30 - kOrderKeyBits);
+    dkey[i] = hilbert_key(qd[0], qd[1], qd[2]) >> (30 - kOrderKeyBits);
+    lkey[i] = (uint32_t)((1.0 - frac) * (double)((1 << kChordKeyBits) - 1) + 0.5);
     idx[i] = (int32_t)i;
 }
 
@@ -666,18 +681,18 @@ extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, c
     const bool chords = N >= kChordBinsMinRays;
     vor_status rc = VOR_OK;
     if (chords) {   // chord bins: rank by chord, longest first
-        rc = vrt_radix_sort_pairs(lkey, order, ktmp, vtmp, N, 16, hist, hl, st);
+        rc = vrt_radix_sort_pairs(lkey, order, ktmp, vtmp, N, kChordKeyBits, hist, hl, st);
         if (rc != VOR_OK) return rc;
         hipLaunchKernelGGL(k_rank_bins, dim3(nb), dim3(T), 0, st, order, N, kChordBins, bins);
         hipLaunchKernelGGL(k_iota, dim3(nb), dim3(T), 0, st, order, N);
     }
     // by direction, then stably by origin: rays from one place in similar directions end up together
-    rc = vrt_radix_sort_pairs(dkey, order, ktmp, vtmp, N, 30, hist, hl, st);
+    rc = vrt_radix_sort_pairs(dkey, order, ktmp, vtmp, N, kOrderKeyBits, hist, hl, st);
     if (rc != VOR_OK) return rc;
     // the origin keys must follow the same permutation before the second sort
     rc = vrt_gather_u32(okey, order, N, ktmp, st);
     if (rc != VOR_OK) return rc;
-    rc = vrt_radix_sort_pairs(ktmp, order, okey, vtmp, N, 30, hist, hl, st);
+    rc = vrt_radix_sort_pairs(ktmp, order, okey, vtmp, N, kOrderKeyBits, hist, hl, st);
     if (rc != VOR_OK) return rc;
     // then stably by (part of the order, chord bin)
     static_assert(kParts * kChordBins <= 256, "one 8-bit pass sorts by part and bin");

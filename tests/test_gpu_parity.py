@@ -770,7 +770,7 @@ def test_build_errors(vrt):
     assert e.value.code == vrt.VOR_EINVAL
 
 
-@pytest.mark.parametrize("n", [0, 1, 2047, 2048, 2049, 1_000_003])
+@pytest.mark.parametrize("n", [0, 1, 1023, 1024, 2047, 2048, 2049, 65535, 65536, 65537, 1_000_003])
 def test_exclusive_scan(vrt, n):
     import torch
     rng = np.random.default_rng(n)
