@@ -386,7 +386,7 @@ __device__ __forceinline__ void plane_bound32q(float nx, float ny, float nz, con
     const float wx = fmaf(0.5f, nx, -Q.qx), wy = fmaf(0.5f, ny, -Q.qy), wz = fmaf(0.5f, nz, -Q.qz);
     const float num = fmaf(nx, wx, fmaf(ny, wy, nz * wz));
     const float n1 = fabsf(nx) + fabsf(ny) + fabsf(nz);
-    const float d4 = fmaf(32.0f * 5.9604645e-8f, n1, 3.5f);   // 4 (8u |n|_1 + 0.87), floored well above 0
+    const float d4 = fmaf(32.0f * 5.9604645e-8f, n1, 3.5f);   // 4 (8u |n|_1 + 0.875)
     pos = den > d4;
     maybe = den > -d4;
     const float rc = __builtin_amdgcn_rcpf(den);
