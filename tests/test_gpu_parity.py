@@ -906,3 +906,25 @@ def test_exact_paths_from_one_traversal(vrt, mode):
     ref = oracle.trace(w.sites, w.box, w.density, w.origins[:300], w.dirs[:300], cap=1024)
     st = compare(gpu_paths(b), ref, TOL[mode])
     assert st["clean"] > 0.9 * 300 and st["max_len_diff"] <= TOL[mode]
+
+
+def test_gather_paths_without_spill(vrt):
+    """vor_gather_paths on windows that hold every path (no spill arrays):
+    the rows equal the exact layout's."""
+    import torch
+    w = W.uniform_cube(M=2000, N=5000, seed=84)
+    grid = vrt.build_grid(w.sites, w.box)
+    ex = vrt.trace(grid, w.origins, w.dirs, w.density, mode="mixed", segments="exact_two_pass")
+    stride = int(ex["n_seg"].max().item())
+    o = torch.as_tensor(w.origins, device="cuda")
+    d = torch.as_tensor(w.dirs, device="cuda")
+    rho = torch.as_tensor(w.density, device="cuda")
+    b = vrt.TraceBuffers(w.N, seg_stride=stride)
+    vrt.trace_into(grid, o, d, rho, b, mode="mixed")
+    off = vrt.exclusive_scan(b.n_seg)
+    total = int(off[-1].item())
+    cell = torch.empty(total, dtype=torch.int32, device="cuda")
+    length = torch.empty(total, dtype=torch.float64, device="cuda")
+    vrt.gather_paths(b, off, cell, length)
+    torch.cuda.synchronize()
+    assert torch.equal(off, ex["ray_off"]) and torch.equal(cell, ex["seg_cell"]) and torch.equal(length, ex["seg_len"])
