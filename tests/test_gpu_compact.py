@@ -246,3 +246,19 @@ def test_server_over_a_compact_grid(vrt):
             srv.release(rid)
     finally:
         srv.close()
+
+
+def test_tiny_grids_with_compact_records(vrt):
+    """One, two and three sites (cells with no or few neighbours) on compact
+    records: mixed mode equals FP64 and the oracle."""
+    rng = np.random.default_rng(31)
+    box = np.array([-1.0, -1, -1, 1, 1, 1])
+    for sites in (np.array([[0.1, 0.2, 0.3]]), np.array([[-0.5, 0, 0], [0.5, 0, 0]]),
+                  rng.uniform(-1, 1, (3, 3))):
+        o = rng.uniform(-1, 1, (500, 3))
+        d = rng.normal(size=(500, 3))
+        dens = rng.uniform(0.5, 2.0, len(sites))
+        a, _ = _fp64_vs_compact(vrt, sites, box, o, d, dens)
+        ref = oracle.trace(sites, box, dens, o, d, cap=16)
+        st = compare(gpu_paths(a), ref, 1e-12)
+        assert st["max_len_diff"] == 0.0
