@@ -368,7 +368,9 @@ vor_status vor_trace_noalloc(const vor_grid *grid, const double *origins, const 
  * each part grouped by the length of their chord (the distance to the wall
  * they head for, Eq. 5 on every axis; 8 groups ranked over the batch), the
  * longest first, keeping that order within a group (batches of fewer than
- * 2^17 rays keep the first order alone). Pass it as
+ * 2^17 rays keep the first order alone; batches of fewer than 2^14 rays keep
+ * their own order, the identity, as sorting them costs more than it saves).
+ * Pass it as
  * vor_trace_out.ray_order; results do not depend on the order, only the
  * speed does.
  *   origins, dirs  device, N x 3.   order  device, N int32 (a permutation).

@@ -638,6 +638,12 @@ extern "C" vor_status vor_trace_noalloc(const vor_grid *G, const double *origins
 // ones, which shortens the drain where only a few lanes of a wave still
 // work; the parts keep their spatial coherence.
 constexpr int kChordBins = 8;
+#ifndef VRT_ORDER_MIN_RAYS
+#define VRT_ORDER_MIN_RAYS (1 << 14)
+#endif
+// Below this many rays a batch keeps its own order: the sort's launches
+// would cost more than coherence can save in so short a trace.
+constexpr int64_t kOrderMinRays = VRT_ORDER_MIN_RAYS;
 // Below this many rays a launch is too short for a drain to matter (and is
 // launch-bound): the order is the coherent one alone.
 constexpr int64_t kChordBinsMinRays = 1 << 17;
@@ -677,6 +683,10 @@ extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, c
     B.diag = sqrt(d2);
     const int T = 256;
     const unsigned nb = (unsigned)((N + T - 1) / T);
+    if (N < kOrderMinRays) {
+        hipLaunchKernelGGL(k_iota, dim3(nb), dim3(T), 0, st, order, N);
+        return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
+    }
     hipLaunchKernelGGL(k_ray_keys, dim3(nb), dim3(T), 0, st, origins, dirs, N, B, okey, dkey, lkey, order);
     const bool chords = N >= kChordBinsMinRays;
     vor_status rc = VOR_OK;

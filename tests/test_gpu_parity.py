@@ -157,6 +157,28 @@ def test_ray_order_is_a_permutation_and_changes_nothing(vrt):
         assert np.array_equal(ca, cb) and np.array_equal(la, lb)
 
 
+@pytest.mark.parametrize("n", [16383, 16384])
+def test_ray_order_at_the_small_batch_threshold(vrt, n):
+    """Below 2^14 rays the order is the identity; from there on it is the
+    coherent sort. Either way a permutation that changes no result."""
+    import torch
+    w = W.exp_disc(M=20_000, N=n, seed=22)
+    grid = vrt.build_grid(w.sites, w.box)
+    o = torch.as_tensor(w.origins, device="cuda")
+    d = torch.as_tensor(w.dirs, device="cuda")
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(int(vrt.load().vor_order_workspace_bytes(n)), dtype=torch.uint8, device="cuda")
+    vrt.order_rays(grid, o, d, order, ws)
+    ordr = order.cpu().numpy()
+    assert np.array_equal(np.sort(ordr), np.arange(n))
+    assert np.array_equal(ordr, np.arange(n)) == (n < 1 << 14)
+    kw = dict(mode="mixed", segments="exact", persistent=True)
+    a = vrt.trace(grid, o, d, w.density, **kw)
+    b = vrt.trace(grid, o, d, w.density, ordered=True, **kw)
+    for k in ("tau", "n_seg", "status", "ray_off", "seg_cell", "seg_len"):
+        assert torch.equal(a[k], b[k]), k
+
+
 @pytest.mark.parametrize("persistent", [False, True])
 def test_start_cell_pass_changes_nothing(vrt, cube, persistent):
     """Start cells located at each ray's start and in a pass of their own
