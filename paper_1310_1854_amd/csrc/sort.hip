@@ -5,9 +5,10 @@
 // Per pass: a per-tile digit histogram (LDS atomics), an exclusive scan of
 // the digit-major histogram (digit d's slot for tile t lands after every
 // smaller digit and every earlier tile), and a stable scatter in which each
-// 64-lane wave ranks equal digits with eight ballots, the waves of a block
-// combine their per-digit counts through LDS, and the tile is reordered in
-// LDS so that its runs of equal digits are written out contiguously.
+// 64-lane wave ranks equal digits with eight ballots over its own quarter of
+// the tile, the waves then combine their per-digit counts through LDS, and
+// the tile is reordered in LDS so that its runs of equal digits are written
+// out contiguously.
 #include "vrt_internal.h"
 
 namespace {
@@ -32,18 +33,23 @@ __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint32_t *__restr
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter of one tile: the tile's pairs are first put in digit order
-// in LDS (ranked round by round, in index order, as above), then written out
-// in that order, so that the lanes of a wave write runs of equal digits to
-// consecutive addresses instead of one scattered word each.
+// Stable scatter of one tile. Each wave ranks its own quarter of the tile
+// (consecutive indices), 64 keys at a time: eight ballots group the lanes
+// with equal digits, and the wave keeps its running count of each digit in
+// LDS, so the waves need no barrier until their quarters are ranked. Then
+// the per-digit counts of the waves are combined (a digit's keys of wave w
+// follow those of the earlier waves: the order of the indices), the tile is
+// put in digit order in LDS, and written out in that order, so that runs of
+// equal digits leave contiguously.
 __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__restrict__ kin,
                                                             const int32_t *__restrict__ vin, int64_t n, int shift,
                                                             const int32_t *__restrict__ off, int64_t ntiles,
                                                             uint32_t *__restrict__ kout, int32_t *__restrict__ vout)
 {
-    __shared__ int32_t run[256];        // next local slot of each digit
-    __shared__ int32_t loc[256];        // where each digit's run starts in the tile
-    __shared__ int32_t wcnt[kWaves][256];
+    constexpr int kQuarter = kTile / kWaves;        // keys a wave ranks
+    constexpr int kWaveRounds = kQuarter / 64;
+    __shared__ int32_t wcnt[kWaves][256];           // each wave's running count of each digit, then its offset
+    __shared__ int32_t loc[256];                    // where each digit's run starts in the tile
     __shared__ uint32_t skey[kTile];
     __shared__ int32_t sval[kTile];
     const int tid = threadIdx.x;
@@ -52,21 +58,47 @@ __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__re
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
+    int32_t *mine = wcnt[wave];
+    for (int d = lane; d < 256; d += 64) mine[d] = 0;
+    __builtin_amdgcn_wave_barrier();
 
-    // the tile's digit counts and their exclusive scan
-    run[tid] = 0;
-    __syncthreads();
-    for (int r = 0; r < kRounds; ++r) {
-        const int i = r * kThreads + tid;
-        if (i < cnt) atomicAdd(&run[(kin[base + i] >> shift) & 255u], 1);
+    // phase 1: each wave ranks its quarter in index order, with no block barrier
+    uint32_t key[kWaveRounds];
+    int32_t val[kWaveRounds], pos[kWaveRounds];
+#pragma unroll
+    for (int r = 0; r < kWaveRounds; ++r) {
+        const int i = wave * kQuarter + r * 64 + lane;
+        const bool valid = i < cnt;
+        key[r] = valid ? kin[base + i] : 0u;
+        val[r] = valid ? vin[base + i] : 0;
+        const uint32_t d = (key[r] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const int rank = __popcll(peers & lt);
+        pos[r] = valid ? mine[d] + rank : -1;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) mine[d] += __popcll(peers);   // one lane per digit group
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    if (tid < 64) {   // one wave scans the 256 counts, 4 per lane
-        const int c0 = run[4 * lane], c1 = run[4 * lane + 1], c2 = run[4 * lane + 2], c3 = run[4 * lane + 3];
+
+    // phase 2: the tile's digit totals, their exclusive scan, and each wave's offset per digit
+    {
+        int tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += wcnt[w][tid];
+        loc[tid] = tot;
+    }
+    __syncthreads();
+    if (tid < 64) {   // one wave scans the 256 totals, 4 per lane
+        const int c0 = loc[4 * lane], c1 = loc[4 * lane + 1], c2 = loc[4 * lane + 2], c3 = loc[4 * lane + 3];
         int v = c0 + c1 + c2 + c3;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int u = __shfl_up(v, d, 64);
-            if (lane >= d) v += u;
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const int u = __shfl_up(v, dd, 64);
+            if (lane >= dd) v += u;
         }
         const int e = v - (c0 + c1 + c2 + c3);
         loc[4 * lane] = e;
@@ -75,46 +107,35 @@ __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__re
         loc[4 * lane + 3] = e + c0 + c1 + c2;
     }
     __syncthreads();
-    run[tid] = loc[tid];
-
-    // stable ranks into LDS, round by round
-    for (int r = 0; r < kRounds; ++r) {
-        for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        const int i = r * kThreads + tid;
-        const bool valid = i < cnt;
-        const uint32_t key = valid ? kin[base + i] : 0u;
-        const int32_t val = valid ? vin[base + i] : 0;
-        const uint32_t d = (key >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
+    {
+        int run = loc[tid];
+        for (int w = 0; w < kWaves; ++w) {
+            const int c = wcnt[w][tid];
+            wcnt[w][tid] = run;
+            run += c;
         }
-        const int rank = __popcll(peers & lt);
-        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int pos = run[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            skey[pos] = key;
-            sval[pos] = val;
-        }
-        __syncthreads();
-        int add = 0;
-        for (int w = 0; w < kWaves; ++w) add += wcnt[w][tid];
-        run[tid] += add;
-        __syncthreads();
     }
+    __syncthreads();
 
-    // out in digit order: slot j of digit d goes after the digit's earlier tiles
+    // phase 3: the tile in digit order in LDS
+#pragma unroll
+    for (int r = 0; r < kWaveRounds; ++r) {
+        if (pos[r] >= 0) {
+            const uint32_t d = (key[r] >> shift) & 255u;
+            const int p = mine[d] + pos[r];
+            skey[p] = key[r];
+            sval[p] = val[r];
+        }
+    }
+    __syncthreads();
+
+    // phase 4: out in digit order: slot j of digit d goes after the digit's earlier tiles
     for (int j = tid; j < cnt; j += kThreads) {
-        const uint32_t key = skey[j];
-        const uint32_t d = (key >> shift) & 255u;
-        const int64_t pos = (int64_t)off[(int64_t)d * ntiles + blockIdx.x] + (j - loc[d]);
-        kout[pos] = key;
-        vout[pos] = sval[j];
+        const uint32_t k = skey[j];
+        const uint32_t d = (k >> shift) & 255u;
+        const int64_t q = (int64_t)off[(int64_t)d * ntiles + blockIdx.x] + (j - loc[d]);
+        kout[q] = k;
+        vout[q] = sval[j];
     }
 }
 
