@@ -37,6 +37,7 @@ inline LocView loc_view(const Grid &g)
     return L;
 }
 
+template <bool STOP_AT_SITE = false>
 __device__ __forceinline__ int32_t nearest_in_blocks(const LocView &L, const double q[3], int32_t *uid)
 {
     int b[3];
@@ -55,6 +56,7 @@ __device__ __forceinline__ int32_t nearest_in_blocks(const LocView &L, const dou
             best_u = u;
             best_m = m;
         }
+        if (STOP_AT_SITE && dx == 0.0 && dy == 0.0 && dz == 0.0) break;   // the point is this site: no other is as near
     }
     *uid = best_u;
     return best_m;
@@ -147,7 +149,9 @@ __device__ inline int32_t nearest_site_wave(const BucketGridView &g, const doubl
 // (a point they cannot place falls back to the ring search), else the ring
 // search; one cooperative search when all 64 lanes of the wave share the
 // point (a point source), else one per lane. Every lane of the wave must
-// call it.
+// call it. STOP_AT_SITE: a search ends at a site the point coincides with
+// (rays that start at sites), which costs the calling kernel registers.
+template <bool STOP_AT_SITE = true>
 __device__ __forceinline__ int32_t start_cell(const BucketGridView &grid, const LocView &L, const double q[3], bool ok)
 {
     const double q0 = __shfl(q[0], 0, 64), q1 = __shfl(q[1], 0, 64), q2 = __shfl(q[2], 0, 64);
@@ -156,12 +160,12 @@ __device__ __forceinline__ int32_t start_cell(const BucketGridView &grid, const 
     int32_t m = -1, uid;
     if (L.start) {
         if (shared) m = nearest_in_blocks_wave(L, q);
-        else if (ok) m = nearest_in_blocks(L, q, &uid);
-        if (ok && m < 0) m = nearest_site(grid, q, nullptr);   // empty list: not in the box
+        else if (ok) m = nearest_in_blocks<STOP_AT_SITE>(L, q, &uid);
+        if (ok && m < 0) m = nearest_site<STOP_AT_SITE>(grid, q, nullptr);   // empty list: not in the box
     } else if (shared) {
         m = nearest_site_wave(grid, q, nullptr);
     } else if (ok) {
-        m = nearest_site(grid, q, nullptr);
+        m = nearest_site<STOP_AT_SITE>(grid, q, nullptr);
     }
     return ok ? m : -1;
 }

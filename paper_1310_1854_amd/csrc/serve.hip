@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(256) k_serve(const GridRef *__restrict__ grids
                     double qp[3] = {0.0, 0.0, 0.0};
                     if (mine) start_point(R.r0, R.k, s0, qp);
                     const bool ok = mine && R.st == RAY_OK;
-                    const int32_t m0 = start_cell(G.grid, locs[ctx >> 2], qp, ok);
+                    const int32_t m0 = start_cell<false>(G.grid, locs[ctx >> 2], qp, ok);   // (registers: no early stop)
                     if (mine) {
                         if (ok) {
                             ray_begin_at<MODE>(G, R, m0, s0);

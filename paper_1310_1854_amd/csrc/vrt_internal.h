@@ -205,6 +205,9 @@ VRT_HD inline void for_shell(const BucketGridView &g, const int b[3], int r, F &
 // Exact nearest site (internal index) by ring search; squared distances in
 // the same operation order as a plain (x-p)^2 sum; equal distances go to
 // the lower user index. q must be inside the box.
+// STOP_AT_SITE: end the search when the point is a site (no other is as
+// near: the sites are distinct), as rays that start at sites do.
+template <bool STOP_AT_SITE = false>
 VRT_HD inline int32_t nearest_site(const BucketGridView &g, const double q[3], int32_t *uid_out)
 {
     int b[3];
@@ -212,10 +215,11 @@ VRT_HD inline int32_t nearest_site(const BucketGridView &g, const double q[3], i
     double best = 1e308 * 10.0;  // +inf
     int32_t best_i = -1;
     int32_t best_u = 0x7fffffff;
+    bool at_site = false;
     for (int r = 0;; ++r) {
         for_shell(g, b, r, [&](int bk) {
             int s0 = g.start[bk], s1 = g.start[bk + 1];
-            for (int s = s0; s < s1; ++s) {
+            for (int s = s0; s < s1 && !(STOP_AT_SITE && at_site); ++s) {
                 Site p = g.items[s];
                 double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
                 double d = dx * dx + dy * dy + dz * dz;
@@ -226,8 +230,10 @@ VRT_HD inline int32_t nearest_site(const BucketGridView &g, const double q[3], i
                     best_i = idx;
                     best_u = uid;
                 }
+                if (STOP_AT_SITE) at_site = dx == 0.0 && dy == 0.0 && dz == 0.0;
             }
         });
+        if (STOP_AT_SITE && at_site) break;
         double lb = shell_bound(g, q, b, r);
         if (lb < 0.0) break;
         // sites outside the block are at least lb away; the slack keeps a
