@@ -2,13 +2,15 @@
 // bits per pass. Used by the grid build (sites in Hilbert order) and by the
 // coherent ray order.
 //
-// Per pass: a per-tile digit histogram (LDS atomics), an exclusive scan of
-// the digit-major histogram (digit d's slot for tile t lands after every
-// smaller digit and every earlier tile), and a stable scatter in which each
-// 64-lane wave ranks equal digits with eight ballots over its own quarter of
-// the tile, the waves then combine their per-digit counts through LDS, and
-// the tile is reordered in LDS so that its runs of equal digits are written
-// out contiguously.
+// Per pass, three launches: a per-tile digit histogram (LDS atomics) laid
+// out digit-major; one block per digit that scans its row along the tiles in
+// place and leaves the digit's total; and a stable scatter. The scatter
+// scans the 256 totals itself, so digit d of tile t starts at (keys of every
+// smaller digit) + (keys of digit d in earlier tiles). In it each 64-lane
+// wave ranks equal digits with eight ballots over its own quarter of the
+// tile, the waves then combine their per-digit counts through LDS, and the
+// tile is reordered in LDS so that its runs of equal digits are written out
+// contiguously.
 #include "vrt_internal.h"
 
 namespace {
@@ -33,6 +35,52 @@ __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint32_t *__restr
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Exclusive scan of row d = blockIdx.x of the digit-major histogram, in
+// place (the count of digit d in the tiles before each tile), and the row's
+// total in tot[d]. Each thread takes 8 consecutive tiles per round.
+__global__ void __launch_bounds__(kThreads) k_digit_rows(int32_t *__restrict__ hist, int64_t ntiles,
+                                                         int32_t *__restrict__ tot)
+{
+    constexpr int kItems = 8;
+    __shared__ int32_t wsum[kWaves];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int32_t *row = hist + (int64_t)blockIdx.x * ntiles;
+    int32_t carry = 0;
+    for (int64_t c = 0; c < ntiles; c += (int64_t)kThreads * kItems) {
+        const int64_t first = c + (int64_t)tid * kItems;
+        int32_t v[kItems];
+        int32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            v[i] = (first + i < ntiles) ? row[first + i] : 0;
+            sum += v[i];
+        }
+        int32_t incl = sum;   // inclusive scan over the wave
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const int32_t u = __shfl_up(incl, dd, 64);
+            if (lane >= dd) incl += u;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int32_t before = 0, round = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            before += (w < wave) ? wsum[w] : 0;
+            round += wsum[w];
+        }
+        __syncthreads();   // wsum is rewritten in the next round
+        int32_t run = carry + before + incl - sum;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            if (first + i < ntiles) row[first + i] = run;
+            run += v[i];
+        }
+        carry += round;
+    }
+    if (tid == 0) tot[blockIdx.x] = carry;
+}
+
 // Stable scatter of one tile. Each wave ranks its own quarter of the tile
 // (consecutive indices), 64 keys at a time: eight ballots group the lanes
 // with equal digits, and the wave keeps its running count of each digit in
@@ -43,13 +91,15 @@ __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint32_t *__restr
 // equal digits leave contiguously.
 __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__restrict__ kin,
                                                             const int32_t *__restrict__ vin, int64_t n, int shift,
-                                                            const int32_t *__restrict__ off, int64_t ntiles,
+                                                            const int32_t *__restrict__ rows,
+                                                            const int32_t *__restrict__ tot, int64_t ntiles,
                                                             uint32_t *__restrict__ kout, int32_t *__restrict__ vout)
 {
     constexpr int kQuarter = kTile / kWaves;        // keys a wave ranks
     constexpr int kWaveRounds = kQuarter / 64;
     __shared__ int32_t wcnt[kWaves][256];           // each wave's running count of each digit, then its offset
     __shared__ int32_t loc[256];                    // where each digit's run starts in the tile
+    __shared__ int32_t dst[256];                    // where it starts in the output
     __shared__ uint32_t skey[kTile];
     __shared__ int32_t sval[kTile];
     const int tid = threadIdx.x;
@@ -86,27 +136,31 @@ __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__re
     }
     __syncthreads();
 
-    // phase 2: the tile's digit totals, their exclusive scan, and each wave's offset per digit
+    // phase 2: the tile's digit totals and the batch's, their exclusive scans (wave 0
+    // the tile's, wave 1 the batch's: 4 digits per lane), and each wave's offset per digit
     {
-        int tot = 0;
-        for (int w = 0; w < kWaves; ++w) tot += wcnt[w][tid];
-        loc[tid] = tot;
+        int t = 0;
+        for (int w = 0; w < kWaves; ++w) t += wcnt[w][tid];
+        loc[tid] = t;
+        dst[tid] = tot[tid];
     }
     __syncthreads();
-    if (tid < 64) {   // one wave scans the 256 totals, 4 per lane
-        const int c0 = loc[4 * lane], c1 = loc[4 * lane + 1], c2 = loc[4 * lane + 2], c3 = loc[4 * lane + 3];
+    if (tid < 128) {
+        int32_t *a = (tid < 64) ? loc : dst;
+        const int c0 = a[4 * lane], c1 = a[4 * lane + 1], c2 = a[4 * lane + 2], c3 = a[4 * lane + 3];
         int v = c0 + c1 + c2 + c3;
         for (int dd = 1; dd < 64; dd <<= 1) {
             const int u = __shfl_up(v, dd, 64);
             if (lane >= dd) v += u;
         }
         const int e = v - (c0 + c1 + c2 + c3);
-        loc[4 * lane] = e;
-        loc[4 * lane + 1] = e + c0;
-        loc[4 * lane + 2] = e + c0 + c1;
-        loc[4 * lane + 3] = e + c0 + c1 + c2;
+        a[4 * lane] = e;
+        a[4 * lane + 1] = e + c0;
+        a[4 * lane + 2] = e + c0 + c1;
+        a[4 * lane + 3] = e + c0 + c1 + c2;
     }
     __syncthreads();
+    dst[tid] += rows[(int64_t)tid * ntiles + blockIdx.x];
     {
         int run = loc[tid];
         for (int w = 0; w < kWaves; ++w) {
@@ -129,11 +183,11 @@ __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__re
     }
     __syncthreads();
 
-    // phase 4: out in digit order: slot j of digit d goes after the digit's earlier tiles
+    // phase 4: out in digit order: slot j of digit d goes after the smaller digits and the digit's earlier tiles
     for (int j = tid; j < cnt; j += kThreads) {
         const uint32_t k = skey[j];
         const uint32_t d = (k >> shift) & 255u;
-        const int64_t q = (int64_t)off[(int64_t)d * ntiles + blockIdx.x] + (j - loc[d]);
+        const int64_t q = (int64_t)dst[d] + (j - loc[d]);
         kout[q] = k;
         vout[q] = sval[j];
     }
@@ -162,7 +216,7 @@ int64_t vrt_radix_hist_len(int64_t n)
     return 256 * ntiles;
 }
 
-// hist_scratch must hold 2 * hist_len + 1 int32. The sorted pairs end in
+// hist_scratch must hold hist_len + 256 int32. The sorted pairs end in
 // (keys, vals); keys_tmp / vals_tmp are ping-pong buffers of n entries.
 vor_status vrt_radix_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tmp, int32_t *vals_tmp, int64_t n,
                                 int bits, int32_t *hist_scratch, int64_t hist_len, hipStream_t st)
@@ -172,17 +226,16 @@ vor_status vrt_radix_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tm
     int64_t ntiles = (n + kTile - 1) / kTile;
     if (hist_len < 256 * ntiles) return VOR_EINVAL;
     int32_t *hist = hist_scratch;
-    int32_t *off = hist_scratch + hist_len;
+    int32_t *tot = hist_scratch + hist_len;
     uint32_t *ka = keys, *kb = keys_tmp;
     int32_t *va = vals, *vb = vals_tmp;
     int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
         hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, n, shift, hist, ntiles);
-        vor_status s = vrt_scan_i32_to_i32(hist, 256 * ntiles, off, st);
-        if (s != VOR_OK) return s;
-        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, va, n, shift, off,
-                           ntiles, kb, vb);
+        hipLaunchKernelGGL(k_digit_rows, dim3(256), dim3(kThreads), 0, st, hist, ntiles, tot);
+        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, va, n, shift, hist,
+                           tot, ntiles, kb, vb);
         uint32_t *tk = ka; ka = kb; kb = tk;
         int32_t *tv = va; va = vb; vb = tv;
     }

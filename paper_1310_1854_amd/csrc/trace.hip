@@ -307,8 +307,8 @@ __global__ void __launch_bounds__(256) VRT_OCC k_trace_persistent(TraceArgs A)
 // Sort keys of a ray: Hilbert index of its origin (10 bits per axis over the
 // box) and of its direction ((k/|k| + 1)/2 over the unit cube), and its
 // chord -- the distance to the wall it heads for (Eq. 5 on every axis) --
-// as a 16-bit key that is smallest for the longest chords (0 for rays
-// without one).
+// as a key of up to 8 bits that is smallest for the longest chords (0 for
+// rays without one).
 struct OrderBox {
     double lo[3], hi[3], scale[3], diag;
 };
@@ -321,18 +321,21 @@ struct OrderBox {
 #endif
 // Bits of the origin and direction keys of the coherent order (the leading
 // bits of 30-bit Hilbert keys: coarser cells), and of the chord key, which
-// only has to rank the rays into a few chord groups (one sort pass). Keys
+// only has to rank the rays into a few chord groups (by its histogram). Keys
 // of 24 and 18 bits were measured: the sort saves a pass per key, the trace
 // kernel loses about as much to coarser coherence.
 constexpr int kOrderKeyBits = VRT_ORDER_KEY_BITS;
 constexpr int kChordKeyBits = VRT_CHORD_KEY_BITS;
-static_assert(kOrderKeyBits % 3 == 0 && kOrderKeyBits <= 30 && kChordKeyBits <= 16, "key widths");
+static_assert(kOrderKeyBits % 3 == 0 && kOrderKeyBits <= 30 && kChordKeyBits <= 8, "key widths");
 
+// Block 0 also clears the chord-key counts (ccount, 256 entries) that
+// k_chord_counts fills after it.
 __global__ void k_ray_keys(const double *__restrict__ origins, const double *__restrict__ dirs, int64_t N,
                            OrderBox B, uint32_t *__restrict__ okey, uint32_t *__restrict__ dkey,
-                           uint32_t *__restrict__ lkey, int32_t *__restrict__ idx)
+                           uint32_t *__restrict__ lkey, int32_t *__restrict__ idx, int32_t *__restrict__ ccount)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ccount && blockIdx.x == 0 && threadIdx.x < 256) ccount[threadIdx.x] = 0;
     if (i >= N) return;
     uint32_t qo[3], qd[3];
     double k[3] = {dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
@@ -356,22 +359,53 @@ __global__ void k_ray_keys(const double *__restrict__ origins, const double *__r
     idx[i] = (int32_t)i;
 }
 
-// The chord bin of every ray from its rank in chord order (order = the rays
-// sorted longest chord first): bin = rank * bins / N.
-__global__ void k_rank_bins(const int32_t *__restrict__ order, int64_t N, int bins, uint32_t *__restrict__ bin)
+// How many rays have each chord key (an LDS histogram per block, then one
+// atomic per block and key).
+__global__ void __launch_bounds__(256) k_chord_counts(const uint32_t *__restrict__ ckey, int64_t N,
+                                                      int32_t *__restrict__ ccount)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < N) bin[order[r]] = (uint32_t)((r * bins) / N);
+    __shared__ int32_t c[256];
+    c[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&c[ckey[i] & 255u], 1);
+    __syncthreads();
+    if (c[threadIdx.x]) atomicAdd(&ccount[threadIdx.x], c[threadIdx.x]);
 }
 
 // The final sort key of the ray at rank r of the coherent order: its part
 // of the order (the contiguous part a persistent launch gives one XCD),
-// then its chord bin.
-__global__ void k_part_bin_key(const int32_t *__restrict__ order, const uint32_t *__restrict__ bin, int64_t N,
-                               int parts, int bins, uint32_t *__restrict__ key)
+// then its chord bin. The bin is the ray's rank in chord order (longest
+// first) scaled to `bins`, every ray of one chord key taking the rank at the
+// middle of its key's run: ((rays of smaller keys) + (rays of its key) / 2)
+// * bins / N. Each block derives the 256 bins from the key counts.
+__global__ void __launch_bounds__(256) k_part_bin_key(const int32_t *__restrict__ order,
+                                                      const uint32_t *__restrict__ ckey,
+                                                      const int32_t *__restrict__ ccount, int64_t N, int parts,
+                                                      int bins, uint32_t *__restrict__ key)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < N) key[r] = (uint32_t)((r * parts) / N) * (uint32_t)bins + bin[order[r]];
+    __shared__ uint32_t bin_of[256];
+    const int t = threadIdx.x, lane = t & 63;
+    if (t < 64) {   // one wave scans the 256 counts, 4 per lane
+        int64_t c[4], v = 0;
+        for (int j = 0; j < 4; ++j) {
+            c[j] = ccount[4 * lane + j];
+            v += c[j];
+        }
+        int64_t incl = v;
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const int64_t u = __shfl_up(incl, dd, 64);
+            if (lane >= dd) incl += u;
+        }
+        int64_t before = incl - v;
+        for (int j = 0; j < 4; ++j) {
+            bin_of[4 * lane + j] = (uint32_t)(((before + c[j] / 2) * bins) / N);
+            before += c[j];
+        }
+    }
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + t;
+    if (r < N) key[r] = (uint32_t)((r * parts) / N) * (uint32_t)bins + bin_of[ckey[order[r]] & 255u];
 }
 
 __global__ void k_iota(int32_t *__restrict__ idx, int64_t N)
@@ -652,7 +686,7 @@ extern "C" int64_t vor_order_workspace_bytes(int64_t N)
 {
     if (N < 0) return -1;
     int64_t hl = vrt_radix_hist_len(N);
-    return 6 * N * (int64_t)sizeof(uint32_t) + (2 * hl + 1) * (int64_t)sizeof(int32_t) + 1024;
+    return 6 * N * (int64_t)sizeof(uint32_t) + (hl + 512) * (int64_t)sizeof(int32_t) + 1024;
 }
 
 extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, const double *dirs, int64_t N,
@@ -687,15 +721,13 @@ extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, c
         hipLaunchKernelGGL(k_iota, dim3(nb), dim3(T), 0, st, order, N);
         return hipGetLastError() == hipSuccess ? VOR_OK : VOR_EDEVICE;
     }
-    hipLaunchKernelGGL(k_ray_keys, dim3(nb), dim3(T), 0, st, origins, dirs, N, B, okey, dkey, lkey, order);
     const bool chords = N >= kChordBinsMinRays;
+    int32_t *ccount = chords ? hist + hl + 256 : nullptr;   // past the sort's histogram and digit totals
+    // chord keys go to `bins` (the final keys are written to lkey while they are read)
+    hipLaunchKernelGGL(k_ray_keys, dim3(nb), dim3(T), 0, st, origins, dirs, N, B, okey, dkey, bins, order, ccount);
     vor_status rc = VOR_OK;
-    if (chords) {   // chord bins: rank by chord, longest first
-        rc = vrt_radix_sort_pairs(lkey, order, ktmp, vtmp, N, kChordKeyBits, hist, hl, st);
-        if (rc != VOR_OK) return rc;
-        hipLaunchKernelGGL(k_rank_bins, dim3(nb), dim3(T), 0, st, order, N, kChordBins, bins);
-        hipLaunchKernelGGL(k_iota, dim3(nb), dim3(T), 0, st, order, N);
-    }
+    if (chords)   // chord bins: how many rays have each chord key
+        hipLaunchKernelGGL(k_chord_counts, dim3(256), dim3(T), 0, st, bins, N, ccount);
     // by direction, then stably by origin: rays from one place in similar directions end up together
     rc = vrt_radix_sort_pairs(dkey, order, ktmp, vtmp, N, kOrderKeyBits, hist, hl, st);
     if (rc != VOR_OK) return rc;
@@ -707,7 +739,8 @@ extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, c
     // then stably by (part of the order, chord bin)
     static_assert(kParts * kChordBins <= 256, "one 8-bit pass sorts by part and bin");
     if (chords) {
-        hipLaunchKernelGGL(k_part_bin_key, dim3(nb), dim3(T), 0, st, order, bins, N, kParts, kChordBins, lkey);
+        hipLaunchKernelGGL(k_part_bin_key, dim3(nb), dim3(T), 0, st, order, bins, ccount, N, kParts, kChordBins,
+                           lkey);
         rc = vrt_radix_sort_pairs(lkey, order, ktmp, vtmp, N, 8, hist, hl, st);
         if (rc != VOR_OK) return rc;
     }
