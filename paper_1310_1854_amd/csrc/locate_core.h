@@ -37,6 +37,11 @@ inline LocView loc_view(const Grid &g)
     return L;
 }
 
+// STOP_AT_SITE: the search ends at a site the point coincides with (no
+// other is as near), and takes the list four entries per round, their
+// indices and sites loaded together (the minimum does not depend on the
+// order the entries are seen in); the one-at-a-time loop of the other
+// instance holds fewer registers in the kernels that inline it.
 template <bool STOP_AT_SITE = false>
 __device__ __forceinline__ int32_t nearest_in_blocks(const LocView &L, const double q[3], int32_t *uid)
 {
@@ -45,9 +50,7 @@ __device__ __forceinline__ int32_t nearest_in_blocks(const LocView &L, const dou
     const int64_t k = ((int64_t)b[0] * L.dims[1] + b[1]) * L.dims[2] + b[2];
     double best = __builtin_huge_val();
     int32_t best_u = -1, best_m = -1;
-    for (int s = L.start[k]; s < L.start[k + 1]; ++s) {
-        const int32_t m = L.cells[s];
-        const Site p = L.sites[m];
+    auto visit = [&](int32_t m, const Site &p) {
         const double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
         const double d2 = dx * dx + dy * dy + dz * dz;
         const int32_t u = (int32_t)p.uid;
@@ -56,7 +59,33 @@ __device__ __forceinline__ int32_t nearest_in_blocks(const LocView &L, const dou
             best_u = u;
             best_m = m;
         }
-        if (STOP_AT_SITE && dx == 0.0 && dy == 0.0 && dz == 0.0) break;   // the point is this site: no other is as near
+        return dx == 0.0 && dy == 0.0 && dz == 0.0;
+    };
+    const int s0 = L.start[k], s1 = L.start[k + 1];
+    if constexpr (STOP_AT_SITE) {
+#ifndef VRT_LOC_BATCH
+#define VRT_LOC_BATCH 4
+#endif
+        constexpr int kBatch = VRT_LOC_BATCH;
+        for (int s = s0; s < s1; s += kBatch) {
+            int32_t m[kBatch];
+            Site p[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) m[j] = (s + j < s1) ? L.cells[s + j] : -1;
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (m[j] >= 0) p[j] = L.sites[m[j]];
+            bool at_site = false;
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (m[j] >= 0) at_site |= visit(m[j], p[j]);
+            if (at_site) break;
+        }
+    } else {
+        for (int s = s0; s < s1; ++s) {
+            const int32_t m = L.cells[s];
+            visit(m, L.sites[m]);
+        }
     }
     *uid = best_u;
     return best_m;

@@ -216,21 +216,34 @@ VRT_HD inline int32_t nearest_site(const BucketGridView &g, const double q[3], i
     int32_t best_i = -1;
     int32_t best_u = 0x7fffffff;
     bool at_site = false;
+    auto visit = [&](const Site &p) {
+        double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
+        double d = dx * dx + dy * dy + dz * dz;
+        int32_t idx = (int32_t)(p.uid & 0xffffffff);
+        int32_t uid = (int32_t)(p.uid >> 32);
+        if (d < best || (d == best && uid < best_u)) {
+            best = d;
+            best_i = idx;
+            best_u = uid;
+        }
+        return dx == 0.0 && dy == 0.0 && dz == 0.0;
+    };
     for (int r = 0;; ++r) {
         for_shell(g, b, r, [&](int bk) {
             int s0 = g.start[bk], s1 = g.start[bk + 1];
-            for (int s = s0; s < s1 && !(STOP_AT_SITE && at_site); ++s) {
-                Site p = g.items[s];
-                double dx = q[0] - p.x, dy = q[1] - p.y, dz = q[2] - p.z;
-                double d = dx * dx + dy * dy + dz * dz;
-                int32_t idx = (int32_t)(p.uid & 0xffffffff);
-                int32_t uid = (int32_t)(p.uid >> 32);
-                if (d < best || (d == best && uid < best_u)) {
-                    best = d;
-                    best_i = idx;
-                    best_u = uid;
+            if constexpr (STOP_AT_SITE) {   // four sites per round, loaded together
+                for (int s = s0; s < s1 && !at_site; s += 4) {
+                    const int n = (s1 - s < 4) ? s1 - s : 4;
+                    Site p[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (j < n) p[j] = g.items[s + j];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (j < n) at_site |= visit(p[j]);
                 }
-                if (STOP_AT_SITE) at_site = dx == 0.0 && dy == 0.0 && dz == 0.0;
+            } else {
+                for (int s = s0; s < s1; ++s) visit(g.items[s]);
             }
         });
         if (STOP_AT_SITE && at_site) break;
