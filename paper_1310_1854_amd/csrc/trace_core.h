@@ -52,7 +52,10 @@ constexpr int kSpillChunk = VOR_SPILL_CHUNK;
 #define VRT_VEC_STORE 1
 #endif
 #ifndef VRT_NT_STORE
-#define VRT_NT_STORE 1
+#define VRT_NT_STORE 0
+#endif
+#ifndef VRT_NT_STORE_SERVE
+#define VRT_NT_STORE_SERVE 1
 #endif
 
 // A pool of spill chunks read from memory by the lane that takes a chunk: in
@@ -817,19 +820,19 @@ constexpr int lens_per_store()
     return (WIDE && MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
 }
 
-// 16 bytes of segment output: non-temporal (streaming) by default, since the
-// segments are not read again here and the stores should leave the L2 to the
-// records.
+// 16 bytes of segment output. The tracer stores them as ordinary stores:
+// the L2 gathers a lane's 16-byte pieces of one line before writing it back,
+// where non-temporal stores leave as separate partial writes. The serving
+// kernel (LP: its spill chunks come from request pools) stores them
+// non-temporal: its rays come in submission order, and there the records
+// need the L2 more than the output lines do.
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
-template <class V>
+template <bool LP, class V>
 __device__ __forceinline__ void put16(V v, V *p)
 {
-#if VRT_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    if (LP ? VRT_NT_STORE_SERVE : VRT_NT_STORE) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 template <int CG, int LG, bool LP = false>
@@ -910,21 +913,21 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
             if (p >= 0) {
                 v2d *lp = reinterpret_cast<v2d *>(slot_lens<LP>(O, spill) + p);
                 v4i *cp = reinterpret_cast<v4i *>(slot_cells<LP>(O, spill) + p);
-                put16(v2d{R.l0, R.l1}, lp);
-                put16(v2d{R.l2, R.l3}, lp + 1);
-                put16(v2d{R.l4, R.l5}, lp + 2);
-                put16(v2d{R.l6, R.l7}, lp + 3);
+                put16<LP>(v2d{R.l0, R.l1}, lp);
+                put16<LP>(v2d{R.l2, R.l3}, lp + 1);
+                put16<LP>(v2d{R.l4, R.l5}, lp + 2);
+                put16<LP>(v2d{R.l6, R.l7}, lp + 3);
                 if (CG == 8) {
-                    put16(v4i{R.c0, R.c1, R.c2, R.c3}, cp);
-                    put16(v4i{R.c4, R.c5, R.c6, R.c7}, cp + 1);
+                    put16<LP>(v4i{R.c0, R.c1, R.c2, R.c3}, cp);
+                    put16<LP>(v4i{R.c4, R.c5, R.c6, R.c7}, cp + 1);
                 } else if (O.vec < 2) {          // windows on 8-slot boundaries only: the last 8 cells
-                    put16(v4i{R.c8, R.c9, R.c10, R.c11}, cp);
-                    put16(v4i{R.c12, R.c13, R.c14, R.c15}, cp + 1);
+                    put16<LP>(v4i{R.c8, R.c9, R.c10, R.c11}, cp);
+                    put16<LP>(v4i{R.c12, R.c13, R.c14, R.c15}, cp + 1);
                 } else if ((idx & 15) == 15) {   // the group of 16 started 8 slots earlier
-                    put16(v4i{R.c0, R.c1, R.c2, R.c3}, cp - 2);
-                    put16(v4i{R.c4, R.c5, R.c6, R.c7}, cp - 1);
-                    put16(v4i{R.c8, R.c9, R.c10, R.c11}, cp);
-                    put16(v4i{R.c12, R.c13, R.c14, R.c15}, cp + 1);
+                    put16<LP>(v4i{R.c0, R.c1, R.c2, R.c3}, cp - 2);
+                    put16<LP>(v4i{R.c4, R.c5, R.c6, R.c7}, cp - 1);
+                    put16<LP>(v4i{R.c8, R.c9, R.c10, R.c11}, cp);
+                    put16<LP>(v4i{R.c12, R.c13, R.c14, R.c15}, cp + 1);
                 }
             }
         }
@@ -934,13 +937,13 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
             if (p >= 0) {
                 int32_t *cp = slot_cells<LP>(O, spill) + p;
                 v2d *lp = reinterpret_cast<v2d *>(slot_lens<LP>(O, spill) + p);
-                put16(v2d{R.l0, R.l1}, lp);
-                put16(v2d{R.l2, R.l3}, lp + 1);
+                put16<LP>(v2d{R.l0, R.l1}, lp);
+                put16<LP>(v2d{R.l2, R.l3}, lp + 1);
                 if (CG == 4) {
-                    put16(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp));
+                    put16<LP>(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp));
                 } else if ((idx & 7) == 7) {
-                    put16(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp - 4));
-                    put16(v4i{R.c4, R.c5, R.c6, R.c7}, reinterpret_cast<v4i *>(cp));
+                    put16<LP>(v4i{R.c0, R.c1, R.c2, R.c3}, reinterpret_cast<v4i *>(cp - 4));
+                    put16<LP>(v4i{R.c4, R.c5, R.c6, R.c7}, reinterpret_cast<v4i *>(cp));
                 }
             }
         }
