@@ -88,7 +88,7 @@ typedef struct {
     int32_t block_lists;      /* 1: also build the locate structure of Sect. 2.3 (blocks of a regular grid,
                                  each listing the cells whose bounding box overlaps it) and keep the cells'
                                  bounding boxes, for vor_locate_blocks and vor_grid_bboxes; 0: not */
-    double block_occupancy;   /* with block_lists: about M / block_occupancy blocks (default 1) */
+    double block_occupancy;   /* with block_lists: about M / block_occupancy blocks (default 0.25) */
     int32_t record_layout;    /* the neighbour records that mixed-mode traces read (results are the same either
                                  way): VOR_RECORDS_AUTO (0, default: compact when the FP32 table would exceed
                                  512 MiB, i.e. would not stay in the last-level cache), VOR_RECORDS_FP32 (12-byte

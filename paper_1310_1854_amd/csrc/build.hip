@@ -533,7 +533,7 @@ extern "C" vor_status vor_build_grid(const double *sites, int64_t M, const doubl
         if (!std::isfinite(box[a]) || !std::isfinite(box[a + 3]) || !(box[a] < box[a + 3])) return VOR_EINVAL;
     double occ = (opts && opts->bucket_occupancy > 0) ? opts->bucket_occupancy : 2.0;
     const bool want_loc = opts && opts->block_lists;
-    const double locc = (opts && opts->block_occupancy > 0) ? opts->block_occupancy : 1.0;
+    const double locc = (opts && opts->block_occupancy > 0) ? opts->block_occupancy : 0.25;
     if (opts && (opts->block_lists < 0 || opts->block_lists > 1 || !(opts->block_occupancy >= 0))) return VOR_EINVAL;
     const int layout = opts ? opts->record_layout : VOR_RECORDS_AUTO;
     if (layout < VOR_RECORDS_AUTO || layout > VOR_RECORDS_COMPACT) return VOR_EINVAL;
