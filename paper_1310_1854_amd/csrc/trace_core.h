@@ -54,6 +54,9 @@ constexpr int kSpillChunk = VOR_SPILL_CHUNK;
 #ifndef VRT_NT_STORE
 #define VRT_NT_STORE 0
 #endif
+#ifndef VRT_LDS_STAGE
+#define VRT_LDS_STAGE 1
+#endif
 #ifndef VRT_NT_STORE_SERVE
 #define VRT_NT_STORE_SERVE 1
 #endif
@@ -835,6 +838,64 @@ __device__ __forceinline__ void put16(V v, V *p)
     else *p = v;
 }
 
+#if VRT_VEC_STORE
+// The wide groups (16 cells, 8 lengths) of the tracer kernels are held in
+// LDS rather than in registers: a lane's segment number i goes to slot
+// i mod 16 (cells) and i mod 8 (lengths) of its own column (slot-major, 256
+// lanes of a block side by side), so a step writes one cell and one length
+// there instead of shifting 32 registers, and the registers stay free for
+// the exit search. 32 KB per block of 256 threads.
+template <int CG, int LG, bool LP>
+constexpr bool lds_stage()
+{
+    return VRT_LDS_STAGE && CG == 16 && LG == 8 && !LP;
+}
+constexpr int kStageLanes = 256;   // threads per block of the kernels that stage
+__device__ __forceinline__ int32_t *stage_cells()
+{
+    __shared__ int32_t s[16 * kStageLanes];
+    return s;
+}
+__device__ __forceinline__ double *stage_lens()
+{
+    __shared__ double s[8 * kStageLanes];
+    return s;
+}
+
+// Write the staged groups that end at segment idx (lengths when idx ends a
+// group of 8; cells when it ends one of 16, or of 8 on windows that start
+// on 8- but not 16-slot boundaries).
+template <bool LP>
+__device__ __forceinline__ void store_staged(const SegOut &O, const RayState &R, int64_t idx)
+{
+    const int t = threadIdx.x;
+    const int32_t *sc = stage_cells();
+    const double *sl = stage_lens();
+    bool spill;
+    const int64_t p = segment_slot<LP>(O, R, idx - 7, spill);
+    if (p < 0) return;
+    v2d *lp = reinterpret_cast<v2d *>(slot_lens<LP>(O, spill) + p);
+    v4i *cp = reinterpret_cast<v4i *>(slot_cells<LP>(O, spill) + p);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        put16<LP>(v2d{sl[(2 * j) * kStageLanes + t], sl[(2 * j + 1) * kStageLanes + t]}, lp + j);
+    if (O.vec < 2) {   // the last 8 cells
+        const int b = (int)(idx & 8);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            put16<LP>(v4i{sc[(b + 4 * j) * kStageLanes + t], sc[(b + 4 * j + 1) * kStageLanes + t],
+                          sc[(b + 4 * j + 2) * kStageLanes + t], sc[(b + 4 * j + 3) * kStageLanes + t]},
+                      cp + j);
+    } else if ((idx & 15) == 15) {   // the group of 16 started 8 slots earlier
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            put16<LP>(v4i{sc[(4 * j) * kStageLanes + t], sc[(4 * j + 1) * kStageLanes + t],
+                          sc[(4 * j + 2) * kStageLanes + t], sc[(4 * j + 3) * kStageLanes + t]},
+                      cp - 2 + j);
+    }
+}
+#endif
+
 template <int CG, int LG, bool LP = false>
 __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int64_t idx, int32_t cell, double len)
 {
@@ -866,6 +927,13 @@ __device__ __forceinline__ void store_segment(const SegOut &O, RayState &R, int6
         }
     }
 #if VRT_VEC_STORE
+    if (lds_stage<CG, LG, LP>() && O.vec) {
+        const int t = threadIdx.x;
+        stage_cells()[(int)(idx & 15) * kStageLanes + t] = cell;
+        stage_lens()[(int)(idx & 7) * kStageLanes + t] = len;
+        if ((idx & 7) == 7) store_staged<LP>(O, R, idx);
+        return;
+    }
     if (O.vec) {
         // The cells go out CG and the lengths LG at a time: 64 B each with
         // CG = 16, LG = 8 (a partial write of the memory's write unit costs the
@@ -967,6 +1035,19 @@ __device__ __forceinline__ void finish_segments(const SegOut &O, const RayState 
     const int cg = (CG == 16 && O.vec < 2) ? 8 : CG;                // 16 only on 16-slot windows
     const int rc = (int)(n & (cg - 1)), rl = (int)(n & (LG - 1));   // cells and lengths not yet written
     if (rc == 0) return;
+    if (lds_stage<CG, LG, LP>()) {   // from the lane's LDS column
+        const int t = threadIdx.x;
+        for (int j = 0; j < rc; ++j) {
+            const int64_t i = n - rc + j;
+            bool spill;
+            const int64_t p = segment_slot<LP>(O, R, i, spill);
+            if (p >= 0) {
+                slot_cells<LP>(O, spill)[p] = stage_cells()[(int)(i & 15) * kStageLanes + t];
+                if (j >= rc - rl) slot_lens<LP>(O, spill)[p] = stage_lens()[(int)(i & 7) * kStageLanes + t];
+            }
+        }
+        return;
+    }
     // the held cells, right-aligned in 16 entries
     int32_t cs[16] = {R.c0, R.c1, R.c2, R.c3, R.c4, R.c5, R.c6, R.c7, R.c8, R.c9, R.c10, R.c11, R.c12, R.c13, R.c14, R.c15};
     if (CG == 8) {
