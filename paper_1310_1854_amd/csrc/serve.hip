@@ -112,10 +112,11 @@ __device__ __forceinline__ void chunk_complete(const ReqDev *__restrict__ reqs, 
 }
 
 #ifndef VRT_SERVE_WIDE
-#define VRT_SERVE_WIDE 0
+#define VRT_SERVE_WIDE VRT_LDS_STAGE
 #endif
 // Store groups of the serving kernels (see cells_per_store): the mixed
-// kernel keeps 8 cells and 4 lengths unless VRT_SERVE_WIDE.
+// kernels write 16 cells and 8 lengths at a time, held in LDS, or with
+// VRT_SERVE_WIDE = 0 8 cells and 4 lengths held in registers.
 constexpr bool kServeWide = VRT_SERVE_WIDE != 0;
 
 // The serving kernel of one precision class (MODE): a launch runs the

@@ -839,8 +839,8 @@ __device__ __forceinline__ void put16(V v, V *p)
 }
 
 #if VRT_VEC_STORE
-// The wide groups (16 cells, 8 lengths) of the tracer kernels are held in
-// LDS rather than in registers: a lane's segment number i goes to slot
+// The wide groups (16 cells, 8 lengths) of the mixed tracer and serving
+// kernels are held in LDS rather than in registers: a lane's segment number i goes to slot
 // i mod 16 (cells) and i mod 8 (lengths) of its own column (slot-major, 256
 // lanes of a block side by side), so a step writes one cell and one length
 // there instead of shifting 32 registers, and the registers stay free for
@@ -848,7 +848,7 @@ __device__ __forceinline__ void put16(V v, V *p)
 template <int CG, int LG, bool LP>
 constexpr bool lds_stage()
 {
-    return VRT_LDS_STAGE && CG == 16 && LG == 8 && !LP;
+    return VRT_LDS_STAGE && CG == 16 && LG == 8;
 }
 constexpr int kStageLanes = 256;   // threads per block of the kernels that stage
 __device__ __forceinline__ int32_t *stage_cells()
