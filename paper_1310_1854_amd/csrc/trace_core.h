@@ -805,22 +805,34 @@ __device__ __forceinline__ void take_pool_chunks(const SpillPool *pool, RayState
 // Store segment number idx of the ray: in its window, else in its spill
 // chain. A new chunk is taken when a path reaches the first slot of one;
 // lanes that do so in the same step share one atomic.
-// Segments written together per lane: in the mixed-mode kernels without
-// the optional features, 16 cells (64 B) and 8 lengths (64 B) where the
-// registers allow it (on windows that start on 8- but not 16-slot
-// boundaries the cells go out 8 at a time); in the others 4 of each (16 B and 32 B), since
-// more registers would cut their occupancy. WIDE = false keeps 8 cells and
-// 4 lengths (for the serving kernel, which holds both the mixed and the FP64
-// step).
+// Segments written together per lane: 16 cells (64 B) and 8 lengths (64 B),
+// held in LDS until then (on windows that start on 8- but not 16-slot
+// boundaries the cells go out 8 at a time), except in the FP64 kernels
+// without the optional features, which write 4 of each (16 B and 32 B) from
+// registers: measured, the wide groups made them slower (8% on a grid
+// beyond the last-level cache), where they make the mixed and the
+// transport kernels faster. Held in registers (VRT_LDS_STAGE = 0), the
+// mixed-mode kernels without the optional features keep 16 and 8 and the
+// others 4 of each, since more registers would cut their occupancy, and
+// WIDE = false keeps 8 cells and 4 lengths (serving kernels).
+template <int MODE, bool EXT>
+constexpr bool narrow_fp64()
+{
+    return MODE == VOR_MODE_FP64 && !EXT;
+}
 template <int MODE, bool EXT, bool WIDE = true>
 constexpr int cells_per_store()
 {
-    return (MODE != VOR_MODE_FP64 && !EXT) ? (WIDE ? 16 : 8) : 4;
+    return (VRT_LDS_STAGE && WIDE && !narrow_fp64<MODE, EXT>()) ? 16
+           : (MODE != VOR_MODE_FP64 && !EXT)                    ? (WIDE ? 16 : 8)
+                                                                : 4;
 }
 template <int MODE, bool EXT, bool WIDE = true>
 constexpr int lens_per_store()
 {
-    return (WIDE && MODE != VOR_MODE_FP64 && !EXT) ? 8 : 4;
+    return (VRT_LDS_STAGE && WIDE && !narrow_fp64<MODE, EXT>()) ? 8
+           : (WIDE && MODE != VOR_MODE_FP64 && !EXT)            ? 8
+                                                                : 4;
 }
 
 // 16 bytes of segment output. The tracer stores them as ordinary stores:
@@ -839,8 +851,8 @@ __device__ __forceinline__ void put16(V v, V *p)
 }
 
 #if VRT_VEC_STORE
-// The wide groups (16 cells, 8 lengths) of the mixed tracer and serving
-// kernels are held in LDS rather than in registers: a lane's segment number i goes to slot
+// The groups of 16 cells and 8 lengths are held in LDS rather than in
+// registers: a lane's segment number i goes to slot
 // i mod 16 (cells) and i mod 8 (lengths) of its own column (slot-major, 256
 // lanes of a block side by side), so a step writes one cell and one length
 // there instead of shifting 32 registers, and the registers stay free for
