@@ -17,12 +17,25 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kRounds = 16;
-constexpr int kTile = kThreads * kRounds;
+// Keys per tile: 256 threads times 16 rounds, or times 4 below kSmallTileKeys
+// keys, where tiles of 4096 would leave compute units idle.
+constexpr int kRoundsBig = 16, kRoundsSmall = 4;
+#ifndef VRT_SORT_SMALL_TILE_KEYS
+#define VRT_SORT_SMALL_TILE_KEYS (1 << 22)
+#endif
+constexpr int64_t kSmallTileKeys = VRT_SORT_SMALL_TILE_KEYS;
+inline int sort_rounds(int64_t n) { return n < kSmallTileKeys ? kRoundsSmall : kRoundsBig; }
+inline int64_t sort_tiles(int64_t n)
+{
+    const int64_t tile = (int64_t)kThreads * sort_rounds(n);
+    return (n + tile - 1) / tile;
+}
 
+template <int kRounds>
 __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint32_t *__restrict__ keys, int64_t n, int shift,
                                                          int32_t *__restrict__ hist, int64_t ntiles)
 {
+    constexpr int kTile = kThreads * kRounds;
     __shared__ int32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -89,12 +102,14 @@ __global__ void __launch_bounds__(kThreads) k_digit_rows(int32_t *__restrict__ h
 // follow those of the earlier waves: the order of the indices), the tile is
 // put in digit order in LDS, and written out in that order, so that runs of
 // equal digits leave contiguously.
+template <int kRounds>
 __global__ void __launch_bounds__(kThreads) k_digit_scatter(const uint32_t *__restrict__ kin,
                                                             const int32_t *__restrict__ vin, int64_t n, int shift,
                                                             const int32_t *__restrict__ rows,
                                                             const int32_t *__restrict__ tot, int64_t ntiles,
                                                             uint32_t *__restrict__ kout, int32_t *__restrict__ vout)
 {
+    constexpr int kTile = kThreads * kRounds;
     constexpr int kQuarter = kTile / kWaves;        // keys a wave ranks
     constexpr int kWaveRounds = kQuarter / 64;
     __shared__ int32_t wcnt[kWaves][256];           // each wave's running count of each digit, then its offset
@@ -211,7 +226,7 @@ vor_status vrt_gather_u32(const uint32_t *src, const int32_t *idx, int64_t n, ui
 
 int64_t vrt_radix_hist_len(int64_t n)
 {
-    int64_t ntiles = (n + kTile - 1) / kTile;
+    int64_t ntiles = sort_tiles(n);
     if (ntiles < 1) ntiles = 1;
     return 256 * ntiles;
 }
@@ -223,7 +238,8 @@ vor_status vrt_radix_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tm
 {
     if (n <= 1) return VOR_OK;
     if (n > 0x7fffffff) return VOR_EINVAL;
-    int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t ntiles = sort_tiles(n);
+    const bool small = sort_rounds(n) == kRoundsSmall;
     if (hist_len < 256 * ntiles) return VOR_EINVAL;
     int32_t *hist = hist_scratch;
     int32_t *tot = hist_scratch + hist_len;
@@ -232,10 +248,19 @@ vor_status vrt_radix_sort_pairs(uint32_t *keys, int32_t *vals, uint32_t *keys_tm
     int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
-        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, n, shift, hist, ntiles);
+        if (small)
+            hipLaunchKernelGGL(k_digit_hist<kRoundsSmall>, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, n, shift,
+                               hist, ntiles);
+        else
+            hipLaunchKernelGGL(k_digit_hist<kRoundsBig>, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, n, shift,
+                               hist, ntiles);
         hipLaunchKernelGGL(k_digit_rows, dim3(256), dim3(kThreads), 0, st, hist, ntiles, tot);
-        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, va, n, shift, hist,
-                           tot, ntiles, kb, vb);
+        if (small)
+            hipLaunchKernelGGL(k_digit_scatter<kRoundsSmall>, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, va, n,
+                               shift, hist, tot, ntiles, kb, vb);
+        else
+            hipLaunchKernelGGL(k_digit_scatter<kRoundsBig>, dim3((unsigned)ntiles), dim3(kThreads), 0, st, ka, va, n,
+                               shift, hist, tot, ntiles, kb, vb);
         uint32_t *tk = ka; ka = kb; kb = tk;
         int32_t *tv = va; va = vb; vb = tv;
     }

@@ -5,7 +5,8 @@ origin, then of the direction (a stable radix sort of each 30-bit key), and,
 from 2^17 rays on, cut into 8 parts with the rays of each part grouped by
 chord length, longest first. The order changes no result (the parity tests
 show that); these tests check that it is the order those keys define, which
-pins the radix sort (every digit, stability, tiles and the ragged tail) and
+pins the radix sort (every digit, stability, tiles of 1024 keys below 2^22
+keys and of 4096 above, rows of more than 2048 tiles, the ragged tail) and
 the chord groups. The keys are restated here in numpy from their
 definition: coordinates quantised to 10 bits over the box (origins) or over
 [-1, 1] (unit directions), the Hilbert index by Skilling's transform
@@ -112,7 +113,7 @@ def gpu_order(vrt, grid, origins, dirs):
     return order.cpu().numpy()
 
 
-@pytest.mark.parametrize("N,seed", [(ORDER_MIN_RAYS, 1), (CHORD_MIN_RAYS - 1, 2), (300_001, 3)])
+@pytest.mark.parametrize("N,seed", [(ORDER_MIN_RAYS, 1), (CHORD_MIN_RAYS - 1, 2), (300_001, 3), (3_000_000, 5)])
 def test_order_is_the_key_order(vrt, N, seed):
     w = W.flared_disc(M=20_000, N=N, seed=seed)
     grid = vrt.build_grid(w.sites, w.box)
