@@ -392,7 +392,6 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid
     taus = [None] * len(reqs)
     stats = [None] * len(reqs)
     done = threading.Event()
-    lock = threading.Lock()
     index = {}
 
     def reaper():
@@ -401,8 +400,10 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid
             rid = srv.next_done(1.0)
             if rid is None:
                 continue
-            with lock:   # the submitter records the id under the same lock
-                i = index[rid]
+            i = index.get(rid)
+            while i is None:   # the submitter records the id just after submit returns
+                time.sleep(0)
+                i = index.get(rid)
             lat[i] = srv.latency(rid)
             if keep:   # the per-ray results (the release below waits for these copies)
                 res = srv.result(rid, paths=False)
@@ -421,11 +422,13 @@ def run_server(vrt, grids, rhos, reqs, offsets, stride, budget, keep=False, grid
             time.sleep(wait)
         n = r["o"].shape[0]
         chunks = request_chunks(n, per_ray[r["grid"]]) if stride > 0 else 0
-        with lock:
-            t_sub[i] = time.perf_counter()
-            rid = srv.submit(r["grid"], r["o"], r["d"], None if grid_density else rhos[r["grid"]], mode=r["mode"],
-                             seg_stride=stride, spill_chunks=chunks, grid_density=grid_density)
-            index[rid] = i
+        # no lock around submit: a lock held there kept the reaper from releasing
+        # completed requests (and so from returning their memory) while the
+        # submissions went on
+        t_sub[i] = time.perf_counter()
+        rid = srv.submit(r["grid"], r["o"], r["d"], None if grid_density else rhos[r["grid"]], mode=r["mode"],
+                         seg_stride=stride, spill_chunks=chunks, grid_density=grid_density)
+        index[rid] = i
     if not done.wait(600):
         raise RuntimeError("serving run did not finish within 600 s")
     t1 = max(a + b for a, b in zip(t_sub, lat))   # the last completion
