@@ -516,6 +516,7 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 
             f[4 * u + 3] = x.w;
         }
         const int rem = n - e0;
+        int ws = -1;   // the winner's slot in this batch, if it is in this batch
 #pragma unroll
         for (int v = 0; v < kBatch32; ++v) {
             const bool in = v < rem;
@@ -529,10 +530,11 @@ __device__ __forceinline__ int exit_mixed(const Rec64 *__restrict__ rec64, int2 
             const bool w = pos && t < t1;
             t1 = w ? t : t1;
             err1 = w ? err : err1;
-            w1 = w ? e0 + v : w1;
+            ws = w ? v : ws;
             lo_b = __builtin_amdgcn_fmed3f(lo_a, lo_b, lo);
             lo_a = fminf(lo_a, lo);
         }
+        w1 = ws >= 0 ? e0 + ws : w1;
     }
     // the winner's own lower bound, computed as in the loop; the smallest
     // lower bound of the others is lo_b if the winner holds the smallest
