@@ -135,3 +135,44 @@ def test_tallies_from_a_point_source(env):
         assert np.max(np.abs(g_abs - t_abs)) <= 1e-12 * t_abs.max() + n_near * 1e-9 * L * 1e-2 * float(w.density.max())
     a, b = (o["tally_len"].cpu().numpy() for o in outs)
     assert np.max(np.abs(a - b)) <= 1e-12 * a.max()
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_transport_segment_groups_in_windows(mode):
+    """The transport kernels (stops and tallies) write their segments in
+    groups as the plain kernels do: windows of 16, 24 and 40 slots (16-cell
+    groups, 8-cell groups on 8-slot boundaries), every count of cells held at
+    a path's end (mod 16), paths cut at their interaction points and paths
+    past the window continuing in spill chains. Every path equals the exact
+    rows of the same trace, and the tallies and interaction points do not
+    depend on the output layout."""
+    import torch
+    from paper_1310_1854_amd import vrt
+    vrt.load()
+    w = W.uniform_cube(M=100_000, N=4000, seed=4313)
+    grid = vrt.build_grid(w.sites, w.box)
+    rng = np.random.default_rng(4314)
+    ts = -np.log(rng.uniform(size=w.N))
+    kw = dict(kappa=1.5, mode=mode, persistent=True, ordered=True, tau_stop=ts, tallies=True)
+    ex = vrt.trace(grid, w.origins, w.dirs, w.density, segments="exact", **kw)
+    ns = ex["n_seg"].cpu().numpy()
+    off = ex["ray_off"].cpu().numpy()
+    cells = ex["seg_cell"].cpu().numpy()
+    lens = ex["seg_len"].cpu().numpy()
+    stop = ex["stop_cell"].cpu().numpy()
+    assert len(set((ns % 16).tolist())) == 16
+    assert 0.2 * w.N < int((stop >= 0).sum()) < 0.9 * w.N    # many paths cut, many whole
+    for stride in (16, 24, 40):
+        out = vrt.trace(grid, w.origins, w.dirs, w.density, segments="stride", seg_stride=stride,
+                        spill_chunks=20000, **kw)
+        for k in ("tau", "n_seg", "stop_cell", "stop_s"):
+            assert torch.equal(out[k], ex[k]), (stride, k)
+        for k in ("tally_len", "tally_abs"):   # sums of atomics in no fixed order
+            a, b = out[k].cpu().numpy(), ex[k].cpu().numpy()
+            assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), (stride, k)
+        assert int(out["work"][2].item()) == int((ns > stride).sum()) > 0
+        host = {}
+        for r in range(w.N):
+            c, l = vrt.ray_path(out, r, host)
+            assert np.array_equal(c, cells[off[r]:off[r + 1]]), (stride, r)
+            assert np.array_equal(l, lens[off[r]:off[r + 1]]), (stride, r)
