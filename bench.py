@@ -49,7 +49,8 @@ KERNEL_SOURCES = ("paper_1310_1854_amd/csrc/trace.hip", "paper_1310_1854_amd/csr
 # Counter summaries of the trace kernel per workload (profiles/).
 TRAFFIC_SUMMARIES = {"flared_disc": "profiles/k_trace_flared_disc_1e6_mixed_traffic.md",
                      "exp_disc": "profiles/k_trace_exp_disc_1e5_mixed_traffic.md",
-                     "clumpy": "profiles/k_trace_clumpy_4e6_mixed_traffic.md"}
+                     "clumpy": "profiles/k_trace_clumpy_4e6_mixed_traffic.md",
+                     "flared_disc_transport": "profiles/k_trace_flared_disc_1e6_transport_traffic.md"}
 
 
 def kernel_source_hash() -> str:
