@@ -672,6 +672,10 @@ extern "C" vor_status vor_trace_noalloc(const vor_grid *G, const double *origins
 // ones, which shortens the drain where only a few lanes of a wave still
 // work; the parts keep their spatial coherence.
 constexpr int kChordBins = 8;
+// Batches below 2^22 rays (a few rays per lane of a full launch, so the
+// drain weighs more) use 16 groups.
+constexpr int kChordBinsSmall = 16;
+constexpr int64_t kChordBinsSmallMaxRays = 1 << 22;
 #ifndef VRT_ORDER_MIN_RAYS
 #define VRT_ORDER_MIN_RAYS (1 << 14)
 #endif
@@ -737,9 +741,10 @@ extern "C" vor_status vor_order_rays(const vor_grid *G, const double *origins, c
     rc = vrt_radix_sort_pairs(ktmp, order, okey, vtmp, N, kOrderKeyBits, hist, hl, st);
     if (rc != VOR_OK) return rc;
     // then stably by (part of the order, chord bin)
-    static_assert(kParts * kChordBins <= 256, "one 8-bit pass sorts by part and bin");
+    static_assert(kParts * kChordBinsSmall <= 256, "one 8-bit pass sorts by part and bin");
+    const int bins_n = N < kChordBinsSmallMaxRays ? kChordBinsSmall : kChordBins;
     if (chords) {
-        hipLaunchKernelGGL(k_part_bin_key, dim3(nb), dim3(T), 0, st, order, bins, ccount, N, kParts, kChordBins,
+        hipLaunchKernelGGL(k_part_bin_key, dim3(nb), dim3(T), 0, st, order, bins, ccount, N, kParts, bins_n,
                            lkey);
         rc = vrt_radix_sort_pairs(lkey, order, ktmp, vtmp, N, 8, hist, hl, st);
         if (rc != VOR_OK) return rc;

@@ -3,7 +3,7 @@
 vor_order_rays puts rays in a coherent order: by the Hilbert index of the
 origin, then of the direction (a stable radix sort of each 30-bit key), and,
 from 2^17 rays on, cut into 8 parts with the rays of each part grouped by
-chord length, longest first. The order changes no result (the parity tests
+chord length, longest first (16 groups below 2^22 rays, 8 from there on). The order changes no result (the parity tests
 show that); these tests check that it is the order those keys define, which
 pins the radix sort (every digit, stability, tiles of 1024 keys below 2^22
 keys and of 4096 above, rows of more than 2048 tiles, the ragged tail) and
@@ -22,7 +22,8 @@ from paper_1310_1854_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 BITS = 10
-PARTS, BINS = 8, 8
+PARTS = 8
+BINS_SMALL, BINS, BINS_SMALL_MAX_RAYS = 16, 8, 1 << 22
 CHORD_MIN_RAYS = 1 << 17
 ORDER_MIN_RAYS = 1 << 14
 
@@ -96,9 +97,10 @@ def expected_order(origins, dirs, box):
     ckey = ((1.0 - frac) * 255.0 + 0.5).astype(np.int64)
     cnt = np.bincount(ckey, minlength=256)
     before = np.concatenate([[0], np.cumsum(cnt)[:-1]])
-    bin_of = ((before + cnt // 2) * BINS) // N                   # the middle rank of each key's run
+    bins = BINS_SMALL if N < BINS_SMALL_MAX_RAYS else BINS
+    bin_of = ((before + cnt // 2) * bins) // N                   # the middle rank of each key's run
     r = np.arange(N)
-    final = (r * PARTS) // N * BINS + bin_of[ckey[coherent]]
+    final = (r * PARTS) // N * bins + bin_of[ckey[coherent]]
     return coherent[np.argsort(final, kind="stable")]
 
 
